@@ -1,0 +1,182 @@
+"""Benchmark of the particle-in-cell hot path on one MI355X.
+
+Workload (default): the 2-d double Harris current sheet, 1024 x 512 cells,
+100 particles per cell per species at the sheet peak (20 in the 0.2
+background), m_i/m_e = 25, T_i/T_e = 5, 2nd-order shape, float32, 32 x 32
+patches -- about 29.2 M particles.  A step is one full pass of the hot path in
+the order of the paper's optimized time step: B half step, fused particle
+kernel (gather, Boris, move, Esirkepov deposit), B half step, current fold,
+E full step, sort.  Inputs are synthetic and seeded, resident in HBM before
+the timed region.
+
+Prints one JSON line: whole-step particle throughput (particle pushes per
+second over complete steps), the roofline of the dominant kernel (the fused
+particle kernel) from HIP events recorded on its stream inside the timed
+region, and the double-precision oracle timed on a bounded sample on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# non-packed FP32 vector issue: 256 CUs x 64 lanes x 2.4 GHz (FMA = 2 flop)
+VALU_PEAK_TFLOPS = 256 * 64 * 2.4e9 * 2 / 1e12
+
+
+def algorithmic_bytes(case) -> float:
+    """Minimum HBM bytes of one particle-kernel launch: every particle's state
+    read and written once (int32 cell + D float32 offsets + 3 float32 momenta),
+    plus each patch's E and B read and its 3-component current tile written."""
+    D = case.dim
+    per_particle = 2 * (4 + 4 * D + 12)
+    return case.n_particles * per_particle + case.ncell * (6 + 3) * 4
+
+
+def make_case(name: str):
+    from paper_1310_7866_amd import cases
+    if name == "harris2d":
+        return cases.harris2d()
+    if name == "thermal2d":
+        return cases.thermal2d()
+    if name == "weibel3d":
+        return cases.weibel3d()
+    if name == "harris2d_small":
+        return cases.harris2d(ny=256, nz=256, ppc=64, seed=5050, steps=50)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(case, thin: int):
+    """The oracle as it stands, single-threaded, on every `thin`-th particle
+    of the same workload for one complete step."""
+    from oracle import oracle as O
+    from paper_1310_7866_amd import cases
+    sample = cases.thin(case, thin)
+    sim = O.OracleSim(sample)
+    t0 = time.perf_counter()
+    sim.step(1)
+    dt = time.perf_counter() - t0
+    return dict(value=sample.n_particles / dt, unit="particle pushes/s", cores=1, kind="oracle",
+                sample=f"1 full step of every {thin}th particle ({sample.n_particles} particles) "
+                       f"of the {case.name} workload on the full {case.gdims[1]}x{case.gdims[2]}"
+                       f"{'' if case.dim == 2 else 'x' + str(case.gdims[0])} grid, float64, 1 thread",
+                seconds=dt)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="harris2d")
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--cpu-thin", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(every GPU box here has one GPU); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1310_7866_amd.psc import PscSim, B_HALF, E_FULL
+
+    case = make_case(args.workload)
+    print(f"[bench] workload {case.name}: gdims={case.gdims} order={case.order} patch={case.patch} "
+          f"particles={case.n_particles}", file=sys.stderr, flush=True)
+    sim = PscSim(case, with_ids=False, chunk=args.chunk)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        sim.step(1)
+    sim.check()
+
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    push_ev = [(ev(), ev()) for _ in range(args.steps)]
+    sort_ev = [(ev(), ev()) for _ in range(args.steps)]
+    t_start, t_end = ev(), ev()
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_start.record(stream)
+    for k in range(args.steps):
+        sim.push_fields(B_HALF)
+        push_ev[k][0].record(stream)
+        sim.push_particles()
+        push_ev[k][1].record(stream)
+        sim.push_fields(B_HALF)
+        sim.deposit_current()
+        sim.push_fields(E_FULL)
+        sort_ev[k][0].record(stream)
+        sim.sort()
+        sort_ev[k][1].record(stream)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    sim.check()
+
+    total_ms = t_start.elapsed_time(t_end)
+    push_ms = sum(a.elapsed_time(b) for a, b in push_ev) / args.steps
+    sort_ms = sum(a.elapsed_time(b) for a, b in sort_ev) / args.steps
+    ms_step = total_ms / args.steps
+    n = case.n_particles
+    value = n * args.steps / (total_ms / 1e3)
+    abytes = algorithmic_bytes(case)
+    achieved_gbs = abytes / (push_ms / 1e3) / 1e9
+
+    roof = dict(bound="hbm", achieved=round(achieved_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved_gbs / HBM_PEAK_GBS, 4), traffic=None)
+    traffic_file = os.path.join(ROOT, "profiles", f"traffic_{case.name}.json")
+    if os.path.exists(traffic_file):
+        with open(traffic_file) as f:
+            tr = json.load(f)
+        if tr.get("kernel_source_hash") == _push_source_hash():
+            roof["traffic"] = tr.get("bytes_per_launch")
+
+    out = {
+        "metric": "particle pushes/sec (gather+push+deposit) and % HBM roofline; adjoint/forward time",
+        "value": value,
+        "unit": "particle pushes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{case.name} {case.gdims[1]}x{case.gdims[2]}"
+                               f"{'' if case.dim == 2 else 'x' + str(case.gdims[0])} cells, "
+                               f"order {case.order}, patches {case.patch[1]}x{case.patch[2]}",
+                   "particles": n, "cells": case.ncell, "order": case.order,
+                   "patch": list(case.patch), "parallelism": "single GPU"},
+        "push_kernel_ms": push_ms,
+        "push_kernel_pushes_per_s": n / (push_ms / 1e3),
+        "sort_ms": sort_ms,
+        "wall_s_timed": wall,
+        "roofline": roof,
+    }
+    del sim
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_thin)
+    print(json.dumps(out))
+
+
+def _push_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1310_7866_amd", "csrc", "psc_push.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,212 @@
+/*
+ * psc.h -- C ABI of the MI355X particle-in-cell hot path.
+ *
+ * One explicit electromagnetic PIC time step in the staggered order of the
+ * paper's optimized time step (Germaschewski et al., "The Plasma Simulation
+ * Code", fig. psc_new): B half step, particle loop (field interpolation,
+ * relativistic Boris push, position update, charge-conserving current
+ * deposit), B half step, fold of the per-patch current halos, E full step,
+ * and the per-step sort of particles by patch and cell (section "Sorting and
+ * Communication").  Everything runs in hand-written HIP kernels for gfx950 on
+ * the stream the caller passes; the library allocates no particle or field
+ * state.
+ *
+ * Units: c = eps0 = 1.  Maxwell: dE/dt = curl B - J, dB/dt = -curl E,
+ * div E = rho.  Motion: du/dt = (q/m)(E + u x B / gamma), u = gamma v.
+ * A particle of species s carries charge density q_s * w_s.
+ *
+ * Grid (section "FDTD method", fig. grid): cells (nx, ny, nz), x fastest;
+ * a 2-d run is the (y, z) plane with nx == 1 and no x derivatives.  Field
+ * arrays are float32, component-major, 3 * ncell elements, cell index
+ * i + nx*(j + ny*k).  Yee staggering, each value stored at its lower index:
+ * E_x (i+1/2, j, k), E_y (i, j+1/2, k), E_z (i, j, k+1/2);
+ * B_x (i, j+1/2, k+1/2), B_y (i+1/2, j, k+1/2), B_z (i+1/2, j+1/2, k);
+ * J located like E.  Periodic in every direction.
+ *
+ * Particles (structure of arrays, float32 precision with an integer cell):
+ *   cell  int32    patch-major cell key (see below) of the particle's cell
+ *   off   float32  D arrays of in-cell offsets in [0, 1) (D = 2: y, z;
+ *                  D = 3: x, y, z), array d at off + d * capacity
+ *   u     float32  3 arrays of momentum per mass u = gamma v / c, array c
+ *                  at u + c * capacity
+ *   id    int32    optional user tag carried through pushes and sorts
+ * Cell key: patches of patch[d] cells tile the grid in row-major patch order
+ * (x fastest), the last patch along a dimension truncated at the grid edge;
+ * cells inside a patch are numbered row-major; the key is the cell's rank in
+ * this enumeration.  Sorting by key groups particles by patch, then by cell.
+ *
+ * Ownership: the caller allocates every device buffer (fields, two particle
+ * buffer sets per species used as ping-pong, and one workspace block whose
+ * size psc_workspace_size reports) and keeps them alive until psc_destroy.
+ * The context object itself is host memory owned by the library.  A context
+ * is used by one host thread at a time; all device work is ordered on the
+ * stream argument.
+ *
+ * Errors: every call returns a psc_status.  Argument problems are reported
+ * synchronously.  Device-side problems (non-finite momenta, a particle that
+ * would move more than one cell, a cell key out of range, an overfull cell)
+ * set a sticky device error word that psc_check returns.  HIP runtime
+ * failures return PSC_ERR_HIP; psc_last_error gives the text.
+ */
+#ifndef PSC_H
+#define PSC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PSC_OK = 0,
+    PSC_ERR_INVALID = 1,      /* bad argument or descriptor                  */
+    PSC_ERR_CFL = 2,          /* dt violates the CFL limit                    */
+    PSC_ERR_LDS = 3,          /* patch tile does not fit in LDS               */
+    PSC_ERR_HIP = 4,          /* HIP runtime error                            */
+    PSC_ERR_NONFINITE = 5,    /* a momentum became NaN/Inf (device word)      */
+    PSC_ERR_PARTICLE = 6,     /* move > 1 cell or key out of range (device)   */
+    PSC_ERR_UNSUPPORTED = 7,  /* valid but not implemented combination        */
+    PSC_ERR_STATE = 8         /* call out of order (e.g. no particles loaded) */
+} psc_status;
+
+#define PSC_MAX_SPECIES 4
+#define PSC_MAX_RUNS 4096
+
+/* Field operations of psc_push_fields (fig. psc_new: push_field_B_half,
+ * push_field_E). */
+#define PSC_B_HALF 0   /* B <- B - (dt/2) curl^+ E                            */
+#define PSC_E_FULL 1   /* E <- E + dt (curl^- B - J)                          */
+
+/* Error word bits (psc_check / psc_error_word). */
+#define PSC_DEV_NONFINITE 1u
+#define PSC_DEV_MOVE 2u
+#define PSC_DEV_KEY 4u
+#define PSC_DEV_OVERFULL 8u
+
+typedef struct {
+    int dim;                        /* 2 or 3                                        */
+    int gdims[3];                   /* cells along x, y, z (gdims[0] == 1 in 2-d);   */
+                                    /* active dimensions need >= 3 cells             */
+    int patch[3];                   /* patch size in cells (patch[0] == 1 in 2-d)    */
+    double dx[3];                   /* cell sizes (dx[0] ignored in 2-d)             */
+    double dt;                      /* time step, below the Yee CFL limit            */
+    int order;                      /* 1: b1 interpolation weights, 2: b2            */
+    int n_species;                  /* 1 .. PSC_MAX_SPECIES                          */
+    double q[PSC_MAX_SPECIES];      /* charge                                        */
+    double m[PSC_MAX_SPECIES];      /* mass                                          */
+    double w[PSC_MAX_SPECIES];      /* density weight per particle                   */
+    int64_t capacity[PSC_MAX_SPECIES]; /* particle slots per buffer                  */
+} psc_run_desc;
+
+typedef struct {
+    float *E, *B, *J;                          /* 3 * ncell float32 each               */
+    int32_t *cell[PSC_MAX_SPECIES][2];         /* ping-pong particle buffer sets       */
+    float *off[PSC_MAX_SPECIES][2];            /* D * capacity                          */
+    float *u[PSC_MAX_SPECIES][2];              /* 3 * capacity                          */
+    int32_t *id[PSC_MAX_SPECIES][2];           /* optional: all NULL or all set         */
+} psc_run_bufs;
+
+typedef struct psc_ctx psc_ctx;
+
+/* Validate run descriptors and create a context (host only, no device work).
+ * runs: n_runs descriptors (1 <= n_runs <= PSC_MAX_RUNS), copied.
+ * chunk: particles per work item of the particle kernel (0 = default 8192).
+ * Synchronous errors: PSC_ERR_INVALID, PSC_ERR_CFL (dt >= CFL limit),
+ * PSC_ERR_LDS (a patch tile does not fit in 160 KiB of LDS). */
+psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc_ctx **out);
+
+/* Bytes of device workspace the context needs (per-patch current tiles,
+ * cell offsets, sort counters, permutation, work tables, error word). */
+psc_status psc_workspace_size(const psc_ctx *ctx, size_t *bytes);
+
+/* Attach caller buffers: bufs[r] for each run, and a device workspace of at
+ * least psc_workspace_size bytes (256-byte aligned).  Uploads the device
+ * descriptor tables on `stream` (a hipStream_t, NULL = default stream). */
+psc_status psc_bind(psc_ctx *ctx, const psc_run_bufs *bufs, int n_runs, void *workspace, void *stream);
+
+/* Load the particles of one (run, species) from caller device arrays in
+ * geometric form: gcell int32 (n) geometric cell index i + nx*(j + ny*k),
+ * goff float32 (D, n) row-major (array d at goff + d*n), gu float32 (3, n),
+ * gid int32 (n) or NULL.  Converts cells to patch-major keys and stably sorts
+ * by key into buffer set 0 (input order kept among equal keys).  n must not
+ * exceed the species capacity.  Call for every species before stepping. */
+psc_status psc_load_particles(psc_ctx *ctx, int run, int species, int64_t n, const int32_t *gcell,
+                              const float *goff, const float *gu, const int32_t *gid, void *stream);
+
+/* Field update of every run (section "FDTD method"; fig. psc_new).
+ * op: PSC_B_HALF or PSC_E_FULL. */
+psc_status psc_push_fields(psc_ctx *ctx, int op, void *stream);
+
+/* Particle loop of every run and species (fig. psc_new: push_particle_p,
+ * push_particle_x, deposit_j), fused in one kernel: per patch, E and B are
+ * staged in LDS with ghost layers; each particle is interpolated (b1/b2
+ * weights of its Yee component), pushed with the relativistic Boris scheme,
+ * moved, and its Esirkepov current is accumulated in an LDS tile that is
+ * added to the patch's current tile in the workspace.  Reads the particles
+ * through the permutation left by psc_sort (if any), writes them in that
+ * sorted order into the other buffer set, and records each particle's move
+ * code for the next psc_sort. */
+psc_status psc_push_particles(psc_ctx *ctx, void *stream);
+
+/* Fold the per-patch current tiles (with their halos) into J with periodic
+ * wrap, in a fixed order, and clear the tiles (fig. psc_new:
+ * add_and_fill_ghosts_j). */
+psc_status psc_deposit_current(psc_ctx *ctx, void *stream);
+
+/* Stable counting sort of every species by cell key (section "Sorting and
+ * Communication"): uses the move codes of the last psc_push_particles (each
+ * particle moved by at most one cell per dimension), computes the new cell
+ * offsets and the permutation into key order, equal keys in their current
+ * order.  The physical reorder is deferred into the next
+ * psc_push_particles. */
+psc_status psc_sort(psc_ctx *ctx, void *stream);
+
+/* nsteps full steps in the order of fig. psc_new: B half, particles, B half,
+ * fold J, E full, sort.  use_graph != 0 records the step into a HIP graph
+ * once per buffer parity and replays it. */
+psc_status psc_step(psc_ctx *ctx, int nsteps, int use_graph, void *stream);
+
+/* Write the particles of (run, species) in sorted key order into caller
+ * device arrays (same layout as the buffers, stride n): cell keys, offsets,
+ * momenta, ids (any pointer may be NULL to skip it). */
+psc_status psc_get_particles(psc_ctx *ctx, int run, int species, int32_t *cell, float *off, float *u,
+                             int32_t *id, void *stream);
+
+/* Convert patch-major keys to geometric cell indices for (run): n keys in,
+ * n geometric indices out (device arrays). */
+psc_status psc_keys_to_cells(psc_ctx *ctx, int run, int64_t n, const int32_t *keys, int32_t *cells,
+                             void *stream);
+
+/* Per-step state queries (host side, no device work). */
+psc_status psc_particle_count(const psc_ctx *ctx, int run, int species, int64_t *n);
+psc_status psc_front(const psc_ctx *ctx, int *front, int *perm_pending);
+
+/* Device views for tests: the permutation (int32, capacity) and the current
+ * cell offsets (int32, ncell + 1) of (run, species). */
+psc_status psc_sort_view(const psc_ctx *ctx, int run, int species, const int32_t **perm,
+                         const int32_t **cell_start);
+
+/* Double-precision diagnostics of every run (the only FP64 on the GPU), on
+ * the stored time levels E^{n+1/2}, B^n, u^n.  out_dev: device float64,
+ * n_runs * PSC_DIAG_STRIDE values per run:
+ *   [0] 1/2 sum E^2 dV   [1] 1/2 sum B^2 dV   [2..5] sum m w dV (gamma-1) per species
+ *   [6] max |div^- E - rho|   [7] max |div^+ B|   [8] sum rho dV   [9] particle count
+ * gauss_dev: optional float64 (sum of ncell over runs) receiving div^- E - rho
+ * per node, runs concatenated. */
+#define PSC_DIAG_STRIDE 10
+psc_status psc_diagnostics(psc_ctx *ctx, double *out_dev, double *gauss_dev, void *stream);
+
+/* Synchronize `stream` and return the device error word as a status:
+ * PSC_OK, PSC_ERR_NONFINITE, PSC_ERR_PARTICLE. *word (optional) receives the
+ * raw bits (PSC_DEV_*). clear != 0 resets the word. */
+psc_status psc_check(psc_ctx *ctx, void *stream, uint32_t *word, int clear);
+
+const char *psc_status_string(psc_status s);
+psc_status psc_last_error(const psc_ctx *ctx, char *buf, size_t n);
+psc_status psc_destroy(psc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSC_H */

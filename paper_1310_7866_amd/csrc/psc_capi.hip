@@ -1,0 +1,601 @@
+// psc_capi.hip -- the C ABI: validation, workspace carving, device descriptor
+// tables, call sequencing and HIP graph capture of whole time steps.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "psc_internal.h"
+
+namespace psc {
+size_t push_lds_bytes(int dim, int order, const int P[3]);
+}
+
+using namespace psc;
+
+struct psc_ctx {
+    std::vector<psc_run_desc> desc;
+    std::vector<RunDev> runs;   // host mirror of the device table
+    int n_runs = 0, dim = 2, order = 1, chunk = 8192;
+    size_t lds = 0;
+
+    // workspace layout (offsets in bytes)
+    size_t ws_bytes = 0;
+    char *ws = nullptr;
+    std::vector<Unit> units;
+    int64_t max_items = 0;
+    int64_t total_cells = 0;
+    std::vector<int64_t> run_base;       // n_runs + 1
+    int n_segs = 0;
+    std::vector<int64_t> seg_base;       // n_segs + 1
+    std::vector<int32_t> seg_run, seg_sp;
+    int64_t total_seg_cells = 0;
+    int64_t n_scan_blocks = 0;
+    std::vector<int32_t> block_seg;
+    int64_t max_cap = 0, max_ncell = 0;
+    size_t cub_bytes = 0;
+
+    struct Off {
+        size_t runs, units, item_start, run_base, seg_base, seg_run, seg_sp, segs0, segs1, scan_tmp, err;
+        size_t load_seg, load_blockseg, load_sums, load_keys, load_idx, load_keys_s, load_idx_s, cub;
+    } off{};
+    std::vector<size_t> off_jtile, off_rho;
+    std::vector<std::vector<size_t>> off_cs0, off_cs1, off_perm, off_mc, off_cnt, off_pre, off_tot;
+
+    // state
+    bool bound = false;
+    bool stepped = false;
+    std::vector<std::vector<bool>> loaded;
+    int front = 0, cs_sel = 0, perm_pending = 0, mc_valid = 0;
+    std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
+    hipStream_t cap_stream = nullptr;   // private stream used only to record graphs
+    std::string last_error;
+
+    template <class T>
+    T *at(size_t o) const { return reinterpret_cast<T *>(ws + o); }
+    uint32_t *err() const { return at<uint32_t>(off.err); }
+};
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+psc_status fail(psc_ctx *c, psc_status s, const std::string &msg) {
+    if (c) c->last_error = msg;
+    return s;
+}
+
+psc_status hipfail(psc_ctx *c, hipError_t e, const char *where) {
+    if (e == hipSuccess) return PSC_OK;
+    if (c) c->last_error = std::string(where) + ": " + hipGetErrorString(e);
+    return PSC_ERR_HIP;
+}
+
+#define HIPCHECK(call, where)                                         \
+    do {                                                              \
+        hipError_t e_ = (call);                                       \
+        if (e_ != hipSuccess) return hipfail(ctx, e_, where);         \
+    } while (0)
+
+Launch make_launch(psc_ctx *ctx, hipStream_t s) {
+    Launch L;
+    L.runs_dev = ctx->at<RunDev>(ctx->off.runs);
+    L.runs_host = ctx->runs.data();
+    L.n_runs = ctx->n_runs;
+    L.stream = s;
+    L.err = ctx->err();
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *psc_status_string(psc_status s) {
+    switch (s) {
+        case PSC_OK: return "ok";
+        case PSC_ERR_INVALID: return "invalid argument";
+        case PSC_ERR_CFL: return "time step violates the CFL limit";
+        case PSC_ERR_LDS: return "patch tile does not fit in LDS";
+        case PSC_ERR_HIP: return "HIP runtime error";
+        case PSC_ERR_NONFINITE: return "non-finite particle momentum";
+        case PSC_ERR_PARTICLE: return "particle moved more than one cell or has an invalid cell";
+        case PSC_ERR_UNSUPPORTED: return "unsupported combination";
+        case PSC_ERR_STATE: return "call out of order";
+    }
+    return "unknown status";
+}
+
+psc_status psc_last_error(const psc_ctx *ctx, char *buf, size_t n) {
+    if (!ctx || !buf || n == 0) return PSC_ERR_INVALID;
+    std::snprintf(buf, n, "%s", ctx->last_error.c_str());
+    return PSC_OK;
+}
+
+psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc_ctx **out) {
+    if (!out) return PSC_ERR_INVALID;
+    *out = nullptr;
+    if (!runs || n_runs < 1 || n_runs > PSC_MAX_RUNS || chunk < 0) return PSC_ERR_INVALID;
+    psc_ctx *ctx = new psc_ctx();
+    ctx->n_runs = n_runs;
+    ctx->desc.assign(runs, runs + n_runs);
+    ctx->dim = runs[0].dim;
+    ctx->order = runs[0].order;
+    ctx->chunk = chunk ? chunk : 8192;
+    for (int r = 0; r < n_runs; ++r) {
+        const psc_run_desc &d = runs[r];
+        char msg[256];
+        if (d.dim != ctx->dim || d.order != ctx->order) {
+            std::snprintf(msg, sizeof msg, "run %d: every run of a context needs the same dim and order", r);
+            psc_status s = fail(ctx, PSC_ERR_UNSUPPORTED, msg);
+            delete ctx;
+            return s;
+        }
+        bool ok = (d.dim == 2 || d.dim == 3) && (d.order == 1 || d.order == 2) && d.n_species >= 1 &&
+                  d.n_species <= PSC_MAX_SPECIES && d.dt > 0.0;
+        if (ok && d.dim == 2) ok = d.gdims[0] == 1 && d.patch[0] == 1;
+        for (int k = 0; ok && k < 3; ++k) {
+            const bool active = d.dim == 3 || k > 0;
+            ok = d.patch[k] >= 1 && d.patch[k] <= d.gdims[k] && (!active || (d.gdims[k] >= 3 && d.dx[k] > 0.0));
+        }
+        double ncell = ok ? (double)d.gdims[0] * d.gdims[1] * d.gdims[2] : 0.0;
+        if (ok && ncell >= 2147483647.0) ok = false;
+        for (int s = 0; ok && s < d.n_species; ++s)
+            ok = d.m[s] > 0.0 && d.capacity[s] >= 0 && d.capacity[s] < 2147483647LL;
+        if (!ok) {
+            std::snprintf(msg, sizeof msg, "run %d: invalid descriptor", r);
+            psc_status s = fail(ctx, PSC_ERR_INVALID, msg);
+            delete ctx;
+            return s;
+        }
+        double inv2 = 0.0;
+        for (int k = (d.dim == 3 ? 0 : 1); k < 3; ++k) inv2 += 1.0 / (d.dx[k] * d.dx[k]);
+        if (d.dt >= 1.0 / std::sqrt(inv2)) {
+            std::snprintf(msg, sizeof msg, "run %d: dt %.6g >= CFL limit %.6g", r, d.dt, 1.0 / std::sqrt(inv2));
+            psc_status s = fail(ctx, PSC_ERR_CFL, msg);
+            delete ctx;
+            return s;
+        }
+        const size_t lds = push_lds_bytes(d.dim, d.order, d.patch);
+        if (lds > 65536) {
+            std::snprintf(msg, sizeof msg, "run %d: patch tile needs %zu bytes of LDS (max 65536)", r, lds);
+            psc_status s = fail(ctx, PSC_ERR_LDS, msg);
+            delete ctx;
+            return s;
+        }
+        if (lds > ctx->lds) ctx->lds = lds;
+    }
+
+    // host mirrors and layout
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + (bytes ? bytes : 1));
+        return at;
+    };
+    ctx->runs.resize(n_runs);
+    ctx->run_base.assign(n_runs + 1, 0);
+    ctx->loaded.assign(n_runs, std::vector<bool>(PSC_MAX_SPECIES, false));
+    for (int r = 0; r < n_runs; ++r) {
+        const psc_run_desc &d = runs[r];
+        RunDev &R = ctx->runs[r];
+        std::memset(&R, 0, sizeof R);
+        R.dim = d.dim;
+        R.order = d.order;
+        for (int k = 0; k < 3; ++k) {
+            R.n[k] = d.gdims[k];
+            R.P[k] = d.patch[k];
+            R.np[k] = (d.gdims[k] + d.patch[k] - 1) / d.patch[k];
+            const bool active = d.dim == 3 || k > 0;
+            R.dx[k] = active ? (float)d.dx[k] : 1.0f;
+            R.inv_dx[k] = active ? (float)(1.0 / d.dx[k]) : 0.0f;
+            R.jt[k] = active ? d.patch[k] + cur_lo(d.order) + cur_hi(d.order) : 1;
+        }
+        R.n_patches = R.np[0] * R.np[1] * R.np[2];
+        R.n_species = d.n_species;
+        R.ncell = (int64_t)d.gdims[0] * d.gdims[1] * d.gdims[2];
+        R.cell_base = ctx->total_cells;
+        ctx->total_cells += R.ncell;
+        ctx->run_base[r + 1] = ctx->total_cells;
+        R.dt = (float)d.dt;
+        R.jtile_cells = (int64_t)R.jt[0] * R.jt[1] * R.jt[2];
+        if (R.ncell > ctx->max_ncell) ctx->max_ncell = R.ncell;
+        for (int s = 0; s < d.n_species; ++s) {
+            SpeciesDev &S = R.sp[s];
+            S.q = (float)d.q[s];
+            S.m = (float)d.m[s];
+            S.w = (float)d.w[s];
+            S.qdt_2m = (float)(d.q[s] * d.dt / (2.0 * d.m[s]));
+            S.qw = (float)(d.q[s] * d.w[s]);
+            S.cap = d.capacity[s];
+            S.n = 0;
+            if (S.cap > ctx->max_cap) ctx->max_cap = S.cap;
+        }
+        for (int p = 0; p < R.n_patches; ++p)
+            for (int s = 0; s < d.n_species; ++s) ctx->units.push_back(Unit{r, s, p, 0});
+    }
+    int64_t items = (int64_t)ctx->units.size();
+    for (int r = 0; r < n_runs; ++r)
+        for (int s = 0; s < runs[r].n_species; ++s) items += (runs[r].capacity[s] + ctx->chunk - 1) / ctx->chunk;
+    ctx->max_items = items;
+
+    // scan segments: one per (run, species)
+    ctx->seg_base.push_back(0);
+    for (int r = 0; r < n_runs; ++r)
+        for (int s = 0; s < runs[r].n_species; ++s) {
+            ctx->seg_run.push_back(r);
+            ctx->seg_sp.push_back(s);
+            ctx->runs[r].sp[s].seg = ctx->n_segs++;
+            const int64_t nb = (ctx->runs[r].ncell + kScanBlock - 1) / kScanBlock;
+            for (int64_t b = 0; b < nb; ++b) ctx->block_seg.push_back(ctx->n_segs - 1);
+            ctx->n_scan_blocks += nb;
+            ctx->total_seg_cells += ctx->runs[r].ncell;
+            ctx->seg_base.push_back(ctx->total_seg_cells);
+        }
+
+    const int M = n_moves(ctx->dim);
+    ctx->off.runs = take(sizeof(RunDev) * n_runs);
+    ctx->off.units = take(sizeof(Unit) * ctx->units.size());
+    ctx->off.item_start = take(sizeof(int32_t) * (ctx->units.size() + 1));
+    ctx->off.run_base = take(sizeof(int64_t) * (n_runs + 1));
+    ctx->off.seg_base = take(sizeof(int64_t) * (ctx->n_segs + 1));
+    ctx->off.seg_run = take(sizeof(int32_t) * ctx->n_segs);
+    ctx->off.seg_sp = take(sizeof(int32_t) * ctx->n_segs);
+    ctx->off.segs0 = take(sizeof(ScanSeg) * ctx->n_segs);
+    ctx->off.segs1 = take(sizeof(ScanSeg) * ctx->n_segs);
+    ctx->off.scan_tmp = take(sizeof(int32_t) * 2 * ctx->n_scan_blocks);
+    ctx->off.err = take(sizeof(uint32_t) * 64);
+    const int64_t load_blocks = (ctx->max_ncell + kScanBlock - 1) / kScanBlock;
+    ctx->off.load_seg = take(sizeof(ScanSeg));
+    ctx->off.load_blockseg = take(sizeof(int32_t) * load_blocks);
+    ctx->off.load_sums = take(sizeof(int32_t) * load_blocks);
+    ctx->off.load_keys = take(sizeof(int32_t) * ctx->max_cap);
+    ctx->off.load_idx = take(sizeof(int32_t) * ctx->max_cap);
+    ctx->off.load_keys_s = take(sizeof(int32_t) * ctx->max_cap);
+    ctx->off.load_idx_s = take(sizeof(int32_t) * ctx->max_cap);
+    ctx->off_jtile.resize(n_runs);
+    ctx->off_rho.resize(n_runs);
+    ctx->off_cs0.assign(n_runs, std::vector<size_t>(PSC_MAX_SPECIES, 0));
+    ctx->off_cs1 = ctx->off_perm = ctx->off_mc = ctx->off_cnt = ctx->off_pre = ctx->off_tot = ctx->off_cs0;
+    for (int r = 0; r < n_runs; ++r) {
+        const RunDev &R = ctx->runs[r];
+        ctx->off_jtile[r] = take(sizeof(float) * (size_t)R.n_patches * 3 * R.jtile_cells);
+        ctx->off_rho[r] = take(sizeof(double) * R.ncell);
+        for (int s = 0; s < R.n_species; ++s) {
+            ctx->off_cs0[r][s] = take(sizeof(int32_t) * (R.ncell + 1));
+            ctx->off_cs1[r][s] = take(sizeof(int32_t) * (R.ncell + 1));
+            ctx->off_perm[r][s] = take(sizeof(int32_t) * R.sp[s].cap);
+            ctx->off_mc[r][s] = take(R.sp[s].cap);
+            ctx->off_cnt[r][s] = take(sizeof(uint16_t) * M * R.ncell);
+            ctx->off_pre[r][s] = take(sizeof(uint16_t) * M * R.ncell);
+            ctx->off_tot[r][s] = take(sizeof(int32_t) * R.ncell);
+        }
+    }
+    ctx->off.cub = o;     // radix-sort temp storage goes last, sized in psc_workspace_size
+    ctx->ws_bytes = o;
+    *out = ctx;
+    return PSC_OK;
+}
+
+psc_status psc_workspace_size(const psc_ctx *cctx, size_t *bytes) {
+    psc_ctx *ctx = const_cast<psc_ctx *>(cctx);
+    if (!ctx || !bytes) return PSC_ERR_INVALID;
+    if (ctx->cub_bytes == 0) {
+        size_t tb = 0;
+        int bits = 1;
+        while ((int64_t(1) << bits) < ctx->max_ncell) ++bits;
+        hipError_t e = radix_sort_pairs(nullptr, &tb, nullptr, nullptr, nullptr, nullptr,
+                                        ctx->max_cap > 0 ? ctx->max_cap : 1, bits, 0);
+        if (e != hipSuccess) return hipfail(ctx, e, "radix sort size query");
+        ctx->cub_bytes = align256(tb + 256);
+    }
+    *bytes = ctx->off.cub + ctx->cub_bytes;
+    return PSC_OK;
+}
+
+psc_status psc_bind(psc_ctx *ctx, const psc_run_bufs *bufs, int n_runs, void *workspace, void *stream) {
+    if (!ctx || !bufs || n_runs != ctx->n_runs || !workspace) return PSC_ERR_INVALID;
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(ctx, PSC_ERR_INVALID, "workspace not 256-byte aligned");
+    if (ctx->cub_bytes == 0) {
+        size_t b;
+        psc_status st = psc_workspace_size(ctx, &b);
+        if (st != PSC_OK) return st;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    ctx->ws = (char *)workspace;
+    for (int r = 0; r < ctx->n_runs; ++r) {
+        RunDev &R = ctx->runs[r];
+        const psc_run_bufs &b = bufs[r];
+        if (!b.E || !b.B || !b.J) return fail(ctx, PSC_ERR_INVALID, "null field buffer");
+        R.E = b.E;
+        R.B = b.B;
+        R.J = b.J;
+        R.jtile = ctx->at<float>(ctx->off_jtile[r]);
+        R.rho = ctx->at<double>(ctx->off_rho[r]);
+        for (int sp = 0; sp < R.n_species; ++sp) {
+            SpeciesDev &S = R.sp[sp];
+            const bool any_id = b.id[sp][0] || b.id[sp][1];
+            for (int k = 0; k < 2; ++k) {
+                if (S.cap > 0 && (!b.cell[sp][k] || !b.off[sp][k] || !b.u[sp][k]))
+                    return fail(ctx, PSC_ERR_INVALID, "null particle buffer");
+                if (any_id && !b.id[sp][k]) return fail(ctx, PSC_ERR_INVALID, "ids must be given for both buffers");
+                S.cell[k] = b.cell[sp][k];
+                S.off[k] = b.off[sp][k];
+                S.u[k] = b.u[sp][k];
+                S.id[k] = b.id[sp][k];
+            }
+            S.cs[0] = ctx->at<int32_t>(ctx->off_cs0[r][sp]);
+            S.cs[1] = ctx->at<int32_t>(ctx->off_cs1[r][sp]);
+            S.perm = ctx->at<int32_t>(ctx->off_perm[r][sp]);
+            S.mc = ctx->at<uint8_t>(ctx->off_mc[r][sp]);
+            S.cnt = ctx->at<uint16_t>(ctx->off_cnt[r][sp]);
+            S.pre = ctx->at<uint16_t>(ctx->off_pre[r][sp]);
+            S.tot = ctx->at<int32_t>(ctx->off_tot[r][sp]);
+        }
+    }
+    std::vector<ScanSeg> segs0(ctx->n_segs), segs1(ctx->n_segs);
+    {
+        int64_t b0 = 0;
+        for (int g = 0; g < ctx->n_segs; ++g) {
+            const RunDev &R = ctx->runs[ctx->seg_run[g]];
+            const SpeciesDev &S = R.sp[ctx->seg_sp[g]];
+            segs0[g] = ScanSeg{S.tot, S.cs[1], R.ncell, b0};   // cs_sel 0: new offsets go to cs[1]
+            segs1[g] = ScanSeg{S.tot, S.cs[0], R.ncell, b0};
+            b0 += (R.ncell + kScanBlock - 1) / kScanBlock;
+        }
+    }
+    HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.runs), ctx->runs.data(), sizeof(RunDev) * ctx->n_runs,
+                            hipMemcpyHostToDevice, s), "upload runs");
+    HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.units), ctx->units.data(), sizeof(Unit) * ctx->units.size(),
+                            hipMemcpyHostToDevice, s), "upload units");
+    HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.run_base), ctx->run_base.data(), sizeof(int64_t) * (ctx->n_runs + 1),
+                            hipMemcpyHostToDevice, s), "upload run base");
+    HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.seg_base), ctx->seg_base.data(), sizeof(int64_t) * (ctx->n_segs + 1),
+                            hipMemcpyHostToDevice, s), "upload seg base");
+    HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.seg_run), ctx->seg_run.data(), sizeof(int32_t) * ctx->n_segs,
+                            hipMemcpyHostToDevice, s), "upload seg run");
+    HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.seg_sp), ctx->seg_sp.data(), sizeof(int32_t) * ctx->n_segs,
+                            hipMemcpyHostToDevice, s), "upload seg species");
+    HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.segs0), segs0.data(), sizeof(ScanSeg) * ctx->n_segs,
+                            hipMemcpyHostToDevice, s), "upload segs0");
+    HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.segs1), segs1.data(), sizeof(ScanSeg) * ctx->n_segs,
+                            hipMemcpyHostToDevice, s), "upload segs1");
+    HIPCHECK(hipMemcpyAsync(ctx->at<int32_t>(ctx->off.scan_tmp) + ctx->n_scan_blocks, ctx->block_seg.data(),
+                            sizeof(int32_t) * ctx->n_scan_blocks, hipMemcpyHostToDevice, s), "upload block table");
+    HIPCHECK(hipMemsetAsync(ctx->err(), 0, sizeof(uint32_t), s), "clear error word");
+    // clear the current tiles and every cell-offset array once
+    for (int r = 0; r < ctx->n_runs; ++r) {
+        const RunDev &R = ctx->runs[r];
+        HIPCHECK(hipMemsetAsync(R.jtile, 0, sizeof(float) * (size_t)R.n_patches * 3 * R.jtile_cells, s), "clear tiles");
+        for (int sp = 0; sp < R.n_species; ++sp) {
+            HIPCHECK(hipMemsetAsync(R.sp[sp].cs[0], 0, sizeof(int32_t) * (R.ncell + 1), s), "clear cs");
+            HIPCHECK(hipMemsetAsync(R.sp[sp].cs[1], 0, sizeof(int32_t) * (R.ncell + 1), s), "clear cs");
+        }
+    }
+    HIPCHECK(hipStreamSynchronize(s), "bind sync");
+    ctx->bound = true;
+    ctx->stepped = false;
+    ctx->front = ctx->cs_sel = ctx->perm_pending = ctx->mc_valid = 0;
+    return PSC_OK;
+}
+
+psc_status psc_load_particles(psc_ctx *ctx, int run, int species, int64_t n, const int32_t *gcell, const float *goff,
+                              const float *gu, const int32_t *gid, void *stream) {
+    if (!ctx || !ctx->bound) return PSC_ERR_STATE;
+    if (ctx->stepped) return fail(ctx, PSC_ERR_STATE, "particles must be loaded before the first push");
+    if (run < 0 || run >= ctx->n_runs || species < 0 || species >= ctx->runs[run].n_species)
+        return PSC_ERR_INVALID;
+    RunDev &R = ctx->runs[run];
+    SpeciesDev &S = R.sp[species];
+    if (n < 0 || n > S.cap) return fail(ctx, PSC_ERR_INVALID, "particle count exceeds capacity");
+    if (n > 0 && (!gcell || !goff || !gu)) return PSC_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    int32_t *keys = ctx->at<int32_t>(ctx->off.load_keys), *idx = ctx->at<int32_t>(ctx->off.load_idx);
+    int32_t *keys_s = ctx->at<int32_t>(ctx->off.load_keys_s), *idx_s = ctx->at<int32_t>(ctx->off.load_idx_s);
+    HIPCHECK(launch_keys(R, n, gcell, keys, idx, ctx->err(), s), "load keys");
+    if (n > 0) {
+        int bits = 1;
+        while ((int64_t(1) << bits) < R.ncell) ++bits;
+        size_t tb = ctx->cub_bytes;
+        HIPCHECK(radix_sort_pairs(ctx->at<void>(ctx->off.cub), &tb, keys, keys_s, idx, idx_s, n, bits, s), "load sort");
+    }
+    HIPCHECK(launch_load_gather(R, species, n, keys_s, idx_s, goff, gu, gid, s), "load gather");
+    HIPCHECK(launch_fill_i32(S.tot, R.ncell, 0, s), "load clear counts");
+    HIPCHECK(launch_count_cells(R, species, n, keys_s, S.tot, s), "load count");
+    const int64_t nb = (R.ncell + kScanBlock - 1) / kScanBlock;
+    ScanSeg seg{S.tot, S.cs[0], R.ncell, 0};
+    HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.load_seg), &seg, sizeof seg, hipMemcpyHostToDevice, s), "load seg");
+    HIPCHECK(launch_fill_i32(ctx->at<int32_t>(ctx->off.load_blockseg), nb, 0, s), "load block table");
+    HIPCHECK(launch_scan(ctx->at<ScanSeg>(ctx->off.load_seg), 1, nb, ctx->at<int32_t>(ctx->off.load_blockseg),
+                         ctx->at<int32_t>(ctx->off.load_sums), s), "load scan");
+    S.n = n;
+    HIPCHECK(hipMemcpyAsync(ctx->at<RunDev>(ctx->off.runs) + run, &R, sizeof(RunDev), hipMemcpyHostToDevice, s),
+             "upload run");
+    HIPCHECK(hipStreamSynchronize(s), "load sync");
+    ctx->loaded[run][species] = true;
+    return PSC_OK;
+}
+
+static psc_status require_loaded(psc_ctx *ctx) {
+    if (!ctx || !ctx->bound) return PSC_ERR_STATE;
+    for (int r = 0; r < ctx->n_runs; ++r)
+        for (int s = 0; s < ctx->runs[r].n_species; ++s)
+            if (!ctx->loaded[r][s]) return fail(ctx, PSC_ERR_STATE, "species not loaded");
+    return PSC_OK;
+}
+
+psc_status psc_push_fields(psc_ctx *ctx, int op, void *stream) {
+    if (!ctx || !ctx->bound) return PSC_ERR_STATE;
+    if (op != PSC_B_HALF && op != PSC_E_FULL) return PSC_ERR_INVALID;
+    Launch L = make_launch(ctx, (hipStream_t)stream);
+    HIPCHECK(launch_fields(L, op, ctx->total_cells, ctx->at<int64_t>(ctx->off.run_base)), "push fields");
+    return PSC_OK;
+}
+
+psc_status psc_push_particles(psc_ctx *ctx, void *stream) {
+    psc_status st = require_loaded(ctx);
+    if (st != PSC_OK) return st;
+    Launch L = make_launch(ctx, (hipStream_t)stream);
+    HIPCHECK(launch_push(L, nullptr, 0, ctx->at<Unit>(ctx->off.units), (int)ctx->units.size(),
+                         ctx->at<int32_t>(ctx->off.item_start), ctx->max_items, ctx->chunk, ctx->dim, ctx->order,
+                         ctx->front, ctx->cs_sel, ctx->perm_pending, ctx->lds, nullptr),
+             "push particles");
+    ctx->front = 1 - ctx->front;
+    ctx->perm_pending = 0;
+    ctx->mc_valid = 1;
+    ctx->stepped = true;
+    return PSC_OK;
+}
+
+psc_status psc_deposit_current(psc_ctx *ctx, void *stream) {
+    if (!ctx || !ctx->bound) return PSC_ERR_STATE;
+    Launch L = make_launch(ctx, (hipStream_t)stream);
+    HIPCHECK(launch_fold(L, ctx->total_cells, ctx->at<int64_t>(ctx->off.run_base)), "deposit current");
+    return PSC_OK;
+}
+
+psc_status psc_sort(psc_ctx *ctx, void *stream) {
+    psc_status st = require_loaded(ctx);
+    if (st != PSC_OK) return st;
+    if (!ctx->mc_valid) return fail(ctx, PSC_ERR_STATE, "psc_sort needs a preceding psc_push_particles");
+    Launch L = make_launch(ctx, (hipStream_t)stream);
+    HIPCHECK(launch_sort(L, ctx->at<int64_t>(ctx->off.seg_base), ctx->at<int32_t>(ctx->off.seg_run),
+                         ctx->at<int32_t>(ctx->off.seg_sp), ctx->n_segs, ctx->total_seg_cells,
+                         ctx->at<ScanSeg>(ctx->cs_sel == 0 ? ctx->off.segs0 : ctx->off.segs1), ctx->n_scan_blocks,
+                         ctx->at<int32_t>(ctx->off.scan_tmp), ctx->cs_sel, ctx->dim),
+             "sort");
+    ctx->cs_sel = 1 - ctx->cs_sel;
+    ctx->perm_pending = 1;
+    ctx->mc_valid = 0;
+    return PSC_OK;
+}
+
+static psc_status one_step(psc_ctx *ctx, void *stream) {
+    psc_status st;
+    if ((st = psc_push_fields(ctx, PSC_B_HALF, stream)) != PSC_OK) return st;
+    if ((st = psc_push_particles(ctx, stream)) != PSC_OK) return st;
+    if ((st = psc_push_fields(ctx, PSC_B_HALF, stream)) != PSC_OK) return st;
+    if ((st = psc_deposit_current(ctx, stream)) != PSC_OK) return st;
+    if ((st = psc_push_fields(ctx, PSC_E_FULL, stream)) != PSC_OK) return st;
+    return psc_sort(ctx, stream);
+}
+
+psc_status psc_step(psc_ctx *ctx, int nsteps, int use_graph, void *stream) {
+    psc_status st = require_loaded(ctx);
+    if (st != PSC_OK) return st;
+    if (nsteps < 0) return PSC_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    for (int k = 0; k < nsteps; ++k) {
+        if (!use_graph) {
+            if ((st = one_step(ctx, stream)) != PSC_OK) return st;
+            continue;
+        }
+        const auto key = std::make_tuple(ctx->front, ctx->cs_sel, ctx->perm_pending);
+        auto it = ctx->graphs.find(key);
+        if (it == ctx->graphs.end()) {
+            const int f = ctx->front, c = ctx->cs_sel, p = ctx->perm_pending, m = ctx->mc_valid;
+            const bool was_stepped = ctx->stepped;
+            // record on a private stream (the caller's may be the legacy null
+            // stream, which cannot be captured); recording runs nothing
+            if (!ctx->cap_stream) HIPCHECK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking), "capture stream");
+            HIPCHECK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+            st = one_step(ctx, (void *)ctx->cap_stream);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
+            if (st != PSC_OK) return st;
+            if (e != hipSuccess) return hipfail(ctx, e, "end capture");
+            hipGraphExec_t ex = nullptr;
+            e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            hipGraphDestroy(g);
+            if (e != hipSuccess) return hipfail(ctx, e, "graph instantiate");
+            it = ctx->graphs.emplace(key, ex).first;
+            // capture recorded the work without running it: restore the state
+            ctx->front = f;
+            ctx->cs_sel = c;
+            ctx->perm_pending = p;
+            ctx->mc_valid = m;
+            ctx->stepped = was_stepped;
+        }
+        HIPCHECK(hipGraphLaunch(it->second, s), "graph launch");
+        ctx->front = 1 - ctx->front;
+        ctx->cs_sel = 1 - ctx->cs_sel;
+        ctx->perm_pending = 1;
+        ctx->mc_valid = 0;
+        ctx->stepped = true;
+    }
+    return PSC_OK;
+}
+
+psc_status psc_get_particles(psc_ctx *ctx, int run, int species, int32_t *cell, float *off, float *u, int32_t *id,
+                             void *stream) {
+    if (!ctx || !ctx->bound) return PSC_ERR_STATE;
+    if (run < 0 || run >= ctx->n_runs || species < 0 || species >= ctx->runs[run].n_species) return PSC_ERR_INVALID;
+    HIPCHECK(launch_get(ctx->runs[run], species, ctx->front, ctx->perm_pending, cell, off, u, id, (hipStream_t)stream),
+             "get particles");
+    return PSC_OK;
+}
+
+psc_status psc_keys_to_cells(psc_ctx *ctx, int run, int64_t n, const int32_t *keys, int32_t *cells, void *stream) {
+    if (!ctx || run < 0 || run >= ctx->n_runs || n < 0 || (n > 0 && (!keys || !cells))) return PSC_ERR_INVALID;
+    HIPCHECK(launch_keys_to_cells(ctx->runs[run], n, keys, cells, (hipStream_t)stream), "keys to cells");
+    return PSC_OK;
+}
+
+psc_status psc_particle_count(const psc_ctx *ctx, int run, int species, int64_t *n) {
+    if (!ctx || !n || run < 0 || run >= ctx->n_runs || species < 0 || species >= ctx->runs[run].n_species)
+        return PSC_ERR_INVALID;
+    *n = ctx->runs[run].sp[species].n;
+    return PSC_OK;
+}
+
+psc_status psc_front(const psc_ctx *ctx, int *front, int *perm_pending) {
+    if (!ctx) return PSC_ERR_INVALID;
+    if (front) *front = ctx->front;
+    if (perm_pending) *perm_pending = ctx->perm_pending;
+    return PSC_OK;
+}
+
+psc_status psc_sort_view(const psc_ctx *ctx, int run, int species, const int32_t **perm, const int32_t **cell_start) {
+    if (!ctx || !ctx->bound || run < 0 || run >= ctx->n_runs || species < 0 || species >= ctx->runs[run].n_species)
+        return PSC_ERR_INVALID;
+    if (perm) *perm = ctx->runs[run].sp[species].perm;
+    if (cell_start) *cell_start = ctx->runs[run].sp[species].cs[ctx->cs_sel];
+    return PSC_OK;
+}
+
+psc_status psc_diagnostics(psc_ctx *ctx, double *out_dev, double *gauss_dev, void *stream) {
+    if (!ctx || !ctx->bound || !out_dev) return PSC_ERR_INVALID;
+    Launch L = make_launch(ctx, (hipStream_t)stream);
+    HIPCHECK(launch_diag(L, out_dev, gauss_dev, ctx->total_cells, ctx->at<int64_t>(ctx->off.run_base), ctx->front),
+             "diagnostics");
+    return PSC_OK;
+}
+
+psc_status psc_check(psc_ctx *ctx, void *stream, uint32_t *word, int clear) {
+    if (!ctx || !ctx->bound) return PSC_ERR_STATE;
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHECK(hipStreamSynchronize(s), "check sync");
+    uint32_t w = 0;
+    HIPCHECK(hipMemcpy(&w, ctx->err(), sizeof w, hipMemcpyDeviceToHost), "read error word");
+    if (clear) HIPCHECK(hipMemset(ctx->err(), 0, sizeof(uint32_t)), "clear error word");
+    if (word) *word = w;
+    if (w & PSC_DEV_NONFINITE) return fail(ctx, PSC_ERR_NONFINITE, "non-finite momentum");
+    if (w & (PSC_DEV_MOVE | PSC_DEV_KEY | PSC_DEV_OVERFULL))
+        return fail(ctx, PSC_ERR_PARTICLE, "particle moved too far, had a bad key, or a cell overflowed");
+    return PSC_OK;
+}
+
+psc_status psc_destroy(psc_ctx *ctx) {
+    if (!ctx) return PSC_ERR_INVALID;
+    for (auto &kv : ctx->graphs) hipGraphExecDestroy(kv.second);
+    if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
+    delete ctx;
+    return PSC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,207 @@
+// psc_internal.h -- device descriptors and index helpers of the HIP library.
+//
+// Data layout in HBM (all float32 unless noted):
+//   fields   E, B, J: 3 * ncell per run, component-major, x fastest.
+//   particles: per species two buffer sets (ping-pong) of SoA arrays
+//            cell (int32 patch-major key), off[D] (in-cell offsets),
+//            u[3] (momentum per mass), optional id (int32).
+//   workspace (library-carved, caller-allocated):
+//            per patch a current tile of 3 * jt[0]*jt[1]*jt[2] floats
+//            (patch cells plus `order` ghost layers below and order+1
+//            above, in the patch's own tile coordinates);
+//            per species two cell-offset arrays cs (int32, ncell + 1),
+//            the permutation (int32), per-particle move codes (uint8),
+//            per-(cell, move) counts and prefixes (uint16, 3^D * ncell),
+//            arrival totals (int32, ncell); per run an FP64 charge array
+//            for the diagnostics; the work tables; the error word.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/psc.h"
+
+namespace psc {
+
+constexpr int kMaxSpecies = PSC_MAX_SPECIES;
+constexpr int kBlock = 256;          // threads per workgroup of the particle kernel
+constexpr int kScanPerThread = 8;    // elements per thread in the scans
+constexpr int kScanBlock = 256 * kScanPerThread;
+
+struct SpeciesDev {
+    float q, m, w;
+    float qdt_2m;        // q dt / (2 m)
+    float qw;            // q * w
+    int32_t pad0;
+    int64_t n;           // particles held
+    int64_t cap;         // slots per buffer (array stride)
+    int32_t *cell[2];
+    float *off[2];
+    float *u[2];
+    int32_t *id[2];      // both null when ids are not carried
+    int32_t *cs[2];      // cell start offsets, ncell + 1
+    int32_t *perm;       // sorted slot -> index in the pushed buffer
+    uint8_t *mc;         // move code of each pushed particle
+    uint16_t *cnt;       // [m * ncell + cell]: particles of `cell` with move m
+    uint16_t *pre;       // [m * ncell + cell]: arrivals into cell+d(m) that precede them
+    int32_t *tot;        // arrivals per new cell (scan input)
+    int64_t seg;         // index of this (run, species) among scan segments
+};
+
+struct RunDev {
+    int dim, order;
+    int n[3];            // cells
+    int P[3];            // nominal patch size
+    int np[3];           // patches per dimension
+    int n_patches;
+    int n_species;
+    int64_t ncell;
+    int64_t cell_base;   // offset of the run in the flat cell space of all runs
+    float dx[3];
+    float inv_dx[3];
+    float dt;
+    int jt[3];           // current-tile extent per dimension
+    int64_t jtile_cells; // jt[0]*jt[1]*jt[2]
+    float *E, *B, *J;
+    float *jtile;        // n_patches * 3 * jtile_cells
+    double *rho;         // ncell, diagnostics scratch
+    SpeciesDev sp[kMaxSpecies];
+};
+
+// One (run, species, patch) unit of particle work.
+struct Unit {
+    int32_t run, species, patch, pad;
+};
+
+// Scan segment: one (run, species) array of ncell counts.
+struct ScanSeg {
+    int32_t *in;         // ncell counts
+    int32_t *out;        // ncell + 1 exclusive prefix
+    int64_t n;
+    int64_t block0;      // first scan block of the segment
+};
+
+// ----------------------------------------------------------------------------
+// ghost widths
+// ----------------------------------------------------------------------------
+// Field tile: one layer below, `order` above (interpolation supports).
+// Current tile: `order` below, `order + 1` above (Esirkepov stencils of a
+// particle that moves at most one cell).
+__host__ __device__ inline int field_lo(int) { return 1; }
+__host__ __device__ inline int field_hi(int order) { return order; }
+__host__ __device__ inline int cur_lo(int order) { return order; }
+__host__ __device__ inline int cur_hi(int order) { return order + 1; }
+
+__host__ __device__ inline int imin(int a, int b) { return a < b ? a : b; }
+__host__ __device__ inline int wrap(int i, int n) {
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+// actual extent of patch coordinate pc along d (the last one is truncated)
+__host__ __device__ inline int patch_ext(const RunDev &r, int d, int pc) {
+    return imin(r.P[d], r.n[d] - pc * r.P[d]);
+}
+
+// key of the first cell of patch (pi, pj, pk)
+__host__ __device__ inline int64_t patch_key_base(const RunDev &r, int pi, int pj, int pk) {
+    int64_t hz = patch_ext(r, 2, pk), hy = patch_ext(r, 1, pj);
+    return (int64_t)pk * r.P[2] * r.n[1] * r.n[0] + (int64_t)pj * r.P[1] * hz * r.n[0] +
+           (int64_t)pi * r.P[0] * hy * hz;
+}
+
+__host__ __device__ inline void patch_coords(const RunDev &r, int p, int pc[3]) {
+    pc[0] = p % r.np[0];
+    pc[1] = (p / r.np[0]) % r.np[1];
+    pc[2] = p / (r.np[0] * r.np[1]);
+}
+
+// patch-major key of geometric cell (i, j, k) (already wrapped)
+__host__ __device__ inline int64_t encode_key(const RunDev &r, int i, int j, int k) {
+    int pi = i / r.P[0], pj = j / r.P[1], pk = k / r.P[2];
+    int hx = patch_ext(r, 0, pi), hy = patch_ext(r, 1, pj);
+    int li = i - pi * r.P[0], lj = j - pj * r.P[1], lk = k - pk * r.P[2];
+    return patch_key_base(r, pi, pj, pk) + li + (int64_t)hx * (lj + (int64_t)hy * lk);
+}
+
+// inverse of encode_key
+__host__ __device__ inline void decode_key(const RunDev &r, int64_t key, int g[3]) {
+    int64_t slab = (int64_t)r.P[2] * r.n[1] * r.n[0];
+    int pk = (int)(key / slab);
+    int64_t rem = key - pk * slab;
+    int hz = patch_ext(r, 2, pk);
+    int64_t row = (int64_t)r.P[1] * hz * r.n[0];
+    int pj = (int)(rem / row);
+    rem -= pj * row;
+    int hy = patch_ext(r, 1, pj);
+    int64_t pcells = (int64_t)r.P[0] * hy * hz;
+    int pi = (int)(rem / pcells);
+    rem -= pi * pcells;
+    int hx = patch_ext(r, 0, pi);
+    int li = (int)(rem % hx);
+    rem /= hx;
+    int lj = (int)(rem % hy);
+    int lk = (int)(rem / hy);
+    g[0] = pi * r.P[0] + li;
+    g[1] = pj * r.P[1] + lj;
+    g[2] = pk * r.P[2] + lk;
+}
+
+// number of move codes and the code of "stays in its cell"
+__host__ __device__ inline int n_moves(int dim) { return dim == 3 ? 27 : 9; }
+
+// displacement (-1, 0, 1 per dimension) of move code m
+__host__ __device__ inline void move_delta(int dim, int m, int d[3]) {
+    if (dim == 3) {
+        d[0] = m % 3 - 1;
+        d[1] = (m / 3) % 3 - 1;
+        d[2] = m / 9 - 1;
+    } else {
+        d[0] = 0;
+        d[1] = m % 3 - 1;
+        d[2] = m / 3 - 1;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// launchers (defined in the .hip files)
+// ----------------------------------------------------------------------------
+struct Launch {
+    const RunDev *runs_dev;   // device copy of the run table
+    const RunDev *runs_host;  // host copy
+    int n_runs;
+    hipStream_t stream;
+    uint32_t *err;            // device error word
+};
+
+hipError_t launch_push(const Launch &L, const int *run_ids, int n_ids, const Unit *units_dev,
+                       int n_units, int32_t *item_start, int64_t max_items, int chunk, int dim,
+                       int order, int front, int cs_sel, int use_perm, size_t lds_bytes,
+                       int32_t *scan_tmp);
+hipError_t launch_fields(const Launch &L, int op, int64_t total_cells, const int64_t *run_cell_base_dev);
+hipError_t launch_fold(const Launch &L, int64_t total_cells, const int64_t *run_cell_base_dev);
+hipError_t launch_sort(const Launch &L, const int64_t *seg_cell_base_dev, const int32_t *seg_run_dev,
+                       const int32_t *seg_species_dev, int n_segs, int64_t total_seg_cells,
+                       const ScanSeg *segs_dev, int64_t n_scan_blocks, int32_t *scan_tmp, int cs_sel,
+                       int max_dim);
+hipError_t launch_scan(const ScanSeg *segs_dev, int n_segs, int64_t n_blocks,
+                       const int32_t *block_seg_dev, int32_t *block_sums, hipStream_t s);
+hipError_t launch_keys(const RunDev &r, int64_t n, const int32_t *gcell, int32_t *keys, int32_t *idx,
+                       uint32_t *err, hipStream_t s);
+hipError_t launch_keys_to_cells(const RunDev &r, int64_t n, const int32_t *keys, int32_t *cells,
+                                hipStream_t s);
+hipError_t launch_load_gather(const RunDev &r, int species, int64_t n, const int32_t *sorted_keys,
+                              const int32_t *sorted_idx, const float *goff, const float *gu,
+                              const int32_t *gid, hipStream_t s);
+hipError_t launch_count_cells(const RunDev &r, int species, int64_t n, const int32_t *sorted_keys,
+                              int32_t *tot, hipStream_t s);
+hipError_t launch_get(const RunDev &r, int species, int front, int perm_pending, int32_t *cell,
+                      float *off, float *u, int32_t *id, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_diag(const Launch &L, double *out, double *gauss, int64_t total_cells,
+                       const int64_t *run_cell_base_dev, int front);
+hipError_t radix_sort_pairs(void *temp, size_t *temp_bytes, const int32_t *keys_in, int32_t *keys_out,
+                            const int32_t *vals_in, int32_t *vals_out, int64_t n, int bits,
+                            hipStream_t s);
+
+}  // namespace psc

@@ -1,0 +1,515 @@
+// psc_push.hip -- the fused particle kernel: field interpolation, relativistic
+// Boris push, position update and Esirkepov current deposit (paper: section
+// "Time integration of the quasi-particle equations of motion", fig. psc_new
+// particle loop; GPU design: sections "Particle Advance and Field
+// Interpolation", "Current deposition" and "Fusing of GPU kernels").
+//
+// One workgroup takes one work item = up to `chunk` consecutive particles of
+// one (run, species, patch).  It stages E and B of the patch plus ghost layers
+// in LDS, zeroes an LDS current tile, pushes its particles (reading them
+// through the sort permutation, writing them in sorted order into the other
+// buffer set, so the physical reorder of the sort costs no extra pass), and
+// adds the LDS tile into the patch's current tile in HBM.
+#include "psc_internal.h"
+
+namespace psc {
+
+// ---------------------------------------------------------------------------
+// B-spline weights (b1 or b2 evaluated at the nodes around the particle)
+// ---------------------------------------------------------------------------
+// Position given as in-cell offset o in [0, 1) of cell 0.  "node" weights are
+// for quantities located at integer positions, "half" weights for quantities
+// located at half-integer positions (stored at their lower index).  Returns
+// the first node (relative to the cell) and ORDER+1 weights.
+template <int ORDER>
+__device__ __forceinline__ int node_weights(float o, float w[ORDER + 1]) {
+    if constexpr (ORDER == 1) {
+        w[0] = 1.0f - o;
+        w[1] = o;
+        return 0;
+    } else {
+        const int up = o >= 0.5f;
+        const float d = o - (float)up;  // distance from the nearest node, [-1/2, 1/2)
+        const float a = 0.5f - d, b = 0.5f + d;
+        w[0] = 0.5f * a * a;
+        w[1] = 0.75f - d * d;
+        w[2] = 0.5f * b * b;
+        return up - 1;
+    }
+}
+
+template <int ORDER>
+__device__ __forceinline__ int half_weights(float o, float w[ORDER + 1]) {
+    if constexpr (ORDER == 1) {
+        const int up = o >= 0.5f;
+        const float d = up ? o - 0.5f : o + 0.5f;
+        w[0] = 1.0f - d;
+        w[1] = d;
+        return up - 1;
+    } else {
+        const float d = o - 0.5f;
+        const float a = 0.5f - d, b = 0.5f + d;
+        w[0] = 0.5f * a * a;
+        w[1] = 0.75f - d * d;
+        w[2] = 0.5f * b * b;
+        return -1;
+    }
+}
+
+// Start and end weights of one dimension on a common stencil of ORDER+2
+// nodes: the particle starts at offset o0 in cell 0 and ends at offset o1 in
+// cell s (|s| <= 1).  Both weight sets use node_weights so that the end
+// weights equal the start weights of the next step bit for bit.
+template <int ORDER>
+__device__ __forceinline__ int stencil(float o0, int s, float o1, float S0[ORDER + 2], float S1[ORDER + 2]) {
+    float w0[ORDER + 1], w1[ORDER + 1];
+    const int b0 = node_weights<ORDER>(o0, w0);
+    const int b1 = node_weights<ORDER>(o1, w1) + s;
+    const int base = b0 < b1 ? b0 : b1;
+    const bool k0 = b0 != base, k1 = b1 != base;
+#pragma unroll
+    for (int r = 0; r < ORDER + 2; ++r) {
+        const float lo0 = r <= ORDER ? w0[r] : 0.0f, hi0 = r >= 1 ? w0[r - 1] : 0.0f;
+        const float lo1 = r <= ORDER ? w1[r] : 0.0f, hi1 = r >= 1 ? w1[r - 1] : 0.0f;
+        S0[r] = k0 ? hi0 : lo0;
+        S1[r] = k1 ? hi1 : lo1;
+    }
+    return base;
+}
+
+// ---------------------------------------------------------------------------
+// interpolation from an LDS tile
+// ---------------------------------------------------------------------------
+template <int ORDER>
+__device__ __forceinline__ float gather2(const float *F, int pitch, int iy, int iz, const float *wy,
+                                         const float *wz) {
+    const float *p = F + iz * pitch + iy;
+    float s = 0.0f;
+#pragma unroll
+    for (int b = 0; b <= ORDER; ++b) {
+        float r = 0.0f;
+#pragma unroll
+        for (int a = 0; a <= ORDER; ++a) r = fmaf(wy[a], p[b * pitch + a], r);
+        s = fmaf(wz[b], r, s);
+    }
+    return s;
+}
+
+template <int ORDER>
+__device__ __forceinline__ float gather3(const float *F, int px, int pxy, int ix, int iy, int iz,
+                                         const float *wx, const float *wy, const float *wz) {
+    const float *p = F + iz * pxy + iy * px + ix;
+    float s = 0.0f;
+#pragma unroll
+    for (int c = 0; c <= ORDER; ++c) {
+        float t = 0.0f;
+#pragma unroll
+        for (int b = 0; b <= ORDER; ++b) {
+            float r = 0.0f;
+#pragma unroll
+            for (int a = 0; a <= ORDER; ++a) r = fmaf(wx[a], p[c * pxy + b * px + a], r);
+            t = fmaf(wy[b], r, t);
+        }
+        s = fmaf(wz[c], t, s);
+    }
+    return s;
+}
+
+__device__ __forceinline__ void lds_add(float *p, float v) { atomicAdd(p, v); }
+
+// fast quotient/remainder for small non-negative a
+__device__ __forceinline__ int divmod_small(int a, int b, float inv_b, int &rem) {
+    int q = (int)((float)a * inv_b);
+    int r = a - q * b;
+    if (r < 0) { --q; r += b; }
+    else if (r >= b) { ++q; r -= b; }
+    rem = r;
+    return q;
+}
+
+// ---------------------------------------------------------------------------
+// work items
+// ---------------------------------------------------------------------------
+// One workgroup computes, per unit, how many chunks its particles need and the
+// exclusive prefix item_start[0..n_units].
+__global__ void __launch_bounds__(1024) k_build_items(const RunDev *__restrict__ runs, const Unit *__restrict__ units,
+                                                      int n_units, int chunk, int cs_sel,
+                                                      int32_t *__restrict__ item_start) {
+    __shared__ int32_t part[1024];
+    const int t = threadIdx.x;
+    const int per = (n_units + 1023) / 1024;
+    const int u0 = t * per, u1 = imin(u0 + per, n_units);
+    int32_t sum = 0;
+    for (int u = u0; u < u1; ++u) {
+        const Unit U = units[u];
+        const RunDev &R = runs[U.run];
+        int pc[3];
+        patch_coords(R, U.patch, pc);
+        const int64_t kb = patch_key_base(R, pc[0], pc[1], pc[2]);
+        const int64_t ke = kb + (int64_t)patch_ext(R, 0, pc[0]) * patch_ext(R, 1, pc[1]) * patch_ext(R, 2, pc[2]);
+        const int32_t *cs = R.sp[U.species].cs[cs_sel];
+        const int32_t cnt = cs[ke] - cs[kb];
+        sum += (cnt + chunk - 1) / chunk;
+    }
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int32_t v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int32_t run = part[t] - sum;  // exclusive
+    for (int u = u0; u < u1; ++u) {
+        item_start[u] = run;
+        const Unit U = units[u];
+        const RunDev &R = runs[U.run];
+        int pc[3];
+        patch_coords(R, U.patch, pc);
+        const int64_t kb = patch_key_base(R, pc[0], pc[1], pc[2]);
+        const int64_t ke = kb + (int64_t)patch_ext(R, 0, pc[0]) * patch_ext(R, 1, pc[1]) * patch_ext(R, 2, pc[2]);
+        const int32_t *cs = R.sp[U.species].cs[cs_sel];
+        run += (cs[ke] - cs[kb] + chunk - 1) / chunk;
+    }
+    if (t == 1023) item_start[n_units] = part[1023];
+}
+
+// ---------------------------------------------------------------------------
+// the particle kernel
+// ---------------------------------------------------------------------------
+template <int DIM, int ORDER>
+__global__ void __launch_bounds__(kBlock) k_push(const RunDev *__restrict__ runs, const Unit *__restrict__ units,
+                                                 const int32_t *__restrict__ item_start, int n_units,
+                                                 int chunk, int front, int cs_sel, int use_perm,
+                                                 uint32_t *__restrict__ err) {
+    extern __shared__ float lds[];
+    constexpr int L = ORDER + 2;          // Esirkepov stencil nodes per dimension
+    constexpr int FLO = 1, FHI = ORDER;   // field ghosts
+    constexpr int JLO = ORDER, JHI = ORDER + 1;
+
+    // XCD-aware item order: workgroups are dispatched round-robin over the 8
+    // XCDs; give each XCD a contiguous range of items so that the chunks of a
+    // patch share one L2.
+    const int nb = gridDim.x;
+    const int item = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+    const int total = item_start[n_units];
+    if (item >= total) return;
+    int lo = 0, hi = n_units;  // find u with item_start[u] <= item < item_start[u+1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (item_start[mid] <= item) lo = mid; else hi = mid;
+    }
+    const Unit U = units[lo];
+    const RunDev &R = runs[U.run];
+    const SpeciesDev &S = R.sp[U.species];
+
+    int pc[3];
+    patch_coords(R, U.patch, pc);
+    const int hx = DIM == 3 ? patch_ext(R, 0, pc[0]) : 1;
+    const int hy = patch_ext(R, 1, pc[1]);
+    const int hz = patch_ext(R, 2, pc[2]);
+    const int ox = pc[0] * R.P[0], oy = pc[1] * R.P[1], oz = pc[2] * R.P[2];
+    const int64_t kb = patch_key_base(R, pc[0], pc[1], pc[2]);
+    const int32_t *cs = S.cs[cs_sel];
+    const int32_t pbeg = cs[kb], pend = cs[kb + (int64_t)hx * hy * hz];
+    const int32_t beg = pbeg + (item - item_start[lo]) * chunk;
+    const int32_t end = min(beg + chunk, pend);
+
+    // tile geometry (nominal patch size so every tile of the run has one pitch)
+    const int fx = DIM == 3 ? R.P[0] + FLO + FHI : 1;
+    const int fy = R.P[1] + FLO + FHI, fz = R.P[2] + FLO + FHI;
+    const int fcells = fx * fy * fz;
+    const int jx_ = DIM == 3 ? R.P[0] + JLO + JHI : 1;
+    const int jy_ = R.P[1] + JLO + JHI, jz_ = R.P[2] + JLO + JHI;
+    const int jcells = jx_ * jy_ * jz_;
+    float *ftile = lds;               // 6 * fcells: Ex Ey Ez Bx By Bz
+    float *jtile = lds + 6 * fcells;  // 3 * jcells: Jx Jy Jz
+
+    // stage E, B (+ghosts) and clear the current tile
+    {
+        const float inv_fx = 1.0f / fx, inv_fy = 1.0f / fy;
+        const int64_t nc = R.ncell;
+        for (int t = threadIdx.x; t < fcells; t += kBlock) {
+            int tx = 0, ty, tz, r;
+            if constexpr (DIM == 3) {
+                const int q = divmod_small(t, fx, inv_fx, tx);
+                tz = divmod_small(q, fy, inv_fy, ty);
+            } else {
+                tz = divmod_small(t, fy, inv_fy, ty);
+            }
+            (void)r;
+            const int gx = DIM == 3 ? wrap(ox + tx - FLO, R.n[0]) : 0;
+            const int gy = wrap(oy + ty - FLO, R.n[1]);
+            const int gz = wrap(oz + tz - FLO, R.n[2]);
+            const int64_t g = gx + (int64_t)R.n[0] * (gy + (int64_t)R.n[1] * gz);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                ftile[c * fcells + t] = R.E[c * nc + g];
+                ftile[(3 + c) * fcells + t] = R.B[c * nc + g];
+            }
+        }
+        for (int t = threadIdx.x; t < 3 * jcells; t += kBlock) jtile[t] = 0.0f;
+    }
+    __syncthreads();
+
+    const int in = front, outb = 1 - front;
+    const int32_t *__restrict__ cell_in = S.cell[in];
+    const float *__restrict__ off_in = S.off[in];
+    const float *__restrict__ u_in = S.u[in];
+    const int32_t *__restrict__ id_in = S.id[in];
+    int32_t *__restrict__ cell_out = S.cell[outb];
+    float *__restrict__ off_out = S.off[outb];
+    float *__restrict__ u_out = S.u[outb];
+    int32_t *__restrict__ id_out = S.id[outb];
+    const int32_t *__restrict__ perm = S.perm;
+    uint8_t *__restrict__ mc = S.mc;
+    const int64_t cap = S.cap;
+    const float h = S.qdt_2m;
+    const float qw = S.qw;
+    const float dt = R.dt;
+    const float cfx = DIM == 3 ? dt * R.inv_dx[0] : 0.0f;
+    const float cfy = dt * R.inv_dx[1], cfz = dt * R.inv_dx[2];
+    const float jfx = -qw * R.dx[0] / dt, jfy = -qw * R.dx[1] / dt, jfz = -qw * R.dx[2] / dt;
+    const float inv_hx = 1.0f / hx, inv_hy = 1.0f / hy;
+    const int pcells = hx * hy * hz;
+    uint32_t flags = 0;
+
+    for (int32_t i = beg + threadIdx.x; i < end; i += kBlock) {
+        int32_t src = use_perm ? perm[i] : i;
+        if ((uint32_t)src >= (uint32_t)S.n) {   // corrupt permutation: stay in bounds
+            flags |= PSC_DEV_KEY;
+            src = i;
+        }
+        const int32_t key = cell_in[src];
+        float o[3];
+        o[0] = DIM == 3 ? off_in[src] : 0.0f;
+        o[1] = off_in[(DIM == 3 ? 1 : 0) * cap + src];
+        o[2] = off_in[(DIM == 3 ? 2 : 1) * cap + src];
+        float ux = u_in[src], uy = u_in[cap + src], uz = u_in[2 * cap + src];
+        const int32_t idv = id_in ? id_in[src] : 0;
+
+        int local = key - (int32_t)kb;
+        if (local < 0 || local >= pcells) {  // not in this patch: corrupt state
+            flags |= PSC_DEV_KEY;
+            local = 0;
+        }
+        int lx = 0, ly, lz;
+        if constexpr (DIM == 3) {
+            const int q = divmod_small(local, hx, inv_hx, lx);
+            lz = divmod_small(q, hy, inv_hy, ly);
+        } else {
+            lz = divmod_small(local, hy, inv_hy, ly);
+        }
+
+        // ---- interpolation ------------------------------------------------
+        float wny[ORDER + 1], why[ORDER + 1], wnz[ORDER + 1], whz[ORDER + 1];
+        const int bny = node_weights<ORDER>(o[1], wny), bhy = half_weights<ORDER>(o[1], why);
+        const int bnz = node_weights<ORDER>(o[2], wnz), bhz = half_weights<ORDER>(o[2], whz);
+        float Ex, Ey, Ez, Bx, By, Bz;
+        if constexpr (DIM == 2) {
+            const int ty = ly + FLO, tz = lz + FLO;
+            Ex = gather2<ORDER>(ftile + 0 * fcells, fy, ty + bny, tz + bnz, wny, wnz);
+            Ey = gather2<ORDER>(ftile + 1 * fcells, fy, ty + bhy, tz + bnz, why, wnz);
+            Ez = gather2<ORDER>(ftile + 2 * fcells, fy, ty + bny, tz + bhz, wny, whz);
+            Bx = gather2<ORDER>(ftile + 3 * fcells, fy, ty + bhy, tz + bhz, why, whz);
+            By = gather2<ORDER>(ftile + 4 * fcells, fy, ty + bny, tz + bhz, wny, whz);
+            Bz = gather2<ORDER>(ftile + 5 * fcells, fy, ty + bhy, tz + bnz, why, wnz);
+        } else {
+            float wnx[ORDER + 1], whx[ORDER + 1];
+            const int bnx = node_weights<ORDER>(o[0], wnx), bhx = half_weights<ORDER>(o[0], whx);
+            const int tx = lx + FLO, ty = ly + FLO, tz = lz + FLO;
+            const int pxy = fx * fy;
+            Ex = gather3<ORDER>(ftile + 0 * fcells, fx, pxy, tx + bhx, ty + bny, tz + bnz, whx, wny, wnz);
+            Ey = gather3<ORDER>(ftile + 1 * fcells, fx, pxy, tx + bnx, ty + bhy, tz + bnz, wnx, why, wnz);
+            Ez = gather3<ORDER>(ftile + 2 * fcells, fx, pxy, tx + bnx, ty + bny, tz + bhz, wnx, wny, whz);
+            Bx = gather3<ORDER>(ftile + 3 * fcells, fx, pxy, tx + bnx, ty + bhy, tz + bhz, wnx, why, whz);
+            By = gather3<ORDER>(ftile + 4 * fcells, fx, pxy, tx + bhx, ty + bny, tz + bhz, whx, wny, whz);
+            Bz = gather3<ORDER>(ftile + 5 * fcells, fx, pxy, tx + bhx, ty + bhy, tz + bnz, whx, why, wnz);
+        }
+
+        // ---- relativistic Boris push: half E kick, rotation, half E kick --
+        {
+            const float mx = fmaf(h, Ex, ux), my = fmaf(h, Ey, uy), mz = fmaf(h, Ez, uz);
+            const float igm = rsqrtf(1.0f + mx * mx + my * my + mz * mz);
+            const float tx = h * Bx * igm, ty = h * By * igm, tz = h * Bz * igm;
+            const float f = 2.0f / (1.0f + tx * tx + ty * ty + tz * tz);
+            const float sx = f * tx, sy = f * ty, sz = f * tz;
+            const float px = mx + (my * tz - mz * ty);
+            const float py = my + (mz * tx - mx * tz);
+            const float pz = mz + (mx * ty - my * tx);
+            ux = fmaf(h, Ex, mx + (py * sz - pz * sy));
+            uy = fmaf(h, Ey, my + (pz * sx - px * sz));
+            uz = fmaf(h, Ez, mz + (px * sy - py * sx));
+        }
+        const float ig = rsqrtf(1.0f + ux * ux + uy * uy + uz * uz);
+        if (!(ig > 0.0f)) flags |= PSC_DEV_NONFINITE;   // NaN or Inf momentum
+
+        // ---- move: xi^{n+3/2} = xi^{n+1/2} + dt u^{n+1} / (gamma dx) -------
+        int s[3] = {0, 0, 0};
+        float o1[3] = {o[0], o[1], o[2]};
+#pragma unroll
+        for (int d = (DIM == 3 ? 0 : 1); d < 3; ++d) {
+            const float cf = d == 0 ? cfx : (d == 1 ? cfy : cfz);
+            const float uu = d == 0 ? ux : (d == 1 ? uy : uz);
+            float disp = cf * uu * ig;
+            if (!(fabsf(disp) < 0.99f)) {   // CFL broken or non-finite: keep it in bounds
+                flags |= PSC_DEV_MOVE;
+                disp = 0.0f;
+            }
+            const float x1 = o[d] + disp;
+            int sd = (int)floorf(x1);
+            float od = x1 - (float)sd;
+            if (od >= 1.0f) { od -= 1.0f; sd += 1; }
+            s[d] = sd;
+            o1[d] = od;
+        }
+
+        // ---- Esirkepov deposit into the LDS current tile --------------------
+        {
+            float S0y[L], S1y[L], S0z[L], S1z[L];
+            const int by = stencil<ORDER>(o[1], s[1], o1[1], S0y, S1y);
+            const int bz = stencil<ORDER>(o[2], s[2], o1[2], S0z, S1z);
+            float DSy[L], DSz[L], Ay[L], Az[L], Cy[L], Cz[L];
+#pragma unroll
+            for (int r = 0; r < L; ++r) {
+                DSy[r] = S1y[r] - S0y[r];
+                DSz[r] = S1z[r] - S0z[r];
+                Ay[r] = fmaf(0.5f, DSy[r], S0y[r]);
+                Az[r] = fmaf(0.5f, DSz[r], S0z[r]);
+                Cy[r] = r == 0 ? DSy[0] : Cy[r - 1] + DSy[r];
+                Cz[r] = r == 0 ? DSz[0] : Cz[r - 1] + DSz[r];
+            }
+            float *Jx = jtile, *Jy = jtile + jcells, *Jz = jtile + 2 * jcells;
+            if constexpr (DIM == 2) {
+                const int base = (lz + bz + JLO) * jy_ + (ly + by + JLO);
+                const float vx = ux * ig;
+                const float fxv = qw * vx;
+#pragma unroll
+                for (int b = 0; b < L; ++b)
+#pragma unroll
+                    for (int a = 0; a < L - 1; ++a) lds_add(&Jy[base + b * jy_ + a], jfy * Cy[a] * Az[b]);
+#pragma unroll
+                for (int b = 0; b < L - 1; ++b)
+#pragma unroll
+                    for (int a = 0; a < L; ++a) lds_add(&Jz[base + b * jy_ + a], jfz * Ay[a] * Cz[b]);
+#pragma unroll
+                for (int b = 0; b < L; ++b)
+#pragma unroll
+                    for (int a = 0; a < L; ++a)
+                        lds_add(&Jx[base + b * jy_ + a], fxv * fmaf(DSy[a] * DSz[b], 1.0f / 12.0f, Ay[a] * Az[b]));
+            } else {
+                float S0x[L], S1x[L];
+                const int bx = stencil<ORDER>(o[0], s[0], o1[0], S0x, S1x);
+                float DSx[L], Ax[L], Cx[L];
+#pragma unroll
+                for (int r = 0; r < L; ++r) {
+                    DSx[r] = S1x[r] - S0x[r];
+                    Ax[r] = fmaf(0.5f, DSx[r], S0x[r]);
+                    Cx[r] = r == 0 ? DSx[0] : Cx[r - 1] + DSx[r];
+                }
+                const int pxy = jx_ * jy_;
+                const int base = (lz + bz + JLO) * pxy + (ly + by + JLO) * jx_ + (lx + bx + JLO);
+#pragma unroll
+                for (int c = 0; c < L; ++c)
+#pragma unroll
+                    for (int b = 0; b < L; ++b) {
+                        const float wyz = fmaf(DSy[b] * DSz[c], 1.0f / 12.0f, Ay[b] * Az[c]);
+#pragma unroll
+                        for (int a = 0; a < L - 1; ++a) lds_add(&Jx[base + c * pxy + b * jx_ + a], jfx * Cx[a] * wyz);
+                    }
+#pragma unroll
+                for (int c = 0; c < L; ++c)
+#pragma unroll
+                    for (int b = 0; b < L - 1; ++b)
+#pragma unroll
+                        for (int a = 0; a < L; ++a) {
+                            const float wxz = fmaf(DSx[a] * DSz[c], 1.0f / 12.0f, Ax[a] * Az[c]);
+                            lds_add(&Jy[base + c * pxy + b * jx_ + a], jfy * Cy[b] * wxz);
+                        }
+#pragma unroll
+                for (int c = 0; c < L - 1; ++c)
+#pragma unroll
+                    for (int b = 0; b < L; ++b)
+#pragma unroll
+                        for (int a = 0; a < L; ++a) {
+                            const float wxy = fmaf(DSx[a] * DSy[b], 1.0f / 12.0f, Ax[a] * Ay[b]);
+                            lds_add(&Jz[base + c * pxy + b * jx_ + a], jfz * Cz[c] * wxy);
+                        }
+            }
+        }
+
+        // ---- new cell key and move code ------------------------------------
+        const int nlx = lx + s[0], nly = ly + s[1], nlz = lz + s[2];
+        int32_t nkey;
+        if (nlx >= 0 && nlx < hx && nly >= 0 && nly < hy && nlz >= 0 && nlz < hz) {
+            nkey = (int32_t)kb + nlx + hx * (nly + hy * nlz);
+        } else {
+            const int gx = DIM == 3 ? wrap(ox + nlx, R.n[0]) : 0;
+            nkey = (int32_t)encode_key(R, gx, wrap(oy + nly, R.n[1]), wrap(oz + nlz, R.n[2]));
+        }
+        cell_out[i] = nkey;
+        if constexpr (DIM == 3) {
+            off_out[i] = o1[0];
+            off_out[cap + i] = o1[1];
+            off_out[2 * cap + i] = o1[2];
+            mc[i] = (uint8_t)((s[0] + 1) + 3 * (s[1] + 1) + 9 * (s[2] + 1));
+        } else {
+            off_out[i] = o1[1];
+            off_out[cap + i] = o1[2];
+            mc[i] = (uint8_t)((s[1] + 1) + 3 * (s[2] + 1));
+        }
+        u_out[i] = ux;
+        u_out[cap + i] = uy;
+        u_out[2 * cap + i] = uz;
+        if (id_out) id_out[i] = idv;
+    }
+    if (flags) atomicOr(err, flags);
+    __syncthreads();
+
+    // add the LDS current tile into the patch's tile in HBM
+    float *gt = R.jtile + (int64_t)U.patch * 3 * jcells;
+    for (int t = threadIdx.x; t < 3 * jcells; t += kBlock) {
+        const float v = jtile[t];
+        if (v != 0.0f) atomicAdd(&gt[t], v);
+    }
+}
+
+template <int DIM, int ORDER>
+static hipError_t launch_push_t(const Launch &L, const Unit *units, int n_units, int32_t *item_start,
+                                int64_t max_items, int chunk, int front, int cs_sel, int use_perm,
+                                size_t lds) {
+    hipLaunchKernelGGL(k_build_items, dim3(1), dim3(1024), 0, L.stream, L.runs_dev, units, n_units, chunk,
+                       cs_sel, item_start);
+    int64_t grid = (max_items + 7) / 8 * 8;
+    if (grid < 8) grid = 8;
+    hipLaunchKernelGGL((k_push<DIM, ORDER>), dim3((unsigned)grid), dim3(kBlock), lds, L.stream, L.runs_dev,
+                       units, item_start, n_units, chunk, front, cs_sel, use_perm, L.err);
+    return hipGetLastError();
+}
+
+hipError_t launch_push(const Launch &L, const int *, int, const Unit *units_dev, int n_units,
+                       int32_t *item_start, int64_t max_items, int chunk, int dim, int order, int front,
+                       int cs_sel, int use_perm, size_t lds_bytes, int32_t *) {
+    if (dim == 2 && order == 1)
+        return launch_push_t<2, 1>(L, units_dev, n_units, item_start, max_items, chunk, front, cs_sel, use_perm, lds_bytes);
+    if (dim == 2 && order == 2)
+        return launch_push_t<2, 2>(L, units_dev, n_units, item_start, max_items, chunk, front, cs_sel, use_perm, lds_bytes);
+    if (dim == 3 && order == 1)
+        return launch_push_t<3, 1>(L, units_dev, n_units, item_start, max_items, chunk, front, cs_sel, use_perm, lds_bytes);
+    if (dim == 3 && order == 2)
+        return launch_push_t<3, 2>(L, units_dev, n_units, item_start, max_items, chunk, front, cs_sel, use_perm, lds_bytes);
+    return hipErrorInvalidValue;
+}
+
+// LDS bytes the particle kernel of a run needs
+size_t push_lds_bytes(int dim, int order, const int P[3]) {
+    const int fx = dim == 3 ? P[0] + field_lo(order) + field_hi(order) : 1;
+    const int fy = P[1] + field_lo(order) + field_hi(order);
+    const int fz = P[2] + field_lo(order) + field_hi(order);
+    const int jx = dim == 3 ? P[0] + cur_lo(order) + cur_hi(order) : 1;
+    const int jy = P[1] + cur_lo(order) + cur_hi(order);
+    const int jz = P[2] + cur_lo(order) + cur_hi(order);
+    return sizeof(float) * (6 * (size_t)fx * fy * fz + 3 * (size_t)jx * jy * jz);
+}
+
+}  // namespace psc

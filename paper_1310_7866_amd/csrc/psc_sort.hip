@@ -1,0 +1,407 @@
+// psc_sort.hip -- per-step stable counting sort of particles by cell key,
+// exploiting that a particle moves at most one cell per dimension per step
+// (section "Sorting and Communication": 9 move cases in 2-d, 27 in 3-d).
+//
+// The pushed buffer is ordered by the *old* key (the kernel wrote it in the
+// previous sorted order) and each particle carries its move code m, so the new
+// key is old + d(m).  The stable position of particle i with old cell o and
+// move m is
+//   cs_new[o + d(m)] + (arrivals into o + d(m) from source cells whose key is
+//   below o's) + (earlier particles of o with the same move),
+// which three integer passes compute without comparisons of particle keys:
+//   count   per old cell: particles per move code          (cnt)
+//   prefix  per new cell: arrivals per source, ordered     (pre, tot)
+//   scan    tot -> cs_new
+//   scatter per old cell: perm[position] = i
+// The physical reorder is deferred into the next particle kernel, which reads
+// through perm (section "Fusing of GPU kernels").
+//
+// Also here: the segmented exclusive scan, and the one-off general sort used
+// to load particles in arbitrary order.
+#include <hipcub/hipcub.hpp>
+
+#include "psc_internal.h"
+
+namespace psc {
+
+__device__ __forceinline__ int find_seg(const int64_t *base, int n, int64_t c) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (base[mid] <= c) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+constexpr int kSortBlock = 256;
+
+// per old cell: count particles per move code
+template <int DIM>
+__global__ void __launch_bounds__(kSortBlock) k_sort_count(const RunDev *__restrict__ runs,
+                                                           const int64_t *__restrict__ seg_base,
+                                                           const int32_t *__restrict__ seg_run,
+                                                           const int32_t *__restrict__ seg_sp, int n_segs,
+                                                           int64_t total, int cs_sel, uint32_t *err) {
+    constexpr int M = DIM == 3 ? 27 : 9;
+    __shared__ int32_t cnt[M * kSortBlock];
+    const int64_t c = (int64_t)blockIdx.x * kSortBlock + threadIdx.x;
+    if (c >= total) return;
+    const int sg = find_seg(seg_base, n_segs, c);
+    const RunDev &R = runs[seg_run[sg]];
+    const SpeciesDev &S = R.sp[seg_sp[sg]];
+    const int64_t o = c - seg_base[sg];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int m = 0; m < M; ++m) cnt[m * kSortBlock + t] = 0;
+    const int32_t *cs = S.cs[cs_sel];
+    const int32_t b = cs[o], e = cs[o + 1];
+    uint32_t flags = 0;
+    for (int32_t i = b; i < e; ++i) {
+        int m = S.mc[i];
+        if (m >= M) { flags |= PSC_DEV_MOVE; m = M / 2; }
+        cnt[m * kSortBlock + t] += 1;
+    }
+    const int64_t nc = R.ncell;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        int32_t v = cnt[m * kSortBlock + t];
+        if (v > 65535) { flags |= PSC_DEV_OVERFULL; v = 65535; }
+        S.cnt[m * nc + o] = (uint16_t)v;
+    }
+    if (flags) atomicOr(err, flags);
+}
+
+// per new cell: order the source cells by key and assign arrival prefixes
+template <int DIM>
+__global__ void __launch_bounds__(kSortBlock) k_sort_prefix(const RunDev *__restrict__ runs,
+                                                            const int64_t *__restrict__ seg_base,
+                                                            const int32_t *__restrict__ seg_run,
+                                                            const int32_t *__restrict__ seg_sp, int n_segs,
+                                                            int64_t total, uint32_t *err) {
+    constexpr int M = DIM == 3 ? 27 : 9;
+    const int64_t c = (int64_t)blockIdx.x * kSortBlock + threadIdx.x;
+    if (c >= total) return;
+    const int sg = find_seg(seg_base, n_segs, c);
+    const RunDev &R = runs[seg_run[sg]];
+    const SpeciesDev &S = R.sp[seg_sp[sg]];
+    const int64_t n = c - seg_base[sg];
+    const int64_t nc = R.ncell;
+    int g[3];
+    decode_key(R, n, g);
+    int32_t ks[M];
+    int32_t cn[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        int d[3];
+        move_delta(DIM, m, d);
+        const int sx = DIM == 3 ? wrap(g[0] - d[0], R.n[0]) : 0;
+        ks[m] = (int32_t)encode_key(R, sx, wrap(g[1] - d[1], R.n[1]), wrap(g[2] - d[2], R.n[2]));
+        cn[m] = S.cnt[m * nc + ks[m]];
+    }
+    int32_t tot = 0;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        int32_t pre = 0;
+#pragma unroll
+        for (int q = 0; q < M; ++q) pre += ks[q] < ks[m] ? cn[q] : 0;
+        S.pre[m * nc + ks[m]] = (uint16_t)pre;
+        tot += cn[m];
+    }
+    if (tot > 65535) atomicOr(err, PSC_DEV_OVERFULL);
+    S.tot[n] = tot;
+}
+
+// per old cell: stable positions of its particles
+template <int DIM>
+__global__ void __launch_bounds__(kSortBlock) k_sort_scatter(const RunDev *__restrict__ runs,
+                                                             const int64_t *__restrict__ seg_base,
+                                                             const int32_t *__restrict__ seg_run,
+                                                             const int32_t *__restrict__ seg_sp, int n_segs,
+                                                             int64_t total, int cs_sel, uint32_t *err) {
+    constexpr int M = DIM == 3 ? 27 : 9;
+    __shared__ int32_t pos[M * kSortBlock];
+    const int64_t c = (int64_t)blockIdx.x * kSortBlock + threadIdx.x;
+    if (c >= total) return;
+    const int sg = find_seg(seg_base, n_segs, c);
+    const RunDev &R = runs[seg_run[sg]];
+    const SpeciesDev &S = R.sp[seg_sp[sg]];
+    const int64_t o = c - seg_base[sg];
+    const int64_t nc = R.ncell;
+    const int t = threadIdx.x;
+    const int32_t *cs_old = S.cs[cs_sel];
+    const int32_t *cs_new = S.cs[1 - cs_sel];
+    const int32_t b = cs_old[o], e = cs_old[o + 1];
+    if (b == e) return;
+    int g[3];
+    decode_key(R, o, g);
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        int d[3];
+        move_delta(DIM, m, d);
+        const int dx = DIM == 3 ? wrap(g[0] + d[0], R.n[0]) : 0;
+        const int64_t dst = encode_key(R, dx, wrap(g[1] + d[1], R.n[1]), wrap(g[2] + d[2], R.n[2]));
+        pos[m * kSortBlock + t] = cs_new[dst] + S.pre[m * nc + o];
+    }
+    bool bad = false;
+    for (int32_t i = b; i < e; ++i) {
+        int m = S.mc[i];
+        if (m >= M) m = M / 2;
+        const int32_t p = pos[m * kSortBlock + t];
+        pos[m * kSortBlock + t] = p + 1;
+        if (p >= 0 && p < S.n) S.perm[p] = i;   // out of range only after a counter overflow
+        else bad = true;
+    }
+    if (bad) atomicOr(err, PSC_DEV_OVERFULL);
+}
+
+// ---------------------------------------------------------------------------
+// segmented exclusive scan: out[0..n] with out[n] = total, per segment
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *sh, int32_t &total) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int32_t a = t >= off ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += a;
+        __syncthreads();
+    }
+    total = sh[255];
+    const int32_t r = sh[t] - v;
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(256) k_scan_reduce(const ScanSeg *__restrict__ segs,
+                                                     const int32_t *__restrict__ block_seg,
+                                                     int32_t *__restrict__ block_sums) {
+    __shared__ int32_t sh[256];
+    const int64_t b = blockIdx.x;
+    const ScanSeg sg = segs[block_seg[b]];
+    const int64_t i0 = (b - sg.block0) * kScanBlock + (int64_t)threadIdx.x * kScanPerThread;
+    int32_t s = 0;
+#pragma unroll
+    for (int q = 0; q < kScanPerThread; ++q)
+        if (i0 + q < sg.n) s += sg.in[i0 + q];
+    int32_t total;
+    block_exclusive_scan(s, sh, total);
+    if (threadIdx.x == 0) block_sums[b] = total;
+}
+
+// one workgroup: segmented exclusive scan of the block sums, in place
+__global__ void __launch_bounds__(1024) k_scan_blocks(const ScanSeg *__restrict__ segs,
+                                                      const int32_t *__restrict__ block_seg, int64_t n_blocks,
+                                                      int32_t *__restrict__ block_sums) {
+    __shared__ int32_t val[1024];
+    __shared__ int32_t flg[1024];
+    const int t = threadIdx.x;
+    int32_t carry = 0;
+    for (int64_t cb = 0; cb < n_blocks; cb += 1024) {
+        const int64_t b = cb + t;
+        const int32_t v = b < n_blocks ? block_sums[b] : 0;
+        const int32_t f = b < n_blocks ? (b == segs[block_seg[b]].block0) : 1;
+        val[t] = v;
+        flg[t] = f;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            int32_t av = 0, af = 0;
+            if (t >= off) { av = val[t - off]; af = flg[t - off]; }
+            __syncthreads();
+            if (t >= off) {
+                if (!flg[t]) val[t] += av;
+                flg[t] |= af;
+            }
+            __syncthreads();
+        }
+        // val: inclusive segmented sum since the last head in this chunk
+        const int32_t excl = val[t] - v + (flg[t] ? 0 : carry);
+        const int32_t last_v = val[1023], last_f = flg[1023];
+        __syncthreads();
+        if (b < n_blocks) block_sums[b] = excl;
+        carry = last_f ? last_v : carry + last_v;
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(256) k_scan_final(const ScanSeg *__restrict__ segs,
+                                                    const int32_t *__restrict__ block_seg,
+                                                    const int32_t *__restrict__ block_sums) {
+    __shared__ int32_t sh[256];
+    const int64_t b = blockIdx.x;
+    const ScanSeg sg = segs[block_seg[b]];
+    const int64_t i0 = (b - sg.block0) * kScanBlock + (int64_t)threadIdx.x * kScanPerThread;
+    int32_t v[kScanPerThread];
+    int32_t s = 0;
+#pragma unroll
+    for (int q = 0; q < kScanPerThread; ++q) {
+        v[q] = i0 + q < sg.n ? sg.in[i0 + q] : 0;
+        s += v[q];
+    }
+    int32_t total;
+    int32_t run = block_exclusive_scan(s, sh, total) + block_sums[b];
+#pragma unroll
+    for (int q = 0; q < kScanPerThread; ++q) {
+        if (i0 + q < sg.n) sg.out[i0 + q] = run;
+        run += v[q];
+    }
+    const int64_t blocks = (sg.n + kScanBlock - 1) / kScanBlock;
+    if (threadIdx.x == 255 && b - sg.block0 == blocks - 1) sg.out[sg.n] = block_sums[b] + total;
+}
+
+hipError_t launch_scan(const ScanSeg *segs, int, int64_t n_blocks, const int32_t *block_seg, int32_t *block_sums,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)n_blocks), dim3(256), 0, s, segs, block_seg, block_sums);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, segs, block_seg, n_blocks, block_sums);
+    hipLaunchKernelGGL(k_scan_final, dim3((unsigned)n_blocks), dim3(256), 0, s, segs, block_seg, block_sums);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort(const Launch &L, const int64_t *seg_base, const int32_t *seg_run, const int32_t *seg_sp,
+                       int n_segs, int64_t total, const ScanSeg *segs_dev, int64_t n_scan_blocks,
+                       int32_t *scan_tmp, int cs_sel, int dim) {
+    const unsigned grid = (unsigned)((total + kSortBlock - 1) / kSortBlock);
+    // scan_tmp: [0, n_scan_blocks) block sums; then the block -> segment table
+    const int32_t *block_seg = scan_tmp + n_scan_blocks;
+    if (dim == 3) {
+        hipLaunchKernelGGL(k_sort_count<3>, dim3(grid), dim3(kSortBlock), 0, L.stream, L.runs_dev, seg_base, seg_run,
+                           seg_sp, n_segs, total, cs_sel, L.err);
+        hipLaunchKernelGGL(k_sort_prefix<3>, dim3(grid), dim3(kSortBlock), 0, L.stream, L.runs_dev, seg_base,
+                           seg_run, seg_sp, n_segs, total, L.err);
+    } else {
+        hipLaunchKernelGGL(k_sort_count<2>, dim3(grid), dim3(kSortBlock), 0, L.stream, L.runs_dev, seg_base, seg_run,
+                           seg_sp, n_segs, total, cs_sel, L.err);
+        hipLaunchKernelGGL(k_sort_prefix<2>, dim3(grid), dim3(kSortBlock), 0, L.stream, L.runs_dev, seg_base,
+                           seg_run, seg_sp, n_segs, total, L.err);
+    }
+    hipError_t e = launch_scan(segs_dev, n_segs, n_scan_blocks, block_seg, scan_tmp, L.stream);
+    if (e != hipSuccess) return e;
+    if (dim == 3)
+        hipLaunchKernelGGL(k_sort_scatter<3>, dim3(grid), dim3(kSortBlock), 0, L.stream, L.runs_dev, seg_base,
+                           seg_run, seg_sp, n_segs, total, cs_sel, L.err);
+    else
+        hipLaunchKernelGGL(k_sort_scatter<2>, dim3(grid), dim3(kSortBlock), 0, L.stream, L.runs_dev, seg_base,
+                           seg_run, seg_sp, n_segs, total, cs_sel, L.err);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// particle loading (general stable sort, once) and read-back
+// ---------------------------------------------------------------------------
+__global__ void k_keys(RunDev R, int64_t n, const int32_t *__restrict__ gcell, int32_t *__restrict__ keys,
+                       int32_t *__restrict__ idx, uint32_t *err) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int64_t c = gcell[p];
+    if (c < 0 || c >= R.ncell) {
+        atomicOr(err, PSC_DEV_KEY);
+        c = 0;
+    }
+    const int i = (int)(c % R.n[0]);
+    const int j = (int)((c / R.n[0]) % R.n[1]);
+    const int k = (int)(c / ((int64_t)R.n[0] * R.n[1]));
+    keys[p] = (int32_t)encode_key(R, i, j, k);
+    idx[p] = (int32_t)p;
+}
+
+hipError_t launch_keys(const RunDev &r, int64_t n, const int32_t *gcell, int32_t *keys, int32_t *idx,
+                       uint32_t *err, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, r, n, gcell, keys, idx, err);
+    return hipGetLastError();
+}
+
+__global__ void k_keys_to_cells(RunDev R, int64_t n, const int32_t *__restrict__ keys, int32_t *__restrict__ cells) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int64_t key = keys[p];
+    if (key < 0 || key >= R.ncell) {
+        cells[p] = -1;
+        return;
+    }
+    int g[3];
+    decode_key(R, key, g);
+    cells[p] = (int32_t)(g[0] + (int64_t)R.n[0] * (g[1] + (int64_t)R.n[1] * g[2]));
+}
+
+hipError_t launch_keys_to_cells(const RunDev &r, int64_t n, const int32_t *keys, int32_t *cells, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_keys_to_cells, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, r, n, keys, cells);
+    return hipGetLastError();
+}
+
+__global__ void k_load_gather(RunDev R, int sp, int64_t n, const int32_t *__restrict__ skeys,
+                              const int32_t *__restrict__ sidx, const float *__restrict__ goff,
+                              const float *__restrict__ gu, const int32_t *__restrict__ gid) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const SpeciesDev &S = R.sp[sp];
+    const int64_t src = sidx[r];
+    S.cell[0][r] = skeys[r];
+    for (int d = 0; d < R.dim; ++d) S.off[0][d * S.cap + r] = goff[d * n + src];
+    for (int c = 0; c < 3; ++c) S.u[0][c * S.cap + r] = gu[c * n + src];
+    if (S.id[0]) S.id[0][r] = gid ? gid[src] : (int32_t)src;
+}
+
+hipError_t launch_load_gather(const RunDev &r, int species, int64_t n, const int32_t *skeys, const int32_t *sidx,
+                              const float *goff, const float *gu, const int32_t *gid, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_load_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, r, species, n, skeys, sidx,
+                       goff, gu, gid);
+    return hipGetLastError();
+}
+
+__global__ void k_count_cells(int64_t n, const int32_t *__restrict__ skeys, int32_t *__restrict__ tot) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    atomicAdd(&tot[skeys[r]], 1);
+}
+
+hipError_t launch_count_cells(const RunDev &, int, int64_t n, const int32_t *skeys, int32_t *tot, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_count_cells, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, skeys, tot);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+__global__ void k_get(RunDev R, int sp, int front, int perm_pending, int32_t *__restrict__ cell,
+                      float *__restrict__ off, float *__restrict__ u, int32_t *__restrict__ id) {
+    const SpeciesDev &S = R.sp[sp];
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = S.n;
+    if (r >= n) return;
+    const int64_t src = perm_pending ? S.perm[r] : r;
+    if (cell) cell[r] = S.cell[front][src];
+    if (off)
+        for (int d = 0; d < R.dim; ++d) off[d * n + r] = S.off[front][d * S.cap + src];
+    if (u)
+        for (int c = 0; c < 3; ++c) u[c * n + r] = S.u[front][c * S.cap + src];
+    if (id) id[r] = S.id[front] ? S.id[front][src] : -1;
+}
+
+hipError_t launch_get(const RunDev &r, int species, int front, int perm_pending, int32_t *cell, float *off, float *u,
+                      int32_t *id, hipStream_t s) {
+    const int64_t n = r.sp[species].n;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_get, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, r, species, front, perm_pending,
+                       cell, off, u, id);
+    return hipGetLastError();
+}
+
+hipError_t radix_sort_pairs(void *temp, size_t *temp_bytes, const int32_t *keys_in, int32_t *keys_out,
+                            const int32_t *vals_in, int32_t *vals_out, int64_t n, int bits, hipStream_t s) {
+    return hipcub::DeviceRadixSort::SortPairs(temp, *temp_bytes, keys_in, keys_out, vals_in, vals_out, (int)n, 0, bits,
+                                              s);
+}
+
+}  // namespace psc

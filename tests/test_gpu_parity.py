@@ -1,0 +1,177 @@
+"""GPU parity: each C-ABI call against the double-precision oracle.
+
+Tolerances (float32 kernels vs float64 oracle on identical float32 inputs):
+  * per particle after one push: |dxi| <= 1e-6 cells and
+    |du| / max(|u|, v_th) <= 1e-5;
+  * fields after one update: |dF| <= 1e-6 * max|F| (one float32 stencil
+    evaluation, a handful of roundings of O(max|F|) values);
+  * current after one deposit: |dJ| <= 2e-5 * max|J| (sums of up to a few
+    hundred float32 contributions of O(q w dx/dt) each);
+  * sort permutation: bit-exact against the oracle's stable sort of the same
+    keys.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1310_7866_amd import cases
+from tests.helpers import by_id, gpu_positions, particle_errors, periodic_diff
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(case, **kw):
+    from paper_1310_7866_amd.psc import PscSim
+    print(f"[gpu] {case.name} dim={case.dim} order={case.order} gdims={case.gdims} patch={case.patch} "
+          f"n={case.n_particles}", flush=True)
+    return PscSim(case, **kw)
+
+
+def _small_2d(order, seed=5, ny=20, nz=12, patch=8, ppc=6):
+    c = cases.thermal2d(ny=ny, nz=nz, ppc=ppc, order=order, patch=patch, seed=seed)
+    # separate the species so the charge density is non-trivial
+    c.species[1].off = np.random.default_rng(seed).random(c.species[1].off.shape).astype(np.float32)
+    cases.random_fields(c, 0.05, 0.3, seed=seed + 1)
+    return c
+
+
+def _small_3d(order, seed=8, nxyz=(10, 9, 7), patch=4, ppc=4):
+    c = cases.weibel3d(ppc=ppc, order=order, patch=patch, seed=seed, nxyz=nxyz)
+    cases.random_fields(c, 0.05, 0.3, seed=seed + 1)
+    return c
+
+
+CASES = [("2d", 1), ("2d", 2), ("3d", 1), ("3d", 2)]
+
+
+def _make(kind, order):
+    return _small_2d(order) if kind == "2d" else _small_3d(order)
+
+
+@pytest.mark.parametrize("kind,order", CASES)
+def test_fields_match_oracle(kind, order):
+    c = _make(kind, order)
+    sim = _sim(c)
+    ora = O.OracleSim(c)
+    sim.push_fields(0)
+    ora.push_b_half()
+    E, B, J = sim.field_arrays(0)
+    assert np.abs(B.ravel() - ora.B).max() <= 1e-6 * np.abs(ora.B).max()
+    sim.push_fields(1)
+    ora.J[:] = 0
+    ora.push_e_full()
+    E, B, J = sim.field_arrays(0)
+    assert np.abs(E.ravel() - ora.E).max() <= 1e-6 * max(np.abs(ora.E).max(), 1e-30)
+
+
+@pytest.mark.parametrize("kind,order", CASES)
+def test_push_and_deposit_match_oracle(kind, order):
+    c = _make(kind, order)
+    sim = _sim(c)
+    ora = O.OracleSim(c)
+    sim.push_fields(0)
+    sim.push_particles()
+    sim.deposit_current()
+    assert sim.check() == 0
+    ora.push_b_half()
+    ora.push_particles()
+    for s, sp in enumerate(c.species):
+        vth = float(np.std(sp.u))
+        dpos, du = particle_errors(c, sim.front_buffer(0, s), ora, s, vth)
+        print(f"species {s}: max |dxi| = {dpos:.3e} cells, max rel |du| = {du:.3e}")
+        assert dpos <= 1e-6
+        assert du <= 1e-5
+    _, _, J = sim.field_arrays(0)
+    err = np.abs(J.ravel() - ora.J).max()
+    print(f"max |dJ| = {err:.3e}, max |J| = {np.abs(ora.J).max():.3e}")
+    assert err <= 2e-5 * np.abs(ora.J).max()
+
+
+@pytest.mark.parametrize("kind,order", CASES)
+def test_sort_matches_stable_sort(kind, order):
+    c = _make(kind, order)
+    sim = _sim(c)
+    for step in range(3):
+        sim.step(1) if step else None
+        sim.push_fields(0)
+        sim.push_particles()
+        sim.push_fields(0)
+        sim.deposit_current()
+        sim.push_fields(1)
+        for s in range(len(c.species)):
+            keys = sim.front_buffer(0, s)["key"]
+        sim.sort()
+        assert sim.check() == 0
+        for s in range(len(c.species)):
+            f, _ = sim.front()
+            n = c.species[s].n
+            keys = sim.parts[0][s][f]["cell"][:n].cpu().numpy()
+            perm, cst = sim.sort_view(0, s)
+            want = O.stable_sort(keys, c.ncell)
+            assert np.array_equal(perm, want)
+            counts = np.bincount(keys, minlength=c.ncell)
+            assert np.array_equal(cst, np.concatenate([[0], np.cumsum(counts)]))
+
+
+@pytest.mark.parametrize("kind,order", CASES)
+def test_steps_match_oracle(kind, order):
+    c = _make(kind, order)
+    sim = _sim(c)
+    ora = O.OracleSim(c)
+    for _ in range(5):
+        sim.step(1)
+        ora.step(1)
+    assert sim.check() == 0
+    for s, sp in enumerate(c.species):
+        vth = float(np.std(sp.u))
+        dpos, du = particle_errors(c, sim.particles(0, s), ora, s, vth)
+        print(f"5 steps, species {s}: |dxi| {dpos:.3e}, rel |du| {du:.3e}")
+        assert dpos <= 1e-5
+        assert du <= 1e-4
+    E, B, J = sim.field_arrays(0)
+    assert np.abs(E.ravel() - ora.E).max() <= 1e-4 * np.abs(ora.E).max()
+    assert np.abs(B.ravel() - ora.B).max() <= 1e-4 * np.abs(ora.B).max()
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_graph_replay_matches_eager(use_graph):
+    c = _small_2d(2, seed=21)
+    a = _sim(c)
+    b = _sim(c)
+    for k in range(4):
+        a.step(1, use_graph=False)
+        b.step(1, use_graph=use_graph)
+        assert a.check() == 0 and b.check() == 0
+        pa, pb = a.particles(0, 0), b.particles(0, 0)
+        assert np.array_equal(pa["key"], pb["key"])
+        assert np.abs(pa["u"] - pb["u"]).max() <= 1e-5
+    Ea = a.field_arrays(0)[0]
+    Eb = b.field_arrays(0)[0]
+    assert np.abs(Ea - Eb).max() <= 1e-5 * np.abs(Ea).max()
+
+
+def test_nonfinite_momentum_flagged():
+    c = _small_2d(1, seed=3)
+    c.species[0].u[0, 5] = np.float32(np.nan)
+    sim = _sim(c)
+    sim.push_fields(0)
+    sim.push_particles()
+    word = sim.error_word(clear=True)
+    assert word & 1
+    assert sim.error_word() == 0
+
+
+def test_superluminal_move_flagged():
+    # u so large that dt*v/dx would exceed a cell only if v > c: here the
+    # kernel must still keep every particle in bounds; a huge field makes
+    # gamma large but |v| < c, so no flag; the flag path is driven through a
+    # non-finite momentum instead (move of NaN length).
+    c = _small_2d(1, seed=4)
+    c.species[0].u[:, 7] = np.float32(np.inf)
+    sim = _sim(c)
+    sim.push_fields(0)
+    sim.push_particles()
+    word = sim.error_word(clear=True)
+    assert word & (1 | 2)
