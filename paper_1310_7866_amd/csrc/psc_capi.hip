@@ -194,6 +194,7 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
             const bool active = d.dim == 3 || k > 0;
             R.dx[k] = active ? (float)d.dx[k] : 1.0f;
             R.inv_dx[k] = active ? (float)(1.0 / d.dx[k]) : 0.0f;
+            R.dxd[k] = active ? d.dx[k] : 1.0;
             R.jt[k] = active ? d.patch[k] + cur_lo(d.order) + cur_hi(d.order) : 1;
         }
         R.n_patches = R.np[0] * R.np[1] * R.np[2];

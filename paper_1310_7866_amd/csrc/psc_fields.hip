@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(256) k_kinetic(const RunDev *__restrict__ runs
     }
     v = wave_sum(v);
     if ((threadIdx.x & 63) == 0 && v != 0.0) {
-        const double dV = (double)R.dx[1] * R.dx[2] * (R.dim == 3 ? (double)R.dx[0] : 1.0);
+        const double dV = R.dxd[1] * R.dxd[2] * (R.dim == 3 ? R.dxd[0] : 1.0);
         atomicAdd(&out[2 + sp], (double)S.m * S.w * dV * v);
     }
 }
@@ -238,8 +238,8 @@ __global__ void __launch_bounds__(256) k_field_diag(const RunDev *__restrict__ r
         const int i = (int)(idx % nx), j = (int)((idx / nx) % ny), k = (int)(idx / ((int64_t)nx * ny));
         const int64_t nc = R.ncell;
         const bool three = R.dim == 3;
-        const double dV = (double)R.dx[1] * R.dx[2] * (three ? (double)R.dx[0] : 1.0);
-        const double ix = three ? 1.0 / R.dx[0] : 0.0, iy = 1.0 / R.dx[1], iz = 1.0 / R.dx[2];
+        const double dV = R.dxd[1] * R.dxd[2] * (three ? R.dxd[0] : 1.0);
+        const double ix = three ? 1.0 / R.dxd[0] : 0.0, iy = 1.0 / R.dxd[1], iz = 1.0 / R.dxd[2];
         for (int q = 0; q < 3; ++q) {
             const double e = R.E[q * nc + idx], b = R.B[q * nc + idx];
             we += e * e;

@@ -59,6 +59,7 @@ struct RunDev {
     int64_t cell_base;   // offset of the run in the flat cell space of all runs
     float dx[3];
     float inv_dx[3];
+    double dxd[3];       // exact cell sizes for the float64 diagnostics
     float dt;
     int jt[3];           // current-tile extent per dimension
     int64_t jtile_cells; // jt[0]*jt[1]*jt[2]

@@ -175,6 +175,160 @@ __global__ void __launch_bounds__(1024) k_build_items(const RunDev *__restrict__
 }
 
 // ---------------------------------------------------------------------------
+// wave-level segmented sums (DPP) for the current deposit
+// ---------------------------------------------------------------------------
+// Particles are sorted by cell, so the 64 lanes of a wave mostly share one or
+// two cells and would hit the same LDS words with atomics.  Instead each lane
+// writes its current into a fixed per-cell frame, the wave forms prefix sums
+// across lanes with DPP row shifts and row broadcasts, and the last lane of
+// every run of equal cells adds the run's sum to LDS.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_take(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, true));
+}
+
+__device__ __forceinline__ float wave_prefix_sum(float v) {
+    v += dpp_take<0x111, 0xF>(v);  // row_shr:1
+    v += dpp_take<0x112, 0xF>(v);  // row_shr:2
+    v += dpp_take<0x114, 0xF>(v);  // row_shr:4
+    v += dpp_take<0x118, 0xF>(v);  // row_shr:8   -> inclusive within rows of 16
+    v += dpp_take<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_take<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+struct Segments {
+    int prev;      // lane holding the prefix just before this lane's run (or -1)
+    bool tail;     // last lane of its run
+};
+
+__device__ __forceinline__ Segments wave_segments(int key) {
+    const int lane = threadIdx.x & 63;
+    const int left = __shfl_up(key, 1, 64);
+    const uint64_t heads = __ballot(lane == 0 || left != key);
+    const uint64_t le = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+    const int start = 63 - __clzll(heads & le);
+    Segments s;
+    s.prev = start - 1;
+    s.tail = lane == 63 || ((heads >> (lane + 1)) & 1ull);
+    return s;
+}
+
+__device__ __forceinline__ float segment_sum(float v, const Segments &sg) {
+    const float incl = wave_prefix_sum(v);
+    const float before = __shfl(incl, sg.prev < 0 ? 0 : sg.prev, 64);
+    return sg.prev < 0 ? incl : incl - before;
+}
+
+// ---------------------------------------------------------------------------
+// Esirkepov current of one particle, added lane by lane with LDS atomics
+// (general stencil: used for particles whose support changes cell)
+// ---------------------------------------------------------------------------
+template <int DIM, int ORDER>
+__device__ __forceinline__ void deposit_lane(float *jtile, int jcells, int jx_, int jy_, int lx, int ly, int lz,
+                                             const float o[3], const int s[3], const float o1[3], float jfx,
+                                             float jfy, float jfz, float fxv) {
+    constexpr int L = ORDER + 2;
+    constexpr int JLO = ORDER;
+    float S0y[L], S1y[L], S0z[L], S1z[L];
+    const int by = stencil<ORDER>(o[1], s[1], o1[1], S0y, S1y);
+    const int bz = stencil<ORDER>(o[2], s[2], o1[2], S0z, S1z);
+    float DSy[L], DSz[L], Ay[L], Az[L], Cy[L], Cz[L];
+#pragma unroll
+    for (int r = 0; r < L; ++r) {
+        DSy[r] = S1y[r] - S0y[r];
+        DSz[r] = S1z[r] - S0z[r];
+        Ay[r] = fmaf(0.5f, DSy[r], S0y[r]);
+        Az[r] = fmaf(0.5f, DSz[r], S0z[r]);
+        Cy[r] = r == 0 ? DSy[0] : Cy[r - 1] + DSy[r];
+        Cz[r] = r == 0 ? DSz[0] : Cz[r - 1] + DSz[r];
+    }
+    float *Jx = jtile, *Jy = jtile + jcells, *Jz = jtile + 2 * jcells;
+    if constexpr (DIM == 2) {
+        const int base = (lz + bz + JLO) * jy_ + (ly + by + JLO);
+#pragma unroll
+        for (int b = 0; b < L; ++b)
+#pragma unroll
+            for (int a = 0; a < L - 1; ++a) lds_add(&Jy[base + b * jy_ + a], jfy * Cy[a] * Az[b]);
+#pragma unroll
+        for (int b = 0; b < L - 1; ++b)
+#pragma unroll
+            for (int a = 0; a < L; ++a) lds_add(&Jz[base + b * jy_ + a], jfz * Ay[a] * Cz[b]);
+#pragma unroll
+        for (int b = 0; b < L; ++b)
+#pragma unroll
+            for (int a = 0; a < L; ++a)
+                lds_add(&Jx[base + b * jy_ + a], fxv * fmaf(DSy[a] * DSz[b], 1.0f / 12.0f, Ay[a] * Az[b]));
+    } else {
+        float S0x[L], S1x[L];
+        const int bx = stencil<ORDER>(o[0], s[0], o1[0], S0x, S1x);
+        float DSx[L], Ax[L], Cx[L];
+#pragma unroll
+        for (int r = 0; r < L; ++r) {
+            DSx[r] = S1x[r] - S0x[r];
+            Ax[r] = fmaf(0.5f, DSx[r], S0x[r]);
+            Cx[r] = r == 0 ? DSx[0] : Cx[r - 1] + DSx[r];
+        }
+        const int pxy = jx_ * jy_;
+        const int base = (lz + bz + JLO) * pxy + (ly + by + JLO) * jx_ + (lx + bx + JLO);
+#pragma unroll
+        for (int c = 0; c < L; ++c)
+#pragma unroll
+            for (int b = 0; b < L; ++b) {
+                const float wyz = fmaf(DSy[b] * DSz[c], 1.0f / 12.0f, Ay[b] * Az[c]);
+#pragma unroll
+                for (int a = 0; a < L - 1; ++a) lds_add(&Jx[base + c * pxy + b * jx_ + a], jfx * Cx[a] * wyz);
+            }
+#pragma unroll
+        for (int c = 0; c < L; ++c)
+#pragma unroll
+            for (int b = 0; b < L - 1; ++b)
+#pragma unroll
+                for (int a = 0; a < L; ++a) {
+                    const float wxz = fmaf(DSx[a] * DSz[c], 1.0f / 12.0f, Ax[a] * Az[c]);
+                    lds_add(&Jy[base + c * pxy + b * jx_ + a], jfy * Cy[b] * wxz);
+                }
+#pragma unroll
+        for (int c = 0; c < L - 1; ++c)
+#pragma unroll
+            for (int b = 0; b < L; ++b)
+#pragma unroll
+                for (int a = 0; a < L; ++a) {
+                    const float wxy = fmaf(DSx[a] * DSy[b], 1.0f / 12.0f, Ax[a] * Ay[b]);
+                    lds_add(&Jz[base + c * pxy + b * jx_ + a], jfz * Cz[c] * wxy);
+                }
+    }
+}
+
+// Node weights of one dimension on the fixed per-cell frame used by the wave
+// reduction: order 1 -> nodes {0, 1}, order 2 -> nodes {-1, 0, 1, 2}.  Valid
+// for a particle whose support does not change (see `stays` below).
+template <int ORDER>
+__device__ __forceinline__ void frame_weights(float o0, float o1, float S0[2 * ORDER], float S1[2 * ORDER]) {
+    float w0[ORDER + 1], w1[ORDER + 1];
+    const int b0 = node_weights<ORDER>(o0, w0);
+    node_weights<ORDER>(o1, w1);
+    if constexpr (ORDER == 1) {
+        S0[0] = w0[0]; S0[1] = w0[1];
+        S1[0] = w1[0]; S1[1] = w1[1];
+    } else {
+        const bool up = b0 == 0;  // support {0,1,2} instead of {-1,0,1}
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            S0[r] = up ? (r >= 1 ? w0[r - 1] : 0.0f) : (r <= 2 ? w0[r] : 0.0f);
+            S1[r] = up ? (r >= 1 ? w1[r - 1] : 0.0f) : (r <= 2 ? w1[r] : 0.0f);
+        }
+    }
+}
+
+// does the particle's interpolation support stay on the same nodes?
+template <int ORDER>
+__device__ __forceinline__ bool stays(float o0, int s, float o1) {
+    if constexpr (ORDER == 1) return s == 0;
+    else return s + (o1 >= 0.5f ? 1 : 0) == (o0 >= 0.5f ? 1 : 0);
+}
+
+// ---------------------------------------------------------------------------
 // the particle kernel
 // ---------------------------------------------------------------------------
 template <int DIM, int ORDER>
@@ -183,9 +337,12 @@ __global__ void __launch_bounds__(kBlock) k_push(const RunDev *__restrict__ runs
                                                  int chunk, int front, int cs_sel, int use_perm,
                                                  uint32_t *__restrict__ err) {
     extern __shared__ float lds[];
-    constexpr int L = ORDER + 2;          // Esirkepov stencil nodes per dimension
     constexpr int FLO = 1, FHI = ORDER;   // field ghosts
     constexpr int JLO = ORDER, JHI = ORDER + 1;
+    constexpr int FL = 2 * ORDER;         // frame nodes per dimension
+    constexpr int FB = ORDER == 1 ? 0 : -1;
+    // the 3-d order-2 frame holds 144 values per particle: lane atomics instead
+    constexpr bool kReduce = !(DIM == 3 && ORDER == 2);
 
     // XCD-aware item order: workgroups are dispatched round-robin over the 8
     // XCDs; give each XCD a contiguous range of items so that the chunks of a
@@ -230,14 +387,13 @@ __global__ void __launch_bounds__(kBlock) k_push(const RunDev *__restrict__ runs
         const float inv_fx = 1.0f / fx, inv_fy = 1.0f / fy;
         const int64_t nc = R.ncell;
         for (int t = threadIdx.x; t < fcells; t += kBlock) {
-            int tx = 0, ty, tz, r;
+            int tx = 0, ty, tz;
             if constexpr (DIM == 3) {
                 const int q = divmod_small(t, fx, inv_fx, tx);
                 tz = divmod_small(q, fy, inv_fy, ty);
             } else {
                 tz = divmod_small(t, fy, inv_fy, ty);
             }
-            (void)r;
             const int gx = DIM == 3 ? wrap(ox + tx - FLO, R.n[0]) : 0;
             const int gy = wrap(oy + ty - FLO, R.n[1]);
             const int gz = wrap(oz + tz - FLO, R.n[2]);
@@ -272,13 +428,21 @@ __global__ void __launch_bounds__(kBlock) k_push(const RunDev *__restrict__ runs
     const float jfx = -qw * R.dx[0] / dt, jfy = -qw * R.dx[1] / dt, jfz = -qw * R.dx[2] / dt;
     const float inv_hx = 1.0f / hx, inv_hy = 1.0f / hy;
     const int pcells = hx * hy * hz;
+    float *Jx = jtile, *Jy = jtile + jcells, *Jz = jtile + 2 * jcells;
     uint32_t flags = 0;
 
-    for (int32_t i = beg + threadIdx.x; i < end; i += kBlock) {
-        int32_t src = use_perm ? perm[i] : i;
+    // every lane runs the same number of iterations (the wave reduction needs
+    // all 64 lanes); lanes past the end carry zero current and write nothing
+    for (int32_t i0 = beg; i0 < end; i0 += kBlock) {
+        const int32_t i = i0 + threadIdx.x;
+        const bool valid = i < end;
+        // lanes past the end stand in with the chunk's first particle (taken
+        // through the permutation, so it lies in this patch)
+        const int32_t slot = valid ? i : beg;
+        int32_t src = use_perm ? perm[slot] : slot;
         if ((uint32_t)src >= (uint32_t)S.n) {   // corrupt permutation: stay in bounds
-            flags |= PSC_DEV_KEY;
-            src = i;
+            if (valid) flags |= PSC_DEV_KEY;
+            src = slot;
         }
         const int32_t key = cell_in[src];
         float o[3];
@@ -290,7 +454,7 @@ __global__ void __launch_bounds__(kBlock) k_push(const RunDev *__restrict__ runs
 
         int local = key - (int32_t)kb;
         if (local < 0 || local >= pcells) {  // not in this patch: corrupt state
-            flags |= PSC_DEV_KEY;
+            if (valid) flags |= PSC_DEV_KEY;
             local = 0;
         }
         int lx = 0, ly, lz;
@@ -342,7 +506,7 @@ __global__ void __launch_bounds__(kBlock) k_push(const RunDev *__restrict__ runs
             uz = fmaf(h, Ez, mz + (px * sy - py * sx));
         }
         const float ig = rsqrtf(1.0f + ux * ux + uy * uy + uz * uz);
-        if (!(ig > 0.0f)) flags |= PSC_DEV_NONFINITE;   // NaN or Inf momentum
+        if (valid && !(ig > 0.0f)) flags |= PSC_DEV_NONFINITE;   // NaN or Inf momentum
 
         // ---- move: xi^{n+3/2} = xi^{n+1/2} + dt u^{n+1} / (gamma dx) -------
         int s[3] = {0, 0, 0};
@@ -353,7 +517,7 @@ __global__ void __launch_bounds__(kBlock) k_push(const RunDev *__restrict__ runs
             const float uu = d == 0 ? ux : (d == 1 ? uy : uz);
             float disp = cf * uu * ig;
             if (!(fabsf(disp) < 0.99f)) {   // CFL broken or non-finite: keep it in bounds
-                flags |= PSC_DEV_MOVE;
+                if (valid) flags |= PSC_DEV_MOVE;
                 disp = 0.0f;
             }
             const float x1 = o[d] + disp;
@@ -364,104 +528,125 @@ __global__ void __launch_bounds__(kBlock) k_push(const RunDev *__restrict__ runs
             o1[d] = od;
         }
 
-        // ---- Esirkepov deposit into the LDS current tile --------------------
-        {
-            float S0y[L], S1y[L], S0z[L], S1z[L];
-            const int by = stencil<ORDER>(o[1], s[1], o1[1], S0y, S1y);
-            const int bz = stencil<ORDER>(o[2], s[2], o1[2], S0z, S1z);
-            float DSy[L], DSz[L], Ay[L], Az[L], Cy[L], Cz[L];
+        // ---- Esirkepov deposit ----------------------------------------------
+        const float fxv = qw * ux * ig;   // 2-d out-of-plane current factor q w v_x
+        bool frame = valid && stays<ORDER>(o[1], s[1], o1[1]) && stays<ORDER>(o[2], s[2], o1[2]);
+        if constexpr (DIM == 3) frame = frame && stays<ORDER>(o[0], s[0], o1[0]);
+        if (!kReduce) frame = false;
+        if (valid && !frame)
+            deposit_lane<DIM, ORDER>(jtile, jcells, jx_, jy_, lx, ly, lz, o, s, o1, jfx, jfy, jfz, fxv);
+        if constexpr (kReduce) {
+            const Segments sg = wave_segments(valid ? local : -1);
+            const bool put = sg.tail && valid;
+            float S0y[FL], S1y[FL], S0z[FL], S1z[FL];
+            frame_weights<ORDER>(o[1], o1[1], S0y, S1y);
+            frame_weights<ORDER>(o[2], o1[2], S0z, S1z);
+            const float on = frame ? 1.0f : 0.0f;
+            float DSy[FL], DSz[FL], Ay[FL], Az[FL], Cy[FL], Cz[FL];
 #pragma unroll
-            for (int r = 0; r < L; ++r) {
-                DSy[r] = S1y[r] - S0y[r];
-                DSz[r] = S1z[r] - S0z[r];
-                Ay[r] = fmaf(0.5f, DSy[r], S0y[r]);
-                Az[r] = fmaf(0.5f, DSz[r], S0z[r]);
+            for (int r = 0; r < FL; ++r) {
+                DSy[r] = (S1y[r] - S0y[r]) * on;
+                DSz[r] = (S1z[r] - S0z[r]) * on;
+                Ay[r] = fmaf(0.5f, DSy[r], S0y[r] * on);
+                Az[r] = fmaf(0.5f, DSz[r], S0z[r] * on);
                 Cy[r] = r == 0 ? DSy[0] : Cy[r - 1] + DSy[r];
                 Cz[r] = r == 0 ? DSz[0] : Cz[r - 1] + DSz[r];
             }
-            float *Jx = jtile, *Jy = jtile + jcells, *Jz = jtile + 2 * jcells;
             if constexpr (DIM == 2) {
-                const int base = (lz + bz + JLO) * jy_ + (ly + by + JLO);
-                const float vx = ux * ig;
-                const float fxv = qw * vx;
+                const int base = (lz + FB + JLO) * jy_ + (ly + FB + JLO);
 #pragma unroll
-                for (int b = 0; b < L; ++b)
+                for (int b = 0; b < FL; ++b)
 #pragma unroll
-                    for (int a = 0; a < L - 1; ++a) lds_add(&Jy[base + b * jy_ + a], jfy * Cy[a] * Az[b]);
+                    for (int a = 0; a < FL - 1; ++a) {
+                        const float v = segment_sum(jfy * Cy[a] * Az[b], sg);
+                        if (put) lds_add(&Jy[base + b * jy_ + a], v);
+                    }
 #pragma unroll
-                for (int b = 0; b < L - 1; ++b)
+                for (int b = 0; b < FL - 1; ++b)
 #pragma unroll
-                    for (int a = 0; a < L; ++a) lds_add(&Jz[base + b * jy_ + a], jfz * Ay[a] * Cz[b]);
+                    for (int a = 0; a < FL; ++a) {
+                        const float v = segment_sum(jfz * Ay[a] * Cz[b], sg);
+                        if (put) lds_add(&Jz[base + b * jy_ + a], v);
+                    }
 #pragma unroll
-                for (int b = 0; b < L; ++b)
+                for (int b = 0; b < FL; ++b)
 #pragma unroll
-                    for (int a = 0; a < L; ++a)
-                        lds_add(&Jx[base + b * jy_ + a], fxv * fmaf(DSy[a] * DSz[b], 1.0f / 12.0f, Ay[a] * Az[b]));
+                    for (int a = 0; a < FL; ++a) {
+                        const float v = segment_sum(fxv * fmaf(DSy[a] * DSz[b], 1.0f / 12.0f, Ay[a] * Az[b]), sg);
+                        if (put) lds_add(&Jx[base + b * jy_ + a], v);
+                    }
             } else {
-                float S0x[L], S1x[L];
-                const int bx = stencil<ORDER>(o[0], s[0], o1[0], S0x, S1x);
-                float DSx[L], Ax[L], Cx[L];
+                float S0x[FL], S1x[FL];
+                frame_weights<ORDER>(o[0], o1[0], S0x, S1x);
+                float DSx[FL], Ax[FL], Cx[FL];
 #pragma unroll
-                for (int r = 0; r < L; ++r) {
-                    DSx[r] = S1x[r] - S0x[r];
-                    Ax[r] = fmaf(0.5f, DSx[r], S0x[r]);
+                for (int r = 0; r < FL; ++r) {
+                    DSx[r] = (S1x[r] - S0x[r]) * on;
+                    Ax[r] = fmaf(0.5f, DSx[r], S0x[r] * on);
                     Cx[r] = r == 0 ? DSx[0] : Cx[r - 1] + DSx[r];
                 }
                 const int pxy = jx_ * jy_;
-                const int base = (lz + bz + JLO) * pxy + (ly + by + JLO) * jx_ + (lx + bx + JLO);
+                const int base = (lz + FB + JLO) * pxy + (ly + FB + JLO) * jx_ + (lx + FB + JLO);
 #pragma unroll
-                for (int c = 0; c < L; ++c)
+                for (int c = 0; c < FL; ++c)
 #pragma unroll
-                    for (int b = 0; b < L; ++b) {
+                    for (int b = 0; b < FL; ++b) {
                         const float wyz = fmaf(DSy[b] * DSz[c], 1.0f / 12.0f, Ay[b] * Az[c]);
 #pragma unroll
-                        for (int a = 0; a < L - 1; ++a) lds_add(&Jx[base + c * pxy + b * jx_ + a], jfx * Cx[a] * wyz);
+                        for (int a = 0; a < FL - 1; ++a) {
+                            const float v = segment_sum(jfx * Cx[a] * wyz, sg);
+                            if (put) lds_add(&Jx[base + c * pxy + b * jx_ + a], v);
+                        }
                     }
 #pragma unroll
-                for (int c = 0; c < L; ++c)
+                for (int c = 0; c < FL; ++c)
 #pragma unroll
-                    for (int b = 0; b < L - 1; ++b)
+                    for (int b = 0; b < FL - 1; ++b)
 #pragma unroll
-                        for (int a = 0; a < L; ++a) {
+                        for (int a = 0; a < FL; ++a) {
                             const float wxz = fmaf(DSx[a] * DSz[c], 1.0f / 12.0f, Ax[a] * Az[c]);
-                            lds_add(&Jy[base + c * pxy + b * jx_ + a], jfy * Cy[b] * wxz);
+                            const float v = segment_sum(jfy * Cy[b] * wxz, sg);
+                            if (put) lds_add(&Jy[base + c * pxy + b * jx_ + a], v);
                         }
 #pragma unroll
-                for (int c = 0; c < L - 1; ++c)
+                for (int c = 0; c < FL - 1; ++c)
 #pragma unroll
-                    for (int b = 0; b < L; ++b)
+                    for (int b = 0; b < FL; ++b)
 #pragma unroll
-                        for (int a = 0; a < L; ++a) {
+                        for (int a = 0; a < FL; ++a) {
                             const float wxy = fmaf(DSx[a] * DSy[b], 1.0f / 12.0f, Ax[a] * Ay[b]);
-                            lds_add(&Jz[base + c * pxy + b * jx_ + a], jfz * Cz[c] * wxy);
+                            const float v = segment_sum(jfz * Cz[c] * wxy, sg);
+                            if (put) lds_add(&Jz[base + c * pxy + b * jx_ + a], v);
                         }
             }
         }
 
         // ---- new cell key and move code ------------------------------------
-        const int nlx = lx + s[0], nly = ly + s[1], nlz = lz + s[2];
-        int32_t nkey;
-        if (nlx >= 0 && nlx < hx && nly >= 0 && nly < hy && nlz >= 0 && nlz < hz) {
-            nkey = (int32_t)kb + nlx + hx * (nly + hy * nlz);
-        } else {
-            const int gx = DIM == 3 ? wrap(ox + nlx, R.n[0]) : 0;
-            nkey = (int32_t)encode_key(R, gx, wrap(oy + nly, R.n[1]), wrap(oz + nlz, R.n[2]));
+        if (valid) {
+            const int nlx = lx + s[0], nly = ly + s[1], nlz = lz + s[2];
+            int32_t nkey;
+            if (nlx >= 0 && nlx < hx && nly >= 0 && nly < hy && nlz >= 0 && nlz < hz) {
+                nkey = (int32_t)kb + nlx + hx * (nly + hy * nlz);
+            } else {
+                const int gx = DIM == 3 ? wrap(ox + nlx, R.n[0]) : 0;
+                nkey = (int32_t)encode_key(R, gx, wrap(oy + nly, R.n[1]), wrap(oz + nlz, R.n[2]));
+            }
+            cell_out[i] = nkey;
+            if constexpr (DIM == 3) {
+                off_out[i] = o1[0];
+                off_out[cap + i] = o1[1];
+                off_out[2 * cap + i] = o1[2];
+                mc[i] = (uint8_t)((s[0] + 1) + 3 * (s[1] + 1) + 9 * (s[2] + 1));
+            } else {
+                off_out[i] = o1[1];
+                off_out[cap + i] = o1[2];
+                mc[i] = (uint8_t)((s[1] + 1) + 3 * (s[2] + 1));
+            }
+            u_out[i] = ux;
+            u_out[cap + i] = uy;
+            u_out[2 * cap + i] = uz;
+            if (id_out) id_out[i] = idv;
         }
-        cell_out[i] = nkey;
-        if constexpr (DIM == 3) {
-            off_out[i] = o1[0];
-            off_out[cap + i] = o1[1];
-            off_out[2 * cap + i] = o1[2];
-            mc[i] = (uint8_t)((s[0] + 1) + 3 * (s[1] + 1) + 9 * (s[2] + 1));
-        } else {
-            off_out[i] = o1[1];
-            off_out[cap + i] = o1[2];
-            mc[i] = (uint8_t)((s[1] + 1) + 3 * (s[2] + 1));
-        }
-        u_out[i] = ux;
-        u_out[cap + i] = uy;
-        u_out[2 * cap + i] = uz;
-        if (id_out) id_out[i] = idv;
     }
     if (flags) atomicOr(err, flags);
     __syncthreads();
@@ -473,7 +658,6 @@ __global__ void __launch_bounds__(kBlock) k_push(const RunDev *__restrict__ runs
         if (v != 0.0f) atomicAdd(&gt[t], v);
     }
 }
-
 template <int DIM, int ORDER>
 static hipError_t launch_push_t(const Launch &L, const Unit *units, int n_units, int32_t *item_start,
                                 int64_t max_items, int chunk, int front, int cs_sel, int use_perm,

@@ -102,8 +102,11 @@ def test_sort_matches_stable_sort(kind, order):
         sim.push_fields(1)
         for s in range(len(c.species)):
             keys = sim.front_buffer(0, s)["key"]
+        word_push = sim.error_word()
         sim.sort()
-        assert sim.check() == 0
+        word = sim.error_word()
+        print(f"step {step}: error word after push {word_push:#x}, after sort {word:#x}", flush=True)
+        assert word == 0
         for s in range(len(c.species)):
             f, _ = sim.front()
             n = c.species[s].n
@@ -175,3 +178,28 @@ def test_superluminal_move_flagged():
     sim.push_particles()
     word = sim.error_word(clear=True)
     assert word & (1 | 2)
+
+
+@pytest.mark.parametrize("kind,order", CASES)
+def test_dense_cells_deposit(kind, order):
+    """Many particles per cell: long same-cell runs inside each wave (the
+    wave-segmented current reduction), plus cell-crossers."""
+    if kind == "2d":
+        c = _small_2d(order, seed=41, ny=12, nz=10, patch=4, ppc=90)
+    else:
+        c = _small_3d(order, seed=42, nxyz=(6, 5, 4), patch=3, ppc=70)
+    sim = _sim(c)
+    ora = O.OracleSim(c)
+    sim.push_fields(0)
+    sim.push_particles()
+    sim.deposit_current()
+    assert sim.check() == 0
+    ora.push_b_half()
+    ora.push_particles()
+    for s, sp in enumerate(c.species):
+        dpos, du = particle_errors(c, sim.front_buffer(0, s), ora, s, float(np.std(sp.u)))
+        assert dpos <= 1e-6 and du <= 1e-5
+    _, _, J = sim.field_arrays(0)
+    err = np.abs(J.ravel() - ora.J).max()
+    print(f"dense: max |dJ| = {err:.3e}, max |J| = {np.abs(ora.J).max():.3e}")
+    assert err <= 2e-5 * np.abs(ora.J).max()

@@ -1,0 +1,149 @@
+"""GPU physics checks against the oracle and against invariants.
+
+* FP64 diagnostics (field/kinetic energy, charge, Gauss residual) equal the
+  oracle's on the same float32 state to 1e-9 relative.
+* Gauss invariant: max|G^n - G^0| stays at float32 roundoff
+  (<= 1e-5 * max|rho_species|) over 50 steps (FDTD section: exact under
+  discrete continuity).
+* The 64x64 thermal workload, 100 steps: relative field-energy error <= 1e-4
+  and relative kinetic-energy error <= 1e-5 against the oracle.
+* k = 0 cold plasma oscillation: omega = (2/dt) asin(dt/2) to 1e-5.
+* Batching: runs advanced in one context equal the same runs alone.
+* Patch size does not change the physics (16x16 vs 8x8 patches).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1310_7866_amd import cases
+from tests.helpers import particle_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(case, **kw):
+    from paper_1310_7866_amd.psc import PscSim
+    name = case[0].name + f" x{len(case)}" if isinstance(case, list) else case.name
+    print(f"[gpu] {name}", flush=True)
+    return PscSim(case, **kw)
+
+
+def _charged(order, seed=11, ny=24, nz=20, patch=8, ppc=8):
+    c = cases.thermal2d(ny=ny, nz=nz, ppc=ppc, order=order, patch=patch, seed=seed)
+    c.species[1].off = np.random.default_rng(seed).random(c.species[1].off.shape).astype(np.float32)
+    cases.random_fields(c, 0.02, 0.2, seed=seed + 1)
+    return c
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_diagnostics_match_oracle(order):
+    c = _charged(order)
+    sim = _sim(c)
+    ora = O.OracleSim(c)
+    d, G = sim.diagnostics(with_gauss=True)
+    we, wb = ora.field_energy()
+    ke = ora.kinetic_energy()
+    rho = ora.rho()
+    dV = c.dx[1] * c.dx[2]
+    assert abs(d[0, 0] - we) <= 1e-9 * max(we, 1e-30)
+    assert abs(d[0, 1] - wb) <= 1e-9 * wb
+    for s in range(2):
+        assert abs(d[0, 2 + s] - ke[s]) <= 1e-9 * ke[s]
+    g_ref = ora.div_e() - rho
+    assert np.abs(G - g_ref).max() <= 1e-9 * np.abs(rho).max()
+    assert abs(d[0, 6] - np.abs(g_ref).max()) <= 1e-9 * np.abs(rho).max()
+    assert abs(d[0, 8] - rho.sum() * dV) <= 1e-9 * np.abs(rho).sum() * dV
+    assert d[0, 9] == c.n_particles
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_gauss_invariant_over_steps(order):
+    c = _charged(order, seed=13)
+    sim = _sim(c)
+    _, G0 = sim.diagnostics(with_gauss=True)
+    scale = max(abs(s.q * s.w) for s in c.species)
+    worst = 0.0
+    for k in range(50):
+        sim.step(1)
+        _, G = sim.diagnostics(with_gauss=True)
+        worst = max(worst, np.abs(G - G0).max())
+    sim.check()
+    print(f"order {order}: max |G^n - G^0| over 50 steps = {worst:.3e} (rho scale {scale:.3e})")
+    assert worst <= 1e-5 * scale
+
+
+def test_thermal_workload_energies_100_steps():
+    c = cases.thermal2d()   # 64x64 cells, 16 pairs/cell, order 1, seed 1310
+    sim = _sim(c)
+    ora = O.OracleSim(c)
+    for _ in range(100):
+        sim.step(1, use_graph=True)
+    ora.step(100)
+    sim.check()
+    d = sim.diagnostics()
+    we, wb = ora.field_energy()
+    ke = ora.kinetic_energy()
+    wf = we + wb
+    rel_f = abs(d[0, 0] + d[0, 1] - wf) / wf
+    rel_k = max(abs(d[0, 2 + s] - ke[s]) / ke[s] for s in range(2))
+    print(f"thermal2d 100 steps: field energy {wf:.6e} rel err {rel_f:.2e}; kinetic rel err {rel_k:.2e}")
+    assert rel_f <= 1e-4
+    assert rel_k <= 1e-5
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_plasma_frequency_gpu(order):
+    c = cases.plasma_oscillation2d(order=order, patch=4)
+    sim = _sim(c)
+    hist = []
+    for _ in range(300):
+        sim.step(1)
+        E, _, _ = sim.field_arrays(0)
+        hist.append(float(E[2].astype(np.float64).mean()))
+    e = np.array(hist)
+    cw = (e[1:-1] @ (e[2:] + e[:-2])) / (2 * e[1:-1] @ e[1:-1])
+    omega = math.acos(cw) / c.dt
+    want = (2.0 / c.dt) * math.asin(c.dt / 2.0)
+    print(f"order {order}: omega {omega:.8f} want {want:.8f}")
+    assert abs(omega - want) <= 1e-5 * want
+
+
+def test_batch_equals_runs_alone():
+    runs = [_charged(1, seed=20 + r, ny=16 + 8 * r, nz=12 + 4 * r, patch=8, ppc=4 + 2 * r) for r in range(3)]
+    batch = _sim(runs)
+    alone = [_sim(r) for r in runs]
+    for _ in range(4):
+        batch.step(1)
+        for a in alone:
+            a.step(1)
+    batch.check()
+    for r, a in enumerate(alone):
+        a.check()
+        for s in range(2):
+            pb, pa = batch.particles(r, s), a.particles(0, s)
+            assert np.array_equal(pb["key"], pa["key"])
+            assert np.array_equal(pb["id"], pa["id"])
+            assert np.abs(pb["u"] - pa["u"]).max() <= 1e-6
+            assert np.abs(pb["off"] - pa["off"]).max() <= 1e-6
+        Eb, Bb, _ = batch.field_arrays(r)
+        Ea, Ba, _ = a.field_arrays(0)
+        assert np.abs(Eb - Ea).max() <= 1e-6 * max(np.abs(Ea).max(), 1e-30)
+
+
+def test_patch_size_independence():
+    a = _charged(2, seed=31, ny=32, nz=32, patch=16)
+    b = _charged(2, seed=31, ny=32, nz=32, patch=8)
+    sa, sb = _sim(a), _sim(b)
+    for _ in range(3):
+        sa.step(1)
+        sb.step(1)
+    for s in range(2):
+        pa, pb = sa.particles(0, s), sb.particles(0, s)
+        oa, ob = np.argsort(pa["id"]), np.argsort(pb["id"])
+        assert np.array_equal(pa["cell"][oa], pb["cell"][ob])
+        assert np.abs(pa["u"][:, oa] - pb["u"][:, ob]).max() <= 1e-6
+    Ea, _, _ = sa.field_arrays(0)
+    Eb, _, _ = sb.field_arrays(0)
+    assert np.abs(Ea - Eb).max() <= 1e-6 * np.abs(Ea).max()
