@@ -97,7 +97,11 @@ typedef struct {
     double m[PSC_MAX_SPECIES];      /* mass                                          */
     double w[PSC_MAX_SPECIES];      /* density weight per particle                   */
     int64_t capacity[PSC_MAX_SPECIES]; /* particle slots per buffer                  */
+    int flags;                      /* PSC_RUN_* bits                                 */
 } psc_run_desc;
+
+/* psc_run_desc.flags: reserve workspace for psc_adjoint_step */
+#define PSC_RUN_ADJOINT 1
 
 typedef struct {
     float *E, *B, *J;                          /* 3 * ncell float32 each               */
@@ -130,7 +134,9 @@ psc_status psc_bind(psc_ctx *ctx, const psc_run_bufs *bufs, int n_runs, void *wo
  * goff float32 (D, n) row-major (array d at goff + d*n), gu float32 (3, n),
  * gid int32 (n) or NULL.  Converts cells to patch-major keys and stably sorts
  * by key into buffer set 0 (input order kept among equal keys).  n must not
- * exceed the species capacity.  Call for every species before stepping. */
+ * exceed the species capacity.  Call for every species before stepping.
+ * Loading after steps have run restarts the context: every species must be
+ * loaded again before the next step (used to restore checkpoints). */
 psc_status psc_load_particles(psc_ctx *ctx, int run, int species, int64_t n, const int32_t *gcell,
                               const float *goff, const float *gu, const int32_t *gid, void *stream);
 
@@ -167,6 +173,33 @@ psc_status psc_sort(psc_ctx *ctx, void *stream);
  * once per buffer parity and replays it. */
 psc_status psc_step(psc_ctx *ctx, int nsteps, int use_graph, void *stream);
 
+/* Launch shape of the particle kernel (batching and autotuning).
+ * mode: PSC_LAUNCH_GRID      one workgroup per work item (default);
+ *       PSC_LAUNCH_QUEUE     persistent workgroups pulling work items from
+ *                            eight queues (one per XCD, with stealing);
+ *       PSC_LAUNCH_PARTITION persistent workgroups, each over a contiguous
+ *                            segment of (run, patch, species) units chosen
+ *                            by psc_balance (called here once).
+ * chunk: particles per work item (0 keeps the current value).
+ * workers: persistent workgroups (0 = compute units x workgroups that fit
+ * in one unit's LDS).  Drops recorded step graphs.  May synchronize. */
+#define PSC_LAUNCH_GRID 0
+#define PSC_LAUNCH_QUEUE 1
+#define PSC_LAUNCH_PARTITION 2
+psc_status psc_set_launch(psc_ctx *ctx, int mode, int chunk, int workers, void *stream);
+
+/* Recompute the PSC_LAUNCH_PARTITION split from the current particle
+ * counts (App. A, "Load balancing algorithm", with every workgroup of equal
+ * capability): unit loads L = N_particles + cell_cost * N_cells (the load
+ * estimate of the load-balancing section), in unit order.  Synchronizes
+ * `stream`. */
+psc_status psc_balance(psc_ctx *ctx, double cell_cost, void *stream);
+
+/* The greedy partition of App. A on host arrays: loads L[n_patches] in
+ * space-filling-curve order and capabilities C[n_ranks] give N[n_ranks],
+ * the number of consecutive patches of each rank.  Pure host function. */
+psc_status psc_partition(const double *L, int n_patches, const double *C, int n_ranks, int32_t *N);
+
 /* Write the particles of (run, species) in sorted key order into caller
  * device arrays (same layout as the buffers, stride n): cell keys, offsets,
  * momenta, ids (any pointer may be NULL to skip it). */
@@ -196,6 +229,43 @@ psc_status psc_sort_view(const psc_ctx *ctx, int run, int species, const int32_t
  * per node, runs concatenated. */
 #define PSC_DIAG_STRIDE 10
 psc_status psc_diagnostics(psc_ctx *ctx, double *out_dev, double *gauss_dev, void *stream);
+
+/* Copy the permutation of the last psc_sort of (run, species) to a caller
+ * device array (int32, n): entry j is the slot, in the order the last
+ * psc_push_particles wrote, of the particle that sorts to position j. */
+psc_status psc_get_perm(psc_ctx *ctx, int run, int species, int32_t *perm, void *stream);
+
+/* Forward state of one step, per run, as the adjoint needs it: fields at the
+ * start of the step (E^{n+1/2}, B^n), the particles at the start of the step
+ * in sorted key order (as psc_get_particles writes them, stride n), and the
+ * permutation of the step's sort (psc_get_perm after the step). */
+typedef struct {
+    const float *E, *B;
+    const int32_t *cell[PSC_MAX_SPECIES];
+    const float *off[PSC_MAX_SPECIES];
+    const float *u[PSC_MAX_SPECIES];
+    const int32_t *perm[PSC_MAX_SPECIES];
+} psc_adj_fwd;
+
+/* Adjoint state, per run: on entry the adjoints of the step's outputs
+ * (E^{n+3/2}, B^{n+1}, particle offsets and momenta in the sorted order of the
+ * next step); on return those of its inputs (E^{n+1/2}, B^n, particles in the
+ * sorted order of this step).  Float32, same layouts as the state; updated in
+ * place. */
+typedef struct {
+    float *lE, *lB;
+    float *loff[PSC_MAX_SPECIES];   /* D x n */
+    float *lu[PSC_MAX_SPECIES];     /* 3 x n */
+} psc_adj_state;
+
+/* Reverse of one full time step (transpose of the discrete step of
+ * fig. psc_new: E full step, second B half step, particle loop with the
+ * Esirkepov deposit, move, Boris rotation and interpolation, first B half
+ * step).  The paper defines no adjoint; this is the exact derivative of the
+ * forward kernels' arithmetic.  Needs PSC_RUN_ADJOINT in every run's flags;
+ * 2-d runs only (PSC_ERR_UNSUPPORTED for 3-d).  fwd and adj hold n_runs
+ * entries. */
+psc_status psc_adjoint_step(psc_ctx *ctx, const psc_adj_fwd *fwd, const psc_adj_state *adj, void *stream);
 
 /* Synchronize `stream` and return the device error word as a status:
  * PSC_OK, PSC_ERR_NONFINITE, PSC_ERR_PARTICLE. *word (optional) receives the

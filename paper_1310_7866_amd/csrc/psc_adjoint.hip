@@ -1,0 +1,605 @@
+// psc_adjoint.hip -- hand-written reverse of one time step (2-d runs).
+//
+// The paper has no adjoint; this is the exact transpose of the discrete step
+// of fig. psc_new as implemented by the forward kernels:
+//   B1 = B  - dt/2 curl^+ E                    (B half step)
+//   particles: gather E, B1 -> Boris -> move -> Esirkepov J
+//   B2 = B1 - dt/2 curl^+ E                    (B half step)
+//   E' = E  + dt (curl^- B2 - J)               (E full step)
+// Given the adjoints (lE', lB2, lx', lu') of the step's output it returns
+// (lE, lB, lx, lu) of its input.  On a periodic Yee grid curl^+ and curl^- are
+// transposes of each other.  The particle part recomputes the forward of every
+// particle and back-propagates through the deposit, the move, the Boris
+// rotation and the interpolation; the transpose of the interpolation scatters
+// into LDS tiles that are added into the grid adjoints like the current fold.
+#include "psc_device.h"
+
+namespace psc {
+
+// derivatives of node_weights / half_weights with respect to the offset
+template <int ORDER>
+__device__ __forceinline__ void node_dweights(float o, float dw[ORDER + 1]) {
+    if constexpr (ORDER == 1) {
+        dw[0] = -1.0f;
+        dw[1] = 1.0f;
+    } else {
+        const float d = o - (o >= 0.5f ? 1.0f : 0.0f);
+        dw[0] = -(0.5f - d);
+        dw[1] = -2.0f * d;
+        dw[2] = 0.5f + d;
+    }
+}
+
+template <int ORDER>
+__device__ __forceinline__ void half_dweights(float o, float dw[ORDER + 1]) {
+    if constexpr (ORDER == 1) {
+        dw[0] = -1.0f;
+        dw[1] = 1.0f;
+    } else {
+        const float d = o - 0.5f;
+        dw[0] = -(0.5f - d);
+        dw[1] = -2.0f * d;
+        dw[2] = 0.5f + d;
+    }
+}
+
+// stencil() with the derivatives of the placed weights
+template <int ORDER>
+__device__ __forceinline__ int stencil_d(float o0, int s, float o1, float S0[ORDER + 2], float S1[ORDER + 2],
+                                        float D0[ORDER + 2], float D1[ORDER + 2]) {
+    float w0[ORDER + 1], w1[ORDER + 1], d0[ORDER + 1], d1[ORDER + 1];
+    const int b0 = node_weights<ORDER>(o0, w0);
+    const int b1 = node_weights<ORDER>(o1, w1) + s;
+    node_dweights<ORDER>(o0, d0);
+    node_dweights<ORDER>(o1, d1);
+    const int base = b0 < b1 ? b0 : b1;
+    const bool k0 = b0 != base, k1 = b1 != base;
+#pragma unroll
+    for (int r = 0; r < ORDER + 2; ++r) {
+        S0[r] = k0 ? (r >= 1 ? w0[r - 1] : 0.0f) : (r <= ORDER ? w0[r] : 0.0f);
+        S1[r] = k1 ? (r >= 1 ? w1[r - 1] : 0.0f) : (r <= ORDER ? w1[r] : 0.0f);
+        D0[r] = k0 ? (r >= 1 ? d0[r - 1] : 0.0f) : (r <= ORDER ? d0[r] : 0.0f);
+        D1[r] = k1 ? (r >= 1 ? d1[r - 1] : 0.0f) : (r <= ORDER ? d1[r] : 0.0f);
+    }
+    return base;
+}
+
+// interpolation of one component with its offset derivatives
+template <int ORDER>
+__device__ __forceinline__ float gather2_d(const float *F, int pitch, int iy, int iz, const float *wy,
+                                           const float *dwy, const float *wz, const float *dwz, float &gy,
+                                           float &gz) {
+    const float *p = F + iz * pitch + iy;
+    float s = 0.0f, sy = 0.0f, sz = 0.0f;
+#pragma unroll
+    for (int b = 0; b <= ORDER; ++b) {
+        float r = 0.0f, rd = 0.0f;
+#pragma unroll
+        for (int a = 0; a <= ORDER; ++a) {
+            const float f = p[b * pitch + a];
+            r = fmaf(wy[a], f, r);
+            rd = fmaf(dwy[a], f, rd);
+        }
+        s = fmaf(wz[b], r, s);
+        sy = fmaf(wz[b], rd, sy);
+        sz = fmaf(dwz[b], r, sz);
+    }
+    gy = sy;
+    gz = sz;
+    return s;
+}
+
+// transpose of the interpolation: scatter lam * weights into an LDS tile
+template <int ORDER>
+__device__ __forceinline__ void scatter2(float *G, int pitch, int iy, int iz, const float *wy, const float *wz,
+                                         float lam) {
+    float *p = G + iz * pitch + iy;
+#pragma unroll
+    for (int b = 0; b <= ORDER; ++b)
+#pragma unroll
+        for (int a = 0; a <= ORDER; ++a) atomicAdd(&p[b * pitch + a], lam * wy[a] * wz[b]);
+}
+
+__device__ __forceinline__ float3 cross3(float3 a, float3 b) {
+    return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ float3 add3(float3 a, float3 b) { return make_float3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ float3 scale3(float3 a, float s) { return make_float3(a.x * s, a.y * s, a.z * s); }
+
+// ---------------------------------------------------------------------------
+// field parts of the reverse step
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int find_run_a(const int64_t *base, int n_runs, int64_t c) {
+    int lo = 0, hi = n_runs;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (base[mid] <= c) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// op 0: LJ = -dt lE ; lB += dt curl^+ lE
+// op 1: lE -= dt/2 curl^- lB ; B1 = B - dt/2 curl^+ E
+// op 2: lE -= dt/2 curl^- lB
+__global__ void __launch_bounds__(256) k_adj_fields(const RunDev *__restrict__ runs, const AdjRun *__restrict__ adj,
+                                                    int n_runs, const int64_t *__restrict__ run_base, int64_t total,
+                                                    int op) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= total) return;
+    const int r = find_run_a(run_base, n_runs, c);
+    const RunDev &R = runs[r];
+    const AdjRun &A = adj[r];
+    const int64_t idx = c - R.cell_base;
+    const int nx = R.n[0], ny = R.n[1], nz = R.n[2];
+    const int i = (int)(idx % nx), j = (int)((idx / nx) % ny), k = (int)(idx / ((int64_t)nx * ny));
+    const int64_t nc = R.ncell;
+    const bool three = R.dim == 3;
+    const float ix = three ? R.inv_dx[0] : 0.0f, iy = R.inv_dx[1], iz = R.inv_dx[2];
+    const int64_t sy = nx, sz = (int64_t)nx * ny;
+    const int64_t ip = i + 1 < nx ? idx + 1 : idx - (nx - 1);
+    const int64_t jp = j + 1 < ny ? idx + sy : idx - (int64_t)(ny - 1) * sy;
+    const int64_t kp = k + 1 < nz ? idx + sz : idx - (int64_t)(nz - 1) * sz;
+    const int64_t im = i > 0 ? idx - 1 : idx + (nx - 1);
+    const int64_t jm = j > 0 ? idx - sy : idx + (int64_t)(ny - 1) * sy;
+    const int64_t km = k > 0 ? idx - sz : idx + (int64_t)(nz - 1) * sz;
+    auto curl_plus = [&](const float *F, float &cx, float &cy, float &cz) {
+        const float fx = F[idx], fy = F[nc + idx], fz = F[2 * nc + idx];
+        cx = (F[2 * nc + jp] - fz) * iy - (F[nc + kp] - fy) * iz;
+        cy = (F[kp] - fx) * iz - (three ? (F[2 * nc + ip] - fz) * ix : 0.0f);
+        cz = (three ? (F[nc + ip] - fy) * ix : 0.0f) - (F[jp] - fx) * iy;
+    };
+    auto curl_minus = [&](const float *F, float &cx, float &cy, float &cz) {
+        const float fx = F[idx], fy = F[nc + idx], fz = F[2 * nc + idx];
+        cx = (fz - F[2 * nc + jm]) * iy - (fy - F[nc + km]) * iz;
+        cy = (fx - F[km]) * iz - (three ? (fz - F[2 * nc + im]) * ix : 0.0f);
+        cz = (three ? (fy - F[nc + im]) * ix : 0.0f) - (fx - F[jm]) * iy;
+    };
+    const float dt = R.dt;
+    float cx, cy, cz;
+    if (op == 0) {
+        curl_plus(A.lE, cx, cy, cz);
+        for (int q = 0; q < 3; ++q) A.LJ[q * nc + idx] = -dt * A.lE[q * nc + idx];
+        A.lB[idx] += dt * cx;
+        A.lB[nc + idx] += dt * cy;
+        A.lB[2 * nc + idx] += dt * cz;
+    } else {
+        curl_minus(A.lB, cx, cy, cz);
+        A.lE[idx] -= 0.5f * dt * cx;
+        A.lE[nc + idx] -= 0.5f * dt * cy;
+        A.lE[2 * nc + idx] -= 0.5f * dt * cz;
+        if (op == 1) {
+            curl_plus(A.E, cx, cy, cz);
+            A.B1[idx] = A.B[idx] - 0.5f * dt * cx;
+            A.B1[nc + idx] = A.B[nc + idx] - 0.5f * dt * cy;
+            A.B1[2 * nc + idx] = A.B[2 * nc + idx] - 0.5f * dt * cz;
+        }
+    }
+}
+
+// move the incoming particle adjoints (next step's sorted order) to this
+// step's slots: slot perm[j] holds the particle that the sort put at j
+__global__ void k_adj_unpermute(const AdjRun *__restrict__ adj, int r, int s, int dim) {
+    const AdjSpecies &S = adj[r].sp[s];
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= S.n) return;
+    const int64_t p = S.perm[j];
+    if (p < 0 || p >= S.n) return;
+    for (int d = 0; d < dim; ++d) S.soff[d * S.n + p] = S.loff[d * S.n + j];
+    for (int c = 0; c < 3; ++c) S.su[c * S.n + p] = S.lu[c * S.n + j];
+}
+
+__global__ void k_adj_count(const RunDev *__restrict__ runs, const AdjRun *__restrict__ adj, int r, int s,
+                            uint32_t *err) {
+    const AdjSpecies &S = adj[r].sp[s];
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= S.n) return;
+    const int32_t key = S.key[j];
+    if (key < 0 || key >= runs[r].ncell) {
+        atomicOr(err, PSC_DEV_KEY);
+        return;
+    }
+    atomicAdd(&S.tot[key], 1);
+}
+
+__global__ void __launch_bounds__(1024) k_adj_items(const RunDev *__restrict__ runs, const AdjRun *__restrict__ adj,
+                                                    const Unit *__restrict__ units, int n_units, int chunk,
+                                                    int32_t *__restrict__ item_start) {
+    __shared__ int32_t part[1024];
+    const int t = threadIdx.x;
+    const int per = (n_units + 1023) / 1024;
+    const int u0 = t * per, u1 = imin(u0 + per, n_units);
+    auto count = [&](int u) {
+        const Unit U = units[u];
+        const RunDev &R = runs[U.run];
+        int pc[3];
+        patch_coords(R, U.patch, pc);
+        const int64_t kb = patch_key_base(R, pc[0], pc[1], pc[2]);
+        const int64_t ke = kb + (int64_t)patch_ext(R, 0, pc[0]) * patch_ext(R, 1, pc[1]) * patch_ext(R, 2, pc[2]);
+        const int32_t *cs = adj[U.run].sp[U.species].cs;
+        return (cs[ke] - cs[kb] + chunk - 1) / chunk;
+    };
+    int32_t sum = 0;
+    for (int u = u0; u < u1; ++u) sum += count(u);
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int32_t v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int32_t run = part[t] - sum;
+    for (int u = u0; u < u1; ++u) {
+        item_start[u] = run;
+        run += count(u);
+    }
+    if (t == 1023) item_start[n_units] = part[1023];
+}
+
+// ---------------------------------------------------------------------------
+// the particle adjoint kernel (2-d)
+// ---------------------------------------------------------------------------
+template <int ORDER>
+__global__ void __launch_bounds__(kBlock) k_adj_particles(const RunDev *__restrict__ runs,
+                                                          const AdjRun *__restrict__ adj,
+                                                          const Unit *__restrict__ units,
+                                                          const int32_t *__restrict__ item_start, int n_units,
+                                                          int chunk) {
+    extern __shared__ float lds[];
+    constexpr int L = ORDER + 2;
+    constexpr int FLO = 1, FHI = ORDER;
+    constexpr int JLO = ORDER;
+
+    const int nb = gridDim.x;
+    const int item = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+    const int total = item_start[n_units];
+    if (item >= total) return;
+    int lo = 0, hi = n_units;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (item_start[mid] <= item) lo = mid; else hi = mid;
+    }
+    const Unit U = units[lo];
+    const RunDev &R = runs[U.run];
+    const AdjRun &A = adj[U.run];
+    const SpeciesDev &S = R.sp[U.species];
+    const AdjSpecies &AS = A.sp[U.species];
+
+    int pc[3];
+    patch_coords(R, U.patch, pc);
+    const int hy = patch_ext(R, 1, pc[1]), hz = patch_ext(R, 2, pc[2]);
+    const int oy = pc[1] * R.P[1], oz = pc[2] * R.P[2];
+    const int64_t kb = patch_key_base(R, 0, pc[1], pc[2]);
+    const int32_t pbeg = AS.cs[kb], pend = AS.cs[kb + (int64_t)hy * hz];
+    const int32_t beg = pbeg + (item - item_start[lo]) * chunk;
+    const int32_t end = min(beg + chunk, pend);
+
+    const int fy = R.P[1] + FLO + FHI, fz = R.P[2] + FLO + FHI;
+    const int fcells = fy * fz;
+    float *ftile = lds;               // E, B1
+    float *gt = lds + 6 * fcells;     // transposed interpolation of E, B1
+    const int64_t nc = R.ncell;
+    {
+        const float inv_fy = 1.0f / fy;
+        for (int t = threadIdx.x; t < fcells; t += kBlock) {
+            int ty;
+            const int tz = divmod_small(t, fy, inv_fy, ty);
+            const int64_t g = wrap(oy + ty - FLO, R.n[1]) + (int64_t)R.n[1] * wrap(oz + tz - FLO, R.n[2]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                ftile[c * fcells + t] = A.E[c * nc + g];
+                ftile[(3 + c) * fcells + t] = A.B1[c * nc + g];
+            }
+        }
+        for (int t = threadIdx.x; t < 6 * fcells; t += kBlock) gt[t] = 0.0f;
+    }
+    __syncthreads();
+
+    const int64_t n = AS.n;
+    const float h = S.qdt_2m, qw = S.qw, dt = R.dt;
+    const float cfy = dt * R.inv_dx[1], cfz = dt * R.inv_dx[2];
+    const float jfy = -qw * R.dx[1] / dt, jfz = -qw * R.dx[2] / dt;
+    const float inv_hy = 1.0f / hy;
+    const int ny = R.n[1], nzc = R.n[2];
+
+    for (int32_t i = beg + threadIdx.x; i < end; i += kBlock) {
+        const int32_t key = AS.key[i];
+        int local = key - (int32_t)kb;
+        if (local < 0 || local >= hy * hz) local = 0;
+        int ly;
+        const int lz = divmod_small(local, hy, inv_hy, ly);
+        const float oyv = AS.off[i], ozv = AS.off[n + i];
+        const float3 u0 = make_float3(AS.u[i], AS.u[n + i], AS.u[2 * n + i]);
+
+        // ---- forward recompute: interpolation (with offset derivatives) ----
+        float wny[ORDER + 1], why[ORDER + 1], wnz[ORDER + 1], whz[ORDER + 1];
+        float dny[ORDER + 1], dhy[ORDER + 1], dnz[ORDER + 1], dhz[ORDER + 1];
+        const int bny = node_weights<ORDER>(oyv, wny), bhy = half_weights<ORDER>(oyv, why);
+        const int bnz = node_weights<ORDER>(ozv, wnz), bhz = half_weights<ORDER>(ozv, whz);
+        node_dweights<ORDER>(oyv, dny);
+        half_dweights<ORDER>(oyv, dhy);
+        node_dweights<ORDER>(ozv, dnz);
+        half_dweights<ORDER>(ozv, dhz);
+        const int ty = ly + FLO, tz = lz + FLO;
+        // component c: (y index, z index, y weights, z weights)
+        const int cy_[6] = {ty + bny, ty + bhy, ty + bny, ty + bhy, ty + bny, ty + bhy};
+        const int cz_[6] = {tz + bnz, tz + bnz, tz + bhz, tz + bhz, tz + bhz, tz + bnz};
+        float F[6], Gy[6], Gz[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            const bool hyc = c == 1 || c == 3 || c == 5;
+            const bool hzc = c == 2 || c == 3 || c == 4;
+            F[c] = gather2_d<ORDER>(ftile + c * fcells, fy, cy_[c], cz_[c], hyc ? why : wny, hyc ? dhy : dny,
+                                    hzc ? whz : wnz, hzc ? dhz : dnz, Gy[c], Gz[c]);
+        }
+        const float3 Ep = make_float3(F[0], F[1], F[2]);
+        const float3 Bp = make_float3(F[3], F[4], F[5]);
+
+        // ---- Boris with intermediates ---------------------------------------
+        const float3 um = add3(u0, scale3(Ep, h));
+        const float igm = rsqrtf(1.0f + dot3(um, um));
+        const float3 t = scale3(Bp, h * igm);
+        const float t2 = dot3(t, t);
+        const float f = 2.0f / (1.0f + t2);
+        const float3 s = scale3(t, f);
+        const float3 up = add3(um, cross3(um, t));
+        const float3 uq = add3(um, cross3(up, s));
+        const float3 un = add3(uq, scale3(Ep, h));
+        const float ig = rsqrtf(1.0f + dot3(un, un));
+
+        // ---- move -------------------------------------------------------------
+        int sh[2];
+        float o1[2];
+        const float o0[2] = {oyv, ozv};
+        const float cf[2] = {cfy, cfz};
+        const float uu[2] = {un.y, un.z};
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            float disp = cf[d] * uu[d] * ig;
+            if (!(fabsf(disp) < 0.99f)) disp = 0.0f;
+            const float x1 = o0[d] + disp;
+            int sd = (int)floorf(x1);
+            float od = x1 - (float)sd;
+            if (od >= 1.0f) { od -= 1.0f; sd += 1; }
+            sh[d] = sd;
+            o1[d] = od;
+        }
+
+        // ---- reverse ----------------------------------------------------------
+        float lx1[2] = {AS.soff[i], AS.soff[n + i]};          // adjoint of the moved offsets
+        float3 lun = make_float3(AS.su[i], AS.su[n + i], AS.su[2 * n + i]);
+        float lo0[2] = {0.0f, 0.0f};
+        float lig = 0.0f;
+
+        // deposit: J values on the stencil, adjoint read from the grid
+        {
+            float S0y[L], S1y[L], S0z[L], S1z[L], D0y[L], D1y[L], D0z[L], D1z[L];
+            const int by = stencil_d<ORDER>(oyv, sh[0], o1[0], S0y, S1y, D0y, D1y);
+            const int bz = stencil_d<ORDER>(ozv, sh[1], o1[1], S0z, S1z, D0z, D1z);
+            float DSy[L], DSz[L], Ay[L], Az[L], Cy[L], Cz[L];
+#pragma unroll
+            for (int r = 0; r < L; ++r) {
+                DSy[r] = S1y[r] - S0y[r];
+                DSz[r] = S1z[r] - S0z[r];
+                Ay[r] = fmaf(0.5f, DSy[r], S0y[r]);
+                Az[r] = fmaf(0.5f, DSz[r], S0z[r]);
+                Cy[r] = r == 0 ? DSy[0] : Cy[r - 1] + DSy[r];
+                Cz[r] = r == 0 ? DSz[0] : Cz[r - 1] + DSz[r];
+            }
+            const float vx = un.x * ig;
+            const float fxv = qw * vx;
+            float gCy[L], gCz[L], gAy[L], gAz[L], gDy[L], gDz[L];
+#pragma unroll
+            for (int r = 0; r < L; ++r) gCy[r] = gCz[r] = gAy[r] = gAz[r] = gDy[r] = gDz[r] = 0.0f;
+            float gfxv = 0.0f;
+            const int gy0 = oy + ly + by, gz0 = oz + lz + bz;
+#pragma unroll
+            for (int b = 0; b < L; ++b) {
+                const int64_t row = (int64_t)ny * wrap(gz0 + b, nzc);
+#pragma unroll
+                for (int a = 0; a < L; ++a) {
+                    const int64_t g = row + wrap(gy0 + a, ny);
+                    const float ljx = A.LJ[g], ljy = A.LJ[nc + g], ljz = A.LJ[2 * nc + g];
+                    if (a < L - 1) {   // J_y(a, b) = jfy Cy[a] Az[b]
+                        gCy[a] += jfy * ljy * Az[b];
+                        gAz[b] += jfy * ljy * Cy[a];
+                    }
+                    if (b < L - 1) {   // J_z(a, b) = jfz Ay[a] Cz[b]
+                        gAy[a] += jfz * ljz * Cz[b];
+                        gCz[b] += jfz * ljz * Ay[a];
+                    }
+                    // J_x(a, b) = fxv (Ay Az + DSy DSz / 12)
+                    gAy[a] += fxv * ljx * Az[b];
+                    gAz[b] += fxv * ljx * Ay[a];
+                    gDy[a] += fxv * ljx * DSz[b] * (1.0f / 12.0f);
+                    gDz[b] += fxv * ljx * DSy[a] * (1.0f / 12.0f);
+                    gfxv += ljx * fmaf(DSy[a] * DSz[b], 1.0f / 12.0f, Ay[a] * Az[b]);
+                }
+            }
+            // cumulative sums: C[r] = sum_{r' <= r} DS[r'], used for r < L-1
+            float accy = 0.0f, accz = 0.0f;
+#pragma unroll
+            for (int r = L - 1; r >= 0; --r) {
+                accy += r < L - 1 ? gCy[r] : 0.0f;
+                accz += r < L - 1 ? gCz[r] : 0.0f;
+                gDy[r] += accy;
+                gDz[r] += accz;
+            }
+            // A = S0 + DS/2, DS = S1 - S0
+            float l1y = 0.0f, l1z = 0.0f;
+#pragma unroll
+            for (int r = 0; r < L; ++r) {
+                const float dsy = gDy[r] + 0.5f * gAy[r], dsz = gDz[r] + 0.5f * gAz[r];
+                lo0[0] += (gAy[r] - dsy) * D0y[r];
+                lo0[1] += (gAz[r] - dsz) * D0z[r];
+                l1y += dsy * D1y[r];
+                l1z += dsz * D1z[r];
+            }
+            lx1[0] += l1y;
+            lx1[1] += l1z;
+            // fxv = qw un.x ig
+            lun.x += qw * ig * gfxv;
+            lig += qw * un.x * gfxv;
+        }
+        // move: x1 = o0 + cf un ig
+        lo0[0] += lx1[0];
+        lo0[1] += lx1[1];
+        lun.y += cfy * ig * lx1[0];
+        lun.z += cfz * ig * lx1[1];
+        lig += cfy * un.y * lx1[0] + cfz * un.z * lx1[1];
+        lun = add3(lun, scale3(un, -ig * ig * ig * lig));
+
+        // Boris reverse
+        float3 lE = scale3(lun, h);
+        const float3 luq = lun;
+        float3 lum = luq;
+        const float3 lup = cross3(s, luq);
+        const float3 ls = cross3(luq, up);
+        lum = add3(lum, add3(lup, cross3(t, lup)));
+        float3 lt = cross3(lup, um);
+        // s = f t with f = 2 / (1 + |t|^2), df/dt = -f^2 t
+        lt = add3(lt, add3(scale3(ls, f), scale3(t, -f * f * dot3(ls, t))));
+        const float3 lB = scale3(lt, h * igm);
+        const float ligm = h * dot3(Bp, lt);
+        lum = add3(lum, scale3(um, -igm * igm * igm * ligm));
+        lE = add3(lE, scale3(lum, h));
+        const float3 lu0 = lum;
+
+        // interpolation reverse: offsets and scatter into the tiles
+        const float lF[6] = {lE.x, lE.y, lE.z, lB.x, lB.y, lB.z};
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            lo0[0] += lF[c] * Gy[c];
+            lo0[1] += lF[c] * Gz[c];
+            const bool hyc = c == 1 || c == 3 || c == 5;
+            const bool hzc = c == 2 || c == 3 || c == 4;
+            scatter2<ORDER>(gt + c * fcells, fy, cy_[c], cz_[c], hyc ? why : wny, hzc ? whz : wnz, lF[c]);
+        }
+
+        AS.loff[i] = lo0[0];
+        AS.loff[n + i] = lo0[1];
+        AS.lu[i] = lu0.x;
+        AS.lu[n + i] = lu0.y;
+        AS.lu[2 * n + i] = lu0.z;
+    }
+    __syncthreads();
+    float *gp = A.gtile + (int64_t)U.patch * 6 * fcells;
+    for (int t2 = threadIdx.x; t2 < 6 * fcells; t2 += kBlock) {
+        const float v = gt[t2];
+        if (v != 0.0f) atomicAdd(&gp[t2], v);
+    }
+}
+
+// fold the transposed-interpolation tiles (field-tile geometry) into lE, lB
+__global__ void __launch_bounds__(256) k_adj_fold(const RunDev *__restrict__ runs, const AdjRun *__restrict__ adj,
+                                                  int n_runs, const int64_t *__restrict__ run_base, int64_t total) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= total) return;
+    const int r = find_run_a(run_base, n_runs, c);
+    const RunDev &R = runs[r];
+    const AdjRun &A = adj[r];
+    const int64_t idx = c - R.cell_base;
+    const int g[2] = {(int)(idx % R.n[1]), (int)(idx / R.n[1])};   // 2-d: (y, z)
+    const int lo = 1, hi = R.order;
+    const int fy = R.P[1] + lo + hi, fz = R.P[2] + lo + hi;
+    const int64_t fcells = (int64_t)fy * fz;
+    int cand[2][3], ncand[2];
+    for (int d = 0; d < 2; ++d) {
+        const int own = g[d] / R.P[d + 1];
+        ncand[d] = 0;
+        for (int t = -1; t <= 1; ++t) {
+            const int pcd = wrap(own + t, R.np[d + 1]);
+            bool dup = false;
+            for (int q = 0; q < ncand[d]; ++q) dup |= cand[d][q] == pcd;
+            if (!dup) cand[d][ncand[d]++] = pcd;
+        }
+    }
+    float acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int a1 = 0; a1 < ncand[1]; ++a1)
+        for (int a0 = 0; a0 < ncand[0]; ++a0) {
+            const int pcy = cand[0][a0], pcz = cand[1][a1];
+            const int p = R.np[0] * (pcy + R.np[1] * pcz);
+            float *tile = A.gtile + (int64_t)p * 6 * fcells;
+            int ls[2][3], nl[2];
+            const int pcs[2] = {pcy, pcz};
+            for (int d = 0; d < 2; ++d) {
+                nl[d] = 0;
+                const int ext = patch_ext(R, d + 1, pcs[d]);
+                const int base = g[d] - pcs[d] * R.P[d + 1];
+                for (int m = -1; m <= 1; ++m) {
+                    const int l = base + m * R.n[d + 1];
+                    if (l >= -lo && l < ext + hi) ls[d][nl[d]++] = l;
+                }
+            }
+            for (int z = 0; z < nl[1]; ++z)
+                for (int y = 0; y < nl[0]; ++y) {
+                    const int64_t t = (ls[0][y] + lo) + (int64_t)fy * (ls[1][z] + lo);
+                    for (int q = 0; q < 6; ++q) {
+                        acc[q] += tile[q * fcells + t];
+                        tile[q * fcells + t] = 0.0f;
+                    }
+                }
+        }
+    const int64_t nc = R.ncell;
+    for (int q = 0; q < 3; ++q) {
+        A.lE[q * nc + idx] += acc[q];
+        A.lB[q * nc + idx] += acc[3 + q];
+    }
+}
+
+size_t adjoint_lds_bytes(int order, const int P[3]) {
+    const int fy = P[1] + 1 + order, fz = P[2] + 1 + order;
+    return sizeof(float) * 12 * (size_t)fy * fz;
+}
+
+hipError_t launch_adjoint(const Launch &L, const AdjRun *adj_dev, const AdjRun *adj_host, const Unit *units,
+                          int n_units, int32_t *item_start, int64_t max_items, int chunk, int order,
+                          int64_t total_cells, const int64_t *run_base, const ScanSeg *seg_dev, int32_t *blockseg,
+                          int32_t *sums, size_t lds, hipStream_t s) {
+    const unsigned gc = (unsigned)((total_cells + 255) / 256);
+    // (1) LJ = -dt lE', lB2 = lB' + dt curl^+ lE'
+    hipLaunchKernelGGL(k_adj_fields, dim3(gc), dim3(256), 0, s, L.runs_dev, adj_dev, L.n_runs, run_base, total_cells, 0);
+    // (2) lE -= dt/2 curl^- lB2, B1 = B - dt/2 curl^+ E
+    hipLaunchKernelGGL(k_adj_fields, dim3(gc), dim3(256), 0, s, L.runs_dev, adj_dev, L.n_runs, run_base, total_cells, 1);
+    // (3) particle adjoints to this step's slots; cell offsets of the forward keys
+    for (int r = 0; r < L.n_runs; ++r) {
+        const RunDev &R = L.runs_host[r];
+        for (int sp = 0; sp < R.n_species; ++sp) {
+            const AdjSpecies &S = adj_host[r].sp[sp];
+            if (S.n == 0) {
+                hipError_t e = launch_fill_i32(S.cs, R.ncell + 1, 0, s);
+                if (e != hipSuccess) return e;
+                continue;
+            }
+            const unsigned gp = (unsigned)((S.n + 255) / 256);
+            hipLaunchKernelGGL(k_adj_unpermute, dim3(gp), dim3(256), 0, s, adj_dev, r, sp, R.dim);
+            hipError_t e = launch_fill_i32(S.tot, R.ncell, 0, s);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_adj_count, dim3(gp), dim3(256), 0, s, L.runs_dev, adj_dev, r, sp, L.err);
+            const ScanSeg *sg = seg_dev + (r * kMaxSpecies + sp);
+            const int64_t nb = (R.ncell + kScanBlock - 1) / kScanBlock;
+            e = launch_fill_i32(blockseg, nb, 0, s);
+            if (e != hipSuccess) return e;
+            e = launch_scan(sg, 1, nb, blockseg, sums, s);
+            if (e != hipSuccess) return e;
+        }
+    }
+    // (4) particles
+    hipLaunchKernelGGL(k_adj_items, dim3(1), dim3(1024), 0, s, L.runs_dev, adj_dev, units, n_units, chunk, item_start);
+    int64_t grid = (max_items + 7) / 8 * 8;
+    if (grid < 8) grid = 8;
+    if (order == 1)
+        hipLaunchKernelGGL(k_adj_particles<1>, dim3((unsigned)grid), dim3(kBlock), lds, s, L.runs_dev, adj_dev, units,
+                           item_start, n_units, chunk);
+    else
+        hipLaunchKernelGGL(k_adj_particles<2>, dim3((unsigned)grid), dim3(kBlock), lds, s, L.runs_dev, adj_dev, units,
+                           item_start, n_units, chunk);
+    // (5) transposed interpolation into lE, lB1
+    hipLaunchKernelGGL(k_adj_fold, dim3(gc), dim3(256), 0, s, L.runs_dev, adj_dev, L.n_runs, run_base, total_cells);
+    // (6) lE -= dt/2 curl^- lB1   (lB = lB1 is the adjoint of B^n)
+    hipLaunchKernelGGL(k_adj_fields, dim3(gc), dim3(256), 0, s, L.runs_dev, adj_dev, L.n_runs, run_base, total_cells, 2);
+    return hipGetLastError();
+}
+
+}  // namespace psc

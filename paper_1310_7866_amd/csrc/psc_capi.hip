@@ -43,9 +43,19 @@ struct psc_ctx {
     struct Off {
         size_t runs, units, item_start, run_base, seg_base, seg_run, seg_sp, segs0, segs1, scan_tmp, err;
         size_t load_seg, load_blockseg, load_sums, load_keys, load_idx, load_keys_s, load_idx_s, cub;
+        size_t adj_runs, adj_segs;
+        size_t queue, part, unit_counts;
     } off{};
+    PushMode pm;                             // particle-kernel launch shape
+    int max_workers = 0;
     std::vector<size_t> off_jtile, off_rho;
     std::vector<std::vector<size_t>> off_cs0, off_cs1, off_perm, off_mc, off_cnt, off_pre, off_tot;
+    // adjoint scratch (PSC_RUN_ADJOINT)
+    bool adjoint = false;
+    size_t adj_lds = 0;
+    std::vector<AdjRun> adj;                 // host mirror of the adjoint table
+    std::vector<size_t> off_b1, off_lj, off_gt;
+    std::vector<std::vector<size_t>> off_soff, off_su, off_acs, off_atot;
 
     // state
     bool bound = false;
@@ -251,6 +261,10 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
     ctx->off.segs1 = take(sizeof(ScanSeg) * ctx->n_segs);
     ctx->off.scan_tmp = take(sizeof(int32_t) * 2 * ctx->n_scan_blocks);
     ctx->off.err = take(sizeof(uint32_t) * 64);
+    ctx->max_workers = 256 * 16;
+    ctx->off.queue = take(sizeof(int32_t) * 8);
+    ctx->off.part = take(sizeof(int32_t) * (ctx->max_workers + 1));
+    ctx->off.unit_counts = take(sizeof(int32_t) * ctx->units.size());
     const int64_t load_blocks = (ctx->max_ncell + kScanBlock - 1) / kScanBlock;
     ctx->off.load_seg = take(sizeof(ScanSeg));
     ctx->off.load_blockseg = take(sizeof(int32_t) * load_blocks);
@@ -275,6 +289,37 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
             ctx->off_cnt[r][s] = take(sizeof(uint16_t) * M * R.ncell);
             ctx->off_pre[r][s] = take(sizeof(uint16_t) * M * R.ncell);
             ctx->off_tot[r][s] = take(sizeof(int32_t) * R.ncell);
+        }
+    }
+    // adjoint scratch
+    for (int r = 0; r < n_runs; ++r) ctx->adjoint |= (runs[r].flags & PSC_RUN_ADJOINT) != 0;
+    if (ctx->adjoint) {
+        ctx->off.adj_runs = take(sizeof(AdjRun) * n_runs);
+        ctx->off.adj_segs = take(sizeof(ScanSeg) * n_runs * PSC_MAX_SPECIES);
+        ctx->adj.assign(n_runs, AdjRun{});
+        ctx->off_b1.resize(n_runs);
+        ctx->off_lj.resize(n_runs);
+        ctx->off_gt.resize(n_runs);
+        ctx->off_soff = ctx->off_su = ctx->off_acs = ctx->off_atot = ctx->off_cs0;
+        for (int r = 0; r < n_runs; ++r) {
+            const RunDev &R = ctx->runs[r];
+            const size_t lds = adjoint_lds_bytes(R.order, R.P);
+            if (lds > ctx->adj_lds) ctx->adj_lds = lds;
+            const int fy = R.P[1] + 1 + R.order, fz = R.P[2] + 1 + R.order;
+            ctx->off_b1[r] = take(sizeof(float) * 3 * R.ncell);
+            ctx->off_lj[r] = take(sizeof(float) * 3 * R.ncell);
+            ctx->off_gt[r] = take(sizeof(float) * (size_t)R.n_patches * 6 * fy * fz);
+            for (int s = 0; s < R.n_species; ++s) {
+                ctx->off_soff[r][s] = take(sizeof(float) * R.dim * R.sp[s].cap);
+                ctx->off_su[r][s] = take(sizeof(float) * 3 * R.sp[s].cap);
+                ctx->off_acs[r][s] = take(sizeof(int32_t) * (R.ncell + 1));
+                ctx->off_atot[r][s] = take(sizeof(int32_t) * R.ncell);
+            }
+        }
+        if (ctx->adj_lds > 65536) {
+            psc_status st = fail(ctx, PSC_ERR_LDS, "adjoint patch tile does not fit in 64 KiB of LDS");
+            delete ctx;
+            return st;
         }
     }
     ctx->off.cub = o;     // radix-sort temp storage goes last, sized in psc_workspace_size
@@ -378,6 +423,28 @@ psc_status psc_bind(psc_ctx *ctx, const psc_run_bufs *bufs, int n_runs, void *wo
             HIPCHECK(hipMemsetAsync(R.sp[sp].cs[1], 0, sizeof(int32_t) * (R.ncell + 1), s), "clear cs");
         }
     }
+    if (ctx->adjoint) {
+        std::vector<ScanSeg> asegs(ctx->n_runs * PSC_MAX_SPECIES, ScanSeg{nullptr, nullptr, 0, 0});
+        for (int r = 0; r < ctx->n_runs; ++r) {
+            const RunDev &R = ctx->runs[r];
+            AdjRun &A = ctx->adj[r];
+            A.B1 = ctx->at<float>(ctx->off_b1[r]);
+            A.LJ = ctx->at<float>(ctx->off_lj[r]);
+            A.gtile = ctx->at<float>(ctx->off_gt[r]);
+            const int fy = R.P[1] + 1 + R.order, fz = R.P[2] + 1 + R.order;
+            HIPCHECK(hipMemsetAsync(A.gtile, 0, sizeof(float) * (size_t)R.n_patches * 6 * fy * fz, s), "clear adj tiles");
+            for (int sp = 0; sp < R.n_species; ++sp) {
+                AdjSpecies &S = A.sp[sp];
+                S.soff = ctx->at<float>(ctx->off_soff[r][sp]);
+                S.su = ctx->at<float>(ctx->off_su[r][sp]);
+                S.cs = ctx->at<int32_t>(ctx->off_acs[r][sp]);
+                S.tot = ctx->at<int32_t>(ctx->off_atot[r][sp]);
+                asegs[r * PSC_MAX_SPECIES + sp] = ScanSeg{S.tot, S.cs, R.ncell, 0};
+            }
+        }
+        HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.adj_segs), asegs.data(), sizeof(ScanSeg) * asegs.size(),
+                                hipMemcpyHostToDevice, s), "upload adjoint segments");
+    }
     HIPCHECK(hipStreamSynchronize(s), "bind sync");
     ctx->bound = true;
     ctx->stepped = false;
@@ -388,9 +455,15 @@ psc_status psc_bind(psc_ctx *ctx, const psc_run_bufs *bufs, int n_runs, void *wo
 psc_status psc_load_particles(psc_ctx *ctx, int run, int species, int64_t n, const int32_t *gcell, const float *goff,
                               const float *gu, const int32_t *gid, void *stream) {
     if (!ctx || !ctx->bound) return PSC_ERR_STATE;
-    if (ctx->stepped) return fail(ctx, PSC_ERR_STATE, "particles must be loaded before the first push");
     if (run < 0 || run >= ctx->n_runs || species < 0 || species >= ctx->runs[run].n_species)
         return PSC_ERR_INVALID;
+    if (ctx->stepped || ctx->front || ctx->cs_sel || ctx->perm_pending) {
+        // restart: the particle state of every species lives in buffer set 0
+        // again, so every species has to be loaded before the next step
+        ctx->stepped = false;
+        ctx->front = ctx->cs_sel = ctx->perm_pending = ctx->mc_valid = 0;
+        for (auto &v : ctx->loaded) std::fill(v.begin(), v.end(), false);
+    }
     RunDev &R = ctx->runs[run];
     SpeciesDev &S = R.sp[species];
     if (n < 0 || n > S.cap) return fail(ctx, PSC_ERR_INVALID, "particle count exceeds capacity");
@@ -442,9 +515,12 @@ psc_status psc_push_particles(psc_ctx *ctx, void *stream) {
     psc_status st = require_loaded(ctx);
     if (st != PSC_OK) return st;
     Launch L = make_launch(ctx, (hipStream_t)stream);
-    HIPCHECK(launch_push(L, nullptr, 0, ctx->at<Unit>(ctx->off.units), (int)ctx->units.size(),
+    PushMode pm = ctx->pm;
+    pm.queue = ctx->at<int32_t>(ctx->off.queue);
+    pm.part = ctx->at<int32_t>(ctx->off.part);
+    HIPCHECK(launch_push(L, ctx->at<Unit>(ctx->off.units), (int)ctx->units.size(),
                          ctx->at<int32_t>(ctx->off.item_start), ctx->max_items, ctx->chunk, ctx->dim, ctx->order,
-                         ctx->front, ctx->cs_sel, ctx->perm_pending, ctx->lds, nullptr),
+                         ctx->front, ctx->cs_sel, ctx->perm_pending, ctx->lds, pm),
              "push particles");
     ctx->front = 1 - ctx->front;
     ctx->perm_pending = 0;
@@ -574,6 +650,166 @@ psc_status psc_diagnostics(psc_ctx *ctx, double *out_dev, double *gauss_dev, voi
     Launch L = make_launch(ctx, (hipStream_t)stream);
     HIPCHECK(launch_diag(L, out_dev, gauss_dev, ctx->total_cells, ctx->at<int64_t>(ctx->off.run_base), ctx->front),
              "diagnostics");
+    return PSC_OK;
+}
+
+psc_status psc_partition(const double *L, int n_patches, const double *C, int n_ranks, int32_t *N) {
+    if (!L || !C || !N || n_patches < 0 || n_ranks < 1) return PSC_ERR_INVALID;
+    // App. A: walk the patches along the curve, filling rank r up to its
+    // share T_hat * C_r of the total load; at the patch that crosses the
+    // target keep it on r or start r + 1 with it, whichever lands closer to
+    // the target (a rank keeps at least one patch); once only as many patches
+    // as ranks remain, each remaining rank gets one.  The last rank takes the
+    // rest.
+    double ltot = 0.0, ctot = 0.0;
+    for (int p = 0; p < n_patches; ++p) ltot += L[p];
+    for (int r = 0; r < n_ranks; ++r) {
+        if (!(C[r] > 0.0)) return PSC_ERR_INVALID;
+        ctot += C[r];
+        N[r] = 0;
+    }
+    const double that = ltot / ctot;
+    int r = 0, ncur = 0;
+    double lcur = 0.0;
+    for (int p = 0; p < n_patches; ++p) {
+        lcur += L[p];
+        ncur += 1;
+        if (r < n_ranks - 1) {
+            const double tcur = that * C[r];
+            if (lcur > tcur || n_ranks - r >= n_patches - p) {
+                const double above = lcur - tcur;
+                const double below = tcur - (lcur - L[p]);
+                if (above > below && ncur > 1) {
+                    N[r] = ncur - 1;   // patch p opens the next rank
+                    ncur = 1;
+                    lcur = L[p];
+                } else {
+                    N[r] = ncur;       // patch p closes this rank
+                    ncur = 0;
+                    lcur = 0.0;
+                }
+                ++r;
+            }
+        }
+        if (p == n_patches - 1) N[n_ranks - 1] += ncur;
+    }
+    return PSC_OK;
+}
+
+psc_status psc_balance(psc_ctx *ctx, double cell_cost, void *stream) {
+    psc_status st = require_loaded(ctx);
+    if (st != PSC_OK) return st;
+    const int workers = ctx->pm.workers;
+    if (workers < 1) return fail(ctx, PSC_ERR_STATE, "psc_balance needs a persistent launch shape");
+    hipStream_t s = (hipStream_t)stream;
+    Launch L = make_launch(ctx, s);
+    const int nu = (int)ctx->units.size();
+    HIPCHECK(launch_unit_counts(L, ctx->at<Unit>(ctx->off.units), nu, ctx->cs_sel, ctx->at<int32_t>(ctx->off.unit_counts)),
+             "unit counts");
+    std::vector<int32_t> cnt(nu);
+    HIPCHECK(hipMemcpyAsync(cnt.data(), ctx->at<int32_t>(ctx->off.unit_counts), sizeof(int32_t) * nu,
+                            hipMemcpyDeviceToHost, s), "read unit counts");
+    HIPCHECK(hipStreamSynchronize(s), "balance sync");
+    std::vector<double> load(nu), cap(workers, 1.0);
+    for (int u = 0; u < nu; ++u) {
+        const Unit &U = ctx->units[u];
+        const RunDev &R = ctx->runs[U.run];
+        int pc[3];
+        patch_coords(R, U.patch, pc);
+        const double cells = (double)patch_ext(R, 0, pc[0]) * patch_ext(R, 1, pc[1]) * patch_ext(R, 2, pc[2]);
+        load[u] = cnt[u] + cell_cost * cells;
+    }
+    std::vector<int32_t> N(workers);
+    st = psc_partition(load.data(), nu, cap.data(), workers, N.data());
+    if (st != PSC_OK) return st;
+    std::vector<int32_t> part(workers + 1, 0);
+    for (int w = 0; w < workers; ++w) part[w + 1] = part[w] + N[w];
+    HIPCHECK(hipMemcpyAsync(ctx->at<int32_t>(ctx->off.part), part.data(), sizeof(int32_t) * (workers + 1),
+                            hipMemcpyHostToDevice, s), "upload partition");
+    HIPCHECK(hipStreamSynchronize(s), "balance sync");
+    return PSC_OK;
+}
+
+psc_status psc_set_launch(psc_ctx *ctx, int mode, int chunk, int workers, void *stream) {
+    if (!ctx || !ctx->bound || mode < 0 || mode > 2 || chunk < 0 || workers < 0 || workers > ctx->max_workers)
+        return PSC_ERR_INVALID;
+    if (chunk > 0 && chunk != ctx->chunk) {
+        ctx->chunk = chunk;
+        int64_t items = (int64_t)ctx->units.size();
+        for (int r = 0; r < ctx->n_runs; ++r)
+            for (int s = 0; s < ctx->runs[r].n_species; ++s)
+                items += (ctx->runs[r].sp[s].cap + chunk - 1) / chunk;
+        ctx->max_items = items;
+    }
+    if (mode != 0 && workers == 0) {
+        int dev = 0, cus = 0;
+        HIPCHECK(hipGetDevice(&dev), "get device");
+        HIPCHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+        int per = (int)(160 * 1024 / (ctx->lds + 1024));
+        per = per < 1 ? 1 : (per > 8 ? 8 : per);
+        workers = cus * per;
+        if (workers > ctx->max_workers) workers = ctx->max_workers;
+    }
+    ctx->pm.mode = mode;
+    ctx->pm.workers = mode == 0 ? 0 : workers;
+    for (auto &kv : ctx->graphs) hipGraphExecDestroy(kv.second);
+    ctx->graphs.clear();
+    if (mode == 2) {
+        psc_status st = psc_balance(ctx, 1.0, stream);
+        if (st != PSC_OK) return st;
+    }
+    return PSC_OK;
+}
+
+psc_status psc_get_perm(psc_ctx *ctx, int run, int species, int32_t *perm, void *stream) {
+    if (!ctx || !ctx->bound || run < 0 || run >= ctx->n_runs || species < 0 || species >= ctx->runs[run].n_species ||
+        !perm)
+        return PSC_ERR_INVALID;
+    if (!ctx->perm_pending) return fail(ctx, PSC_ERR_STATE, "no permutation: psc_sort has not run since the last push");
+    const SpeciesDev &S = ctx->runs[run].sp[species];
+    HIPCHECK(hipMemcpyAsync(perm, S.perm, sizeof(int32_t) * S.n, hipMemcpyDeviceToDevice, (hipStream_t)stream),
+             "copy permutation");
+    return PSC_OK;
+}
+
+psc_status psc_adjoint_step(psc_ctx *ctx, const psc_adj_fwd *fwd, const psc_adj_state *adj, void *stream) {
+    if (!ctx || !ctx->bound || !fwd || !adj) return PSC_ERR_INVALID;
+    if (!ctx->adjoint) return fail(ctx, PSC_ERR_STATE, "context was created without PSC_RUN_ADJOINT");
+    if (ctx->dim != 2) return fail(ctx, PSC_ERR_UNSUPPORTED, "the adjoint step is implemented for 2-d runs");
+    hipStream_t s = (hipStream_t)stream;
+    for (int r = 0; r < ctx->n_runs; ++r) {
+        const RunDev &R = ctx->runs[r];
+        AdjRun &A = ctx->adj[r];
+        if (!fwd[r].E || !fwd[r].B || !adj[r].lE || !adj[r].lB) return PSC_ERR_INVALID;
+        A.E = fwd[r].E;
+        A.B = fwd[r].B;
+        A.lE = adj[r].lE;
+        A.lB = adj[r].lB;
+        for (int sp = 0; sp < R.n_species; ++sp) {
+            AdjSpecies &S = A.sp[sp];
+            S.n = R.sp[sp].n;
+            if (S.n > 0 && (!fwd[r].cell[sp] || !fwd[r].off[sp] || !fwd[r].u[sp] || !fwd[r].perm[sp] ||
+                            !adj[r].loff[sp] || !adj[r].lu[sp]))
+                return PSC_ERR_INVALID;
+            S.key = fwd[r].cell[sp];
+            S.off = fwd[r].off[sp];
+            S.u = fwd[r].u[sp];
+            S.perm = fwd[r].perm[sp];
+            S.loff = adj[r].loff[sp];
+            S.lu = adj[r].lu[sp];
+        }
+    }
+    HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.adj_runs), ctx->adj.data(), sizeof(AdjRun) * ctx->n_runs,
+                            hipMemcpyHostToDevice, s), "upload adjoint table");
+    Launch L = make_launch(ctx, s);
+    HIPCHECK(launch_adjoint(L, ctx->at<AdjRun>(ctx->off.adj_runs), ctx->adj.data(), ctx->at<Unit>(ctx->off.units),
+                            (int)ctx->units.size(), ctx->at<int32_t>(ctx->off.item_start), ctx->max_items, ctx->chunk,
+                            ctx->order, ctx->total_cells, ctx->at<int64_t>(ctx->off.run_base),
+                            ctx->at<ScanSeg>(ctx->off.adj_segs), ctx->at<int32_t>(ctx->off.load_blockseg),
+                            ctx->at<int32_t>(ctx->off.load_sums), ctx->adj_lds, s),
+             "adjoint step");
+    // the host table is reused by the next call: make sure the copy is done
+    HIPCHECK(hipStreamSynchronize(s), "adjoint sync");
     return PSC_OK;
 }
 

@@ -82,6 +82,28 @@ struct ScanSeg {
     int64_t block0;      // first scan block of the segment
 };
 
+// Adjoint step: forward state, adjoint state and scratch of one species/run.
+struct AdjSpecies {
+    const int32_t *key;   // forward particles at the start of the step, sorted by key
+    const float *off;     // D x n (stride n)
+    const float *u;       // 3 x n
+    const int32_t *perm;  // sort permutation of the step: next sorted slot -> slot
+    int64_t n;
+    float *loff, *lu;     // caller: in (next step's sorted order), out (this step's)
+    float *soff, *su;     // scratch: incoming adjoints moved to this step's slots
+    int32_t *cs;          // scratch: cell offsets of `key`, ncell + 1
+    int32_t *tot;         // scratch: counts
+};
+
+struct AdjRun {
+    const float *E, *B;   // forward fields at the start of the step: E^{n+1/2}, B^n
+    float *lE, *lB;       // in: adjoints of E', B2; out: adjoints of E, B
+    float *B1;            // scratch: B after the first half step
+    float *LJ;            // scratch: adjoint of J = -dt lE'
+    float *gtile;         // scratch: per-patch transposed-interpolation tiles (6 comps)
+    AdjSpecies sp[kMaxSpecies];
+};
+
 // ----------------------------------------------------------------------------
 // ghost widths
 // ----------------------------------------------------------------------------
@@ -175,10 +197,20 @@ struct Launch {
     uint32_t *err;            // device error word
 };
 
-hipError_t launch_push(const Launch &L, const int *run_ids, int n_ids, const Unit *units_dev,
-                       int n_units, int32_t *item_start, int64_t max_items, int chunk, int dim,
-                       int order, int front, int cs_sel, int use_perm, size_t lds_bytes,
-                       int32_t *scan_tmp);
+// how the particle kernel is launched: 0 one workgroup per work item,
+// 1 persistent workgroups with per-XCD queues, 2 persistent workgroups over a
+// load-balanced partition of the units
+struct PushMode {
+    int mode = 0;
+    int workers = 0;           // persistent workgroups (modes 1, 2)
+    int32_t *queue = nullptr;  // 8 counters (mode 1; reset every launch)
+    const int32_t *part = nullptr;  // workers + 1 unit boundaries (mode 2)
+};
+
+hipError_t launch_push(const Launch &L, const Unit *units_dev, int n_units, int32_t *item_start, int64_t max_items,
+                       int chunk, int dim, int order, int front, int cs_sel, int use_perm, size_t lds_bytes,
+                       const PushMode &pm);
+hipError_t launch_unit_counts(const Launch &L, const Unit *units, int n_units, int cs_sel, int32_t *out);
 hipError_t launch_fields(const Launch &L, int op, int64_t total_cells, const int64_t *run_cell_base_dev);
 hipError_t launch_fold(const Launch &L, int64_t total_cells, const int64_t *run_cell_base_dev);
 hipError_t launch_sort(const Launch &L, const int64_t *seg_cell_base_dev, const int32_t *seg_run_dev,
@@ -201,6 +233,11 @@ hipError_t launch_get(const RunDev &r, int species, int front, int perm_pending,
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_diag(const Launch &L, double *out, double *gauss, int64_t total_cells,
                        const int64_t *run_cell_base_dev, int front);
+size_t adjoint_lds_bytes(int order, const int P[3]);
+hipError_t launch_adjoint(const Launch &L, const AdjRun *adj_dev, const AdjRun *adj_host, const Unit *units,
+                          int n_units, int32_t *item_start, int64_t max_items, int chunk, int order,
+                          int64_t total_cells, const int64_t *run_base, const ScanSeg *seg_dev, int32_t *blockseg,
+                          int32_t *sums, size_t lds, hipStream_t s);
 hipError_t radix_sort_pairs(void *temp, size_t *temp_bytes, const int32_t *keys_in, int32_t *keys_out,
                             const int32_t *vals_in, int32_t *vals_out, int64_t n, int bits,
                             hipStream_t s);

@@ -10,122 +10,9 @@
 // through the sort permutation, writing them in sorted order into the other
 // buffer set, so the physical reorder of the sort costs no extra pass), and
 // adds the LDS tile into the patch's current tile in HBM.
-#include "psc_internal.h"
+#include "psc_device.h"
 
 namespace psc {
-
-// ---------------------------------------------------------------------------
-// B-spline weights (b1 or b2 evaluated at the nodes around the particle)
-// ---------------------------------------------------------------------------
-// Position given as in-cell offset o in [0, 1) of cell 0.  "node" weights are
-// for quantities located at integer positions, "half" weights for quantities
-// located at half-integer positions (stored at their lower index).  Returns
-// the first node (relative to the cell) and ORDER+1 weights.
-template <int ORDER>
-__device__ __forceinline__ int node_weights(float o, float w[ORDER + 1]) {
-    if constexpr (ORDER == 1) {
-        w[0] = 1.0f - o;
-        w[1] = o;
-        return 0;
-    } else {
-        const int up = o >= 0.5f;
-        const float d = o - (float)up;  // distance from the nearest node, [-1/2, 1/2)
-        const float a = 0.5f - d, b = 0.5f + d;
-        w[0] = 0.5f * a * a;
-        w[1] = 0.75f - d * d;
-        w[2] = 0.5f * b * b;
-        return up - 1;
-    }
-}
-
-template <int ORDER>
-__device__ __forceinline__ int half_weights(float o, float w[ORDER + 1]) {
-    if constexpr (ORDER == 1) {
-        const int up = o >= 0.5f;
-        const float d = up ? o - 0.5f : o + 0.5f;
-        w[0] = 1.0f - d;
-        w[1] = d;
-        return up - 1;
-    } else {
-        const float d = o - 0.5f;
-        const float a = 0.5f - d, b = 0.5f + d;
-        w[0] = 0.5f * a * a;
-        w[1] = 0.75f - d * d;
-        w[2] = 0.5f * b * b;
-        return -1;
-    }
-}
-
-// Start and end weights of one dimension on a common stencil of ORDER+2
-// nodes: the particle starts at offset o0 in cell 0 and ends at offset o1 in
-// cell s (|s| <= 1).  Both weight sets use node_weights so that the end
-// weights equal the start weights of the next step bit for bit.
-template <int ORDER>
-__device__ __forceinline__ int stencil(float o0, int s, float o1, float S0[ORDER + 2], float S1[ORDER + 2]) {
-    float w0[ORDER + 1], w1[ORDER + 1];
-    const int b0 = node_weights<ORDER>(o0, w0);
-    const int b1 = node_weights<ORDER>(o1, w1) + s;
-    const int base = b0 < b1 ? b0 : b1;
-    const bool k0 = b0 != base, k1 = b1 != base;
-#pragma unroll
-    for (int r = 0; r < ORDER + 2; ++r) {
-        const float lo0 = r <= ORDER ? w0[r] : 0.0f, hi0 = r >= 1 ? w0[r - 1] : 0.0f;
-        const float lo1 = r <= ORDER ? w1[r] : 0.0f, hi1 = r >= 1 ? w1[r - 1] : 0.0f;
-        S0[r] = k0 ? hi0 : lo0;
-        S1[r] = k1 ? hi1 : lo1;
-    }
-    return base;
-}
-
-// ---------------------------------------------------------------------------
-// interpolation from an LDS tile
-// ---------------------------------------------------------------------------
-template <int ORDER>
-__device__ __forceinline__ float gather2(const float *F, int pitch, int iy, int iz, const float *wy,
-                                         const float *wz) {
-    const float *p = F + iz * pitch + iy;
-    float s = 0.0f;
-#pragma unroll
-    for (int b = 0; b <= ORDER; ++b) {
-        float r = 0.0f;
-#pragma unroll
-        for (int a = 0; a <= ORDER; ++a) r = fmaf(wy[a], p[b * pitch + a], r);
-        s = fmaf(wz[b], r, s);
-    }
-    return s;
-}
-
-template <int ORDER>
-__device__ __forceinline__ float gather3(const float *F, int px, int pxy, int ix, int iy, int iz,
-                                         const float *wx, const float *wy, const float *wz) {
-    const float *p = F + iz * pxy + iy * px + ix;
-    float s = 0.0f;
-#pragma unroll
-    for (int c = 0; c <= ORDER; ++c) {
-        float t = 0.0f;
-#pragma unroll
-        for (int b = 0; b <= ORDER; ++b) {
-            float r = 0.0f;
-#pragma unroll
-            for (int a = 0; a <= ORDER; ++a) r = fmaf(wx[a], p[c * pxy + b * px + a], r);
-            t = fmaf(wy[b], r, t);
-        }
-        s = fmaf(wz[c], t, s);
-    }
-    return s;
-}
-
-__device__ __forceinline__ void lds_add(float *p, float v) { atomicAdd(p, v); }
-
-// fast quotient/remainder for small non-negative a
-__device__ __forceinline__ int divmod_small(int a, int b, float inv_b, int &rem) {
-    int q = (int)((float)a * inv_b);
-    int r = a - q * b;
-    if (r < 0) { --q; r += b; }
-    else if (r >= b) { ++q; r -= b; }
-    rem = r;
-    return q;
-}
 
 // ---------------------------------------------------------------------------
 // work items
@@ -134,8 +21,12 @@ __device__ __forceinline__ int divmod_small(int a, int b, float inv_b, int &rem)
 // exclusive prefix item_start[0..n_units].
 __global__ void __launch_bounds__(1024) k_build_items(const RunDev *__restrict__ runs, const Unit *__restrict__ units,
                                                       int n_units, int chunk, int cs_sel,
-                                                      int32_t *__restrict__ item_start) {
+                                                      int32_t *__restrict__ item_start,
+                                                      int32_t *__restrict__ queue) {
     __shared__ int32_t part[1024];
+    // reset the work queues of the persistent launch (written before the
+    // particle kernel starts: same stream)
+    if (queue && threadIdx.x < 8) queue[threadIdx.x] = 0;
     const int t = threadIdx.x;
     const int per = (n_units + 1023) / 1024;
     const int u0 = t * per, u1 = imin(u0 + per, n_units);
@@ -331,12 +222,24 @@ __device__ __forceinline__ bool stays(float o0, int s, float o1) {
 // ---------------------------------------------------------------------------
 // the particle kernel
 // ---------------------------------------------------------------------------
+// unit u with item_start[u] <= item < item_start[u+1]
+__device__ __forceinline__ int unit_of_item(const int32_t *__restrict__ item_start, int n_units, int item) {
+    int lo = 0, hi = n_units;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (item_start[mid] <= item) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// One work item: stage the patch's fields, push its chunk of particles,
+// add the chunk's current into the patch tile.  Ends with a barrier so the
+// caller may start the next item on the same LDS.
 template <int DIM, int ORDER>
-__global__ void __launch_bounds__(kBlock) k_push(const RunDev *__restrict__ runs, const Unit *__restrict__ units,
-                                                 const int32_t *__restrict__ item_start, int n_units,
-                                                 int chunk, int front, int cs_sel, int use_perm,
-                                                 uint32_t *__restrict__ err) {
-    extern __shared__ float lds[];
+__device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const Unit *__restrict__ units,
+                                          const int32_t *__restrict__ item_start, int lo, int item, int chunk,
+                                          int front, int cs_sel, int use_perm, uint32_t *__restrict__ err,
+                                          float *lds) {
     constexpr int FLO = 1, FHI = ORDER;   // field ghosts
     constexpr int JLO = ORDER, JHI = ORDER + 1;
     constexpr int FL = 2 * ORDER;         // frame nodes per dimension
@@ -344,18 +247,6 @@ __global__ void __launch_bounds__(kBlock) k_push(const RunDev *__restrict__ runs
     // the 3-d order-2 frame holds 144 values per particle: lane atomics instead
     constexpr bool kReduce = !(DIM == 3 && ORDER == 2);
 
-    // XCD-aware item order: workgroups are dispatched round-robin over the 8
-    // XCDs; give each XCD a contiguous range of items so that the chunks of a
-    // patch share one L2.
-    const int nb = gridDim.x;
-    const int item = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
-    const int total = item_start[n_units];
-    if (item >= total) return;
-    int lo = 0, hi = n_units;  // find u with item_start[u] <= item < item_start[u+1]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (item_start[mid] <= item) lo = mid; else hi = mid;
-    }
     const Unit U = units[lo];
     const RunDev &R = runs[U.run];
     const SpeciesDev &S = R.sp[U.species];
@@ -657,32 +548,127 @@ __global__ void __launch_bounds__(kBlock) k_push(const RunDev *__restrict__ runs
         const float v = jtile[t];
         if (v != 0.0f) atomicAdd(&gt[t], v);
     }
+    __syncthreads();
 }
+
+// launch mode 0: one workgroup per item.  Workgroups are dispatched
+// round-robin over the 8 XCDs; give each XCD a contiguous range of items so
+// that the chunks of a patch share one L2.
+template <int DIM, int ORDER>
+__global__ void __launch_bounds__(kBlock) k_push(const RunDev *__restrict__ runs, const Unit *__restrict__ units,
+                                                 const int32_t *__restrict__ item_start, int n_units,
+                                                 int chunk, int front, int cs_sel, int use_perm,
+                                                 uint32_t *__restrict__ err) {
+    extern __shared__ float lds[];
+    const int nb = gridDim.x;
+    const int item = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+    if (item >= item_start[n_units]) return;
+    push_item<DIM, ORDER>(runs, units, item_start, unit_of_item(item_start, n_units, item), item, chunk, front,
+                          cs_sel, use_perm, err, lds);
+}
+
+// launch mode 1: persistent workgroups pull items from 8 queues, one per
+// XCD (queue q owns the q-th eighth of the items, so an XCD works on
+// neighbouring patches), and steal from the other queues when theirs is
+// empty.  Every workgroup leaves once all queues are drained.
+template <int DIM, int ORDER>
+__global__ void __launch_bounds__(kBlock) k_push_queue(const RunDev *__restrict__ runs,
+                                                       const Unit *__restrict__ units,
+                                                       const int32_t *__restrict__ item_start, int n_units,
+                                                       int chunk, int front, int cs_sel, int use_perm,
+                                                       uint32_t *__restrict__ err, int32_t *__restrict__ queue) {
+    extern __shared__ float lds[];
+    __shared__ int s_item;
+    const int total = item_start[n_units];
+    const int xcd = blockIdx.x & 7;
+    for (int k = 0; k < 8; ++k) {
+        const int q = (xcd + k) & 7;
+        const int qb = (int)((int64_t)q * total / 8), qe = (int)((int64_t)(q + 1) * total / 8);
+        for (;;) {
+            if (threadIdx.x == 0) s_item = qb + atomicAdd(&queue[q], 1);
+            __syncthreads();
+            const int item = s_item;
+            __syncthreads();
+            if (item >= qe) break;
+            push_item<DIM, ORDER>(runs, units, item_start, unit_of_item(item_start, n_units, item), item, chunk,
+                                  front, cs_sel, use_perm, err, lds);
+        }
+    }
+}
+
+// launch mode 2: persistent workgroup w processes the contiguous units
+// [part[w], part[w+1]) chosen by the load-balancing partition.
+template <int DIM, int ORDER>
+__global__ void __launch_bounds__(kBlock) k_push_part(const RunDev *__restrict__ runs,
+                                                      const Unit *__restrict__ units,
+                                                      const int32_t *__restrict__ item_start, int n_units,
+                                                      int chunk, int front, int cs_sel, int use_perm,
+                                                      uint32_t *__restrict__ err, const int32_t *__restrict__ part) {
+    extern __shared__ float lds[];
+    const int u0 = part[blockIdx.x], u1 = min(part[blockIdx.x + 1], n_units);
+    for (int u = u0; u < u1; ++u)
+        for (int item = item_start[u]; item < item_start[u + 1]; ++item)
+            push_item<DIM, ORDER>(runs, units, item_start, u, item, chunk, front, cs_sel, use_perm, err, lds);
+}
+
 template <int DIM, int ORDER>
 static hipError_t launch_push_t(const Launch &L, const Unit *units, int n_units, int32_t *item_start,
                                 int64_t max_items, int chunk, int front, int cs_sel, int use_perm,
-                                size_t lds) {
+                                size_t lds, const PushMode &pm) {
     hipLaunchKernelGGL(k_build_items, dim3(1), dim3(1024), 0, L.stream, L.runs_dev, units, n_units, chunk,
-                       cs_sel, item_start);
-    int64_t grid = (max_items + 7) / 8 * 8;
-    if (grid < 8) grid = 8;
-    hipLaunchKernelGGL((k_push<DIM, ORDER>), dim3((unsigned)grid), dim3(kBlock), lds, L.stream, L.runs_dev,
-                       units, item_start, n_units, chunk, front, cs_sel, use_perm, L.err);
+                       cs_sel, item_start, pm.queue);
+    if (pm.mode == 1) {
+        hipLaunchKernelGGL((k_push_queue<DIM, ORDER>), dim3((unsigned)pm.workers), dim3(kBlock), lds, L.stream,
+                           L.runs_dev, units, item_start, n_units, chunk, front, cs_sel, use_perm, L.err, pm.queue);
+    } else if (pm.mode == 2) {
+        hipLaunchKernelGGL((k_push_part<DIM, ORDER>), dim3((unsigned)pm.workers), dim3(kBlock), lds, L.stream,
+                           L.runs_dev, units, item_start, n_units, chunk, front, cs_sel, use_perm, L.err, pm.part);
+    } else {
+        int64_t grid = (max_items + 7) / 8 * 8;
+        if (grid < 8) grid = 8;
+        hipLaunchKernelGGL((k_push<DIM, ORDER>), dim3((unsigned)grid), dim3(kBlock), lds, L.stream, L.runs_dev,
+                           units, item_start, n_units, chunk, front, cs_sel, use_perm, L.err);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_push(const Launch &L, const int *, int, const Unit *units_dev, int n_units,
-                       int32_t *item_start, int64_t max_items, int chunk, int dim, int order, int front,
-                       int cs_sel, int use_perm, size_t lds_bytes, int32_t *) {
+hipError_t launch_push(const Launch &L, const Unit *units_dev, int n_units, int32_t *item_start, int64_t max_items,
+                       int chunk, int dim, int order, int front, int cs_sel, int use_perm, size_t lds_bytes,
+                       const PushMode &pm) {
     if (dim == 2 && order == 1)
-        return launch_push_t<2, 1>(L, units_dev, n_units, item_start, max_items, chunk, front, cs_sel, use_perm, lds_bytes);
+        return launch_push_t<2, 1>(L, units_dev, n_units, item_start, max_items, chunk, front, cs_sel, use_perm,
+                                   lds_bytes, pm);
     if (dim == 2 && order == 2)
-        return launch_push_t<2, 2>(L, units_dev, n_units, item_start, max_items, chunk, front, cs_sel, use_perm, lds_bytes);
+        return launch_push_t<2, 2>(L, units_dev, n_units, item_start, max_items, chunk, front, cs_sel, use_perm,
+                                   lds_bytes, pm);
     if (dim == 3 && order == 1)
-        return launch_push_t<3, 1>(L, units_dev, n_units, item_start, max_items, chunk, front, cs_sel, use_perm, lds_bytes);
+        return launch_push_t<3, 1>(L, units_dev, n_units, item_start, max_items, chunk, front, cs_sel, use_perm,
+                                   lds_bytes, pm);
     if (dim == 3 && order == 2)
-        return launch_push_t<3, 2>(L, units_dev, n_units, item_start, max_items, chunk, front, cs_sel, use_perm, lds_bytes);
+        return launch_push_t<3, 2>(L, units_dev, n_units, item_start, max_items, chunk, front, cs_sel, use_perm,
+                                   lds_bytes, pm);
     return hipErrorInvalidValue;
+}
+
+// particles per unit (for the load-balancing partition)
+__global__ void k_unit_counts(const RunDev *__restrict__ runs, const Unit *__restrict__ units, int n_units,
+                              int cs_sel, int32_t *__restrict__ out) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n_units) return;
+    const Unit U = units[u];
+    const RunDev &R = runs[U.run];
+    int pc[3];
+    patch_coords(R, U.patch, pc);
+    const int64_t kb = patch_key_base(R, pc[0], pc[1], pc[2]);
+    const int64_t ke = kb + (int64_t)patch_ext(R, 0, pc[0]) * patch_ext(R, 1, pc[1]) * patch_ext(R, 2, pc[2]);
+    const int32_t *cs = R.sp[U.species].cs[cs_sel];
+    out[u] = cs[ke] - cs[kb];
+}
+
+hipError_t launch_unit_counts(const Launch &L, const Unit *units, int n_units, int cs_sel, int32_t *out) {
+    hipLaunchKernelGGL(k_unit_counts, dim3((unsigned)((n_units + 255) / 256)), dim3(256), 0, L.stream, L.runs_dev,
+                       units, n_units, cs_sel, out);
+    return hipGetLastError();
 }
 
 // LDS bytes the particle kernel of a run needs

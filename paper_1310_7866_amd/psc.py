@@ -28,7 +28,10 @@ STATUS = {0: "PSC_OK", 1: "PSC_ERR_INVALID", 2: "PSC_ERR_CFL", 3: "PSC_ERR_LDS",
 EXPORTS = ["psc_init_patches", "psc_workspace_size", "psc_bind", "psc_load_particles", "psc_push_fields",
            "psc_push_particles", "psc_deposit_current", "psc_sort", "psc_step", "psc_get_particles",
            "psc_keys_to_cells", "psc_particle_count", "psc_front", "psc_sort_view", "psc_diagnostics",
+           "psc_get_perm", "psc_adjoint_step", "psc_set_launch", "psc_balance", "psc_partition",
            "psc_check", "psc_status_string", "psc_last_error", "psc_destroy"]
+LAUNCH_GRID, LAUNCH_QUEUE, LAUNCH_PARTITION = 0, 1, 2
+RUN_ADJOINT = 1
 
 
 class PscError(RuntimeError):
@@ -41,7 +44,16 @@ class RunDesc(C.Structure):
     _fields_ = [("dim", C.c_int), ("gdims", C.c_int * 3), ("patch", C.c_int * 3),
                 ("dx", C.c_double * 3), ("dt", C.c_double), ("order", C.c_int),
                 ("n_species", C.c_int), ("q", C.c_double * 4), ("m", C.c_double * 4),
-                ("w", C.c_double * 4), ("capacity", C.c_int64 * 4)]
+                ("w", C.c_double * 4), ("capacity", C.c_int64 * 4), ("flags", C.c_int)]
+
+
+class AdjFwd(C.Structure):
+    _fields_ = [("E", C.c_void_p), ("B", C.c_void_p), ("cell", C.c_void_p * 4), ("off", C.c_void_p * 4),
+                ("u", C.c_void_p * 4), ("perm", C.c_void_p * 4)]
+
+
+class AdjState(C.Structure):
+    _fields_ = [("lE", C.c_void_p), ("lB", C.c_void_p), ("loff", C.c_void_p * 4), ("lu", C.c_void_p * 4)]
 
 
 class RunBufs(C.Structure):
@@ -77,6 +89,11 @@ def load_library(path: str = LIB_PATH):
     L.psc_front.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
     L.psc_sort_view.argtypes = [vp, i32, i32, C.POINTER(vp), C.POINTER(vp)]
     L.psc_diagnostics.argtypes = [vp, vp, vp, vp]
+    L.psc_get_perm.argtypes = [vp, i32, i32, vp, vp]
+    L.psc_adjoint_step.argtypes = [vp, C.POINTER(AdjFwd), C.POINTER(AdjState), vp]
+    L.psc_set_launch.argtypes = [vp, i32, i32, i32, vp]
+    L.psc_balance.argtypes = [vp, C.c_double, vp]
+    L.psc_partition.argtypes = [C.POINTER(C.c_double), i32, C.POINTER(C.c_double), i32, C.POINTER(C.c_int32)]
     L.psc_check.argtypes = [vp, vp, C.POINTER(C.c_uint32), i32]
     L.psc_status_string.argtypes = [i32]
     L.psc_status_string.restype = C.c_char_p
@@ -89,8 +106,23 @@ def load_library(path: str = LIB_PATH):
     return L
 
 
-def run_desc(case, capacity: Optional[Sequence[int]] = None) -> RunDesc:
+def partition(loads: Sequence[float], caps: Sequence[float]) -> np.ndarray:
+    """App. A greedy partition (host function of the library): patches per rank."""
+    L = load_library()
+    lo = np.ascontiguousarray(loads, dtype=np.float64)
+    ca = np.ascontiguousarray(caps, dtype=np.float64)
+    out = np.zeros(ca.size, np.int32)
+    st = L.psc_partition(lo.ctypes.data_as(C.POINTER(C.c_double)), lo.size,
+                         ca.ctypes.data_as(C.POINTER(C.c_double)), ca.size,
+                         out.ctypes.data_as(C.POINTER(C.c_int32)))
+    if st != 0:
+        raise PscError(st, "psc_partition")
+    return out
+
+
+def run_desc(case, capacity: Optional[Sequence[int]] = None, flags: int = 0) -> RunDesc:
     d = RunDesc()
+    d.flags = int(flags)
     d.dim = case.dim
     for k in range(3):
         d.gdims[k] = int(case.gdims[k])
@@ -112,7 +144,8 @@ class PscSim:
     kernel covers every run).  Buffers are torch tensors on ``device``.
     """
 
-    def __init__(self, cases, device: str = "cuda", with_ids: bool = True, chunk: int = 0):
+    def __init__(self, cases, device: str = "cuda", with_ids: bool = True, chunk: int = 0,
+                 adjoint: bool = False):
         import torch
         self.torch = torch
         if not torch.cuda.is_available():
@@ -121,7 +154,8 @@ class PscSim:
         self.cases = list(cases) if isinstance(cases, (list, tuple)) else [cases]
         self.device = torch.device(device)
         n_runs = len(self.cases)
-        descs = (RunDesc * n_runs)(*[run_desc(c) for c in self.cases])
+        flags = RUN_ADJOINT if adjoint else 0
+        descs = (RunDesc * n_runs)(*[run_desc(c, flags=flags) for c in self.cases])
         ctx = C.c_void_p()
         self._call(self.L.psc_init_patches(descs, n_runs, int(chunk), C.byref(ctx)), None)
         self.ctx = ctx
@@ -163,11 +197,17 @@ class PscSim:
                 off = torch.from_numpy(np.ascontiguousarray(sp.off, dtype=np.float32).reshape(-1)).to(self.device)
                 u = torch.from_numpy(np.ascontiguousarray(sp.u, dtype=np.float32).reshape(-1)).to(self.device)
                 gid = torch.arange(sp.n, dtype=i32, device=self.device)
-                torch.cuda.synchronize()
-                self._call(self.L.psc_load_particles(self.ctx, r, s, sp.n, cell.data_ptr(), off.data_ptr(),
-                                                     u.data_ptr(), gid.data_ptr(), self._stream()))
+                self.load(r, s, cell, off, u, gid)
                 del cell, off, u, gid
         self.check()
+
+    def load(self, r: int, s: int, cell, off, u, ids=None):
+        """Load particles given as device tensors in geometric form (cell index,
+        offsets (D*n), momenta (3*n), ids); sorts them by key on the device."""
+        self.torch.cuda.synchronize()
+        n = int(cell.numel())
+        self._call(self.L.psc_load_particles(self.ctx, r, s, n, cell.data_ptr(), off.data_ptr(), u.data_ptr(),
+                                             ids.data_ptr() if ids is not None else None, self._stream()))
 
     # -- plumbing ------------------------------------------------------------
     def _stream(self):
@@ -209,6 +249,12 @@ class PscSim:
 
     def step(self, nsteps: int = 1, use_graph: bool = False):
         self._call(self.L.psc_step(self.ctx, int(nsteps), int(use_graph), self._stream()))
+
+    def set_launch(self, mode: int, chunk: int = 0, workers: int = 0):
+        self._call(self.L.psc_set_launch(self.ctx, int(mode), int(chunk), int(workers), self._stream()))
+
+    def balance(self, cell_cost: float = 1.0):
+        self._call(self.L.psc_balance(self.ctx, float(cell_cost), self._stream()))
 
     def check(self, clear: bool = False) -> int:
         word = C.c_uint32()
@@ -285,6 +331,62 @@ class PscSim:
             hip.hipMemcpy(perm.ctypes.data, p, perm.nbytes, 2)
         hip.hipMemcpy(cst.ctypes.data, cs, cst.nbytes, 2)
         return perm, cst
+
+    def get_perm(self, r: int, s: int):
+        """Device copy of the last sort's permutation of (run, species)."""
+        n = self.cases[r].species[s].n
+        out = self.torch.empty(max(n, 1), dtype=self.torch.int32, device=self.device)
+        self._call(self.L.psc_get_perm(self.ctx, r, s, out.data_ptr(), self._stream()))
+        return out[:n]
+
+    def device_particles(self, r: int, s: int):
+        """Sorted-order particles of (run, species) as device tensors
+        (key int32 (n), off float32 (D*n), u float32 (3*n), id int32 (n))."""
+        torch = self.torch
+        c = self.cases[r]
+        n = c.species[s].n
+        t = dict(key=torch.empty(max(n, 1), dtype=torch.int32, device=self.device),
+                 off=torch.empty(c.dim * max(n, 1), dtype=torch.float32, device=self.device),
+                 u=torch.empty(3 * max(n, 1), dtype=torch.float32, device=self.device),
+                 id=torch.empty(max(n, 1), dtype=torch.int32, device=self.device))
+        self._call(self.L.psc_get_particles(self.ctx, r, s, t["key"].data_ptr(), t["off"].data_ptr(),
+                                            t["u"].data_ptr(), t["id"].data_ptr(), self._stream()))
+        return {k: v[:(c.dim * n if k == "off" else 3 * n if k == "u" else n)] for k, v in t.items()}
+
+    def snapshot(self):
+        """Device copy of the whole state (fields, sorted particles)."""
+        snap = []
+        for r, c in enumerate(self.cases):
+            E, B, _ = self.fields[r]
+            snap.append(dict(E=E.clone(), B=B.clone(),
+                             parts=[self.device_particles(r, s) for s in range(len(c.species))]))
+        return snap
+
+    def restore(self, snap):
+        """Put a snapshot back (restarts the context)."""
+        for r, c in enumerate(self.cases):
+            E, B, _ = self.fields[r]
+            E.copy_(snap[r]["E"])
+            B.copy_(snap[r]["B"])
+            for s, p in enumerate(snap[r]["parts"]):
+                cells = self.keys_to_cells(r, p["key"])
+                self.load(r, s, cells, p["off"], p["u"], p["id"])
+
+    def adjoint_step(self, fwd, lam):
+        """One reverse step.  fwd: per run dict(E, B, parts=[dict(key, off, u)],
+        perm=[tensor]); lam: per run dict(lE, lB, loff=[...], lu=[...]) updated
+        in place."""
+        n_runs = len(self.cases)
+        F = (AdjFwd * n_runs)()
+        S = (AdjState * n_runs)()
+        for r in range(n_runs):
+            F[r].E, F[r].B = fwd[r]["E"].data_ptr(), fwd[r]["B"].data_ptr()
+            S[r].lE, S[r].lB = lam[r]["lE"].data_ptr(), lam[r]["lB"].data_ptr()
+            for s, p in enumerate(fwd[r]["parts"]):
+                F[r].cell[s], F[r].off[s], F[r].u[s] = p["key"].data_ptr(), p["off"].data_ptr(), p["u"].data_ptr()
+                F[r].perm[s] = fwd[r]["perm"][s].data_ptr()
+                S[r].loff[s], S[r].lu[s] = lam[r]["loff"][s].data_ptr(), lam[r]["lu"][s].data_ptr()
+        self._call(self.L.psc_adjoint_step(self.ctx, F, S, self._stream()))
 
     def field_arrays(self, r: int):
         self.torch.cuda.synchronize()
