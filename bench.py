@@ -70,6 +70,86 @@ def cpu_baseline(case, thin: int):
                 seconds=dt)
 
 
+def adjoint_leg(every: int = 10, nsteps: int = 50):
+    """Gradient of the final field energy on the 256 x 256 double Harris sheet
+    (64 particles per cell at n = 1, 2nd order, 32 x 32 patches): forward with
+    checkpoints every `every` steps, then the hand-written reverse."""
+    from paper_1310_7866_amd import cases
+    from paper_1310_7866_amd.adjoint import EnergyGradient
+    c = cases.harris2d(ny=256, nz=256, ppc=64, order=2, patch=32, seed=5050, steps=nsteps)
+    eg = EnergyGradient(c, nsteps, every)
+    eg.forward()           # warm-up (kernel loading, graph-free)
+    eg.backward()
+    W = eg.forward()
+    eg.backward()
+    return dict(workload=f"harris2d 256x256, order 2, {c.n_particles} particles, {nsteps} steps, "
+                         f"checkpoints every {every}",
+                forward_ms=eg.forward_ms, adjoint_ms=eg.adjoint_ms,
+                adjoint_over_forward=eg.adjoint_ms / eg.forward_ms, W=float(W[0]))
+
+
+def batch_leg(steps: int = 10, n_runs: int = 64):
+    """64 independent two-stream runs (uneven grids, ragged patches) advanced
+    in one context (autotuned launch shape, HIP-graph replay) vs the same runs
+    advanced one after another in their own contexts."""
+    import numpy as np
+    import torch
+    from paper_1310_7866_amd import cases
+    from paper_1310_7866_amd.autotune import tune
+    from paper_1310_7866_amd.psc import PscSim
+    cs = cases.twostream_batch(n_runs=n_runs, seed=4064)
+    n = sum(c.n_particles for c in cs)
+    batch = PscSim(cs, with_ids=False)
+    mode, chunk, _, table = tune(batch, cache=None, steps=2)
+    batch.step(2, use_graph=True)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    batch.step(steps, use_graph=True)
+    b.record()
+    torch.cuda.synchronize()
+    batch.check()
+    batch_ms = a.elapsed_time(b)
+    del batch
+    torch.cuda.empty_cache()
+    # the same runs, one context each, one after another
+    plain_ms = 0.0
+    for c in cs:
+        sim = PscSim(c, with_ids=False)
+        sim.step(2)
+        torch.cuda.synchronize()
+        a.record()
+        sim.step(steps)
+        b.record()
+        torch.cuda.synchronize()
+        plain_ms += a.elapsed_time(b)
+        sim.close()
+        del sim
+    torch.cuda.empty_cache()
+    # agreement of batched vs alone after the same steps on a few runs
+    dev = 0.0
+    pick = [0, n_runs // 2, n_runs - 1]
+    sub = [cs[i] for i in pick]
+    bt = PscSim(sub)
+    bt.set_launch(mode, chunk)
+    bt.step(steps, use_graph=True)
+    for r, c in enumerate(sub):
+        al = PscSim(c)
+        al.step(steps)
+        pa, pb = al.particles(0, 0), bt.particles(r, 0)
+        oa, ob = np.argsort(pa["id"]), np.argsort(pb["id"])
+        dev = max(dev, float(np.abs(pa["u"][:, oa] - pb["u"][:, ob]).max()))
+        al.close()
+    bt.close()
+    return dict(workload=f"{n_runs} two-stream runs, {n} particles, "
+                         f"{sum(c.ncell for c in cs)} cells, order 1",
+                launch=dict(mode=mode, chunk=chunk), steps=steps,
+                batched_pushes_per_s=n * steps / (batch_ms / 1e3),
+                plain_pushes_per_s=n * steps / (plain_ms / 1e3),
+                batched_over_plain=plain_ms / batch_ms,
+                max_abs_du_vs_alone=dev)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +159,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--cpu-thin", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the adjoint and batch legs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -165,6 +246,11 @@ def main():
     }
     del sim
     torch.cuda.empty_cache()
+    if not args.no_extras:
+        print("[bench] adjoint leg", file=sys.stderr, flush=True)
+        out["adjoint"] = adjoint_leg()
+        print("[bench] batch leg", file=sys.stderr, flush=True)
+        out["batched"] = batch_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_thin)
     print(json.dumps(out))

@@ -1,0 +1,119 @@
+"""Launch-shape autotuner for the particle kernel.
+
+For a context it times candidate launch shapes (one workgroup per work item,
+persistent workgroups with per-XCD queues, persistent workgroups over the
+App. A partition) and chunk sizes on the live state during warm-up, keeps
+the fastest, and caches the choice in a JSON file keyed by the architecture
+and an occupancy class (dimension, order, patch size, particles per cell
+rounded to a power of two).  Optionally also picks the patch size by timing
+trial contexts.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from typing import Dict, Iterable, List, Optional, Sequence, Tuple
+
+MODES = (0, 1, 2)
+CHUNKS = (1024, 2048, 4096, 8192, 16384)
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "psc_autotune.json")
+
+
+def occupancy_class(cases) -> str:
+    cs = cases if isinstance(cases, (list, tuple)) else [cases]
+    c0 = cs[0]
+    ppc = sum(c.n_particles for c in cs) / max(1, sum(c.ncell for c in cs))
+    bucket = 2 ** int(round(math.log2(max(ppc, 1.0))))
+    return f"d{c0.dim}o{c0.order}p{c0.patch[1]}x{c0.patch[2]}x{c0.patch[0]}ppc{bucket}r{len(cs)}"
+
+
+def _arch() -> str:
+    import torch
+    try:
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        return "unknown"
+
+
+def _load(path: str) -> Dict:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save(path: str, data: Dict) -> None:
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def time_push(sim, steps: int = 3) -> float:
+    """Mean milliseconds of the particle kernel over `steps` full steps."""
+    import torch
+    from .psc import B_HALF, E_FULL
+    stream = torch.cuda.current_stream()
+    total = 0.0
+    for _ in range(steps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        sim.push_fields(B_HALF)
+        a.record(stream)
+        sim.push_particles()
+        b.record(stream)
+        sim.push_fields(B_HALF)
+        sim.deposit_current()
+        sim.push_fields(E_FULL)
+        sim.sort()
+        torch.cuda.synchronize()
+        total += a.elapsed_time(b)
+    return total / steps
+
+
+def tune(sim, cache: Optional[str] = DEFAULT_CACHE, steps: int = 2,
+         modes: Sequence[int] = MODES, chunks: Sequence[int] = CHUNKS, force: bool = False):
+    """Pick and apply the fastest (mode, chunk) for `sim`; returns
+    (mode, chunk, ms, table of every candidate's ms).  The state advances by
+    the timed steps (use during warm-up)."""
+    key = f"{_arch()}/{occupancy_class(sim.cases)}"
+    data = _load(cache) if cache else {}
+    if not force and key in data:
+        e = data[key]
+        sim.set_launch(e["mode"], e["chunk"])
+        return e["mode"], e["chunk"], e["ms"], e.get("table", {})
+    table = {}
+    best = None
+    for mode in modes:
+        for chunk in chunks:
+            sim.set_launch(mode, chunk)
+            sim.step(1)                     # settle (first launch of a shape)
+            ms = time_push(sim, steps)
+            table[f"{mode}/{chunk}"] = ms
+            if best is None or ms < best[2]:
+                best = (mode, chunk, ms)
+    sim.set_launch(best[0], best[1])
+    sim.check()
+    if cache:
+        data[key] = dict(mode=best[0], chunk=best[1], ms=best[2], table=table)
+        _save(cache, data)
+    return best[0], best[1], best[2], table
+
+
+def tune_patch(make_cases, patches: Iterable[int], steps: int = 2, **kw):
+    """Time trial contexts built by make_cases(patch) for each patch size;
+    returns (best patch, {patch: ms})."""
+    from .psc import PscSim
+    import torch
+    res = {}
+    for p in patches:
+        sim = PscSim(make_cases(p), with_ids=False, **kw)
+        sim.step(1)
+        res[p] = time_push(sim, steps)
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    best = min(res, key=res.get)
+    return best, res

@@ -273,7 +273,7 @@ def twostream2d(ny: int, nz: int, ppc: int, dx: float = 0.1, beam_v: float = 0.2
     E = np.zeros((3, ncell), np.float32)
     B = np.zeros((3, ncell), np.float32)
     return Case("twostream2d", 2, (1, ny, nz), dxs, half_cfl_dt(2, dxs), order,
-                (1, patch, patch), steps, seed, sp, E, B)
+                (1, min(patch, ny), min(patch, nz)), steps, seed, sp, E, B)
 
 
 def twostream_batch(n_runs: int = 64, seed: int = 4064, steps: int = 200,

@@ -20,7 +20,8 @@ def _batch(n=5):
 
 def _sim(cs, **kw):
     from paper_1310_7866_amd.psc import PscSim
-    print(f"[gpu] batch of {len(cs)}: {[c.gdims[1:] for c in cs]}", flush=True)
+    cl = cs if isinstance(cs, list) else [cs]
+    print(f"[gpu] batch of {len(cl)}: {[c.gdims[1:] for c in cl]}", flush=True)
     return PscSim(cs, **kw)
 
 

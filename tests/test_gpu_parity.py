@@ -32,7 +32,7 @@ def _sim(case, **kw):
 def _small_2d(order, seed=5, ny=20, nz=12, patch=8, ppc=6):
     c = cases.thermal2d(ny=ny, nz=nz, ppc=ppc, order=order, patch=patch, seed=seed)
     # separate the species so the charge density is non-trivial
-    c.species[1].off = np.random.default_rng(seed).random(c.species[1].off.shape).astype(np.float32)
+    c.species[1].off = np.random.default_rng(seed + 1000).random(c.species[1].off.shape).astype(np.float32)
     cases.random_fields(c, 0.05, 0.3, seed=seed + 1)
     return c
 

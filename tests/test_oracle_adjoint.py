@@ -23,7 +23,7 @@ torch = pytest.importorskip("torch")
 def _case(dim, order, seed):
     if dim == 2:
         c = cases.thermal2d(ny=10, nz=9, ppc=3, order=order, patch=5, seed=seed)
-        c.species[1].off = np.random.default_rng(seed).random(c.species[1].off.shape).astype(np.float32)
+        c.species[1].off = np.random.default_rng(seed + 1000).random(c.species[1].off.shape).astype(np.float32)
     else:
         c = cases.weibel3d(ppc=2, order=order, patch=3, seed=seed, nxyz=(5, 4, 6))
     cases.random_fields(c, 0.05, 0.3, seed=seed + 1)
