@@ -100,7 +100,7 @@ def batch_leg(steps: int = 10, n_runs: int = 64):
     cs = cases.twostream_batch(n_runs=n_runs, seed=4064)
     n = sum(c.n_particles for c in cs)
     batch = PscSim(cs, with_ids=False)
-    mode, chunk, _, table = tune(batch, cache=None, steps=2)
+    mode, chunk, threads, _, table = tune(batch, cache=None, steps=2)
     batch.step(2, use_graph=True)
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -131,7 +131,7 @@ def batch_leg(steps: int = 10, n_runs: int = 64):
     pick = [0, n_runs // 2, n_runs - 1]
     sub = [cs[i] for i in pick]
     bt = PscSim(sub)
-    bt.set_launch(mode, chunk)
+    bt.set_launch(mode, chunk, 0, threads)
     bt.step(steps, use_graph=True)
     for r, c in enumerate(sub):
         al = PscSim(c)
@@ -143,7 +143,7 @@ def batch_leg(steps: int = 10, n_runs: int = 64):
     bt.close()
     return dict(workload=f"{n_runs} two-stream runs, {n} particles, "
                          f"{sum(c.ncell for c in cs)} cells, order 1",
-                launch=dict(mode=mode, chunk=chunk), steps=steps,
+                launch=dict(mode=mode, chunk=chunk, threads=threads), steps=steps,
                 batched_pushes_per_s=n * steps / (batch_ms / 1e3),
                 plain_pushes_per_s=n * steps / (plain_ms / 1e3),
                 batched_over_plain=plain_ms / batch_ms,
@@ -160,6 +160,7 @@ def main():
     ap.add_argument("--cpu-thin", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the adjoint and batch legs")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -175,6 +176,12 @@ def main():
     sim = PscSim(case, with_ids=False, chunk=args.chunk)
     stream = torch.cuda.current_stream()
 
+    launch = None
+    if not args.no_tune:
+        from paper_1310_7866_amd.autotune import tune
+        mode, chunk, threads, ms, _ = tune(sim, cache=None, steps=2)
+        launch = dict(mode=mode, chunk=chunk, threads=threads)
+        print(f"[bench] autotuned launch {launch} ({ms:.3f} ms)", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         sim.step(1)
     sim.check()
@@ -237,7 +244,7 @@ def main():
                                f"{'' if case.dim == 2 else 'x' + str(case.gdims[0])} cells, "
                                f"order {case.order}, patches {case.patch[1]}x{case.patch[2]}",
                    "particles": n, "cells": case.ncell, "order": case.order,
-                   "patch": list(case.patch), "parallelism": "single GPU"},
+                   "patch": list(case.patch), "parallelism": "single GPU", "launch": launch},
         "push_kernel_ms": push_ms,
         "push_kernel_pushes_per_s": n / (push_ms / 1e3),
         "sort_ms": sort_ms,

@@ -182,11 +182,13 @@ psc_status psc_step(psc_ctx *ctx, int nsteps, int use_graph, void *stream);
  *                            by psc_balance (called here once).
  * chunk: particles per work item (0 keeps the current value).
  * workers: persistent workgroups (0 = compute units x workgroups that fit
- * in one unit's LDS).  Drops recorded step graphs.  May synchronize. */
+ * in one unit's LDS).  threads: workgroup size, 256 or 512 (0 keeps; the
+ * LDS tiles of a work item are shared by all its waves).  Drops recorded
+ * step graphs.  May synchronize. */
 #define PSC_LAUNCH_GRID 0
 #define PSC_LAUNCH_QUEUE 1
 #define PSC_LAUNCH_PARTITION 2
-psc_status psc_set_launch(psc_ctx *ctx, int mode, int chunk, int workers, void *stream);
+psc_status psc_set_launch(psc_ctx *ctx, int mode, int chunk, int workers, int threads, void *stream);
 
 /* Recompute the PSC_LAUNCH_PARTITION split from the current particle
  * counts (App. A, "Load balancing algorithm", with every workgroup of equal

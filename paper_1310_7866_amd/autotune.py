@@ -73,33 +73,38 @@ def time_push(sim, steps: int = 3) -> float:
     return total / steps
 
 
+THREADS = (256, 512)
+
+
 def tune(sim, cache: Optional[str] = DEFAULT_CACHE, steps: int = 2,
-         modes: Sequence[int] = MODES, chunks: Sequence[int] = CHUNKS, force: bool = False):
-    """Pick and apply the fastest (mode, chunk) for `sim`; returns
-    (mode, chunk, ms, table of every candidate's ms).  The state advances by
-    the timed steps (use during warm-up)."""
+         modes: Sequence[int] = MODES, chunks: Sequence[int] = CHUNKS,
+         threads: Sequence[int] = THREADS, force: bool = False):
+    """Pick and apply the fastest (mode, chunk, threads) for `sim`; returns
+    (mode, chunk, threads, ms, table of every candidate's ms).  The state
+    advances by the timed steps (use during warm-up)."""
     key = f"{_arch()}/{occupancy_class(sim.cases)}"
     data = _load(cache) if cache else {}
     if not force and key in data:
         e = data[key]
-        sim.set_launch(e["mode"], e["chunk"])
-        return e["mode"], e["chunk"], e["ms"], e.get("table", {})
+        sim.set_launch(e["mode"], e["chunk"], 0, e["threads"])
+        return e["mode"], e["chunk"], e["threads"], e["ms"], e.get("table", {})
     table = {}
     best = None
-    for mode in modes:
-        for chunk in chunks:
-            sim.set_launch(mode, chunk)
-            sim.step(1)                     # settle (first launch of a shape)
-            ms = time_push(sim, steps)
-            table[f"{mode}/{chunk}"] = ms
-            if best is None or ms < best[2]:
-                best = (mode, chunk, ms)
-    sim.set_launch(best[0], best[1])
+    for nt in threads:
+        for mode in modes:
+            for chunk in chunks:
+                sim.set_launch(mode, chunk, 0, nt)
+                sim.step(1)                     # settle (first launch of a shape)
+                ms = time_push(sim, steps)
+                table[f"{mode}/{chunk}/{nt}"] = ms
+                if best is None or ms < best[3]:
+                    best = (mode, chunk, nt, ms)
+    sim.set_launch(best[0], best[1], 0, best[2])
     sim.check()
     if cache:
-        data[key] = dict(mode=best[0], chunk=best[1], ms=best[2], table=table)
+        data[key] = dict(mode=best[0], chunk=best[1], threads=best[2], ms=best[3], table=table)
         _save(cache, data)
-    return best[0], best[1], best[2], table
+    return best[0], best[1], best[2], best[3], table
 
 
 def tune_patch(make_cases, patches: Iterable[int], steps: int = 2, **kw):

@@ -730,9 +730,11 @@ psc_status psc_balance(psc_ctx *ctx, double cell_cost, void *stream) {
     return PSC_OK;
 }
 
-psc_status psc_set_launch(psc_ctx *ctx, int mode, int chunk, int workers, void *stream) {
-    if (!ctx || !ctx->bound || mode < 0 || mode > 2 || chunk < 0 || workers < 0 || workers > ctx->max_workers)
+psc_status psc_set_launch(psc_ctx *ctx, int mode, int chunk, int workers, int threads, void *stream) {
+    if (!ctx || !ctx->bound || mode < 0 || mode > 2 || chunk < 0 || workers < 0 || workers > ctx->max_workers ||
+        (threads != 0 && threads != 256 && threads != 512))
         return PSC_ERR_INVALID;
+    if (threads) ctx->pm.threads = threads;
     if (chunk > 0 && chunk != ctx->chunk) {
         ctx->chunk = chunk;
         int64_t items = (int64_t)ctx->units.size();
@@ -746,7 +748,8 @@ psc_status psc_set_launch(psc_ctx *ctx, int mode, int chunk, int workers, void *
         HIPCHECK(hipGetDevice(&dev), "get device");
         HIPCHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
         int per = (int)(160 * 1024 / (ctx->lds + 1024));
-        per = per < 1 ? 1 : (per > 8 ? 8 : per);
+        const int wave_cap = 32 / (ctx->pm.threads / 64);   // 32 waves per CU
+        per = per < 1 ? 1 : (per > wave_cap ? wave_cap : per);
         workers = cus * per;
         if (workers > ctx->max_workers) workers = ctx->max_workers;
     }

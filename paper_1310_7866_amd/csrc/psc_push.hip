@@ -235,7 +235,7 @@ __device__ __forceinline__ int unit_of_item(const int32_t *__restrict__ item_sta
 // One work item: stage the patch's fields, push its chunk of particles,
 // add the chunk's current into the patch tile.  Ends with a barrier so the
 // caller may start the next item on the same LDS.
-template <int DIM, int ORDER>
+template <int DIM, int ORDER, int NT>
 __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const Unit *__restrict__ units,
                                           const int32_t *__restrict__ item_start, int lo, int item, int chunk,
                                           int front, int cs_sel, int use_perm, uint32_t *__restrict__ err,
@@ -277,7 +277,7 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
     {
         const float inv_fx = 1.0f / fx, inv_fy = 1.0f / fy;
         const int64_t nc = R.ncell;
-        for (int t = threadIdx.x; t < fcells; t += kBlock) {
+        for (int t = threadIdx.x; t < fcells; t += NT) {
             int tx = 0, ty, tz;
             if constexpr (DIM == 3) {
                 const int q = divmod_small(t, fx, inv_fx, tx);
@@ -295,7 +295,7 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
                 ftile[(3 + c) * fcells + t] = R.B[c * nc + g];
             }
         }
-        for (int t = threadIdx.x; t < 3 * jcells; t += kBlock) jtile[t] = 0.0f;
+        for (int t = threadIdx.x; t < 3 * jcells; t += NT) jtile[t] = 0.0f;
     }
     __syncthreads();
 
@@ -324,7 +324,7 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
 
     // every lane runs the same number of iterations (the wave reduction needs
     // all 64 lanes); lanes past the end carry zero current and write nothing
-    for (int32_t i0 = beg; i0 < end; i0 += kBlock) {
+    for (int32_t i0 = beg; i0 < end; i0 += NT) {
         const int32_t i = i0 + threadIdx.x;
         const bool valid = i < end;
         // lanes past the end stand in with the chunk's first particle (taken
@@ -544,7 +544,7 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
 
     // add the LDS current tile into the patch's tile in HBM
     float *gt = R.jtile + (int64_t)U.patch * 3 * jcells;
-    for (int t = threadIdx.x; t < 3 * jcells; t += kBlock) {
+    for (int t = threadIdx.x; t < 3 * jcells; t += NT) {
         const float v = jtile[t];
         if (v != 0.0f) atomicAdd(&gt[t], v);
     }
@@ -554,8 +554,8 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
 // launch mode 0: one workgroup per item.  Workgroups are dispatched
 // round-robin over the 8 XCDs; give each XCD a contiguous range of items so
 // that the chunks of a patch share one L2.
-template <int DIM, int ORDER>
-__global__ void __launch_bounds__(kBlock) k_push(const RunDev *__restrict__ runs, const Unit *__restrict__ units,
+template <int DIM, int ORDER, int NT>
+__global__ void __launch_bounds__(NT) k_push(const RunDev *__restrict__ runs, const Unit *__restrict__ units,
                                                  const int32_t *__restrict__ item_start, int n_units,
                                                  int chunk, int front, int cs_sel, int use_perm,
                                                  uint32_t *__restrict__ err) {
@@ -563,7 +563,7 @@ __global__ void __launch_bounds__(kBlock) k_push(const RunDev *__restrict__ runs
     const int nb = gridDim.x;
     const int item = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
     if (item >= item_start[n_units]) return;
-    push_item<DIM, ORDER>(runs, units, item_start, unit_of_item(item_start, n_units, item), item, chunk, front,
+    push_item<DIM, ORDER, NT>(runs, units, item_start, unit_of_item(item_start, n_units, item), item, chunk, front,
                           cs_sel, use_perm, err, lds);
 }
 
@@ -571,8 +571,8 @@ __global__ void __launch_bounds__(kBlock) k_push(const RunDev *__restrict__ runs
 // XCD (queue q owns the q-th eighth of the items, so an XCD works on
 // neighbouring patches), and steal from the other queues when theirs is
 // empty.  Every workgroup leaves once all queues are drained.
-template <int DIM, int ORDER>
-__global__ void __launch_bounds__(kBlock) k_push_queue(const RunDev *__restrict__ runs,
+template <int DIM, int ORDER, int NT>
+__global__ void __launch_bounds__(NT) k_push_queue(const RunDev *__restrict__ runs,
                                                        const Unit *__restrict__ units,
                                                        const int32_t *__restrict__ item_start, int n_units,
                                                        int chunk, int front, int cs_sel, int use_perm,
@@ -590,7 +590,7 @@ __global__ void __launch_bounds__(kBlock) k_push_queue(const RunDev *__restrict_
             const int item = s_item;
             __syncthreads();
             if (item >= qe) break;
-            push_item<DIM, ORDER>(runs, units, item_start, unit_of_item(item_start, n_units, item), item, chunk,
+            push_item<DIM, ORDER, NT>(runs, units, item_start, unit_of_item(item_start, n_units, item), item, chunk,
                                   front, cs_sel, use_perm, err, lds);
         }
     }
@@ -598,8 +598,8 @@ __global__ void __launch_bounds__(kBlock) k_push_queue(const RunDev *__restrict_
 
 // launch mode 2: persistent workgroup w processes the contiguous units
 // [part[w], part[w+1]) chosen by the load-balancing partition.
-template <int DIM, int ORDER>
-__global__ void __launch_bounds__(kBlock) k_push_part(const RunDev *__restrict__ runs,
+template <int DIM, int ORDER, int NT>
+__global__ void __launch_bounds__(NT) k_push_part(const RunDev *__restrict__ runs,
                                                       const Unit *__restrict__ units,
                                                       const int32_t *__restrict__ item_start, int n_units,
                                                       int chunk, int front, int cs_sel, int use_perm,
@@ -608,45 +608,56 @@ __global__ void __launch_bounds__(kBlock) k_push_part(const RunDev *__restrict__
     const int u0 = part[blockIdx.x], u1 = min(part[blockIdx.x + 1], n_units);
     for (int u = u0; u < u1; ++u)
         for (int item = item_start[u]; item < item_start[u + 1]; ++item)
-            push_item<DIM, ORDER>(runs, units, item_start, u, item, chunk, front, cs_sel, use_perm, err, lds);
+            push_item<DIM, ORDER, NT>(runs, units, item_start, u, item, chunk, front, cs_sel, use_perm, err, lds);
 }
 
-template <int DIM, int ORDER>
+template <int DIM, int ORDER, int NT>
 static hipError_t launch_push_t(const Launch &L, const Unit *units, int n_units, int32_t *item_start,
                                 int64_t max_items, int chunk, int front, int cs_sel, int use_perm,
                                 size_t lds, const PushMode &pm) {
     hipLaunchKernelGGL(k_build_items, dim3(1), dim3(1024), 0, L.stream, L.runs_dev, units, n_units, chunk,
                        cs_sel, item_start, pm.queue);
     if (pm.mode == 1) {
-        hipLaunchKernelGGL((k_push_queue<DIM, ORDER>), dim3((unsigned)pm.workers), dim3(kBlock), lds, L.stream,
+        hipLaunchKernelGGL((k_push_queue<DIM, ORDER, NT>), dim3((unsigned)pm.workers), dim3(NT), lds, L.stream,
                            L.runs_dev, units, item_start, n_units, chunk, front, cs_sel, use_perm, L.err, pm.queue);
     } else if (pm.mode == 2) {
-        hipLaunchKernelGGL((k_push_part<DIM, ORDER>), dim3((unsigned)pm.workers), dim3(kBlock), lds, L.stream,
+        hipLaunchKernelGGL((k_push_part<DIM, ORDER, NT>), dim3((unsigned)pm.workers), dim3(NT), lds, L.stream,
                            L.runs_dev, units, item_start, n_units, chunk, front, cs_sel, use_perm, L.err, pm.part);
     } else {
         int64_t grid = (max_items + 7) / 8 * 8;
         if (grid < 8) grid = 8;
-        hipLaunchKernelGGL((k_push<DIM, ORDER>), dim3((unsigned)grid), dim3(kBlock), lds, L.stream, L.runs_dev,
+        hipLaunchKernelGGL((k_push<DIM, ORDER, NT>), dim3((unsigned)grid), dim3(NT), lds, L.stream, L.runs_dev,
                            units, item_start, n_units, chunk, front, cs_sel, use_perm, L.err);
     }
     return hipGetLastError();
+}
+
+template <int DIM, int ORDER>
+static hipError_t launch_push_nt(const Launch &L, const Unit *units, int n_units, int32_t *item_start,
+                                 int64_t max_items, int chunk, int front, int cs_sel, int use_perm, size_t lds,
+                                 const PushMode &pm) {
+    if (pm.threads == 512)
+        return launch_push_t<DIM, ORDER, 512>(L, units, n_units, item_start, max_items, chunk, front, cs_sel,
+                                              use_perm, lds, pm);
+    return launch_push_t<DIM, ORDER, 256>(L, units, n_units, item_start, max_items, chunk, front, cs_sel, use_perm,
+                                          lds, pm);
 }
 
 hipError_t launch_push(const Launch &L, const Unit *units_dev, int n_units, int32_t *item_start, int64_t max_items,
                        int chunk, int dim, int order, int front, int cs_sel, int use_perm, size_t lds_bytes,
                        const PushMode &pm) {
     if (dim == 2 && order == 1)
-        return launch_push_t<2, 1>(L, units_dev, n_units, item_start, max_items, chunk, front, cs_sel, use_perm,
-                                   lds_bytes, pm);
+        return launch_push_nt<2, 1>(L, units_dev, n_units, item_start, max_items, chunk, front, cs_sel, use_perm,
+                                    lds_bytes, pm);
     if (dim == 2 && order == 2)
-        return launch_push_t<2, 2>(L, units_dev, n_units, item_start, max_items, chunk, front, cs_sel, use_perm,
-                                   lds_bytes, pm);
+        return launch_push_nt<2, 2>(L, units_dev, n_units, item_start, max_items, chunk, front, cs_sel, use_perm,
+                                    lds_bytes, pm);
     if (dim == 3 && order == 1)
-        return launch_push_t<3, 1>(L, units_dev, n_units, item_start, max_items, chunk, front, cs_sel, use_perm,
-                                   lds_bytes, pm);
+        return launch_push_nt<3, 1>(L, units_dev, n_units, item_start, max_items, chunk, front, cs_sel, use_perm,
+                                    lds_bytes, pm);
     if (dim == 3 && order == 2)
-        return launch_push_t<3, 2>(L, units_dev, n_units, item_start, max_items, chunk, front, cs_sel, use_perm,
-                                   lds_bytes, pm);
+        return launch_push_nt<3, 2>(L, units_dev, n_units, item_start, max_items, chunk, front, cs_sel, use_perm,
+                                    lds_bytes, pm);
     return hipErrorInvalidValue;
 }
 

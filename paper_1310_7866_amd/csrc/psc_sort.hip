@@ -43,28 +43,31 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_count(const RunDev *__restr
                                                            const int32_t *__restrict__ seg_sp, int n_segs,
                                                            int64_t total, int cs_sel, uint32_t *err) {
     constexpr int M = DIM == 3 ? 27 : 9;
-    __shared__ int32_t cnt[M * kSortBlock];
     const int64_t c = (int64_t)blockIdx.x * kSortBlock + threadIdx.x;
     if (c >= total) return;
     const int sg = find_seg(seg_base, n_segs, c);
     const RunDev &R = runs[seg_run[sg]];
     const SpeciesDev &S = R.sp[seg_sp[sg]];
     const int64_t o = c - seg_base[sg];
-    const int t = threadIdx.x;
+    // counters live in registers: each particle's code is matched against
+    // all M codes by unrolled compares (no dependent LDS traffic)
+    int32_t cnt[M];
 #pragma unroll
-    for (int m = 0; m < M; ++m) cnt[m * kSortBlock + t] = 0;
+    for (int m = 0; m < M; ++m) cnt[m] = 0;
     const int32_t *cs = S.cs[cs_sel];
     const int32_t b = cs[o], e = cs[o + 1];
+    const uint8_t *__restrict__ mc = S.mc;
     uint32_t flags = 0;
     for (int32_t i = b; i < e; ++i) {
-        int m = S.mc[i];
+        int m = mc[i];
         if (m >= M) { flags |= PSC_DEV_MOVE; m = M / 2; }
-        cnt[m * kSortBlock + t] += 1;
+#pragma unroll
+        for (int q = 0; q < M; ++q) cnt[q] += q == m;
     }
     const int64_t nc = R.ncell;
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-        int32_t v = cnt[m * kSortBlock + t];
+        int32_t v = cnt[m];
         if (v > 65535) { flags |= PSC_DEV_OVERFULL; v = 65535; }
         S.cnt[m * nc + o] = (uint16_t)v;
     }
@@ -119,7 +122,6 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_scatter(const RunDev *__res
                                                              const int32_t *__restrict__ seg_sp, int n_segs,
                                                              int64_t total, int cs_sel, uint32_t *err) {
     constexpr int M = DIM == 3 ? 27 : 9;
-    __shared__ int32_t pos[M * kSortBlock];
     const int64_t c = (int64_t)blockIdx.x * kSortBlock + threadIdx.x;
     if (c >= total) return;
     const int sg = find_seg(seg_base, n_segs, c);
@@ -127,28 +129,37 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_scatter(const RunDev *__res
     const SpeciesDev &S = R.sp[seg_sp[sg]];
     const int64_t o = c - seg_base[sg];
     const int64_t nc = R.ncell;
-    const int t = threadIdx.x;
     const int32_t *cs_old = S.cs[cs_sel];
     const int32_t *cs_new = S.cs[1 - cs_sel];
     const int32_t b = cs_old[o], e = cs_old[o + 1];
     if (b == e) return;
     int g[3];
     decode_key(R, o, g);
+    // next output position per move code, in registers
+    int32_t pos[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         int d[3];
         move_delta(DIM, m, d);
         const int dx = DIM == 3 ? wrap(g[0] + d[0], R.n[0]) : 0;
         const int64_t dst = encode_key(R, dx, wrap(g[1] + d[1], R.n[1]), wrap(g[2] + d[2], R.n[2]));
-        pos[m * kSortBlock + t] = cs_new[dst] + S.pre[m * nc + o];
+        pos[m] = cs_new[dst] + S.pre[m * nc + o];
     }
+    const uint8_t *__restrict__ mc = S.mc;
+    int32_t *__restrict__ perm = S.perm;
+    const int32_t n = (int32_t)S.n;
     bool bad = false;
     for (int32_t i = b; i < e; ++i) {
-        int m = S.mc[i];
+        int m = mc[i];
         if (m >= M) m = M / 2;
-        const int32_t p = pos[m * kSortBlock + t];
-        pos[m * kSortBlock + t] = p + 1;
-        if (p >= 0 && p < S.n) S.perm[p] = i;   // out of range only after a counter overflow
+        int32_t p = 0;
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+            const bool hit = q == m;
+            p = hit ? pos[q] : p;
+            pos[q] += hit;
+        }
+        if (p >= 0 && p < n) perm[p] = i;   // out of range only after a counter overflow
         else bad = true;
     }
     if (bad) atomicOr(err, PSC_DEV_OVERFULL);
