@@ -27,8 +27,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# launch shapes chosen by the autotuner on MI355X, per occupancy class
+TUNED = os.path.join(ROOT, "paper_1310_7866_amd", "tuned_gfx950.json")
 # non-packed FP32 vector issue: 256 CUs x 64 lanes x 2.4 GHz (FMA = 2 flop)
 VALU_PEAK_TFLOPS = 256 * 64 * 2.4e9 * 2 / 1e12
+# wave64 VALU instructions per second: each CU issues one per clock over its
+# four 16-lane SIMDs (one wave instruction takes four cycles on a SIMD)
+VALU_ISSUE_PEAK = 256 * 2.4e9
 
 
 def algorithmic_bytes(case) -> float:
@@ -67,7 +72,44 @@ def cpu_baseline(case, thin: int):
                 sample=f"1 full step of every {thin}th particle ({sample.n_particles} particles) "
                        f"of the {case.name} workload on the full {case.gdims[1]}x{case.gdims[2]}"
                        f"{'' if case.dim == 2 else 'x' + str(case.gdims[0])} grid, float64, 1 thread",
-                seconds=dt)
+                seconds=dt, error_of_gpu_path=oracle_error(sample, sim))
+
+
+def oracle_error(sample, osim):
+    """The float32 GPU path against the float64 oracle after the same full
+    step on the same sample: largest position difference (cells), largest
+    momentum difference relative to the species' largest |u|, and largest
+    field differences relative to the largest oracle value."""
+    import numpy as np
+    from paper_1310_7866_amd.psc import PscSim
+    g = PscSim(sample, with_ids=True)
+    g.step(1)
+    g.check()
+    nx, ny, nz = sample.gdims
+    dpos, du = 0.0, 0.0
+    for s in range(len(sample.species)):
+        p = g.particles(0, s)
+        ids = p["id"].astype(np.int64)
+        c = p["cell"].astype(np.int64)
+        idx = (c % nx, (c // nx) % ny, c // (nx * ny))
+        dims = (1, 2) if sample.dim == 2 else (0, 1, 2)
+        order = np.argsort(osim.species[s].ids)
+        xo, uo = osim.species[s].xi[:, order], osim.species[s].u[:, order]
+        for k, d in enumerate(dims):
+            xg = np.empty(ids.size)
+            xg[ids] = idx[d] + p["off"][k].astype(np.float64)
+            diff = xg - xo[d]
+            diff -= sample.gdims[d] * np.round(diff / sample.gdims[d])
+            dpos = max(dpos, float(np.abs(diff).max(initial=0.0)))
+        ug = np.empty((3, ids.size))
+        ug[:, ids] = p["u"].astype(np.float64)
+        du = max(du, float(np.abs(ug - uo).max(initial=0.0) / max(np.abs(uo).max(initial=0.0), 1e-30)))
+    E, B, J = g.field_arrays(0)
+    rel = lambda a, b: float(np.abs(a.astype(np.float64).ravel() - b).max() / max(np.abs(b).max(), 1e-30))
+    out = dict(steps=1, max_position_cells=dpos, max_momentum_rel=du,
+               E_rel=rel(E, osim.E), B_rel=rel(B, osim.B), J_rel=rel(J, osim.J))
+    g.close()
+    return out
 
 
 def adjoint_leg(every: int = 10, nsteps: int = 50):
@@ -88,7 +130,7 @@ def adjoint_leg(every: int = 10, nsteps: int = 50):
                 adjoint_over_forward=eg.adjoint_ms / eg.forward_ms, W=float(W[0]))
 
 
-def batch_leg(steps: int = 10, n_runs: int = 64):
+def batch_leg(steps: int = 10, n_runs: int = 64, tune_cache=None, retune=False):
     """64 independent two-stream runs (uneven grids, ragged patches) advanced
     in one context (autotuned launch shape, HIP-graph replay) vs the same runs
     advanced one after another in their own contexts."""
@@ -100,7 +142,7 @@ def batch_leg(steps: int = 10, n_runs: int = 64):
     cs = cases.twostream_batch(n_runs=n_runs, seed=4064)
     n = sum(c.n_particles for c in cs)
     batch = PscSim(cs, with_ids=False)
-    mode, chunk, threads, _, table = tune(batch, cache=None, steps=2)
+    launch, _, table = tune(batch, cache=tune_cache, steps=2, force=retune)
     batch.step(2, use_graph=True)
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -131,7 +173,7 @@ def batch_leg(steps: int = 10, n_runs: int = 64):
     pick = [0, n_runs // 2, n_runs - 1]
     sub = [cs[i] for i in pick]
     bt = PscSim(sub)
-    bt.set_launch(mode, chunk, 0, threads)
+    bt.set_launch(**launch)
     bt.step(steps, use_graph=True)
     for r, c in enumerate(sub):
         al = PscSim(c)
@@ -143,7 +185,7 @@ def batch_leg(steps: int = 10, n_runs: int = 64):
     bt.close()
     return dict(workload=f"{n_runs} two-stream runs, {n} particles, "
                          f"{sum(c.ncell for c in cs)} cells, order 1",
-                launch=dict(mode=mode, chunk=chunk, threads=threads), steps=steps,
+                launch=launch, steps=steps,
                 batched_pushes_per_s=n * steps / (batch_ms / 1e3),
                 plain_pushes_per_s=n * steps / (plain_ms / 1e3),
                 batched_over_plain=plain_ms / batch_ms,
@@ -160,7 +202,15 @@ def main():
     ap.add_argument("--cpu-thin", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the adjoint and batch legs")
+    ap.add_argument("--only", choices=("adjoint", "batch"), default=None,
+                    help="run only the adjoint or the batch leg and print its JSON")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--launch", default="", help="fixed launch shape mode,chunk,threads,run (skips tuning)")
+    ap.add_argument("--tune-cache", default=TUNED, help="autotuner cache (JSON) to read and extend")
+    ap.add_argument("--retune", action="store_true", help="time every launch shape again")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="first run a 1 GiB fill and a 1 GiB device copy (reference kernels of known "
+                         "traffic for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -170,6 +220,23 @@ def main():
     import torch
     from paper_1310_7866_amd.psc import PscSim, B_HALF, E_FULL
 
+    if args.only == "adjoint":
+        print(json.dumps({"adjoint": adjoint_leg()}))
+        return
+    if args.only == "batch":
+        print(json.dumps({"batched": batch_leg(tune_cache=args.tune_cache, retune=args.retune)}))
+        return
+
+    if args.calibrate:
+        n = 256 * 1024 * 1024                      # float32 -> 1 GiB
+        src = torch.ones(n, dtype=torch.float32, device="cuda")   # fill: writes 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)                                             # copy: reads and writes 1 GiB
+        torch.cuda.synchronize()
+        print(f"[bench] calibration fill + copy of {4 * n} bytes", file=sys.stderr, flush=True)
+        del src, dst
+        torch.cuda.empty_cache()
+
     case = make_case(args.workload)
     print(f"[bench] workload {case.name}: gdims={case.gdims} order={case.order} patch={case.patch} "
           f"particles={case.n_particles}", file=sys.stderr, flush=True)
@@ -177,10 +244,13 @@ def main():
     stream = torch.cuda.current_stream()
 
     launch = None
-    if not args.no_tune:
+    if args.launch:
+        mode, chunk, threads, run = (int(x) for x in args.launch.split(","))
+        launch = dict(mode=mode, chunk=chunk, threads=threads, run=run)
+        sim.set_launch(**launch)
+    elif not args.no_tune:
         from paper_1310_7866_amd.autotune import tune
-        mode, chunk, threads, ms, _ = tune(sim, cache=None, steps=2)
-        launch = dict(mode=mode, chunk=chunk, threads=threads)
+        launch, ms, _ = tune(sim, cache=args.tune_cache, steps=2, force=args.retune)
         print(f"[bench] autotuned launch {launch} ({ms:.3f} ms)", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         sim.step(1)
@@ -220,12 +290,16 @@ def main():
 
     roof = dict(bound="hbm", achieved=round(achieved_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved_gbs / HBM_PEAK_GBS, 4), traffic=None)
-    traffic_file = os.path.join(ROOT, "profiles", f"traffic_{case.name}.json")
-    if os.path.exists(traffic_file):
-        with open(traffic_file) as f:
-            tr = json.load(f)
-        if tr.get("kernel_source_hash") == _push_source_hash():
-            roof["traffic"] = tr.get("bytes_per_launch")
+    # hardware counters of this kernel source at this launch shape, if recorded
+    roofs = None
+    counters = _recorded_counters(case, launch)
+    if counters is not None:
+        roof["traffic"] = counters["bytes_per_launch"]
+        valu_rate = counters["valu_per_launch"] / (push_ms / 1e3)
+        roofs = {"hbm_frac": roof["frac"],
+                 "valu_issue": {"achieved_instr_per_s": valu_rate, "peak_instr_per_s": VALU_ISSUE_PEAK,
+                                "frac": round(valu_rate / VALU_ISSUE_PEAK, 4)},
+                 "counters": counters["source"]}
 
     out = {
         "metric": "particle pushes/sec (gather+push+deposit) and % HBM roofline; adjoint/forward time",
@@ -251,24 +325,42 @@ def main():
         "wall_s_timed": wall,
         "roofline": roof,
     }
+    if roofs is not None:
+        out["roofs"] = roofs
     del sim
     torch.cuda.empty_cache()
     if not args.no_extras:
         print("[bench] adjoint leg", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_leg()
         print("[bench] batch leg", file=sys.stderr, flush=True)
-        out["batched"] = batch_leg()
+        out["batched"] = batch_leg(tune_cache=args.tune_cache, retune=args.retune)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_thin)
     print(json.dumps(out))
 
 
-def _push_source_hash() -> str:
+def push_source_hash() -> str:
+    """Hash of the sources the particle kernel is compiled from."""
     import hashlib
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1310_7866_amd", "csrc", "psc_push.hip"), "rb") as f:
-        h.update(f.read())
+    for name in ("psc_push.hip", "psc_device.h", "psc_internal.h"):
+        with open(os.path.join(ROOT, "paper_1310_7866_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def _recorded_counters(case, launch):
+    """HBM bytes and VALU instructions per particle-kernel launch from the
+    hardware-counter record of this workload, if it was taken on the current
+    kernel source with the same launch shape."""
+    path = os.path.join(ROOT, "profiles", f"counters_{case.name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_hash") != push_source_hash() or rec.get("launch") != launch:
+        return None
+    return rec
 
 
 if __name__ == "__main__":

@@ -73,38 +73,59 @@ def time_push(sim, steps: int = 3) -> float:
     return total / steps
 
 
-THREADS = (256, 512)
+THREADS = (256, 384, 512)
+RUNS = (1, 2, 4, 8)
 
 
 def tune(sim, cache: Optional[str] = DEFAULT_CACHE, steps: int = 2,
          modes: Sequence[int] = MODES, chunks: Sequence[int] = CHUNKS,
-         threads: Sequence[int] = THREADS, force: bool = False):
-    """Pick and apply the fastest (mode, chunk, threads) for `sim`; returns
-    (mode, chunk, threads, ms, table of every candidate's ms).  The state
-    advances by the timed steps (use during warm-up)."""
+         threads: Sequence[int] = THREADS, runs: Sequence[int] = RUNS, force: bool = False):
+    """Pick and apply the fastest launch shape for `sim`: first the workgroup
+    size and particles per lane (persistent queue launch, 4096-particle
+    chunks), then the launch mode and chunk size with those.  Returns
+    (launch dict with mode, chunk, threads, run; its ms; table of every
+    candidate's ms).  The state advances by the timed steps (use during
+    warm-up)."""
+    from .psc import PscError
     key = f"{_arch()}/{occupancy_class(sim.cases)}"
     data = _load(cache) if cache else {}
     if not force and key in data:
         e = data[key]
-        sim.set_launch(e["mode"], e["chunk"], 0, e["threads"])
-        return e["mode"], e["chunk"], e["threads"], e["ms"], e.get("table", {})
+        launch = {k: e[k] for k in ("mode", "chunk", "threads", "run")}
+        sim.set_launch(**launch)
+        return launch, e["ms"], e.get("table", {})
     table = {}
     best = None
+
+    def trial(launch):
+        nonlocal best
+        try:
+            sim.set_launch(**launch)
+        except PscError:
+            return                              # shape not possible (LDS)
+        sim.step(1)                             # settle (first launch of a shape)
+        ms = time_push(sim, steps)
+        table["{mode}/{chunk}/{threads}/{run}".format(**launch)] = ms
+        if best is None or ms < best[1]:
+            best = (dict(launch), ms)
+
+    base_mode = 1 if 1 in modes else modes[0]
+    base_chunk = 4096 if 4096 in chunks else chunks[0]
     for nt in threads:
-        for mode in modes:
-            for chunk in chunks:
-                sim.set_launch(mode, chunk, 0, nt)
-                sim.step(1)                     # settle (first launch of a shape)
-                ms = time_push(sim, steps)
-                table[f"{mode}/{chunk}/{nt}"] = ms
-                if best is None or ms < best[3]:
-                    best = (mode, chunk, nt, ms)
-    sim.set_launch(best[0], best[1], 0, best[2])
+        for run in runs:
+            trial(dict(mode=base_mode, chunk=base_chunk, threads=nt, run=run))
+    nt, run = best[0]["threads"], best[0]["run"]
+    for mode in modes:
+        for chunk in chunks:
+            if (mode, chunk) != (base_mode, base_chunk):
+                trial(dict(mode=mode, chunk=chunk, threads=nt, run=run))
+    launch, ms = best
+    sim.set_launch(**launch)
     sim.check()
     if cache:
-        data[key] = dict(mode=best[0], chunk=best[1], threads=best[2], ms=best[3], table=table)
+        data[key] = dict(launch, ms=ms, table=table)
         _save(cache, data)
-    return best[0], best[1], best[2], best[3], table
+    return launch, ms, table
 
 
 def tune_patch(make_cases, patches: Iterable[int], steps: int = 2, **kw):

@@ -338,7 +338,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_particles(const RunDev *__restri
 
         // ---- Boris with intermediates ---------------------------------------
         const float3 um = add3(u0, scale3(Ep, h));
-        const float igm = rsqrtf(1.0f + dot3(um, um));
+        const float igm = rsqrt_ge1(1.0f + dot3(um, um));
         const float3 t = scale3(Bp, h * igm);
         const float t2 = dot3(t, t);
         const float f = 2.0f / (1.0f + t2);
@@ -346,7 +346,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_particles(const RunDev *__restri
         const float3 up = add3(um, cross3(um, t));
         const float3 uq = add3(um, cross3(up, s));
         const float3 un = add3(uq, scale3(Ep, h));
-        const float ig = rsqrtf(1.0f + dot3(un, un));
+        const float ig = rsqrt_ge1(1.0f + dot3(un, un));
 
         // ---- move -------------------------------------------------------------
         int sh[2];

@@ -110,15 +110,26 @@ __device__ __forceinline__ float gather3(const float *F, int px, int pxy, int ix
 
 __device__ __forceinline__ void lds_add(float *p, float v) { atomicAdd(p, v); }
 
-// fast quotient/remainder for small non-negative a
+// quotient and remainder of 0 <= a < 2^22 by b >= 1 (inv_b = 1/b rounded to
+// float).  (a + 1/2)/b lies at least 1/(2b) from an integer; a + 1/2 is exact
+// and the two roundings (of 1/b and of the product) change the product by a
+// relative 2^-23 at most, i.e. by less than 2^22/b * 2^-23 = 1/(2b), so the
+// truncation is the exact quotient.
 __device__ __forceinline__ int divmod_small(int a, int b, float inv_b, int &rem) {
-    int q = (int)((float)a * inv_b);
-    int r = a - q * b;
-    if (r < 0) { --q; r += b; }
-    else if (r >= b) { ++q; r -= b; }
-    rem = r;
+    const int q = (int)(((float)a + 0.5f) * inv_b);
+    rem = a - q * b;
     return q;
 }
+
+// 1/sqrt(x) for x >= 1 (no denormal range to guard): the hardware estimate
+__device__ __forceinline__ float rsqrt_ge1(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// pointers into device memory known to be global (loads and stores become
+// global_* instead of flat_*, which would also wait on LDS traffic)
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ gptr<T> to_global(T *p) { return (gptr<T>)p; }
 
 
 }  // namespace psc

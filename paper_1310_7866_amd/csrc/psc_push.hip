@@ -14,6 +14,33 @@
 
 namespace psc {
 
+// Compile-time shape of the particle kernel (the defaults are the measured
+// best on gfx950; -D overrides build the alternatives for comparison):
+//   PSC_SCAN_WIDTH   lanes per group of the segmented current sums (16/32/64)
+//   PSC_QUEUE_SLOTS  per-wave queue of particles whose support changes nodes
+#ifndef PSC_SCAN_WIDTH
+#define PSC_SCAN_WIDTH 64
+#endif
+#ifndef PSC_QUEUE_SLOTS
+#define PSC_QUEUE_SLOTS 32
+#endif
+//   PSC_WAVES_PER_EU occupancy the register allocator must allow (0: free)
+#ifndef PSC_WAVES_PER_EU
+#define PSC_WAVES_PER_EU 0
+#endif
+#if PSC_WAVES_PER_EU > 0
+#define PSC_OCCUPANCY __attribute__((amdgpu_waves_per_eu(PSC_WAVES_PER_EU)))
+#else
+#define PSC_OCCUPANCY
+#endif
+constexpr int kScanWidth = PSC_SCAN_WIDTH;
+constexpr int kQueueSlots = PSC_QUEUE_SLOTS;
+static_assert(kQueueSlots >= 1 && kQueueSlots <= 64, "queue slots 1..64");
+
+// words of one queued particle whose support changes nodes: packed cell and
+// moves, start and end offsets, and in 2-d the out-of-plane current factor
+constexpr int cross_words(int dim) { return dim == 2 ? 6 : 7; }
+
 // ---------------------------------------------------------------------------
 // work items
 // ---------------------------------------------------------------------------
@@ -70,45 +97,84 @@ __global__ void __launch_bounds__(1024) k_build_items(const RunDev *__restrict__
 // ---------------------------------------------------------------------------
 // Particles are sorted by cell, so the 64 lanes of a wave mostly share one or
 // two cells and would hit the same LDS words with atomics.  Instead each lane
-// writes its current into a fixed per-cell frame, the wave forms prefix sums
-// across lanes with DPP row shifts and row broadcasts, and the last lane of
-// every run of equal cells adds the run's sum to LDS.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ float dpp_take(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, true));
-}
-
-__device__ __forceinline__ float wave_prefix_sum(float v) {
-    v += dpp_take<0x111, 0xF>(v);  // row_shr:1
-    v += dpp_take<0x112, 0xF>(v);  // row_shr:2
-    v += dpp_take<0x114, 0xF>(v);  // row_shr:4
-    v += dpp_take<0x118, 0xF>(v);  // row_shr:8   -> inclusive within rows of 16
-    v += dpp_take<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
-    v += dpp_take<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
-    return v;
-}
-
-struct Segments {
-    int prev;      // lane holding the prefix just before this lane's run (or -1)
-    bool tail;     // last lane of its run
+// writes its current into a fixed per-cell frame and the wave forms segmented
+// inclusive sums (segment = run of lanes with equal cell) over rows of SW
+// lanes: DPP row shifts and row broadcasts, each multiplied by a per-lane
+// 0/1 mask that is 1 only where the source lane lies in the same segment, so
+// every step is one DPP multiply-add.  The last lane of each segment piece
+// within a row group then adds the piece's sum to LDS.
+struct RowScan {
+    float m[6];    // multipliers of the six steps (1: source lane in my segment)
+    bool tail;     // last lane of its segment within its group of SW lanes
 };
 
-__device__ __forceinline__ Segments wave_segments(int key) {
+template <int SW>
+__device__ __forceinline__ RowScan row_scan_setup(int key) {
     const int lane = threadIdx.x & 63;
     const int left = __shfl_up(key, 1, 64);
     const uint64_t heads = __ballot(lane == 0 || left != key);
     const uint64_t le = lane == 63 ? ~0ull : ((2ull << lane) - 1);
-    const int start = 63 - __clzll(heads & le);
-    Segments s;
-    s.prev = start - 1;
-    s.tail = lane == 63 || ((heads >> (lane + 1)) & 1ull);
-    return s;
+    const int start = 63 - __clzll(heads & le);   // first lane of my segment
+    const int row0 = lane & ~15;
+    const int d = lane - (start > row0 ? start : row0);
+    RowScan r;
+    r.m[0] = d >= 1 ? 1.0f : 0.0f;
+    r.m[1] = d >= 2 ? 1.0f : 0.0f;
+    r.m[2] = d >= 4 ? 1.0f : 0.0f;
+    r.m[3] = d >= 8 ? 1.0f : 0.0f;
+    r.m[4] = ((lane & 16) && start < row0) ? 1.0f : 0.0f;   // from the last lane of the row below
+    r.m[5] = (lane >= 32 && start < 32) ? 1.0f : 0.0f;     // from lane 31
+    r.tail = lane == 63 || ((heads >> (lane + 1)) & 1ull) || (lane & (SW - 1)) == SW - 1;
+    return r;
 }
 
-__device__ __forceinline__ float segment_sum(float v, const Segments &sg) {
-    const float incl = wave_prefix_sum(v);
-    const float before = __shfl(incl, sg.prev < 0 ? 0 : sg.prev, 64);
-    return sg.prev < 0 ? incl : incl - before;
+// Segmented inclusive sums of four independent values: every step is one
+// v_fmac_f32_dpp (v += m * v[source lane]).  The four chains are interleaved
+// so that a value is read through DPP three instructions after it was
+// written (the hardware wants two wait states between a VALU write and a DPP
+// read of the same register, five after a VALU write of EXEC; the leading
+// s_nop covers whatever precedes the block).  Rows not selected by a
+// broadcast's row mask keep their value.  The block is volatile: it reads
+// other lanes, so it must stay where every lane of the wave executes it.
+#define PSC_FMAC_DPP(CTL, M) \
+    "v_fmac_f32_dpp %0, %0, " M " " CTL "\n\t" \
+    "v_fmac_f32_dpp %1, %1, " M " " CTL "\n\t" \
+    "v_fmac_f32_dpp %2, %2, " M " " CTL "\n\t" \
+    "v_fmac_f32_dpp %3, %3, " M " " CTL "\n\t"
+#define PSC_SHR(N) "row_shr:" #N " row_mask:0xf bank_mask:0xf bound_ctrl:1"
+
+template <int SW>
+__device__ __forceinline__ void row_scan4(float &a, float &b, float &c, float &d, const RowScan &r) {
+    if constexpr (SW == 16) {
+        asm volatile("s_nop 4\n\t" PSC_FMAC_DPP(PSC_SHR(1), "%4") PSC_FMAC_DPP(PSC_SHR(2), "%5")
+                PSC_FMAC_DPP(PSC_SHR(4), "%6") PSC_FMAC_DPP(PSC_SHR(8), "%7")
+            : "+v"(a), "+v"(b), "+v"(c), "+v"(d)
+            : "v"(r.m[0]), "v"(r.m[1]), "v"(r.m[2]), "v"(r.m[3]));
+    } else if constexpr (SW == 32) {
+        asm volatile("s_nop 4\n\t" PSC_FMAC_DPP(PSC_SHR(1), "%4") PSC_FMAC_DPP(PSC_SHR(2), "%5")
+                PSC_FMAC_DPP(PSC_SHR(4), "%6") PSC_FMAC_DPP(PSC_SHR(8), "%7")
+                    PSC_FMAC_DPP("row_bcast:15 row_mask:0xa bank_mask:0xf", "%8")
+            : "+v"(a), "+v"(b), "+v"(c), "+v"(d)
+            : "v"(r.m[0]), "v"(r.m[1]), "v"(r.m[2]), "v"(r.m[3]), "v"(r.m[4]));
+    } else {
+        static_assert(SW == 64, "scan width 16, 32 or 64");
+        asm volatile("s_nop 4\n\t" PSC_FMAC_DPP(PSC_SHR(1), "%4") PSC_FMAC_DPP(PSC_SHR(2), "%5")
+                PSC_FMAC_DPP(PSC_SHR(4), "%6") PSC_FMAC_DPP(PSC_SHR(8), "%7")
+                    PSC_FMAC_DPP("row_bcast:15 row_mask:0xa bank_mask:0xf", "%8")
+                        PSC_FMAC_DPP("row_bcast:31 row_mask:0xc bank_mask:0xf", "%9")
+            : "+v"(a), "+v"(b), "+v"(c), "+v"(d)
+            : "v"(r.m[0]), "v"(r.m[1]), "v"(r.m[2]), "v"(r.m[3]), "v"(r.m[4]), "v"(r.m[5]));
+    }
+}
+#undef PSC_SHR
+#undef PSC_FMAC_DPP
+
+// segmented sums of N values (N a multiple of 4) in place
+template <int SW, int N>
+__device__ __forceinline__ void row_scan(float (&v)[N], const RowScan &r) {
+    static_assert(N % 4 == 0, "values come in groups of four");
+#pragma unroll
+    for (int k = 0; k < N; k += 4) row_scan4<SW>(v[k], v[k + 1], v[k + 2], v[k + 3], r);
 }
 
 // ---------------------------------------------------------------------------
@@ -232,13 +298,26 @@ __device__ __forceinline__ int unit_of_item(const int32_t *__restrict__ item_sta
     return lo;
 }
 
-// One work item: stage the patch's fields, push its chunk of particles,
-// add the chunk's current into the patch tile.  Ends with a barrier so the
-// caller may start the next item on the same LDS.
+// One work item: stage the patch's fields, push its chunk of particles, add
+// the chunk's current into the patch tile.  Ends with a barrier so the caller
+// may start the next item on the same LDS.
+//
+// The chunk's particles are sorted by cell.  A cell with n particles gets
+// r = ceil(n / K) lanes ("runs"); member q of the cell's lanes pushes the
+// cell's particles q, q + r, q + 2r, ... one after another, adding the
+// Esirkepov current of those whose interpolation support keeps its nodes
+// into a per-cell frame held in registers.  (Interleaving the cell's
+// particles over its lanes keeps every step's loads and stores contiguous
+// per cell.)  At the end of a round the wave forms segmented sums of the
+// frames over lanes of equal cell (the lanes of a cell are consecutive) and
+// the last lane of each segment adds them to the LDS current tile: one scan
+// and one set of LDS atomics per K particles of a lane.  Particles whose
+// support changes nodes wait in a per-wave queue and are deposited in
+// batches with per-lane LDS atomics.
 template <int DIM, int ORDER, int NT>
 __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const Unit *__restrict__ units,
                                           const int32_t *__restrict__ item_start, int lo, int item, int chunk,
-                                          int front, int cs_sel, int use_perm, uint32_t *__restrict__ err,
+                                          int front, int cs_sel, int use_perm, int K, uint32_t *__restrict__ err,
                                           float *lds) {
     constexpr int FLO = 1, FHI = ORDER;   // field ghosts
     constexpr int JLO = ORDER, JHI = ORDER + 1;
@@ -246,6 +325,13 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
     constexpr int FB = ORDER == 1 ? 0 : -1;
     // the 3-d order-2 frame holds 144 values per particle: lane atomics instead
     constexpr bool kReduce = !(DIM == 3 && ORDER == 2);
+    // frame values: 2-d Jy FL(FL-1), Jz (FL-1)FL, Jx FL^2; 3-d FL^2(FL-1) each
+    constexpr int NY2 = FL * (FL - 1);
+    constexpr int NC3 = FL * FL * (FL - 1);
+    constexpr int NV = !kReduce ? 4 : (DIM == 2 ? 2 * NY2 + FL * FL : 3 * NC3);
+    constexpr int SW = kScanWidth;
+    constexpr int QW = cross_words(DIM);   // words of one queued crossing particle
+    constexpr int QS = kQueueSlots;
 
     const Unit U = units[lo];
     const RunDev &R = runs[U.run];
@@ -256,10 +342,11 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
     const int hx = DIM == 3 ? patch_ext(R, 0, pc[0]) : 1;
     const int hy = patch_ext(R, 1, pc[1]);
     const int hz = patch_ext(R, 2, pc[2]);
+    const int pcells = hx * hy * hz;
     const int ox = pc[0] * R.P[0], oy = pc[1] * R.P[1], oz = pc[2] * R.P[2];
     const int64_t kb = patch_key_base(R, pc[0], pc[1], pc[2]);
     const int32_t *cs = S.cs[cs_sel];
-    const int32_t pbeg = cs[kb], pend = cs[kb + (int64_t)hx * hy * hz];
+    const int32_t pbeg = cs[kb], pend = cs[kb + pcells];
     const int32_t beg = pbeg + (item - item_start[lo]) * chunk;
     const int32_t end = min(beg + chunk, pend);
 
@@ -270,13 +357,24 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
     const int jx_ = DIM == 3 ? R.P[0] + JLO + JHI : 1;
     const int jy_ = R.P[1] + JLO + JHI, jz_ = R.P[2] + JLO + JHI;
     const int jcells = jx_ * jy_ * jz_;
+    const int npc = (DIM == 3 ? R.P[0] : 1) * R.P[1] * R.P[2];
     float *ftile = lds;               // 6 * fcells: Ex Ey Ez Bx By Bz
     float *jtile = lds + 6 * fcells;  // 3 * jcells: Jx Jy Jz
+    // per-wave queue of particles whose support changes nodes: QW words
+    // (field-major) for each of QS slots
+    float *cq = jtile + 3 * jcells + (threadIdx.x >> 6) * (QS * QW);
+    // cell table: clamped first particle of every cell (npc + 1), run prefix
+    // (npc + 1), per-wave sums of the prefix scan (NT / 64)
+    int32_t *ccs = reinterpret_cast<int32_t *>(jtile + 3 * jcells + (NT / 64) * QS * QW);
+    int32_t *crs = ccs + (npc + 1);
+    int32_t *wsum = crs + (npc + 1);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
-    // stage E, B (+ghosts) and clear the current tile
+    // stage E, B (+ghosts), clear the current tile, clamp the cell offsets
     {
         const float inv_fx = 1.0f / fx, inv_fy = 1.0f / fy;
         const int64_t nc = R.ncell;
+        const gptr<const float> Eg = to_global<const float>(R.E), Bg = to_global<const float>(R.B);
         for (int t = threadIdx.x; t < fcells; t += NT) {
             int tx = 0, ty, tz;
             if constexpr (DIM == 3) {
@@ -291,25 +389,57 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
             const int64_t g = gx + (int64_t)R.n[0] * (gy + (int64_t)R.n[1] * gz);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                ftile[c * fcells + t] = R.E[c * nc + g];
-                ftile[(3 + c) * fcells + t] = R.B[c * nc + g];
+                ftile[c * fcells + t] = Eg[c * nc + g];
+                ftile[(3 + c) * fcells + t] = Bg[c * nc + g];
             }
         }
         for (int t = threadIdx.x; t < 3 * jcells; t += NT) jtile[t] = 0.0f;
+        for (int c = threadIdx.x; c <= pcells; c += NT) {
+            const int32_t v = cs[kb + c];
+            ccs[c] = v < beg ? beg : (v > end ? end : v);
+        }
     }
     __syncthreads();
 
+    // K = 1: lane t of a round takes particle beg + r0 + t (coalesced) and
+    // its cell comes from its key; no cell table is needed
+    const bool single = K == 1;
+    // runs per cell (ceil(particles / K)) and their exclusive prefix
+    if (!single) {
+        const int per = (pcells + NT - 1) / NT;
+        const int c0 = imin((int)threadIdx.x * per, pcells), c1 = imin(c0 + per, pcells);
+        int32_t sum = 0;
+        for (int c = c0; c < c1; ++c) sum += (ccs[c + 1] - ccs[c] + K - 1) / K;
+        int32_t x = sum;   // inclusive scan over the wave
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int32_t y = __shfl_up(x, d, 64);
+            if (lane >= d) x += y;
+        }
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        int32_t run = x - sum;
+        for (int w = 0; w < wave; ++w) run += wsum[w];
+        for (int c = c0; c < c1; ++c) {
+            crs[c] = run;
+            run += (ccs[c + 1] - ccs[c] + K - 1) / K;
+        }
+        if (threadIdx.x == NT - 1) crs[pcells] = run;
+        __syncthreads();
+    }
+    const int32_t nruns = single ? end - beg : crs[pcells];
+
     const int in = front, outb = 1 - front;
-    const int32_t *__restrict__ cell_in = S.cell[in];
-    const float *__restrict__ off_in = S.off[in];
-    const float *__restrict__ u_in = S.u[in];
-    const int32_t *__restrict__ id_in = S.id[in];
-    int32_t *__restrict__ cell_out = S.cell[outb];
-    float *__restrict__ off_out = S.off[outb];
-    float *__restrict__ u_out = S.u[outb];
-    int32_t *__restrict__ id_out = S.id[outb];
-    const int32_t *__restrict__ perm = S.perm;
-    uint8_t *__restrict__ mc = S.mc;
+    const gptr<const int32_t> cell_in = to_global<const int32_t>(S.cell[in]);
+    const gptr<const float> off_in = to_global<const float>(S.off[in]);
+    const gptr<const float> u_in = to_global<const float>(S.u[in]);
+    const gptr<const int32_t> id_in = to_global<const int32_t>(S.id[in]);
+    const gptr<int32_t> cell_out = to_global(S.cell[outb]);
+    const gptr<float> off_out = to_global(S.off[outb]);
+    const gptr<float> u_out = to_global(S.u[outb]);
+    const gptr<int32_t> id_out = to_global(S.id[outb]);
+    const gptr<const int32_t> perm = to_global<const int32_t>(S.perm);
+    const gptr<uint8_t> mc = to_global(S.mc);
     const int64_t cap = S.cap;
     const float h = S.qdt_2m;
     const float qw = S.qw;
@@ -318,226 +448,345 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
     const float cfy = dt * R.inv_dx[1], cfz = dt * R.inv_dx[2];
     const float jfx = -qw * R.dx[0] / dt, jfy = -qw * R.dx[1] / dt, jfz = -qw * R.dx[2] / dt;
     const float inv_hx = 1.0f / hx, inv_hy = 1.0f / hy;
-    const int pcells = hx * hy * hz;
     float *Jx = jtile, *Jy = jtile + jcells, *Jz = jtile + 2 * jcells;
     uint32_t flags = 0;
 
-    // every lane runs the same number of iterations (the wave reduction needs
-    // all 64 lanes); lanes past the end carry zero current and write nothing
-    for (int32_t i0 = beg; i0 < end; i0 += NT) {
-        const int32_t i = i0 + threadIdx.x;
-        const bool valid = i < end;
-        // lanes past the end stand in with the chunk's first particle (taken
-        // through the permutation, so it lies in this patch)
-        const int32_t slot = valid ? i : beg;
-        int32_t src = use_perm ? perm[slot] : slot;
-        if ((uint32_t)src >= (uint32_t)S.n) {   // corrupt permutation: stay in bounds
-            if (valid) flags |= PSC_DEV_KEY;
-            src = slot;
-        }
-        const int32_t key = cell_in[src];
-        float o[3];
-        o[0] = DIM == 3 ? off_in[src] : 0.0f;
-        o[1] = off_in[(DIM == 3 ? 1 : 0) * cap + src];
-        o[2] = off_in[(DIM == 3 ? 2 : 1) * cap + src];
-        float ux = u_in[src], uy = u_in[cap + src], uz = u_in[2 * cap + src];
-        const int32_t idv = id_in ? id_in[src] : 0;
-
-        int local = key - (int32_t)kb;
-        if (local < 0 || local >= pcells) {  // not in this patch: corrupt state
-            if (valid) flags |= PSC_DEV_KEY;
-            local = 0;
-        }
-        int lx = 0, ly, lz;
-        if constexpr (DIM == 3) {
-            const int q = divmod_small(local, hx, inv_hx, lx);
-            lz = divmod_small(q, hy, inv_hy, ly);
-        } else {
-            lz = divmod_small(local, hy, inv_hy, ly);
-        }
-
-        // ---- interpolation ------------------------------------------------
-        float wny[ORDER + 1], why[ORDER + 1], wnz[ORDER + 1], whz[ORDER + 1];
-        const int bny = node_weights<ORDER>(o[1], wny), bhy = half_weights<ORDER>(o[1], why);
-        const int bnz = node_weights<ORDER>(o[2], wnz), bhz = half_weights<ORDER>(o[2], whz);
-        float Ex, Ey, Ez, Bx, By, Bz;
-        if constexpr (DIM == 2) {
-            const int ty = ly + FLO, tz = lz + FLO;
-            Ex = gather2<ORDER>(ftile + 0 * fcells, fy, ty + bny, tz + bnz, wny, wnz);
-            Ey = gather2<ORDER>(ftile + 1 * fcells, fy, ty + bhy, tz + bnz, why, wnz);
-            Ez = gather2<ORDER>(ftile + 2 * fcells, fy, ty + bny, tz + bhz, wny, whz);
-            Bx = gather2<ORDER>(ftile + 3 * fcells, fy, ty + bhy, tz + bhz, why, whz);
-            By = gather2<ORDER>(ftile + 4 * fcells, fy, ty + bny, tz + bhz, wny, whz);
-            Bz = gather2<ORDER>(ftile + 5 * fcells, fy, ty + bhy, tz + bnz, why, wnz);
-        } else {
-            float wnx[ORDER + 1], whx[ORDER + 1];
-            const int bnx = node_weights<ORDER>(o[0], wnx), bhx = half_weights<ORDER>(o[0], whx);
-            const int tx = lx + FLO, ty = ly + FLO, tz = lz + FLO;
-            const int pxy = fx * fy;
-            Ex = gather3<ORDER>(ftile + 0 * fcells, fx, pxy, tx + bhx, ty + bny, tz + bnz, whx, wny, wnz);
-            Ey = gather3<ORDER>(ftile + 1 * fcells, fx, pxy, tx + bnx, ty + bhy, tz + bnz, wnx, why, wnz);
-            Ez = gather3<ORDER>(ftile + 2 * fcells, fx, pxy, tx + bnx, ty + bny, tz + bhz, wnx, wny, whz);
-            Bx = gather3<ORDER>(ftile + 3 * fcells, fx, pxy, tx + bnx, ty + bhy, tz + bhz, wnx, why, whz);
-            By = gather3<ORDER>(ftile + 4 * fcells, fx, pxy, tx + bhx, ty + bny, tz + bhz, whx, wny, whz);
-            Bz = gather3<ORDER>(ftile + 5 * fcells, fx, pxy, tx + bhx, ty + bhy, tz + bnz, whx, why, wnz);
-        }
-
-        // ---- relativistic Boris push: half E kick, rotation, half E kick --
-        {
-            const float mx = fmaf(h, Ex, ux), my = fmaf(h, Ey, uy), mz = fmaf(h, Ez, uz);
-            const float igm = rsqrtf(1.0f + mx * mx + my * my + mz * mz);
-            const float tx = h * Bx * igm, ty = h * By * igm, tz = h * Bz * igm;
-            const float f = 2.0f / (1.0f + tx * tx + ty * ty + tz * tz);
-            const float sx = f * tx, sy = f * ty, sz = f * tz;
-            const float px = mx + (my * tz - mz * ty);
-            const float py = my + (mz * tx - mx * tz);
-            const float pz = mz + (mx * ty - my * tx);
-            ux = fmaf(h, Ex, mx + (py * sz - pz * sy));
-            uy = fmaf(h, Ey, my + (pz * sx - px * sz));
-            uz = fmaf(h, Ez, mz + (px * sy - py * sx));
-        }
-        const float ig = rsqrtf(1.0f + ux * ux + uy * uy + uz * uz);
-        if (valid && !(ig > 0.0f)) flags |= PSC_DEV_NONFINITE;   // NaN or Inf momentum
-
-        // ---- move: xi^{n+3/2} = xi^{n+1/2} + dt u^{n+1} / (gamma dx) -------
-        int s[3] = {0, 0, 0};
-        float o1[3] = {o[0], o[1], o[2]};
+    // deposit queued particles [0, n) of this wave, one per lane
+    int qn = 0;   // queued particles (the same in every lane of the wave)
+    auto drain = [&](int n) {
+        __builtin_amdgcn_wave_barrier();
+        if (lane < n) {
+            const int pk = __float_as_int(cq[lane]);
+            const int qs[3] = {((pk >> 24) & 3) - 1, ((pk >> 26) & 3) - 1, ((pk >> 28) & 3) - 1};
+            float a0[3] = {0.0f, 0.0f, 0.0f}, a1[3] = {0.0f, 0.0f, 0.0f};
+            constexpr int D = DIM == 3 ? 3 : 2, d0 = 3 - D;
 #pragma unroll
-        for (int d = (DIM == 3 ? 0 : 1); d < 3; ++d) {
-            const float cf = d == 0 ? cfx : (d == 1 ? cfy : cfz);
-            const float uu = d == 0 ? ux : (d == 1 ? uy : uz);
-            float disp = cf * uu * ig;
-            if (!(fabsf(disp) < 0.99f)) {   // CFL broken or non-finite: keep it in bounds
-                if (valid) flags |= PSC_DEV_MOVE;
-                disp = 0.0f;
+            for (int k = 0; k < D; ++k) {
+                a0[d0 + k] = cq[(1 + k) * QS + lane];
+                a1[d0 + k] = cq[(1 + D + k) * QS + lane];
             }
-            const float x1 = o[d] + disp;
-            int sd = (int)floorf(x1);
-            float od = x1 - (float)sd;
-            if (od >= 1.0f) { od -= 1.0f; sd += 1; }
-            s[d] = sd;
-            o1[d] = od;
+            const float qfx = DIM == 2 ? cq[5 * QS + lane] : 0.0f;
+            deposit_lane<DIM, ORDER>(jtile, jcells, jx_, jy_, pk & 255, (pk >> 8) & 255, (pk >> 16) & 255, a0, qs,
+                                     a1, jfx, jfy, jfz, qfx);
         }
+        __builtin_amdgcn_wave_barrier();
+    };
 
-        // ---- Esirkepov deposit ----------------------------------------------
-        const float fxv = qw * ux * ig;   // 2-d out-of-plane current factor q w v_x
-        bool frame = valid && stays<ORDER>(o[1], s[1], o1[1]) && stays<ORDER>(o[2], s[2], o1[2]);
-        if constexpr (DIM == 3) frame = frame && stays<ORDER>(o[0], s[0], o1[0]);
-        if (!kReduce) frame = false;
-        if (valid && !frame)
-            deposit_lane<DIM, ORDER>(jtile, jcells, jx_, jy_, lx, ly, lz, o, s, o1, jfx, jfy, jfz, fxv);
-        if constexpr (kReduce) {
-            const Segments sg = wave_segments(valid ? local : -1);
-            const bool put = sg.tail && valid;
-            float S0y[FL], S1y[FL], S0z[FL], S1z[FL];
-            frame_weights<ORDER>(o[1], o1[1], S0y, S1y);
-            frame_weights<ORDER>(o[2], o1[2], S0z, S1z);
-            const float on = frame ? 1.0f : 0.0f;
-            float DSy[FL], DSz[FL], Ay[FL], Az[FL], Cy[FL], Cz[FL];
-#pragma unroll
-            for (int r = 0; r < FL; ++r) {
-                DSy[r] = (S1y[r] - S0y[r]) * on;
-                DSz[r] = (S1z[r] - S0z[r]) * on;
-                Ay[r] = fmaf(0.5f, DSy[r], S0y[r] * on);
-                Az[r] = fmaf(0.5f, DSz[r], S0z[r] * on);
-                Cy[r] = r == 0 ? DSy[0] : Cy[r - 1] + DSy[r];
-                Cz[r] = r == 0 ? DSz[0] : Cz[r - 1] + DSz[r];
+    // every lane runs the same number of rounds and of steps per round (the
+    // wave operations need all 64 lanes); lanes without a particle carry zero
+    // current and write nothing
+    for (int32_t r0 = 0; r0 < nruns; r0 += NT) {
+        const int32_t g = r0 + (int32_t)threadIdx.x;
+        int c = 0;
+        int32_t first = beg, nleft = 0, stride = 1;   // particle j: first + j * stride while j*stride < nleft
+        if (single) {
+            first = beg + g;
+            nleft = g < nruns ? 1 : 0;
+        } else if (g < nruns) {
+            int a = 0, b = pcells;   // crs[a] <= g < crs[b]
+            while (b - a > 1) {
+                const int m = (a + b) >> 1;
+                if (crs[m] <= g) a = m;
+                else b = m;
             }
-            if constexpr (DIM == 2) {
-                const int base = (lz + FB + JLO) * jy_ + (ly + FB + JLO);
-#pragma unroll
-                for (int b = 0; b < FL; ++b)
-#pragma unroll
-                    for (int a = 0; a < FL - 1; ++a) {
-                        const float v = segment_sum(jfy * Cy[a] * Az[b], sg);
-                        if (put) lds_add(&Jy[base + b * jy_ + a], v);
-                    }
-#pragma unroll
-                for (int b = 0; b < FL - 1; ++b)
-#pragma unroll
-                    for (int a = 0; a < FL; ++a) {
-                        const float v = segment_sum(jfz * Ay[a] * Cz[b], sg);
-                        if (put) lds_add(&Jz[base + b * jy_ + a], v);
-                    }
-#pragma unroll
-                for (int b = 0; b < FL; ++b)
-#pragma unroll
-                    for (int a = 0; a < FL; ++a) {
-                        const float v = segment_sum(fxv * fmaf(DSy[a] * DSz[b], 1.0f / 12.0f, Ay[a] * Az[b]), sg);
-                        if (put) lds_add(&Jx[base + b * jy_ + a], v);
-                    }
+            c = a;
+            const int32_t q = g - crs[c];
+            stride = crs[c + 1] - crs[c];
+            first = ccs[c] + q;
+            nleft = ccs[c + 1] - ccs[c] - q;
+        }
+        const int32_t len = nleft > 0 ? (nleft + stride - 1) / stride : 0;   // this lane's particles
+        int lx = 0, ly = 0, lz = 0;
+        auto cell_coords = [&]() {
+            if constexpr (DIM == 3) {
+                const int q = divmod_small(c, hx, inv_hx, lx);
+                lz = divmod_small(q, hy, inv_hy, ly);
             } else {
-                float S0x[FL], S1x[FL];
-                frame_weights<ORDER>(o[0], o1[0], S0x, S1x);
-                float DSx[FL], Ax[FL], Cx[FL];
+                lz = divmod_small(c, hy, inv_hy, ly);
+            }
+        };
+        if (!single) cell_coords();
+        float acc[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = 0.0f;
+
+        for (int j = 0; j < K; ++j) {
+            const bool valid = j < len;
+            // lanes without a particle stand in with the chunk's first
+            // particle (taken through the permutation, so it lies in range)
+            const int32_t slot = valid ? first + j * stride : beg;
+            int32_t src = use_perm ? perm[slot] : slot;
+            if ((uint32_t)src >= (uint32_t)S.n) {   // corrupt permutation: stay in bounds
+                if (valid) flags |= PSC_DEV_KEY;
+                src = slot;
+            }
+            const int32_t key = cell_in[src];
+            if (single) {   // the cell is the particle's own
+                c = key - (int32_t)kb;
+                if (c < 0 || c >= pcells) {   // not in this patch: corrupt state
+                    if (valid) flags |= PSC_DEV_KEY;
+                    c = 0;
+                }
+                cell_coords();
+            } else if (valid && key != (int32_t)kb + c) {
+                flags |= PSC_DEV_KEY;   // not the cell the order says
+            }
+            float o[3];
+            o[0] = DIM == 3 ? off_in[src] : 0.0f;
+            o[1] = off_in[(DIM == 3 ? 1 : 0) * cap + src];
+            o[2] = off_in[(DIM == 3 ? 2 : 1) * cap + src];
+            float ux = u_in[src], uy = u_in[cap + src], uz = u_in[2 * cap + src];
+            const int32_t idv = id_in ? id_in[src] : 0;
+
+            // ---- interpolation ----------------------------------------------
+            float wny[ORDER + 1], why[ORDER + 1], wnz[ORDER + 1], whz[ORDER + 1];
+            const int bny = node_weights<ORDER>(o[1], wny), bhy = half_weights<ORDER>(o[1], why);
+            const int bnz = node_weights<ORDER>(o[2], wnz), bhz = half_weights<ORDER>(o[2], whz);
+            float Ex, Ey, Ez, Bx, By, Bz;
+            if constexpr (DIM == 2) {
+                const int ty = ly + FLO, tz = lz + FLO;
+                Ex = gather2<ORDER>(ftile + 0 * fcells, fy, ty + bny, tz + bnz, wny, wnz);
+                Ey = gather2<ORDER>(ftile + 1 * fcells, fy, ty + bhy, tz + bnz, why, wnz);
+                Ez = gather2<ORDER>(ftile + 2 * fcells, fy, ty + bny, tz + bhz, wny, whz);
+                Bx = gather2<ORDER>(ftile + 3 * fcells, fy, ty + bhy, tz + bhz, why, whz);
+                By = gather2<ORDER>(ftile + 4 * fcells, fy, ty + bny, tz + bhz, wny, whz);
+                Bz = gather2<ORDER>(ftile + 5 * fcells, fy, ty + bhy, tz + bnz, why, wnz);
+            } else {
+                float wnx[ORDER + 1], whx[ORDER + 1];
+                const int bnx = node_weights<ORDER>(o[0], wnx), bhx = half_weights<ORDER>(o[0], whx);
+                const int tx = lx + FLO, ty = ly + FLO, tz = lz + FLO;
+                const int pxy = fx * fy;
+                Ex = gather3<ORDER>(ftile + 0 * fcells, fx, pxy, tx + bhx, ty + bny, tz + bnz, whx, wny, wnz);
+                Ey = gather3<ORDER>(ftile + 1 * fcells, fx, pxy, tx + bnx, ty + bhy, tz + bnz, wnx, why, wnz);
+                Ez = gather3<ORDER>(ftile + 2 * fcells, fx, pxy, tx + bnx, ty + bny, tz + bhz, wnx, wny, whz);
+                Bx = gather3<ORDER>(ftile + 3 * fcells, fx, pxy, tx + bnx, ty + bhy, tz + bhz, wnx, why, whz);
+                By = gather3<ORDER>(ftile + 4 * fcells, fx, pxy, tx + bhx, ty + bny, tz + bhz, whx, wny, whz);
+                Bz = gather3<ORDER>(ftile + 5 * fcells, fx, pxy, tx + bhx, ty + bhy, tz + bnz, whx, why, wnz);
+            }
+
+            // ---- relativistic Boris push: half E kick, rotation, half E kick
+            {
+                const float mx = fmaf(h, Ex, ux), my = fmaf(h, Ey, uy), mz = fmaf(h, Ez, uz);
+                const float igm = rsqrt_ge1(1.0f + mx * mx + my * my + mz * mz);
+                const float tx = h * Bx * igm, ty = h * By * igm, tz = h * Bz * igm;
+                const float f = 2.0f / (1.0f + tx * tx + ty * ty + tz * tz);
+                const float sx = f * tx, sy = f * ty, sz = f * tz;
+                const float px = mx + (my * tz - mz * ty);
+                const float py = my + (mz * tx - mx * tz);
+                const float pz = mz + (mx * ty - my * tx);
+                ux = fmaf(h, Ex, mx + (py * sz - pz * sy));
+                uy = fmaf(h, Ey, my + (pz * sx - px * sz));
+                uz = fmaf(h, Ez, mz + (px * sy - py * sx));
+            }
+            const float ig = rsqrt_ge1(1.0f + ux * ux + uy * uy + uz * uz);
+            if (valid && !(ig > 0.0f)) flags |= PSC_DEV_NONFINITE;   // NaN or Inf momentum
+
+            // ---- move: xi^{n+3/2} = xi^{n+1/2} + dt u^{n+1} / (gamma dx) ---
+            int s[3] = {0, 0, 0};
+            float o1[3] = {o[0], o[1], o[2]};
+#pragma unroll
+            for (int d = (DIM == 3 ? 0 : 1); d < 3; ++d) {
+                const float cf = d == 0 ? cfx : (d == 1 ? cfy : cfz);
+                const float uu = d == 0 ? ux : (d == 1 ? uy : uz);
+                float disp = cf * uu * ig;
+                if (!(fabsf(disp) < 0.99f)) {   // CFL broken or non-finite: keep it in bounds
+                    if (valid) flags |= PSC_DEV_MOVE;
+                    disp = 0.0f;
+                }
+                const float x1 = o[d] + disp;
+                int sd = (int)floorf(x1);
+                float od = x1 - (float)sd;
+                if (od >= 1.0f) { od -= 1.0f; sd += 1; }
+                s[d] = sd;
+                o1[d] = od;
+            }
+
+            // ---- Esirkepov deposit --------------------------------------------
+            const float fxv = qw * ux * ig;   // 2-d out-of-plane current factor q w v_x
+            if constexpr (!kReduce) {
+                if (valid)
+                    deposit_lane<DIM, ORDER>(jtile, jcells, jx_, jy_, lx, ly, lz, o, s, o1, jfx, jfy, jfz, fxv);
+            } else {
+                bool frame = valid && stays<ORDER>(o[1], s[1], o1[1]) && stays<ORDER>(o[2], s[2], o1[2]);
+                if constexpr (DIM == 3) frame = frame && stays<ORDER>(o[0], s[0], o1[0]);
+
+                // support changes nodes: to the wave's queue; a full queue is
+                // deposited with its slots' lanes busy (more crossings at once
+                // than the queue holds deposit in place)
+                const bool cross = valid && !frame;
+                const uint64_t cm = __ballot(cross);
+                if (cm) {
+                    const int nq = __popcll(cm);
+                    if (nq > QS) {
+                        if (cross)
+                            deposit_lane<DIM, ORDER>(jtile, jcells, jx_, jy_, lx, ly, lz, o, s, o1, jfx, jfy, jfz,
+                                                     fxv);
+                    } else {
+                        if (qn + nq > QS) {
+                            drain(qn);
+                            qn = 0;
+                        }
+                        if (cross) {
+                            const int slot_q = qn + (int)__builtin_amdgcn_mbcnt_hi(
+                                                        (uint32_t)(cm >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)cm, 0u));
+                            const int pk = lx | (ly << 8) | (lz << 16) | ((s[0] + 1) << 24) |
+                                           ((s[1] + 1) << 26) | ((s[2] + 1) << 28);
+                            cq[slot_q] = __int_as_float(pk);
+                            constexpr int D = DIM == 3 ? 3 : 2, d0 = 3 - D;
+#pragma unroll
+                            for (int k = 0; k < D; ++k) {
+                                cq[(1 + k) * QS + slot_q] = o[d0 + k];
+                                cq[(1 + D + k) * QS + slot_q] = o1[d0 + k];
+                            }
+                            if constexpr (DIM == 2) cq[5 * QS + slot_q] = fxv;
+                        }
+                        qn += nq;
+                    }
+                }
+
+                // the rest: into this lane's frame of its cell
+                float S0y[FL], S1y[FL], S0z[FL], S1z[FL];
+                frame_weights<ORDER>(o[1], o1[1], S0y, S1y);
+                frame_weights<ORDER>(o[2], o1[2], S0z, S1z);
+                float DSy[FL], DSz[FL], Ay[FL], Az[FL], Cy[FL], Cz[FL];
 #pragma unroll
                 for (int r = 0; r < FL; ++r) {
-                    DSx[r] = (S1x[r] - S0x[r]) * on;
-                    Ax[r] = fmaf(0.5f, DSx[r], S0x[r] * on);
-                    Cx[r] = r == 0 ? DSx[0] : Cx[r - 1] + DSx[r];
+                    DSy[r] = S1y[r] - S0y[r];
+                    DSz[r] = S1z[r] - S0z[r];
+                    Ay[r] = fmaf(0.5f, DSy[r], S0y[r]);
+                    Az[r] = fmaf(0.5f, DSz[r], S0z[r]);
+                    Cy[r] = r == 0 ? DSy[0] : Cy[r - 1] + DSy[r];
+                    Cz[r] = r == 0 ? DSz[0] : Cz[r - 1] + DSz[r];
                 }
-                const int pxy = jx_ * jy_;
-                const int base = (lz + FB + JLO) * pxy + (ly + FB + JLO) * jx_ + (lx + FB + JLO);
+                const float gy = frame ? jfy : 0.0f, gz = frame ? jfz : 0.0f;
+                if constexpr (DIM == 2) {
+                    const float gx = frame ? fxv : 0.0f;
 #pragma unroll
-                for (int c = 0; c < FL; ++c)
+                    for (int a = 0; a < FL - 1; ++a) {
+                        const float cy = gy * Cy[a], cz = gz * Cz[a];
 #pragma unroll
-                    for (int b = 0; b < FL; ++b) {
-                        const float wyz = fmaf(DSy[b] * DSz[c], 1.0f / 12.0f, Ay[b] * Az[c]);
-#pragma unroll
-                        for (int a = 0; a < FL - 1; ++a) {
-                            const float v = segment_sum(jfx * Cx[a] * wyz, sg);
-                            if (put) lds_add(&Jx[base + c * pxy + b * jx_ + a], v);
+                        for (int b = 0; b < FL; ++b) {
+                            acc[b * (FL - 1) + a] = fmaf(cy, Az[b], acc[b * (FL - 1) + a]);
+                            acc[NY2 + a * FL + b] = fmaf(Ay[b], cz, acc[NY2 + a * FL + b]);
                         }
                     }
 #pragma unroll
-                for (int c = 0; c < FL; ++c)
+                    for (int a = 0; a < FL; ++a) {
+                        const float pa = gx * Ay[a], qa = gx * (1.0f / 12.0f) * DSy[a];
 #pragma unroll
-                    for (int b = 0; b < FL - 1; ++b)
+                        for (int b = 0; b < FL; ++b)
+                            acc[2 * NY2 + b * FL + a] = fmaf(pa, Az[b], fmaf(qa, DSz[b], acc[2 * NY2 + b * FL + a]));
+                    }
+                } else {
+                    const float gx = frame ? jfx : 0.0f;
+                    float S0x[FL], S1x[FL];
+                    frame_weights<ORDER>(o[0], o1[0], S0x, S1x);
+                    float DSx[FL], Ax[FL], Cx[FL];
 #pragma unroll
-                        for (int a = 0; a < FL; ++a) {
-                            const float wxz = fmaf(DSx[a] * DSz[c], 1.0f / 12.0f, Ax[a] * Az[c]);
-                            const float v = segment_sum(jfy * Cy[b] * wxz, sg);
-                            if (put) lds_add(&Jy[base + c * pxy + b * jx_ + a], v);
+                    for (int r = 0; r < FL; ++r) {
+                        DSx[r] = S1x[r] - S0x[r];
+                        Ax[r] = fmaf(0.5f, DSx[r], S0x[r]);
+                        Cx[r] = r == 0 ? DSx[0] : Cx[r - 1] + DSx[r];
+                    }
+#pragma unroll
+                    for (int c2 = 0; c2 < FL; ++c2)
+#pragma unroll
+                        for (int b = 0; b < FL; ++b) {
+                            const float wyz = fmaf(DSy[b] * DSz[c2], 1.0f / 12.0f, Ay[b] * Az[c2]);
+                            const float wxz = fmaf(DSx[b] * DSz[c2], 1.0f / 12.0f, Ax[b] * Az[c2]);
+                            const float wxy = fmaf(DSx[b] * DSy[c2], 1.0f / 12.0f, Ax[b] * Ay[c2]);
+#pragma unroll
+                            for (int a = 0; a < FL - 1; ++a) {
+                                // Jx(a; b, c2), Jy(b; a, c2), Jz(b, c2; a) in the index order of the flush
+                                acc[(c2 * FL + b) * (FL - 1) + a] =
+                                    fmaf(gx * Cx[a], wyz, acc[(c2 * FL + b) * (FL - 1) + a]);
+                                acc[NC3 + (c2 * (FL - 1) + a) * FL + b] =
+                                    fmaf(gy * Cy[a], wxz, acc[NC3 + (c2 * (FL - 1) + a) * FL + b]);
+                                acc[2 * NC3 + (a * FL + c2) * FL + b] =
+                                    fmaf(gz * Cz[a], wxy, acc[2 * NC3 + (a * FL + c2) * FL + b]);
+                            }
                         }
-#pragma unroll
-                for (int c = 0; c < FL - 1; ++c)
+                }
+            }
+
+            // ---- outputs: new cell key, move code, offsets, momenta ------------
+            if (valid) {
+                const int nlx = lx + s[0], nly = ly + s[1], nlz = lz + s[2];
+                int32_t nkey;
+                if (nlx >= 0 && nlx < hx && nly >= 0 && nly < hy && nlz >= 0 && nlz < hz) {
+                    nkey = (int32_t)kb + nlx + hx * (nly + hy * nlz);
+                } else {
+                    const int gx = DIM == 3 ? wrap(ox + nlx, R.n[0]) : 0;
+                    nkey = (int32_t)encode_key(R, gx, wrap(oy + nly, R.n[1]), wrap(oz + nlz, R.n[2]));
+                }
+                cell_out[slot] = nkey;
+                if constexpr (DIM == 3) {
+                    off_out[slot] = o1[0];
+                    off_out[cap + slot] = o1[1];
+                    off_out[2 * cap + slot] = o1[2];
+                    mc[slot] = (uint8_t)((s[0] + 1) + 3 * (s[1] + 1) + 9 * (s[2] + 1));
+                } else {
+                    off_out[slot] = o1[1];
+                    off_out[cap + slot] = o1[2];
+                    mc[slot] = (uint8_t)((s[1] + 1) + 3 * (s[2] + 1));
+                }
+                u_out[slot] = ux;
+                u_out[cap + slot] = uy;
+                u_out[2 * cap + slot] = uz;
+                if (id_out) id_out[slot] = idv;
+            }
+        }
+
+        // ---- the round's frames: segmented sums over lanes of one cell ------
+        if constexpr (kReduce) {
+            const RowScan rs = row_scan_setup<SW>(len > 0 ? c : -1);
+            row_scan<SW>(acc, rs);
+            if (rs.tail && len > 0) {
+                if constexpr (DIM == 2) {
+                    const int base = (lz + FB + JLO) * jy_ + (ly + FB + JLO);
 #pragma unroll
                     for (int b = 0; b < FL; ++b)
 #pragma unroll
-                        for (int a = 0; a < FL; ++a) {
-                            const float wxy = fmaf(DSx[a] * DSy[b], 1.0f / 12.0f, Ax[a] * Ay[b]);
-                            const float v = segment_sum(jfz * Cz[c] * wxy, sg);
-                            if (put) lds_add(&Jz[base + c * pxy + b * jx_ + a], v);
-                        }
+                        for (int a = 0; a < FL - 1; ++a) lds_add(&Jy[base + b * jy_ + a], acc[b * (FL - 1) + a]);
+#pragma unroll
+                    for (int b = 0; b < FL - 1; ++b)
+#pragma unroll
+                        for (int a = 0; a < FL; ++a) lds_add(&Jz[base + b * jy_ + a], acc[NY2 + b * FL + a]);
+#pragma unroll
+                    for (int b = 0; b < FL; ++b)
+#pragma unroll
+                        for (int a = 0; a < FL; ++a) lds_add(&Jx[base + b * jy_ + a], acc[2 * NY2 + b * FL + a]);
+                } else {
+                    const int pxy = jx_ * jy_;
+                    const int base = (lz + FB + JLO) * pxy + (ly + FB + JLO) * jx_ + (lx + FB + JLO);
+#pragma unroll
+                    for (int c2 = 0; c2 < FL; ++c2)
+#pragma unroll
+                        for (int b = 0; b < FL; ++b)
+#pragma unroll
+                            for (int a = 0; a < FL - 1; ++a)
+                                lds_add(&Jx[base + c2 * pxy + b * jx_ + a], acc[(c2 * FL + b) * (FL - 1) + a]);
+#pragma unroll
+                    for (int c2 = 0; c2 < FL; ++c2)
+#pragma unroll
+                        for (int b = 0; b < FL - 1; ++b)
+#pragma unroll
+                            for (int a = 0; a < FL; ++a)
+                                lds_add(&Jy[base + c2 * pxy + b * jx_ + a], acc[NC3 + (c2 * (FL - 1) + b) * FL + a]);
+#pragma unroll
+                    for (int c2 = 0; c2 < FL - 1; ++c2)
+#pragma unroll
+                        for (int b = 0; b < FL; ++b)
+#pragma unroll
+                            for (int a = 0; a < FL; ++a)
+                                lds_add(&Jz[base + c2 * pxy + b * jx_ + a], acc[2 * NC3 + (c2 * FL + b) * FL + a]);
+                }
             }
         }
-
-        // ---- new cell key and move code ------------------------------------
-        if (valid) {
-            const int nlx = lx + s[0], nly = ly + s[1], nlz = lz + s[2];
-            int32_t nkey;
-            if (nlx >= 0 && nlx < hx && nly >= 0 && nly < hy && nlz >= 0 && nlz < hz) {
-                nkey = (int32_t)kb + nlx + hx * (nly + hy * nlz);
-            } else {
-                const int gx = DIM == 3 ? wrap(ox + nlx, R.n[0]) : 0;
-                nkey = (int32_t)encode_key(R, gx, wrap(oy + nly, R.n[1]), wrap(oz + nlz, R.n[2]));
-            }
-            cell_out[i] = nkey;
-            if constexpr (DIM == 3) {
-                off_out[i] = o1[0];
-                off_out[cap + i] = o1[1];
-                off_out[2 * cap + i] = o1[2];
-                mc[i] = (uint8_t)((s[0] + 1) + 3 * (s[1] + 1) + 9 * (s[2] + 1));
-            } else {
-                off_out[i] = o1[1];
-                off_out[cap + i] = o1[2];
-                mc[i] = (uint8_t)((s[1] + 1) + 3 * (s[2] + 1));
-            }
-            u_out[i] = ux;
-            u_out[cap + i] = uy;
-            u_out[2 * cap + i] = uz;
-            if (id_out) id_out[i] = idv;
-        }
+    }
+    if constexpr (kReduce) {
+        if (qn) drain(qn);
     }
     if (flags) atomicOr(err, flags);
     __syncthreads();
@@ -555,16 +804,16 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
 // round-robin over the 8 XCDs; give each XCD a contiguous range of items so
 // that the chunks of a patch share one L2.
 template <int DIM, int ORDER, int NT>
-__global__ void __launch_bounds__(NT) k_push(const RunDev *__restrict__ runs, const Unit *__restrict__ units,
+__global__ void __launch_bounds__(NT) PSC_OCCUPANCY k_push(const RunDev *__restrict__ runs, const Unit *__restrict__ units,
                                                  const int32_t *__restrict__ item_start, int n_units,
-                                                 int chunk, int front, int cs_sel, int use_perm,
+                                                 int chunk, int front, int cs_sel, int use_perm, int K,
                                                  uint32_t *__restrict__ err) {
     extern __shared__ float lds[];
     const int nb = gridDim.x;
     const int item = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
     if (item >= item_start[n_units]) return;
     push_item<DIM, ORDER, NT>(runs, units, item_start, unit_of_item(item_start, n_units, item), item, chunk, front,
-                          cs_sel, use_perm, err, lds);
+                              cs_sel, use_perm, K, err, lds);
 }
 
 // launch mode 1: persistent workgroups pull items from 8 queues, one per
@@ -572,10 +821,10 @@ __global__ void __launch_bounds__(NT) k_push(const RunDev *__restrict__ runs, co
 // neighbouring patches), and steal from the other queues when theirs is
 // empty.  Every workgroup leaves once all queues are drained.
 template <int DIM, int ORDER, int NT>
-__global__ void __launch_bounds__(NT) k_push_queue(const RunDev *__restrict__ runs,
+__global__ void __launch_bounds__(NT) PSC_OCCUPANCY k_push_queue(const RunDev *__restrict__ runs,
                                                        const Unit *__restrict__ units,
                                                        const int32_t *__restrict__ item_start, int n_units,
-                                                       int chunk, int front, int cs_sel, int use_perm,
+                                                       int chunk, int front, int cs_sel, int use_perm, int K,
                                                        uint32_t *__restrict__ err, int32_t *__restrict__ queue) {
     extern __shared__ float lds[];
     __shared__ int s_item;
@@ -591,7 +840,7 @@ __global__ void __launch_bounds__(NT) k_push_queue(const RunDev *__restrict__ ru
             __syncthreads();
             if (item >= qe) break;
             push_item<DIM, ORDER, NT>(runs, units, item_start, unit_of_item(item_start, n_units, item), item, chunk,
-                                  front, cs_sel, use_perm, err, lds);
+                                      front, cs_sel, use_perm, K, err, lds);
         }
     }
 }
@@ -599,16 +848,16 @@ __global__ void __launch_bounds__(NT) k_push_queue(const RunDev *__restrict__ ru
 // launch mode 2: persistent workgroup w processes the contiguous units
 // [part[w], part[w+1]) chosen by the load-balancing partition.
 template <int DIM, int ORDER, int NT>
-__global__ void __launch_bounds__(NT) k_push_part(const RunDev *__restrict__ runs,
+__global__ void __launch_bounds__(NT) PSC_OCCUPANCY k_push_part(const RunDev *__restrict__ runs,
                                                       const Unit *__restrict__ units,
                                                       const int32_t *__restrict__ item_start, int n_units,
-                                                      int chunk, int front, int cs_sel, int use_perm,
+                                                      int chunk, int front, int cs_sel, int use_perm, int K,
                                                       uint32_t *__restrict__ err, const int32_t *__restrict__ part) {
     extern __shared__ float lds[];
     const int u0 = part[blockIdx.x], u1 = min(part[blockIdx.x + 1], n_units);
     for (int u = u0; u < u1; ++u)
         for (int item = item_start[u]; item < item_start[u + 1]; ++item)
-            push_item<DIM, ORDER, NT>(runs, units, item_start, u, item, chunk, front, cs_sel, use_perm, err, lds);
+            push_item<DIM, ORDER, NT>(runs, units, item_start, u, item, chunk, front, cs_sel, use_perm, K, err, lds);
 }
 
 template <int DIM, int ORDER, int NT>
@@ -619,15 +868,17 @@ static hipError_t launch_push_t(const Launch &L, const Unit *units, int n_units,
                        cs_sel, item_start, pm.queue);
     if (pm.mode == 1) {
         hipLaunchKernelGGL((k_push_queue<DIM, ORDER, NT>), dim3((unsigned)pm.workers), dim3(NT), lds, L.stream,
-                           L.runs_dev, units, item_start, n_units, chunk, front, cs_sel, use_perm, L.err, pm.queue);
+                           L.runs_dev, units, item_start, n_units, chunk, front, cs_sel, use_perm, pm.run, L.err,
+                           pm.queue);
     } else if (pm.mode == 2) {
         hipLaunchKernelGGL((k_push_part<DIM, ORDER, NT>), dim3((unsigned)pm.workers), dim3(NT), lds, L.stream,
-                           L.runs_dev, units, item_start, n_units, chunk, front, cs_sel, use_perm, L.err, pm.part);
+                           L.runs_dev, units, item_start, n_units, chunk, front, cs_sel, use_perm, pm.run, L.err,
+                           pm.part);
     } else {
         int64_t grid = (max_items + 7) / 8 * 8;
         if (grid < 8) grid = 8;
         hipLaunchKernelGGL((k_push<DIM, ORDER, NT>), dim3((unsigned)grid), dim3(NT), lds, L.stream, L.runs_dev,
-                           units, item_start, n_units, chunk, front, cs_sel, use_perm, L.err);
+                           units, item_start, n_units, chunk, front, cs_sel, use_perm, pm.run, L.err);
     }
     return hipGetLastError();
 }
@@ -638,6 +889,9 @@ static hipError_t launch_push_nt(const Launch &L, const Unit *units, int n_units
                                  const PushMode &pm) {
     if (pm.threads == 512)
         return launch_push_t<DIM, ORDER, 512>(L, units, n_units, item_start, max_items, chunk, front, cs_sel,
+                                              use_perm, lds, pm);
+    if (pm.threads == 384)
+        return launch_push_t<DIM, ORDER, 384>(L, units, n_units, item_start, max_items, chunk, front, cs_sel,
                                               use_perm, lds, pm);
     return launch_push_t<DIM, ORDER, 256>(L, units, n_units, item_start, max_items, chunk, front, cs_sel, use_perm,
                                           lds, pm);
@@ -661,6 +915,32 @@ hipError_t launch_push(const Launch &L, const Unit *units_dev, int n_units, int3
     return hipErrorInvalidValue;
 }
 
+// resident workgroups per compute unit of the persistent particle kernel of
+// a launch mode (registers and LDS both counted), 0 on failure
+template <int DIM, int ORDER, int NT>
+static int push_occupancy_t(int mode, size_t lds) {
+    int n = 0;
+    hipError_t e;
+    if (mode == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_push_part<DIM, ORDER, NT>, NT, lds);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_push_queue<DIM, ORDER, NT>, NT, lds);
+    return e == hipSuccess ? n : 0;
+}
+
+template <int DIM, int ORDER>
+static int push_occupancy_nt(int mode, int threads, size_t lds) {
+    if (threads == 512) return push_occupancy_t<DIM, ORDER, 512>(mode, lds);
+    if (threads == 384) return push_occupancy_t<DIM, ORDER, 384>(mode, lds);
+    return push_occupancy_t<DIM, ORDER, 256>(mode, lds);
+}
+
+int push_occupancy(int dim, int order, int mode, int threads, size_t lds) {
+    if (dim == 2 && order == 1) return push_occupancy_nt<2, 1>(mode, threads, lds);
+    if (dim == 2 && order == 2) return push_occupancy_nt<2, 2>(mode, threads, lds);
+    if (dim == 3 && order == 1) return push_occupancy_nt<3, 1>(mode, threads, lds);
+    if (dim == 3 && order == 2) return push_occupancy_nt<3, 2>(mode, threads, lds);
+    return 0;
+}
+
 // particles per unit (for the load-balancing partition)
 __global__ void k_unit_counts(const RunDev *__restrict__ runs, const Unit *__restrict__ units, int n_units,
                               int cs_sel, int32_t *__restrict__ out) {
@@ -682,15 +962,18 @@ hipError_t launch_unit_counts(const Launch &L, const Unit *units, int n_units, i
     return hipGetLastError();
 }
 
-// LDS bytes the particle kernel of a run needs
-size_t push_lds_bytes(int dim, int order, const int P[3]) {
+// LDS bytes the particle kernel of a run needs with `threads` per workgroup
+size_t push_lds_bytes(int dim, int order, const int P[3], int threads) {
     const int fx = dim == 3 ? P[0] + field_lo(order) + field_hi(order) : 1;
     const int fy = P[1] + field_lo(order) + field_hi(order);
     const int fz = P[2] + field_lo(order) + field_hi(order);
     const int jx = dim == 3 ? P[0] + cur_lo(order) + cur_hi(order) : 1;
     const int jy = P[1] + cur_lo(order) + cur_hi(order);
     const int jz = P[2] + cur_lo(order) + cur_hi(order);
-    return sizeof(float) * (6 * (size_t)fx * fy * fz + 3 * (size_t)jx * jy * jz);
+    const size_t queue = (size_t)(threads / 64) * kQueueSlots * cross_words(dim);
+    const size_t npc = (size_t)(dim == 3 ? P[0] : 1) * P[1] * P[2];
+    const size_t table = 2 * (npc + 1) + threads / 64;   // cell starts, run prefix, wave sums
+    return sizeof(float) * (6 * (size_t)fx * fy * fz + 3 * (size_t)jx * jy * jz + queue + table);
 }
 
 }  // namespace psc

@@ -35,41 +35,125 @@ __device__ __forceinline__ int find_seg(const int64_t *base, int n, int64_t c) {
 
 constexpr int kSortBlock = 256;
 
+using gptr_i32 = __attribute__((address_space(1))) int32_t *;
+
+// Count and scatter: a workgroup owns 256 consecutive old cells of one
+// segment, each of its four waves 64 of them (lane q: cell cw + q), i.e. one
+// contiguous range of particles (the buffer is ordered by old cell).  The
+// wave walks that range 64 particles at a time with coalesced loads.  Each
+// lane finds its particle's cell by binary search over the cells' first
+// indices in LDS; its rank among the earlier particles of the same cell and
+// move code is the population count of the code's ballot restricted to the
+// lanes of its cell below it; the last such lane advances the (cell, code)
+// counter kept in LDS.  Sort block b lies in scan block b/8 of the same
+// segment, whose table gives the segment.
+constexpr int kSortCells = 256;
+static_assert(kScanBlock == 8 * kSortCells, "eight sort blocks per scan block");
+
+struct CellBlock {
+    const RunDev *R;
+    const SpeciesDev *S;
+    int64_t cw, ce;   // this wave's cells [cw, ce)
+};
+
+__device__ __forceinline__ CellBlock cell_block(const RunDev *runs, const ScanSeg *segs, const int32_t *block_seg,
+                                                const int32_t *seg_run, const int32_t *seg_sp) {
+    CellBlock B;
+    const int sg = block_seg[blockIdx.x >> 3];
+    B.R = &runs[seg_run[sg]];
+    B.S = &B.R->sp[seg_sp[sg]];
+    B.cw = ((int64_t)blockIdx.x - 8 * segs[sg].block0) * kSortCells + 64 * (threadIdx.x >> 6);
+    B.ce = B.cw + 64 < B.R->ncell ? B.cw + 64 : B.R->ncell;
+    return B;
+}
+
+// Walk the wave's particles: for each, f(i, q, m, rank, last) with q its
+// cell (0..63 within the wave), m its move code, rank its index among the
+// earlier particles of (q, m) in this wave, last whether it is the final one
+// of (q, m) in the current group of 64.  sb: the wave's 65 first indices.
+template <int M, typename F>
+__device__ __forceinline__ void walk_cells(const int32_t *sb, int nw, int32_t pb, int32_t pe,
+                                           const uint8_t *__restrict__ mc, uint32_t &flags, F &&f) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int32_t i0 = pb; i0 < pe; i0 += 64) {
+        const int32_t i = i0 + lane;
+        const bool valid = i < pe;
+        int m = -1, q = -1;
+        if (valid) {
+            m = mc[i];
+            if (m >= M) { flags |= PSC_DEV_MOVE; m = M / 2; }
+            int a = 0, b = nw;   // sb[a] <= i < sb[b]
+            while (b - a > 1) {
+                const int h = (a + b) >> 1;
+                if (sb[h] <= i) a = h;
+                else b = h;
+            }
+            q = a;
+        }
+        // lanes of my cell: a contiguous range starting at the last head <= me
+        const int left = __shfl_up(q, 1, 64);
+        const uint64_t heads = __ballot(lane == 0 || left != q);
+        const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
+        const int s0 = 63 - __clzll(heads & upto);
+        const uint64_t after = heads & ~upto;   // heads above me
+        const int e1 = after ? __ffsll((unsigned long long)after) - 1 : 64;   // one past my cell's last lane
+        const uint64_t mine = (e1 == 64 ? ~0ull : ((1ull << e1) - 1)) & ~((1ull << s0) - 1);
+        uint32_t lo = 0, hi = 0;   // lane k: ballot of code k
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const uint64_t bk = __ballot(m == k);
+            if (lane == k) {
+                lo = (uint32_t)bk;
+                hi = (uint32_t)(bk >> 32);
+            }
+        }
+        const int mm = valid ? m : 0;
+        const uint64_t bm = ((uint64_t)(uint32_t)__shfl((int)hi, mm, 64) << 32) | (uint32_t)__shfl((int)lo, mm, 64);
+        const uint64_t grp = bm & mine;
+        const int rank = __popcll(grp & below);
+        const bool last = (grp & ~upto) == 0;
+        if (valid) f(i, q, m, rank, last);
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 // per old cell: count particles per move code
 template <int DIM>
-__global__ void __launch_bounds__(kSortBlock) k_sort_count(const RunDev *__restrict__ runs,
-                                                           const int64_t *__restrict__ seg_base,
+__global__ void __launch_bounds__(kSortCells) k_sort_count(const RunDev *__restrict__ runs,
+                                                           const ScanSeg *__restrict__ segs,
+                                                           const int32_t *__restrict__ block_seg,
                                                            const int32_t *__restrict__ seg_run,
-                                                           const int32_t *__restrict__ seg_sp, int n_segs,
-                                                           int64_t total, int cs_sel, uint32_t *err) {
+                                                           const int32_t *__restrict__ seg_sp, int cs_sel,
+                                                           uint32_t *err) {
     constexpr int M = DIM == 3 ? 27 : 9;
-    const int64_t c = (int64_t)blockIdx.x * kSortBlock + threadIdx.x;
-    if (c >= total) return;
-    const int sg = find_seg(seg_base, n_segs, c);
-    const RunDev &R = runs[seg_run[sg]];
-    const SpeciesDev &S = R.sp[seg_sp[sg]];
-    const int64_t o = c - seg_base[sg];
-    // counters live in registers: each particle's code is matched against
-    // all M codes by unrolled compares (no dependent LDS traffic)
-    int32_t cnt[M];
-#pragma unroll
-    for (int m = 0; m < M; ++m) cnt[m] = 0;
+    __shared__ int32_t tab_all[4][64 * M];
+    __shared__ int32_t sb_all[4][65];
+    const CellBlock B = cell_block(runs, segs, block_seg, seg_run, seg_sp);
+    if (B.cw >= B.ce) return;   // whole wave: past the segment's cells
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int32_t *tab = tab_all[wave], *sb = sb_all[wave];
+    const SpeciesDev &S = *B.S;
     const int32_t *cs = S.cs[cs_sel];
-    const int32_t b = cs[o], e = cs[o + 1];
-    const uint8_t *__restrict__ mc = S.mc;
+    const int nw = (int)(B.ce - B.cw);
+    sb[lane] = cs[B.cw + (lane < nw ? lane : nw)];
+    if (lane == 0) sb[64] = cs[B.ce];
+#pragma unroll
+    for (int m = 0; m < M; ++m) tab[m * 64 + lane] = 0;
+    __builtin_amdgcn_wave_barrier();
     uint32_t flags = 0;
-    for (int32_t i = b; i < e; ++i) {
-        int m = mc[i];
-        if (m >= M) { flags |= PSC_DEV_MOVE; m = M / 2; }
+    walk_cells<M>(sb, nw, sb[0], sb[nw], S.mc, flags, [&](int32_t, int q, int m, int rank, bool last) {
+        if (last) tab[m * 64 + q] += rank + 1;
+    });
+    __builtin_amdgcn_wave_barrier();
+    if (lane < nw) {
+        const int64_t nc = B.R->ncell;
 #pragma unroll
-        for (int q = 0; q < M; ++q) cnt[q] += q == m;
-    }
-    const int64_t nc = R.ncell;
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-        int32_t v = cnt[m];
-        if (v > 65535) { flags |= PSC_DEV_OVERFULL; v = 65535; }
-        S.cnt[m * nc + o] = (uint16_t)v;
+        for (int m = 0; m < M; ++m) {
+            int32_t v = tab[m * 64 + lane];
+            if (v > 65535) { flags |= PSC_DEV_OVERFULL; v = 65535; }
+            S.cnt[m * nc + B.cw + lane] = (uint16_t)v;
+        }
     }
     if (flags) atomicOr(err, flags);
 }
@@ -114,54 +198,56 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_prefix(const RunDev *__rest
     S.tot[n] = tot;
 }
 
-// per old cell: stable positions of its particles
+// per old cell: stable positions of its particles.  Lane q sets up the first
+// position of every move code of its cell in LDS; the walk then writes
+// perm[position] = index for 64 consecutive particles at a time, so the
+// particles that stay (one code, consecutive positions) are stored coalesced.
 template <int DIM>
-__global__ void __launch_bounds__(kSortBlock) k_sort_scatter(const RunDev *__restrict__ runs,
-                                                             const int64_t *__restrict__ seg_base,
+__global__ void __launch_bounds__(kSortCells) k_sort_scatter(const RunDev *__restrict__ runs,
+                                                             const ScanSeg *__restrict__ segs,
+                                                             const int32_t *__restrict__ block_seg,
                                                              const int32_t *__restrict__ seg_run,
-                                                             const int32_t *__restrict__ seg_sp, int n_segs,
-                                                             int64_t total, int cs_sel, uint32_t *err) {
+                                                             const int32_t *__restrict__ seg_sp, int cs_sel,
+                                                             uint32_t *err) {
     constexpr int M = DIM == 3 ? 27 : 9;
-    const int64_t c = (int64_t)blockIdx.x * kSortBlock + threadIdx.x;
-    if (c >= total) return;
-    const int sg = find_seg(seg_base, n_segs, c);
-    const RunDev &R = runs[seg_run[sg]];
-    const SpeciesDev &S = R.sp[seg_sp[sg]];
-    const int64_t o = c - seg_base[sg];
+    __shared__ int32_t tab_all[4][64 * M];
+    __shared__ int32_t sb_all[4][65];
+    const CellBlock B = cell_block(runs, segs, block_seg, seg_run, seg_sp);
+    if (B.cw >= B.ce) return;   // whole wave
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int32_t *tab = tab_all[wave], *sb = sb_all[wave];
+    const RunDev &R = *B.R;
+    const SpeciesDev &S = *B.S;
     const int64_t nc = R.ncell;
     const int32_t *cs_old = S.cs[cs_sel];
     const int32_t *cs_new = S.cs[1 - cs_sel];
-    const int32_t b = cs_old[o], e = cs_old[o + 1];
-    if (b == e) return;
-    int g[3];
-    decode_key(R, o, g);
-    // next output position per move code, in registers
-    int32_t pos[M];
+    const int nw = (int)(B.ce - B.cw);
+    sb[lane] = cs_old[B.cw + (lane < nw ? lane : nw)];
+    if (lane == 0) sb[64] = cs_old[B.ce];
+    if (lane < nw) {
+        const int64_t o = B.cw + lane;
+        int g[3];
+        decode_key(R, o, g);
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-        int d[3];
-        move_delta(DIM, m, d);
-        const int dx = DIM == 3 ? wrap(g[0] + d[0], R.n[0]) : 0;
-        const int64_t dst = encode_key(R, dx, wrap(g[1] + d[1], R.n[1]), wrap(g[2] + d[2], R.n[2]));
-        pos[m] = cs_new[dst] + S.pre[m * nc + o];
-    }
-    const uint8_t *__restrict__ mc = S.mc;
-    int32_t *__restrict__ perm = S.perm;
-    const int32_t n = (int32_t)S.n;
-    bool bad = false;
-    for (int32_t i = b; i < e; ++i) {
-        int m = mc[i];
-        if (m >= M) m = M / 2;
-        int32_t p = 0;
-#pragma unroll
-        for (int q = 0; q < M; ++q) {
-            const bool hit = q == m;
-            p = hit ? pos[q] : p;
-            pos[q] += hit;
+        for (int m = 0; m < M; ++m) {
+            int d[3];
+            move_delta(DIM, m, d);
+            const int dx = DIM == 3 ? wrap(g[0] + d[0], R.n[0]) : 0;
+            const int64_t dst = encode_key(R, dx, wrap(g[1] + d[1], R.n[1]), wrap(g[2] + d[2], R.n[2]));
+            tab[m * 64 + lane] = cs_new[dst] + S.pre[m * nc + o];
         }
+    }
+    __builtin_amdgcn_wave_barrier();
+    const gptr_i32 perm = (gptr_i32)S.perm;
+    const int32_t n = (int32_t)S.n;
+    uint32_t flags = 0;
+    bool bad = false;
+    walk_cells<M>(sb, nw, sb[0], sb[nw], S.mc, flags, [&](int32_t i, int q, int m, int rank, bool last) {
+        const int32_t p = tab[m * 64 + q] + rank;
         if (p >= 0 && p < n) perm[p] = i;   // out of range only after a counter overflow
         else bad = true;
-    }
+        if (last) tab[m * 64 + q] = p + 1;
+    });
     if (bad) atomicOr(err, PSC_DEV_OVERFULL);
 }
 
@@ -274,25 +360,26 @@ hipError_t launch_sort(const Launch &L, const int64_t *seg_base, const int32_t *
     const unsigned grid = (unsigned)((total + kSortBlock - 1) / kSortBlock);
     // scan_tmp: [0, n_scan_blocks) block sums; then the block -> segment table
     const int32_t *block_seg = scan_tmp + n_scan_blocks;
+    const unsigned cgrid = (unsigned)(8 * n_scan_blocks);   // 256-cell blocks
     if (dim == 3) {
-        hipLaunchKernelGGL(k_sort_count<3>, dim3(grid), dim3(kSortBlock), 0, L.stream, L.runs_dev, seg_base, seg_run,
-                           seg_sp, n_segs, total, cs_sel, L.err);
+        hipLaunchKernelGGL(k_sort_count<3>, dim3(cgrid), dim3(kSortCells), 0, L.stream, L.runs_dev, segs_dev,
+                           block_seg, seg_run, seg_sp, cs_sel, L.err);
         hipLaunchKernelGGL(k_sort_prefix<3>, dim3(grid), dim3(kSortBlock), 0, L.stream, L.runs_dev, seg_base,
                            seg_run, seg_sp, n_segs, total, L.err);
     } else {
-        hipLaunchKernelGGL(k_sort_count<2>, dim3(grid), dim3(kSortBlock), 0, L.stream, L.runs_dev, seg_base, seg_run,
-                           seg_sp, n_segs, total, cs_sel, L.err);
+        hipLaunchKernelGGL(k_sort_count<2>, dim3(cgrid), dim3(kSortCells), 0, L.stream, L.runs_dev, segs_dev,
+                           block_seg, seg_run, seg_sp, cs_sel, L.err);
         hipLaunchKernelGGL(k_sort_prefix<2>, dim3(grid), dim3(kSortBlock), 0, L.stream, L.runs_dev, seg_base,
                            seg_run, seg_sp, n_segs, total, L.err);
     }
     hipError_t e = launch_scan(segs_dev, n_segs, n_scan_blocks, block_seg, scan_tmp, L.stream);
     if (e != hipSuccess) return e;
     if (dim == 3)
-        hipLaunchKernelGGL(k_sort_scatter<3>, dim3(grid), dim3(kSortBlock), 0, L.stream, L.runs_dev, seg_base,
-                           seg_run, seg_sp, n_segs, total, cs_sel, L.err);
+        hipLaunchKernelGGL(k_sort_scatter<3>, dim3(cgrid), dim3(kSortCells), 0, L.stream, L.runs_dev, segs_dev,
+                           block_seg, seg_run, seg_sp, cs_sel, L.err);
     else
-        hipLaunchKernelGGL(k_sort_scatter<2>, dim3(grid), dim3(kSortBlock), 0, L.stream, L.runs_dev, seg_base,
-                           seg_run, seg_sp, n_segs, total, cs_sel, L.err);
+        hipLaunchKernelGGL(k_sort_scatter<2>, dim3(cgrid), dim3(kSortCells), 0, L.stream, L.runs_dev, segs_dev,
+                           block_seg, seg_run, seg_sp, cs_sel, L.err);
     return hipGetLastError();
 }
 

@@ -14,7 +14,8 @@ from typing import List, Optional, Sequence, Union
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpsc.so")
+# the in-tree build; PSC_LIBRARY may name another build of the same sources
+LIB_PATH = os.environ.get("PSC_LIBRARY") or os.path.join(HERE, "libpsc.so")
 
 MAX_SPECIES = 4
 B_HALF, E_FULL = 0, 1
@@ -91,7 +92,7 @@ def load_library(path: str = LIB_PATH):
     L.psc_diagnostics.argtypes = [vp, vp, vp, vp]
     L.psc_get_perm.argtypes = [vp, i32, i32, vp, vp]
     L.psc_adjoint_step.argtypes = [vp, C.POINTER(AdjFwd), C.POINTER(AdjState), vp]
-    L.psc_set_launch.argtypes = [vp, i32, i32, i32, i32, vp]
+    L.psc_set_launch.argtypes = [vp, i32, i32, i32, i32, i32, vp]
     L.psc_balance.argtypes = [vp, C.c_double, vp]
     L.psc_partition.argtypes = [C.POINTER(C.c_double), i32, C.POINTER(C.c_double), i32, C.POINTER(C.c_int32)]
     L.psc_check.argtypes = [vp, vp, C.POINTER(C.c_uint32), i32]
@@ -250,8 +251,8 @@ class PscSim:
     def step(self, nsteps: int = 1, use_graph: bool = False):
         self._call(self.L.psc_step(self.ctx, int(nsteps), int(use_graph), self._stream()))
 
-    def set_launch(self, mode: int, chunk: int = 0, workers: int = 0, threads: int = 0):
-        self._call(self.L.psc_set_launch(self.ctx, int(mode), int(chunk), int(workers), int(threads),
+    def set_launch(self, mode: int, chunk: int = 0, workers: int = 0, threads: int = 0, run: int = 0):
+        self._call(self.L.psc_set_launch(self.ctx, int(mode), int(chunk), int(workers), int(threads), int(run),
                                          self._stream()))
 
     def balance(self, cell_cost: float = 1.0):
