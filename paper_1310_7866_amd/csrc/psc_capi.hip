@@ -661,12 +661,16 @@ psc_status psc_diagnostics(psc_ctx *ctx, double *out_dev, double *gauss_dev, voi
 
 psc_status psc_partition(const double *L, int n_patches, const double *C, int n_ranks, int32_t *N) {
     if (!L || !C || !N || n_patches < 0 || n_ranks < 1) return PSC_ERR_INVALID;
-    // App. A: walk the patches along the curve, filling rank r up to its
-    // share T_hat * C_r of the total load; at the patch that crosses the
-    // target keep it on r or start r + 1 with it, whichever lands closer to
-    // the target (a rank keeps at least one patch); once only as many patches
-    // as ranks remain, each remaining rank gets one.  The last rank takes the
-    // rest.
+    // App. A: walk the patches along the curve, tentatively adding each to
+    // rank r.  The appendix never resets the running load when it moves to
+    // the next rank, so the running load is cumulative and is compared with
+    // the cumulative target T_hat * (C_0 + ... + C_r) of ranks 0..r (a
+    // per-rank target against a cumulative load could not work; a per-rank
+    // target with a per-rank load would pass every boundary's rounding on
+    // to the last rank).  At the patch that crosses the target it stays on r
+    // or opens r + 1, whichever leaves the boundary closer to the target (a
+    // rank keeps at least one patch); once only as many patches as ranks
+    // remain, each remaining rank gets one.  The last rank takes the rest.
     double ltot = 0.0, ctot = 0.0;
     for (int p = 0; p < n_patches; ++p) ltot += L[p];
     for (int r = 0; r < n_ranks; ++r) {
@@ -676,24 +680,23 @@ psc_status psc_partition(const double *L, int n_patches, const double *C, int n_
     }
     const double that = ltot / ctot;
     int r = 0, ncur = 0;
-    double lcur = 0.0;
+    double lcur = 0.0, tdone = 0.0;   // cumulative load so far, cumulative target of ranks < r
     for (int p = 0; p < n_patches; ++p) {
         lcur += L[p];
         ncur += 1;
         if (r < n_ranks - 1) {
-            const double tcur = that * C[r];
+            const double tcur = tdone + that * C[r];
             if (lcur > tcur || n_ranks - r >= n_patches - p) {
                 const double above = lcur - tcur;
                 const double below = tcur - (lcur - L[p]);
                 if (above > below && ncur > 1) {
                     N[r] = ncur - 1;   // patch p opens the next rank
                     ncur = 1;
-                    lcur = L[p];
                 } else {
                     N[r] = ncur;       // patch p closes this rank
                     ncur = 0;
-                    lcur = 0.0;
                 }
+                tdone = tcur;
                 ++r;
             }
         }

@@ -1,12 +1,16 @@
 """The greedy partition of App. A ("Load balancing algorithm").
 
-Checked against a direct Python transcription of the appendix's description
-(walk the space-filling curve, fill each rank up to T_hat * C_r, keep or pass
-on the boundary patch by which side lands closer to the target, give one
-patch to each remaining rank once patches run short, the last rank takes the
-rest) and against the properties any such partition has: every patch is
-assigned once, in order, and with at least as many patches as ranks no rank
-is empty.  Pure host code: runs without a GPU.
+Checked against a direct Python transcription of the appendix (walk the
+space-filling curve adding patches to rank r; the running load is never reset
+between ranks, so it is compared with the cumulative target T_hat * (C_0 +
+... + C_r); at the crossing patch keep it on r or open r + 1 with it,
+whichever lands closer to the target; give one patch to each remaining rank
+once patches run short; the last rank takes the rest) and against the
+properties such a partition has: every patch is assigned once, in order,
+with at least as many patches as ranks no rank is empty, every boundary lies
+within half a patch of its cumulative target, so no rank (the last one
+included) is off its target by more than one patch.  Pure host code: runs
+without a GPU.
 """
 import numpy as np
 import pytest
@@ -18,19 +22,20 @@ def reference(L, C):
     P, R = len(L), len(C)
     T = sum(L) / sum(C)
     N = [0] * R
-    r, n, load = 0, 0, 0.0
+    r, n, load, target = 0, 0, 0.0, 0.0
     for p in range(P):
         load += L[p]
         n += 1
         if r < R - 1:
-            target = T * C[r]
-            if load > target or R - r >= P - p:
-                over = load - target
-                under = target - (load - L[p])
+            t = target + T * C[r]
+            if load > t or R - r >= P - p:
+                over = load - t
+                under = t - (load - L[p])
                 if over > under and n > 1:
-                    N[r], n, load = n - 1, 1, L[p]
+                    N[r], n = n - 1, 1
                 else:
-                    N[r], n, load = n, 0, 0.0
+                    N[r], n = n, 0
+                target = t
                 r += 1
         if p == P - 1:
             N[R - 1] += n
@@ -70,7 +75,24 @@ def test_partition_uniform_and_skewed():
     T = L.sum() / C.sum()               # 610 / 70
     assert abs(got[0] - 60 * T) <= 0.5  # 523 patches
     loads = np.add.reduceat(L, np.concatenate([[0], np.cumsum(got)[:-1]]))
-    # each rank but the last lands within half a patch of its target; the
-    # greedy walk leaves the accumulated rounding to the last rank
-    assert np.all(np.abs(loads[:-1] - T * C[:-1]) <= 0.5 * L.max() + 1e-9)
+    assert np.all(np.abs(loads - T * C) <= L.max() + 1e-9)
     assert got.sum() == L.size
+
+
+@pytest.mark.parametrize("R", [7, 256, 300, 512])
+def test_partition_does_not_drift(R):
+    """Uneven loads over many ranks: boundaries stay within half a patch of
+    the cumulative targets, so the last rank is not left with the rounding of
+    all earlier boundaries."""
+    _lib_or_skip()
+    rng = np.random.default_rng(R)
+    L = rng.uniform(40000, 110000, 1024)
+    C = np.ones(R)
+    got = psc.partition(L, C)
+    assert got.sum() == L.size and (got >= 1).all()
+    bounds = np.cumsum(got)[:-1]
+    cum = np.cumsum(L)[bounds - 1]
+    T = L.sum() / C.sum()
+    assert np.all(np.abs(cum - T * np.arange(1, R)) <= 0.5 * L.max() + 1e-6)
+    loads = np.add.reduceat(L, np.concatenate([[0], bounds]))
+    assert loads.max() <= T + L.max() + 1e-6
