@@ -118,8 +118,8 @@ typedef struct psc_ctx psc_ctx;
  * chunk: particles per work item of the particle kernel (0 = default 8192).
  * Synchronous errors: PSC_ERR_INVALID, PSC_ERR_CFL (dt >= CFL limit),
  * PSC_ERR_LDS (a patch's field and current tiles plus the per-wave queues of
- * a 256-thread workgroup exceed 64 KiB of LDS, or a patch side exceeds 255
- * cells). */
+ * a 256-thread workgroup exceed the 160 KiB of LDS of a workgroup, or a patch
+ * side exceeds 255 cells). */
 psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc_ctx **out);
 
 /* Bytes of device workspace the context needs (per-patch current tiles,
@@ -186,10 +186,10 @@ psc_status psc_step(psc_ctx *ctx, int nsteps, int use_graph, void *stream);
  * workers: persistent workgroups (0 = compute units x workgroups that fit
  * in one unit's LDS).  threads: workgroup size, 256, 384 or 512 (0 keeps;
  * the LDS tiles of a work item are shared by all its waves; PSC_ERR_LDS if
- * the tiles, cell tables and per-wave queues exceed 64 KiB).  run: 1..64
- * consecutive particles of one cell that a lane pushes in sequence,
- * accumulating their current before the wave-level sums (0 keeps; default
- * 8).  Drops recorded step graphs.  May synchronize. */
+ * the tiles, cell tables and per-wave queues exceed 160 KiB).  run: 1..64
+ * particles of one cell that a lane pushes in sequence, accumulating their
+ * current before the wave-level sums (0 keeps; default 1: one particle per
+ * lane, consecutive particles on consecutive lanes).  Drops recorded step graphs.  May synchronize. */
 #define PSC_LAUNCH_GRID 0
 #define PSC_LAUNCH_QUEUE 1
 #define PSC_LAUNCH_PARTITION 2

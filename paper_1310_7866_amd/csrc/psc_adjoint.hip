@@ -91,13 +91,13 @@ __device__ __forceinline__ float gather2_d(const float *F, int pitch, int iy, in
 
 // transpose of the interpolation: scatter lam * weights into an LDS tile
 template <int ORDER>
-__device__ __forceinline__ void scatter2(float *G, int pitch, int iy, int iz, const float *wy, const float *wz,
+__device__ __forceinline__ void scatter2(double *G, int pitch, int iy, int iz, const float *wy, const float *wz,
                                          float lam) {
-    float *p = G + iz * pitch + iy;
+    double *p = G + iz * pitch + iy;
 #pragma unroll
     for (int b = 0; b <= ORDER; ++b)
 #pragma unroll
-        for (int a = 0; a <= ORDER; ++a) atomicAdd(&p[b * pitch + a], lam * wy[a] * wz[b]);
+        for (int a = 0; a <= ORDER; ++a) atomicAdd(&p[b * pitch + a], (double)(lam * wy[a] * wz[b]));
 }
 
 __device__ __forceinline__ float3 cross3(float3 a, float3 b) {
@@ -246,7 +246,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_particles(const RunDev *__restri
                                                           const Unit *__restrict__ units,
                                                           const int32_t *__restrict__ item_start, int n_units,
                                                           int chunk) {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];   // 16-byte aligned: holds doubles and float4
     constexpr int L = ORDER + 2;
     constexpr int FLO = 1, FHI = ORDER;
     constexpr int JLO = ORDER;
@@ -278,7 +278,9 @@ __global__ void __launch_bounds__(kBlock) k_adj_particles(const RunDev *__restri
     const int fy = R.P[1] + FLO + FHI, fz = R.P[2] + FLO + FHI;
     const int fcells = fy * fz;
     float *ftile = lds;               // E, B1
-    float *gt = lds + 6 * fcells;     // transposed interpolation of E, B1
+    // transposed interpolation of E, B1, accumulated in double (the LDS add
+    // of doubles runs at the rate of integer atomics, the float one far slower)
+    double *gt = reinterpret_cast<double *>(lds + ((6 * fcells + 3) & ~3));
     const int64_t nc = R.ncell;
     {
         const float inv_fy = 1.0f / fy;
@@ -292,7 +294,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_particles(const RunDev *__restri
                 ftile[(3 + c) * fcells + t] = A.B1[c * nc + g];
             }
         }
-        for (int t = threadIdx.x; t < 6 * fcells; t += kBlock) gt[t] = 0.0f;
+        for (int t = threadIdx.x; t < 6 * fcells; t += kBlock) gt[t] = 0.0;
     }
     __syncthreads();
 
@@ -486,8 +488,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_particles(const RunDev *__restri
     __syncthreads();
     float *gp = A.gtile + (int64_t)U.patch * 6 * fcells;
     for (int t2 = threadIdx.x; t2 < 6 * fcells; t2 += kBlock) {
-        const float v = gt[t2];
-        if (v != 0.0f) atomicAdd(&gp[t2], v);
+        const double v = gt[t2];
+        if (v != 0.0) atomicAdd(&gp[t2], (float)v);
     }
 }
 
@@ -550,7 +552,7 @@ __global__ void __launch_bounds__(256) k_adj_fold(const RunDev *__restrict__ run
 
 size_t adjoint_lds_bytes(int order, const int P[3]) {
     const int fy = P[1] + 1 + order, fz = P[2] + 1 + order;
-    return sizeof(float) * 12 * (size_t)fy * fz;
+    return sizeof(float) * (((6 * (size_t)fy * fz + 3) & ~(size_t)3) + 12 * (size_t)fy * fz);
 }
 
 hipError_t launch_adjoint(const Launch &L, const AdjRun *adj_dev, const AdjRun *adj_host, const Unit *units,

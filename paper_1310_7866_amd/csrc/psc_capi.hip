@@ -13,18 +13,28 @@
 #include "psc_internal.h"
 
 namespace psc {
-size_t push_lds_bytes(int dim, int order, const int P[3], int threads);
-int push_occupancy(int dim, int order, int mode, int threads, size_t lds);
+size_t push_lds_bytes(int dim, int order, const int P[3], int threads, int run);
+int push_occupancy(int dim, int order, int mode, int threads, int run, size_t lds);
 }
 
 using namespace psc;
+
+// LDS one workgroup may allocate on gfx950 (160 KiB per compute unit)
+static constexpr size_t kMaxLds = 160 * 1024;
 
 struct psc_ctx {
     std::vector<psc_run_desc> desc;
     std::vector<RunDev> runs;   // host mirror of the device table
     int n_runs = 0, dim = 2, order = 1, chunk = 8192;
-    size_t lds = 0, lds384 = 0, lds512 = 0;   // particle-kernel LDS with 256 / 384 / 512 threads
-    size_t push_lds(int threads) const { return threads == 512 ? lds512 : (threads == 384 ? lds384 : lds); }
+    // particle-kernel LDS bytes for a workgroup size and particles per lane
+    size_t push_lds(int threads, int run) const {
+        size_t m = 0;
+        for (const psc_run_desc &d : desc) {
+            const size_t b = push_lds_bytes(d.dim, d.order, d.patch, threads, run);
+            if (b > m) m = b;
+        }
+        return m;
+    }
 
     // workspace layout (offsets in bytes)
     size_t ws_bytes = 0;
@@ -173,18 +183,13 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
             delete ctx;
             return s;
         }
-        const size_t lds = push_lds_bytes(d.dim, d.order, d.patch, 256);
-        const size_t lds384 = push_lds_bytes(d.dim, d.order, d.patch, 384);
-        const size_t lds512 = push_lds_bytes(d.dim, d.order, d.patch, 512);
-        if (d.patch[0] > 255 || d.patch[1] > 255 || d.patch[2] > 255 || lds > 65536) {
-            std::snprintf(msg, sizeof msg, "run %d: patch tile needs %zu bytes of LDS (max 65536)", r, lds);
+        const size_t lds = push_lds_bytes(d.dim, d.order, d.patch, 256, 1);
+        if (d.patch[0] > 255 || d.patch[1] > 255 || d.patch[2] > 255 || lds > kMaxLds) {
+            std::snprintf(msg, sizeof msg, "run %d: patch tile needs %zu bytes of LDS (max %zu)", r, lds, kMaxLds);
             psc_status s = fail(ctx, PSC_ERR_LDS, msg);
             delete ctx;
             return s;
         }
-        if (lds > ctx->lds) ctx->lds = lds;
-        if (lds384 > ctx->lds384) ctx->lds384 = lds384;
-        if (lds512 > ctx->lds512) ctx->lds512 = lds512;
     }
 
     // host mirrors and layout
@@ -322,8 +327,8 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
                 ctx->off_atot[r][s] = take(sizeof(int32_t) * R.ncell);
             }
         }
-        if (ctx->adj_lds > 65536) {
-            psc_status st = fail(ctx, PSC_ERR_LDS, "adjoint patch tile does not fit in 64 KiB of LDS");
+        if (ctx->adj_lds > kMaxLds) {
+            psc_status st = fail(ctx, PSC_ERR_LDS, "adjoint patch tiles do not fit in 160 KiB of LDS");
             delete ctx;
             return st;
         }
@@ -526,7 +531,7 @@ psc_status psc_push_particles(psc_ctx *ctx, void *stream) {
     pm.part = ctx->at<int32_t>(ctx->off.part);
     HIPCHECK(launch_push(L, ctx->at<Unit>(ctx->off.units), (int)ctx->units.size(),
                          ctx->at<int32_t>(ctx->off.item_start), ctx->max_items, ctx->chunk, ctx->dim, ctx->order,
-                         ctx->front, ctx->cs_sel, ctx->perm_pending, ctx->push_lds(pm.threads), pm),
+                         ctx->front, ctx->cs_sel, ctx->perm_pending, ctx->push_lds(pm.threads, pm.run), pm),
              "push particles");
     ctx->front = 1 - ctx->front;
     ctx->perm_pending = 0;
@@ -743,7 +748,7 @@ psc_status psc_set_launch(psc_ctx *ctx, int mode, int chunk, int workers, int th
     if (!ctx || !ctx->bound || mode < 0 || mode > 2 || chunk < 0 || workers < 0 || workers > ctx->max_workers ||
         (threads != 0 && threads != 256 && threads != 384 && threads != 512) || run < 0 || run > 64)
         return PSC_ERR_INVALID;
-    if (threads && ctx->push_lds(threads) > 65536) return PSC_ERR_LDS;
+    if (ctx->push_lds(threads ? threads : ctx->pm.threads, run ? run : ctx->pm.run) > kMaxLds) return PSC_ERR_LDS;
     if (threads) ctx->pm.threads = threads;
     if (run) ctx->pm.run = run;
     if (chunk > 0 && chunk != ctx->chunk) {
@@ -758,7 +763,8 @@ psc_status psc_set_launch(psc_ctx *ctx, int mode, int chunk, int workers, int th
         int dev = 0, cus = 0;
         HIPCHECK(hipGetDevice(&dev), "get device");
         HIPCHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
-        int per = push_occupancy(ctx->dim, ctx->order, mode, ctx->pm.threads, ctx->push_lds(ctx->pm.threads));
+        int per = push_occupancy(ctx->dim, ctx->order, mode, ctx->pm.threads, ctx->pm.run,
+                                 ctx->push_lds(ctx->pm.threads, ctx->pm.run));
         if (per < 1) per = 1;
         workers = cus * per;
         if (workers > ctx->max_workers) workers = ctx->max_workers;

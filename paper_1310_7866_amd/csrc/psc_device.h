@@ -88,6 +88,27 @@ __device__ __forceinline__ float gather2(const float *F, int pitch, int iy, int 
     return s;
 }
 
+// two components interleaved in one tile (same staggering, same weights)
+template <int ORDER>
+__device__ __forceinline__ float2 gather2_pair(const float2 *F, int pitch, int iy, int iz, const float *wy,
+                                               const float *wz) {
+    const float2 *p = F + iz * pitch + iy;
+    float sx = 0.0f, sy = 0.0f;
+#pragma unroll
+    for (int b = 0; b <= ORDER; ++b) {
+        float rx = 0.0f, ry = 0.0f;
+#pragma unroll
+        for (int a = 0; a <= ORDER; ++a) {
+            const float2 f = p[b * pitch + a];
+            rx = fmaf(wy[a], f.x, rx);
+            ry = fmaf(wy[a], f.y, ry);
+        }
+        sx = fmaf(wz[b], rx, sx);
+        sy = fmaf(wz[b], ry, sy);
+    }
+    return make_float2(sx, sy);
+}
+
 template <int ORDER>
 __device__ __forceinline__ float gather3(const float *F, int px, int pxy, int ix, int iy, int iz,
                                          const float *wx, const float *wy, const float *wz) {
@@ -109,6 +130,7 @@ __device__ __forceinline__ float gather3(const float *F, int px, int pxy, int ix
 }
 
 __device__ __forceinline__ void lds_add(float *p, float v) { atomicAdd(p, v); }
+__device__ __forceinline__ void lds_add(double *p, float v) { atomicAdd(p, (double)v); }
 
 // quotient and remainder of 0 <= a < 2^22 by b >= 1 (inv_b = 1/b rounded to
 // float).  (a + 1/2)/b lies at least 1/(2b) from an integer; a + 1/2 is exact

@@ -22,24 +22,51 @@ namespace psc {
 #define PSC_SCAN_WIDTH 64
 #endif
 #ifndef PSC_QUEUE_SLOTS
-#define PSC_QUEUE_SLOTS 32
+#define PSC_QUEUE_SLOTS 16
 #endif
-//   PSC_WAVES_PER_EU occupancy the register allocator must allow (0: free)
+//   PSC_PACK_TAILS   segments per wave whose sums are staged and added with
+//                    full-lane atomics (more fall back to per-tail atomics)
+#ifndef PSC_PACK_TAILS
+#define PSC_PACK_TAILS 3
+#endif
+//   PSC_WAVES_PER_EU occupancy the register allocator must allow for every
+//                    instantiation (0: the measured per-shape choice below)
 #ifndef PSC_WAVES_PER_EU
 #define PSC_WAVES_PER_EU 0
 #endif
-#if PSC_WAVES_PER_EU > 0
-#define PSC_OCCUPANCY __attribute__((amdgpu_waves_per_eu(PSC_WAVES_PER_EU)))
-#else
-#define PSC_OCCUPANCY
-#endif
+// Waves per SIMD the register allocator must leave room for (0: its free
+// choice; the LDS tiles already limit a compute unit to two workgroups).
+template <int DIM, int ORDER, bool RUNS>
+constexpr int push_waves() {
+    return PSC_WAVES_PER_EU > 0 ? PSC_WAVES_PER_EU : 0;
+}
+#define PSC_OCCUPANCY __attribute__((amdgpu_waves_per_eu(push_waves<DIM, ORDER, RUNS>())))
 constexpr int kScanWidth = PSC_SCAN_WIDTH;
 constexpr int kQueueSlots = PSC_QUEUE_SLOTS;
+constexpr int kPackTails = PSC_PACK_TAILS;
 static_assert(kQueueSlots >= 1 && kQueueSlots <= 64, "queue slots 1..64");
 
 // words of one queued particle whose support changes nodes: packed cell and
 // moves, start and end offsets, and in 2-d the out-of-plane current factor
 constexpr int cross_words(int dim) { return dim == 2 ? 6 : 7; }
+
+// LDS layout of the particle kernel (offsets in floats, each region starting
+// on 16 bytes): field tile, current tile (doubles), per-wave crossing queues,
+// per-wave staging of segment sums, cell table.  Returns the total.
+struct PushLds {
+    int cur, queue, stage, table, total;
+};
+__host__ __device__ constexpr int align4(int n) { return (n + 3) & ~3; }
+__host__ __device__ inline PushLds push_lds_layout(int fcells, int jcells, int waves, int qwords, int swords,
+                                                   int twords) {
+    PushLds L{};
+    L.cur = align4(6 * fcells);
+    L.queue = align4(L.cur + 6 * jcells);   // current tile in doubles
+    L.stage = align4(L.queue + waves * qwords);
+    L.table = align4(L.stage + waves * align4(swords));
+    L.total = L.table + twords;
+    return L;
+}
 
 // ---------------------------------------------------------------------------
 // work items
@@ -182,7 +209,7 @@ __device__ __forceinline__ void row_scan(float (&v)[N], const RowScan &r) {
 // (general stencil: used for particles whose support changes cell)
 // ---------------------------------------------------------------------------
 template <int DIM, int ORDER>
-__device__ __forceinline__ void deposit_lane(float *jtile, int jcells, int jx_, int jy_, int lx, int ly, int lz,
+__device__ __forceinline__ void deposit_lane(double *jtile, int jcells, int jx_, int jy_, int lx, int ly, int lz,
                                              const float o[3], const int s[3], const float o1[3], float jfx,
                                              float jfy, float jfz, float fxv) {
     constexpr int L = ORDER + 2;
@@ -200,7 +227,7 @@ __device__ __forceinline__ void deposit_lane(float *jtile, int jcells, int jx_, 
         Cy[r] = r == 0 ? DSy[0] : Cy[r - 1] + DSy[r];
         Cz[r] = r == 0 ? DSz[0] : Cz[r - 1] + DSz[r];
     }
-    float *Jx = jtile, *Jy = jtile + jcells, *Jz = jtile + 2 * jcells;
+    double *Jx = jtile, *Jy = jtile + jcells, *Jz = jtile + 2 * jcells;
     if constexpr (DIM == 2) {
         const int base = (lz + bz + JLO) * jy_ + (ly + by + JLO);
 #pragma unroll
@@ -298,6 +325,42 @@ __device__ __forceinline__ int unit_of_item(const int32_t *__restrict__ item_sta
     return lo;
 }
 
+// Number of per-cell frame values of a particle whose support keeps its
+// nodes (2-d: Jy FL(FL-1), Jz (FL-1)FL, Jx FL^2; 3-d: FL^2(FL-1) each, FL =
+// 2 ORDER frame nodes per dimension), 0 where the kernel deposits per lane.
+template <int DIM, int ORDER>
+__host__ __device__ constexpr int frame_values() {
+    return (DIM == 3 && ORDER == 2) ? 0
+                                    : (DIM == 2 ? 2 * (2 * ORDER) * (2 * ORDER - 1) + (2 * ORDER) * (2 * ORDER)
+                                                : 3 * (2 * ORDER) * (2 * ORDER) * (2 * ORDER - 1));
+}
+
+// LDS offset of frame value j relative to the frame's base node in the
+// current tile (the order of the values is the order of the flush loops)
+template <int DIM, int ORDER>
+__device__ __forceinline__ int frame_offset(int j, int jx_, int jy_, int jcells) {
+    constexpr int FL = 2 * ORDER;
+    if constexpr (DIM == 2) {
+        constexpr int NY2 = FL * (FL - 1);
+        if (j < NY2) return jcells + (j / (FL - 1)) * jy_ + j % (FL - 1);
+        if (j < 2 * NY2) return 2 * jcells + ((j - NY2) / FL) * jy_ + (j - NY2) % FL;
+        return ((j - 2 * NY2) / FL) * jy_ + (j - 2 * NY2) % FL;
+    } else {
+        constexpr int NC3 = FL * FL * (FL - 1);
+        const int pxy = jx_ * jy_;
+        if (j < NC3) {
+            const int t = j / (FL - 1);
+            return (t / FL) * pxy + (t % FL) * jx_ + j % (FL - 1);
+        }
+        if (j < 2 * NC3) {
+            const int jj = j - NC3, t = jj / FL;
+            return jcells + (t / (FL - 1)) * pxy + (t % (FL - 1)) * jx_ + jj % FL;
+        }
+        const int jj = j - 2 * NC3, t = jj / FL;
+        return 2 * jcells + (t / FL) * pxy + (t % FL) * jx_ + jj % FL;
+    }
+}
+
 // One work item: stage the patch's fields, push its chunk of particles, add
 // the chunk's current into the patch tile.  Ends with a barrier so the caller
 // may start the next item on the same LDS.
@@ -314,7 +377,7 @@ __device__ __forceinline__ int unit_of_item(const int32_t *__restrict__ item_sta
 // and one set of LDS atomics per K particles of a lane.  Particles whose
 // support changes nodes wait in a per-wave queue and are deposited in
 // batches with per-lane LDS atomics.
-template <int DIM, int ORDER, int NT>
+template <int DIM, int ORDER, int NT, bool RUNS>
 __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const Unit *__restrict__ units,
                                           const int32_t *__restrict__ item_start, int lo, int item, int chunk,
                                           int front, int cs_sel, int use_perm, int K, uint32_t *__restrict__ err,
@@ -358,14 +421,25 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
     const int jy_ = R.P[1] + JLO + JHI, jz_ = R.P[2] + JLO + JHI;
     const int jcells = jx_ * jy_ * jz_;
     const int npc = (DIM == 3 ? R.P[0] : 1) * R.P[1] * R.P[2];
-    float *ftile = lds;               // 6 * fcells: Ex Ey Ez Bx By Bz
-    float *jtile = lds + 6 * fcells;  // 3 * jcells: Jx Jy Jz
+    // 6 * fcells: 3-d Ex Ey Ez Bx By Bz; 2-d Ex, Bx, then (Ey, Bz) and
+    // (Ez, By) interleaved in pairs: the two of a pair share their staggering,
+    // so one 8-byte LDS read serves both
+    // per-wave staging of the segment sums: kPackTails frames of NV values,
+    // then their base offsets
+    constexpr int PKW = kReduce ? kPackTails * (NV + 1) : 0;
+    const PushLds LL = push_lds_layout(fcells, jcells, NT / 64, QS * QW, PKW, 0);
+    float *ftile = lds;
+    // 3 * jcells doubles: Jx Jy Jz.  Accumulated in double: the LDS add of
+    // doubles runs at the full rate of integer atomics on this hardware,
+    // the float one more than 20 times slower.
+    double *jtile = reinterpret_cast<double *>(lds + LL.cur);
     // per-wave queue of particles whose support changes nodes: QW words
     // (field-major) for each of QS slots
-    float *cq = jtile + 3 * jcells + (threadIdx.x >> 6) * (QS * QW);
+    float *cq = lds + LL.queue + (threadIdx.x >> 6) * (QS * QW);
+    float *pk = lds + LL.stage + (threadIdx.x >> 6) * align4(PKW);
     // cell table: clamped first particle of every cell (npc + 1), run prefix
     // (npc + 1), per-wave sums of the prefix scan (NT / 64)
-    int32_t *ccs = reinterpret_cast<int32_t *>(jtile + 3 * jcells + (NT / 64) * QS * QW);
+    int32_t *ccs = reinterpret_cast<int32_t *>(lds + LL.table);
     int32_t *crs = ccs + (npc + 1);
     int32_t *wsum = crs + (npc + 1);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -387,23 +461,35 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
             const int gy = wrap(oy + ty - FLO, R.n[1]);
             const int gz = wrap(oz + tz - FLO, R.n[2]);
             const int64_t g = gx + (int64_t)R.n[0] * (gy + (int64_t)R.n[1] * gz);
+            if constexpr (DIM == 2) {
+                ftile[t] = Eg[g];
+                ftile[fcells + t] = Bg[g];
+                reinterpret_cast<float2 *>(ftile + 2 * fcells)[t] = make_float2(Eg[nc + g], Bg[2 * nc + g]);
+                reinterpret_cast<float2 *>(ftile + 4 * fcells)[t] = make_float2(Eg[2 * nc + g], Bg[nc + g]);
+            } else {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                ftile[c * fcells + t] = Eg[c * nc + g];
-                ftile[(3 + c) * fcells + t] = Bg[c * nc + g];
+                for (int c = 0; c < 3; ++c) {
+                    ftile[c * fcells + t] = Eg[c * nc + g];
+                    ftile[(3 + c) * fcells + t] = Bg[c * nc + g];
+                }
             }
         }
-        for (int t = threadIdx.x; t < 3 * jcells; t += NT) jtile[t] = 0.0f;
-        for (int c = threadIdx.x; c <= pcells; c += NT) {
-            const int32_t v = cs[kb + c];
-            ccs[c] = v < beg ? beg : (v > end ? end : v);
+        for (int t = threadIdx.x; t < 3 * jcells; t += NT) jtile[t] = 0.0;
+        if constexpr (RUNS) {   // the cell table exists only with runs
+            for (int c = threadIdx.x; c <= pcells; c += NT) {
+                const int32_t v = cs[kb + c];
+                ccs[c] = v < beg ? beg : (v > end ? end : v);
+            }
         }
     }
     __syncthreads();
 
-    // K = 1: lane t of a round takes particle beg + r0 + t (coalesced) and
-    // its cell comes from its key; no cell table is needed
-    const bool single = K == 1;
+    // without runs (K = 1, a separate instantiation: its registers are not
+    // sized for the run accumulators) lane t of a round takes particle
+    // beg + r0 + t (coalesced) and its cell comes from its key; no cell
+    // table is needed
+    constexpr bool single = !RUNS;
+    if constexpr (single) K = 1;
     // runs per cell (ceil(particles / K)) and their exclusive prefix
     if (!single) {
         const int per = (pcells + NT - 1) / NT;
@@ -448,7 +534,7 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
     const float cfy = dt * R.inv_dx[1], cfz = dt * R.inv_dx[2];
     const float jfx = -qw * R.dx[0] / dt, jfy = -qw * R.dx[1] / dt, jfz = -qw * R.dx[2] / dt;
     const float inv_hx = 1.0f / hx, inv_hy = 1.0f / hy;
-    float *Jx = jtile, *Jy = jtile + jcells, *Jz = jtile + 2 * jcells;
+    double *Jx = jtile, *Jy = jtile + jcells, *Jz = jtile + 2 * jcells;
     uint32_t flags = 0;
 
     // deposit queued particles [0, n) of this wave, one per lane
@@ -545,12 +631,16 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
             float Ex, Ey, Ez, Bx, By, Bz;
             if constexpr (DIM == 2) {
                 const int ty = ly + FLO, tz = lz + FLO;
-                Ex = gather2<ORDER>(ftile + 0 * fcells, fy, ty + bny, tz + bnz, wny, wnz);
-                Ey = gather2<ORDER>(ftile + 1 * fcells, fy, ty + bhy, tz + bnz, why, wnz);
-                Ez = gather2<ORDER>(ftile + 2 * fcells, fy, ty + bny, tz + bhz, wny, whz);
-                Bx = gather2<ORDER>(ftile + 3 * fcells, fy, ty + bhy, tz + bhz, why, whz);
-                By = gather2<ORDER>(ftile + 4 * fcells, fy, ty + bny, tz + bhz, wny, whz);
-                Bz = gather2<ORDER>(ftile + 5 * fcells, fy, ty + bhy, tz + bnz, why, wnz);
+                Ex = gather2<ORDER>(ftile, fy, ty + bny, tz + bnz, wny, wnz);
+                Bx = gather2<ORDER>(ftile + fcells, fy, ty + bhy, tz + bhz, why, whz);
+                const float2 EyBz = gather2_pair<ORDER>(reinterpret_cast<const float2 *>(ftile + 2 * fcells), fy,
+                                                        ty + bhy, tz + bnz, why, wnz);
+                const float2 EzBy = gather2_pair<ORDER>(reinterpret_cast<const float2 *>(ftile + 4 * fcells), fy,
+                                                        ty + bny, tz + bhz, wny, whz);
+                Ey = EyBz.x;
+                Bz = EyBz.y;
+                Ez = EzBy.x;
+                By = EzBy.y;
             } else {
                 float wnx[ORDER + 1], whx[ORDER + 1];
                 const int bnx = node_weights<ORDER>(o[0], wnx), bhx = half_weights<ORDER>(o[0], whx);
@@ -742,9 +832,33 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
         if constexpr (kReduce) {
             const RowScan rs = row_scan_setup<SW>(len > 0 ? c : -1);
             row_scan<SW>(acc, rs);
-            if (rs.tail && len > 0) {
+            const bool put = rs.tail && len > 0;
+            int base;
+            if constexpr (DIM == 2) base = (lz + FB + JLO) * jy_ + (ly + FB + JLO);
+            else base = (lz + FB + JLO) * (jx_ * jy_) + (ly + FB + JLO) * jx_ + (lx + FB + JLO);
+            const uint64_t tails = __ballot(put);
+            const int nt = __popcll(tails);
+            if (nt <= kPackTails) {
+                // few segments: stage their sums, then add them with every
+                // lane of the wave busy (one atomic per lane per pass)
+                if (put) {
+                    const int ti = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(tails >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)tails, 0u));
+                    float4 *dst = reinterpret_cast<float4 *>(pk + ti * NV);
+#pragma unroll
+                    for (int v = 0; v < NV / 4; ++v)
+                        dst[v] = make_float4(acc[4 * v], acc[4 * v + 1], acc[4 * v + 2], acc[4 * v + 3]);
+                    reinterpret_cast<int32_t *>(pk + kPackTails * NV)[ti] = base;
+                }
+                __builtin_amdgcn_wave_barrier();
+                for (int k = lane; k < nt * NV; k += 64) {
+                    const int ti = k / NV, j = k - ti * NV;
+                    const int b0 = reinterpret_cast<const int32_t *>(pk + kPackTails * NV)[ti];
+                    lds_add(&jtile[b0 + frame_offset<DIM, ORDER>(j, jx_, jy_, jcells)], pk[k]);
+                }
+                __builtin_amdgcn_wave_barrier();
+            } else if (put) {
                 if constexpr (DIM == 2) {
-                    const int base = (lz + FB + JLO) * jy_ + (ly + FB + JLO);
 #pragma unroll
                     for (int b = 0; b < FL; ++b)
 #pragma unroll
@@ -759,7 +873,6 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
                         for (int a = 0; a < FL; ++a) lds_add(&Jx[base + b * jy_ + a], acc[2 * NY2 + b * FL + a]);
                 } else {
                     const int pxy = jx_ * jy_;
-                    const int base = (lz + FB + JLO) * pxy + (ly + FB + JLO) * jx_ + (lx + FB + JLO);
 #pragma unroll
                     for (int c2 = 0; c2 < FL; ++c2)
 #pragma unroll
@@ -794,8 +907,8 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
     // add the LDS current tile into the patch's tile in HBM
     float *gt = R.jtile + (int64_t)U.patch * 3 * jcells;
     for (int t = threadIdx.x; t < 3 * jcells; t += NT) {
-        const float v = jtile[t];
-        if (v != 0.0f) atomicAdd(&gt[t], v);
+        const double v = jtile[t];
+        if (v != 0.0) atomicAdd(&gt[t], (float)v);
     }
     __syncthreads();
 }
@@ -803,16 +916,16 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
 // launch mode 0: one workgroup per item.  Workgroups are dispatched
 // round-robin over the 8 XCDs; give each XCD a contiguous range of items so
 // that the chunks of a patch share one L2.
-template <int DIM, int ORDER, int NT>
+template <int DIM, int ORDER, int NT, bool RUNS>
 __global__ void __launch_bounds__(NT) PSC_OCCUPANCY k_push(const RunDev *__restrict__ runs, const Unit *__restrict__ units,
                                                  const int32_t *__restrict__ item_start, int n_units,
                                                  int chunk, int front, int cs_sel, int use_perm, int K,
                                                  uint32_t *__restrict__ err) {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];   // 16-byte aligned: holds doubles and float4
     const int nb = gridDim.x;
     const int item = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
     if (item >= item_start[n_units]) return;
-    push_item<DIM, ORDER, NT>(runs, units, item_start, unit_of_item(item_start, n_units, item), item, chunk, front,
+    push_item<DIM, ORDER, NT, RUNS>(runs, units, item_start, unit_of_item(item_start, n_units, item), item, chunk, front,
                               cs_sel, use_perm, K, err, lds);
 }
 
@@ -820,13 +933,13 @@ __global__ void __launch_bounds__(NT) PSC_OCCUPANCY k_push(const RunDev *__restr
 // XCD (queue q owns the q-th eighth of the items, so an XCD works on
 // neighbouring patches), and steal from the other queues when theirs is
 // empty.  Every workgroup leaves once all queues are drained.
-template <int DIM, int ORDER, int NT>
+template <int DIM, int ORDER, int NT, bool RUNS>
 __global__ void __launch_bounds__(NT) PSC_OCCUPANCY k_push_queue(const RunDev *__restrict__ runs,
                                                        const Unit *__restrict__ units,
                                                        const int32_t *__restrict__ item_start, int n_units,
                                                        int chunk, int front, int cs_sel, int use_perm, int K,
                                                        uint32_t *__restrict__ err, int32_t *__restrict__ queue) {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];   // 16-byte aligned: holds doubles and float4
     __shared__ int s_item;
     const int total = item_start[n_units];
     const int xcd = blockIdx.x & 7;
@@ -839,7 +952,7 @@ __global__ void __launch_bounds__(NT) PSC_OCCUPANCY k_push_queue(const RunDev *_
             const int item = s_item;
             __syncthreads();
             if (item >= qe) break;
-            push_item<DIM, ORDER, NT>(runs, units, item_start, unit_of_item(item_start, n_units, item), item, chunk,
+            push_item<DIM, ORDER, NT, RUNS>(runs, units, item_start, unit_of_item(item_start, n_units, item), item, chunk,
                                       front, cs_sel, use_perm, K, err, lds);
         }
     }
@@ -847,40 +960,51 @@ __global__ void __launch_bounds__(NT) PSC_OCCUPANCY k_push_queue(const RunDev *_
 
 // launch mode 2: persistent workgroup w processes the contiguous units
 // [part[w], part[w+1]) chosen by the load-balancing partition.
-template <int DIM, int ORDER, int NT>
+template <int DIM, int ORDER, int NT, bool RUNS>
 __global__ void __launch_bounds__(NT) PSC_OCCUPANCY k_push_part(const RunDev *__restrict__ runs,
                                                       const Unit *__restrict__ units,
                                                       const int32_t *__restrict__ item_start, int n_units,
                                                       int chunk, int front, int cs_sel, int use_perm, int K,
                                                       uint32_t *__restrict__ err, const int32_t *__restrict__ part) {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];   // 16-byte aligned: holds doubles and float4
     const int u0 = part[blockIdx.x], u1 = min(part[blockIdx.x + 1], n_units);
     for (int u = u0; u < u1; ++u)
         for (int item = item_start[u]; item < item_start[u + 1]; ++item)
-            push_item<DIM, ORDER, NT>(runs, units, item_start, u, item, chunk, front, cs_sel, use_perm, K, err, lds);
+            push_item<DIM, ORDER, NT, RUNS>(runs, units, item_start, u, item, chunk, front, cs_sel, use_perm, K, err, lds);
+}
+
+template <int DIM, int ORDER, int NT, bool RUNS>
+static hipError_t launch_push_r(const Launch &L, const Unit *units, int n_units, int32_t *item_start,
+                                int64_t max_items, int chunk, int front, int cs_sel, int use_perm,
+                                size_t lds, const PushMode &pm) {
+    hipLaunchKernelGGL(k_build_items, dim3(1), dim3(1024), 0, L.stream, L.runs_dev, units, n_units, chunk,
+                       cs_sel, item_start, pm.queue);
+    if (pm.mode == 1) {
+        hipLaunchKernelGGL((k_push_queue<DIM, ORDER, NT, RUNS>), dim3((unsigned)pm.workers), dim3(NT), lds, L.stream,
+                           L.runs_dev, units, item_start, n_units, chunk, front, cs_sel, use_perm, pm.run, L.err,
+                           pm.queue);
+    } else if (pm.mode == 2) {
+        hipLaunchKernelGGL((k_push_part<DIM, ORDER, NT, RUNS>), dim3((unsigned)pm.workers), dim3(NT), lds, L.stream,
+                           L.runs_dev, units, item_start, n_units, chunk, front, cs_sel, use_perm, pm.run, L.err,
+                           pm.part);
+    } else {
+        int64_t grid = (max_items + 7) / 8 * 8;
+        if (grid < 8) grid = 8;
+        hipLaunchKernelGGL((k_push<DIM, ORDER, NT, RUNS>), dim3((unsigned)grid), dim3(NT), lds, L.stream, L.runs_dev,
+                           units, item_start, n_units, chunk, front, cs_sel, use_perm, pm.run, L.err);
+    }
+    return hipGetLastError();
 }
 
 template <int DIM, int ORDER, int NT>
 static hipError_t launch_push_t(const Launch &L, const Unit *units, int n_units, int32_t *item_start,
                                 int64_t max_items, int chunk, int front, int cs_sel, int use_perm,
                                 size_t lds, const PushMode &pm) {
-    hipLaunchKernelGGL(k_build_items, dim3(1), dim3(1024), 0, L.stream, L.runs_dev, units, n_units, chunk,
-                       cs_sel, item_start, pm.queue);
-    if (pm.mode == 1) {
-        hipLaunchKernelGGL((k_push_queue<DIM, ORDER, NT>), dim3((unsigned)pm.workers), dim3(NT), lds, L.stream,
-                           L.runs_dev, units, item_start, n_units, chunk, front, cs_sel, use_perm, pm.run, L.err,
-                           pm.queue);
-    } else if (pm.mode == 2) {
-        hipLaunchKernelGGL((k_push_part<DIM, ORDER, NT>), dim3((unsigned)pm.workers), dim3(NT), lds, L.stream,
-                           L.runs_dev, units, item_start, n_units, chunk, front, cs_sel, use_perm, pm.run, L.err,
-                           pm.part);
-    } else {
-        int64_t grid = (max_items + 7) / 8 * 8;
-        if (grid < 8) grid = 8;
-        hipLaunchKernelGGL((k_push<DIM, ORDER, NT>), dim3((unsigned)grid), dim3(NT), lds, L.stream, L.runs_dev,
-                           units, item_start, n_units, chunk, front, cs_sel, use_perm, pm.run, L.err);
-    }
-    return hipGetLastError();
+    if (pm.run > 1)
+        return launch_push_r<DIM, ORDER, NT, true>(L, units, n_units, item_start, max_items, chunk, front, cs_sel,
+                                                   use_perm, lds, pm);
+    return launch_push_r<DIM, ORDER, NT, false>(L, units, n_units, item_start, max_items, chunk, front, cs_sel,
+                                                use_perm, lds, pm);
 }
 
 template <int DIM, int ORDER>
@@ -917,27 +1041,33 @@ hipError_t launch_push(const Launch &L, const Unit *units_dev, int n_units, int3
 
 // resident workgroups per compute unit of the persistent particle kernel of
 // a launch mode (registers and LDS both counted), 0 on failure
-template <int DIM, int ORDER, int NT>
-static int push_occupancy_t(int mode, size_t lds) {
+template <int DIM, int ORDER, int NT, bool RUNS>
+static int push_occupancy_r(int mode, size_t lds) {
     int n = 0;
     hipError_t e;
-    if (mode == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_push_part<DIM, ORDER, NT>, NT, lds);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_push_queue<DIM, ORDER, NT>, NT, lds);
+    if (mode == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_push_part<DIM, ORDER, NT, RUNS>, NT, lds);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_push_queue<DIM, ORDER, NT, RUNS>, NT, lds);
     return e == hipSuccess ? n : 0;
 }
 
-template <int DIM, int ORDER>
-static int push_occupancy_nt(int mode, int threads, size_t lds) {
-    if (threads == 512) return push_occupancy_t<DIM, ORDER, 512>(mode, lds);
-    if (threads == 384) return push_occupancy_t<DIM, ORDER, 384>(mode, lds);
-    return push_occupancy_t<DIM, ORDER, 256>(mode, lds);
+template <int DIM, int ORDER, int NT>
+static int push_occupancy_t(int mode, int run, size_t lds) {
+    return run > 1 ? push_occupancy_r<DIM, ORDER, NT, true>(mode, lds)
+                   : push_occupancy_r<DIM, ORDER, NT, false>(mode, lds);
 }
 
-int push_occupancy(int dim, int order, int mode, int threads, size_t lds) {
-    if (dim == 2 && order == 1) return push_occupancy_nt<2, 1>(mode, threads, lds);
-    if (dim == 2 && order == 2) return push_occupancy_nt<2, 2>(mode, threads, lds);
-    if (dim == 3 && order == 1) return push_occupancy_nt<3, 1>(mode, threads, lds);
-    if (dim == 3 && order == 2) return push_occupancy_nt<3, 2>(mode, threads, lds);
+template <int DIM, int ORDER>
+static int push_occupancy_nt(int mode, int threads, int run, size_t lds) {
+    if (threads == 512) return push_occupancy_t<DIM, ORDER, 512>(mode, run, lds);
+    if (threads == 384) return push_occupancy_t<DIM, ORDER, 384>(mode, run, lds);
+    return push_occupancy_t<DIM, ORDER, 256>(mode, run, lds);
+}
+
+int push_occupancy(int dim, int order, int mode, int threads, int run, size_t lds) {
+    if (dim == 2 && order == 1) return push_occupancy_nt<2, 1>(mode, threads, run, lds);
+    if (dim == 2 && order == 2) return push_occupancy_nt<2, 2>(mode, threads, run, lds);
+    if (dim == 3 && order == 1) return push_occupancy_nt<3, 1>(mode, threads, run, lds);
+    if (dim == 3 && order == 2) return push_occupancy_nt<3, 2>(mode, threads, run, lds);
     return 0;
 }
 
@@ -963,17 +1093,21 @@ hipError_t launch_unit_counts(const Launch &L, const Unit *units, int n_units, i
 }
 
 // LDS bytes the particle kernel of a run needs with `threads` per workgroup
-size_t push_lds_bytes(int dim, int order, const int P[3], int threads) {
+// and `run` particles per lane (the cell tables only when run > 1)
+size_t push_lds_bytes(int dim, int order, const int P[3], int threads, int run) {
     const int fx = dim == 3 ? P[0] + field_lo(order) + field_hi(order) : 1;
     const int fy = P[1] + field_lo(order) + field_hi(order);
     const int fz = P[2] + field_lo(order) + field_hi(order);
     const int jx = dim == 3 ? P[0] + cur_lo(order) + cur_hi(order) : 1;
     const int jy = P[1] + cur_lo(order) + cur_hi(order);
     const int jz = P[2] + cur_lo(order) + cur_hi(order);
-    const size_t queue = (size_t)(threads / 64) * kQueueSlots * cross_words(dim);
-    const size_t npc = (size_t)(dim == 3 ? P[0] : 1) * P[1] * P[2];
-    const size_t table = 2 * (npc + 1) + threads / 64;   // cell starts, run prefix, wave sums
-    return sizeof(float) * (6 * (size_t)fx * fy * fz + 3 * (size_t)jx * jy * jz + queue + table);
+    const int nv = dim == 2 ? (order == 1 ? frame_values<2, 1>() : frame_values<2, 2>())
+                            : (order == 1 ? frame_values<3, 1>() : frame_values<3, 2>());
+    const int npc = (dim == 3 ? P[0] : 1) * P[1] * P[2];
+    const int table = run > 1 ? 2 * (npc + 1) + threads / 64 : 0;   // cell starts, run prefix, wave sums
+    const PushLds L = push_lds_layout(fx * fy * fz, jx * jy * jz, threads / 64, kQueueSlots * cross_words(dim),
+                                      nv ? kPackTails * (nv + 1) : 0, table);
+    return sizeof(float) * (size_t)L.total;
 }
 
 }  // namespace psc
