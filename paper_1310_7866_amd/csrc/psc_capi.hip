@@ -297,7 +297,7 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
             ctx->off_cs1[r][s] = take(sizeof(int32_t) * (R.ncell + 1));
             ctx->off_perm[r][s] = take(sizeof(int32_t) * R.sp[s].cap);
             ctx->off_mc[r][s] = take(R.sp[s].cap);
-            ctx->off_cnt[r][s] = take(sizeof(uint16_t) * M * R.ncell);
+            ctx->off_cnt[r][s] = take(sizeof(uint16_t) * (M * R.ncell + 2));   // whole 32-bit words
             ctx->off_pre[r][s] = take(sizeof(uint16_t) * M * R.ncell);
             ctx->off_tot[r][s] = take(sizeof(int32_t) * R.ncell);
         }
@@ -432,6 +432,8 @@ psc_status psc_bind(psc_ctx *ctx, const psc_run_bufs *bufs, int n_runs, void *wo
         for (int sp = 0; sp < R.n_species; ++sp) {
             HIPCHECK(hipMemsetAsync(R.sp[sp].cs[0], 0, sizeof(int32_t) * (R.ncell + 1), s), "clear cs");
             HIPCHECK(hipMemsetAsync(R.sp[sp].cs[1], 0, sizeof(int32_t) * (R.ncell + 1), s), "clear cs");
+            HIPCHECK(hipMemsetAsync(R.sp[sp].cnt, 0, sizeof(uint16_t) * (n_moves(R.dim) * R.ncell + 2), s),
+                     "clear move counts");
         }
     }
     if (ctx->adjoint) {
@@ -463,6 +465,19 @@ psc_status psc_bind(psc_ctx *ctx, const psc_run_bufs *bufs, int n_runs, void *wo
     return PSC_OK;
 }
 
+// zero the per (cell, move) counts the particle kernel accumulates (needed
+// only when a push was not followed by the sort, which clears them)
+static psc_status clear_move_counts(psc_ctx *ctx, hipStream_t s) {
+    for (int r = 0; r < ctx->n_runs; ++r) {
+        const RunDev &R = ctx->runs[r];
+        for (int sp = 0; sp < R.n_species; ++sp)
+            HIPCHECK(launch_fill_i32(reinterpret_cast<int32_t *>(R.sp[sp].cnt),
+                                     (n_moves(R.dim) * R.ncell + 2) / 2, 0, s),
+                     "clear move counts");
+    }
+    return PSC_OK;
+}
+
 psc_status psc_load_particles(psc_ctx *ctx, int run, int species, int64_t n, const int32_t *gcell, const float *goff,
                               const float *gu, const int32_t *gid, void *stream) {
     if (!ctx || !ctx->bound) return PSC_ERR_STATE;
@@ -471,6 +486,10 @@ psc_status psc_load_particles(psc_ctx *ctx, int run, int species, int64_t n, con
     if (ctx->stepped || ctx->front || ctx->cs_sel || ctx->perm_pending) {
         // restart: the particle state of every species lives in buffer set 0
         // again, so every species has to be loaded before the next step
+        if (ctx->mc_valid) {
+            psc_status st = clear_move_counts(ctx, (hipStream_t)stream);
+            if (st != PSC_OK) return st;
+        }
         ctx->stepped = false;
         ctx->front = ctx->cs_sel = ctx->perm_pending = ctx->mc_valid = 0;
         for (auto &v : ctx->loaded) std::fill(v.begin(), v.end(), false);
@@ -491,7 +510,7 @@ psc_status psc_load_particles(psc_ctx *ctx, int run, int species, int64_t n, con
     }
     HIPCHECK(launch_load_gather(R, species, n, keys_s, idx_s, goff, gu, gid, s), "load gather");
     HIPCHECK(launch_fill_i32(S.tot, R.ncell, 0, s), "load clear counts");
-    HIPCHECK(launch_count_cells(R, species, n, keys_s, S.tot, s), "load count");
+    HIPCHECK(launch_count_cells(R, species, n, keys_s, S.tot, ctx->err(), s), "load count");
     const int64_t nb = (R.ncell + kScanBlock - 1) / kScanBlock;
     ScanSeg seg{S.tot, S.cs[0], R.ncell, 0};
     HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.load_seg), &seg, sizeof seg, hipMemcpyHostToDevice, s), "load seg");
@@ -525,6 +544,7 @@ psc_status psc_push_fields(psc_ctx *ctx, int op, void *stream) {
 psc_status psc_push_particles(psc_ctx *ctx, void *stream) {
     psc_status st = require_loaded(ctx);
     if (st != PSC_OK) return st;
+    if (ctx->mc_valid && (st = clear_move_counts(ctx, (hipStream_t)stream)) != PSC_OK) return st;
     Launch L = make_launch(ctx, (hipStream_t)stream);
     PushMode pm = ctx->pm;
     pm.queue = ctx->at<int32_t>(ctx->off.queue);

@@ -42,7 +42,8 @@ struct SpeciesDev {
     int32_t *cs[2];      // cell start offsets, ncell + 1
     int32_t *perm;       // sorted slot -> index in the pushed buffer
     uint8_t *mc;         // move code of each pushed particle
-    uint16_t *cnt;       // [m * ncell + cell]: particles of `cell` with move m
+    uint16_t *cnt;       // [m * ncell + cell]: particles of `cell` with move m (filled by the
+                         // particle kernel, cleared by the sort's prefix pass)
     uint16_t *pre;       // [m * ncell + cell]: arrivals into cell+d(m) that precede them
     int32_t *tot;        // arrivals per new cell (scan input)
     int64_t seg;         // index of this (run, species) among scan segments
@@ -229,7 +230,7 @@ hipError_t launch_load_gather(const RunDev &r, int species, int64_t n, const int
                               const int32_t *sorted_idx, const float *goff, const float *gu,
                               const int32_t *gid, hipStream_t s);
 hipError_t launch_count_cells(const RunDev &r, int species, int64_t n, const int32_t *sorted_keys,
-                              int32_t *tot, hipStream_t s);
+                              int32_t *tot, uint32_t *err, hipStream_t s);
 hipError_t launch_get(const RunDev &r, int species, int front, int perm_pending, int32_t *cell,
                       float *off, float *u, int32_t *id, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);

@@ -118,46 +118,6 @@ __device__ __forceinline__ void walk_cells(const int32_t *sb, int nw, int32_t pb
     }
 }
 
-// per old cell: count particles per move code
-template <int DIM>
-__global__ void __launch_bounds__(kSortCells) k_sort_count(const RunDev *__restrict__ runs,
-                                                           const ScanSeg *__restrict__ segs,
-                                                           const int32_t *__restrict__ block_seg,
-                                                           const int32_t *__restrict__ seg_run,
-                                                           const int32_t *__restrict__ seg_sp, int cs_sel,
-                                                           uint32_t *err) {
-    constexpr int M = DIM == 3 ? 27 : 9;
-    __shared__ int32_t tab_all[4][64 * M];
-    __shared__ int32_t sb_all[4][65];
-    const CellBlock B = cell_block(runs, segs, block_seg, seg_run, seg_sp);
-    if (B.cw >= B.ce) return;   // whole wave: past the segment's cells
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int32_t *tab = tab_all[wave], *sb = sb_all[wave];
-    const SpeciesDev &S = *B.S;
-    const int32_t *cs = S.cs[cs_sel];
-    const int nw = (int)(B.ce - B.cw);
-    sb[lane] = cs[B.cw + (lane < nw ? lane : nw)];
-    if (lane == 0) sb[64] = cs[B.ce];
-#pragma unroll
-    for (int m = 0; m < M; ++m) tab[m * 64 + lane] = 0;
-    __builtin_amdgcn_wave_barrier();
-    uint32_t flags = 0;
-    walk_cells<M>(sb, nw, sb[0], sb[nw], S.mc, flags, [&](int32_t, int q, int m, int rank, bool last) {
-        if (last) tab[m * 64 + q] += rank + 1;
-    });
-    __builtin_amdgcn_wave_barrier();
-    if (lane < nw) {
-        const int64_t nc = B.R->ncell;
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-            int32_t v = tab[m * 64 + lane];
-            if (v > 65535) { flags |= PSC_DEV_OVERFULL; v = 65535; }
-            S.cnt[m * nc + B.cw + lane] = (uint16_t)v;
-        }
-    }
-    if (flags) atomicOr(err, flags);
-}
-
 // per new cell: order the source cells by key and assign arrival prefixes
 template <int DIM>
 __global__ void __launch_bounds__(kSortBlock) k_sort_prefix(const RunDev *__restrict__ runs,
@@ -184,6 +144,7 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_prefix(const RunDev *__rest
         const int sx = DIM == 3 ? wrap(g[0] - d[0], R.n[0]) : 0;
         ks[m] = (int32_t)encode_key(R, sx, wrap(g[1] - d[1], R.n[1]), wrap(g[2] - d[2], R.n[2]));
         cn[m] = S.cnt[m * nc + ks[m]];
+        S.cnt[m * nc + ks[m]] = 0;   // read once (each (source, move) has one destination): clear for the next push
     }
     int32_t tot = 0;
 #pragma unroll
@@ -361,17 +322,13 @@ hipError_t launch_sort(const Launch &L, const int64_t *seg_base, const int32_t *
     // scan_tmp: [0, n_scan_blocks) block sums; then the block -> segment table
     const int32_t *block_seg = scan_tmp + n_scan_blocks;
     const unsigned cgrid = (unsigned)(8 * n_scan_blocks);   // 256-cell blocks
-    if (dim == 3) {
-        hipLaunchKernelGGL(k_sort_count<3>, dim3(cgrid), dim3(kSortCells), 0, L.stream, L.runs_dev, segs_dev,
-                           block_seg, seg_run, seg_sp, cs_sel, L.err);
+    // the per (cell, move) counts come from the particle kernel
+    if (dim == 3)
         hipLaunchKernelGGL(k_sort_prefix<3>, dim3(grid), dim3(kSortBlock), 0, L.stream, L.runs_dev, seg_base,
                            seg_run, seg_sp, n_segs, total, L.err);
-    } else {
-        hipLaunchKernelGGL(k_sort_count<2>, dim3(cgrid), dim3(kSortCells), 0, L.stream, L.runs_dev, segs_dev,
-                           block_seg, seg_run, seg_sp, cs_sel, L.err);
+    else
         hipLaunchKernelGGL(k_sort_prefix<2>, dim3(grid), dim3(kSortBlock), 0, L.stream, L.runs_dev, seg_base,
                            seg_run, seg_sp, n_segs, total, L.err);
-    }
     hipError_t e = launch_scan(segs_dev, n_segs, n_scan_blocks, block_seg, scan_tmp, L.stream);
     if (e != hipSuccess) return e;
     if (dim == 3)
@@ -449,15 +406,19 @@ hipError_t launch_load_gather(const RunDev &r, int species, int64_t n, const int
     return hipGetLastError();
 }
 
-__global__ void k_count_cells(int64_t n, const int32_t *__restrict__ skeys, int32_t *__restrict__ tot) {
+// particles per cell of sorted keys; a cell's 65536th particle flags the
+// overflow of the 16-bit per (cell, move) counters of the step sort
+__global__ void k_count_cells(int64_t n, const int32_t *__restrict__ skeys, int32_t *__restrict__ tot,
+                              uint32_t *err) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
-    atomicAdd(&tot[skeys[r]], 1);
+    if (atomicAdd(&tot[skeys[r]], 1) == 65535) atomicOr(err, PSC_DEV_OVERFULL);
 }
 
-hipError_t launch_count_cells(const RunDev &, int, int64_t n, const int32_t *skeys, int32_t *tot, hipStream_t s) {
+hipError_t launch_count_cells(const RunDev &, int, int64_t n, const int32_t *skeys, int32_t *tot, uint32_t *err,
+                              hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_count_cells, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, skeys, tot);
+    hipLaunchKernelGGL(k_count_cells, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, skeys, tot, err);
     return hipGetLastError();
 }
 
