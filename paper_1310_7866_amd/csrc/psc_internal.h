@@ -42,8 +42,8 @@ struct SpeciesDev {
     int32_t *cs[2];      // cell start offsets, ncell + 1
     int32_t *perm;       // sorted slot -> index in the pushed buffer
     uint8_t *mc;         // move code of each pushed particle
-    uint16_t *cnt;       // [m * ncell + cell]: particles of `cell` with move m (filled by the
-                         // particle kernel, cleared by the sort's prefix pass)
+    uint16_t *cnt;       // [m * ncell + cell]: particles of `cell` with move m != stay
+                         // (counted by the particle kernel, cleared by the sort's scatter)
     uint16_t *pre;       // [m * ncell + cell]: arrivals into cell+d(m) that precede them
     int32_t *tot;        // arrivals per new cell (scan input)
     int64_t seg;         // index of this (run, species) among scan segments

@@ -802,37 +802,15 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
             }
 
             // ---- per (old cell, move code) counts for the sort ------------------
-            // Lanes of one cell are consecutive; within them, the particles of
-            // one move code form a group (the code's ballot restricted to the
-            // cell's lanes).  The group's first lane adds its size to the 16-bit
-            // counter of (code, cell) through the 32-bit word holding it.
+            // Only particles that change cell are counted (one atomic each on the
+            // 32-bit word holding the 16-bit counter); the sort takes the rest of
+            // a cell's particles as staying.
             {
-                constexpr int M = DIM == 3 ? 27 : 9;
+                constexpr int CENTER = DIM == 3 ? 13 : 4;
                 const int code = DIM == 3 ? (s[0] + 1) + 3 * (s[1] + 1) + 9 * (s[2] + 1) : (s[1] + 1) + 3 * (s[2] + 1);
-                const int mcode = valid ? code : -1;
-                const int ckey = valid ? c : -1;
-                const int left = __shfl_up(ckey, 1, 64);
-                const uint64_t heads = __ballot(lane == 0 || left != ckey);
-                const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
-                const int s0 = 63 - __clzll(heads & upto);
-                const uint64_t above = heads & ~upto;
-                const int e1 = above ? __ffsll((unsigned long long)above) - 1 : 64;
-                const uint64_t mine = (e1 == 64 ? ~0ull : ((1ull << e1) - 1)) & ~((1ull << s0) - 1);
-                uint32_t blo = 0, bhi = 0;   // lane k: ballot of code k
-#pragma unroll
-                for (int k = 0; k < M; ++k) {
-                    const uint64_t bk = __ballot(mcode == k);
-                    if (lane == k) {
-                        blo = (uint32_t)bk;
-                        bhi = (uint32_t)(bk >> 32);
-                    }
-                }
-                const int mm = valid ? mcode : 0;
-                const uint64_t grp = (((uint64_t)(uint32_t)__shfl((int)bhi, mm, 64) << 32) |
-                                      (uint32_t)__shfl((int)blo, mm, 64)) & mine;
-                if (valid && (grp & (upto >> 1)) == 0) {   // no lane of my group below me
-                    const int64_t w = (int64_t)mcode * R.ncell + kb + c;
-                    atomicAdd(cnt32 + (w >> 1), (uint32_t)__popcll(grp) << (16 * (int)(w & 1)));
+                if (valid && code != CENTER) {
+                    const int64_t w = (int64_t)code * R.ncell + kb + c;
+                    atomicAdd(cnt32 + (w >> 1), 1u << (16 * (int)(w & 1)));
                 }
             }
 

@@ -124,8 +124,9 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_prefix(const RunDev *__rest
                                                             const int64_t *__restrict__ seg_base,
                                                             const int32_t *__restrict__ seg_run,
                                                             const int32_t *__restrict__ seg_sp, int n_segs,
-                                                            int64_t total, uint32_t *err) {
+                                                            int64_t total, int cs_sel, uint32_t *err) {
     constexpr int M = DIM == 3 ? 27 : 9;
+    constexpr int CENTER = M / 2;   // the move that stays in the cell
     const int64_t c = (int64_t)blockIdx.x * kSortBlock + threadIdx.x;
     if (c >= total) return;
     const int sg = find_seg(seg_base, n_segs, c);
@@ -137,15 +138,26 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_prefix(const RunDev *__rest
     decode_key(R, n, g);
     int32_t ks[M];
     int32_t cn[M];
+    // arrivals into n from each source (the particle kernel counts the
+    // particles that change cell); those that stay in n are the rest of n
+    const int32_t *cs_old = S.cs[cs_sel];
+    int32_t stay = cs_old[n + 1] - cs_old[n];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         int d[3];
         move_delta(DIM, m, d);
         const int sx = DIM == 3 ? wrap(g[0] - d[0], R.n[0]) : 0;
         ks[m] = (int32_t)encode_key(R, sx, wrap(g[1] - d[1], R.n[1]), wrap(g[2] - d[2], R.n[2]));
-        cn[m] = S.cnt[m * nc + ks[m]];
-        S.cnt[m * nc + ks[m]] = 0;   // read once (each (source, move) has one destination): clear for the next push
+        if (m != CENTER) {
+            cn[m] = S.cnt[m * nc + ks[m]];
+            stay -= S.cnt[m * nc + n];   // leaving n with move m
+        }
     }
+    if (stay < 0) {   // counts inconsistent with the cell offsets
+        atomicOr(err, PSC_DEV_OVERFULL);
+        stay = 0;
+    }
+    cn[CENTER] = stay;
     int32_t tot = 0;
 #pragma unroll
     for (int m = 0; m < M; ++m) {
@@ -196,6 +208,7 @@ __global__ void __launch_bounds__(kSortCells) k_sort_scatter(const RunDev *__res
             const int dx = DIM == 3 ? wrap(g[0] + d[0], R.n[0]) : 0;
             const int64_t dst = encode_key(R, dx, wrap(g[1] + d[1], R.n[1]), wrap(g[2] + d[2], R.n[2]));
             tab[m * 64 + lane] = cs_new[dst] + S.pre[m * nc + o];
+            if (m != M / 2) S.cnt[m * nc + o] = 0;   // consumed by the prefix pass: clear for the next push
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -325,10 +338,10 @@ hipError_t launch_sort(const Launch &L, const int64_t *seg_base, const int32_t *
     // the per (cell, move) counts come from the particle kernel
     if (dim == 3)
         hipLaunchKernelGGL(k_sort_prefix<3>, dim3(grid), dim3(kSortBlock), 0, L.stream, L.runs_dev, seg_base,
-                           seg_run, seg_sp, n_segs, total, L.err);
+                           seg_run, seg_sp, n_segs, total, cs_sel, L.err);
     else
         hipLaunchKernelGGL(k_sort_prefix<2>, dim3(grid), dim3(kSortBlock), 0, L.stream, L.runs_dev, seg_base,
-                           seg_run, seg_sp, n_segs, total, L.err);
+                           seg_run, seg_sp, n_segs, total, cs_sel, L.err);
     hipError_t e = launch_scan(segs_dev, n_segs, n_scan_blocks, block_seg, scan_tmp, L.stream);
     if (e != hipSuccess) return e;
     if (dim == 3)
