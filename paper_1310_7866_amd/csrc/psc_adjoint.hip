@@ -89,15 +89,56 @@ __device__ __forceinline__ float gather2_d(const float *F, int pitch, int iy, in
     return s;
 }
 
-// transpose of the interpolation: scatter lam * weights into an LDS tile
-template <int ORDER>
-__device__ __forceinline__ void scatter2(double *G, int pitch, int iy, int iz, const float *wy, const float *wz,
-                                         float lam) {
-    double *p = G + iz * pitch + iy;
+// Transposed interpolation through per-cell frames.  Along one dimension a
+// particle of a cell touches a fixed window of nodes: order 1 node-centred
+// 0..1, order 2 node-centred -1..2 (the first node moves with the offset),
+// half-centred -1..1 at both orders.  Each lane writes lam * wy * wz over the
+// window of its cell; lanes of one cell are summed with the segmented wave
+// scan and only the last lane of each cell adds the frame to LDS.
+template <int ORDER, bool HALF>
+struct AdjFrame {
+    static constexpr int len = HALF ? 3 : (ORDER == 1 ? 2 : 4);
+    static constexpr int origin = HALF ? -1 : (ORDER == 1 ? 0 : -1);
+};
+
+// the ORDER+1 weights with first node b (relative to the cell) on the window
+template <int ORDER, bool HALF>
+__device__ __forceinline__ void frame_place(int b, const float *w, float *f) {
+    constexpr int n = AdjFrame<ORDER, HALF>::len;
+    if constexpr (n == ORDER + 1) {
 #pragma unroll
-    for (int b = 0; b <= ORDER; ++b)
+        for (int k = 0; k < n; ++k) f[k] = w[k];
+    } else {
+        const bool up = b != AdjFrame<ORDER, HALF>::origin;
 #pragma unroll
-        for (int a = 0; a <= ORDER; ++a) atomicAdd(&p[b * pitch + a], (double)(lam * wy[a] * wz[b]));
+        for (int k = 0; k < n; ++k) f[k] = up ? (k >= 1 ? w[k - 1] : 0.0f) : (k <= ORDER ? w[k] : 0.0f);
+    }
+}
+
+template <int ORDER, bool HY, bool HZ>
+constexpr int frame_size() {
+    return AdjFrame<ORDER, HY>::len * AdjFrame<ORDER, HZ>::len;
+}
+
+template <int ORDER, bool HY, bool HZ>
+__device__ __forceinline__ void frame_put(float *v, float lam, const float *fy, const float *fz) {
+    constexpr int ny = AdjFrame<ORDER, HY>::len, nz = AdjFrame<ORDER, HZ>::len;
+#pragma unroll
+    for (int b = 0; b < nz; ++b) {
+        const float lb = lam * fz[b];
+#pragma unroll
+        for (int a = 0; a < ny; ++a) v[a + ny * b] = lb * fy[a];
+    }
+}
+
+template <int ORDER, bool HY, bool HZ>
+__device__ __forceinline__ void frame_add(double *G, int pitch, int ty, int tz, const float *v) {
+    constexpr int ny = AdjFrame<ORDER, HY>::len, nz = AdjFrame<ORDER, HZ>::len;
+    double *p = G + (tz + AdjFrame<ORDER, HZ>::origin) * pitch + ty + AdjFrame<ORDER, HY>::origin;
+#pragma unroll
+    for (int b = 0; b < nz; ++b)
+#pragma unroll
+        for (int a = 0; a < ny; ++a) lds_add(p + b * pitch + a, v[a + ny * b]);
 }
 
 __device__ __forceinline__ float3 cross3(float3 a, float3 b) {
@@ -240,16 +281,32 @@ __global__ void __launch_bounds__(1024) k_adj_items(const RunDev *__restrict__ r
 // ---------------------------------------------------------------------------
 // the particle adjoint kernel (2-d)
 // ---------------------------------------------------------------------------
+// LDS layout (offsets in floats, regions on 16 bytes): the field tile of E and
+// B1 (6 components, field-tile geometry), the tile of the current adjoint LJ
+// (3 components, current-tile geometry), the transposed-interpolation tile
+// (6 components in double, field-tile geometry).
+struct AdjLds {
+    int lj, gt, total;
+};
+__host__ __device__ inline AdjLds adj_lds_layout(int fcells, int jcells) {
+    AdjLds L{};
+    L.lj = (6 * fcells + 3) & ~3;
+    L.gt = (L.lj + 3 * jcells + 3) & ~3;
+    L.total = L.gt + 12 * fcells;
+    return L;
+}
+
 template <int ORDER>
-__global__ void __launch_bounds__(kBlock) k_adj_particles(const RunDev *__restrict__ runs,
-                                                          const AdjRun *__restrict__ adj,
-                                                          const Unit *__restrict__ units,
-                                                          const int32_t *__restrict__ item_start, int n_units,
-                                                          int chunk) {
-    extern __shared__ __align__(16) float lds[];   // 16-byte aligned: holds doubles and float4
+__global__ void __launch_bounds__(kAdjBlock) k_adj_particles(const RunDev *__restrict__ runs,
+                                                             const AdjRun *__restrict__ adj,
+                                                             const Unit *__restrict__ units,
+                                                             const int32_t *__restrict__ item_start, int n_units,
+                                                             int chunk) {
+    extern __shared__ __align__(16) float lds[];   // 16-byte aligned: holds doubles
     constexpr int L = ORDER + 2;
     constexpr int FLO = 1, FHI = ORDER;
-    constexpr int JLO = ORDER;
+    constexpr int JLO = ORDER, JHI = ORDER + 1;
+    constexpr int NT = kAdjBlock;
 
     const int nb = gridDim.x;
     const int item = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
@@ -277,14 +334,18 @@ __global__ void __launch_bounds__(kBlock) k_adj_particles(const RunDev *__restri
 
     const int fy = R.P[1] + FLO + FHI, fz = R.P[2] + FLO + FHI;
     const int fcells = fy * fz;
+    const int jy = R.P[1] + JLO + JHI, jz = R.P[2] + JLO + JHI;
+    const int jcells = jy * jz;
+    const AdjLds LL = adj_lds_layout(fcells, jcells);
     float *ftile = lds;               // E, B1
+    float *ljt = lds + LL.lj;         // LJ
     // transposed interpolation of E, B1, accumulated in double (the LDS add
     // of doubles runs at the rate of integer atomics, the float one far slower)
-    double *gt = reinterpret_cast<double *>(lds + ((6 * fcells + 3) & ~3));
+    double *gt = reinterpret_cast<double *>(lds + LL.gt);
     const int64_t nc = R.ncell;
     {
         const float inv_fy = 1.0f / fy;
-        for (int t = threadIdx.x; t < fcells; t += kBlock) {
+        for (int t = threadIdx.x; t < fcells; t += NT) {
             int ty;
             const int tz = divmod_small(t, fy, inv_fy, ty);
             const int64_t g = wrap(oy + ty - FLO, R.n[1]) + (int64_t)R.n[1] * wrap(oz + tz - FLO, R.n[2]);
@@ -294,7 +355,15 @@ __global__ void __launch_bounds__(kBlock) k_adj_particles(const RunDev *__restri
                 ftile[(3 + c) * fcells + t] = A.B1[c * nc + g];
             }
         }
-        for (int t = threadIdx.x; t < 6 * fcells; t += kBlock) gt[t] = 0.0;
+        const float inv_jy = 1.0f / jy;
+        for (int t = threadIdx.x; t < jcells; t += NT) {
+            int ty;
+            const int tz = divmod_small(t, jy, inv_jy, ty);
+            const int64_t g = wrap(oy + ty - JLO, R.n[1]) + (int64_t)R.n[1] * wrap(oz + tz - JLO, R.n[2]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ljt[c * jcells + t] = A.LJ[c * nc + g];
+        }
+        for (int t = threadIdx.x; t < 6 * fcells; t += NT) gt[t] = 0.0;
     }
     __syncthreads();
 
@@ -303,9 +372,12 @@ __global__ void __launch_bounds__(kBlock) k_adj_particles(const RunDev *__restri
     const float cfy = dt * R.inv_dx[1], cfz = dt * R.inv_dx[2];
     const float jfy = -qw * R.dx[1] / dt, jfz = -qw * R.dx[2] / dt;
     const float inv_hy = 1.0f / hy;
-    const int ny = R.n[1], nzc = R.n[2];
 
-    for (int32_t i = beg + threadIdx.x; i < end; i += kBlock) {
+    // every round gives each thread one particle; the rounds are uniform over
+    // the workgroup so that the wave scans see all lanes
+    for (int32_t base = beg; base < end; base += NT) {
+        const bool valid = base + (int32_t)threadIdx.x < end;
+        const int32_t i = valid ? base + (int32_t)threadIdx.x : beg;
         const int32_t key = AS.key[i];
         int local = key - (int32_t)kb;
         if (local < 0 || local >= hy * hz) local = 0;
@@ -374,7 +446,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_particles(const RunDev *__restri
         float lo0[2] = {0.0f, 0.0f};
         float lig = 0.0f;
 
-        // deposit: J values on the stencil, adjoint read from the grid
+        // deposit: J values on the stencil, adjoint read from the LJ tile
         {
             float S0y[L], S1y[L], S0z[L], S1z[L], D0y[L], D1y[L], D0z[L], D1z[L];
             const int by = stencil_d<ORDER>(oyv, sh[0], o1[0], S0y, S1y, D0y, D1y);
@@ -395,14 +467,13 @@ __global__ void __launch_bounds__(kBlock) k_adj_particles(const RunDev *__restri
 #pragma unroll
             for (int r = 0; r < L; ++r) gCy[r] = gCz[r] = gAy[r] = gAz[r] = gDy[r] = gDz[r] = 0.0f;
             float gfxv = 0.0f;
-            const int gy0 = oy + ly + by, gz0 = oz + lz + bz;
+            const float *lj = ljt + (lz + bz + JLO) * jy + (ly + by + JLO);
 #pragma unroll
             for (int b = 0; b < L; ++b) {
-                const int64_t row = (int64_t)ny * wrap(gz0 + b, nzc);
 #pragma unroll
                 for (int a = 0; a < L; ++a) {
-                    const int64_t g = row + wrap(gy0 + a, ny);
-                    const float ljx = A.LJ[g], ljy = A.LJ[nc + g], ljz = A.LJ[2 * nc + g];
+                    const int q = b * jy + a;
+                    const float ljx = lj[q], ljy = lj[jcells + q], ljz = lj[2 * jcells + q];
                     if (a < L - 1) {   // J_y(a, b) = jfy Cy[a] Az[b]
                         gCy[a] += jfy * ljy * Az[b];
                         gAz[b] += jfy * ljy * Cy[a];
@@ -468,26 +539,69 @@ __global__ void __launch_bounds__(kBlock) k_adj_particles(const RunDev *__restri
         lE = add3(lE, scale3(lum, h));
         const float3 lu0 = lum;
 
-        // interpolation reverse: offsets and scatter into the tiles
+        // interpolation reverse: offsets, then the transposed interpolation
+        // through per-cell frames (lanes past the end add zeros in a segment
+        // of their own)
         const float lF[6] = {lE.x, lE.y, lE.z, lB.x, lB.y, lB.z};
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
             lo0[0] += lF[c] * Gy[c];
             lo0[1] += lF[c] * Gz[c];
-            const bool hyc = c == 1 || c == 3 || c == 5;
-            const bool hzc = c == 2 || c == 3 || c == 4;
-            scatter2<ORDER>(gt + c * fcells, fy, cy_[c], cz_[c], hyc ? why : wny, hzc ? whz : wnz, lF[c]);
         }
-
-        AS.loff[i] = lo0[0];
-        AS.loff[n + i] = lo0[1];
-        AS.lu[i] = lu0.x;
-        AS.lu[n + i] = lu0.y;
-        AS.lu[2 * n + i] = lu0.z;
+        if (valid) {
+            AS.loff[i] = lo0[0];
+            AS.loff[n + i] = lo0[1];
+            AS.lu[i] = lu0.x;
+            AS.lu[n + i] = lu0.y;
+            AS.lu[2 * n + i] = lu0.z;
+        }
+        float fny[AdjFrame<ORDER, false>::len], fhy[AdjFrame<ORDER, true>::len];
+        float fnz[AdjFrame<ORDER, false>::len], fhz[AdjFrame<ORDER, true>::len];
+        frame_place<ORDER, false>(bny, wny, fny);
+        frame_place<ORDER, true>(bhy, why, fhy);
+        frame_place<ORDER, false>(bnz, wnz, fnz);
+        frame_place<ORDER, true>(bhz, whz, fhz);
+        const float vm = valid ? 1.0f : 0.0f;
+        const RowScan rs = row_scan_setup<64>(valid ? local : -1);
+        const bool add = rs.tail && valid;
+        {   // E: (node, node), (half, node), (node, half)
+            constexpr int n0 = frame_size<ORDER, false, false>(), n1 = frame_size<ORDER, true, false>();
+            constexpr int n2 = frame_size<ORDER, false, true>();
+            constexpr int NV = (n0 + n1 + n2 + 3) & ~3;
+            float v[NV];
+#pragma unroll
+            for (int k = n0 + n1 + n2; k < NV; ++k) v[k] = 0.0f;
+            frame_put<ORDER, false, false>(v, vm * lF[0], fny, fnz);
+            frame_put<ORDER, true, false>(v + n0, vm * lF[1], fhy, fnz);
+            frame_put<ORDER, false, true>(v + n0 + n1, vm * lF[2], fny, fhz);
+            row_scan<64>(v, rs);
+            if (add) {
+                frame_add<ORDER, false, false>(gt, fy, ty, tz, v);
+                frame_add<ORDER, true, false>(gt + fcells, fy, ty, tz, v + n0);
+                frame_add<ORDER, false, true>(gt + 2 * fcells, fy, ty, tz, v + n0 + n1);
+            }
+        }
+        {   // B: (half, half), (node, half), (half, node)
+            constexpr int n0 = frame_size<ORDER, true, true>(), n1 = frame_size<ORDER, false, true>();
+            constexpr int n2 = frame_size<ORDER, true, false>();
+            constexpr int NV = (n0 + n1 + n2 + 3) & ~3;
+            float v[NV];
+#pragma unroll
+            for (int k = n0 + n1 + n2; k < NV; ++k) v[k] = 0.0f;
+            frame_put<ORDER, true, true>(v, vm * lF[3], fhy, fhz);
+            frame_put<ORDER, false, true>(v + n0, vm * lF[4], fny, fhz);
+            frame_put<ORDER, true, false>(v + n0 + n1, vm * lF[5], fhy, fnz);
+            row_scan<64>(v, rs);
+            if (add) {
+                frame_add<ORDER, true, true>(gt + 3 * fcells, fy, ty, tz, v);
+                frame_add<ORDER, false, true>(gt + 4 * fcells, fy, ty, tz, v + n0);
+                frame_add<ORDER, true, false>(gt + 5 * fcells, fy, ty, tz, v + n0 + n1);
+            }
+        }
     }
     __syncthreads();
     float *gp = A.gtile + (int64_t)U.patch * 6 * fcells;
-    for (int t2 = threadIdx.x; t2 < 6 * fcells; t2 += kBlock) {
+    for (int t2 = threadIdx.x; t2 < 6 * fcells; t2 += NT) {
         const double v = gt[t2];
         if (v != 0.0) atomicAdd(&gp[t2], (float)v);
     }
@@ -551,8 +665,9 @@ __global__ void __launch_bounds__(256) k_adj_fold(const RunDev *__restrict__ run
 }
 
 size_t adjoint_lds_bytes(int order, const int P[3]) {
-    const int fy = P[1] + 1 + order, fz = P[2] + 1 + order;
-    return sizeof(float) * (((6 * (size_t)fy * fz + 3) & ~(size_t)3) + 12 * (size_t)fy * fz);
+    const int fcells = (P[1] + 1 + order) * (P[2] + 1 + order);
+    const int jcells = (P[1] + 2 * order + 1) * (P[2] + 2 * order + 1);
+    return sizeof(float) * (size_t)adj_lds_layout(fcells, jcells).total;
 }
 
 hipError_t launch_adjoint(const Launch &L, const AdjRun *adj_dev, const AdjRun *adj_host, const Unit *units,
@@ -592,10 +707,10 @@ hipError_t launch_adjoint(const Launch &L, const AdjRun *adj_dev, const AdjRun *
     int64_t grid = (max_items + 7) / 8 * 8;
     if (grid < 8) grid = 8;
     if (order == 1)
-        hipLaunchKernelGGL(k_adj_particles<1>, dim3((unsigned)grid), dim3(kBlock), lds, s, L.runs_dev, adj_dev, units,
+        hipLaunchKernelGGL(k_adj_particles<1>, dim3((unsigned)grid), dim3(kAdjBlock), lds, s, L.runs_dev, adj_dev, units,
                            item_start, n_units, chunk);
     else
-        hipLaunchKernelGGL(k_adj_particles<2>, dim3((unsigned)grid), dim3(kBlock), lds, s, L.runs_dev, adj_dev, units,
+        hipLaunchKernelGGL(k_adj_particles<2>, dim3((unsigned)grid), dim3(kAdjBlock), lds, s, L.runs_dev, adj_dev, units,
                            item_start, n_units, chunk);
     // (5) transposed interpolation into lE, lB1
     hipLaunchKernelGGL(k_adj_fold, dim3(gc), dim3(256), 0, s, L.runs_dev, adj_dev, L.n_runs, run_base, total_cells);

@@ -65,6 +65,7 @@ struct psc_ctx {
     // adjoint scratch (PSC_RUN_ADJOINT)
     bool adjoint = false;
     size_t adj_lds = 0;
+    int64_t adj_items = 0;                  // work items of the particle adjoint (kAdjChunk particles)
     std::vector<AdjRun> adj;                 // host mirror of the adjoint table
     std::vector<size_t> off_b1, off_lj, off_gt;
     std::vector<std::vector<size_t>> off_soff, off_su, off_acs, off_atot;
@@ -325,8 +326,10 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
                 ctx->off_su[r][s] = take(sizeof(float) * 3 * R.sp[s].cap);
                 ctx->off_acs[r][s] = take(sizeof(int32_t) * (R.ncell + 1));
                 ctx->off_atot[r][s] = take(sizeof(int32_t) * R.ncell);
+                ctx->adj_items += (R.sp[s].cap + kAdjChunk - 1) / kAdjChunk;
             }
         }
+        ctx->adj_items += (int64_t)ctx->units.size();
         if (ctx->adj_lds > kMaxLds) {
             psc_status st = fail(ctx, PSC_ERR_LDS, "adjoint patch tiles do not fit in 160 KiB of LDS");
             delete ctx;
@@ -842,7 +845,7 @@ psc_status psc_adjoint_step(psc_ctx *ctx, const psc_adj_fwd *fwd, const psc_adj_
                             hipMemcpyHostToDevice, s), "upload adjoint table");
     Launch L = make_launch(ctx, s);
     HIPCHECK(launch_adjoint(L, ctx->at<AdjRun>(ctx->off.adj_runs), ctx->adj.data(), ctx->at<Unit>(ctx->off.units),
-                            (int)ctx->units.size(), ctx->at<int32_t>(ctx->off.item_start), ctx->max_items, ctx->chunk,
+                            (int)ctx->units.size(), ctx->at<int32_t>(ctx->off.item_start), ctx->adj_items, kAdjChunk,
                             ctx->order, ctx->total_cells, ctx->at<int64_t>(ctx->off.run_base),
                             ctx->at<ScanSeg>(ctx->off.adj_segs), ctx->at<int32_t>(ctx->off.load_blockseg),
                             ctx->at<int32_t>(ctx->off.load_sums), ctx->adj_lds, s),

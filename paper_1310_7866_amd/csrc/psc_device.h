@@ -153,5 +153,90 @@ using gptr = __attribute__((address_space(1))) T *;
 template <typename T>
 __device__ __forceinline__ gptr<T> to_global(T *p) { return (gptr<T>)p; }
 
+// ---------------------------------------------------------------------------
+// wave-level segmented sums (DPP) for frame sums of sorted particles
+// ---------------------------------------------------------------------------
+// Particles are sorted by cell, so the 64 lanes of a wave mostly share one or
+// two cells and would hit the same LDS words with atomics.  Instead each lane
+// writes what it adds (current, or the transposed interpolation of the
+// adjoint) into a fixed per-cell frame and the wave forms segmented
+// inclusive sums (segment = run of lanes with equal cell) over rows of SW
+// lanes: DPP row shifts and row broadcasts, each multiplied by a per-lane
+// 0/1 mask that is 1 only where the source lane lies in the same segment, so
+// every step is one DPP multiply-add.  The last lane of each segment piece
+// within a row group then adds the piece's sum to LDS.
+struct RowScan {
+    float m[6];    // multipliers of the six steps (1: source lane in my segment)
+    bool tail;     // last lane of its segment within its group of SW lanes
+};
+
+template <int SW>
+__device__ __forceinline__ RowScan row_scan_setup(int key) {
+    const int lane = threadIdx.x & 63;
+    const int left = __shfl_up(key, 1, 64);
+    const uint64_t heads = __ballot(lane == 0 || left != key);
+    const uint64_t le = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+    const int start = 63 - __clzll(heads & le);   // first lane of my segment
+    const int row0 = lane & ~15;
+    const int d = lane - (start > row0 ? start : row0);
+    RowScan r;
+    r.m[0] = d >= 1 ? 1.0f : 0.0f;
+    r.m[1] = d >= 2 ? 1.0f : 0.0f;
+    r.m[2] = d >= 4 ? 1.0f : 0.0f;
+    r.m[3] = d >= 8 ? 1.0f : 0.0f;
+    r.m[4] = ((lane & 16) && start < row0) ? 1.0f : 0.0f;   // from the last lane of the row below
+    r.m[5] = (lane >= 32 && start < 32) ? 1.0f : 0.0f;     // from lane 31
+    r.tail = lane == 63 || ((heads >> (lane + 1)) & 1ull) || (lane & (SW - 1)) == SW - 1;
+    return r;
+}
+
+// Segmented inclusive sums of four independent values: every step is one
+// v_fmac_f32_dpp (v += m * v[source lane]).  The four chains are interleaved
+// so that a value is read through DPP three instructions after it was
+// written (the hardware wants two wait states between a VALU write and a DPP
+// read of the same register, five after a VALU write of EXEC; the leading
+// s_nop covers whatever precedes the block).  Rows not selected by a
+// broadcast's row mask keep their value.  The block is volatile: it reads
+// other lanes, so it must stay where every lane of the wave executes it.
+#define PSC_FMAC_DPP(CTL, M) \
+    "v_fmac_f32_dpp %0, %0, " M " " CTL "\n\t" \
+    "v_fmac_f32_dpp %1, %1, " M " " CTL "\n\t" \
+    "v_fmac_f32_dpp %2, %2, " M " " CTL "\n\t" \
+    "v_fmac_f32_dpp %3, %3, " M " " CTL "\n\t"
+#define PSC_SHR(N) "row_shr:" #N " row_mask:0xf bank_mask:0xf bound_ctrl:1"
+
+template <int SW>
+__device__ __forceinline__ void row_scan4(float &a, float &b, float &c, float &d, const RowScan &r) {
+    if constexpr (SW == 16) {
+        asm volatile("s_nop 4\n\t" PSC_FMAC_DPP(PSC_SHR(1), "%4") PSC_FMAC_DPP(PSC_SHR(2), "%5")
+                PSC_FMAC_DPP(PSC_SHR(4), "%6") PSC_FMAC_DPP(PSC_SHR(8), "%7")
+            : "+v"(a), "+v"(b), "+v"(c), "+v"(d)
+            : "v"(r.m[0]), "v"(r.m[1]), "v"(r.m[2]), "v"(r.m[3]));
+    } else if constexpr (SW == 32) {
+        asm volatile("s_nop 4\n\t" PSC_FMAC_DPP(PSC_SHR(1), "%4") PSC_FMAC_DPP(PSC_SHR(2), "%5")
+                PSC_FMAC_DPP(PSC_SHR(4), "%6") PSC_FMAC_DPP(PSC_SHR(8), "%7")
+                    PSC_FMAC_DPP("row_bcast:15 row_mask:0xa bank_mask:0xf", "%8")
+            : "+v"(a), "+v"(b), "+v"(c), "+v"(d)
+            : "v"(r.m[0]), "v"(r.m[1]), "v"(r.m[2]), "v"(r.m[3]), "v"(r.m[4]));
+    } else {
+        static_assert(SW == 64, "scan width 16, 32 or 64");
+        asm volatile("s_nop 4\n\t" PSC_FMAC_DPP(PSC_SHR(1), "%4") PSC_FMAC_DPP(PSC_SHR(2), "%5")
+                PSC_FMAC_DPP(PSC_SHR(4), "%6") PSC_FMAC_DPP(PSC_SHR(8), "%7")
+                    PSC_FMAC_DPP("row_bcast:15 row_mask:0xa bank_mask:0xf", "%8")
+                        PSC_FMAC_DPP("row_bcast:31 row_mask:0xc bank_mask:0xf", "%9")
+            : "+v"(a), "+v"(b), "+v"(c), "+v"(d)
+            : "v"(r.m[0]), "v"(r.m[1]), "v"(r.m[2]), "v"(r.m[3]), "v"(r.m[4]), "v"(r.m[5]));
+    }
+}
+#undef PSC_SHR
+#undef PSC_FMAC_DPP
+
+// segmented sums of N values (N a multiple of 4) in place
+template <int SW, int N>
+__device__ __forceinline__ void row_scan(float (&v)[N], const RowScan &r) {
+    static_assert(N % 4 == 0, "values come in groups of four");
+#pragma unroll
+    for (int k = 0; k < N; k += 4) row_scan4<SW>(v[k], v[k + 1], v[k + 2], v[k + 3], r);
+}
 
 }  // namespace psc

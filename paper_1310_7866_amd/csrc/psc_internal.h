@@ -27,6 +27,8 @@ constexpr int kMaxSpecies = PSC_MAX_SPECIES;
 constexpr int kBlock = 256;          // threads per workgroup of the particle kernel
 constexpr int kScanPerThread = 8;    // elements per thread in the scans
 constexpr int kScanBlock = 256 * kScanPerThread;
+constexpr int kAdjBlock = 512;       // threads per workgroup of the particle adjoint
+constexpr int kAdjChunk = 2048;      // particles per work item of the particle adjoint
 
 struct SpeciesDev {
     float q, m, w;

@@ -120,91 +120,6 @@ __global__ void __launch_bounds__(1024) k_build_items(const RunDev *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-// wave-level segmented sums (DPP) for the current deposit
-// ---------------------------------------------------------------------------
-// Particles are sorted by cell, so the 64 lanes of a wave mostly share one or
-// two cells and would hit the same LDS words with atomics.  Instead each lane
-// writes its current into a fixed per-cell frame and the wave forms segmented
-// inclusive sums (segment = run of lanes with equal cell) over rows of SW
-// lanes: DPP row shifts and row broadcasts, each multiplied by a per-lane
-// 0/1 mask that is 1 only where the source lane lies in the same segment, so
-// every step is one DPP multiply-add.  The last lane of each segment piece
-// within a row group then adds the piece's sum to LDS.
-struct RowScan {
-    float m[6];    // multipliers of the six steps (1: source lane in my segment)
-    bool tail;     // last lane of its segment within its group of SW lanes
-};
-
-template <int SW>
-__device__ __forceinline__ RowScan row_scan_setup(int key) {
-    const int lane = threadIdx.x & 63;
-    const int left = __shfl_up(key, 1, 64);
-    const uint64_t heads = __ballot(lane == 0 || left != key);
-    const uint64_t le = lane == 63 ? ~0ull : ((2ull << lane) - 1);
-    const int start = 63 - __clzll(heads & le);   // first lane of my segment
-    const int row0 = lane & ~15;
-    const int d = lane - (start > row0 ? start : row0);
-    RowScan r;
-    r.m[0] = d >= 1 ? 1.0f : 0.0f;
-    r.m[1] = d >= 2 ? 1.0f : 0.0f;
-    r.m[2] = d >= 4 ? 1.0f : 0.0f;
-    r.m[3] = d >= 8 ? 1.0f : 0.0f;
-    r.m[4] = ((lane & 16) && start < row0) ? 1.0f : 0.0f;   // from the last lane of the row below
-    r.m[5] = (lane >= 32 && start < 32) ? 1.0f : 0.0f;     // from lane 31
-    r.tail = lane == 63 || ((heads >> (lane + 1)) & 1ull) || (lane & (SW - 1)) == SW - 1;
-    return r;
-}
-
-// Segmented inclusive sums of four independent values: every step is one
-// v_fmac_f32_dpp (v += m * v[source lane]).  The four chains are interleaved
-// so that a value is read through DPP three instructions after it was
-// written (the hardware wants two wait states between a VALU write and a DPP
-// read of the same register, five after a VALU write of EXEC; the leading
-// s_nop covers whatever precedes the block).  Rows not selected by a
-// broadcast's row mask keep their value.  The block is volatile: it reads
-// other lanes, so it must stay where every lane of the wave executes it.
-#define PSC_FMAC_DPP(CTL, M) \
-    "v_fmac_f32_dpp %0, %0, " M " " CTL "\n\t" \
-    "v_fmac_f32_dpp %1, %1, " M " " CTL "\n\t" \
-    "v_fmac_f32_dpp %2, %2, " M " " CTL "\n\t" \
-    "v_fmac_f32_dpp %3, %3, " M " " CTL "\n\t"
-#define PSC_SHR(N) "row_shr:" #N " row_mask:0xf bank_mask:0xf bound_ctrl:1"
-
-template <int SW>
-__device__ __forceinline__ void row_scan4(float &a, float &b, float &c, float &d, const RowScan &r) {
-    if constexpr (SW == 16) {
-        asm volatile("s_nop 4\n\t" PSC_FMAC_DPP(PSC_SHR(1), "%4") PSC_FMAC_DPP(PSC_SHR(2), "%5")
-                PSC_FMAC_DPP(PSC_SHR(4), "%6") PSC_FMAC_DPP(PSC_SHR(8), "%7")
-            : "+v"(a), "+v"(b), "+v"(c), "+v"(d)
-            : "v"(r.m[0]), "v"(r.m[1]), "v"(r.m[2]), "v"(r.m[3]));
-    } else if constexpr (SW == 32) {
-        asm volatile("s_nop 4\n\t" PSC_FMAC_DPP(PSC_SHR(1), "%4") PSC_FMAC_DPP(PSC_SHR(2), "%5")
-                PSC_FMAC_DPP(PSC_SHR(4), "%6") PSC_FMAC_DPP(PSC_SHR(8), "%7")
-                    PSC_FMAC_DPP("row_bcast:15 row_mask:0xa bank_mask:0xf", "%8")
-            : "+v"(a), "+v"(b), "+v"(c), "+v"(d)
-            : "v"(r.m[0]), "v"(r.m[1]), "v"(r.m[2]), "v"(r.m[3]), "v"(r.m[4]));
-    } else {
-        static_assert(SW == 64, "scan width 16, 32 or 64");
-        asm volatile("s_nop 4\n\t" PSC_FMAC_DPP(PSC_SHR(1), "%4") PSC_FMAC_DPP(PSC_SHR(2), "%5")
-                PSC_FMAC_DPP(PSC_SHR(4), "%6") PSC_FMAC_DPP(PSC_SHR(8), "%7")
-                    PSC_FMAC_DPP("row_bcast:15 row_mask:0xa bank_mask:0xf", "%8")
-                        PSC_FMAC_DPP("row_bcast:31 row_mask:0xc bank_mask:0xf", "%9")
-            : "+v"(a), "+v"(b), "+v"(c), "+v"(d)
-            : "v"(r.m[0]), "v"(r.m[1]), "v"(r.m[2]), "v"(r.m[3]), "v"(r.m[4]), "v"(r.m[5]));
-    }
-}
-#undef PSC_SHR
-#undef PSC_FMAC_DPP
-
-// segmented sums of N values (N a multiple of 4) in place
-template <int SW, int N>
-__device__ __forceinline__ void row_scan(float (&v)[N], const RowScan &r) {
-    static_assert(N % 4 == 0, "values come in groups of four");
-#pragma unroll
-    for (int k = 0; k < N; k += 4) row_scan4<SW>(v[k], v[k + 1], v[k + 2], v[k + 3], r);
-}
-
-// ---------------------------------------------------------------------------
 // Esirkepov current of one particle, added lane by lane with LDS atomics
 // (general stencil: used for particles whose support changes cell)
 // ---------------------------------------------------------------------------
@@ -365,18 +280,18 @@ __device__ __forceinline__ int frame_offset(int j, int jx_, int jy_, int jcells)
 // the chunk's current into the patch tile.  Ends with a barrier so the caller
 // may start the next item on the same LDS.
 //
-// The chunk's particles are sorted by cell.  A cell with n particles gets
-// r = ceil(n / K) lanes ("runs"); member q of the cell's lanes pushes the
-// cell's particles q, q + r, q + 2r, ... one after another, adding the
+// The chunk's particles are sorted by cell.  Lane g of a round pushes the K
+// consecutive particles beg + g K + j (j < K) one after another (K = 1 is
+// its own instantiation, with coalesced loads and stores), adding the
 // Esirkepov current of those whose interpolation support keeps its nodes
-// into a per-cell frame held in registers.  (Interleaving the cell's
-// particles over its lanes keeps every step's loads and stores contiguous
-// per cell.)  At the end of a round the wave forms segmented sums of the
-// frames over lanes of equal cell (the lanes of a cell are consecutive) and
-// the last lane of each segment adds them to the LDS current tile: one scan
-// and one set of LDS atomics per K particles of a lane.  Particles whose
-// support changes nodes wait in a per-wave queue and are deposited in
-// batches with per-lane LDS atomics.
+// and whose cell is the one of the lane's first particle into a per-cell
+// frame held in registers.  At the end of a round the wave forms segmented
+// sums of the frames over lanes of equal cell (consecutive, since the
+// particles are sorted) and the last lane of each segment adds them to the
+// LDS current tile: one scan and one set of LDS atomics per K particles of a
+// lane.  The other particles (support changes nodes, or a later cell than
+// the lane's frame) wait in a per-wave queue and are deposited in batches
+// with per-lane LDS atomics.
 template <int DIM, int ORDER, int NT, bool RUNS>
 __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const Unit *__restrict__ units,
                                           const int32_t *__restrict__ item_start, int lo, int item, int chunk,
@@ -420,7 +335,6 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
     const int jx_ = DIM == 3 ? R.P[0] + JLO + JHI : 1;
     const int jy_ = R.P[1] + JLO + JHI, jz_ = R.P[2] + JLO + JHI;
     const int jcells = jx_ * jy_ * jz_;
-    const int npc = (DIM == 3 ? R.P[0] : 1) * R.P[1] * R.P[2];
     // 6 * fcells: 3-d Ex Ey Ez Bx By Bz; 2-d Ex, Bx, then (Ey, Bz) and
     // (Ez, By) interleaved in pairs: the two of a pair share their staggering,
     // so one 8-byte LDS read serves both
@@ -437,14 +351,9 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
     // (field-major) for each of QS slots
     float *cq = lds + LL.queue + (threadIdx.x >> 6) * (QS * QW);
     float *pk = lds + LL.stage + (threadIdx.x >> 6) * align4(PKW);
-    // cell table: clamped first particle of every cell (npc + 1), run prefix
-    // (npc + 1), per-wave sums of the prefix scan (NT / 64)
-    int32_t *ccs = reinterpret_cast<int32_t *>(lds + LL.table);
-    int32_t *crs = ccs + (npc + 1);
-    int32_t *wsum = crs + (npc + 1);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
-    // stage E, B (+ghosts), clear the current tile, clamp the cell offsets
+    // stage E, B (+ghosts), clear the current tile
     {
         const float inv_fx = 1.0f / fx, inv_fy = 1.0f / fy;
         const int64_t nc = R.ncell;
@@ -475,46 +384,15 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
             }
         }
         for (int t = threadIdx.x; t < 3 * jcells; t += NT) jtile[t] = 0.0;
-        if constexpr (RUNS) {   // the cell table exists only with runs
-            for (int c = threadIdx.x; c <= pcells; c += NT) {
-                const int32_t v = cs[kb + c];
-                ccs[c] = v < beg ? beg : (v > end ? end : v);
-            }
-        }
     }
     __syncthreads();
 
     // without runs (K = 1, a separate instantiation: its registers are not
     // sized for the run accumulators) lane t of a round takes particle
-    // beg + r0 + t (coalesced) and its cell comes from its key; no cell
-    // table is needed
+    // beg + r0 + t, so loads and stores are coalesced
     constexpr bool single = !RUNS;
     if constexpr (single) K = 1;
-    // runs per cell (ceil(particles / K)) and their exclusive prefix
-    if (!single) {
-        const int per = (pcells + NT - 1) / NT;
-        const int c0 = imin((int)threadIdx.x * per, pcells), c1 = imin(c0 + per, pcells);
-        int32_t sum = 0;
-        for (int c = c0; c < c1; ++c) sum += (ccs[c + 1] - ccs[c] + K - 1) / K;
-        int32_t x = sum;   // inclusive scan over the wave
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int32_t y = __shfl_up(x, d, 64);
-            if (lane >= d) x += y;
-        }
-        if (lane == 63) wsum[wave] = x;
-        __syncthreads();
-        int32_t run = x - sum;
-        for (int w = 0; w < wave; ++w) run += wsum[w];
-        for (int c = c0; c < c1; ++c) {
-            crs[c] = run;
-            run += (ccs[c + 1] - ccs[c] + K - 1) / K;
-        }
-        if (threadIdx.x == NT - 1) crs[pcells] = run;
-        __syncthreads();
-    }
-    const int32_t nruns = single ? end - beg : crs[pcells];
-
+    const int32_t nruns = (end - beg + K - 1) / K;   // lanes' strips of K particles
     const int in = front, outb = 1 - front;
     const gptr<const int32_t> cell_in = to_global<const int32_t>(S.cell[in]);
     const gptr<const float> off_in = to_global<const float>(S.off[in]);
@@ -564,26 +442,10 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
     // current and write nothing
     for (int32_t r0 = 0; r0 < nruns; r0 += NT) {
         const int32_t g = r0 + (int32_t)threadIdx.x;
-        int c = 0;
-        int32_t first = beg, nleft = 0, stride = 1;   // particle j: first + j * stride while j*stride < nleft
-        if (single) {
-            first = beg + g;
-            nleft = g < nruns ? 1 : 0;
-        } else if (g < nruns) {
-            int a = 0, b = pcells;   // crs[a] <= g < crs[b]
-            while (b - a > 1) {
-                const int m = (a + b) >> 1;
-                if (crs[m] <= g) a = m;
-                else b = m;
-            }
-            c = a;
-            const int32_t q = g - crs[c];
-            stride = crs[c + 1] - crs[c];
-            first = ccs[c] + q;
-            nleft = ccs[c + 1] - ccs[c] - q;
-        }
-        const int32_t len = nleft > 0 ? (nleft + stride - 1) / stride : 0;   // this lane's particles
-        int lx = 0, ly = 0, lz = 0;
+        const int32_t first = beg + g * K;                       // this lane's strip
+        const int32_t len = g < nruns ? imin(K, end - first) : 0;
+        int c = 0, cf = -1;   // particle's cell, cell of the lane's frame
+        int lx = 0, ly = 0, lz = 0, fx_ = 0, fy_ = 0, fz_ = 0;
         auto cell_coords = [&]() {
             if constexpr (DIM == 3) {
                 const int q = divmod_small(c, hx, inv_hx, lx);
@@ -592,7 +454,6 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
                 lz = divmod_small(c, hy, inv_hy, ly);
             }
         };
-        if (!single) cell_coords();
         float acc[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] = 0.0f;
@@ -601,22 +462,24 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
             const bool valid = j < len;
             // lanes without a particle stand in with the chunk's first
             // particle (taken through the permutation, so it lies in range)
-            const int32_t slot = valid ? first + j * stride : beg;
+            const int32_t slot = valid ? first + j : beg;
             int32_t src = use_perm ? perm[slot] : slot;
             if ((uint32_t)src >= (uint32_t)S.n) {   // corrupt permutation: stay in bounds
                 if (valid) flags |= PSC_DEV_KEY;
                 src = slot;
             }
             const int32_t key = cell_in[src];
-            if (single) {   // the cell is the particle's own
-                c = key - (int32_t)kb;
-                if (c < 0 || c >= pcells) {   // not in this patch: corrupt state
-                    if (valid) flags |= PSC_DEV_KEY;
-                    c = 0;
-                }
-                cell_coords();
-            } else if (valid && key != (int32_t)kb + c) {
-                flags |= PSC_DEV_KEY;   // not the cell the order says
+            c = key - (int32_t)kb;
+            if (c < 0 || c >= pcells) {   // not in this patch: corrupt state
+                if (valid) flags |= PSC_DEV_KEY;
+                c = 0;
+            }
+            cell_coords();
+            if (j == 0 && valid) {   // the lane's frame lies at its first particle's cell
+                cf = c;
+                fx_ = lx;
+                fy_ = ly;
+                fz_ = lz;
             }
             float o[3];
             o[0] = DIM == 3 ? off_in[src] : 0.0f;
@@ -698,7 +561,8 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
                 if (valid)
                     deposit_lane<DIM, ORDER>(jtile, jcells, jx_, jy_, lx, ly, lz, o, s, o1, jfx, jfy, jfz, fxv);
             } else {
-                bool frame = valid && stays<ORDER>(o[1], s[1], o1[1]) && stays<ORDER>(o[2], s[2], o1[2]);
+                bool frame = valid && (single || c == cf) && stays<ORDER>(o[1], s[1], o1[1]) &&
+                             stays<ORDER>(o[2], s[2], o1[2]);
                 if constexpr (DIM == 3) frame = frame && stays<ORDER>(o[0], s[0], o1[0]);
 
                 // support changes nodes: to the wave's queue; a full queue is
@@ -844,12 +708,12 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
 
         // ---- the round's frames: segmented sums over lanes of one cell ------
         if constexpr (kReduce) {
-            const RowScan rs = row_scan_setup<SW>(len > 0 ? c : -1);
+            const RowScan rs = row_scan_setup<SW>(cf);
             row_scan<SW>(acc, rs);
             const bool put = rs.tail && len > 0;
             int base;
-            if constexpr (DIM == 2) base = (lz + FB + JLO) * jy_ + (ly + FB + JLO);
-            else base = (lz + FB + JLO) * (jx_ * jy_) + (ly + FB + JLO) * jx_ + (lx + FB + JLO);
+            if constexpr (DIM == 2) base = (fz_ + FB + JLO) * jy_ + (fy_ + FB + JLO);
+            else base = (fz_ + FB + JLO) * (jx_ * jy_) + (fy_ + FB + JLO) * jx_ + (fx_ + FB + JLO);
             const uint64_t tails = __ballot(put);
             const int nt = __popcll(tails);
             if (nt <= kPackTails) {
@@ -1117,10 +981,9 @@ size_t push_lds_bytes(int dim, int order, const int P[3], int threads, int run) 
     const int jz = P[2] + cur_lo(order) + cur_hi(order);
     const int nv = dim == 2 ? (order == 1 ? frame_values<2, 1>() : frame_values<2, 2>())
                             : (order == 1 ? frame_values<3, 1>() : frame_values<3, 2>());
-    const int npc = (dim == 3 ? P[0] : 1) * P[1] * P[2];
-    const int table = run > 1 ? 2 * (npc + 1) + threads / 64 : 0;   // cell starts, run prefix, wave sums
+    (void)run;
     const PushLds L = push_lds_layout(fx * fy * fz, jx * jy * jz, threads / 64, kQueueSlots * cross_words(dim),
-                                      nv ? kPackTails * (nv + 1) : 0, table);
+                                      nv ? kPackTails * (nv + 1) : 0, 0);
     return sizeof(float) * (size_t)L.total;
 }
 

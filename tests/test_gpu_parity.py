@@ -203,3 +203,51 @@ def test_dense_cells_deposit(kind, order):
     err = np.abs(J.ravel() - ora.J).max()
     print(f"dense: max |dJ| = {err:.3e}, max |J| = {np.abs(ora.J).max():.3e}")
     assert err <= 2e-5 * np.abs(ora.J).max()
+
+
+# launch shapes: (mode, threads, particles per lane and round, chunk).  A lane
+# that pushes several consecutive particles accumulates the current of those
+# in its first particle's cell and queues the rest, so every shape must give
+# the same particles and, up to summation order, the same current.
+SHAPES = [(0, 256, 1, 512), (1, 512, 2, 1024), (1, 384, 4, 256), (2, 512, 8, 2048), (1, 512, 64, 4096)]
+
+
+@pytest.mark.parametrize("kind,order", CASES)
+@pytest.mark.parametrize("mode,threads,run,chunk", SHAPES)
+def test_launch_shapes_match_oracle(kind, order, mode, threads, run, chunk):
+    if kind == "2d":
+        c = _small_2d(order, seed=43, ny=12, nz=10, patch=4, ppc=40)
+    else:
+        c = _small_3d(order, seed=44, nxyz=(6, 5, 4), patch=3, ppc=30)
+    sim = _sim(c)
+    print(f"[gpu] launch mode={mode} threads={threads} run={run} chunk={chunk}", flush=True)
+    sim.set_launch(mode, chunk=chunk, threads=threads, run=run)
+    ora = O.OracleSim(c)
+    sim.push_fields(0)
+    sim.push_particles()
+    sim.deposit_current()
+    assert sim.check() == 0
+    ora.push_b_half()
+    ora.push_particles()
+    for s, sp in enumerate(c.species):
+        dpos, du = particle_errors(c, sim.front_buffer(0, s), ora, s, float(np.std(sp.u)))
+        assert dpos <= 1e-6 and du <= 1e-5
+    _, _, J = sim.field_arrays(0)
+    err = np.abs(J.ravel() - ora.J).max()
+    print(f"one push: max |dJ| = {err:.3e}, max |J| = {np.abs(ora.J).max():.3e}")
+    assert err <= 2e-5 * np.abs(ora.J).max()
+    # three more whole steps: the push then reads through the sort permutation
+    sim2 = _sim(c)
+    sim2.set_launch(mode, chunk=chunk, threads=threads, run=run)
+    ora2 = O.OracleSim(c)
+    for _ in range(3):
+        sim2.step(1)
+        ora2.step(1)
+    assert sim2.check() == 0
+    for s, sp in enumerate(c.species):
+        dpos, du = particle_errors(c, sim2.particles(0, s), ora2, s, float(np.std(sp.u)))
+        print(f"3 steps, species {s}: |dxi| {dpos:.3e}, rel |du| {du:.3e}")
+        assert dpos <= 1e-5 and du <= 1e-4
+    E, B, _ = sim2.field_arrays(0)
+    assert np.abs(E.ravel() - ora2.E).max() <= 1e-4 * np.abs(ora2.E).max()
+    assert np.abs(B.ravel() - ora2.B).max() <= 1e-4 * np.abs(ora2.B).max()
