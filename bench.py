@@ -199,7 +199,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="harris2d")
     ap.add_argument("--chunk", type=int, default=0)
-    ap.add_argument("--cpu-thin", type=int, default=4)
+    ap.add_argument("--cpu-thin", type=int, default=1,
+                    help="oracle baseline on every n-th particle (1: the whole Harris workload, about 18 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the adjoint and batch legs")
     ap.add_argument("--only", choices=("adjoint", "batch"), default=None,

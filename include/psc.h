@@ -272,7 +272,10 @@ typedef struct {
  * step).  The paper defines no adjoint; this is the exact derivative of the
  * forward kernels' arithmetic.  Needs PSC_RUN_ADJOINT in every run's flags;
  * 2-d runs only (PSC_ERR_UNSUPPORTED for 3-d).  fwd and adj hold n_runs
- * entries. */
+ * entries.  Asynchronous on `stream` (the pointer tables are copied before
+ * the call returns): the buffers must stay valid until the stream reaches
+ * the call's end.  Successive calls on different streams must be ordered by
+ * the caller, since they share the adjoint scratch. */
 psc_status psc_adjoint_step(psc_ctx *ctx, const psc_adj_fwd *fwd, const psc_adj_state *adj, void *stream);
 
 /* Synchronize `stream` and return the device error word as a status:

@@ -21,6 +21,10 @@ using namespace psc;
 
 // LDS one workgroup may allocate on gfx950 (160 KiB per compute unit)
 static constexpr size_t kMaxLds = 160 * 1024;
+// adjoint tables in flight: each call fills a pinned host slot and a device
+// slot of its own, so calls queue on the stream without a host wait (a slot
+// is reused only after the call that last used it has finished)
+static constexpr int kAdjRing = 4;
 
 struct psc_ctx {
     std::vector<psc_run_desc> desc;
@@ -67,6 +71,9 @@ struct psc_ctx {
     size_t adj_lds = 0;
     int64_t adj_items = 0;                  // work items of the particle adjoint (kAdjChunk particles)
     std::vector<AdjRun> adj;                 // host mirror of the adjoint table
+    AdjRun *adj_pinned = nullptr;            // kAdjRing * n_runs tables in pinned host memory
+    hipEvent_t adj_done[kAdjRing] = {};      // completion of the call that last used each slot
+    uint64_t adj_calls = 0;
     std::vector<size_t> off_b1, off_lj, off_gt;
     std::vector<std::vector<size_t>> off_soff, off_su, off_acs, off_atot;
 
@@ -82,6 +89,12 @@ struct psc_ctx {
     template <class T>
     T *at(size_t o) const { return reinterpret_cast<T *>(ws + o); }
     uint32_t *err() const { return at<uint32_t>(off.err); }
+
+    ~psc_ctx() {
+        for (hipEvent_t &e : adj_done)
+            if (e) hipEventDestroy(e);
+        if (adj_pinned) hipHostFree(adj_pinned);
+    }
 };
 
 namespace {
@@ -306,7 +319,7 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
     // adjoint scratch
     for (int r = 0; r < n_runs; ++r) ctx->adjoint |= (runs[r].flags & PSC_RUN_ADJOINT) != 0;
     if (ctx->adjoint) {
-        ctx->off.adj_runs = take(sizeof(AdjRun) * n_runs);
+        ctx->off.adj_runs = take(sizeof(AdjRun) * n_runs * kAdjRing);
         ctx->off.adj_segs = take(sizeof(ScanSeg) * n_runs * PSC_MAX_SPECIES);
         ctx->adj.assign(n_runs, AdjRun{});
         ctx->off_b1.resize(n_runs);
@@ -332,6 +345,16 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
         ctx->adj_items += (int64_t)ctx->units.size();
         if (ctx->adj_lds > kMaxLds) {
             psc_status st = fail(ctx, PSC_ERR_LDS, "adjoint patch tiles do not fit in 160 KiB of LDS");
+            delete ctx;
+            return st;
+        }
+    }
+    if (ctx->adjoint) {
+        hipError_t e = hipHostMalloc((void **)&ctx->adj_pinned, sizeof(AdjRun) * n_runs * kAdjRing, hipHostMallocDefault);
+        for (int k = 0; k < kAdjRing && e == hipSuccess; ++k)
+            e = hipEventCreateWithFlags(&ctx->adj_done[k], hipEventDisableTiming);
+        if (e != hipSuccess) {
+            psc_status st = hipfail(ctx, e, "adjoint table staging");
             delete ctx;
             return st;
         }
@@ -841,17 +864,21 @@ psc_status psc_adjoint_step(psc_ctx *ctx, const psc_adj_fwd *fwd, const psc_adj_
             S.lu = adj[r].lu[sp];
         }
     }
-    HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.adj_runs), ctx->adj.data(), sizeof(AdjRun) * ctx->n_runs,
-                            hipMemcpyHostToDevice, s), "upload adjoint table");
+    const int slot = (int)(ctx->adj_calls++ % kAdjRing);
+    HIPCHECK(hipEventSynchronize(ctx->adj_done[slot]), "adjoint table slot");   // done long ago
+    AdjRun *host = ctx->adj_pinned + (size_t)slot * ctx->n_runs;
+    AdjRun *dev = ctx->at<AdjRun>(ctx->off.adj_runs) + (size_t)slot * ctx->n_runs;
+    std::copy(ctx->adj.begin(), ctx->adj.end(), host);
+    HIPCHECK(hipMemcpyAsync(dev, host, sizeof(AdjRun) * ctx->n_runs, hipMemcpyHostToDevice, s),
+             "upload adjoint table");
     Launch L = make_launch(ctx, s);
-    HIPCHECK(launch_adjoint(L, ctx->at<AdjRun>(ctx->off.adj_runs), ctx->adj.data(), ctx->at<Unit>(ctx->off.units),
+    HIPCHECK(launch_adjoint(L, dev, ctx->adj.data(), ctx->at<Unit>(ctx->off.units),
                             (int)ctx->units.size(), ctx->at<int32_t>(ctx->off.item_start), ctx->adj_items, kAdjChunk,
                             ctx->order, ctx->total_cells, ctx->at<int64_t>(ctx->off.run_base),
                             ctx->at<ScanSeg>(ctx->off.adj_segs), ctx->at<int32_t>(ctx->off.load_blockseg),
                             ctx->at<int32_t>(ctx->off.load_sums), ctx->adj_lds, s),
              "adjoint step");
-    // the host table is reused by the next call: make sure the copy is done
-    HIPCHECK(hipStreamSynchronize(s), "adjoint sync");
+    HIPCHECK(hipEventRecord(ctx->adj_done[slot], s), "adjoint step event");
     return PSC_OK;
 }
 
