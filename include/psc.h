@@ -175,8 +175,11 @@ psc_status psc_sort(psc_ctx *ctx, void *stream);
  * once per buffer parity and replays it. */
 psc_status psc_step(psc_ctx *ctx, int nsteps, int use_graph, void *stream);
 
-/* Launch shape of the particle kernel (batching and autotuning).
- * mode: PSC_LAUNCH_GRID      one workgroup per work item (default);
+/* Launch shape of the particle kernel (batching and autotuning).  psc_bind
+ * sets PSC_LAUNCH_QUEUE with 512 threads and one particle per lane (the
+ * shape the autotuner chose for every workload measured on gfx950), or the
+ * largest workgroup whose LDS fits, or PSC_LAUNCH_GRID with 256 threads.
+ * mode: PSC_LAUNCH_GRID      one workgroup per work item;
  *       PSC_LAUNCH_QUEUE     persistent workgroups pulling work items from
  *                            eight queues (one per XCD, with stealing);
  *       PSC_LAUNCH_PARTITION persistent workgroups, each over a contiguous
@@ -186,10 +189,11 @@ psc_status psc_step(psc_ctx *ctx, int nsteps, int use_graph, void *stream);
  * workers: persistent workgroups (0 = compute units x workgroups that fit
  * in one unit's LDS).  threads: workgroup size, 256, 384 or 512 (0 keeps;
  * the LDS tiles of a work item are shared by all its waves; PSC_ERR_LDS if
- * the tiles, cell tables and per-wave queues exceed 160 KiB).  run: 1..64
- * particles of one cell that a lane pushes in sequence, accumulating their
- * current before the wave-level sums (0 keeps; default 1: one particle per
- * lane, consecutive particles on consecutive lanes).  Drops recorded step graphs.  May synchronize. */
+ * the tiles and per-wave queues exceed 160 KiB).  run: 1..64 consecutive
+ * particles that a lane pushes in sequence, accumulating the current of
+ * those in its first particle's cell before the wave-level sums (0 keeps;
+ * default 1: one particle per lane, consecutive particles on consecutive
+ * lanes).  Drops recorded step graphs.  May synchronize. */
 #define PSC_LAUNCH_GRID 0
 #define PSC_LAUNCH_QUEUE 1
 #define PSC_LAUNCH_PARTITION 2

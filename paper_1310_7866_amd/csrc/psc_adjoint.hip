@@ -230,19 +230,6 @@ __global__ void k_adj_unpermute(const AdjRun *__restrict__ adj, int r, int s, in
     for (int c = 0; c < 3; ++c) S.su[c * S.n + p] = S.lu[c * S.n + j];
 }
 
-__global__ void k_adj_count(const RunDev *__restrict__ runs, const AdjRun *__restrict__ adj, int r, int s,
-                            uint32_t *err) {
-    const AdjSpecies &S = adj[r].sp[s];
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= S.n) return;
-    const int32_t key = S.key[j];
-    if (key < 0 || key >= runs[r].ncell) {
-        atomicOr(err, PSC_DEV_KEY);
-        return;
-    }
-    atomicAdd(&S.tot[key], 1);
-}
-
 __global__ void __launch_bounds__(1024) k_adj_items(const RunDev *__restrict__ runs, const AdjRun *__restrict__ adj,
                                                     const Unit *__restrict__ units, int n_units, int chunk,
                                                     int32_t *__restrict__ item_start) {
@@ -672,8 +659,7 @@ size_t adjoint_lds_bytes(int order, const int P[3]) {
 
 hipError_t launch_adjoint(const Launch &L, const AdjRun *adj_dev, const AdjRun *adj_host, const Unit *units,
                           int n_units, int32_t *item_start, int64_t max_items, int chunk, int order,
-                          int64_t total_cells, const int64_t *run_base, const ScanSeg *seg_dev, int32_t *blockseg,
-                          int32_t *sums, size_t lds, hipStream_t s) {
+                          int64_t total_cells, const int64_t *run_base, size_t lds, hipStream_t s) {
     const unsigned gc = (unsigned)((total_cells + 255) / 256);
     // (1) LJ = -dt lE', lB2 = lB' + dt curl^+ lE'
     hipLaunchKernelGGL(k_adj_fields, dim3(gc), dim3(256), 0, s, L.runs_dev, adj_dev, L.n_runs, run_base, total_cells, 0);
@@ -684,21 +670,10 @@ hipError_t launch_adjoint(const Launch &L, const AdjRun *adj_dev, const AdjRun *
         const RunDev &R = L.runs_host[r];
         for (int sp = 0; sp < R.n_species; ++sp) {
             const AdjSpecies &S = adj_host[r].sp[sp];
-            if (S.n == 0) {
-                hipError_t e = launch_fill_i32(S.cs, R.ncell + 1, 0, s);
-                if (e != hipSuccess) return e;
-                continue;
-            }
-            const unsigned gp = (unsigned)((S.n + 255) / 256);
-            hipLaunchKernelGGL(k_adj_unpermute, dim3(gp), dim3(256), 0, s, adj_dev, r, sp, R.dim);
-            hipError_t e = launch_fill_i32(S.tot, R.ncell, 0, s);
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k_adj_count, dim3(gp), dim3(256), 0, s, L.runs_dev, adj_dev, r, sp, L.err);
-            const ScanSeg *sg = seg_dev + (r * kMaxSpecies + sp);
-            const int64_t nb = (R.ncell + kScanBlock - 1) / kScanBlock;
-            e = launch_fill_i32(blockseg, nb, 0, s);
-            if (e != hipSuccess) return e;
-            e = launch_scan(sg, 1, nb, blockseg, sums, s);
+            if (S.n > 0)
+                hipLaunchKernelGGL(k_adj_unpermute, dim3((unsigned)((S.n + 255) / 256)), dim3(256), 0, s, adj_dev, r,
+                                   sp, R.dim);
+            hipError_t e = launch_cell_starts(S.n, R.ncell, S.key, S.cs, L.err, s);
             if (e != hipSuccess) return e;
         }
     }

@@ -58,8 +58,8 @@ struct psc_ctx {
 
     struct Off {
         size_t runs, units, item_start, run_base, seg_base, seg_run, seg_sp, segs0, segs1, scan_tmp, err;
-        size_t load_seg, load_blockseg, load_sums, load_keys, load_idx, load_keys_s, load_idx_s, cub;
-        size_t adj_runs, adj_segs;
+        size_t load_keys, load_idx, load_keys_s, load_idx_s, cub;
+        size_t adj_runs;
         size_t queue, part, unit_counts;
     } off{};
     PushMode pm;                             // particle-kernel launch shape
@@ -75,7 +75,7 @@ struct psc_ctx {
     hipEvent_t adj_done[kAdjRing] = {};      // completion of the call that last used each slot
     uint64_t adj_calls = 0;
     std::vector<size_t> off_b1, off_lj, off_gt;
-    std::vector<std::vector<size_t>> off_soff, off_su, off_acs, off_atot;
+    std::vector<std::vector<size_t>> off_soff, off_su, off_acs;
 
     // state
     bool bound = false;
@@ -290,10 +290,6 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
     ctx->off.queue = take(sizeof(int32_t) * 8);
     ctx->off.part = take(sizeof(int32_t) * (ctx->max_workers + 1));
     ctx->off.unit_counts = take(sizeof(int32_t) * ctx->units.size());
-    const int64_t load_blocks = (ctx->max_ncell + kScanBlock - 1) / kScanBlock;
-    ctx->off.load_seg = take(sizeof(ScanSeg));
-    ctx->off.load_blockseg = take(sizeof(int32_t) * load_blocks);
-    ctx->off.load_sums = take(sizeof(int32_t) * load_blocks);
     ctx->off.load_keys = take(sizeof(int32_t) * ctx->max_cap);
     ctx->off.load_idx = take(sizeof(int32_t) * ctx->max_cap);
     ctx->off.load_keys_s = take(sizeof(int32_t) * ctx->max_cap);
@@ -320,12 +316,11 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
     for (int r = 0; r < n_runs; ++r) ctx->adjoint |= (runs[r].flags & PSC_RUN_ADJOINT) != 0;
     if (ctx->adjoint) {
         ctx->off.adj_runs = take(sizeof(AdjRun) * n_runs * kAdjRing);
-        ctx->off.adj_segs = take(sizeof(ScanSeg) * n_runs * PSC_MAX_SPECIES);
         ctx->adj.assign(n_runs, AdjRun{});
         ctx->off_b1.resize(n_runs);
         ctx->off_lj.resize(n_runs);
         ctx->off_gt.resize(n_runs);
-        ctx->off_soff = ctx->off_su = ctx->off_acs = ctx->off_atot = ctx->off_cs0;
+        ctx->off_soff = ctx->off_su = ctx->off_acs = ctx->off_cs0;
         for (int r = 0; r < n_runs; ++r) {
             const RunDev &R = ctx->runs[r];
             const size_t lds = adjoint_lds_bytes(R.order, R.P);
@@ -338,7 +333,6 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
                 ctx->off_soff[r][s] = take(sizeof(float) * R.dim * R.sp[s].cap);
                 ctx->off_su[r][s] = take(sizeof(float) * 3 * R.sp[s].cap);
                 ctx->off_acs[r][s] = take(sizeof(int32_t) * (R.ncell + 1));
-                ctx->off_atot[r][s] = take(sizeof(int32_t) * R.ncell);
                 ctx->adj_items += (R.sp[s].cap + kAdjChunk - 1) / kAdjChunk;
             }
         }
@@ -463,7 +457,6 @@ psc_status psc_bind(psc_ctx *ctx, const psc_run_bufs *bufs, int n_runs, void *wo
         }
     }
     if (ctx->adjoint) {
-        std::vector<ScanSeg> asegs(ctx->n_runs * PSC_MAX_SPECIES, ScanSeg{nullptr, nullptr, 0, 0});
         for (int r = 0; r < ctx->n_runs; ++r) {
             const RunDev &R = ctx->runs[r];
             AdjRun &A = ctx->adj[r];
@@ -477,17 +470,19 @@ psc_status psc_bind(psc_ctx *ctx, const psc_run_bufs *bufs, int n_runs, void *wo
                 S.soff = ctx->at<float>(ctx->off_soff[r][sp]);
                 S.su = ctx->at<float>(ctx->off_su[r][sp]);
                 S.cs = ctx->at<int32_t>(ctx->off_acs[r][sp]);
-                S.tot = ctx->at<int32_t>(ctx->off_atot[r][sp]);
-                asegs[r * PSC_MAX_SPECIES + sp] = ScanSeg{S.tot, S.cs, R.ncell, 0};
             }
         }
-        HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.adj_segs), asegs.data(), sizeof(ScanSeg) * asegs.size(),
-                                hipMemcpyHostToDevice, s), "upload adjoint segments");
     }
     HIPCHECK(hipStreamSynchronize(s), "bind sync");
     ctx->bound = true;
     ctx->stepped = false;
     ctx->front = ctx->cs_sel = ctx->perm_pending = ctx->mc_valid = 0;
+    // default launch: persistent queues with the largest workgroup that fits
+    for (int threads : {512, 384, 256}) {
+        if (ctx->push_lds(threads, 1) > kMaxLds) continue;
+        psc_status st = psc_set_launch(ctx, PSC_LAUNCH_QUEUE, 0, 0, threads, 1, stream);
+        if (st != PSC_ERR_LDS) return st;
+    }
     return PSC_OK;
 }
 
@@ -535,14 +530,7 @@ psc_status psc_load_particles(psc_ctx *ctx, int run, int species, int64_t n, con
         HIPCHECK(radix_sort_pairs(ctx->at<void>(ctx->off.cub), &tb, keys, keys_s, idx, idx_s, n, bits, s), "load sort");
     }
     HIPCHECK(launch_load_gather(R, species, n, keys_s, idx_s, goff, gu, gid, s), "load gather");
-    HIPCHECK(launch_fill_i32(S.tot, R.ncell, 0, s), "load clear counts");
-    HIPCHECK(launch_count_cells(R, species, n, keys_s, S.tot, ctx->err(), s), "load count");
-    const int64_t nb = (R.ncell + kScanBlock - 1) / kScanBlock;
-    ScanSeg seg{S.tot, S.cs[0], R.ncell, 0};
-    HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.load_seg), &seg, sizeof seg, hipMemcpyHostToDevice, s), "load seg");
-    HIPCHECK(launch_fill_i32(ctx->at<int32_t>(ctx->off.load_blockseg), nb, 0, s), "load block table");
-    HIPCHECK(launch_scan(ctx->at<ScanSeg>(ctx->off.load_seg), 1, nb, ctx->at<int32_t>(ctx->off.load_blockseg),
-                         ctx->at<int32_t>(ctx->off.load_sums), s), "load scan");
+    HIPCHECK(launch_cell_starts(n, R.ncell, keys_s, S.cs[0], ctx->err(), s), "load cell offsets");
     S.n = n;
     HIPCHECK(hipMemcpyAsync(ctx->at<RunDev>(ctx->off.runs) + run, &R, sizeof(RunDev), hipMemcpyHostToDevice, s),
              "upload run");
@@ -874,9 +862,7 @@ psc_status psc_adjoint_step(psc_ctx *ctx, const psc_adj_fwd *fwd, const psc_adj_
     Launch L = make_launch(ctx, s);
     HIPCHECK(launch_adjoint(L, dev, ctx->adj.data(), ctx->at<Unit>(ctx->off.units),
                             (int)ctx->units.size(), ctx->at<int32_t>(ctx->off.item_start), ctx->adj_items, kAdjChunk,
-                            ctx->order, ctx->total_cells, ctx->at<int64_t>(ctx->off.run_base),
-                            ctx->at<ScanSeg>(ctx->off.adj_segs), ctx->at<int32_t>(ctx->off.load_blockseg),
-                            ctx->at<int32_t>(ctx->off.load_sums), ctx->adj_lds, s),
+                            ctx->order, ctx->total_cells, ctx->at<int64_t>(ctx->off.run_base), ctx->adj_lds, s),
              "adjoint step");
     HIPCHECK(hipEventRecord(ctx->adj_done[slot], s), "adjoint step event");
     return PSC_OK;

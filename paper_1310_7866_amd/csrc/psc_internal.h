@@ -95,7 +95,6 @@ struct AdjSpecies {
     float *loff, *lu;     // caller: in (next step's sorted order), out (this step's)
     float *soff, *su;     // scratch: incoming adjoints moved to this step's slots
     int32_t *cs;          // scratch: cell offsets of `key`, ncell + 1
-    int32_t *tot;         // scratch: counts
 };
 
 struct AdjRun {
@@ -231,8 +230,8 @@ hipError_t launch_keys_to_cells(const RunDev &r, int64_t n, const int32_t *keys,
 hipError_t launch_load_gather(const RunDev &r, int species, int64_t n, const int32_t *sorted_keys,
                               const int32_t *sorted_idx, const float *goff, const float *gu,
                               const int32_t *gid, hipStream_t s);
-hipError_t launch_count_cells(const RunDev &r, int species, int64_t n, const int32_t *sorted_keys,
-                              int32_t *tot, uint32_t *err, hipStream_t s);
+hipError_t launch_cell_starts(int64_t n, int64_t ncell, const int32_t *sorted_keys, int32_t *cs, uint32_t *err,
+                              hipStream_t s);
 hipError_t launch_get(const RunDev &r, int species, int front, int perm_pending, int32_t *cell,
                       float *off, float *u, int32_t *id, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
@@ -241,8 +240,7 @@ hipError_t launch_diag(const Launch &L, double *out, double *gauss, int64_t tota
 size_t adjoint_lds_bytes(int order, const int P[3]);
 hipError_t launch_adjoint(const Launch &L, const AdjRun *adj_dev, const AdjRun *adj_host, const Unit *units,
                           int n_units, int32_t *item_start, int64_t max_items, int chunk, int order,
-                          int64_t total_cells, const int64_t *run_base, const ScanSeg *seg_dev, int32_t *blockseg,
-                          int32_t *sums, size_t lds, hipStream_t s);
+                          int64_t total_cells, const int64_t *run_base, size_t lds, hipStream_t s);
 hipError_t radix_sort_pairs(void *temp, size_t *temp_bytes, const int32_t *keys_in, int32_t *keys_out,
                             const int32_t *vals_in, int32_t *vals_out, int64_t n, int bits,
                             hipStream_t s);

@@ -71,45 +71,70 @@ __device__ __forceinline__ CellBlock cell_block(const RunDev *runs, const ScanSe
 // cell (0..63 within the wave), m its move code, rank its index among the
 // earlier particles of (q, m) in this wave, last whether it is the final one
 // of (q, m) in the current group of 64.  sb: the wave's 65 first indices.
+//
+// Lane q keeps the first index of cell q in a register.  The cell starts are
+// non-decreasing, so two ballots give the cells [qa, qb] that a group of 64
+// particles touches, and a lane's cell is qa plus the number of starts in
+// (qa, qb] at or below its index (a short uniform loop over scalar reads;
+// a binary search when the group spans many cells).  Ranks: one ballot for
+// the particles that stay in their cell, one per distinct move code among
+// the others.
 template <int M, typename F>
 __device__ __forceinline__ void walk_cells(const int32_t *sb, int nw, int32_t pb, int32_t pe,
                                            const uint8_t *__restrict__ mc, uint32_t &flags, F &&f) {
+    constexpr int CENTER = M / 2;
+    constexpr int kLoopCells = 8;   // longest cell range walked by the loop
     const int lane = threadIdx.x & 63;
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
+    const uint64_t cells = nw >= 64 ? ~0ull : ((1ull << nw) - 1);
+    const int32_t sbl = sb[lane < nw ? lane : nw];
     for (int32_t i0 = pb; i0 < pe; i0 += 64) {
         const int32_t i = i0 + lane;
         const bool valid = i < pe;
-        int m = -1, q = -1;
-        if (valid) {
-            m = mc[i];
-            if (m >= M) { flags |= PSC_DEV_MOVE; m = M / 2; }
-            int a = 0, b = nw;   // sb[a] <= i < sb[b]
+        const int32_t il = i0 + 63 < pe ? i0 + 63 : pe - 1;
+        const int qa = 63 - __clzll(__ballot(sbl <= i0) & cells);   // sb[0] = pb <= i0
+        const int qb = 63 - __clzll(__ballot(sbl <= il) & cells);
+        int q = qa;
+        bool head = lane == 0 || i == pe;
+        if (qb - qa <= kLoopCells) {
+            for (int k = qa + 1; k <= qb; ++k) {
+                const int32_t s = __builtin_amdgcn_readlane(sbl, k);
+                q += s <= i ? 1 : 0;
+                head |= s == i;
+            }
+        } else {
+            int a = qa, b = qb + 1;   // sb[a] <= i < sb[b] (or b = qb + 1)
             while (b - a > 1) {
                 const int h = (a + b) >> 1;
                 if (sb[h] <= i) a = h;
                 else b = h;
             }
             q = a;
+            head |= sb[a] == i;
         }
-        // lanes of my cell: a contiguous range starting at the last head <= me
-        const int left = __shfl_up(q, 1, 64);
-        const uint64_t heads = __ballot(lane == 0 || left != q);
-        const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
+        int m = -1;
+        if (valid) {
+            m = mc[i];
+            if (m >= M) { flags |= PSC_DEV_MOVE; m = CENTER; }
+        } else {
+            q = -1;
+        }
+        // lanes of my cell: from the last head at or below me to the next head
+        const uint64_t heads = __ballot(head);
         const int s0 = 63 - __clzll(heads & upto);
-        const uint64_t after = heads & ~upto;   // heads above me
-        const int e1 = after ? __ffsll((unsigned long long)after) - 1 : 64;   // one past my cell's last lane
+        const uint64_t after = heads & ~upto;
+        const int e1 = after ? __ffsll((unsigned long long)after) - 1 : 64;
         const uint64_t mine = (e1 == 64 ? ~0ull : ((1ull << e1) - 1)) & ~((1ull << s0) - 1);
-        uint32_t lo = 0, hi = 0;   // lane k: ballot of code k
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
+        // lanes with my move code
+        uint64_t bm = __ballot(m == CENTER);
+        uint64_t mv = __ballot(valid && m != CENTER);
+        while (mv) {
+            const int k = __builtin_amdgcn_readlane(m, __ffsll((unsigned long long)mv) - 1);
             const uint64_t bk = __ballot(m == k);
-            if (lane == k) {
-                lo = (uint32_t)bk;
-                hi = (uint32_t)(bk >> 32);
-            }
+            if (m == k) bm = bk;
+            mv &= ~bk;
         }
-        const int mm = valid ? m : 0;
-        const uint64_t bm = ((uint64_t)(uint32_t)__shfl((int)hi, mm, 64) << 32) | (uint32_t)__shfl((int)lo, mm, 64);
         const uint64_t grp = bm & mine;
         const int rank = __popcll(grp & below);
         const bool last = (grp & ~upto) == 0;
@@ -421,17 +446,29 @@ hipError_t launch_load_gather(const RunDev &r, int species, int64_t n, const int
 
 // particles per cell of sorted keys; a cell's 65536th particle flags the
 // overflow of the 16-bit per (cell, move) counters of the step sort
-__global__ void k_count_cells(int64_t n, const int32_t *__restrict__ skeys, int32_t *__restrict__ tot,
+// Cell offsets of keys sorted ascending: cs[c] = first index whose key is at
+// least c, cs[ncell] = n.  Index i writes the offsets of the cells in
+// (key[i-1], key[i]] (index 0 from cell 0, index n up to ncell), so every
+// entry is written once and no counting is needed.  A cell with more than
+// 65535 particles (the width of the per-(cell, move) counters) sets the
+// overfull flag; keys out of range or out of order set the key flag.
+__global__ void k_cell_starts(int64_t n, int64_t ncell, const int32_t *__restrict__ keys, int32_t *__restrict__ cs,
                               uint32_t *err) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    if (atomicAdd(&tot[skeys[r]], 1) == 65535) atomicOr(err, PSC_DEV_OVERFULL);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    const int64_t lo = i == 0 ? -1 : keys[i - 1];
+    const int64_t hi = i == n ? ncell : keys[i];
+    uint32_t flags = 0;
+    if (lo < -1 || hi > ncell || (i < n && hi >= ncell) || hi < lo) flags |= PSC_DEV_KEY;
+    else
+        for (int64_t c = lo + 1; c <= hi; ++c) cs[c] = (int32_t)i;
+    if (i < n && i >= 65535 && keys[i - 65535] == keys[i]) flags |= PSC_DEV_OVERFULL;
+    if (flags) atomicOr(err, flags);
 }
 
-hipError_t launch_count_cells(const RunDev &, int, int64_t n, const int32_t *skeys, int32_t *tot, uint32_t *err,
+hipError_t launch_cell_starts(int64_t n, int64_t ncell, const int32_t *keys, int32_t *cs, uint32_t *err,
                               hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_count_cells, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, skeys, tot, err);
+    hipLaunchKernelGGL(k_cell_starts, dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, s, n, ncell, keys, cs, err);
     return hipGetLastError();
 }
 
