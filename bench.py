@@ -112,6 +112,117 @@ def oracle_error(sample, osim):
     return out
 
 
+def sort_ablation_leg(sim, stream, steps: int):
+    """The per-step sort by a general multi-pass radix sort of the keys
+    (psc_sort_radix) in place of the single-pass move-code counting sort,
+    timed on the same state after the timed region."""
+    import torch
+    from paper_1310_7866_amd.psc import B_HALF, E_FULL
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    pairs = [(ev(), ev()) for _ in range(steps)]
+    for k in range(steps):
+        sim.push_fields(B_HALF)
+        sim.push_particles()
+        sim.push_fields(B_HALF)
+        sim.deposit_current()
+        sim.push_fields(E_FULL)
+        pairs[k][0].record(stream)
+        sim.sort_radix()
+        pairs[k][1].record(stream)
+    torch.cuda.synchronize()
+    sim.check()
+    return dict(radix_sort_ms=sum(a.elapsed_time(b) for a, b in pairs) / steps, steps=steps)
+
+
+def supercell_leg(sizes=(4, 8, 12, 16, 24, 32, 48), steps: int = 10):
+    """Patch (super-cell) size sweep of the Harris workload: every patch
+    stages its fields and accumulates its current in LDS, so small patches
+    amortise the tile loads over few particles and large ones hold fewer
+    workgroups per compute unit.  Default launch shape, one context each."""
+    import torch
+    from paper_1310_7866_amd import cases
+    from paper_1310_7866_amd.psc import B_HALF, E_FULL, PscError, PscSim
+    case = cases.harris2d()
+    out = {}
+    for P in sizes:
+        case.patch = (1, P, P)
+        try:
+            sim = PscSim(case, with_ids=False)
+        except PscError as e:
+            out[f"{P}x{P}"] = dict(error=str(e))
+            continue
+        stream = torch.cuda.current_stream()
+        sim.step(2)
+        ev = lambda: torch.cuda.Event(enable_timing=True)
+        pe = [(ev(), ev()) for _ in range(steps)]
+        t0, t1 = ev(), ev()
+        torch.cuda.synchronize()
+        t0.record(stream)
+        for k in range(steps):
+            sim.push_fields(B_HALF)
+            pe[k][0].record(stream)
+            sim.push_particles()
+            pe[k][1].record(stream)
+            sim.push_fields(B_HALF)
+            sim.deposit_current()
+            sim.push_fields(E_FULL)
+            sim.sort()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        sim.check()
+        push_ms = sum(a.elapsed_time(b) for a, b in pe) / steps
+        step_ms = t0.elapsed_time(t1) / steps
+        out[f"{P}x{P}"] = dict(push_ms=round(push_ms, 4), step_ms=round(step_ms, 4),
+                               push_pushes_per_s=case.n_particles / (push_ms / 1e3))
+        print(f"[bench] patch {P}x{P}: push {push_ms:.3f} ms, step {step_ms:.3f} ms", file=sys.stderr, flush=True)
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    case.patch = (1, 32, 32)
+    return dict(workload=f"harris2d 1024x512, order 2, {case.n_particles} particles", steps=steps, patches=out)
+
+
+def marder_leg(steps: int = 2000, every: int = 50, frac: float = 0.5):
+    """Gauss-law drift of a long float32 run (Harris 256x256, order 2) with
+    and without Marder cleaning every `every` steps (coefficient `frac` of
+    the stability bound, reference = the residual at the start), and the
+    cost of the cleaning.  Drift: max over nodes of |G^n - G^0|, G the Gauss
+    residual div E - rho in units of the reference density."""
+    import numpy as np
+    import torch
+    from paper_1310_7866_amd import cases
+    from paper_1310_7866_amd.psc import PscSim
+    c = cases.harris2d(ny=256, nz=256, ppc=64, order=2, patch=32, seed=5050, steps=steps)
+    d = frac * 2.0 / (c.dt * (4.0 / c.dx[1] ** 2 + 4.0 / c.dx[2] ** 2))
+    out = dict(workload=f"harris2d 256x256, order 2, {c.n_particles} particles, {steps} steps",
+               every=every, d=d, d_over_bound=frac)
+    for clean in (False, True):
+        sim = PscSim(c, with_ids=False)
+        _, g0 = sim.diagnostics(with_gauss=True)
+        ref = torch.from_numpy(g0).cuda()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for k in range(0, steps, every):
+            sim.step(min(every, steps - k), use_graph=True)
+            if clean:
+                sim.marder(d, ref=ref)
+        b.record()
+        torch.cuda.synchronize()
+        sim.check()
+        _, g = sim.diagnostics(with_gauss=True)
+        tag = "with_marder" if clean else "without"
+        out[tag] = dict(max_drift=float(np.abs(g - g0).max()), rms_drift=float(np.sqrt(np.mean((g - g0) ** 2))),
+                        ms=a.elapsed_time(b))
+        print(f"[bench] marder {tag}: drift {out[tag]['max_drift']:.3e}, {out[tag]['ms']:.1f} ms", file=sys.stderr,
+              flush=True)
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    out["overhead"] = out["with_marder"]["ms"] / out["without"]["ms"] - 1.0
+    return out
+
+
 def adjoint_leg(every: int = 10, nsteps: int = 50):
     """Gradient of the final field energy on the 256 x 256 double Harris sheet
     (64 particles per cell at n = 1, 2nd order, 32 x 32 patches): forward with
@@ -203,7 +314,7 @@ def main():
                     help="oracle baseline on every n-th particle (1: the whole Harris workload, about 18 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the adjoint and batch legs")
-    ap.add_argument("--only", choices=("adjoint", "batch"), default=None,
+    ap.add_argument("--only", choices=("adjoint", "batch", "supercells", "marder"), default=None,
                     help="run only the adjoint or the batch leg and print its JSON")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--launch", default="", help="fixed launch shape mode,chunk,threads,run (skips tuning)")
@@ -226,6 +337,12 @@ def main():
         return
     if args.only == "batch":
         print(json.dumps({"batched": batch_leg(tune_cache=args.tune_cache, retune=args.retune)}))
+        return
+    if args.only == "supercells":
+        print(json.dumps({"supercells": supercell_leg()}))
+        return
+    if args.only == "marder":
+        print(json.dumps({"marder": marder_leg()}))
         return
 
     if args.calibrate:
@@ -283,6 +400,7 @@ def main():
     total_ms = t_start.elapsed_time(t_end)
     push_ms = sum(a.elapsed_time(b) for a, b in push_ev) / args.steps
     sort_ms = sum(a.elapsed_time(b) for a, b in sort_ev) / args.steps
+    sort_ablation = None if args.no_extras else sort_ablation_leg(sim, stream, min(args.steps, 10))
     ms_step = total_ms / args.steps
     n = case.n_particles
     value = n * args.steps / (total_ms / 1e3)
@@ -324,6 +442,9 @@ def main():
         "push_kernel_pushes_per_s": n / (push_ms / 1e3),
         "sort_ms": sort_ms,
         "wall_s_timed": wall,
+        **({"sort_ablation": dict(sort_ablation, counting_sort_ms=sort_ms,
+                                  radix_over_counting=sort_ablation["radix_sort_ms"] / sort_ms)}
+           if sort_ablation else {}),
         "roofline": roof,
     }
     if roofs is not None:
@@ -341,12 +462,18 @@ def main():
 
 
 def push_source_hash() -> str:
-    """Hash of the sources the particle kernel is compiled from."""
+    """Hash of the sources the particle kernel is compiled from: its own file,
+    the device helpers, and the data structures of the internal header (the
+    launcher declarations after them do not change the kernel)."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("psc_push.hip", "psc_device.h", "psc_internal.h"):
-        with open(os.path.join(ROOT, "paper_1310_7866_amd", "csrc", name), "rb") as f:
+    csrc = os.path.join(ROOT, "paper_1310_7866_amd", "csrc")
+    for name in ("psc_push.hip", "psc_device.h"):
+        with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
+    with open(os.path.join(csrc, "psc_internal.h"), "rb") as f:
+        text = f.read()
+    h.update(text.split(b"// launchers (defined in the .hip files)")[0])
     return h.hexdigest()[:16]
 
 

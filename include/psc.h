@@ -116,7 +116,9 @@ typedef struct psc_ctx psc_ctx;
 /* Validate run descriptors and create a context (host only, no device work).
  * runs: n_runs descriptors (1 <= n_runs <= PSC_MAX_RUNS), copied.
  * chunk: particles per work item of the particle kernel (0 = default 8192).
- * Synchronous errors: PSC_ERR_INVALID, PSC_ERR_CFL (dt >= CFL limit),
+ * Synchronous errors: PSC_ERR_INVALID (also: more than three patches along a
+ * dimension with a patch, or the truncated last one, narrower than order + 1
+ * cells, the current tile's halo), PSC_ERR_CFL (dt >= CFL limit),
  * PSC_ERR_LDS (a patch's field and current tiles plus the per-wave queues of
  * a 256-thread workgroup exceed the 160 KiB of LDS of a workgroup, or a patch
  * side exceeds 255 cells). */
@@ -169,6 +171,16 @@ psc_status psc_deposit_current(psc_ctx *ctx, void *stream);
  * order.  The physical reorder is deferred into the next
  * psc_push_particles. */
 psc_status psc_sort(psc_ctx *ctx, void *stream);
+
+/* The same stable order as psc_sort by a general least-significant-digit
+ * radix sort of the new keys (rocPRIM, several passes over all particles),
+ * the multi-pass baseline that the paper's single-pass sort replaces
+ * (section "Sorting and Communication"): for timing the two against each
+ * other.  Same outputs and state change as psc_sort (permutation, cell
+ * offsets, reorder deferred into the next push); the push's move counts are
+ * cleared unused.  Uses the load path's scratch.  May not be recorded into
+ * a graph. */
+psc_status psc_sort_radix(psc_ctx *ctx, void *stream);
 
 /* nsteps full steps in the order of fig. psc_new: B half, particles, B half,
  * fold J, E full, sort.  use_graph != 0 records the step into a HIP graph
@@ -241,6 +253,21 @@ psc_status psc_sort_view(const psc_ctx *ctx, int run, int species, const int32_t
  * per node, runs concatenated. */
 #define PSC_DIAG_STRIDE 10
 psc_status psc_diagnostics(psc_ctx *ctx, double *out_dev, double *gauss_dev, void *stream);
+
+/* Marder's divergence cleaning, the iterative method the paper names for
+ * dissipating the violations of Gauss's law that single-precision runs
+ * accumulate over many steps (section "Time integration of the
+ * quasi-particle equations of motion").  iters times: F = div^- E - rho - ref
+ * at every node (rho of the current particles, FP64), then
+ * E += d dt grad^+ F, which changes only the longitudinal part of E.
+ * ref: optional device float64 array laid out like psc_diagnostics' gauss
+ * output (e.g. the residual at the start of the run, so that only its drift
+ * is removed); NULL means zero.  d: diffusion coefficient (length^2/time),
+ * 0 < d dt sum_d 4/dx_d^2 <= 2 in every run, else PSC_ERR_INVALID (the step
+ * would amplify the residual).  Call between steps (PSC_ERR_STATE right after
+ * a bare psc_push_particles).  Overwrites the diagnostics' charge scratch.
+ * Asynchronous on `stream`. */
+psc_status psc_marder(psc_ctx *ctx, const double *ref, double d, int iters, void *stream);
 
 /* Copy the permutation of the last psc_sort of (run, species) to a caller
  * device array (int32, n): entry j is the slot, in the order the last

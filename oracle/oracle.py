@@ -63,6 +63,7 @@ def lib():
         L.orc_push_b.argtypes = [g, dp, dp, C.c_double]
         L.orc_push_e.argtypes = [g, dp, dp, C.c_void_p, C.c_double]
         L.orc_div_e.argtypes = [g, dp, dp]
+        L.orc_marder.argtypes = [g, dp, dp, C.c_double]
         L.orc_div_b.argtypes = [g, dp, dp]
         L.orc_deposit_rho.argtypes = [g, C.c_long, dp, C.c_double, dp]
         L.orc_patch_keys.argtypes = [g, ip, ip]
@@ -203,6 +204,14 @@ class OracleSim:
 
     def gauss(self) -> np.ndarray:
         return self.div_e() - self.rho()
+
+    def marder(self, d: float, ref: Optional[np.ndarray] = None, iters: int = 1):
+        """Marder's cleaning: E += d dt grad(F), F = Gauss residual - ref."""
+        for _ in range(iters):
+            F = self.gauss()
+            if ref is not None:
+                F = F - ref
+            lib().orc_marder(C.byref(self.g), self.E, np.ascontiguousarray(F), float(d))
 
     def field_energy(self):
         return (lib().orc_field_energy(C.byref(self.g), self.E),

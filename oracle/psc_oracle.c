@@ -310,6 +310,24 @@ void orc_div_e(const orc_grid *g, const double *E, double *out) {
             }
 }
 
+/* Marder's divergence cleaning (the iterative method the paper names for
+ * dissipating violations of Gauss's law): E += d dt nabla^+ F for a field F
+ * at nodes, F being the Gauss residual nabla^- . E - rho (less a reference).
+ * The forward difference of a node quantity sits where E is staggered. */
+void orc_marder(const orc_grid *g, double *E, const double *F, double d) {
+    long nc = ncell(g);
+    double ix = active(g, 0) ? 1.0 / g->d[0] : 0.0, iy = 1.0 / g->d[1], iz = 1.0 / g->d[2];
+    double h = d * g->dt;
+    for (int k = 0; k < g->n[2]; ++k)
+        for (int j = 0; j < g->n[1]; ++j)
+            for (int i = 0; i < g->n[0]; ++i) {
+                long c = idx3(g, i, j, k);
+                E[c] += h * (F[idx3(g, i + 1, j, k)] - F[c]) * ix;
+                E[nc + c] += h * (F[idx3(g, i, j + 1, k)] - F[c]) * iy;
+                E[2 * nc + c] += h * (F[idx3(g, i, j, k + 1)] - F[c]) * iz;
+            }
+}
+
 /* nabla^+ . B at cell centres */
 void orc_div_b(const orc_grid *g, const double *B, double *out) {
     long nc = ncell(g);

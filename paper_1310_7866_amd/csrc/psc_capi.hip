@@ -189,6 +189,21 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
             delete ctx;
             return s;
         }
+        // the current fold gathers a cell's current from the tiles of its own
+        // patch and its two neighbours, so with more than three patches along
+        // a dimension every patch (the truncated last one too) must be at
+        // least as wide as the tile's halo of order + 1 cells
+        for (int k = (d.dim == 3 ? 0 : 1); k < 3; ++k) {
+            const int np = (d.gdims[k] + d.patch[k] - 1) / d.patch[k];
+            const int last = d.gdims[k] - (np - 1) * d.patch[k];
+            if (np > 3 && (d.patch[k] < d.order + 1 || last < d.order + 1)) {
+                std::snprintf(msg, sizeof msg, "run %d: patches along dimension %d are narrower than the current halo "
+                              "(%d cells; patch %d, last patch %d)", r, k, d.order + 1, d.patch[k], last);
+                psc_status s = fail(ctx, PSC_ERR_INVALID, msg);
+                delete ctx;
+                return s;
+            }
+        }
         double inv2 = 0.0;
         for (int k = (d.dim == 3 ? 0 : 1); k < 3; ++k) inv2 += 1.0 / (d.dx[k] * d.dx[k]);
         if (d.dt >= 1.0 / std::sqrt(inv2)) {
@@ -597,6 +612,37 @@ psc_status psc_sort(psc_ctx *ctx, void *stream) {
     return PSC_OK;
 }
 
+psc_status psc_sort_radix(psc_ctx *ctx, void *stream) {
+    psc_status st = require_loaded(ctx);
+    if (st != PSC_OK) return st;
+    if (!ctx->mc_valid) return fail(ctx, PSC_ERR_STATE, "psc_sort_radix needs a preceding psc_push_particles");
+    hipStream_t s = (hipStream_t)stream;
+    int32_t *idx = ctx->at<int32_t>(ctx->off.load_idx), *keys_s = ctx->at<int32_t>(ctx->off.load_keys_s);
+    for (int r = 0; r < ctx->n_runs; ++r) {
+        const RunDev &R = ctx->runs[r];
+        int bits = 1;
+        while ((int64_t(1) << bits) < R.ncell) ++bits;
+        for (int sp = 0; sp < R.n_species; ++sp) {
+            const SpeciesDev &S = R.sp[sp];
+            if (S.n > 0) {
+                HIPCHECK(launch_iota(idx, S.n, s), "radix sort indices");
+                size_t tb = ctx->cub_bytes;
+                HIPCHECK(radix_sort_pairs(ctx->at<void>(ctx->off.cub), &tb, S.cell[ctx->front], keys_s, idx, S.perm,
+                                          S.n, bits, s),
+                         "radix sort");
+            }
+            HIPCHECK(launch_cell_starts(S.n, R.ncell, keys_s, S.cs[1 - ctx->cs_sel], ctx->err(), s),
+                     "radix sort offsets");
+        }
+    }
+    // the per (cell, move) counts of the push are consumed by psc_sort only
+    if ((st = clear_move_counts(ctx, s)) != PSC_OK) return st;
+    ctx->cs_sel = 1 - ctx->cs_sel;
+    ctx->perm_pending = 1;
+    ctx->mc_valid = 0;
+    return PSC_OK;
+}
+
 static psc_status one_step(psc_ctx *ctx, void *stream) {
     psc_status st;
     if ((st = psc_push_fields(ctx, PSC_B_HALF, stream)) != PSC_OK) return st;
@@ -695,6 +741,22 @@ psc_status psc_diagnostics(psc_ctx *ctx, double *out_dev, double *gauss_dev, voi
     Launch L = make_launch(ctx, (hipStream_t)stream);
     HIPCHECK(launch_diag(L, out_dev, gauss_dev, ctx->total_cells, ctx->at<int64_t>(ctx->off.run_base), ctx->front),
              "diagnostics");
+    return PSC_OK;
+}
+
+psc_status psc_marder(psc_ctx *ctx, const double *ref, double d, int iters, void *stream) {
+    psc_status st = require_loaded(ctx);
+    if (st != PSC_OK) return st;
+    if (iters < 0 || !(d > 0.0)) return PSC_ERR_INVALID;
+    if (ctx->mc_valid) return fail(ctx, PSC_ERR_STATE, "psc_marder runs between steps, not after a bare push");
+    for (const psc_run_desc &r : ctx->desc) {
+        double lap = 0.0;
+        for (int k = (r.dim == 3 ? 0 : 1); k < 3; ++k) lap += 4.0 / (r.dx[k] * r.dx[k]);
+        if (d * r.dt * lap > 2.0) return fail(ctx, PSC_ERR_INVALID, "Marder coefficient above the stability bound");
+    }
+    Launch L = make_launch(ctx, (hipStream_t)stream);
+    HIPCHECK(launch_marder(L, ref, d, iters, ctx->total_cells, ctx->at<int64_t>(ctx->off.run_base), ctx->front),
+             "marder");
     return PSC_OK;
 }
 

@@ -304,6 +304,77 @@ __global__ void k_count(const RunDev *__restrict__ runs, int n_runs, double *out
     out[(int64_t)r * PSC_DIAG_STRIDE + 9] = n;
 }
 
+// Marder cleaning, residual: F = (div^- E - rho) - ref at every node, written
+// over rho (which holds the charge density of the current particles)
+__global__ void __launch_bounds__(256) k_marder_residual(const RunDev *__restrict__ runs, int n_runs,
+                                                         const int64_t *__restrict__ run_base, int64_t total,
+                                                         const double *__restrict__ ref) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= total) return;
+    const RunDev &R = runs[find_run(run_base, n_runs, c)];
+    const int64_t idx = c - R.cell_base;
+    const int nx = R.n[0], ny = R.n[1], nz = R.n[2];
+    const int i = (int)(idx % nx), j = (int)((idx / nx) % ny), k = (int)(idx / ((int64_t)nx * ny));
+    const int64_t nc = R.ncell;
+    const double ix = R.dim == 3 ? 1.0 / R.dxd[0] : 0.0, iy = 1.0 / R.dxd[1], iz = 1.0 / R.dxd[2];
+    const int64_t im = i > 0 ? idx - 1 : idx + (nx - 1);
+    const int64_t jm = j > 0 ? idx - nx : idx + (int64_t)(ny - 1) * nx;
+    const int64_t km = k > 0 ? idx - (int64_t)nx * ny : idx + (int64_t)(nz - 1) * nx * ny;
+    const double dive = ((double)R.E[idx] - R.E[im]) * ix + ((double)R.E[nc + idx] - R.E[nc + jm]) * iy +
+                        ((double)R.E[2 * nc + idx] - R.E[2 * nc + km]) * iz;
+    R.rho[idx] = dive - R.rho[idx] - (ref ? ref[c] : 0.0);
+}
+
+// Marder cleaning, update: E += d dt grad^+ F (the forward difference of the
+// node field F lies where each E component is staggered)
+__global__ void __launch_bounds__(256) k_marder_update(const RunDev *__restrict__ runs, int n_runs,
+                                                       const int64_t *__restrict__ run_base, int64_t total, double d) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= total) return;
+    const RunDev &R = runs[find_run(run_base, n_runs, c)];
+    const int64_t idx = c - R.cell_base;
+    const int nx = R.n[0], ny = R.n[1], nz = R.n[2];
+    const int i = (int)(idx % nx), j = (int)((idx / nx) % ny), k = (int)(idx / ((int64_t)nx * ny));
+    const int64_t nc = R.ncell;
+    const double h = d * (double)R.dt;
+    const double ix = R.dim == 3 ? h / R.dxd[0] : 0.0, iy = h / R.dxd[1], iz = h / R.dxd[2];
+    const int64_t ip = i + 1 < nx ? idx + 1 : idx - (nx - 1);
+    const int64_t jp = j + 1 < ny ? idx + nx : idx - (int64_t)(ny - 1) * nx;
+    const int64_t kp = k + 1 < nz ? idx + (int64_t)nx * ny : idx - (int64_t)(nz - 1) * nx * ny;
+    const double *F = R.rho;
+    const double f = F[idx];
+    R.E[idx] = (float)(R.E[idx] + (F[ip] - f) * ix);
+    R.E[nc + idx] = (float)(R.E[nc + idx] + (F[jp] - f) * iy);
+    R.E[2 * nc + idx] = (float)(R.E[2 * nc + idx] + (F[kp] - f) * iz);
+}
+
+// charge density of the current particles into every run's rho
+static void launch_rho(const Launch &L, int front) {
+    for (int r = 0; r < L.n_runs; ++r) {
+        const RunDev &R = L.runs_host[r];
+        hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((R.ncell + 255) / 256)), dim3(256), 0, L.stream, R.rho,
+                           R.ncell);
+        for (int s = 0; s < R.n_species; ++s) {
+            const int64_t n = R.sp[s].n;
+            if (n == 0) continue;
+            hipLaunchKernelGGL(k_rho, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, L.stream, L.runs_dev, r, s,
+                               front, R.rho);
+        }
+    }
+}
+
+hipError_t launch_marder(const Launch &L, const double *ref, double d, int iters, int64_t total,
+                         const int64_t *run_base, int front) {
+    const unsigned g = (unsigned)((total + 255) / 256);
+    for (int it = 0; it < iters; ++it) {
+        launch_rho(L, front);
+        hipLaunchKernelGGL(k_marder_residual, dim3(g), dim3(256), 0, L.stream, L.runs_dev, L.n_runs, run_base, total,
+                           ref);
+        hipLaunchKernelGGL(k_marder_update, dim3(g), dim3(256), 0, L.stream, L.runs_dev, L.n_runs, run_base, total, d);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_diag(const Launch &L, double *out, double *gauss, int64_t total, const int64_t *run_base,
                        int front) {
     const int64_t nout = (int64_t)L.n_runs * PSC_DIAG_STRIDE;

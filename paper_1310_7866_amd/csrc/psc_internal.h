@@ -235,8 +235,11 @@ hipError_t launch_cell_starts(int64_t n, int64_t ncell, const int32_t *sorted_ke
 hipError_t launch_get(const RunDev &r, int species, int front, int perm_pending, int32_t *cell,
                       float *off, float *u, int32_t *id, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_iota(int32_t *p, int64_t n, hipStream_t s);
 hipError_t launch_diag(const Launch &L, double *out, double *gauss, int64_t total_cells,
                        const int64_t *run_cell_base_dev, int front);
+hipError_t launch_marder(const Launch &L, const double *ref, double d, int iters, int64_t total_cells,
+                         const int64_t *run_cell_base_dev, int front);
 size_t adjoint_lds_bytes(int order, const int P[3]);
 hipError_t launch_adjoint(const Launch &L, const AdjRun *adj_dev, const AdjRun *adj_host, const Unit *units,
                           int n_units, int32_t *item_start, int64_t max_items, int chunk, int order,

@@ -507,6 +507,17 @@ hipError_t launch_get(const RunDev &r, int species, int front, int perm_pending,
     return hipGetLastError();
 }
 
+__global__ void k_iota(int32_t *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (int32_t)i;
+}
+
+hipError_t launch_iota(int32_t *p, int64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_iota, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
 hipError_t radix_sort_pairs(void *temp, size_t *temp_bytes, const int32_t *keys_in, int32_t *keys_out,
                             const int32_t *vals_in, int32_t *vals_out, int64_t n, int bits, hipStream_t s) {
     return hipcub::DeviceRadixSort::SortPairs(temp, *temp_bytes, keys_in, keys_out, vals_in, vals_out, (int)n, 0, bits,

@@ -27,9 +27,9 @@ STATUS = {0: "PSC_OK", 1: "PSC_ERR_INVALID", 2: "PSC_ERR_CFL", 3: "PSC_ERR_LDS",
 
 # every symbol include/psc.h declares
 EXPORTS = ["psc_init_patches", "psc_workspace_size", "psc_bind", "psc_load_particles", "psc_push_fields",
-           "psc_push_particles", "psc_deposit_current", "psc_sort", "psc_step", "psc_get_particles",
+           "psc_push_particles", "psc_deposit_current", "psc_sort", "psc_sort_radix", "psc_step", "psc_get_particles",
            "psc_keys_to_cells", "psc_particle_count", "psc_front", "psc_sort_view", "psc_diagnostics",
-           "psc_get_perm", "psc_adjoint_step", "psc_set_launch", "psc_balance", "psc_partition",
+           "psc_get_perm", "psc_marder", "psc_adjoint_step", "psc_set_launch", "psc_balance", "psc_partition",
            "psc_check", "psc_status_string", "psc_last_error", "psc_destroy"]
 LAUNCH_GRID, LAUNCH_QUEUE, LAUNCH_PARTITION = 0, 1, 2
 RUN_ADJOINT = 1
@@ -83,6 +83,8 @@ def load_library(path: str = LIB_PATH):
     L.psc_push_particles.argtypes = [vp, vp]
     L.psc_deposit_current.argtypes = [vp, vp]
     L.psc_sort.argtypes = [vp, vp]
+    L.psc_sort_radix.argtypes = [vp, vp]
+    L.psc_marder.argtypes = [vp, vp, C.c_double, C.c_int, vp]
     L.psc_step.argtypes = [vp, i32, i32, vp]
     L.psc_get_particles.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
     L.psc_keys_to_cells.argtypes = [vp, i32, i64, vp, vp, vp]
@@ -247,6 +249,16 @@ class PscSim:
 
     def sort(self):
         self._call(self.L.psc_sort(self.ctx, self._stream()))
+
+    def marder(self, d: float, ref=None, iters: int = 1):
+        """Marder cleaning: E += d dt grad(div E - rho - ref); ref a device
+        float64 tensor laid out like the gauss output of diagnostics()."""
+        self._call(self.L.psc_marder(self.ctx, None if ref is None else ref.data_ptr(), float(d), int(iters),
+                                     self._stream()))
+
+    def sort_radix(self):
+        """The same order by a general multi-pass radix sort (timing ablation)."""
+        self._call(self.L.psc_sort_radix(self.ctx, self._stream()))
 
     def step(self, nsteps: int = 1, use_graph: bool = False):
         self._call(self.L.psc_step(self.ctx, int(nsteps), int(use_graph), self._stream()))

@@ -68,6 +68,19 @@ def test_bad_geometry_rejected():
     assert _init(d) == 1
 
 
+def test_patches_narrower_than_the_current_halo_rejected():
+    """The current fold reads a cell's own patch and its two neighbours: with
+    more than three patches along a dimension, a patch (or the truncated last
+    one) narrower than order + 1 cells would drop current.  Init refuses it."""
+    for order, patch, n, ok in ((2, 2, 16, False), (2, 3, 15, True), (1, 2, 16, True), (1, 1, 16, False),
+                                (2, 8, 26, False), (2, 8, 27, True), (2, 2, 6, True)):
+        c = cases.thermal2d(ny=n, nz=12, ppc=1, patch=8, order=order)
+        d = psc.run_desc(c)
+        d.patch[1] = patch
+        want = 0 if ok else 1
+        assert _init(d) == want, (order, patch, n)
+
+
 def test_lds_overflow_rejected():
     c = cases.thermal2d(ny=128, nz=128, ppc=1, patch=64, order=2)
     assert _init(psc.run_desc(c)) == 3
