@@ -223,6 +223,47 @@ def marder_leg(steps: int = 2000, every: int = 50, frac: float = 0.5):
     return out
 
 
+def deposit_leg(steps: int = 10):
+    """1st-order particle kernel with the Esirkepov and the Villasenor-Buneman
+    deposit on the same thermal 2-d workload (1024x512 cells, 16 electron-ion
+    pairs per cell, v_th 0.1 / 0.02) and the 3-d Weibel setup at 128^3."""
+    import torch
+    from paper_1310_7866_amd import cases
+    from paper_1310_7866_amd.psc import B_HALF, E_FULL, PscSim
+    out = {}
+    for case in (cases.thermal2d(ny=1024, nz=512, ppc=16, order=1, patch=32),
+                 cases.weibel3d(ppc=32, order=1, patch=8, nxyz=(128, 128, 128))):
+        row = {}
+        for dep in ("esirkepov", "vb"):
+            case.deposit = dep
+            sim = PscSim(case, with_ids=False)
+            stream = torch.cuda.current_stream()
+            sim.step(3)
+            ev = lambda: torch.cuda.Event(enable_timing=True)
+            pe = [(ev(), ev()) for _ in range(steps)]
+            torch.cuda.synchronize()
+            for k in range(steps):
+                sim.push_fields(B_HALF)
+                pe[k][0].record(stream)
+                sim.push_particles()
+                pe[k][1].record(stream)
+                sim.push_fields(B_HALF)
+                sim.deposit_current()
+                sim.push_fields(E_FULL)
+                sim.sort()
+            torch.cuda.synchronize()
+            sim.check()
+            ms = sum(a.elapsed_time(b) for a, b in pe) / steps
+            row[dep] = dict(push_ms=round(ms, 4), pushes_per_s=case.n_particles / (ms / 1e3))
+            print(f"[bench] {case.name} {dep}: push {ms:.3f} ms", file=sys.stderr, flush=True)
+            sim.close()
+            del sim
+            torch.cuda.empty_cache()
+        case.deposit = "esirkepov"
+        out[f"{case.name} {'x'.join(str(g) for g in case.gdims if g > 1)}, {case.n_particles} particles"] = row
+    return out
+
+
 def adjoint_leg(every: int = 10, nsteps: int = 50):
     """Gradient of the final field energy on the 256 x 256 double Harris sheet
     (64 particles per cell at n = 1, 2nd order, 32 x 32 patches): forward with
@@ -314,7 +355,7 @@ def main():
                     help="oracle baseline on every n-th particle (1: the whole Harris workload, about 18 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the adjoint and batch legs")
-    ap.add_argument("--only", choices=("adjoint", "batch", "supercells", "marder"), default=None,
+    ap.add_argument("--only", choices=("adjoint", "batch", "supercells", "marder", "deposit"), default=None,
                     help="run only the adjoint or the batch leg and print its JSON")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--launch", default="", help="fixed launch shape mode,chunk,threads,run (skips tuning)")
@@ -343,6 +384,9 @@ def main():
         return
     if args.only == "marder":
         print(json.dumps({"marder": marder_leg()}))
+        return
+    if args.only == "deposit":
+        print(json.dumps({"deposit": deposit_leg()}))
         return
 
     if args.calibrate:

@@ -102,6 +102,13 @@ typedef struct {
 
 /* psc_run_desc.flags: reserve workspace for psc_adjoint_step */
 #define PSC_RUN_ADJOINT 1
+/* psc_run_desc.flags: deposit the current of this 1st-order run with the
+ * Villasenor-Buneman scheme (the paper's choice at 1st order: the path is
+ * cut at cell faces and each piece adds the flux of its linear cloud; in
+ * 2-d the out-of-plane current takes the linear weights at each piece's
+ * midpoint) instead of Esirkepov's.  Order 2: PSC_ERR_UNSUPPORTED.  Not
+ * with PSC_RUN_ADJOINT (the reverse step differentiates Esirkepov). */
+#define PSC_RUN_VB 2
 
 typedef struct {
     float *E, *B, *J;                          /* 3 * ncell float32 each               */

@@ -37,7 +37,7 @@ def build(force: bool = True) -> str:
 
 class _Grid(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("d", C.c_double * 3),
-                ("dt", C.c_double), ("order", C.c_int)]
+                ("dt", C.c_double), ("order", C.c_int), ("vb", C.c_int)]
 
 
 _lib = None
@@ -59,6 +59,7 @@ def lib():
         L.orc_interp.restype = C.c_double
         L.orc_boris.argtypes = [dp, dp, dp, C.c_double]
         L.orc_deposit.argtypes = [g, dp, dp, dp, C.c_double, C.c_double]
+        L.orc_deposit_vb.argtypes = [g, dp, dp, dp, C.c_double, C.c_double]
         L.orc_push_particles.argtypes = [g, C.c_long, dp, dp, dp, dp, dp, C.c_double, C.c_double, C.c_double]
         L.orc_push_b.argtypes = [g, dp, dp, C.c_double]
         L.orc_push_e.argtypes = [g, dp, dp, C.c_void_p, C.c_double]
@@ -87,8 +88,9 @@ def _bind_adjoint(L, g, dp, ip):
                                    C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), dp, dp, dp]
 
 
-def grid(dim: int, n: Sequence[int], d: Sequence[float], dt: float, order: int) -> _Grid:
+def grid(dim: int, n: Sequence[int], d: Sequence[float], dt: float, order: int, vb: bool = False) -> _Grid:
     g = _Grid()
+    g.vb = int(bool(vb))
     g.dim = dim
     for i in range(3):
         g.n[i] = int(n[i])
@@ -124,7 +126,8 @@ class OracleSim:
     def __init__(self, case, sort_initial: bool = True):
         self.case = case
         self.dim = case.dim
-        self.g = grid(case.dim, case.gdims, case.dx, case.dt, case.order)
+        self.g = grid(case.dim, case.gdims, case.dx, case.dt, case.order,
+                      vb=getattr(case, "deposit", "esirkepov") == "vb")
         self.nc = case.ncell
         self.E = case.E.astype(np.float64).reshape(-1).copy()
         self.B = case.B.astype(np.float64).reshape(-1).copy()
@@ -258,6 +261,15 @@ def deposit(g: _Grid, xi0, xi1, qw, vx=0.0) -> np.ndarray:
     J = np.zeros(3 * n)
     lib().orc_deposit(C.byref(g), J, np.asarray(xi0, np.float64), np.asarray(xi1, np.float64),
                       float(qw), float(vx))
+    return J
+
+
+def deposit_vb(g: _Grid, xi0, xi1, qw, vx=0.0) -> np.ndarray:
+    """Villasenor-Buneman current of one 1st-order particle (path cut at faces)."""
+    n = g.n[0] * g.n[1] * g.n[2]
+    J = np.zeros(3 * n)
+    lib().orc_deposit_vb(C.byref(g), J, np.asarray(xi0, np.float64), np.asarray(xi1, np.float64),
+                         float(qw), float(vx))
     return J
 
 

@@ -22,6 +22,9 @@
  *   - Esirkepov's charge-conserving current deposit (sec. "Time
  *     integration", charge continuity), written from the discrete
  *     continuity equation rho^{n+1/2} - rho^{n-1/2} + dt div^- j = 0;
+ *   - the Villasenor-Buneman deposit the paper uses for 1st-order
+ *     particles (same section), by cutting the path at cell faces;
+ *   - Marder's divergence cleaning step (same section);
  *   - a stable sort of particles by a patch-major cell key (sec. "Sorting
  *     and Communication").
  *
@@ -48,6 +51,7 @@ typedef struct {
     double d[3];    /* cell sizes                                       */
     double dt;      /* time step                                        */
     int order;      /* 1: b1 weights, 2: b2 weights                     */
+    int vb;         /* 1st order: Villasenor-Buneman deposit instead of Esirkepov */
 } orc_grid;
 
 /* ----------------------------------------------------------------------- */
@@ -217,6 +221,79 @@ void orc_deposit(const orc_grid *g, double *J, const double xi0[3], const double
 }
 
 /* ----------------------------------------------------------------------- */
+/* Villasenor-Buneman deposit (1st order; the paper's charge-conserving     */
+/* scheme for 1st-order particles, sec. "Time integration")                 */
+/* ----------------------------------------------------------------------- */
+
+/* The straight path xi0 -> xi1 is cut at the cell faces it crosses.  A piece
+ * inside one cell moves a linear (area in 2-d, volume in 3-d) charge cloud;
+ * the current through each edge of that cell is the cloud's flux: along x,
+ * q w dx/dt times the time average over the piece of the product of the
+ * linear weights in the other directions, which for straight motion is the
+ * product at the piece's midpoint plus (+/-) the product of the other two
+ * displacements over 12 (3-d).  In 2-d the out-of-plane current is
+ * q w v_x times the piece's share of the step times the linear weights at
+ * its midpoint. */
+void orc_deposit_vb(const orc_grid *g, double *J, const double xi0[3], const double xi1[3],
+                    double qw, double vx) {
+    double t[5];
+    int nt = 0;
+    t[nt++] = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        if (!active(g, d)) continue;
+        double a = xi0[d], b = xi1[d];
+        double fa = floor(a), fb = floor(b);
+        if (fa != fb) {                          /* one face between them (|b - a| < 1) */
+            double face = fb > fa ? fb : fa;
+            t[nt++] = (face - a) / (b - a);
+        }
+    }
+    t[nt++] = 1.0;
+    for (int i = 1; i < nt; ++i)                 /* sort the cut parameters */
+        for (int k = i; k > 0 && t[k] < t[k - 1]; --k) {
+            double x = t[k]; t[k] = t[k - 1]; t[k - 1] = x;
+        }
+    long nc = ncell(g);
+    double *Jx = J, *Jy = J + nc, *Jz = J + 2 * nc;
+    for (int p = 0; p + 1 < nt; ++p) {
+        double ta = t[p], tb = t[p + 1];
+        if (!(tb > ta)) continue;
+        int c[3] = {0, 0, 0};
+        double m[3] = {0, 0, 0}, dd[3] = {0, 0, 0};
+        for (int d = 0; d < 3; ++d) {
+            if (!active(g, d)) continue;
+            double pa = xi0[d] + ta * (xi1[d] - xi0[d]), pb = xi0[d] + tb * (xi1[d] - xi0[d]);
+            double mid = 0.5 * (pa + pb);
+            c[d] = (int)floor(mid);
+            m[d] = mid - c[d];
+            dd[d] = pb - pa;
+        }
+        /* linear weights of the midpoint at the cell's lower (0) and upper (1) node */
+        double w[3][2];
+        for (int d = 0; d < 3; ++d) { w[d][0] = 1.0 - m[d]; w[d][1] = m[d]; }
+        if (g->dim == 3) {
+            double fx = qw * g->d[0] / g->dt, fy = qw * g->d[1] / g->dt, fz = qw * g->d[2] / g->dt;
+            for (int b = 0; b < 2; ++b)
+                for (int e = 0; e < 2; ++e) {
+                    double sg = (b == e) ? 1.0 : -1.0;
+                    Jx[idx3(g, c[0], c[1] + b, c[2] + e)] += fx * dd[0] * (w[1][b] * w[2][e] + sg * dd[1] * dd[2] / 12.0);
+                    Jy[idx3(g, c[0] + b, c[1], c[2] + e)] += fy * dd[1] * (w[0][b] * w[2][e] + sg * dd[0] * dd[2] / 12.0);
+                    Jz[idx3(g, c[0] + b, c[1] + e, c[2])] += fz * dd[2] * (w[0][b] * w[1][e] + sg * dd[0] * dd[1] / 12.0);
+                }
+        } else {
+            double fy = qw * g->d[1] / g->dt, fz = qw * g->d[2] / g->dt;
+            for (int e = 0; e < 2; ++e) {
+                Jy[idx3(g, 0, c[1], c[2] + e)] += fy * dd[1] * w[2][e];
+                Jz[idx3(g, 0, c[1] + e, c[2])] += fz * dd[2] * w[1][e];
+            }
+            for (int e = 0; e < 2; ++e)
+                for (int b = 0; b < 2; ++b)
+                    Jx[idx3(g, 0, c[1] + b, c[2] + e)] += qw * vx * (tb - ta) * w[1][b] * w[2][e];
+        }
+    }
+}
+
+/* ----------------------------------------------------------------------- */
 /* Particle loop (fig. psc_new: push_particle_p, push_particle_x, deposit_j) */
 /* ----------------------------------------------------------------------- */
 
@@ -239,7 +316,8 @@ void orc_push_particles(const orc_grid *g, long np, double *xi, double *u,
         double gam = sqrt(1.0 + uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2]);
         for (int d = 0; d < 3; ++d)
             x1[d] = active(g, d) ? x0[d] + g->dt * uu[d] / (gam * g->d[d]) : x0[d];
-        orc_deposit(g, J, x0, x1, q * w, uu[0] / gam);
+        if (g->vb) orc_deposit_vb(g, J, x0, x1, q * w, uu[0] / gam);
+        else orc_deposit(g, J, x0, x1, q * w, uu[0] / gam);
         for (int d = 0; d < 3; ++d) {
             double x = x1[d];
             if (active(g, d)) {

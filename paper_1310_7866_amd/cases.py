@@ -66,6 +66,7 @@ class Case:
     species: List[Species]
     E: np.ndarray             # float32 (3, ncell)
     B: np.ndarray             # float32 (3, ncell)
+    deposit: str = "esirkepov"   # or "vb": Villasenor-Buneman (1st order only)
 
     @property
     def ncell(self) -> int:

@@ -330,27 +330,42 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles(const RunDev *__res
     // of doubles runs at the rate of integer atomics, the float one far slower)
     double *gt = reinterpret_cast<double *>(lds + LL.gt);
     const int64_t nc = R.ncell;
+    // The chunk's particles are sorted by cell, so they lie in the cell rows
+    // between those of its first and last particle; only the tile rows their
+    // stencils reach are staged, cleared and flushed.  Field-tile rows:
+    // lz + FLO - 1 .. lz + FLO + ORDER; current-tile rows: lz .. lz + 2 ORDER + 1.
+    const int pc_cells = hy * hz;
+    const int lf = imin(imax(AS.key[beg] - (int32_t)kb, 0), pc_cells - 1);
+    const int ll = imin(imax(AS.key[end - 1] - (int32_t)kb, 0), pc_cells - 1);
+    const int zf = lf / hy, zl = ll / hy;
+    const int fr0 = zf + FLO - 1, fr1 = imin(zl + FLO + ORDER, fz - 1);   // field-tile rows [fr0, fr1]
+    const int jr0 = zf, jr1 = imin(zl + 2 * ORDER + 1, jz - 1);           // current-tile rows [jr0, jr1]
     {
         const float inv_fy = 1.0f / fy;
-        for (int t = threadIdx.x; t < fcells; t += NT) {
+        const int n_f = (fr1 - fr0 + 1) * fy;
+        for (int q = threadIdx.x; q < n_f; q += NT) {
             int ty;
-            const int tz = divmod_small(t, fy, inv_fy, ty);
+            const int tz = fr0 + divmod_small(q, fy, inv_fy, ty);
+            const int t = tz * fy + ty;
             const int64_t g = wrap(oy + ty - FLO, R.n[1]) + (int64_t)R.n[1] * wrap(oz + tz - FLO, R.n[2]);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 ftile[c * fcells + t] = A.E[c * nc + g];
                 ftile[(3 + c) * fcells + t] = A.B1[c * nc + g];
+                gt[c * fcells + t] = 0.0;
+                gt[(3 + c) * fcells + t] = 0.0;
             }
         }
         const float inv_jy = 1.0f / jy;
-        for (int t = threadIdx.x; t < jcells; t += NT) {
+        const int n_j = (jr1 - jr0 + 1) * jy;
+        for (int q = threadIdx.x; q < n_j; q += NT) {
             int ty;
-            const int tz = divmod_small(t, jy, inv_jy, ty);
+            const int tz = jr0 + divmod_small(q, jy, inv_jy, ty);
+            const int t = tz * jy + ty;
             const int64_t g = wrap(oy + ty - JLO, R.n[1]) + (int64_t)R.n[1] * wrap(oz + tz - JLO, R.n[2]);
 #pragma unroll
             for (int c = 0; c < 3; ++c) ljt[c * jcells + t] = A.LJ[c * nc + g];
         }
-        for (int t = threadIdx.x; t < 6 * fcells; t += NT) gt[t] = 0.0;
     }
     __syncthreads();
 
@@ -588,7 +603,10 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles(const RunDev *__res
     }
     __syncthreads();
     float *gp = A.gtile + (int64_t)U.patch * 6 * fcells;
-    for (int t2 = threadIdx.x; t2 < 6 * fcells; t2 += NT) {
+    const int n_f = (fr1 - fr0 + 1) * fy;
+    for (int q = threadIdx.x; q < 6 * n_f; q += NT) {
+        const int c = q / n_f, r = q - c * n_f;
+        const int t2 = c * fcells + fr0 * fy + r;
         const double v = gt[t2];
         if (v != 0.0) atomicAdd(&gp[t2], (float)v);
     }

@@ -204,6 +204,12 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
                 return s;
             }
         }
+        if ((d.flags & PSC_RUN_VB) && (d.order != 1 || (d.flags & PSC_RUN_ADJOINT))) {
+            std::snprintf(msg, sizeof msg, "run %d: the Villasenor-Buneman deposit is for 1st order, without adjoint", r);
+            psc_status s = fail(ctx, PSC_ERR_UNSUPPORTED, msg);
+            delete ctx;
+            return s;
+        }
         double inv2 = 0.0;
         for (int k = (d.dim == 3 ? 0 : 1); k < 3; ++k) inv2 += 1.0 / (d.dx[k] * d.dx[k]);
         if (d.dt >= 1.0 / std::sqrt(inv2)) {
@@ -237,6 +243,7 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
         std::memset(&R, 0, sizeof R);
         R.dim = d.dim;
         R.order = d.order;
+        R.vb = (d.flags & PSC_RUN_VB) != 0;
         for (int k = 0; k < 3; ++k) {
             R.n[k] = d.gdims[k];
             R.P[k] = d.patch[k];
@@ -891,6 +898,9 @@ psc_status psc_adjoint_step(psc_ctx *ctx, const psc_adj_fwd *fwd, const psc_adj_
     if (!ctx || !ctx->bound || !fwd || !adj) return PSC_ERR_INVALID;
     if (!ctx->adjoint) return fail(ctx, PSC_ERR_STATE, "context was created without PSC_RUN_ADJOINT");
     if (ctx->dim != 2) return fail(ctx, PSC_ERR_UNSUPPORTED, "the adjoint step is implemented for 2-d runs");
+    for (int r = 0; r < ctx->n_runs; ++r)
+        if (ctx->runs[r].vb)
+            return fail(ctx, PSC_ERR_UNSUPPORTED, "the adjoint step differentiates the Esirkepov deposit");
     hipStream_t s = (hipStream_t)stream;
     for (int r = 0; r < ctx->n_runs; ++r) {
         const RunDev &R = ctx->runs[r];

@@ -53,6 +53,7 @@ struct SpeciesDev {
 
 struct RunDev {
     int dim, order;
+    int vb;              // order 1: Villasenor-Buneman deposit instead of Esirkepov
     int n[3];            // cells
     int P[3];            // nominal patch size
     int np[3];           // patches per dimension
@@ -118,6 +119,7 @@ __host__ __device__ inline int cur_lo(int order) { return order; }
 __host__ __device__ inline int cur_hi(int order) { return order + 1; }
 
 __host__ __device__ inline int imin(int a, int b) { return a < b ? a : b; }
+__host__ __device__ inline int imax(int a, int b) { return a > b ? a : b; }
 __host__ __device__ inline int wrap(int i, int n) {
     int r = i % n;
     return r < 0 ? r + n : r;

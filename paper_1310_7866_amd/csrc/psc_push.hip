@@ -29,16 +29,33 @@ namespace psc {
 #ifndef PSC_PACK_TAILS
 #define PSC_PACK_TAILS 3
 #endif
+//   PSC_FRAMES       0 sends every particle through the per-lane atomic
+//                    deposit (the ablation of the frames and wave sums)
+#ifndef PSC_FRAMES
+#define PSC_FRAMES 1
+#endif
+//   PSC_BAND         0 stages and flushes the whole patch tile for every
+//                    work item instead of the band of planes its particles reach
+#ifndef PSC_BAND
+#define PSC_BAND 1
+#endif
+//   PSC_WAVES_3D1    waves per SIMD the 3-d order-1 kernel keeps room for
+//                    (0: the register allocator's free choice)
+#ifndef PSC_WAVES_3D1
+#define PSC_WAVES_3D1 4
+#endif
 //   PSC_WAVES_PER_EU occupancy the register allocator must allow for every
 //                    instantiation (0: the measured per-shape choice below)
 #ifndef PSC_WAVES_PER_EU
 #define PSC_WAVES_PER_EU 0
 #endif
 // Waves per SIMD the register allocator must leave room for (0: its free
-// choice; the LDS tiles already limit a compute unit to two workgroups).
+// choice).  In 2-d the LDS tiles already limit a compute unit to two
+// 512-thread workgroups; the small 3-d order-1 tiles allow more, so that
+// kernel keeps to 128 registers (four waves per SIMD).
 template <int DIM, int ORDER, bool RUNS>
 constexpr int push_waves() {
-    return PSC_WAVES_PER_EU > 0 ? PSC_WAVES_PER_EU : 0;
+    return PSC_WAVES_PER_EU > 0 ? PSC_WAVES_PER_EU : (DIM == 3 && ORDER == 1 && !RUNS ? PSC_WAVES_3D1 : 0);
 }
 #define PSC_OCCUPANCY __attribute__((amdgpu_waves_per_eu(push_waves<DIM, ORDER, RUNS>())))
 constexpr int kScanWidth = PSC_SCAN_WIDTH;
@@ -199,6 +216,86 @@ __device__ __forceinline__ void deposit_lane(double *jtile, int jcells, int jx_,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Villasenor-Buneman current of one 1st-order particle, lane by lane: the
+// straight path from offset o in its cell to s + o1 is cut where it crosses
+// cell faces (at most once per dimension); each piece lies in one cell and
+// adds the flux of its linear cloud through that cell's edges: along y,
+// q w dy/dt times the time average of the other linear weights over the
+// piece (midpoint product, plus the alternating dx dz / 12 term in 3-d).  In
+// 2-d the out-of-plane current is q w v_x times the piece's share of the
+// step times the linear weights at its midpoint.
+// ---------------------------------------------------------------------------
+template <int DIM>
+__device__ __forceinline__ void deposit_lane_vb(double *jtile, int jcells, int jx_, int jy_, int lx, int ly, int lz,
+                                                const float o[3], const int s[3], const float o1[3], float jfx,
+                                                float jfy, float jfz, float fxv) {
+    constexpr int D0 = DIM == 3 ? 0 : 1;   // first active dimension
+    constexpr int JLO = 1;
+    float dx[3] = {0.0f, 0.0f, 0.0f};
+    float t[4];
+    int nt = 0;
+#pragma unroll
+    for (int d = D0; d < 3; ++d) {
+        dx[d] = ((float)s[d] + o1[d]) - o[d];
+        if (s[d] != 0) t[nt++] = ((s[d] > 0 ? 1.0f : 0.0f) - o[d]) / dx[d];
+    }
+    for (int i = 1; i < nt; ++i)   // at most three cut points
+        for (int k = i; k > 0 && t[k] < t[k - 1]; --k) {
+            const float x = t[k];
+            t[k] = t[k - 1];
+            t[k - 1] = x;
+        }
+    t[nt] = 1.0f;
+    double *Jx = jtile, *Jy = jtile + jcells, *Jz = jtile + 2 * jcells;
+    const float gx = -jfx, gy = -jfy, gz = -jfz;   // q w dx_d / dt
+    float ta = 0.0f;
+    for (int p = 0; p <= nt; ++p) {
+        const float tb = t[p];
+        if (tb > ta) {
+            int c[3] = {0, 0, 0};
+            float m[3] = {0.0f, 0.0f, 0.0f}, dd[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int d = D0; d < 3; ++d) {
+                const float pa = fmaf(ta, dx[d], o[d]), pb = fmaf(tb, dx[d], o[d]);
+                const float mid = 0.5f * (pa + pb);
+                c[d] = (int)floorf(mid);
+                m[d] = mid - (float)c[d];
+                dd[d] = pb - pa;
+            }
+            if constexpr (DIM == 2) {
+                const int base = (lz + c[2] + JLO) * jy_ + (ly + c[1] + JLO);
+                const float wy0 = 1.0f - m[1], wy1 = m[1], wz0 = 1.0f - m[2], wz1 = m[2];
+                lds_add(&Jy[base], gy * dd[1] * wz0);
+                lds_add(&Jy[base + jy_], gy * dd[1] * wz1);
+                lds_add(&Jz[base], gz * dd[2] * wy0);
+                lds_add(&Jz[base + 1], gz * dd[2] * wy1);
+                const float f = fxv * (tb - ta);
+                lds_add(&Jx[base], f * wy0 * wz0);
+                lds_add(&Jx[base + 1], f * wy1 * wz0);
+                lds_add(&Jx[base + jy_], f * wy0 * wz1);
+                lds_add(&Jx[base + jy_ + 1], f * wy1 * wz1);
+            } else {
+                const int pxy = jx_ * jy_;
+                const int base = (lz + c[2] + JLO) * pxy + (ly + c[1] + JLO) * jx_ + (lx + c[0] + JLO);
+                const float w[3][2] = {{1.0f - m[0], m[0]}, {1.0f - m[1], m[1]}, {1.0f - m[2], m[2]}};
+                const float xyz = dd[1] * dd[2] * (1.0f / 12.0f), xz = dd[0] * dd[2] * (1.0f / 12.0f),
+                            xy = dd[0] * dd[1] * (1.0f / 12.0f);
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        const float sg = b == e ? 1.0f : -1.0f;
+                        lds_add(&Jx[base + e * pxy + b * jx_], gx * dd[0] * fmaf(sg, xyz, w[1][b] * w[2][e]));
+                        lds_add(&Jy[base + e * pxy + b], gy * dd[1] * fmaf(sg, xz, w[0][b] * w[2][e]));
+                        lds_add(&Jz[base + e * jx_ + b], gz * dd[2] * fmaf(sg, xy, w[0][b] * w[1][e]));
+                    }
+            }
+        }
+        ta = tb;
+    }
+}
+
 // Node weights of one dimension on the fixed per-cell frame used by the wave
 // reduction: order 1 -> nodes {0, 1}, order 2 -> nodes {-1, 0, 1, 2}.  Valid
 // for a particle whose support does not change (see `stays` below).
@@ -353,12 +450,38 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
     float *pk = lds + LL.stage + (threadIdx.x >> 6) * align4(PKW);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
+    // The item's particles are sorted by cell, so they lie in the planes (2-d:
+    // rows) of cells between those of its first and last particle; only the
+    // tile planes their stencils reach are staged, cleared and flushed: field
+    // tile lz + FLO - 1 .. lz + FLO + ORDER, current tile lz .. lz + 2 ORDER + 1.
+    const int fplane = fx * fy, jplane = jx_ * jy_;
+    int fr0, fr1, jr0, jr1;
+    {
+        int32_t sf = use_perm ? S.perm[beg] : beg, sl = use_perm ? S.perm[end - 1] : end - 1;
+        if ((uint32_t)sf >= (uint32_t)S.n) sf = beg;
+        if ((uint32_t)sl >= (uint32_t)S.n) sl = end - 1;
+        const int32_t *ck = S.cell[front];
+        const int cpl = hx * hy;   // cells per plane of the patch
+        int zf = imin(imax(ck[sf] - (int32_t)kb, 0), pcells - 1) / cpl;
+        int zl = imin(imax(ck[sl] - (int32_t)kb, 0), pcells - 1) / cpl;
+        if (zl < zf || !PSC_BAND) {   // not in order (or banding off): the whole tile
+            zf = 0;
+            zl = hz - 1;
+        }
+        fr0 = zf + FLO - 1;
+        fr1 = imin(zl + FLO + ORDER, fz - 1);
+        jr0 = zf;
+        jr1 = imin(zl + 2 * ORDER + 1, jz_ - 1);
+    }
+    const int n_fband = (fr1 - fr0 + 1) * fplane, n_jband = (jr1 - jr0 + 1) * jplane;
+
     // stage E, B (+ghosts), clear the current tile
     {
         const float inv_fx = 1.0f / fx, inv_fy = 1.0f / fy;
         const int64_t nc = R.ncell;
         const gptr<const float> Eg = to_global<const float>(R.E), Bg = to_global<const float>(R.B);
-        for (int t = threadIdx.x; t < fcells; t += NT) {
+        for (int q = threadIdx.x; q < n_fband; q += NT) {
+            const int t = fr0 * fplane + q;
             int tx = 0, ty, tz;
             if constexpr (DIM == 3) {
                 const int q = divmod_small(t, fx, inv_fx, tx);
@@ -383,7 +506,10 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
                 }
             }
         }
-        for (int t = threadIdx.x; t < 3 * jcells; t += NT) jtile[t] = 0.0;
+        for (int q = threadIdx.x; q < 3 * n_jband; q += NT) {
+            const int c = q / n_jband;
+            jtile[c * jcells + jr0 * jplane + (q - c * n_jband)] = 0.0;
+        }
     }
     __syncthreads();
 
@@ -415,6 +541,20 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
     const float inv_hx = 1.0f / hx, inv_hy = 1.0f / hy;
     double *Jx = jtile, *Jy = jtile + jcells, *Jz = jtile + 2 * jcells;
     uint32_t flags = 0;
+    // 1st-order runs may deposit with Villasenor-Buneman: the particles that
+    // leave their cell go through the piece-wise lane deposit, and in 2-d the
+    // out-of-plane frame current drops the path-average term
+    const bool vb = ORDER == 1 && R.vb;
+    const float x12 = vb ? 0.0f : 1.0f / 12.0f;
+    auto deposit_one = [&](int lx_, int ly_, int lz_, const float *a0, const int *qs, const float *a1, float fx_) {
+        if constexpr (ORDER == 1) {
+            if (vb) {
+                deposit_lane_vb<DIM>(jtile, jcells, jx_, jy_, lx_, ly_, lz_, a0, qs, a1, jfx, jfy, jfz, fx_);
+                return;
+            }
+        }
+        deposit_lane<DIM, ORDER>(jtile, jcells, jx_, jy_, lx_, ly_, lz_, a0, qs, a1, jfx, jfy, jfz, fx_);
+    };
 
     // deposit queued particles [0, n) of this wave, one per lane
     int qn = 0;   // queued particles (the same in every lane of the wave)
@@ -431,8 +571,7 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
                 a1[d0 + k] = cq[(1 + D + k) * QS + lane];
             }
             const float qfx = DIM == 2 ? cq[5 * QS + lane] : 0.0f;
-            deposit_lane<DIM, ORDER>(jtile, jcells, jx_, jy_, pk & 255, (pk >> 8) & 255, (pk >> 16) & 255, a0, qs,
-                                     a1, jfx, jfy, jfz, qfx);
+            deposit_one(pk & 255, (pk >> 8) & 255, (pk >> 16) & 255, a0, qs, a1, qfx);
         }
         __builtin_amdgcn_wave_barrier();
     };
@@ -559,9 +698,9 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
             const float fxv = qw * ux * ig;   // 2-d out-of-plane current factor q w v_x
             if constexpr (!kReduce) {
                 if (valid)
-                    deposit_lane<DIM, ORDER>(jtile, jcells, jx_, jy_, lx, ly, lz, o, s, o1, jfx, jfy, jfz, fxv);
+                    deposit_one(lx, ly, lz, o, s, o1, fxv);
             } else {
-                bool frame = valid && (single || c == cf) && stays<ORDER>(o[1], s[1], o1[1]) &&
+                bool frame = PSC_FRAMES && valid && (single || c == cf) && stays<ORDER>(o[1], s[1], o1[1]) &&
                              stays<ORDER>(o[2], s[2], o1[2]);
                 if constexpr (DIM == 3) frame = frame && stays<ORDER>(o[0], s[0], o1[0]);
 
@@ -574,8 +713,7 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
                     const int nq = __popcll(cm);
                     if (nq > QS) {
                         if (cross)
-                            deposit_lane<DIM, ORDER>(jtile, jcells, jx_, jy_, lx, ly, lz, o, s, o1, jfx, jfy, jfz,
-                                                     fxv);
+                            deposit_one(lx, ly, lz, o, s, o1, fxv);
                     } else {
                         if (qn + nq > QS) {
                             drain(qn);
@@ -628,7 +766,7 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
                     }
 #pragma unroll
                     for (int a = 0; a < FL; ++a) {
-                        const float pa = gx * Ay[a], qa = gx * (1.0f / 12.0f) * DSy[a];
+                        const float pa = gx * Ay[a], qa = gx * x12 * DSy[a];
 #pragma unroll
                         for (int b = 0; b < FL; ++b)
                             acc[2 * NY2 + b * FL + a] = fmaf(pa, Az[b], fmaf(qa, DSz[b], acc[2 * NY2 + b * FL + a]));
@@ -784,7 +922,9 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
 
     // add the LDS current tile into the patch's tile in HBM
     float *gt = R.jtile + (int64_t)U.patch * 3 * jcells;
-    for (int t = threadIdx.x; t < 3 * jcells; t += NT) {
+    for (int q = threadIdx.x; q < 3 * n_jband; q += NT) {
+        const int c = q / n_jband;
+        const int t = c * jcells + jr0 * jplane + (q - c * n_jband);
         const double v = jtile[t];
         if (v != 0.0) atomicAdd(&gt[t], (float)v);
     }

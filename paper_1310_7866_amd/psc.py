@@ -33,6 +33,7 @@ EXPORTS = ["psc_init_patches", "psc_workspace_size", "psc_bind", "psc_load_parti
            "psc_check", "psc_status_string", "psc_last_error", "psc_destroy"]
 LAUNCH_GRID, LAUNCH_QUEUE, LAUNCH_PARTITION = 0, 1, 2
 RUN_ADJOINT = 1
+RUN_VB = 2
 
 
 class PscError(RuntimeError):
@@ -125,7 +126,7 @@ def partition(loads: Sequence[float], caps: Sequence[float]) -> np.ndarray:
 
 def run_desc(case, capacity: Optional[Sequence[int]] = None, flags: int = 0) -> RunDesc:
     d = RunDesc()
-    d.flags = int(flags)
+    d.flags = int(flags) | (RUN_VB if getattr(case, "deposit", "esirkepov") == "vb" else 0)
     d.dim = case.dim
     for k in range(3):
         d.gdims[k] = int(case.gdims[k])

@@ -81,6 +81,19 @@ def test_patches_narrower_than_the_current_halo_rejected():
         assert _init(d) == want, (order, patch, n)
 
 
+def test_vb_flag_rules():
+    """The Villasenor-Buneman deposit is a 1st-order option without the adjoint."""
+    d = psc.run_desc(cases.thermal2d(ny=16, nz=12, ppc=1, patch=8, order=1))
+    d.flags = psc.RUN_VB
+    assert _init(d) == 0
+    d = psc.run_desc(cases.thermal2d(ny=16, nz=12, ppc=1, patch=8, order=2))
+    d.flags = psc.RUN_VB
+    assert _init(d) == 7
+    d = psc.run_desc(cases.thermal2d(ny=16, nz=12, ppc=1, patch=8, order=1))
+    d.flags = psc.RUN_VB | psc.RUN_ADJOINT
+    assert _init(d) == 7
+
+
 def test_lds_overflow_rejected():
     c = cases.thermal2d(ny=128, nz=128, ppc=1, patch=64, order=2)
     assert _init(psc.run_desc(c)) == 3

@@ -279,3 +279,53 @@ def test_radix_sort_equals_counting_sort(kind, order):
         qa, qb = a.particles(0, s), b.particles(0, s)
         assert np.array_equal(qa["cell"], qb["cell"])
         assert np.array_equal(qa["u"], qb["u"])
+
+
+@pytest.mark.parametrize("kind", ["2d", "3d"])
+def test_vb_deposit_matches_oracle(kind):
+    """1st-order runs with the Villasenor-Buneman deposit (PSC_RUN_VB): one
+    push + deposit and three whole steps against the oracle's VB deposit, and
+    the Gauss residual stays at its initial value (charge conservation)."""
+    if kind == "2d":
+        c = _small_2d(1, seed=81, ny=12, nz=10, patch=4, ppc=40)
+    else:
+        c = _small_3d(1, seed=82, nxyz=(6, 5, 4), patch=3, ppc=30)
+    c.deposit = "vb"
+    sim = _sim(c)
+    ora = O.OracleSim(c)
+    sim.push_fields(0)
+    sim.push_particles()
+    sim.deposit_current()
+    assert sim.check() == 0
+    ora.push_b_half()
+    ora.push_particles()
+    for s, sp in enumerate(c.species):
+        dpos, du = particle_errors(c, sim.front_buffer(0, s), ora, s, float(np.std(sp.u)))
+        assert dpos <= 1e-6 and du <= 1e-5
+    _, _, J = sim.field_arrays(0)
+    err = np.abs(J.ravel() - ora.J).max()
+    print(f"vb {kind}: max |dJ| = {err:.3e}, max |J| = {np.abs(ora.J).max():.3e}")
+    assert err <= 2e-5 * np.abs(ora.J).max()
+    # the Esirkepov current differs for the same move (crossings, 2-d J_x)
+    c2 = _small_2d(1, seed=81, ny=12, nz=10, patch=4, ppc=40) if kind == "2d" else \
+        _small_3d(1, seed=82, nxyz=(6, 5, 4), patch=3, ppc=30)
+    esk = O.OracleSim(c2)
+    esk.push_b_half()
+    esk.push_particles()
+    assert np.abs(esk.J - ora.J).max() > 100 * err
+    sim2 = _sim(c)
+    ora2 = O.OracleSim(c)
+    _, g0 = sim2.diagnostics(with_gauss=True)
+    for _ in range(3):
+        sim2.step(1)
+        ora2.step(1)
+    assert sim2.check() == 0
+    for s, sp in enumerate(c.species):
+        dpos, du = particle_errors(c, sim2.particles(0, s), ora2, s, float(np.std(sp.u)))
+        assert dpos <= 1e-5 and du <= 1e-4
+    E, _, _ = sim2.field_arrays(0)
+    assert np.abs(E.ravel() - ora2.E).max() <= 1e-4 * np.abs(ora2.E).max()
+    _, g3 = sim2.diagnostics(with_gauss=True)
+    rho_scale = np.abs(ora2.rho()).max()
+    print(f"vb {kind}: Gauss drift over 3 steps {np.abs(g3 - g0).max():.3e} (rho scale {rho_scale:.3e})")
+    assert np.abs(g3 - g0).max() <= 1e-5 * rho_scale
