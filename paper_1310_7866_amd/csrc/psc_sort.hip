@@ -89,9 +89,13 @@ __device__ __forceinline__ void walk_cells(const int32_t *sb, int nw, int32_t pb
     const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
     const uint64_t cells = nw >= 64 ? ~0ull : ((1ull << nw) - 1);
     const int32_t sbl = sb[lane < nw ? lane : nw];
+    // the move codes of the next group are loaded while this one is ranked
+    int m_next = pb + lane < pe ? (int)mc[pb + lane] : -1;
     for (int32_t i0 = pb; i0 < pe; i0 += 64) {
         const int32_t i = i0 + lane;
         const bool valid = i < pe;
+        const int m_here = m_next;
+        if (i + 64 < pe) m_next = mc[i + 64];
         const int32_t il = i0 + 63 < pe ? i0 + 63 : pe - 1;
         const int qa = 63 - __clzll(__ballot(sbl <= i0) & cells);   // sb[0] = pb <= i0
         const int qb = 63 - __clzll(__ballot(sbl <= il) & cells);
@@ -115,7 +119,7 @@ __device__ __forceinline__ void walk_cells(const int32_t *sb, int nw, int32_t pb
         }
         int m = -1;
         if (valid) {
-            m = mc[i];
+            m = m_here;
             if (m >= M) { flags |= PSC_DEV_MOVE; m = CENTER; }
         } else {
             q = -1;
