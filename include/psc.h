@@ -208,11 +208,13 @@ psc_status psc_step(psc_ctx *ctx, int nsteps, int use_graph, void *stream);
  * workers: persistent workgroups (0 = compute units x workgroups that fit
  * in one unit's LDS).  threads: workgroup size, 256, 384 or 512 (0 keeps;
  * the LDS tiles of a work item are shared by all its waves; PSC_ERR_LDS if
- * the tiles and per-wave queues exceed 160 KiB).  run: 1..64 consecutive
- * particles that a lane pushes in sequence, accumulating the current of
- * those in its first particle's cell before the wave-level sums (0 keeps;
- * default 1: one particle per lane, consecutive particles on consecutive
- * lanes).  Drops recorded step graphs.  May synchronize. */
+ * the tiles and per-wave queues exceed 160 KiB).  run: consecutive
+ * particles a lane pushes in sequence, 1 or 2 (0 keeps; default 1: one
+ * particle per lane, consecutive particles on consecutive lanes; 2: a lane
+ * accumulates the current of both when they share a cell, halving the
+ * wave-level sums, and the outputs are exchanged across the wave so that
+ * the stores stay coalesced).  Drops recorded step graphs.  May
+ * synchronize. */
 #define PSC_LAUNCH_GRID 0
 #define PSC_LAUNCH_QUEUE 1
 #define PSC_LAUNCH_PARTITION 2

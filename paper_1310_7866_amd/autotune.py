@@ -74,7 +74,7 @@ def time_push(sim, steps: int = 3) -> float:
 
 
 THREADS = (256, 384, 512)
-RUNS = (1, 2, 4, 8)
+RUNS = (1, 2)
 
 
 def tune(sim, cache: Optional[str] = DEFAULT_CACHE, steps: int = 2,

@@ -849,7 +849,7 @@ psc_status psc_balance(psc_ctx *ctx, double cell_cost, void *stream) {
 
 psc_status psc_set_launch(psc_ctx *ctx, int mode, int chunk, int workers, int threads, int run, void *stream) {
     if (!ctx || !ctx->bound || mode < 0 || mode > 2 || chunk < 0 || workers < 0 || workers > ctx->max_workers ||
-        (threads != 0 && threads != 256 && threads != 384 && threads != 512) || run < 0 || run > 64)
+        (threads != 0 && threads != 256 && threads != 384 && threads != 512) || run < 0 || run > 2)
         return PSC_ERR_INVALID;
     if (ctx->push_lds(threads ? threads : ctx->pm.threads, run ? run : ctx->pm.run) > kMaxLds) return PSC_ERR_LDS;
     if (threads) ctx->pm.threads = threads;

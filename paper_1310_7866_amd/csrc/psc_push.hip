@@ -513,11 +513,13 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
     }
     __syncthreads();
 
-    // without runs (K = 1, a separate instantiation: its registers are not
-    // sized for the run accumulators) lane t of a round takes particle
-    // beg + r0 + t, so loads and stores are coalesced
+    // K = 1 (its own instantiation): lane t of a round takes particle
+    // beg + r0 + t, so loads and stores are coalesced.  K = 2: lane t takes
+    // beg + 2 (r0 + t) and the next one; its outputs are handed across the
+    // wave before the stores so that consecutive lanes store consecutive slots.
     constexpr bool single = !RUNS;
-    if constexpr (single) K = 1;
+    constexpr int KS = RUNS ? 2 : 1;
+    K = KS;
     const int32_t nruns = (end - beg + K - 1) / K;   // lanes' strips of K particles
     const int in = front, outb = 1 - front;
     const gptr<const int32_t> cell_in = to_global<const int32_t>(S.cell[in]);
@@ -596,6 +598,11 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
         float acc[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] = 0.0f;
+        // K = 2: the outputs of the lane's two particles, stored after both
+        int32_t pk0 = 0, pk1 = 0, pi0 = 0, pi1 = 0;
+        int pc0 = 0, pc1 = 0;
+        float po0[3] = {0.0f, 0.0f, 0.0f}, po1[3] = {0.0f, 0.0f, 0.0f};
+        float pu0[3] = {0.0f, 0.0f, 0.0f}, pu1[3] = {0.0f, 0.0f, 0.0f};
 
         for (int j = 0; j < K; ++j) {
             const bool valid = j < len;
@@ -826,21 +833,72 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
                     const int gx = DIM == 3 ? wrap(ox + nlx, R.n[0]) : 0;
                     nkey = (int32_t)encode_key(R, gx, wrap(oy + nly, R.n[1]), wrap(oz + nlz, R.n[2]));
                 }
-                cell_out[slot] = nkey;
-                if constexpr (DIM == 3) {
-                    off_out[slot] = o1[0];
-                    off_out[cap + slot] = o1[1];
-                    off_out[2 * cap + slot] = o1[2];
-                    mc[slot] = (uint8_t)((s[0] + 1) + 3 * (s[1] + 1) + 9 * (s[2] + 1));
+                const int code = DIM == 3 ? (s[0] + 1) + 3 * (s[1] + 1) + 9 * (s[2] + 1) : (s[1] + 1) + 3 * (s[2] + 1);
+                if constexpr (single) {
+                    cell_out[slot] = nkey;
+                    if constexpr (DIM == 3) {
+                        off_out[slot] = o1[0];
+                        off_out[cap + slot] = o1[1];
+                        off_out[2 * cap + slot] = o1[2];
+                    } else {
+                        off_out[slot] = o1[1];
+                        off_out[cap + slot] = o1[2];
+                    }
+                    mc[slot] = (uint8_t)code;
+                    u_out[slot] = ux;
+                    u_out[cap + slot] = uy;
+                    u_out[2 * cap + slot] = uz;
+                    if (id_out) id_out[slot] = idv;
+                } else if (j == 0) {
+                    pk0 = nkey; po0[0] = o1[0]; po0[1] = o1[1]; po0[2] = o1[2];
+                    pu0[0] = ux; pu0[1] = uy; pu0[2] = uz; pc0 = code; pi0 = idv;
                 } else {
-                    off_out[slot] = o1[1];
-                    off_out[cap + slot] = o1[2];
-                    mc[slot] = (uint8_t)((s[1] + 1) + 3 * (s[2] + 1));
+                    pk1 = nkey; po1[0] = o1[0]; po1[1] = o1[1]; po1[2] = o1[2];
+                    pu1[0] = ux; pu1[1] = uy; pu1[2] = uz; pc1 = code; pi1 = idv;
                 }
-                u_out[slot] = ux;
-                u_out[cap + slot] = uy;
-                u_out[2 * cap + slot] = uz;
-                if (id_out) id_out[slot] = idv;
+            }
+        }
+        if constexpr (!single) {
+            // the wave's lanes hold the 128 consecutive slots from wbase (lane
+            // l: wbase + 2l and wbase + 2l + 1); in two passes lane l stores
+            // slot wbase + 64 pass + l, taken from lane 32 pass + l/2
+            const int32_t wbase = beg + 2 * (r0 + (int32_t)(threadIdx.x & ~63));
+            const bool odd = lane & 1;
+#pragma unroll
+            for (int pass = 0; pass < 2; ++pass) {
+                const int src = 32 * pass + (lane >> 1);
+                const int32_t slot = wbase + 64 * pass + lane;
+                const bool ok = slot < end;
+                auto pick = [&](auto a, auto b) {
+                    const auto x = __shfl(a, src, 64), y = __shfl(b, src, 64);
+                    return odd ? y : x;
+                };
+                const int32_t k = pick(pk0, pk1);
+                const int code = pick(pc0, pc1);
+                float o[3], u[3];
+#pragma unroll
+                for (int d = (DIM == 3 ? 0 : 1); d < 3; ++d) o[d] = pick(po0[d], po1[d]);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) u[d] = pick(pu0[d], pu1[d]);
+                if (ok) {
+                    cell_out[slot] = k;
+                    if constexpr (DIM == 3) {
+                        off_out[slot] = o[0];
+                        off_out[cap + slot] = o[1];
+                        off_out[2 * cap + slot] = o[2];
+                    } else {
+                        off_out[slot] = o[1];
+                        off_out[cap + slot] = o[2];
+                    }
+                    mc[slot] = (uint8_t)code;
+                    u_out[slot] = u[0];
+                    u_out[cap + slot] = u[1];
+                    u_out[2 * cap + slot] = u[2];
+                }
+                if (id_out) {
+                    const int32_t iv = pick(pi0, pi1);
+                    if (ok) id_out[slot] = iv;
+                }
             }
         }
 

@@ -209,7 +209,8 @@ def test_dense_cells_deposit(kind, order):
 # that pushes several consecutive particles accumulates the current of those
 # in its first particle's cell and queues the rest, so every shape must give
 # the same particles and, up to summation order, the same current.
-SHAPES = [(0, 256, 1, 512), (1, 512, 2, 1024), (1, 384, 4, 256), (2, 512, 8, 2048), (1, 512, 64, 4096)]
+SHAPES = [(0, 256, 1, 512), (1, 512, 2, 1024), (1, 384, 2, 256), (2, 512, 2, 2048), (1, 512, 1, 4096),
+          (2, 256, 2, 333)]
 
 
 @pytest.mark.parametrize("kind,order", CASES)
