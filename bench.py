@@ -506,18 +506,24 @@ def main():
 
 
 def push_source_hash() -> str:
-    """Hash of the sources the particle kernel is compiled from: its own file,
+    """Hash of the code the particle kernel is compiled from: its own file,
     the device helpers, and the data structures of the internal header (the
-    launcher declarations after them do not change the kernel)."""
+    launcher declarations after them do not change the kernel), with
+    comments and white space removed so that editing a comment keeps it."""
     import hashlib
-    h = hashlib.sha256()
+    import re
     csrc = os.path.join(ROOT, "paper_1310_7866_amd", "csrc")
+    texts = []
     for name in ("psc_push.hip", "psc_device.h"):
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(f.read())
-    with open(os.path.join(csrc, "psc_internal.h"), "rb") as f:
-        text = f.read()
-    h.update(text.split(b"// launchers (defined in the .hip files)")[0])
+        with open(os.path.join(csrc, name)) as f:
+            texts.append(f.read())
+    with open(os.path.join(csrc, "psc_internal.h")) as f:
+        texts.append(f.read().split("// launchers (defined in the .hip files)")[0])
+    h = hashlib.sha256()
+    for text in texts:
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -195,9 +195,9 @@ psc_status psc_sort_radix(psc_ctx *ctx, void *stream);
 psc_status psc_step(psc_ctx *ctx, int nsteps, int use_graph, void *stream);
 
 /* Launch shape of the particle kernel (batching and autotuning).  psc_bind
- * sets PSC_LAUNCH_QUEUE with 512 threads and one particle per lane (the
- * shape the autotuner chose for every workload measured on gfx950), or the
- * largest workgroup whose LDS fits, or PSC_LAUNCH_GRID with 256 threads.
+ * sets PSC_LAUNCH_QUEUE with 512 threads (or the largest workgroup whose LDS
+ * fits), two particles per lane for 2-d order-2 runs and one otherwise (the
+ * shapes the autotuner chose on gfx950).
  * mode: PSC_LAUNCH_GRID      one workgroup per work item;
  *       PSC_LAUNCH_QUEUE     persistent workgroups pulling work items from
  *                            eight queues (one per XCD, with stealing);

@@ -499,10 +499,13 @@ psc_status psc_bind(psc_ctx *ctx, const psc_run_bufs *bufs, int n_runs, void *wo
     ctx->bound = true;
     ctx->stepped = false;
     ctx->front = ctx->cs_sel = ctx->perm_pending = ctx->mc_valid = 0;
-    // default launch: persistent queues with the largest workgroup that fits
+    // default launch: persistent queues with the largest workgroup that fits;
+    // two particles per lane for 2-d order-2 runs, one otherwise (the
+    // autotuner's choices on gfx950)
+    const int run = ctx->dim == 2 && ctx->order == 2 ? 2 : 1;
     for (int threads : {512, 384, 256}) {
-        if (ctx->push_lds(threads, 1) > kMaxLds) continue;
-        psc_status st = psc_set_launch(ctx, PSC_LAUNCH_QUEUE, 0, 0, threads, 1, stream);
+        if (ctx->push_lds(threads, run) > kMaxLds) continue;
+        psc_status st = psc_set_launch(ctx, PSC_LAUNCH_QUEUE, 0, 0, threads, run, stream);
         if (st != PSC_ERR_LDS) return st;
     }
     return PSC_OK;

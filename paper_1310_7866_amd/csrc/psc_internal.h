@@ -207,7 +207,7 @@ struct Launch {
 struct PushMode {
     int mode = 0;
     int threads = 256;         // workgroup size: 256, 384 or 512
-    int run = 1;               // particles of one cell per lane and round (1: one, coalesced)
+    int run = 1;               // consecutive particles per lane and round (1 or 2)
     int workers = 0;           // persistent workgroups (modes 1, 2)
     int32_t *queue = nullptr;  // 8 counters (mode 1; reset every launch)
     const int32_t *part = nullptr;  // workers + 1 unit boundaries (mode 2)

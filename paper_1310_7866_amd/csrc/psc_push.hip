@@ -19,10 +19,10 @@ namespace psc {
 //   PSC_SCAN_WIDTH   lanes per group of the segmented current sums (16/32/64)
 //   PSC_QUEUE_SLOTS  per-wave queue of particles whose support changes nodes
 #ifndef PSC_SCAN_WIDTH
-#define PSC_SCAN_WIDTH 64
+#define PSC_SCAN_WIDTH 32
 #endif
 #ifndef PSC_QUEUE_SLOTS
-#define PSC_QUEUE_SLOTS 16
+#define PSC_QUEUE_SLOTS 64
 #endif
 //   PSC_PACK_TAILS   segments per wave whose sums are staged and added with
 //                    full-lane atomics (more fall back to per-tail atomics)
@@ -378,17 +378,18 @@ __device__ __forceinline__ int frame_offset(int j, int jx_, int jy_, int jcells)
 // may start the next item on the same LDS.
 //
 // The chunk's particles are sorted by cell.  Lane g of a round pushes the K
-// consecutive particles beg + g K + j (j < K) one after another (K = 1 is
-// its own instantiation, with coalesced loads and stores), adding the
-// Esirkepov current of those whose interpolation support keeps its nodes
-// and whose cell is the one of the lane's first particle into a per-cell
-// frame held in registers.  At the end of a round the wave forms segmented
-// sums of the frames over lanes of equal cell (consecutive, since the
-// particles are sorted) and the last lane of each segment adds them to the
-// LDS current tile: one scan and one set of LDS atomics per K particles of a
-// lane.  The other particles (support changes nodes, or a later cell than
-// the lane's frame) wait in a per-wave queue and are deposited in batches
-// with per-lane LDS atomics.
+// consecutive particles beg + g K + j (j < K, K = 1 or 2, one instantiation
+// each) one after another, adding the Esirkepov current of those whose
+// interpolation support keeps its nodes and whose cell is the one of the
+// lane's first particle into a per-cell frame held in registers.  At the end
+// of a round the wave forms segmented sums of the frames over lanes of equal
+// cell (consecutive, since the particles are sorted) and the last lane of
+// each segment adds them to the LDS current tile: one scan and one set of
+// LDS atomics per K particles of a lane.  The other particles (support
+// changes nodes, or a later cell than the lane's frame) wait in a per-wave
+// queue and are deposited in batches with per-lane LDS atomics.  With K = 2
+// the outputs are exchanged across the wave before the stores so that
+// consecutive lanes store consecutive slots.
 template <int DIM, int ORDER, int NT, bool RUNS>
 __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const Unit *__restrict__ units,
                                           const int32_t *__restrict__ item_start, int lo, int item, int chunk,

@@ -147,6 +147,62 @@ __device__ __forceinline__ void walk_cells(const int32_t *sb, int nw, int32_t pb
     }
 }
 
+// Patch coordinate, local coordinate and patch extent of each cell along
+// one dimension, and of its neighbours one cell down (index 0) and up (2):
+// a move of at most one cell leaves the patch only at its faces, so the
+// neighbour's patch is the same or the adjacent one (periodic) and needs
+// no division.
+struct Axis {
+    int pc[3], l[3], ext[3];
+};
+
+__device__ __forceinline__ Axis axis_neighbours(int P, int n, int np, int pc, int l) {
+    Axis a;
+    const int ext = imin(P, n - pc * P);
+    const int pdn = pc == 0 ? np - 1 : pc - 1, pup = pc == np - 1 ? 0 : pc + 1;
+    const int edn = imin(P, n - pdn * P);
+    a.pc[1] = pc;
+    a.l[1] = l;
+    a.ext[1] = ext;
+    const bool out_dn = l == 0;
+    a.pc[0] = out_dn ? pdn : pc;
+    a.l[0] = out_dn ? edn - 1 : l - 1;
+    a.ext[0] = out_dn ? edn : ext;
+    const bool out_up = l == ext - 1;
+    a.pc[2] = out_up ? pup : pc;
+    a.l[2] = out_up ? 0 : l + 1;
+    a.ext[2] = out_up ? imin(P, n - pup * P) : ext;
+    return a;
+}
+
+// decode_key in 32-bit arithmetic (keys and every product below are less
+// than the run's cell count, which is below 2^31)
+__device__ __forceinline__ void decode_key32(const RunDev &r, uint32_t key, int pc[3], int l[3]) {
+    const uint32_t slab = (uint32_t)r.P[2] * r.n[1] * r.n[0];
+    pc[2] = (int)(key / slab);
+    uint32_t rem = key - (uint32_t)pc[2] * slab;
+    const uint32_t hz = (uint32_t)imin(r.P[2], r.n[2] - pc[2] * r.P[2]);
+    const uint32_t row = (uint32_t)r.P[1] * hz * r.n[0];
+    pc[1] = (int)(rem / row);
+    rem -= (uint32_t)pc[1] * row;
+    const uint32_t hy = (uint32_t)imin(r.P[1], r.n[1] - pc[1] * r.P[1]);
+    const uint32_t pcells = (uint32_t)r.P[0] * hy * hz;
+    pc[0] = (int)(rem / pcells);
+    rem -= (uint32_t)pc[0] * pcells;
+    const uint32_t hx = (uint32_t)imin(r.P[0], r.n[0] - pc[0] * r.P[0]);
+    const uint32_t q = rem / hx;
+    l[0] = (int)(rem - q * hx);
+    l[1] = (int)(q % hy);
+    l[2] = (int)(q / hy);
+}
+
+// key of the cell at (patch, local) coordinates, extents given
+__device__ __forceinline__ uint32_t key_of(const RunDev &r, int p0, int p1, int p2, int l0, int l1, int l2, int e0,
+                                           int e1, int e2) {
+    return (uint32_t)p2 * r.P[2] * r.n[1] * r.n[0] + (uint32_t)p1 * r.P[1] * e2 * r.n[0] +
+           (uint32_t)p0 * r.P[0] * e1 * e2 + (uint32_t)(l0 + e0 * (l1 + e1 * l2));
+}
+
 // per new cell: order the source cells by key and assign arrival prefixes
 template <int DIM>
 __global__ void __launch_bounds__(kSortBlock) k_sort_prefix(const RunDev *__restrict__ runs,
@@ -163,8 +219,11 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_prefix(const RunDev *__rest
     const SpeciesDev &S = R.sp[seg_sp[sg]];
     const int64_t n = c - seg_base[sg];
     const int64_t nc = R.ncell;
-    int g[3];
-    decode_key(R, n, g);
+    int pc[3], lc[3];
+    decode_key32(R, (uint32_t)n, pc, lc);
+    Axis ax[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ax[d] = axis_neighbours(R.P[d], R.n[d], R.np[d], pc[d], lc[d]);
     int32_t ks[M];
     int32_t cn[M];
     // arrivals into n from each source (the particle kernel counts the
@@ -175,8 +234,10 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_prefix(const RunDev *__rest
     for (int m = 0; m < M; ++m) {
         int d[3];
         move_delta(DIM, m, d);
-        const int sx = DIM == 3 ? wrap(g[0] - d[0], R.n[0]) : 0;
-        ks[m] = (int32_t)encode_key(R, sx, wrap(g[1] - d[1], R.n[1]), wrap(g[2] - d[2], R.n[2]));
+        // source cell: one step against the move (index 1 - d per axis)
+        const int a0 = DIM == 3 ? 1 - d[0] : 1, a1 = 1 - d[1], a2 = 1 - d[2];
+        ks[m] = (int32_t)key_of(R, ax[0].pc[a0], ax[1].pc[a1], ax[2].pc[a2], ax[0].l[a0], ax[1].l[a1], ax[2].l[a2],
+                                ax[0].ext[a0], ax[1].ext[a1], ax[2].ext[a2]);
         if (m != CENTER) {
             cn[m] = S.cnt[m * nc + ks[m]];
             stay -= S.cnt[m * nc + n];   // leaving n with move m
