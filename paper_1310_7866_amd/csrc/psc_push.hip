@@ -599,6 +599,76 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
         float acc[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] = 0.0f;
+        // inputs of the frames of the lane's particles (start and end offsets,
+        // out-of-plane factor, whether the particle goes into the frame)
+        float fa0[3] = {0.0f, 0.0f, 0.0f}, fb0[3] = {0.0f, 0.0f, 0.0f}, fa1[3] = {0.0f, 0.0f, 0.0f},
+              fb1[3] = {0.0f, 0.0f, 0.0f};
+        float fx0 = 0.0f, fx1 = 0.0f;
+        bool fr0 = false, fr1 = false;
+        auto add_frame = [&](const float *o, const float *o1, float fxv, bool frame) {
+            float S0y[FL], S1y[FL], S0z[FL], S1z[FL];
+            frame_weights<ORDER>(o[1], o1[1], S0y, S1y);
+            frame_weights<ORDER>(o[2], o1[2], S0z, S1z);
+            float DSy[FL], DSz[FL], Ay[FL], Az[FL], Cy[FL], Cz[FL];
+#pragma unroll
+            for (int r = 0; r < FL; ++r) {
+                DSy[r] = S1y[r] - S0y[r];
+                DSz[r] = S1z[r] - S0z[r];
+                Ay[r] = fmaf(0.5f, DSy[r], S0y[r]);
+                Az[r] = fmaf(0.5f, DSz[r], S0z[r]);
+                Cy[r] = r == 0 ? DSy[0] : Cy[r - 1] + DSy[r];
+                Cz[r] = r == 0 ? DSz[0] : Cz[r - 1] + DSz[r];
+            }
+            const float gy = frame ? jfy : 0.0f, gz = frame ? jfz : 0.0f;
+            if constexpr (DIM == 2) {
+                const float gx = frame ? fxv : 0.0f;
+#pragma unroll
+                for (int a = 0; a < FL - 1; ++a) {
+                    const float cy = gy * Cy[a], cz = gz * Cz[a];
+#pragma unroll
+                    for (int b = 0; b < FL; ++b) {
+                        acc[b * (FL - 1) + a] = fmaf(cy, Az[b], acc[b * (FL - 1) + a]);
+                        acc[NY2 + a * FL + b] = fmaf(Ay[b], cz, acc[NY2 + a * FL + b]);
+                    }
+                }
+#pragma unroll
+                for (int a = 0; a < FL; ++a) {
+                    const float pa = gx * Ay[a], qa = gx * x12 * DSy[a];
+#pragma unroll
+                    for (int b = 0; b < FL; ++b)
+                        acc[2 * NY2 + b * FL + a] = fmaf(pa, Az[b], fmaf(qa, DSz[b], acc[2 * NY2 + b * FL + a]));
+                }
+            } else {
+                const float gx = frame ? jfx : 0.0f;
+                float S0x[FL], S1x[FL];
+                frame_weights<ORDER>(o[0], o1[0], S0x, S1x);
+                float DSx[FL], Ax[FL], Cx[FL];
+#pragma unroll
+                for (int r = 0; r < FL; ++r) {
+                    DSx[r] = S1x[r] - S0x[r];
+                    Ax[r] = fmaf(0.5f, DSx[r], S0x[r]);
+                    Cx[r] = r == 0 ? DSx[0] : Cx[r - 1] + DSx[r];
+                }
+#pragma unroll
+                for (int c2 = 0; c2 < FL; ++c2)
+#pragma unroll
+                    for (int b = 0; b < FL; ++b) {
+                        const float wyz = fmaf(DSy[b] * DSz[c2], 1.0f / 12.0f, Ay[b] * Az[c2]);
+                        const float wxz = fmaf(DSx[b] * DSz[c2], 1.0f / 12.0f, Ax[b] * Az[c2]);
+                        const float wxy = fmaf(DSx[b] * DSy[c2], 1.0f / 12.0f, Ax[b] * Ay[c2]);
+#pragma unroll
+                        for (int a = 0; a < FL - 1; ++a) {
+                            // Jx(a; b, c2), Jy(b; a, c2), Jz(b, c2; a) in the index order of the flush
+                            acc[(c2 * FL + b) * (FL - 1) + a] =
+                                fmaf(gx * Cx[a], wyz, acc[(c2 * FL + b) * (FL - 1) + a]);
+                            acc[NC3 + (c2 * (FL - 1) + a) * FL + b] =
+                                fmaf(gy * Cy[a], wxz, acc[NC3 + (c2 * (FL - 1) + a) * FL + b]);
+                            acc[2 * NC3 + (a * FL + c2) * FL + b] =
+                                fmaf(gz * Cz[a], wxy, acc[2 * NC3 + (a * FL + c2) * FL + b]);
+                        }
+                    }
+            }
+        };
         // K = 2: the outputs of the lane's two particles, stored after both
         int32_t pk0 = 0, pk1 = 0, pi0 = 0, pi1 = 0;
         int pc0 = 0, pc1 = 0;
@@ -746,68 +816,17 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
                     }
                 }
 
-                // the rest: into this lane's frame of its cell
-                float S0y[FL], S1y[FL], S0z[FL], S1z[FL];
-                frame_weights<ORDER>(o[1], o1[1], S0y, S1y);
-                frame_weights<ORDER>(o[2], o1[2], S0z, S1z);
-                float DSy[FL], DSz[FL], Ay[FL], Az[FL], Cy[FL], Cz[FL];
-#pragma unroll
-                for (int r = 0; r < FL; ++r) {
-                    DSy[r] = S1y[r] - S0y[r];
-                    DSz[r] = S1z[r] - S0z[r];
-                    Ay[r] = fmaf(0.5f, DSy[r], S0y[r]);
-                    Az[r] = fmaf(0.5f, DSz[r], S0z[r]);
-                    Cy[r] = r == 0 ? DSy[0] : Cy[r - 1] + DSy[r];
-                    Cz[r] = r == 0 ? DSz[0] : Cz[r - 1] + DSz[r];
-                }
-                const float gy = frame ? jfy : 0.0f, gz = frame ? jfz : 0.0f;
-                if constexpr (DIM == 2) {
-                    const float gx = frame ? fxv : 0.0f;
-#pragma unroll
-                    for (int a = 0; a < FL - 1; ++a) {
-                        const float cy = gy * Cy[a], cz = gz * Cz[a];
-#pragma unroll
-                        for (int b = 0; b < FL; ++b) {
-                            acc[b * (FL - 1) + a] = fmaf(cy, Az[b], acc[b * (FL - 1) + a]);
-                            acc[NY2 + a * FL + b] = fmaf(Ay[b], cz, acc[NY2 + a * FL + b]);
-                        }
-                    }
-#pragma unroll
-                    for (int a = 0; a < FL; ++a) {
-                        const float pa = gx * Ay[a], qa = gx * x12 * DSy[a];
-#pragma unroll
-                        for (int b = 0; b < FL; ++b)
-                            acc[2 * NY2 + b * FL + a] = fmaf(pa, Az[b], fmaf(qa, DSz[b], acc[2 * NY2 + b * FL + a]));
-                    }
+                // the rest: into this lane's frame of its cell, built after
+                // the lane's particles are done (keeps the frame registers
+                // free while a second particle is pushed)
+                if (j == 0) {
+                    fa0[0] = o[0]; fa0[1] = o[1]; fa0[2] = o[2];
+                    fb0[0] = o1[0]; fb0[1] = o1[1]; fb0[2] = o1[2];
+                    fx0 = fxv; fr0 = frame;
                 } else {
-                    const float gx = frame ? jfx : 0.0f;
-                    float S0x[FL], S1x[FL];
-                    frame_weights<ORDER>(o[0], o1[0], S0x, S1x);
-                    float DSx[FL], Ax[FL], Cx[FL];
-#pragma unroll
-                    for (int r = 0; r < FL; ++r) {
-                        DSx[r] = S1x[r] - S0x[r];
-                        Ax[r] = fmaf(0.5f, DSx[r], S0x[r]);
-                        Cx[r] = r == 0 ? DSx[0] : Cx[r - 1] + DSx[r];
-                    }
-#pragma unroll
-                    for (int c2 = 0; c2 < FL; ++c2)
-#pragma unroll
-                        for (int b = 0; b < FL; ++b) {
-                            const float wyz = fmaf(DSy[b] * DSz[c2], 1.0f / 12.0f, Ay[b] * Az[c2]);
-                            const float wxz = fmaf(DSx[b] * DSz[c2], 1.0f / 12.0f, Ax[b] * Az[c2]);
-                            const float wxy = fmaf(DSx[b] * DSy[c2], 1.0f / 12.0f, Ax[b] * Ay[c2]);
-#pragma unroll
-                            for (int a = 0; a < FL - 1; ++a) {
-                                // Jx(a; b, c2), Jy(b; a, c2), Jz(b, c2; a) in the index order of the flush
-                                acc[(c2 * FL + b) * (FL - 1) + a] =
-                                    fmaf(gx * Cx[a], wyz, acc[(c2 * FL + b) * (FL - 1) + a]);
-                                acc[NC3 + (c2 * (FL - 1) + a) * FL + b] =
-                                    fmaf(gy * Cy[a], wxz, acc[NC3 + (c2 * (FL - 1) + a) * FL + b]);
-                                acc[2 * NC3 + (a * FL + c2) * FL + b] =
-                                    fmaf(gz * Cz[a], wxy, acc[2 * NC3 + (a * FL + c2) * FL + b]);
-                            }
-                        }
+                    fa1[0] = o[0]; fa1[1] = o[1]; fa1[2] = o[2];
+                    fb1[0] = o1[0]; fb1[1] = o1[1]; fb1[2] = o1[2];
+                    fx1 = fxv; fr1 = frame;
                 }
             }
 
@@ -905,6 +924,8 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
 
         // ---- the round's frames: segmented sums over lanes of one cell ------
         if constexpr (kReduce) {
+            add_frame(fa0, fb0, fx0, fr0);
+            if constexpr (!single) add_frame(fa1, fb1, fx1, fr1);
             const RowScan rs = row_scan_setup<SW>(cf);
             row_scan<SW>(acc, rs);
             const bool put = rs.tail && len > 0;
