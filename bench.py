@@ -366,8 +366,8 @@ def main():
                          "traffic for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(every GPU box here has one GPU); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the particle path has no multi-GPU code "
+              "(its sharding is a design, not an implementation); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -28,11 +28,10 @@
  *   - a stable sort of particles by a patch-major cell key (sec. "Sorting
  *     and Communication").
  *
- * Conventions (readings where the paper fixes no units; see the design doc of the
- * repository): c = eps0 = 1; dE/dt = curl B - J; dB/dt = -curl E;
- * du/dt = (q/m)(E + u x B / gamma); positions are absolute, in cell units
- * (xi = x / dx); a 2-d grid is the (y, z) plane with n[0] == 1 and no x
- * derivatives.  Field arrays are component-major, index i + n0*(j + n1*k).
+ * Conventions (readings where the paper fixes no units): c = eps0 = 1;
+ * dE/dt = curl B - J; dB/dt = -curl E; du/dt = (q/m)(E + u x B / gamma);
+ * positions are absolute, in cell units (xi = x / dx); a 2-d grid is the
+ * (y, z) plane with n[0] == 1 and no x derivatives.  Field arrays are component-major, index i + n0*(j + n1*k).
  *
  * Parity status: every routine is pinned by a closed form, an identity or
  * brute force in the CPU tests, except the out-of-plane current J_x of the
