@@ -182,7 +182,7 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
         double ncell = ok ? (double)d.gdims[0] * d.gdims[1] * d.gdims[2] : 0.0;
         if (ok && ncell >= 2147483647.0) ok = false;
         for (int s = 0; ok && s < d.n_species; ++s)
-            ok = d.m[s] > 0.0 && d.capacity[s] >= 0 && d.capacity[s] < 2147483647LL;
+            ok = d.m[s] > 0.0 && d.capacity[s] >= 0 && d.capacity[s] <= kMaxCapacity;
         if (!ok) {
             std::snprintf(msg, sizeof msg, "run %d: invalid descriptor", r);
             psc_status s = fail(ctx, PSC_ERR_INVALID, msg);
@@ -255,6 +255,12 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
             R.jt[k] = active ? d.patch[k] + cur_lo(d.order) + cur_hi(d.order) : 1;
         }
         R.n_patches = R.np[0] * R.np[1] * R.np[2];
+        R.fold_direct = 1;
+        for (int k = (d.dim == 3 ? 0 : 1); k < 3; ++k) {
+            const int last = d.gdims[k] - (R.np[k] - 1) * d.patch[k];
+            const int halo = imax(cur_lo(d.order), cur_hi(d.order));
+            if (d.patch[k] < halo || last < halo) R.fold_direct = 0;
+        }
         R.n_species = d.n_species;
         R.ncell = (int64_t)d.gdims[0] * d.gdims[1] * d.gdims[2];
         R.cell_base = ctx->total_cells;

@@ -19,6 +19,18 @@ __device__ __forceinline__ int find_run(const int64_t *base, int n_runs, int64_t
     return lo;
 }
 
+// grid coordinates of cell idx of a run (32-bit: a run has fewer than 2^31
+// cells; a 2-d run has n[0] == 1)
+__device__ __forceinline__ void grid_coords(const RunDev &R, int64_t idx, int g[3]) {
+    const uint32_t id = (uint32_t)idx;
+    const uint32_t nx = (uint32_t)R.n[0], ny = (uint32_t)R.n[1];
+    const uint32_t q = R.dim == 3 ? id / nx : id;
+    g[0] = (int)(id - q * nx);
+    const uint32_t k = q / ny;
+    g[1] = (int)(q - k * ny);
+    g[2] = (int)k;
+}
+
 // B <- B - (dt/2) curl^+ E (op 0) or E <- E + dt (curl^- B - J) (op 1)
 __global__ void __launch_bounds__(256) k_fields(const RunDev *__restrict__ runs, int n_runs,
                                                 const int64_t *__restrict__ run_base, int64_t total, int op) {
@@ -28,9 +40,9 @@ __global__ void __launch_bounds__(256) k_fields(const RunDev *__restrict__ runs,
     const RunDev &R = runs[r];
     const int64_t idx = c - R.cell_base;
     const int nx = R.n[0], ny = R.n[1], nz = R.n[2];
-    const int i = (int)(idx % nx);
-    const int j = (int)((idx / nx) % ny);
-    const int k = (int)(idx / ((int64_t)nx * ny));
+    int g[3];
+    grid_coords(R, idx, g);
+    const int i = g[0], j = g[1], k = g[2];
     const int64_t nc = R.ncell;
     const bool three = R.dim == 3;
     const float ix = three ? R.inv_dx[0] : 0.0f, iy = R.inv_dx[1], iz = R.inv_dx[2];
@@ -83,10 +95,60 @@ __global__ void __launch_bounds__(256) k_fold(const RunDev *__restrict__ runs, i
     const RunDev &R = runs[r];
     const int64_t idx = c - R.cell_base;
     int g[3];
-    g[0] = (int)(idx % R.n[0]);
-    g[1] = (int)((idx / R.n[0]) % R.n[1]);
-    g[2] = (int)(idx / ((int64_t)R.n[0] * R.n[1]));
+    grid_coords(R, idx, g);
     const int lo = cur_lo(R.order), hi = cur_hi(R.order);
+    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+    const int64_t jc = R.jtile_cells;
+    const int64_t nc = R.ncell;
+    if (R.fold_direct) {
+        // Per dimension: the patch below (whose upper halo reaches this cell
+        // when l < hi), the own patch, the patch above (lower halo, when
+        // l >= ext - lo), in that order, with the tile-local coordinate of
+        // the cell in each.  With 1 or 2 patches along a dimension these are
+        // different aliases within the same tile.
+        int pcs[3][3], ls[3][3], nd[3];
+        for (int d = 0; d < 3; ++d) {
+            if (R.dim == 2 && d == 0) {
+                pcs[0][0] = 0;
+                ls[0][0] = -lo;   // tile x index 0
+                nd[0] = 1;
+                continue;
+            }
+            const int pc = g[d] / R.P[d];
+            const int l = g[d] - pc * R.P[d];
+            const int ext = imin(R.P[d], R.n[d] - pc * R.P[d]);
+            int k = 0;
+            if (l < hi) {
+                const int pdn = pc == 0 ? R.np[d] - 1 : pc - 1;
+                pcs[d][k] = pdn;
+                ls[d][k++] = l + imin(R.P[d], R.n[d] - pdn * R.P[d]);
+            }
+            pcs[d][k] = pc;
+            ls[d][k++] = l;
+            if (l >= ext - lo) {
+                pcs[d][k] = pc == R.np[d] - 1 ? 0 : pc + 1;
+                ls[d][k++] = l - ext;
+            }
+            nd[d] = k;
+        }
+        for (int z = 0; z < nd[2]; ++z)
+            for (int y = 0; y < nd[1]; ++y)
+                for (int x = 0; x < nd[0]; ++x) {
+                    const int p = pcs[0][x] + R.np[0] * (pcs[1][y] + R.np[1] * pcs[2][z]);
+                    float *tile = R.jtile + (int64_t)p * 3 * jc;
+                    const int64_t t = (ls[0][x] + lo) + (int64_t)R.jt[0] * ((ls[1][y] + lo) + (int64_t)R.jt[1] * (ls[2][z] + lo));
+                    sx += tile[t];
+                    sy += tile[jc + t];
+                    sz += tile[2 * jc + t];
+                    tile[t] = 0.0f;
+                    tile[jc + t] = 0.0f;
+                    tile[2 * jc + t] = 0.0f;
+                }
+        R.J[idx] = sx;
+        R.J[nc + idx] = sy;
+        R.J[2 * nc + idx] = sz;
+        return;
+    }
     // candidate patch coordinates per dimension (deduplicated), and for each
     // the tile-local coordinates that alias this cell
     int cand[3][3], ncand[3];
@@ -100,8 +162,6 @@ __global__ void __launch_bounds__(256) k_fold(const RunDev *__restrict__ runs, i
             if (!dup) cand[d][ncand[d]++] = pcd;
         }
     }
-    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
-    const int64_t jc = R.jtile_cells;
     for (int a2 = 0; a2 < ncand[2]; ++a2)
         for (int a1 = 0; a1 < ncand[1]; ++a1)
             for (int a0 = 0; a0 < ncand[0]; ++a0) {
@@ -133,7 +193,6 @@ __global__ void __launch_bounds__(256) k_fold(const RunDev *__restrict__ runs, i
                             tile[2 * jc + t] = 0.0f;
                         }
             }
-    const int64_t nc = R.ncell;
     R.J[idx] = sx;
     R.J[nc + idx] = sy;
     R.J[2 * nc + idx] = sz;
@@ -235,7 +294,9 @@ __global__ void __launch_bounds__(256) k_field_diag(const RunDev *__restrict__ r
         const RunDev &R = runs[r];
         const int64_t idx = c - R.cell_base;
         const int nx = R.n[0], ny = R.n[1], nz = R.n[2];
-        const int i = (int)(idx % nx), j = (int)((idx / nx) % ny), k = (int)(idx / ((int64_t)nx * ny));
+        int g[3];
+        grid_coords(R, idx, g);
+        const int i = g[0], j = g[1], k = g[2];
         const int64_t nc = R.ncell;
         const bool three = R.dim == 3;
         const double dV = R.dxd[1] * R.dxd[2] * (three ? R.dxd[0] : 1.0);
@@ -314,7 +375,9 @@ __global__ void __launch_bounds__(256) k_marder_residual(const RunDev *__restric
     const RunDev &R = runs[find_run(run_base, n_runs, c)];
     const int64_t idx = c - R.cell_base;
     const int nx = R.n[0], ny = R.n[1], nz = R.n[2];
-    const int i = (int)(idx % nx), j = (int)((idx / nx) % ny), k = (int)(idx / ((int64_t)nx * ny));
+    int g[3];
+    grid_coords(R, idx, g);
+    const int i = g[0], j = g[1], k = g[2];
     const int64_t nc = R.ncell;
     const double ix = R.dim == 3 ? 1.0 / R.dxd[0] : 0.0, iy = 1.0 / R.dxd[1], iz = 1.0 / R.dxd[2];
     const int64_t im = i > 0 ? idx - 1 : idx + (nx - 1);
@@ -334,7 +397,9 @@ __global__ void __launch_bounds__(256) k_marder_update(const RunDev *__restrict_
     const RunDev &R = runs[find_run(run_base, n_runs, c)];
     const int64_t idx = c - R.cell_base;
     const int nx = R.n[0], ny = R.n[1], nz = R.n[2];
-    const int i = (int)(idx % nx), j = (int)((idx / nx) % ny), k = (int)(idx / ((int64_t)nx * ny));
+    int g[3];
+    grid_coords(R, idx, g);
+    const int i = g[0], j = g[1], k = g[2];
     const int64_t nc = R.ncell;
     const double h = d * (double)R.dt;
     const double ix = R.dim == 3 ? h / R.dxd[0] : 0.0, iy = h / R.dxd[1], iz = h / R.dxd[2];

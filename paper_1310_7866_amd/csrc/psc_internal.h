@@ -27,6 +27,9 @@ constexpr int kMaxSpecies = PSC_MAX_SPECIES;
 constexpr int kBlock = 256;          // threads per workgroup of the particle kernel
 constexpr int kScanPerThread = 8;    // elements per thread in the scans
 constexpr int kScanBlock = 256 * kScanPerThread;
+// particle slots per species buffer: indices and the sort's group offsets
+// (index + 255) stay in int32
+constexpr int64_t kMaxCapacity = (1ll << 31) - 1024;
 constexpr int kAdjBlock = 512;       // threads per workgroup of the particle adjoint
 constexpr int kAdjChunk = 2048;      // particles per work item of the particle adjoint
 
@@ -54,6 +57,8 @@ struct SpeciesDev {
 struct RunDev {
     int dim, order;
     int vb;              // order 1: Villasenor-Buneman deposit instead of Esirkepov
+    int fold_direct;     // every patch extent >= the current halo (order + 1):
+                         // a tile aliases cells of its own and adjacent patches only
     int n[3];            // cells
     int P[3];            // nominal patch size
     int np[3];           // patches per dimension

@@ -36,6 +36,7 @@ __device__ __forceinline__ int find_seg(const int64_t *base, int n, int64_t c) {
 constexpr int kSortBlock = 256;
 
 using gptr_i32 = __attribute__((address_space(1))) int32_t *;
+using gcptr_u8 = const __attribute__((address_space(1))) uint8_t *;
 
 // Count and scatter: a workgroup owns 256 consecutive old cells of one
 // segment, each of its four waves 64 of them (lane q: cell cw + q), i.e. one
@@ -67,10 +68,13 @@ __device__ __forceinline__ CellBlock cell_block(const RunDev *runs, const ScanSe
     return B;
 }
 
-// Walk the wave's particles: for each, f(i, q, m, rank, last) with q its
-// cell (0..63 within the wave), m its move code, rank its index among the
-// earlier particles of (q, m) in this wave, last whether it is the final one
-// of (q, m) in the current group of 64.  sb: the wave's 65 first indices.
+// Walk the wave's particles: for each lane of a group, f(valid, i, q, m,
+// rank, last) with q its cell (0..63 within the wave), m its move code, rank
+// its index among the earlier particles of (q, m) in this wave, last whether
+// it is the final one of (q, m) in the current group of 64; lanes past the
+// end get valid = false (f is called on every lane so that a store it makes
+// is issued on every group, whatever the lanes).  sb: the wave's 65 first
+// indices.
 //
 // Lane q keeps the first index of cell q in a register.  The cell starts are
 // non-decreasing, so two ballots give the cells [qa, qb] that a group of 64
@@ -81,7 +85,7 @@ __device__ __forceinline__ CellBlock cell_block(const RunDev *runs, const ScanSe
 // the others.
 template <int M, typename F>
 __device__ __forceinline__ void walk_cells(const int32_t *sb, int nw, int32_t pb, int32_t pe,
-                                           const uint8_t *__restrict__ mc, uint32_t &flags, F &&f) {
+                                           gcptr_u8 mc, uint32_t &flags, F &&f) {
     constexpr int CENTER = M / 2;
     constexpr int kLoopCells = 8;   // longest cell range walked by the loop
     const int lane = threadIdx.x & 63;
@@ -89,13 +93,9 @@ __device__ __forceinline__ void walk_cells(const int32_t *sb, int nw, int32_t pb
     const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
     const uint64_t cells = nw >= 64 ? ~0ull : ((1ull << nw) - 1);
     const int32_t sbl = sb[lane < nw ? lane : nw];
-    // the move codes of the next group are loaded while this one is ranked
-    int m_next = pb + lane < pe ? (int)mc[pb + lane] : -1;
-    for (int32_t i0 = pb; i0 < pe; i0 += 64) {
+    auto group = [&](int32_t i0, int m_here) {
         const int32_t i = i0 + lane;
         const bool valid = i < pe;
-        const int m_here = m_next;
-        if (i + 64 < pe) m_next = mc[i + 64];
         const int32_t il = i0 + 63 < pe ? i0 + 63 : pe - 1;
         const int qa = 63 - __clzll(__ballot(sbl <= i0) & cells);   // sb[0] = pb <= i0
         const int qb = 63 - __clzll(__ballot(sbl <= il) & cells);
@@ -142,8 +142,24 @@ __device__ __forceinline__ void walk_cells(const int32_t *sb, int nw, int32_t pb
         const uint64_t grp = bm & mine;
         const int rank = __popcll(grp & below);
         const bool last = (grp & ~upto) == 0;
-        if (valid) f(i, q, m, rank, last);
+        f(valid, i, q, m, rank, last);
         __builtin_amdgcn_wave_barrier();
+    };
+    // Groups go in pairs, each with its own register for move codes loaded
+    // two groups ahead; every load and store is issued on every group (a
+    // group past the end has no valid lane), so the wait for a group's codes
+    // leaves the two most recent stores in flight.
+    if (pb >= pe) return;
+    const int32_t last_i = pe - 1;
+    int ma = (int)mc[imin(pb + lane, last_i)];
+    int mb = (int)mc[imin(pb + 64 + lane, last_i)];
+    for (int32_t i0 = pb; i0 < pe; i0 += 128) {
+        const int m0 = ma;
+        ma = (int)mc[imin(i0 + 128 + lane, last_i)];
+        group(i0, m0);
+        const int m1 = mb;
+        mb = (int)mc[imin(i0 + 192 + lane, last_i)];
+        group(i0 + 64, m1);
     }
 }
 
@@ -261,6 +277,9 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_prefix(const RunDev *__rest
     S.tot[n] = tot;
 }
 
+// target of the scatter's stores from lanes that have no position
+__device__ int32_t sort_sink;
+
 // per old cell: stable positions of its particles.  Lane q sets up the first
 // position of every move code of its cell in LDS; the walk then writes
 // perm[position] = index for 64 consecutive particles at a time, so the
@@ -289,14 +308,19 @@ __global__ void __launch_bounds__(kSortCells) k_sort_scatter(const RunDev *__res
     if (lane == 0) sb[64] = cs_old[B.ce];
     if (lane < nw) {
         const int64_t o = B.cw + lane;
-        int g[3];
-        decode_key(R, o, g);
+        int pc[3], lc[3];
+        decode_key32(R, (uint32_t)o, pc, lc);
+        Axis ax[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ax[d] = axis_neighbours(R.P[d], R.n[d], R.np[d], pc[d], lc[d]);
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             int d[3];
             move_delta(DIM, m, d);
-            const int dx = DIM == 3 ? wrap(g[0] + d[0], R.n[0]) : 0;
-            const int64_t dst = encode_key(R, dx, wrap(g[1] + d[1], R.n[1]), wrap(g[2] + d[2], R.n[2]));
+            // destination cell: one step along the move (index 1 + d per axis)
+            const int a0 = DIM == 3 ? 1 + d[0] : 1, a1 = 1 + d[1], a2 = 1 + d[2];
+            const uint32_t dst = key_of(R, ax[0].pc[a0], ax[1].pc[a1], ax[2].pc[a2], ax[0].l[a0], ax[1].l[a1],
+                                        ax[2].l[a2], ax[0].ext[a0], ax[1].ext[a1], ax[2].ext[a2]);
             tab[m * 64 + lane] = cs_new[dst] + S.pre[m * nc + o];
             if (m != M / 2) S.cnt[m * nc + o] = 0;   // consumed by the prefix pass: clear for the next push
         }
@@ -306,12 +330,19 @@ __global__ void __launch_bounds__(kSortCells) k_sort_scatter(const RunDev *__res
     const int32_t n = (int32_t)S.n;
     uint32_t flags = 0;
     bool bad = false;
-    walk_cells<M>(sb, nw, sb[0], sb[nw], S.mc, flags, [&](int32_t i, int q, int m, int rank, bool last) {
-        const int32_t p = tab[m * 64 + q] + rank;
-        if (p >= 0 && p < n) perm[p] = i;   // out of range only after a counter overflow
-        else bad = true;
-        if (last) tab[m * 64 + q] = p + 1;
-    });
+    walk_cells<M>(sb, nw, sb[0], sb[nw], (gcptr_u8)S.mc, flags,
+                  [&](bool valid, int32_t i, int q, int m, int rank, bool last) {
+                      const int slot = valid ? m * 64 + q : 0;
+                      const int32_t p = tab[slot] + rank;
+                      // out of range only after a counter overflow
+                      const bool ok = valid && p >= 0 && p < n;
+                      bad |= valid && !ok;
+                      // one store per group on every lane: lanes without a
+                      // position write the sink word
+                      const gptr_i32 dst = ok ? perm + p : (gptr_i32)&sort_sink;
+                      *dst = i;
+                      if (valid && last) tab[slot] = p + 1;
+                  });
     if (bad) atomicOr(err, PSC_DEV_OVERFULL);
 }
 

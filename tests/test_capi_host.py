@@ -68,6 +68,16 @@ def test_bad_geometry_rejected():
     assert _init(d) == 1
 
 
+def test_capacity_limit():
+    # particle indices and the sort's look-ahead offsets stay in int32
+    c = cases.thermal2d(ny=16, nz=12, ppc=2, patch=8)
+    d = psc.run_desc(c)
+    d.capacity[0] = (1 << 31) - 1024
+    assert _init(d) == 0
+    d.capacity[0] = (1 << 31) - 1023
+    assert _init(d) == 1
+
+
 def test_patches_narrower_than_the_current_halo_rejected():
     """The current fold reads a cell's own patch and its two neighbours: with
     more than three patches along a dimension, a patch (or the truncated last
