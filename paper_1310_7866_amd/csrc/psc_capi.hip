@@ -47,6 +47,10 @@ struct psc_ctx {
     int64_t max_items = 0;
     int64_t total_cells = 0;
     std::vector<int64_t> run_base;       // n_runs + 1
+    std::vector<int64_t> patch_base;     // n_runs + 1: first patch of each run in the flat patch space
+    int max_patch_cells = 0;             // cells of the largest patch of any run
+    int fold_direct_dims = 0;            // bit 1 << dim: a run of that dimension folds by patch
+    bool any_fold_search = false;
     int n_segs = 0;
     std::vector<int64_t> seg_base;       // n_segs + 1
     std::vector<int32_t> seg_run, seg_sp;
@@ -57,7 +61,7 @@ struct psc_ctx {
     size_t cub_bytes = 0;
 
     struct Off {
-        size_t runs, units, item_start, run_base, seg_base, seg_run, seg_sp, segs0, segs1, scan_tmp, err;
+        size_t runs, units, item_start, run_base, patch_base, seg_base, seg_run, seg_sp, segs0, segs1, scan_tmp, err;
         size_t load_keys, load_idx, load_keys_s, load_idx_s, cub;
         size_t adj_runs;
         size_t queue, part, unit_counts;
@@ -236,6 +240,7 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
     };
     ctx->runs.resize(n_runs);
     ctx->run_base.assign(n_runs + 1, 0);
+    ctx->patch_base.assign(n_runs + 1, 0);
     ctx->loaded.assign(n_runs, std::vector<bool>(PSC_MAX_SPECIES, false));
     for (int r = 0; r < n_runs; ++r) {
         const psc_run_desc &d = runs[r];
@@ -261,6 +266,10 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
             const int halo = imax(cur_lo(d.order), cur_hi(d.order));
             if (d.patch[k] < halo || last < halo) R.fold_direct = 0;
         }
+        ctx->patch_base[r + 1] = ctx->patch_base[r] + R.n_patches;
+        ctx->max_patch_cells = imax(ctx->max_patch_cells, d.patch[0] * d.patch[1] * d.patch[2]);
+        if (R.fold_direct) ctx->fold_direct_dims |= 1 << d.dim;
+        else ctx->any_fold_search = true;
         R.n_species = d.n_species;
         R.ncell = (int64_t)d.gdims[0] * d.gdims[1] * d.gdims[2];
         R.cell_base = ctx->total_cells;
@@ -307,6 +316,7 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
     ctx->off.units = take(sizeof(Unit) * ctx->units.size());
     ctx->off.item_start = take(sizeof(int32_t) * (ctx->units.size() + 1));
     ctx->off.run_base = take(sizeof(int64_t) * (n_runs + 1));
+    ctx->off.patch_base = take(sizeof(int64_t) * (n_runs + 1));
     ctx->off.seg_base = take(sizeof(int64_t) * (ctx->n_segs + 1));
     ctx->off.seg_run = take(sizeof(int32_t) * ctx->n_segs);
     ctx->off.seg_sp = take(sizeof(int32_t) * ctx->n_segs);
@@ -460,6 +470,9 @@ psc_status psc_bind(psc_ctx *ctx, const psc_run_bufs *bufs, int n_runs, void *wo
                             hipMemcpyHostToDevice, s), "upload units");
     HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.run_base), ctx->run_base.data(), sizeof(int64_t) * (ctx->n_runs + 1),
                             hipMemcpyHostToDevice, s), "upload run base");
+    HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.patch_base), ctx->patch_base.data(),
+                            sizeof(int64_t) * (ctx->n_runs + 1), hipMemcpyHostToDevice, s),
+             "upload patch base");
     HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.seg_base), ctx->seg_base.data(), sizeof(int64_t) * (ctx->n_segs + 1),
                             hipMemcpyHostToDevice, s), "upload seg base");
     HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.seg_run), ctx->seg_run.data(), sizeof(int32_t) * ctx->n_segs,
@@ -608,7 +621,10 @@ psc_status psc_push_particles(psc_ctx *ctx, void *stream) {
 psc_status psc_deposit_current(psc_ctx *ctx, void *stream) {
     if (!ctx || !ctx->bound) return PSC_ERR_STATE;
     Launch L = make_launch(ctx, (hipStream_t)stream);
-    HIPCHECK(launch_fold(L, ctx->total_cells, ctx->at<int64_t>(ctx->off.run_base)), "deposit current");
+    HIPCHECK(launch_fold(L, ctx->total_cells, ctx->at<int64_t>(ctx->off.run_base), ctx->patch_base[ctx->n_runs],
+                         ctx->at<int64_t>(ctx->off.patch_base), ctx->max_patch_cells, ctx->fold_direct_dims,
+                         ctx->any_fold_search),
+             "deposit current");
     return PSC_OK;
 }
 

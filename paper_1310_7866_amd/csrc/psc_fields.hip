@@ -6,7 +6,7 @@
 // fig. psc_new (two B half steps around the particle loop, one E full step).
 // All kernels index a flat cell space spanning every run; the run of a cell is
 // found by binary search over the runs' cell offsets.
-#include "psc_internal.h"
+#include "psc_device.h"
 
 namespace psc {
 
@@ -17,6 +17,31 @@ __device__ __forceinline__ int find_run(const int64_t *base, int n_runs, int64_t
         if (base[mid] <= c) lo = mid; else hi = mid;
     }
     return lo;
+}
+
+// The run of every cell of this workgroup when they lie in one run (the
+// usual case: then the run's fields are read once, through scalar loads),
+// else -1.
+__device__ __forceinline__ int block_run(const int64_t *base, int n_runs, int64_t total) {
+    const int64_t c0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t c1 = (c0 + blockDim.x < total ? c0 + blockDim.x : total) - 1;
+    const int r = find_run(base, n_runs, c0);
+    return base[r + 1] > c1 ? r : -1;
+}
+
+// Call f(R, idx) for the cell c of the flat cell space (idx: its index in
+// run R), with R uniform over the workgroup when block_run finds one run.
+template <typename F>
+__device__ __forceinline__ void with_run(const RunDev *runs, const int64_t *base, int n_runs, int64_t total, F &&f) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int rb = block_run(base, n_runs, total);
+    if (c >= total) return;
+    if (rb >= 0) {
+        f(runs[rb], c - base[rb]);
+    } else {
+        const int r = find_run(base, n_runs, c);
+        f(runs[r], c - base[r]);
+    }
 }
 
 // grid coordinates of cell idx of a run (32-bit: a run has fewer than 2^31
@@ -31,14 +56,7 @@ __device__ __forceinline__ void grid_coords(const RunDev &R, int64_t idx, int g[
     g[2] = (int)k;
 }
 
-// B <- B - (dt/2) curl^+ E (op 0) or E <- E + dt (curl^- B - J) (op 1)
-__global__ void __launch_bounds__(256) k_fields(const RunDev *__restrict__ runs, int n_runs,
-                                                const int64_t *__restrict__ run_base, int64_t total, int op) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= total) return;
-    const int r = find_run(run_base, n_runs, c);
-    const RunDev &R = runs[r];
-    const int64_t idx = c - R.cell_base;
+__device__ __forceinline__ void field_step(const RunDev &R, int64_t idx, int op) {
     const int nx = R.n[0], ny = R.n[1], nz = R.n[2];
     int g[3];
     grid_coords(R, idx, g);
@@ -47,33 +65,47 @@ __global__ void __launch_bounds__(256) k_fields(const RunDev *__restrict__ runs,
     const bool three = R.dim == 3;
     const float ix = three ? R.inv_dx[0] : 0.0f, iy = R.inv_dx[1], iz = R.inv_dx[2];
     const int64_t sx = 1, sy = nx, sz = (int64_t)nx * ny;
+    const gptr<float> E = to_global(R.E), B = to_global(R.B), J = to_global(R.J);
+    // every load before the arithmetic and the stores (in 2-d the x
+    // neighbour is the cell itself and ix is zero, so its term is zero)
     if (op == PSC_B_HALF) {
         const float h = 0.5f * R.dt;
         const int64_t ip = i + 1 < nx ? idx + sx : idx - (int64_t)(nx - 1) * sx;
         const int64_t jp = j + 1 < ny ? idx + sy : idx - (int64_t)(ny - 1) * sy;
         const int64_t kp = k + 1 < nz ? idx + sz : idx - (int64_t)(nz - 1) * sz;
-        const float *Ex = R.E, *Ey = R.E + nc, *Ez = R.E + 2 * nc;
+        const gptr<float> Ex = E, Ey = E + nc, Ez = E + 2 * nc;
         const float ex = Ex[idx], ey = Ey[idx], ez = Ez[idx];
-        const float cx = (Ez[jp] - ez) * iy - (Ey[kp] - ey) * iz;
-        const float cy = (Ex[kp] - ex) * iz - (three ? (Ez[ip] - ez) * ix : 0.0f);
-        const float cz = (three ? (Ey[ip] - ey) * ix : 0.0f) - (Ex[jp] - ex) * iy;
-        R.B[idx] -= h * cx;
-        R.B[nc + idx] -= h * cy;
-        R.B[2 * nc + idx] -= h * cz;
+        const float ez_j = Ez[jp], ey_k = Ey[kp], ex_k = Ex[kp], ez_i = Ez[ip], ey_i = Ey[ip], ex_j = Ex[jp];
+        const float bx = B[idx], by = B[nc + idx], bz = B[2 * nc + idx];
+        const float cx = (ez_j - ez) * iy - (ey_k - ey) * iz;
+        const float cy = (ex_k - ex) * iz - (ez_i - ez) * ix;
+        const float cz = (ey_i - ey) * ix - (ex_j - ex) * iy;
+        B[idx] = bx - h * cx;
+        B[nc + idx] = by - h * cy;
+        B[2 * nc + idx] = bz - h * cz;
     } else {
         const float h = R.dt;
         const int64_t im = i > 0 ? idx - sx : idx + (int64_t)(nx - 1) * sx;
         const int64_t jm = j > 0 ? idx - sy : idx + (int64_t)(ny - 1) * sy;
         const int64_t km = k > 0 ? idx - sz : idx + (int64_t)(nz - 1) * sz;
-        const float *Bx = R.B, *By = R.B + nc, *Bz = R.B + 2 * nc;
+        const gptr<float> Bx = B, By = B + nc, Bz = B + 2 * nc;
         const float bx = Bx[idx], by = By[idx], bz = Bz[idx];
-        const float cx = (bz - Bz[jm]) * iy - (by - By[km]) * iz;
-        const float cy = (bx - Bx[km]) * iz - (three ? (bz - Bz[im]) * ix : 0.0f);
-        const float cz = (three ? (by - By[im]) * ix : 0.0f) - (bx - Bx[jm]) * iy;
-        R.E[idx] += h * (cx - R.J[idx]);
-        R.E[nc + idx] += h * (cy - R.J[nc + idx]);
-        R.E[2 * nc + idx] += h * (cz - R.J[2 * nc + idx]);
+        const float bz_j = Bz[jm], by_k = By[km], bx_k = Bx[km], bz_i = Bz[im], by_i = By[im], bx_j = Bx[jm];
+        const float ex = E[idx], ey = E[nc + idx], ez = E[2 * nc + idx];
+        const float jx = J[idx], jy = J[nc + idx], jz = J[2 * nc + idx];
+        const float cx = (bz - bz_j) * iy - (by - by_k) * iz;
+        const float cy = (bx - bx_k) * iz - (bz - bz_i) * ix;
+        const float cz = (by - by_i) * ix - (bx - bx_j) * iy;
+        E[idx] = ex + h * (cx - jx);
+        E[nc + idx] = ey + h * (cy - jy);
+        E[2 * nc + idx] = ez + h * (cz - jz);
     }
+}
+
+// B <- B - (dt/2) curl^+ E (op 0) or E <- E + dt (curl^- B - J) (op 1)
+__global__ void __launch_bounds__(256) k_fields(const RunDev *__restrict__ runs, int n_runs,
+                                                const int64_t *__restrict__ run_base, int64_t total, int op) {
+    with_run(runs, run_base, n_runs, total, [&](const RunDev &R, int64_t idx) { field_step(R, idx, op); });
 }
 
 hipError_t launch_fields(const Launch &L, int op, int64_t total, const int64_t *run_base) {
@@ -100,55 +132,7 @@ __global__ void __launch_bounds__(256) k_fold(const RunDev *__restrict__ runs, i
     float sx = 0.0f, sy = 0.0f, sz = 0.0f;
     const int64_t jc = R.jtile_cells;
     const int64_t nc = R.ncell;
-    if (R.fold_direct) {
-        // Per dimension: the patch below (whose upper halo reaches this cell
-        // when l < hi), the own patch, the patch above (lower halo, when
-        // l >= ext - lo), in that order, with the tile-local coordinate of
-        // the cell in each.  With 1 or 2 patches along a dimension these are
-        // different aliases within the same tile.
-        int pcs[3][3], ls[3][3], nd[3];
-        for (int d = 0; d < 3; ++d) {
-            if (R.dim == 2 && d == 0) {
-                pcs[0][0] = 0;
-                ls[0][0] = -lo;   // tile x index 0
-                nd[0] = 1;
-                continue;
-            }
-            const int pc = g[d] / R.P[d];
-            const int l = g[d] - pc * R.P[d];
-            const int ext = imin(R.P[d], R.n[d] - pc * R.P[d]);
-            int k = 0;
-            if (l < hi) {
-                const int pdn = pc == 0 ? R.np[d] - 1 : pc - 1;
-                pcs[d][k] = pdn;
-                ls[d][k++] = l + imin(R.P[d], R.n[d] - pdn * R.P[d]);
-            }
-            pcs[d][k] = pc;
-            ls[d][k++] = l;
-            if (l >= ext - lo) {
-                pcs[d][k] = pc == R.np[d] - 1 ? 0 : pc + 1;
-                ls[d][k++] = l - ext;
-            }
-            nd[d] = k;
-        }
-        for (int z = 0; z < nd[2]; ++z)
-            for (int y = 0; y < nd[1]; ++y)
-                for (int x = 0; x < nd[0]; ++x) {
-                    const int p = pcs[0][x] + R.np[0] * (pcs[1][y] + R.np[1] * pcs[2][z]);
-                    float *tile = R.jtile + (int64_t)p * 3 * jc;
-                    const int64_t t = (ls[0][x] + lo) + (int64_t)R.jt[0] * ((ls[1][y] + lo) + (int64_t)R.jt[1] * (ls[2][z] + lo));
-                    sx += tile[t];
-                    sy += tile[jc + t];
-                    sz += tile[2 * jc + t];
-                    tile[t] = 0.0f;
-                    tile[jc + t] = 0.0f;
-                    tile[2 * jc + t] = 0.0f;
-                }
-        R.J[idx] = sx;
-        R.J[nc + idx] = sy;
-        R.J[2 * nc + idx] = sz;
-        return;
-    }
+    if (R.fold_direct) return;   // folded by patch (k_fold_patch)
     // candidate patch coordinates per dimension (deduplicated), and for each
     // the tile-local coordinates that alias this cell
     int cand[3][3], ncand[3];
@@ -198,9 +182,135 @@ __global__ void __launch_bounds__(256) k_fold(const RunDev *__restrict__ runs, i
     R.J[2 * nc + idx] = sz;
 }
 
-hipError_t launch_fold(const Launch &L, int64_t total, const int64_t *run_base) {
-    const unsigned grid = (unsigned)((total + 255) / 256);
-    hipLaunchKernelGGL(k_fold, dim3(grid), dim3(256), 0, L.stream, L.runs_dev, L.n_runs, run_base, total);
+// Runs whose patches are all at least as wide as the current halo: a tile
+// aliases cells of its own patch and, across each face, of the adjacent
+// patch only.  Workgroup row (patch, part) folds part of the patch's cells:
+// per dimension the patch below (whose upper halo reaches the cell when
+// l < hi), the own patch and the patch above (lower halo, when
+// l >= ext - lo), in that order.  With 1 or 2 patches along a dimension
+// these are different aliases within the same tile.  A patch's tile is read
+// by its own workgroups and, at the faces, its neighbours', so the reads
+// stay within a few contiguous tiles at a time.
+constexpr int kFoldBlock = 256;
+
+template <int DIM>
+__global__ void __launch_bounds__(kFoldBlock) k_fold_patch(const RunDev *__restrict__ runs, int n_runs,
+                                                           const int64_t *__restrict__ patch_base) {
+    constexpr int X0 = DIM == 3 ? 0 : 1, X1 = DIM == 3 ? 2 : 1;   // x candidates (2-d: the own one)
+    const int64_t gp = blockIdx.x;
+    const int r = find_run(patch_base, n_runs, gp);
+    const RunDev &R = runs[r];
+    if (!R.fold_direct || R.dim != DIM) return;
+    const int p = (int)(gp - patch_base[r]);
+    int pc[3], ext[3];
+    pc[0] = p % R.np[0];
+    pc[1] = (p / R.np[0]) % R.np[1];
+    pc[2] = p / (R.np[0] * R.np[1]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ext[d] = imin(R.P[d], R.n[d] - pc[d] * R.P[d]);
+    const uint32_t ncells = (uint32_t)(ext[0] * ext[1] * ext[2]);
+    const int lo = cur_lo(R.order), hi = cur_hi(R.order);
+    const int64_t jc = R.jtile_cells;
+    const int64_t nc = R.ncell;
+    const gptr<float> jtile = to_global(R.jtile), J = to_global(R.J);
+    for (uint32_t t = blockIdx.y * kFoldBlock + threadIdx.x; t < ncells; t += gridDim.y * kFoldBlock) {
+        int l[3];
+        const uint32_t q = t / (uint32_t)ext[0];
+        l[0] = (int)(t - q * (uint32_t)ext[0]);
+        l[2] = (int)(q / (uint32_t)ext[1]);
+        l[1] = (int)(q - (uint32_t)l[2] * (uint32_t)ext[1]);
+        // candidates per dimension: 0 below, 1 own, 2 above
+        int pcs[3][3], ls[3][3];
+        bool on[3][3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (DIM == 2 && d == 0) {
+                on[0][1] = true;
+                pcs[0][1] = 0;
+                ls[0][1] = -lo;   // tile x index 0
+                continue;
+            }
+            const int pdn = pc[d] == 0 ? R.np[d] - 1 : pc[d] - 1;
+            on[d][0] = l[d] < hi;
+            pcs[d][0] = pdn;
+            ls[d][0] = l[d] + imin(R.P[d], R.n[d] - pdn * R.P[d]);
+            on[d][1] = true;
+            pcs[d][1] = pc[d];
+            ls[d][1] = l[d];
+            on[d][2] = l[d] >= ext[d] - lo;
+            pcs[d][2] = pc[d] == R.np[d] - 1 ? 0 : pc[d] + 1;
+            ls[d][2] = l[d] - ext[d];
+        }
+        // every load before the sums and the clearing stores, and every
+        // load issued (an unused candidate reads the own entry, counted as
+        // zero), so that a cell's reads are in flight together
+        float v[27][3];
+        int64_t at[27];
+        const int64_t own = (int64_t)p * 3 * jc + (ls[0][1] + lo) +
+                            (int64_t)R.jt[0] * ((l[1] + lo) + (int64_t)R.jt[1] * (l[2] + lo));
+#pragma unroll
+        for (int z = 0; z < 3; ++z)
+#pragma unroll
+            for (int y = 0; y < 3; ++y)
+#pragma unroll
+                for (int x = X0; x <= X1; ++x) {
+                    const int k = (z * 3 + y) * 3 + x;
+                    const int pq = pcs[0][x] + R.np[0] * (pcs[1][y] + R.np[1] * pcs[2][z]);
+                    const bool use = on[2][z] && on[1][y] && on[0][x];
+                    at[k] = use ? (int64_t)pq * 3 * jc + (ls[0][x] + lo) +
+                                      (int64_t)R.jt[0] * ((ls[1][y] + lo) + (int64_t)R.jt[1] * (ls[2][z] + lo))
+                                : own;
+                    const float a = jtile[at[k]], b = jtile[jc + at[k]], c = jtile[2 * jc + at[k]];
+                    v[k][0] = use ? a : 0.0f;
+                    v[k][1] = use ? b : 0.0f;
+                    v[k][2] = use ? c : 0.0f;
+                }
+        float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+#pragma unroll
+        for (int z = 0; z < 3; ++z)
+#pragma unroll
+            for (int y = 0; y < 3; ++y)
+#pragma unroll
+                for (int x = X0; x <= X1; ++x) {
+                    const int k = (z * 3 + y) * 3 + x;
+                    sx += v[k][0];
+                    sy += v[k][1];
+                    sz += v[k][2];
+                }
+#pragma unroll
+        for (int z = 0; z < 3; ++z)
+#pragma unroll
+            for (int y = 0; y < 3; ++y)
+#pragma unroll
+                for (int x = X0; x <= X1; ++x) {
+                    const int k = (z * 3 + y) * 3 + x;
+                    if (on[2][z] && on[1][y] && on[0][x]) {
+                        jtile[at[k]] = 0.0f;
+                        jtile[jc + at[k]] = 0.0f;
+                        jtile[2 * jc + at[k]] = 0.0f;
+                    }
+                }
+        const int64_t idx = (pc[0] * R.P[0] + l[0]) +
+                            (int64_t)R.n[0] * ((pc[1] * R.P[1] + l[1]) + (int64_t)R.n[1] * (pc[2] * R.P[2] + l[2]));
+        J[idx] = sx;
+        J[nc + idx] = sy;
+        J[2 * nc + idx] = sz;
+    }
+}
+
+hipError_t launch_fold(const Launch &L, int64_t total, const int64_t *run_base, int64_t total_patches,
+                       const int64_t *patch_base, int max_patch_cells, int direct_dims, bool any_search) {
+    const unsigned parts = (unsigned)imin((max_patch_cells + kFoldBlock - 1) / kFoldBlock, 1024);
+    if ((direct_dims & 4) && total_patches > 0)
+        hipLaunchKernelGGL(k_fold_patch<2>, dim3((unsigned)total_patches, parts), dim3(kFoldBlock), 0, L.stream,
+                           L.runs_dev, L.n_runs, patch_base);
+    if ((direct_dims & 8) && total_patches > 0)
+        hipLaunchKernelGGL(k_fold_patch<3>, dim3((unsigned)total_patches, parts), dim3(kFoldBlock), 0, L.stream,
+                           L.runs_dev, L.n_runs, patch_base);
+    if (any_search) {
+        const unsigned grid = (unsigned)((total + 255) / 256);
+        hipLaunchKernelGGL(k_fold, dim3(grid), dim3(256), 0, L.stream, L.runs_dev, L.n_runs, run_base, total);
+    }
     return hipGetLastError();
 }
 
@@ -370,47 +480,45 @@ __global__ void k_count(const RunDev *__restrict__ runs, int n_runs, double *out
 __global__ void __launch_bounds__(256) k_marder_residual(const RunDev *__restrict__ runs, int n_runs,
                                                          const int64_t *__restrict__ run_base, int64_t total,
                                                          const double *__restrict__ ref) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= total) return;
-    const RunDev &R = runs[find_run(run_base, n_runs, c)];
-    const int64_t idx = c - R.cell_base;
-    const int nx = R.n[0], ny = R.n[1], nz = R.n[2];
-    int g[3];
-    grid_coords(R, idx, g);
-    const int i = g[0], j = g[1], k = g[2];
-    const int64_t nc = R.ncell;
-    const double ix = R.dim == 3 ? 1.0 / R.dxd[0] : 0.0, iy = 1.0 / R.dxd[1], iz = 1.0 / R.dxd[2];
-    const int64_t im = i > 0 ? idx - 1 : idx + (nx - 1);
-    const int64_t jm = j > 0 ? idx - nx : idx + (int64_t)(ny - 1) * nx;
-    const int64_t km = k > 0 ? idx - (int64_t)nx * ny : idx + (int64_t)(nz - 1) * nx * ny;
-    const double dive = ((double)R.E[idx] - R.E[im]) * ix + ((double)R.E[nc + idx] - R.E[nc + jm]) * iy +
-                        ((double)R.E[2 * nc + idx] - R.E[2 * nc + km]) * iz;
-    R.rho[idx] = dive - R.rho[idx] - (ref ? ref[c] : 0.0);
+    with_run(runs, run_base, n_runs, total, [&](const RunDev &R, int64_t idx) {
+        const int64_t c = R.cell_base + idx;
+        const int nx = R.n[0], ny = R.n[1], nz = R.n[2];
+        int g[3];
+        grid_coords(R, idx, g);
+        const int i = g[0], j = g[1], k = g[2];
+        const int64_t nc = R.ncell;
+        const double ix = R.dim == 3 ? 1.0 / R.dxd[0] : 0.0, iy = 1.0 / R.dxd[1], iz = 1.0 / R.dxd[2];
+        const int64_t im = i > 0 ? idx - 1 : idx + (nx - 1);
+        const int64_t jm = j > 0 ? idx - nx : idx + (int64_t)(ny - 1) * nx;
+        const int64_t km = k > 0 ? idx - (int64_t)nx * ny : idx + (int64_t)(nz - 1) * nx * ny;
+        const double dive = ((double)R.E[idx] - R.E[im]) * ix + ((double)R.E[nc + idx] - R.E[nc + jm]) * iy +
+                            ((double)R.E[2 * nc + idx] - R.E[2 * nc + km]) * iz;
+        R.rho[idx] = dive - R.rho[idx] - (ref ? ref[c] : 0.0);
+    });
 }
 
 // Marder cleaning, update: E += d dt grad^+ F (the forward difference of the
 // node field F lies where each E component is staggered)
 __global__ void __launch_bounds__(256) k_marder_update(const RunDev *__restrict__ runs, int n_runs,
                                                        const int64_t *__restrict__ run_base, int64_t total, double d) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= total) return;
-    const RunDev &R = runs[find_run(run_base, n_runs, c)];
-    const int64_t idx = c - R.cell_base;
-    const int nx = R.n[0], ny = R.n[1], nz = R.n[2];
-    int g[3];
-    grid_coords(R, idx, g);
-    const int i = g[0], j = g[1], k = g[2];
-    const int64_t nc = R.ncell;
-    const double h = d * (double)R.dt;
-    const double ix = R.dim == 3 ? h / R.dxd[0] : 0.0, iy = h / R.dxd[1], iz = h / R.dxd[2];
-    const int64_t ip = i + 1 < nx ? idx + 1 : idx - (nx - 1);
-    const int64_t jp = j + 1 < ny ? idx + nx : idx - (int64_t)(ny - 1) * nx;
-    const int64_t kp = k + 1 < nz ? idx + (int64_t)nx * ny : idx - (int64_t)(nz - 1) * nx * ny;
-    const double *F = R.rho;
-    const double f = F[idx];
-    R.E[idx] = (float)(R.E[idx] + (F[ip] - f) * ix);
-    R.E[nc + idx] = (float)(R.E[nc + idx] + (F[jp] - f) * iy);
-    R.E[2 * nc + idx] = (float)(R.E[2 * nc + idx] + (F[kp] - f) * iz);
+    with_run(runs, run_base, n_runs, total, [&](const RunDev &R, int64_t idx) {
+        const int nx = R.n[0], ny = R.n[1], nz = R.n[2];
+        int g[3];
+        grid_coords(R, idx, g);
+        const int i = g[0], j = g[1], k = g[2];
+        const int64_t nc = R.ncell;
+        const double h = d * (double)R.dt;
+        const double ix = R.dim == 3 ? h / R.dxd[0] : 0.0, iy = h / R.dxd[1], iz = h / R.dxd[2];
+        const int64_t ip = i + 1 < nx ? idx + 1 : idx - (nx - 1);
+        const int64_t jp = j + 1 < ny ? idx + nx : idx - (int64_t)(ny - 1) * nx;
+        const int64_t kp = k + 1 < nz ? idx + (int64_t)nx * ny : idx - (int64_t)(nz - 1) * nx * ny;
+        const double *F = R.rho;
+        const double f = F[idx], fi = F[ip], fj = F[jp], fk = F[kp];
+        const float ex = R.E[idx], ey = R.E[nc + idx], ez = R.E[2 * nc + idx];
+        R.E[idx] = (float)(ex + (fi - f) * ix);
+        R.E[nc + idx] = (float)(ey + (fj - f) * iy);
+        R.E[2 * nc + idx] = (float)(ez + (fk - f) * iz);
+    });
 }
 
 // charge density of the current particles into every run's rho

@@ -223,7 +223,11 @@ hipError_t launch_push(const Launch &L, const Unit *units_dev, int n_units, int3
                        const PushMode &pm);
 hipError_t launch_unit_counts(const Launch &L, const Unit *units, int n_units, int cs_sel, int32_t *out);
 hipError_t launch_fields(const Launch &L, int op, int64_t total_cells, const int64_t *run_cell_base_dev);
-hipError_t launch_fold(const Launch &L, int64_t total_cells, const int64_t *run_cell_base_dev);
+// fold: runs with fold_direct by patch (one workgroup row per patch; bit
+// 1 << dim of direct_dims set when such a run has that dimension), the
+// others by cell with the alias search
+hipError_t launch_fold(const Launch &L, int64_t total_cells, const int64_t *run_cell_base_dev, int64_t total_patches,
+                       const int64_t *run_patch_base_dev, int max_patch_cells, int direct_dims, bool any_search);
 hipError_t launch_sort(const Launch &L, const int64_t *seg_cell_base_dev, const int32_t *seg_run_dev,
                        const int32_t *seg_species_dev, int n_segs, int64_t total_seg_cells,
                        const ScanSeg *segs_dev, int64_t n_scan_blocks, int32_t *scan_tmp, int cs_sel,

@@ -38,18 +38,25 @@ constexpr int kSortBlock = 256;
 using gptr_i32 = __attribute__((address_space(1))) int32_t *;
 using gcptr_u8 = const __attribute__((address_space(1))) uint8_t *;
 
-// Count and scatter: a workgroup owns 256 consecutive old cells of one
-// segment, each of its four waves 64 of them (lane q: cell cw + q), i.e. one
-// contiguous range of particles (the buffer is ordered by old cell).  The
-// wave walks that range 64 particles at a time with coalesced loads.  Each
-// lane finds its particle's cell by binary search over the cells' first
-// indices in LDS; its rank among the earlier particles of the same cell and
-// move code is the population count of the code's ballot restricted to the
-// lanes of its cell below it; the last such lane advances the (cell, code)
-// counter kept in LDS.  Sort block b lies in scan block b/8 of the same
-// segment, whose table gives the segment.
-constexpr int kSortCells = 256;
-static_assert(kScanBlock == 8 * kSortCells, "eight sort blocks per scan block");
+// Scatter: a workgroup owns 4 kWaveCells consecutive old cells of one
+// segment, each of its four waves kWaveCells of them (lane q: cell cw + q),
+// i.e. one contiguous range of particles (the buffer is ordered by old
+// cell).  The wave walks that range 64 particles at a time with coalesced
+// loads.  Each lane finds its particle's cell from the cells' first indices;
+// its rank among the earlier particles of the same cell and move code is the
+// population count of the code's ballot restricted to the lanes of its cell
+// below it; the last such lane advances the (cell, code) counter kept in
+// LDS.  Sort block b lies in scan block b / kSortPerScan of the same
+// segment, whose table gives the segment.  Fewer cells per wave give more,
+// shorter waves, which balances dense and sparse regions better.
+#ifndef PSC_SORT_WAVE_CELLS
+#define PSC_SORT_WAVE_CELLS 32
+#endif
+constexpr int kSortThreads = 256;                      // four waves
+constexpr int kWaveCells = PSC_SORT_WAVE_CELLS;        // old cells per wave
+constexpr int kSortCells = 4 * kWaveCells;             // old cells per workgroup
+constexpr int kSortPerScan = kScanBlock / kSortCells;  // workgroups per scan block
+static_assert(kWaveCells >= 1 && kWaveCells <= 64 && kScanBlock % kSortCells == 0, "sort geometry");
 
 struct CellBlock {
     const RunDev *R;
@@ -60,11 +67,14 @@ struct CellBlock {
 __device__ __forceinline__ CellBlock cell_block(const RunDev *runs, const ScanSeg *segs, const int32_t *block_seg,
                                                 const int32_t *seg_run, const int32_t *seg_sp) {
     CellBlock B;
-    const int sg = block_seg[blockIdx.x >> 3];
+    const int sg = block_seg[blockIdx.x / kSortPerScan];
     B.R = &runs[seg_run[sg]];
     B.S = &B.R->sp[seg_sp[sg]];
-    B.cw = ((int64_t)blockIdx.x - 8 * segs[sg].block0) * kSortCells + 64 * (threadIdx.x >> 6);
-    B.ce = B.cw + 64 < B.R->ncell ? B.cw + 64 : B.R->ncell;
+    // the wave index as a scalar: the walk's bounds, loop counters and cell
+    // masks then live in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    B.cw = ((int64_t)blockIdx.x - kSortPerScan * segs[sg].block0) * kSortCells + kWaveCells * wave;
+    B.ce = B.cw + kWaveCells < B.R->ncell ? B.cw + kWaveCells : B.R->ncell;
     return B;
 }
 
@@ -219,21 +229,13 @@ __device__ __forceinline__ uint32_t key_of(const RunDev &r, int p0, int p1, int 
            (uint32_t)p0 * r.P[0] * e1 * e2 + (uint32_t)(l0 + e0 * (l1 + e1 * l2));
 }
 
-// per new cell: order the source cells by key and assign arrival prefixes
+// per new cell n of species S of run R: order the source cells by key and
+// assign arrival prefixes
 template <int DIM>
-__global__ void __launch_bounds__(kSortBlock) k_sort_prefix(const RunDev *__restrict__ runs,
-                                                            const int64_t *__restrict__ seg_base,
-                                                            const int32_t *__restrict__ seg_run,
-                                                            const int32_t *__restrict__ seg_sp, int n_segs,
-                                                            int64_t total, int cs_sel, uint32_t *err) {
+__device__ __forceinline__ void prefix_cell(const RunDev &R, const SpeciesDev &S, int64_t n, int cs_sel,
+                                            uint32_t *err) {
     constexpr int M = DIM == 3 ? 27 : 9;
     constexpr int CENTER = M / 2;   // the move that stays in the cell
-    const int64_t c = (int64_t)blockIdx.x * kSortBlock + threadIdx.x;
-    if (c >= total) return;
-    const int sg = find_seg(seg_base, n_segs, c);
-    const RunDev &R = runs[seg_run[sg]];
-    const SpeciesDev &S = R.sp[seg_sp[sg]];
-    const int64_t n = c - seg_base[sg];
     const int64_t nc = R.ncell;
     int pc[3], lc[3];
     decode_key32(R, (uint32_t)n, pc, lc);
@@ -277,6 +279,30 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_prefix(const RunDev *__rest
     S.tot[n] = tot;
 }
 
+template <int DIM>
+__global__ void __launch_bounds__(kSortBlock) k_sort_prefix(const RunDev *__restrict__ runs,
+                                                            const int64_t *__restrict__ seg_base,
+                                                            const int32_t *__restrict__ seg_run,
+                                                            const int32_t *__restrict__ seg_sp, int n_segs,
+                                                            int64_t total, int cs_sel, uint32_t *err) {
+    const int64_t c0 = (int64_t)blockIdx.x * kSortBlock;
+    const int64_t c = c0 + threadIdx.x;
+    // the segment of the whole workgroup when it lies in one (the usual case:
+    // the run's and species' fields are then read through scalar loads)
+    const int64_t c1 = (c0 + kSortBlock < total ? c0 + kSortBlock : total) - 1;
+    const int sb = find_seg(seg_base, n_segs, c0);
+    const bool one = seg_base[sb + 1] > c1;
+    if (c >= total) return;
+    if (one) {
+        const RunDev &R = runs[seg_run[sb]];
+        prefix_cell<DIM>(R, R.sp[seg_sp[sb]], c - seg_base[sb], cs_sel, err);
+    } else {
+        const int sg = find_seg(seg_base, n_segs, c);
+        const RunDev &R = runs[seg_run[sg]];
+        prefix_cell<DIM>(R, R.sp[seg_sp[sg]], c - seg_base[sg], cs_sel, err);
+    }
+}
+
 // target of the scatter's stores from lanes that have no position
 __device__ int32_t sort_sink;
 
@@ -285,7 +311,7 @@ __device__ int32_t sort_sink;
 // perm[position] = index for 64 consecutive particles at a time, so the
 // particles that stay (one code, consecutive positions) are stored coalesced.
 template <int DIM>
-__global__ void __launch_bounds__(kSortCells) k_sort_scatter(const RunDev *__restrict__ runs,
+__global__ void __launch_bounds__(kSortThreads) k_sort_scatter(const RunDev *__restrict__ runs,
                                                              const ScanSeg *__restrict__ segs,
                                                              const int32_t *__restrict__ block_seg,
                                                              const int32_t *__restrict__ seg_run,
@@ -296,7 +322,7 @@ __global__ void __launch_bounds__(kSortCells) k_sort_scatter(const RunDev *__res
     __shared__ int32_t sb_all[4][65];
     const CellBlock B = cell_block(runs, segs, block_seg, seg_run, seg_sp);
     if (B.cw >= B.ce) return;   // whole wave
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int32_t *tab = tab_all[wave], *sb = sb_all[wave];
     const RunDev &R = *B.R;
     const SpeciesDev &S = *B.S;
@@ -330,7 +356,9 @@ __global__ void __launch_bounds__(kSortCells) k_sort_scatter(const RunDev *__res
     const int32_t n = (int32_t)S.n;
     uint32_t flags = 0;
     bool bad = false;
-    walk_cells<M>(sb, nw, sb[0], sb[nw], (gcptr_u8)S.mc, flags,
+    // the wave's particle range (read from LDS: made scalar explicitly)
+    const int32_t pb = __builtin_amdgcn_readfirstlane(sb[0]), pe = __builtin_amdgcn_readfirstlane(sb[nw]);
+    walk_cells<M>(sb, nw, pb, pe, (gcptr_u8)S.mc, flags,
                   [&](bool valid, int32_t i, int q, int m, int rank, bool last) {
                       const int slot = valid ? m * 64 + q : 0;
                       const int32_t p = tab[slot] + rank;
@@ -455,7 +483,7 @@ hipError_t launch_sort(const Launch &L, const int64_t *seg_base, const int32_t *
     const unsigned grid = (unsigned)((total + kSortBlock - 1) / kSortBlock);
     // scan_tmp: [0, n_scan_blocks) block sums; then the block -> segment table
     const int32_t *block_seg = scan_tmp + n_scan_blocks;
-    const unsigned cgrid = (unsigned)(8 * n_scan_blocks);   // 256-cell blocks
+    const unsigned cgrid = (unsigned)(kSortPerScan * n_scan_blocks);
     // the per (cell, move) counts come from the particle kernel
     if (dim == 3)
         hipLaunchKernelGGL(k_sort_prefix<3>, dim3(grid), dim3(kSortBlock), 0, L.stream, L.runs_dev, seg_base,
@@ -466,10 +494,10 @@ hipError_t launch_sort(const Launch &L, const int64_t *seg_base, const int32_t *
     hipError_t e = launch_scan(segs_dev, n_segs, n_scan_blocks, block_seg, scan_tmp, L.stream);
     if (e != hipSuccess) return e;
     if (dim == 3)
-        hipLaunchKernelGGL(k_sort_scatter<3>, dim3(cgrid), dim3(kSortCells), 0, L.stream, L.runs_dev, segs_dev,
+        hipLaunchKernelGGL(k_sort_scatter<3>, dim3(cgrid), dim3(kSortThreads), 0, L.stream, L.runs_dev, segs_dev,
                            block_seg, seg_run, seg_sp, cs_sel, L.err);
     else
-        hipLaunchKernelGGL(k_sort_scatter<2>, dim3(cgrid), dim3(kSortCells), 0, L.stream, L.runs_dev, segs_dev,
+        hipLaunchKernelGGL(k_sort_scatter<2>, dim3(cgrid), dim3(kSortThreads), 0, L.stream, L.runs_dev, segs_dev,
                            block_seg, seg_run, seg_sp, cs_sel, L.err);
     return hipGetLastError();
 }
