@@ -322,7 +322,8 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
     ctx->off.seg_sp = take(sizeof(int32_t) * ctx->n_segs);
     ctx->off.segs0 = take(sizeof(ScanSeg) * ctx->n_segs);
     ctx->off.segs1 = take(sizeof(ScanSeg) * ctx->n_segs);
-    ctx->off.scan_tmp = take(sizeof(int32_t) * 2 * ctx->n_scan_blocks);
+    // block sums, block -> segment table, partial sums (kScanBlock / 256 per block)
+    ctx->off.scan_tmp = take(sizeof(int32_t) * (2 + kScanBlock / 256) * ctx->n_scan_blocks);
     ctx->off.err = take(sizeof(uint32_t) * 64);
     ctx->max_workers = 256 * 16;
     ctx->off.queue = take(sizeof(int32_t) * 8);

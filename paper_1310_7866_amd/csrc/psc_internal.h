@@ -232,8 +232,8 @@ hipError_t launch_sort(const Launch &L, const int64_t *seg_cell_base_dev, const 
                        const int32_t *seg_species_dev, int n_segs, int64_t total_seg_cells,
                        const ScanSeg *segs_dev, int64_t n_scan_blocks, int32_t *scan_tmp, int cs_sel,
                        int max_dim);
-hipError_t launch_scan(const ScanSeg *segs_dev, int n_segs, int64_t n_blocks,
-                       const int32_t *block_seg_dev, int32_t *block_sums, hipStream_t s);
+hipError_t launch_scan(const ScanSeg *segs_dev, int n_segs, int64_t n_blocks, const int32_t *block_seg_dev,
+                       const int32_t *partial, int32_t *block_sums, hipStream_t s);
 hipError_t launch_keys(const RunDev &r, int64_t n, const int32_t *gcell, int32_t *keys, int32_t *idx,
                        uint32_t *err, hipStream_t s);
 hipError_t launch_keys_to_cells(const RunDev &r, int64_t n, const int32_t *keys, int32_t *cells,

@@ -24,15 +24,6 @@
 
 namespace psc {
 
-__device__ __forceinline__ int find_seg(const int64_t *base, int n, int64_t c) {
-    int lo = 0, hi = n;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (base[mid] <= c) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
 constexpr int kSortBlock = 256;
 
 using gptr_i32 = __attribute__((address_space(1))) int32_t *;
@@ -232,8 +223,8 @@ __device__ __forceinline__ uint32_t key_of(const RunDev &r, int p0, int p1, int 
 // per new cell n of species S of run R: order the source cells by key and
 // assign arrival prefixes
 template <int DIM>
-__device__ __forceinline__ void prefix_cell(const RunDev &R, const SpeciesDev &S, int64_t n, int cs_sel,
-                                            uint32_t *err) {
+__device__ __forceinline__ int32_t prefix_cell(const RunDev &R, const SpeciesDev &S, int64_t n, int cs_sel,
+                                               uint32_t *err) {
     constexpr int M = DIM == 3 ? 27 : 9;
     constexpr int CENTER = M / 2;   // the move that stays in the cell
     const int64_t nc = R.ncell;
@@ -277,29 +268,38 @@ __device__ __forceinline__ void prefix_cell(const RunDev &R, const SpeciesDev &S
     }
     if (tot > 65535) atomicOr(err, PSC_DEV_OVERFULL);
     S.tot[n] = tot;
+    return tot;
 }
+
+// Also the first pass of the scan of the totals: workgroup blk covers the
+// kSortBlock cells blk % kPrefixPerScan of scan block blk / kPrefixPerScan
+// (so it lies in one segment) and writes their sum to partial[blk].
+constexpr int kPrefixPerScan = kScanBlock / kSortBlock;
 
 template <int DIM>
 __global__ void __launch_bounds__(kSortBlock) k_sort_prefix(const RunDev *__restrict__ runs,
-                                                            const int64_t *__restrict__ seg_base,
+                                                            const ScanSeg *__restrict__ segs,
+                                                            const int32_t *__restrict__ block_seg,
                                                             const int32_t *__restrict__ seg_run,
-                                                            const int32_t *__restrict__ seg_sp, int n_segs,
-                                                            int64_t total, int cs_sel, uint32_t *err) {
-    const int64_t c0 = (int64_t)blockIdx.x * kSortBlock;
-    const int64_t c = c0 + threadIdx.x;
-    // the segment of the whole workgroup when it lies in one (the usual case:
-    // the run's and species' fields are then read through scalar loads)
-    const int64_t c1 = (c0 + kSortBlock < total ? c0 + kSortBlock : total) - 1;
-    const int sb = find_seg(seg_base, n_segs, c0);
-    const bool one = seg_base[sb + 1] > c1;
-    if (c >= total) return;
-    if (one) {
-        const RunDev &R = runs[seg_run[sb]];
-        prefix_cell<DIM>(R, R.sp[seg_sp[sb]], c - seg_base[sb], cs_sel, err);
-    } else {
-        const int sg = find_seg(seg_base, n_segs, c);
-        const RunDev &R = runs[seg_run[sg]];
-        prefix_cell<DIM>(R, R.sp[seg_sp[sg]], c - seg_base[sg], cs_sel, err);
+                                                            const int32_t *__restrict__ seg_sp, int cs_sel,
+                                                            int32_t *__restrict__ partial, uint32_t *err) {
+    __shared__ int32_t wsum[kSortBlock / 64];
+    const int64_t blk = blockIdx.x;
+    const int64_t b = blk / kPrefixPerScan;
+    const int sg = block_seg[b];
+    const RunDev &R = runs[seg_run[sg]];
+    const int64_t n = (b - segs[sg].block0) * kScanBlock + (blk - b * kPrefixPerScan) * kSortBlock + threadIdx.x;
+    int32_t tot = 0;
+    if (n < segs[sg].n) tot = prefix_cell<DIM>(R, R.sp[seg_sp[sg]], n, cs_sel, err);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t s = 0;
+#pragma unroll
+        for (int w = 0; w < kSortBlock / 64; ++w) s += wsum[w];
+        partial[blk] = s;
     }
 }
 
@@ -393,25 +393,11 @@ __device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *sh, 
     return r;
 }
 
-__global__ void __launch_bounds__(256) k_scan_reduce(const ScanSeg *__restrict__ segs,
-                                                     const int32_t *__restrict__ block_seg,
-                                                     int32_t *__restrict__ block_sums) {
-    __shared__ int32_t sh[256];
-    const int64_t b = blockIdx.x;
-    const ScanSeg sg = segs[block_seg[b]];
-    const int64_t i0 = (b - sg.block0) * kScanBlock + (int64_t)threadIdx.x * kScanPerThread;
-    int32_t s = 0;
-#pragma unroll
-    for (int q = 0; q < kScanPerThread; ++q)
-        if (i0 + q < sg.n) s += sg.in[i0 + q];
-    int32_t total;
-    block_exclusive_scan(s, sh, total);
-    if (threadIdx.x == 0) block_sums[b] = total;
-}
-
-// one workgroup: segmented exclusive scan of the block sums, in place
+// one workgroup: segmented exclusive scan of the scan blocks' totals (each
+// the sum of its kPrefixPerScan partial sums) into block_sums
 __global__ void __launch_bounds__(1024) k_scan_blocks(const ScanSeg *__restrict__ segs,
                                                       const int32_t *__restrict__ block_seg, int64_t n_blocks,
+                                                      const int32_t *__restrict__ partial,
                                                       int32_t *__restrict__ block_sums) {
     __shared__ int32_t val[1024];
     __shared__ int32_t flg[1024];
@@ -419,7 +405,10 @@ __global__ void __launch_bounds__(1024) k_scan_blocks(const ScanSeg *__restrict_
     int32_t carry = 0;
     for (int64_t cb = 0; cb < n_blocks; cb += 1024) {
         const int64_t b = cb + t;
-        const int32_t v = b < n_blocks ? block_sums[b] : 0;
+        int32_t v = 0;
+        if (b < n_blocks)
+#pragma unroll
+            for (int k = 0; k < kPrefixPerScan; ++k) v += partial[b * kPrefixPerScan + k];
         const int32_t f = b < n_blocks ? (b == segs[block_seg[b]].block0) : 1;
         val[t] = v;
         flg[t] = f;
@@ -450,6 +439,7 @@ __global__ void __launch_bounds__(256) k_scan_final(const ScanSeg *__restrict__ 
     __shared__ int32_t sh[256];
     const int64_t b = blockIdx.x;
     const ScanSeg sg = segs[block_seg[b]];
+    const int32_t offset = block_sums[b];
     const int64_t i0 = (b - sg.block0) * kScanBlock + (int64_t)threadIdx.x * kScanPerThread;
     int32_t v[kScanPerThread];
     int32_t s = 0;
@@ -459,39 +449,41 @@ __global__ void __launch_bounds__(256) k_scan_final(const ScanSeg *__restrict__ 
         s += v[q];
     }
     int32_t total;
-    int32_t run = block_exclusive_scan(s, sh, total) + block_sums[b];
+    int32_t run = block_exclusive_scan(s, sh, total) + offset;
 #pragma unroll
     for (int q = 0; q < kScanPerThread; ++q) {
         if (i0 + q < sg.n) sg.out[i0 + q] = run;
         run += v[q];
     }
     const int64_t blocks = (sg.n + kScanBlock - 1) / kScanBlock;
-    if (threadIdx.x == 255 && b - sg.block0 == blocks - 1) sg.out[sg.n] = block_sums[b] + total;
+    if (threadIdx.x == 255 && b - sg.block0 == blocks - 1) sg.out[sg.n] = offset + total;
 }
 
-hipError_t launch_scan(const ScanSeg *segs, int, int64_t n_blocks, const int32_t *block_seg, int32_t *block_sums,
-                       hipStream_t s) {
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)n_blocks), dim3(256), 0, s, segs, block_seg, block_sums);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, segs, block_seg, n_blocks, block_sums);
+// partial: kPrefixPerScan partial sums per scan block (from k_sort_prefix)
+hipError_t launch_scan(const ScanSeg *segs, int, int64_t n_blocks, const int32_t *block_seg, const int32_t *partial,
+                       int32_t *block_sums, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, segs, block_seg, n_blocks, partial, block_sums);
     hipLaunchKernelGGL(k_scan_final, dim3((unsigned)n_blocks), dim3(256), 0, s, segs, block_seg, block_sums);
     return hipGetLastError();
 }
 
-hipError_t launch_sort(const Launch &L, const int64_t *seg_base, const int32_t *seg_run, const int32_t *seg_sp,
-                       int n_segs, int64_t total, const ScanSeg *segs_dev, int64_t n_scan_blocks,
-                       int32_t *scan_tmp, int cs_sel, int dim) {
-    const unsigned grid = (unsigned)((total + kSortBlock - 1) / kSortBlock);
-    // scan_tmp: [0, n_scan_blocks) block sums; then the block -> segment table
+hipError_t launch_sort(const Launch &L, const int64_t *, const int32_t *seg_run, const int32_t *seg_sp, int n_segs,
+                       int64_t, const ScanSeg *segs_dev, int64_t n_scan_blocks, int32_t *scan_tmp, int cs_sel,
+                       int dim) {
+    // scan_tmp: [0, n_scan_blocks) block sums; then the block -> segment
+    // table; then kPrefixPerScan partial sums per scan block
     const int32_t *block_seg = scan_tmp + n_scan_blocks;
+    int32_t *partial = scan_tmp + 2 * n_scan_blocks;
+    const unsigned grid = (unsigned)(kPrefixPerScan * n_scan_blocks);
     const unsigned cgrid = (unsigned)(kSortPerScan * n_scan_blocks);
     // the per (cell, move) counts come from the particle kernel
     if (dim == 3)
-        hipLaunchKernelGGL(k_sort_prefix<3>, dim3(grid), dim3(kSortBlock), 0, L.stream, L.runs_dev, seg_base,
-                           seg_run, seg_sp, n_segs, total, cs_sel, L.err);
+        hipLaunchKernelGGL(k_sort_prefix<3>, dim3(grid), dim3(kSortBlock), 0, L.stream, L.runs_dev, segs_dev,
+                           block_seg, seg_run, seg_sp, cs_sel, partial, L.err);
     else
-        hipLaunchKernelGGL(k_sort_prefix<2>, dim3(grid), dim3(kSortBlock), 0, L.stream, L.runs_dev, seg_base,
-                           seg_run, seg_sp, n_segs, total, cs_sel, L.err);
-    hipError_t e = launch_scan(segs_dev, n_segs, n_scan_blocks, block_seg, scan_tmp, L.stream);
+        hipLaunchKernelGGL(k_sort_prefix<2>, dim3(grid), dim3(kSortBlock), 0, L.stream, L.runs_dev, segs_dev,
+                           block_seg, seg_run, seg_sp, cs_sel, partial, L.err);
+    hipError_t e = launch_scan(segs_dev, n_segs, n_scan_blocks, block_seg, partial, scan_tmp, L.stream);
     if (e != hipSuccess) return e;
     if (dim == 3)
         hipLaunchKernelGGL(k_sort_scatter<3>, dim3(cgrid), dim3(kSortThreads), 0, L.stream, L.runs_dev, segs_dev,
