@@ -326,7 +326,7 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
     ctx->off.scan_tmp = take(sizeof(int32_t) * (2 + kScanBlock / 256) * ctx->n_scan_blocks);
     ctx->off.err = take(sizeof(uint32_t) * 64);
     ctx->max_workers = 256 * 16;
-    ctx->off.queue = take(sizeof(int32_t) * 8);
+    ctx->off.queue = take(sizeof(int32_t) * 8 * kQueueStride);
     ctx->off.part = take(sizeof(int32_t) * (ctx->max_workers + 1));
     ctx->off.unit_counts = take(sizeof(int32_t) * ctx->units.size());
     ctx->off.load_keys = take(sizeof(int32_t) * ctx->max_cap);

@@ -206,6 +206,9 @@ struct Launch {
     uint32_t *err;            // device error word
 };
 
+// the persistent particle kernel's 8 queue counters, one per 128-byte line
+constexpr int kQueueStride = 32;
+
 // how the particle kernel is launched: 0 one workgroup per work item,
 // 1 persistent workgroups with per-XCD queues, 2 persistent workgroups over a
 // load-balanced partition of the units

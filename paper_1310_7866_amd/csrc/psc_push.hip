@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(1024) k_build_items(const RunDev *__restrict__
     __shared__ int32_t part[1024];
     // reset the work queues of the persistent launch (written before the
     // particle kernel starts: same stream)
-    if (queue && threadIdx.x < 8) queue[threadIdx.x] = 0;
+    if (queue && threadIdx.x < 8) queue[kQueueStride * threadIdx.x] = 0;
     const int t = threadIdx.x;
     const int per = (n_units + 1023) / 1024;
     const int u0 = t * per, u1 = imin(u0 + per, n_units);
@@ -1045,7 +1045,14 @@ __global__ void __launch_bounds__(NT) PSC_OCCUPANCY k_push_queue(const RunDev *_
         const int q = (xcd + k) & 7;
         const int qb = (int)((int64_t)q * total / 8), qe = (int)((int64_t)(q + 1) * total / 8);
         for (;;) {
-            if (threadIdx.x == 0) s_item = qb + atomicAdd(&queue[q], 1);
+            if (threadIdx.x == 0) {
+                // a drained queue is skipped without an atomic (the counter
+                // only grows; a stale read just leads to the atomic)
+                int32_t *ctr = &queue[kQueueStride * q];
+                s_item = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= qe - qb
+                             ? qe
+                             : qb + atomicAdd(ctr, 1);
+            }
             __syncthreads();
             const int item = s_item;
             __syncthreads();

@@ -371,7 +371,8 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(const RunDev *__r
                       *dst = i;
                       if (valid && last) tab[slot] = p + 1;
                   });
-    if (bad) atomicOr(err, PSC_DEV_OVERFULL);
+    if (bad) flags |= PSC_DEV_OVERFULL;
+    if (flags) atomicOr(err, flags);   // also an invalid move code (PSC_DEV_MOVE)
 }
 
 // ---------------------------------------------------------------------------
