@@ -29,25 +29,33 @@ constexpr int kSortBlock = 256;
 using gptr_i32 = __attribute__((address_space(1))) int32_t *;
 using gcptr_u8 = const __attribute__((address_space(1))) uint8_t *;
 
-// Scatter: a workgroup owns 4 kWaveCells consecutive old cells of one
-// segment, each of its four waves kWaveCells of them (lane q: cell cw + q),
+// Scatter: a workgroup owns 4 wave_cells consecutive old cells of one
+// segment, each of its four waves wave_cells of them (lane q: cell cw + q),
 // i.e. one contiguous range of particles (the buffer is ordered by old
 // cell).  The wave walks that range 64 particles at a time with coalesced
 // loads.  Each lane finds its particle's cell from the cells' first indices;
 // its rank among the earlier particles of the same cell and move code is the
 // population count of the code's ballot restricted to the lanes of its cell
 // below it; the last such lane advances the (cell, code) counter kept in
-// LDS.  Sort block b lies in scan block b / kSortPerScan of the same
+// LDS.  Sort block b lies in scan block b / sort_per_scan of the same
 // segment, whose table gives the segment.  Fewer cells per wave give more,
-// shorter waves, which balances dense and sparse regions better.
-#ifndef PSC_SORT_WAVE_CELLS
-#define PSC_SORT_WAVE_CELLS 32
+// shorter waves, which balances dense and sparse regions better (2-d: 32
+// cells); in 3-d a wave's set-up covers 27 move codes per cell, and 64
+// cells per wave measured faster.
+#ifndef PSC_SORT_WAVE_CELLS_2D
+#define PSC_SORT_WAVE_CELLS_2D 32
 #endif
-constexpr int kSortThreads = 256;                      // four waves
-constexpr int kWaveCells = PSC_SORT_WAVE_CELLS;        // old cells per wave
-constexpr int kSortCells = 4 * kWaveCells;             // old cells per workgroup
-constexpr int kSortPerScan = kScanBlock / kSortCells;  // workgroups per scan block
-static_assert(kWaveCells >= 1 && kWaveCells <= 64 && kScanBlock % kSortCells == 0, "sort geometry");
+#ifndef PSC_SORT_WAVE_CELLS_3D
+#define PSC_SORT_WAVE_CELLS_3D 64
+#endif
+constexpr int kSortThreads = 256;   // four waves
+template <int DIM>
+constexpr int wave_cells() { return DIM == 3 ? PSC_SORT_WAVE_CELLS_3D : PSC_SORT_WAVE_CELLS_2D; }
+template <int DIM>
+constexpr int sort_per_scan() { return kScanBlock / (4 * wave_cells<DIM>()); }   // workgroups per scan block
+static_assert(wave_cells<2>() >= 1 && wave_cells<2>() <= 64 && kScanBlock % (4 * wave_cells<2>()) == 0 &&
+                  wave_cells<3>() >= 1 && wave_cells<3>() <= 64 && kScanBlock % (4 * wave_cells<3>()) == 0,
+              "sort geometry");
 
 struct CellBlock {
     const RunDev *R;
@@ -55,17 +63,19 @@ struct CellBlock {
     int64_t cw, ce;   // this wave's cells [cw, ce)
 };
 
+template <int DIM>
 __device__ __forceinline__ CellBlock cell_block(const RunDev *runs, const ScanSeg *segs, const int32_t *block_seg,
                                                 const int32_t *seg_run, const int32_t *seg_sp) {
     CellBlock B;
-    const int sg = block_seg[blockIdx.x / kSortPerScan];
+    constexpr int WC = wave_cells<DIM>(), SPS = sort_per_scan<DIM>();
+    const int sg = block_seg[blockIdx.x / SPS];
     B.R = &runs[seg_run[sg]];
     B.S = &B.R->sp[seg_sp[sg]];
     // the wave index as a scalar: the walk's bounds, loop counters and cell
     // masks then live in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    B.cw = ((int64_t)blockIdx.x - kSortPerScan * segs[sg].block0) * kSortCells + kWaveCells * wave;
-    B.ce = B.cw + kWaveCells < B.R->ncell ? B.cw + kWaveCells : B.R->ncell;
+    B.cw = ((int64_t)blockIdx.x - SPS * segs[sg].block0) * (4 * WC) + WC * wave;
+    B.ce = B.cw + WC < B.R->ncell ? B.cw + WC : B.R->ncell;
     return B;
 }
 
@@ -320,7 +330,7 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(const RunDev *__r
     constexpr int M = DIM == 3 ? 27 : 9;
     __shared__ int32_t tab_all[4][64 * M];
     __shared__ int32_t sb_all[4][65];
-    const CellBlock B = cell_block(runs, segs, block_seg, seg_run, seg_sp);
+    const CellBlock B = cell_block<DIM>(runs, segs, block_seg, seg_run, seg_sp);
     if (B.cw >= B.ce) return;   // whole wave
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int32_t *tab = tab_all[wave], *sb = sb_all[wave];
@@ -476,7 +486,7 @@ hipError_t launch_sort(const Launch &L, const int64_t *, const int32_t *seg_run,
     const int32_t *block_seg = scan_tmp + n_scan_blocks;
     int32_t *partial = scan_tmp + 2 * n_scan_blocks;
     const unsigned grid = (unsigned)(kPrefixPerScan * n_scan_blocks);
-    const unsigned cgrid = (unsigned)(kSortPerScan * n_scan_blocks);
+    const unsigned cgrid = (unsigned)((dim == 3 ? sort_per_scan<3>() : sort_per_scan<2>()) * n_scan_blocks);
     // the per (cell, move) counts come from the particle kernel
     if (dim == 3)
         hipLaunchKernelGGL(k_sort_prefix<3>, dim3(grid), dim3(kSortBlock), 0, L.stream, L.runs_dev, segs_dev,
