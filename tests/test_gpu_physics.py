@@ -113,8 +113,7 @@ def test_plasma_frequency_gpu(order):
     assert abs(omega - want) <= 1e-5 * want
 
 
-def test_batch_equals_runs_alone():
-    runs = [_charged(1, seed=20 + r, ny=16 + 8 * r, nz=12 + 4 * r, patch=8, ppc=4 + 2 * r) for r in range(3)]
+def _batch_vs_alone(runs):
     batch = _sim(runs)
     alone = [_sim(r) for r in runs]
     for _ in range(4):
@@ -133,6 +132,20 @@ def test_batch_equals_runs_alone():
         Eb, Bb, _ = batch.field_arrays(r)
         Ea, Ba, _ = a.field_arrays(0)
         assert np.abs(Eb - Ea).max() <= 1e-6 * max(np.abs(Ea).max(), 1e-30)
+
+
+def test_batch_equals_runs_alone():
+    _batch_vs_alone([_charged(1, seed=20 + r, ny=16 + 8 * r, nz=12 + 4 * r, patch=8, ppc=4 + 2 * r)
+                     for r in range(3)])
+
+
+def test_batch_mixing_fold_paths_equals_runs_alone():
+    # order 2 (current halo 3 cells): 18 = 8 + 8 + 2 leaves a last patch
+    # narrower than the halo, folded with the alias search; the other run's
+    # patches are all wide enough for the per-patch fold.  One batch launches
+    # both fold kernels.
+    _batch_vs_alone([_charged(2, seed=41, ny=18, nz=12, patch=8, ppc=6),
+                     _charged(2, seed=42, ny=24, nz=16, patch=8, ppc=6)])
 
 
 def test_patch_size_independence():
