@@ -264,6 +264,58 @@ def deposit_leg(steps: int = 10):
     return out
 
 
+def deposit_ablation_leg(steps: int = 10):
+    """The 1st-order Villasenor-Buneman particle kernel on the thermal 2-d
+    workload (1024x512 cells, 16 electron-ion pairs per cell) with 4x4, 8x8
+    and 16x16 super-cells, one particle per lane.  The library it runs is
+    whichever PSC_LIBRARY names: built with -DPSC_FRAMES=0 (per-lane LDS
+    atomics), -DPSC_JCOPIES=16 (redundant tiles) and -DPSC_MIX=1 (lanes
+    spread over the item's cells) it measures the shared-memory deposit
+    variants against the frames of the default build.  A super-cell size
+    whose tiles do not fit in LDS is reported as null."""
+    import torch
+    from paper_1310_7866_amd import cases
+    from paper_1310_7866_amd.psc import B_HALF, E_FULL, PscError, PscSim
+    out = {}
+    for P in (4, 8, 16):
+        case = cases.thermal2d(ny=1024, nz=512, ppc=16, order=1, patch=P)
+        case.deposit = "vb"
+        sim = None
+        try:
+            sim = PscSim(case, with_ids=False)
+            sim.set_launch(mode=1, chunk=4096, threads=256, run=1)
+        except PscError as e:
+            print(f"[bench] ablation {P}x{P}: {e}", file=sys.stderr, flush=True)
+            out[f"{P}x{P}"] = None
+            if sim is not None:
+                sim.close()
+            continue
+        stream = torch.cuda.current_stream()
+        sim.step(3)
+        ev = lambda: torch.cuda.Event(enable_timing=True)
+        pe = [(ev(), ev()) for _ in range(steps)]
+        torch.cuda.synchronize()
+        for k in range(steps):
+            sim.push_fields(B_HALF)
+            pe[k][0].record(stream)
+            sim.push_particles()
+            pe[k][1].record(stream)
+            sim.push_fields(B_HALF)
+            sim.deposit_current()
+            sim.push_fields(E_FULL)
+            sim.sort()
+        torch.cuda.synchronize()
+        sim.check()
+        ms = sum(a.elapsed_time(b) for a, b in pe) / steps
+        out[f"{P}x{P}"] = dict(push_ms=round(ms, 4), pushes_per_s=case.n_particles / (ms / 1e3))
+        print(f"[bench] ablation {P}x{P}: push {ms:.3f} ms", file=sys.stderr, flush=True)
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    return dict(workload=f"thermal2d 1024x512, order 1, VB deposit, {case.n_particles} particles, run 1",
+                library=os.environ.get("PSC_LIBRARY", "in-tree"), supercells=out)
+
+
 def adjoint_leg(every: int = 10, nsteps: int = 50):
     """Gradient of the final field energy on the 256 x 256 double Harris sheet
     (64 particles per cell at n = 1, 2nd order, 32 x 32 patches): forward with
@@ -355,7 +407,8 @@ def main():
                     help="oracle baseline on every n-th particle (1: the whole Harris workload, about 18 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the adjoint and batch legs")
-    ap.add_argument("--only", choices=("adjoint", "batch", "supercells", "marder", "deposit"), default=None,
+    ap.add_argument("--only", choices=("adjoint", "batch", "supercells", "marder", "deposit", "ablation"),
+                    default=None,
                     help="run only the adjoint or the batch leg and print its JSON")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--launch", default="", help="fixed launch shape mode,chunk,threads,run (skips tuning)")
@@ -387,6 +440,9 @@ def main():
         return
     if args.only == "deposit":
         print(json.dumps({"deposit": deposit_leg()}))
+        return
+    if args.only == "ablation":
+        print(json.dumps({"deposit_ablation": deposit_ablation_leg()}))
         return
 
     if args.calibrate:

@@ -34,6 +34,21 @@ namespace psc {
 #ifndef PSC_FRAMES
 #define PSC_FRAMES 1
 #endif
+//   PSC_JCOPIES      redundant copies of the LDS current tile for the
+//                    per-lane atomic deposit: lane l adds into copy l mod N,
+//                    the flush sums them (with PSC_FRAMES 0: the ablation of
+//                    shared-memory copies against atomic conflicts)
+#ifndef PSC_JCOPIES
+#define PSC_JCOPIES 1
+#endif
+//   PSC_MIX          1: lane g of a work item takes particle
+//                    (g mod 64) ceil(n / 64) + g div 64 of its n (one
+//                    particle per lane), so a wave's lanes are spread over
+//                    the item's cells instead of consecutive (with
+//                    PSC_FRAMES 0: the ablation of mixing within super-cells)
+#ifndef PSC_MIX
+#define PSC_MIX 0
+#endif
 //   PSC_BAND         0 stages and flushes the whole patch tile for every
 //                    work item instead of the band of planes its particles reach
 #ifndef PSC_BAND
@@ -59,6 +74,9 @@ constexpr int push_waves() {
 }
 #define PSC_OCCUPANCY __attribute__((amdgpu_waves_per_eu(push_waves<DIM, ORDER, RUNS>())))
 constexpr int kScanWidth = PSC_SCAN_WIDTH;
+constexpr int kJCopies = PSC_JCOPIES;
+static_assert(kJCopies >= 1 && (kJCopies == 1 || !PSC_FRAMES), "redundant tiles only for the per-lane deposit");
+static_assert(!PSC_MIX || !PSC_FRAMES, "mixed lanes only for the per-lane deposit");
 constexpr int kQueueSlots = PSC_QUEUE_SLOTS;
 constexpr int kPackTails = PSC_PACK_TAILS;
 static_assert(kQueueSlots >= 1 && kQueueSlots <= 64, "queue slots 1..64");
@@ -78,7 +96,7 @@ __host__ __device__ inline PushLds push_lds_layout(int fcells, int jcells, int w
                                                    int twords) {
     PushLds L{};
     L.cur = align4(6 * fcells);
-    L.queue = align4(L.cur + 6 * jcells);   // current tile in doubles
+    L.queue = align4(L.cur + 6 * jcells * kJCopies);   // current tile(s) in doubles
     L.stage = align4(L.queue + waves * qwords);
     L.table = align4(L.stage + waves * align4(swords));
     L.total = L.table + twords;
@@ -422,9 +440,13 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
     const int ox = pc[0] * R.P[0], oy = pc[1] * R.P[1], oz = pc[2] * R.P[2];
     const int64_t kb = patch_key_base(R, pc[0], pc[1], pc[2]);
     const int32_t *cs = S.cs[cs_sel];
-    const int32_t pbeg = cs[kb], pend = cs[kb + pcells];
+    // cell offsets outside [0, n] (only after a counter overflow, which the
+    // sort flags) must not send the item outside the particle buffers
+    const int32_t np_ = (int32_t)S.n;
+    const int32_t pend = imin(imax(cs[kb + pcells], 0), np_), pbeg = imin(imax(cs[kb], 0), pend);
     const int32_t beg = pbeg + (item - item_start[lo]) * chunk;
     const int32_t end = min(beg + chunk, pend);
+    if (beg >= end) return;   // only with such offsets (the workgroup's item is uniform)
 
     // tile geometry (nominal patch size so every tile of the run has one pitch)
     const int fx = DIM == 3 ? R.P[0] + FLO + FHI : 1;
@@ -509,7 +531,8 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
         }
         for (int q = threadIdx.x; q < 3 * n_jband; q += NT) {
             const int c = q / n_jband;
-            jtile[c * jcells + jr0 * jplane + (q - c * n_jband)] = 0.0;
+#pragma unroll
+            for (int cp = 0; cp < kJCopies; ++cp) jtile[(3 * cp + c) * jcells + jr0 * jplane + (q - c * n_jband)] = 0.0;
         }
     }
     __syncthreads();
@@ -549,14 +572,15 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
     // out-of-plane frame current drops the path-average term
     const bool vb = ORDER == 1 && R.vb;
     const float x12 = vb ? 0.0f : 1.0f / 12.0f;
+    double *jlane = jtile + (kJCopies > 1 ? (lane % kJCopies) * 3 * jcells : 0);   // this lane's copy
     auto deposit_one = [&](int lx_, int ly_, int lz_, const float *a0, const int *qs, const float *a1, float fx_) {
         if constexpr (ORDER == 1) {
             if (vb) {
-                deposit_lane_vb<DIM>(jtile, jcells, jx_, jy_, lx_, ly_, lz_, a0, qs, a1, jfx, jfy, jfz, fx_);
+                deposit_lane_vb<DIM>(jlane, jcells, jx_, jy_, lx_, ly_, lz_, a0, qs, a1, jfx, jfy, jfz, fx_);
                 return;
             }
         }
-        deposit_lane<DIM, ORDER>(jtile, jcells, jx_, jy_, lx_, ly_, lz_, a0, qs, a1, jfx, jfy, jfz, fx_);
+        deposit_lane<DIM, ORDER>(jlane, jcells, jx_, jy_, lx_, ly_, lz_, a0, qs, a1, jfx, jfy, jfz, fx_);
     };
 
     // deposit queued particles [0, n) of this wave, one per lane
@@ -583,7 +607,11 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
     // wave operations need all 64 lanes); lanes without a particle carry zero
     // current and write nothing
     for (int32_t r0 = 0; r0 < nruns; r0 += NT) {
-        const int32_t g = r0 + (int32_t)threadIdx.x;
+        int32_t g = r0 + (int32_t)threadIdx.x;
+        if constexpr (PSC_MIX && !RUNS) {   // ablation only: a bijection of [0, 64 ceil(n/64))
+            const int32_t M = (nruns + 63) >> 6;
+            g = g < 64 * M ? (g & 63) * M + (g >> 6) : nruns;
+        }
         const int32_t first = beg + g * K;                       // this lane's strip
         const int32_t len = g < nruns ? imin(K, end - first) : 0;
         int c = 0, cf = -1;   // particle's cell, cell of the lane's frame
@@ -1005,7 +1033,9 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
     for (int q = threadIdx.x; q < 3 * n_jband; q += NT) {
         const int c = q / n_jband;
         const int t = c * jcells + jr0 * jplane + (q - c * n_jband);
-        const double v = jtile[t];
+        double v = jtile[t];
+#pragma unroll
+        for (int cp = 1; cp < kJCopies; ++cp) v += jtile[3 * cp * jcells + t];
         if (v != 0.0) atomicAdd(&gt[t], (float)v);
     }
     __syncthreads();

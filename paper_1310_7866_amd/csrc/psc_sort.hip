@@ -366,8 +366,10 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(const RunDev *__r
     const int32_t n = (int32_t)S.n;
     uint32_t flags = 0;
     bool bad = false;
-    // the wave's particle range (read from LDS: made scalar explicitly)
-    const int32_t pb = __builtin_amdgcn_readfirstlane(sb[0]), pe = __builtin_amdgcn_readfirstlane(sb[nw]);
+    // the wave's particle range (read from LDS: made scalar explicitly),
+    // kept inside [0, n] also for offsets corrupted by a counter overflow
+    const int32_t pe = imin(imax(__builtin_amdgcn_readfirstlane(sb[nw]), 0), n);
+    const int32_t pb = imin(imax(__builtin_amdgcn_readfirstlane(sb[0]), 0), pe);
     walk_cells<M>(sb, nw, pb, pe, (gcptr_u8)S.mc, flags,
                   [&](bool valid, int32_t i, int q, int m, int rank, bool last) {
                       const int slot = valid ? m * 64 + q : 0;
