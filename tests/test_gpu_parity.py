@@ -155,6 +155,34 @@ def test_graph_replay_matches_eager(use_graph):
     assert np.abs(Ea - Eb).max() <= 1e-5 * np.abs(Ea).max()
 
 
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_step_matches_separate_calls(use_graph):
+    # psc_step (eager or replayed from a graph) against the separate entry
+    # points called in the order of fig. psc_new: the same state (keys
+    # exactly; values to the summation-order tolerance of the float tile
+    # atomics)
+    from paper_1310_7866_amd.psc import B_HALF, E_FULL
+    c = _small_2d(2, seed=23, ny=40, nz=24)
+    a = _sim(c)
+    b = _sim(c)
+    for k in range(4):
+        a.step(1, use_graph=use_graph)
+        b.push_fields(B_HALF)
+        b.push_particles()
+        b.push_fields(B_HALF)
+        b.deposit_current()
+        b.push_fields(E_FULL)
+        b.sort()
+        assert a.check() == 0 and b.check() == 0
+        for s in range(len(c.species)):
+            pa, pb = a.particles(0, s), b.particles(0, s)
+            assert np.array_equal(pa["key"], pb["key"])
+            assert np.abs(pa["u"] - pb["u"]).max() <= 1e-5
+    for q in range(3):
+        fa, fb = a.field_arrays(0)[q], b.field_arrays(0)[q]
+        assert np.abs(fa - fb).max() <= 1e-5 * max(np.abs(fa).max(), 1e-30)
+
+
 def test_nonfinite_momentum_flagged():
     c = _small_2d(1, seed=3)
     c.species[0].u[0, 5] = np.float32(np.nan)
