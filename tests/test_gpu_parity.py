@@ -138,6 +138,27 @@ def test_steps_match_oracle(kind, order):
     assert np.abs(B.ravel() - ora.B).max() <= 1e-4 * np.abs(ora.B).max()
 
 
+@pytest.mark.parametrize("order", [1, 2])
+def test_steps_match_oracle_3d_patch_fold(order):
+    # every patch 4 wide (at least the current halo at both orders): the 3-d
+    # run folds its current tiles by patch, which the default 3-d case (with
+    # narrower last patches) does not reach
+    c = _small_3d(order, seed=18, nxyz=(8, 8, 12), patch=4, ppc=3)
+    sim = _sim(c)
+    ora = O.OracleSim(c)
+    for _ in range(3):
+        sim.step(1)
+        ora.step(1)
+    assert sim.check() == 0
+    for s, sp in enumerate(c.species):
+        dpos, du = particle_errors(c, sim.particles(0, s), ora, s, float(np.std(sp.u)))
+        assert dpos <= 1e-5 and du <= 1e-4, (s, dpos, du)
+    E, B, J = sim.field_arrays(0)
+    assert np.abs(J.ravel() - ora.J).max() <= 1e-4 * np.abs(ora.J).max()
+    assert np.abs(E.ravel() - ora.E).max() <= 1e-4 * np.abs(ora.E).max()
+    assert np.abs(B.ravel() - ora.B).max() <= 1e-4 * np.abs(ora.B).max()
+
+
 @pytest.mark.parametrize("use_graph", [False, True])
 def test_graph_replay_matches_eager(use_graph):
     c = _small_2d(2, seed=21)
