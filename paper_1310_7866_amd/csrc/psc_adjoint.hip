@@ -160,23 +160,46 @@ __device__ __forceinline__ int find_run_a(const int64_t *base, int n_runs, int64
     return lo;
 }
 
+// Call f(R, A, idx) for cell c of the flat cell space; R and A are uniform
+// over the workgroup (scalar loads) when all its cells lie in one run.
+template <typename F>
+__device__ __forceinline__ void with_run_adj(const RunDev *runs, const AdjRun *adj, const int64_t *base, int n_runs,
+                                             int64_t total, F &&f) {
+    const int64_t c0 = (int64_t)blockIdx.x * blockDim.x, c = c0 + threadIdx.x;
+    const int64_t c1 = (c0 + blockDim.x < total ? c0 + blockDim.x : total) - 1;
+    const int rb = find_run_a(base, n_runs, c0);
+    const bool one = base[rb + 1] > c1;
+    if (c >= total) return;
+    if (one) {
+        f(runs[rb], adj[rb], c - base[rb]);
+    } else {
+        const int r = find_run_a(base, n_runs, c);
+        f(runs[r], adj[r], c - base[r]);
+    }
+}
+
+// grid coordinates of cell idx of a run (32-bit: fewer than 2^31 cells)
+__device__ __forceinline__ void adj_grid_coords(const RunDev &R, int64_t idx, int g[3]) {
+    const uint32_t id = (uint32_t)idx, nx = (uint32_t)R.n[0], ny = (uint32_t)R.n[1];
+    const uint32_t q = R.dim == 3 ? id / nx : id;
+    g[0] = (int)(id - q * nx);
+    const uint32_t k = q / ny;
+    g[1] = (int)(q - k * ny);
+    g[2] = (int)k;
+}
+
 // op 0: LJ = -dt lE ; lB += dt curl^+ lE
 // op 1: lE -= dt/2 curl^- lB ; B1 = B - dt/2 curl^+ E
 // op 2: lE -= dt/2 curl^- lB
-__global__ void __launch_bounds__(256) k_adj_fields(const RunDev *__restrict__ runs, const AdjRun *__restrict__ adj,
-                                                    int n_runs, const int64_t *__restrict__ run_base, int64_t total,
-                                                    int op) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= total) return;
-    const int r = find_run_a(run_base, n_runs, c);
-    const RunDev &R = runs[r];
-    const AdjRun &A = adj[r];
-    const int64_t idx = c - R.cell_base;
+// Every load of a cell before its stores; in 2-d the x neighbours are the
+// cell itself and ix is zero, so their terms are zero.
+__device__ __forceinline__ void adj_field_cell(const RunDev &R, const AdjRun &A, int64_t idx, int op) {
     const int nx = R.n[0], ny = R.n[1], nz = R.n[2];
-    const int i = (int)(idx % nx), j = (int)((idx / nx) % ny), k = (int)(idx / ((int64_t)nx * ny));
+    int g[3];
+    adj_grid_coords(R, idx, g);
+    const int i = g[0], j = g[1], k = g[2];
     const int64_t nc = R.ncell;
-    const bool three = R.dim == 3;
-    const float ix = three ? R.inv_dx[0] : 0.0f, iy = R.inv_dx[1], iz = R.inv_dx[2];
+    const float ix = R.dim == 3 ? R.inv_dx[0] : 0.0f, iy = R.inv_dx[1], iz = R.inv_dx[2];
     const int64_t sy = nx, sz = (int64_t)nx * ny;
     const int64_t ip = i + 1 < nx ? idx + 1 : idx - (nx - 1);
     const int64_t jp = j + 1 < ny ? idx + sy : idx - (int64_t)(ny - 1) * sy;
@@ -186,36 +209,58 @@ __global__ void __launch_bounds__(256) k_adj_fields(const RunDev *__restrict__ r
     const int64_t km = k > 0 ? idx - sz : idx + (int64_t)(nz - 1) * sz;
     auto curl_plus = [&](const float *F, float &cx, float &cy, float &cz) {
         const float fx = F[idx], fy = F[nc + idx], fz = F[2 * nc + idx];
-        cx = (F[2 * nc + jp] - fz) * iy - (F[nc + kp] - fy) * iz;
-        cy = (F[kp] - fx) * iz - (three ? (F[2 * nc + ip] - fz) * ix : 0.0f);
-        cz = (three ? (F[nc + ip] - fy) * ix : 0.0f) - (F[jp] - fx) * iy;
+        const float fz_j = F[2 * nc + jp], fy_k = F[nc + kp], fx_k = F[kp], fz_i = F[2 * nc + ip], fy_i = F[nc + ip],
+                    fx_j = F[jp];
+        cx = (fz_j - fz) * iy - (fy_k - fy) * iz;
+        cy = (fx_k - fx) * iz - (fz_i - fz) * ix;
+        cz = (fy_i - fy) * ix - (fx_j - fx) * iy;
     };
     auto curl_minus = [&](const float *F, float &cx, float &cy, float &cz) {
         const float fx = F[idx], fy = F[nc + idx], fz = F[2 * nc + idx];
-        cx = (fz - F[2 * nc + jm]) * iy - (fy - F[nc + km]) * iz;
-        cy = (fx - F[km]) * iz - (three ? (fz - F[2 * nc + im]) * ix : 0.0f);
-        cz = (three ? (fy - F[nc + im]) * ix : 0.0f) - (fx - F[jm]) * iy;
+        const float fz_j = F[2 * nc + jm], fy_k = F[nc + km], fx_k = F[km], fz_i = F[2 * nc + im], fy_i = F[nc + im],
+                    fx_j = F[jm];
+        cx = (fz - fz_j) * iy - (fy - fy_k) * iz;
+        cy = (fx - fx_k) * iz - (fz - fz_i) * ix;
+        cz = (fy - fy_i) * ix - (fx - fx_j) * iy;
     };
     const float dt = R.dt;
     float cx, cy, cz;
     if (op == 0) {
         curl_plus(A.lE, cx, cy, cz);
-        for (int q = 0; q < 3; ++q) A.LJ[q * nc + idx] = -dt * A.lE[q * nc + idx];
-        A.lB[idx] += dt * cx;
-        A.lB[nc + idx] += dt * cy;
-        A.lB[2 * nc + idx] += dt * cz;
+        const float e0 = A.lE[idx], e1 = A.lE[nc + idx], e2 = A.lE[2 * nc + idx];
+        const float b0 = A.lB[idx], b1 = A.lB[nc + idx], b2 = A.lB[2 * nc + idx];
+        A.LJ[idx] = -dt * e0;
+        A.LJ[nc + idx] = -dt * e1;
+        A.LJ[2 * nc + idx] = -dt * e2;
+        A.lB[idx] = b0 + dt * cx;
+        A.lB[nc + idx] = b1 + dt * cy;
+        A.lB[2 * nc + idx] = b2 + dt * cz;
     } else {
         curl_minus(A.lB, cx, cy, cz);
-        A.lE[idx] -= 0.5f * dt * cx;
-        A.lE[nc + idx] -= 0.5f * dt * cy;
-        A.lE[2 * nc + idx] -= 0.5f * dt * cz;
+        float ex = 0.0f, ey = 0.0f, ez = 0.0f, bx = 0.0f, by = 0.0f, bz = 0.0f;
+        const float e0 = A.lE[idx], e1 = A.lE[nc + idx], e2 = A.lE[2 * nc + idx];
         if (op == 1) {
-            curl_plus(A.E, cx, cy, cz);
-            A.B1[idx] = A.B[idx] - 0.5f * dt * cx;
-            A.B1[nc + idx] = A.B[nc + idx] - 0.5f * dt * cy;
-            A.B1[2 * nc + idx] = A.B[2 * nc + idx] - 0.5f * dt * cz;
+            curl_plus(A.E, ex, ey, ez);
+            bx = A.B[idx];
+            by = A.B[nc + idx];
+            bz = A.B[2 * nc + idx];
+        }
+        A.lE[idx] = e0 - 0.5f * dt * cx;
+        A.lE[nc + idx] = e1 - 0.5f * dt * cy;
+        A.lE[2 * nc + idx] = e2 - 0.5f * dt * cz;
+        if (op == 1) {
+            A.B1[idx] = bx - 0.5f * dt * ex;
+            A.B1[nc + idx] = by - 0.5f * dt * ey;
+            A.B1[2 * nc + idx] = bz - 0.5f * dt * ez;
         }
     }
+}
+
+__global__ void __launch_bounds__(256) k_adj_fields(const RunDev *__restrict__ runs, const AdjRun *__restrict__ adj,
+                                                    int n_runs, const int64_t *__restrict__ run_base, int64_t total,
+                                                    int op) {
+    with_run_adj(runs, adj, run_base, n_runs, total,
+                 [&](const RunDev &R, const AdjRun &A, int64_t idx) { adj_field_cell(R, A, idx, op); });
 }
 
 // move the incoming particle adjoints (next step's sorted order) to this
@@ -613,8 +658,92 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles(const RunDev *__res
 }
 
 // fold the transposed-interpolation tiles (field-tile geometry) into lE, lB
+// Runs whose patches are all at least as wide as the current halo (so also
+// as the field tile's): per dimension the patch below (when l < hi), the
+// own patch and the patch above (when l >= ext - lo), every load issued
+// before the sums and the clearing stores, as in the forward fold.
+__device__ __forceinline__ void adj_fold_direct(const RunDev &R, const AdjRun &A, int64_t idx) {
+    int g3[3];
+    adj_grid_coords(R, idx, g3);
+    const int l0[2] = {g3[1], g3[2]};   // 2-d: (y, z)
+    const int lo = 1, hi = R.order;
+    const int fy = R.P[1] + lo + hi, fz = R.P[2] + lo + hi;
+    const int64_t fcells = (int64_t)fy * fz;
+    int pcs[2][3], ls[2][3];
+    bool on[2][3];
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+        const int P = R.P[d + 1], n = R.n[d + 1], np = R.np[d + 1];
+        const int pc = l0[d] / P, l = l0[d] - pc * P;
+        const int ext = imin(P, n - pc * P);
+        const int pdn = pc == 0 ? np - 1 : pc - 1;
+        on[d][0] = l < hi;
+        pcs[d][0] = pdn;
+        ls[d][0] = l + imin(P, n - pdn * P);
+        on[d][1] = true;
+        pcs[d][1] = pc;
+        ls[d][1] = l;
+        on[d][2] = l >= ext - lo;
+        pcs[d][2] = pc == np - 1 ? 0 : pc + 1;
+        ls[d][2] = l - ext;
+    }
+    const int64_t own = (int64_t)(R.np[0] * (pcs[0][1] + R.np[1] * pcs[1][1])) * 6 * fcells + (ls[0][1] + lo) +
+                        (int64_t)fy * (ls[1][1] + lo);
+    float v[9][6];
+    int64_t at[9];
+#pragma unroll
+    for (int z = 0; z < 3; ++z)
+#pragma unroll
+        for (int y = 0; y < 3; ++y) {
+            const int k = z * 3 + y;
+            const bool use = on[1][z] && on[0][y];
+            const int p = R.np[0] * (pcs[0][y] + R.np[1] * pcs[1][z]);
+            at[k] = use ? (int64_t)p * 6 * fcells + (ls[0][y] + lo) + (int64_t)fy * (ls[1][z] + lo) : own;
+            float w[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) w[q] = A.gtile[q * fcells + at[k]];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) v[k][q] = use ? w[q] : 0.0f;
+        }
+    const int64_t nc = R.ncell;
+    float cur[6];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        cur[q] = A.lE[q * nc + idx];
+        cur[3 + q] = A.lB[q * nc + idx];
+    }
+    float acc[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) acc[q] += v[k][q];
+#pragma unroll
+    for (int z = 0; z < 3; ++z)
+#pragma unroll
+        for (int y = 0; y < 3; ++y)
+            if (on[1][z] && on[0][y])
+#pragma unroll
+                for (int q = 0; q < 6; ++q) A.gtile[q * fcells + at[z * 3 + y]] = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        A.lE[q * nc + idx] = cur[q] + acc[q];
+        A.lB[q * nc + idx] = cur[3 + q] + acc[3 + q];
+    }
+}
+
 __global__ void __launch_bounds__(256) k_adj_fold(const RunDev *__restrict__ runs, const AdjRun *__restrict__ adj,
                                                   int n_runs, const int64_t *__restrict__ run_base, int64_t total) {
+    {
+        // the usual case: the workgroup in one run whose patches allow the direct fold
+        const int64_t c0 = (int64_t)blockIdx.x * blockDim.x;
+        const int64_t c1 = (c0 + blockDim.x < total ? c0 + blockDim.x : total) - 1;
+        const int rb = find_run_a(run_base, n_runs, c0);
+        if (run_base[rb + 1] > c1 && runs[rb].fold_direct) {
+            const int64_t c = c0 + threadIdx.x;
+            if (c < total) adj_fold_direct(runs[rb], adj[rb], c - run_base[rb]);
+            return;
+        }
+    }
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= total) return;
     const int r = find_run_a(run_base, n_runs, c);
