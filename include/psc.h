@@ -151,6 +151,18 @@ psc_status psc_bind(psc_ctx *ctx, const psc_run_bufs *bufs, int n_runs, void *wo
 psc_status psc_load_particles(psc_ctx *ctx, int run, int species, int64_t n, const int32_t *gcell,
                               const float *goff, const float *gu, const int32_t *gid, void *stream);
 
+/* Load the particles of one (run, species) that are already in sorted key
+ * order, in the layout psc_get_particles writes (stride n): key int32 (n)
+ * patch-major cell keys, off float32 (D, n), u float32 (3, n), id int32 (n)
+ * or NULL (ids are then 0 .. n-1 if the context carries them).  No
+ * conversion and no sort: the arrays are copied into buffer set 0 and the
+ * cell offsets taken from the key boundaries; a key outside the run's cells
+ * or a decreasing pair sets PSC_DEV_KEY in the error word (psc_check).
+ * Otherwise as psc_load_particles (restores a checkpoint taken with
+ * psc_get_particles without sorting it again). */
+psc_status psc_load_sorted(psc_ctx *ctx, int run, int species, int64_t n, const int32_t *key, const float *off,
+                           const float *u, const int32_t *id, void *stream);
+
 /* Field update of every run (section "FDTD method"; fig. psc_new).
  * op: PSC_B_HALF or PSC_E_FULL. */
 psc_status psc_push_fields(psc_ctx *ctx, int op, void *stream);

@@ -584,6 +584,45 @@ psc_status psc_load_particles(psc_ctx *ctx, int run, int species, int64_t n, con
     return PSC_OK;
 }
 
+psc_status psc_load_sorted(psc_ctx *ctx, int run, int species, int64_t n, const int32_t *key, const float *off,
+                           const float *u, const int32_t *id, void *stream) {
+    if (!ctx || !ctx->bound) return PSC_ERR_STATE;
+    if (run < 0 || run >= ctx->n_runs || species < 0 || species >= ctx->runs[run].n_species)
+        return PSC_ERR_INVALID;
+    if (ctx->stepped || ctx->front || ctx->cs_sel || ctx->perm_pending) {
+        // restart, as psc_load_particles
+        if (ctx->mc_valid) {
+            psc_status st = clear_move_counts(ctx, (hipStream_t)stream);
+            if (st != PSC_OK) return st;
+        }
+        ctx->stepped = false;
+        ctx->front = ctx->cs_sel = ctx->perm_pending = ctx->mc_valid = 0;
+        for (auto &v : ctx->loaded) std::fill(v.begin(), v.end(), false);
+    }
+    RunDev &R = ctx->runs[run];
+    SpeciesDev &S = R.sp[species];
+    if (n < 0 || n > S.cap) return fail(ctx, PSC_ERR_INVALID, "particle count exceeds capacity");
+    if (n > 0 && (!key || !off || !u)) return PSC_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    if (n > 0) {
+        const size_t row = sizeof(float) * (size_t)n, pitch = sizeof(float) * (size_t)S.cap;
+        HIPCHECK(hipMemcpyAsync(S.cell[0], key, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s), "load keys");
+        HIPCHECK(hipMemcpy2DAsync(S.off[0], pitch, off, row, row, R.dim, hipMemcpyDeviceToDevice, s), "load offsets");
+        HIPCHECK(hipMemcpy2DAsync(S.u[0], pitch, u, row, row, 3, hipMemcpyDeviceToDevice, s), "load momenta");
+        if (S.id[0]) {
+            if (id) HIPCHECK(hipMemcpyAsync(S.id[0], id, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s), "load ids");
+            else HIPCHECK(launch_iota(S.id[0], n, s), "load ids");
+        }
+    }
+    HIPCHECK(launch_cell_starts(n, R.ncell, S.cell[0], S.cs[0], ctx->err(), s), "load cell offsets");
+    S.n = n;
+    HIPCHECK(hipMemcpyAsync(ctx->at<RunDev>(ctx->off.runs) + run, &R, sizeof(RunDev), hipMemcpyHostToDevice, s),
+             "upload run");
+    HIPCHECK(hipStreamSynchronize(s), "load sync");
+    ctx->loaded[run][species] = true;
+    return PSC_OK;
+}
+
 static psc_status require_loaded(psc_ctx *ctx) {
     if (!ctx || !ctx->bound) return PSC_ERR_STATE;
     for (int r = 0; r < ctx->n_runs; ++r)

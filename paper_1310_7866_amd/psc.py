@@ -26,7 +26,8 @@ STATUS = {0: "PSC_OK", 1: "PSC_ERR_INVALID", 2: "PSC_ERR_CFL", 3: "PSC_ERR_LDS",
           5: "PSC_ERR_NONFINITE", 6: "PSC_ERR_PARTICLE", 7: "PSC_ERR_UNSUPPORTED", 8: "PSC_ERR_STATE"}
 
 # every symbol include/psc.h declares
-EXPORTS = ["psc_init_patches", "psc_workspace_size", "psc_bind", "psc_load_particles", "psc_push_fields",
+EXPORTS = ["psc_init_patches", "psc_workspace_size", "psc_bind", "psc_load_particles", "psc_load_sorted",
+           "psc_push_fields",
            "psc_push_particles", "psc_deposit_current", "psc_sort", "psc_sort_radix", "psc_step", "psc_get_particles",
            "psc_keys_to_cells", "psc_particle_count", "psc_front", "psc_sort_view", "psc_diagnostics",
            "psc_get_perm", "psc_marder", "psc_adjoint_step", "psc_set_launch", "psc_balance", "psc_partition",
@@ -80,6 +81,7 @@ def load_library(path: str = LIB_PATH):
     L.psc_workspace_size.argtypes = [vp, C.POINTER(C.c_size_t)]
     L.psc_bind.argtypes = [vp, C.POINTER(RunBufs), i32, vp, vp]
     L.psc_load_particles.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp, vp]
+    L.psc_load_sorted.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp, vp]
     L.psc_push_fields.argtypes = [vp, i32, vp]
     L.psc_push_particles.argtypes = [vp, vp]
     L.psc_deposit_current.argtypes = [vp, vp]
@@ -212,6 +214,13 @@ class PscSim:
         n = int(cell.numel())
         self._call(self.L.psc_load_particles(self.ctx, r, s, n, cell.data_ptr(), off.data_ptr(), u.data_ptr(),
                                              ids.data_ptr() if ids is not None else None, self._stream()))
+
+    def load_sorted(self, r: int, s: int, key, off, u, ids=None):
+        """Load particles already in sorted key order, as device_particles
+        returns them (keys, offsets (D*n), momenta (3*n), ids); no sort."""
+        n = int(key.numel())
+        self._call(self.L.psc_load_sorted(self.ctx, r, s, n, key.data_ptr(), off.data_ptr(), u.data_ptr(),
+                                          ids.data_ptr() if ids is not None else None, self._stream()))
 
     # -- plumbing ------------------------------------------------------------
     def _stream(self):
@@ -384,8 +393,7 @@ class PscSim:
             E.copy_(snap[r]["E"])
             B.copy_(snap[r]["B"])
             for s, p in enumerate(snap[r]["parts"]):
-                cells = self.keys_to_cells(r, p["key"])
-                self.load(r, s, cells, p["off"], p["u"], p["id"])
+                self.load_sorted(r, s, p["key"], p["off"], p["u"], p["id"])
 
     def adjoint_step(self, fwd, lam):
         """One reverse step.  fwd: per run dict(E, B, parts=[dict(key, off, u)],

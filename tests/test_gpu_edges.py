@@ -109,3 +109,39 @@ def test_overfull_cell_refused():
     with pytest.raises(PscError):   # the constructor's final psc_check reports the flag
         sim = _sim(c)
         sim.check()
+
+
+def test_load_sorted_restores_a_snapshot():
+    """A snapshot in psc_get_particles order loaded back with psc_load_sorted
+    (no sort) continues exactly as the run it was taken from."""
+    c = cases.thermal2d(ny=24, nz=16, ppc=6, order=2, patch=8, seed=111)
+    cases.random_fields(c, 0.05, 0.3, seed=112)
+    sim = _sim(c)
+    sim.step(2)
+    snap = sim.snapshot()
+    sim.step(2)
+    ref = [sim.particles(0, s) for s in range(len(c.species))]
+    E_ref = sim.field_arrays(0)[0]
+    sim.restore(snap)
+    sim.step(2)
+    assert sim.check() == 0
+    for s in range(len(c.species)):
+        p = sim.particles(0, s)
+        assert np.array_equal(p["key"], ref[s]["key"])
+        assert np.array_equal(p["id"], ref[s]["id"])
+        assert np.abs(p["u"] - ref[s]["u"]).max() <= 1e-6
+    E = sim.field_arrays(0)[0]
+    assert np.abs(E - E_ref).max() <= 1e-6 * np.abs(E_ref).max()
+    sim.close()
+
+
+def test_load_sorted_flags_unsorted_keys():
+    """Keys in decreasing order are reported through the error word, not
+    used: psc_load_sorted's offset pass checks every adjacent pair."""
+    c = cases.thermal2d(ny=16, nz=16, ppc=2, order=1, patch=8, seed=113)
+    sim = _sim(c)
+    parts = [sim.device_particles(0, s) for s in range(len(c.species))]
+    p = parts[0]
+    sim.load_sorted(0, 0, p["key"].flip(0).contiguous(), p["off"], p["u"], p["id"])
+    assert sim.error_word(clear=True) & 4   # PSC_DEV_KEY
+    sim.close()
