@@ -35,8 +35,8 @@ def _state(sim):
     st = []
     for r, c in enumerate(sim.cases):
         E, B, _ = sim.fields[r]
-        st.append(dict(E=E.clone(), B=B.clone(),
-                       parts=[sim.device_particles(r, s) for s in range(len(c.species))]))
+        st.append(dict(E=E.clone(), B=B.clone(),   # the reverse step reads no ids
+                       parts=[sim.device_particles(r, s, ids=False) for s in range(len(c.species))]))
     return st
 
 

@@ -363,18 +363,21 @@ class PscSim:
         self._call(self.L.psc_get_perm(self.ctx, r, s, out.data_ptr(), self._stream()))
         return out[:n]
 
-    def device_particles(self, r: int, s: int):
+    def device_particles(self, r: int, s: int, ids: bool = True):
         """Sorted-order particles of (run, species) as device tensors
-        (key int32 (n), off float32 (D*n), u float32 (3*n), id int32 (n))."""
+        (key int32 (n), off float32 (D*n), u float32 (3*n), id int32 (n)
+        unless ids is False)."""
         torch = self.torch
         c = self.cases[r]
         n = c.species[s].n
         t = dict(key=torch.empty(max(n, 1), dtype=torch.int32, device=self.device),
                  off=torch.empty(c.dim * max(n, 1), dtype=torch.float32, device=self.device),
-                 u=torch.empty(3 * max(n, 1), dtype=torch.float32, device=self.device),
-                 id=torch.empty(max(n, 1), dtype=torch.int32, device=self.device))
+                 u=torch.empty(3 * max(n, 1), dtype=torch.float32, device=self.device))
+        if ids:
+            t["id"] = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
         self._call(self.L.psc_get_particles(self.ctx, r, s, t["key"].data_ptr(), t["off"].data_ptr(),
-                                            t["u"].data_ptr(), t["id"].data_ptr(), self._stream()))
+                                            t["u"].data_ptr(), t["id"].data_ptr() if ids else None,
+                                            self._stream()))
         return {k: v[:(c.dim * n if k == "off" else 3 * n if k == "u" else n)] for k, v in t.items()}
 
     def snapshot(self):
