@@ -245,7 +245,6 @@ __global__ void __launch_bounds__(kFoldBlock) k_fold_patch(const RunDev *__restr
         // load issued (an unused candidate reads the own entry, counted as
         // zero), so that a cell's reads are in flight together
         float v[27][3];
-        int64_t at[27];
         const int64_t own = (int64_t)p * 3 * jc + (ls[0][1] + lo) +
                             (int64_t)R.jt[0] * ((l[1] + lo) + (int64_t)R.jt[1] * (l[2] + lo));
 #pragma unroll
@@ -257,10 +256,10 @@ __global__ void __launch_bounds__(kFoldBlock) k_fold_patch(const RunDev *__restr
                     const int k = (z * 3 + y) * 3 + x;
                     const int pq = pcs[0][x] + R.np[0] * (pcs[1][y] + R.np[1] * pcs[2][z]);
                     const bool use = on[2][z] && on[1][y] && on[0][x];
-                    at[k] = use ? (int64_t)pq * 3 * jc + (ls[0][x] + lo) +
-                                      (int64_t)R.jt[0] * ((ls[1][y] + lo) + (int64_t)R.jt[1] * (ls[2][z] + lo))
-                                : own;
-                    const float a = jtile[at[k]], b = jtile[jc + at[k]], c = jtile[2 * jc + at[k]];
+                    const int64_t at = use ? (int64_t)pq * 3 * jc + (ls[0][x] + lo) +
+                                                 (int64_t)R.jt[0] * ((ls[1][y] + lo) + (int64_t)R.jt[1] * (ls[2][z] + lo))
+                                           : own;
+                    const float a = jtile[at], b = jtile[jc + at], c = jtile[2 * jc + at];
                     v[k][0] = use ? a : 0.0f;
                     v[k][1] = use ? b : 0.0f;
                     v[k][2] = use ? c : 0.0f;
@@ -283,11 +282,13 @@ __global__ void __launch_bounds__(kFoldBlock) k_fold_patch(const RunDev *__restr
             for (int y = 0; y < 3; ++y)
 #pragma unroll
                 for (int x = X0; x <= X1; ++x) {
-                    const int k = (z * 3 + y) * 3 + x;
-                    if (on[2][z] && on[1][y] && on[0][x]) {
-                        jtile[at[k]] = 0.0f;
-                        jtile[jc + at[k]] = 0.0f;
-                        jtile[2 * jc + at[k]] = 0.0f;
+                    if (on[2][z] && on[1][y] && on[0][x]) {   // the address again: fewer live registers
+                        const int pq = pcs[0][x] + R.np[0] * (pcs[1][y] + R.np[1] * pcs[2][z]);
+                        const int64_t at = (int64_t)pq * 3 * jc + (ls[0][x] + lo) +
+                                           (int64_t)R.jt[0] * ((ls[1][y] + lo) + (int64_t)R.jt[1] * (ls[2][z] + lo));
+                        jtile[at] = 0.0f;
+                        jtile[jc + at] = 0.0f;
+                        jtile[2 * jc + at] = 0.0f;
                     }
                 }
         const int64_t idx = (pc[0] * R.P[0] + l[0]) +
