@@ -36,8 +36,10 @@
  * Parity status: every routine is pinned by a closed form, an identity or
  * brute force in the CPU tests, except the out-of-plane current J_x of the
  * 2-d deposit for cell-crossing moves (pinned only for moves inside one
- * cell, where it equals the exact time average of the shape) and the
- * energy diagnostics (no exact value exists) -- parity unpinned there.
+ * cell, where it equals the exact time average of the shape).  The energy
+ * diagnostics are pinned by closed forms (rational gamma, uniform fields)
+ * and by the energy balance of the cold plasma oscillation; the energy of
+ * a general run has no exact value (the scheme does not conserve it).
  */
 #include <math.h>
 #include <stdint.h>
