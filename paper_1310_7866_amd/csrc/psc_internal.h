@@ -179,6 +179,17 @@ __host__ __device__ inline void decode_key(const RunDev &r, int64_t key, int g[3
     g[2] = pk * r.P[2] + lk;
 }
 
+// Lane map of the mixed-lane ablation of the particle kernel: lane g of a
+// work item with `nruns` lane strips takes strip (g mod 64) M + g div 64,
+// M = ceil(nruns / 64), so the 64 lanes of a wave are spread over the item
+// instead of lying on consecutive strips.  A bijection of [0, 64 M) onto
+// itself; g >= 64 M gives nruns (no strip).  The kernel's rounds visit every
+// g < 64 M since a workgroup is a whole number of waves.
+__host__ __device__ inline int32_t mix_lane(int32_t g, int32_t nruns) {
+    const int32_t M = (nruns + 63) >> 6;
+    return g < 64 * M ? (g & 63) * M + (g >> 6) : nruns;
+}
+
 // number of move codes and the code of "stays in its cell"
 __host__ __device__ inline int n_moves(int dim) { return dim == 3 ? 27 : 9; }
 

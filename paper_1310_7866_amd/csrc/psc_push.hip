@@ -608,10 +608,7 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
     // current and write nothing
     for (int32_t r0 = 0; r0 < nruns; r0 += NT) {
         int32_t g = r0 + (int32_t)threadIdx.x;
-        if constexpr (PSC_MIX && !RUNS) {   // ablation only: a bijection of [0, 64 ceil(n/64))
-            const int32_t M = (nruns + 63) >> 6;
-            g = g < 64 * M ? (g & 63) * M + (g >> 6) : nruns;
-        }
+        if constexpr (PSC_MIX && !RUNS) g = mix_lane(g, nruns);   // ablation only
         const int32_t first = beg + g * K;                       // this lane's strip
         const int32_t len = g < nruns ? imin(K, end - first) : 0;
         int c = 0, cf = -1;   // particle's cell, cell of the lane's frame
