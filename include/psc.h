@@ -245,6 +245,38 @@ psc_status psc_balance(psc_ctx *ctx, double cell_cost, void *stream);
  * the number of consecutive patches of each rank.  Pure host function. */
 psc_status psc_partition(const double *L, int n_patches, const double *C, int n_ranks, int32_t *N);
 
+/* Order in which the (run, species, patch) units of the particle work are
+ * handed out (section "Dynamic load balancing using space filling curves":
+ * patches enumerated along a Hilbert-Peano curve, so that a contiguous
+ * segment of the enumeration is a compact block of the domain).  The units
+ * of a run follow its patches in this order, the species of a patch
+ * together, runs one after another.  It decides which patches the eighth of
+ * the work items owned by one XCD's queue (PSC_LAUNCH_QUEUE), a contiguous
+ * item range (PSC_LAUNCH_GRID) or one workgroup's partition segment
+ * (PSC_LAUNCH_PARTITION) covers; it does not change the particle layout,
+ * the cell keys or any result beyond the summation order of the current.
+ * PSC_ORDER_HILBERT is the default. */
+#define PSC_ORDER_ROWMAJOR 0   /* patch index order, x fastest               */
+#define PSC_ORDER_HILBERT 1    /* psc_hilbert_order                           */
+
+/* Set the unit order of a bound context: uploads the unit table on `stream`
+ * and synchronizes it, drops recorded step graphs, and recomputes the
+ * partition (psc_balance) under PSC_LAUNCH_PARTITION.  PSC_ERR_INVALID for an
+ * unknown order or an unbound context. */
+psc_status psc_set_unit_order(psc_ctx *ctx, int order, void *stream);
+
+/* The Hilbert order of the patches of a grid of np[0] x np[1] x np[2]
+ * patches (x fastest; np[0] == 1 when dim == 2): order[t] is the row-major
+ * patch index p = px + np[0]*(py + np[1]*pz) of the t-th patch along the
+ * curve, for t < np[0]*np[1]*np[2] (at most 2^24 patches).  The curve is
+ * the n-dimensional Hilbert curve (Skilling's construction) of the smallest
+ * power-of-two cube holding the grid, restricted to it, with the grid axes
+ * mapped onto the curve's coordinates by the permutation that leaves the
+ * fewest consecutive pairs that are not face neighbours (none for a cube of
+ * side 2^k, or a 2:1 box in 2-d, 2:1:1 or 2:2:1 in 3-d).  `order` is caller
+ * host memory.  Pure host function; PSC_ERR_INVALID for bad sizes. */
+psc_status psc_hilbert_order(int dim, const int32_t np[3], int32_t *order);
+
 /* Write the particles of (run, species) in sorted key order into caller
  * device arrays (same layout as the buffers, stride n): cell keys, offsets,
  * momenta, ids (any pointer may be NULL to skip it). */

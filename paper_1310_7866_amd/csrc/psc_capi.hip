@@ -15,6 +15,7 @@
 namespace psc {
 size_t push_lds_bytes(int dim, int order, const int P[3], int threads, int run);
 int push_occupancy(int dim, int order, int mode, int threads, int run, size_t lds);
+void hilbert_patch_order(int dim, const int np[3], std::vector<int32_t> &order);
 }
 
 using namespace psc;
@@ -44,6 +45,7 @@ struct psc_ctx {
     size_t ws_bytes = 0;
     char *ws = nullptr;
     std::vector<Unit> units;
+    int unit_order = PSC_ORDER_HILBERT;  // patch order of the units within a run
     int64_t max_items = 0;
     int64_t total_cells = 0;
     std::vector<int64_t> run_base;       // n_runs + 1
@@ -130,6 +132,25 @@ Launch make_launch(psc_ctx *ctx, hipStream_t s) {
     L.stream = s;
     L.err = ctx->err();
     return L;
+}
+
+// the (run, species, patch) units: runs one after another, each run's
+// patches in row-major order or along its Hilbert curve, the species of a
+// patch together
+void build_units(psc_ctx *ctx) {
+    ctx->units.clear();
+    std::vector<int32_t> order;
+    for (int r = 0; r < ctx->n_runs; ++r) {
+        const RunDev &R = ctx->runs[r];
+        if (ctx->unit_order == PSC_ORDER_HILBERT) {
+            hilbert_patch_order(R.dim, R.np, order);
+        } else {
+            order.resize(R.n_patches);
+            for (int p = 0; p < R.n_patches; ++p) order[p] = p;
+        }
+        for (int p : order)
+            for (int s = 0; s < R.n_species; ++s) ctx->units.push_back(Unit{r, s, p, 0});
+    }
 }
 
 }  // namespace
@@ -289,9 +310,8 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
             S.n = 0;
             if (S.cap > ctx->max_cap) ctx->max_cap = S.cap;
         }
-        for (int p = 0; p < R.n_patches; ++p)
-            for (int s = 0; s < d.n_species; ++s) ctx->units.push_back(Unit{r, s, p, 0});
     }
+    build_units(ctx);
     int64_t items = (int64_t)ctx->units.size();
     for (int r = 0; r < n_runs; ++r)
         for (int s = 0; s < runs[r].n_species; ++s) items += (runs[r].capacity[s] + ctx->chunk - 1) / ctx->chunk;
@@ -945,6 +965,21 @@ psc_status psc_set_launch(psc_ctx *ctx, int mode, int chunk, int workers, int th
         psc_status st = psc_balance(ctx, 1.0, stream);
         if (st != PSC_OK) return st;
     }
+    return PSC_OK;
+}
+
+psc_status psc_set_unit_order(psc_ctx *ctx, int order, void *stream) {
+    if (!ctx || !ctx->bound || (order != PSC_ORDER_ROWMAJOR && order != PSC_ORDER_HILBERT)) return PSC_ERR_INVALID;
+    if (order == ctx->unit_order) return PSC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    ctx->unit_order = order;
+    build_units(ctx);
+    HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.units), ctx->units.data(), sizeof(Unit) * ctx->units.size(),
+                            hipMemcpyHostToDevice, s), "upload units");
+    HIPCHECK(hipStreamSynchronize(s), "unit order sync");
+    for (auto &kv : ctx->graphs) hipGraphExecDestroy(kv.second);
+    ctx->graphs.clear();
+    if (ctx->pm.mode == 2) return psc_balance(ctx, 1.0, stream);
     return PSC_OK;
 }
 

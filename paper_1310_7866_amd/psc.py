@@ -31,10 +31,11 @@ EXPORTS = ["psc_init_patches", "psc_workspace_size", "psc_bind", "psc_load_parti
            "psc_push_particles", "psc_deposit_current", "psc_sort", "psc_sort_radix", "psc_step", "psc_get_particles",
            "psc_keys_to_cells", "psc_particle_count", "psc_front", "psc_sort_view", "psc_diagnostics",
            "psc_get_perm", "psc_marder", "psc_adjoint_step", "psc_set_launch", "psc_balance", "psc_partition",
-           "psc_check", "psc_status_string", "psc_last_error", "psc_destroy"]
+           "psc_set_unit_order", "psc_hilbert_order", "psc_check", "psc_status_string", "psc_last_error", "psc_destroy"]
 LAUNCH_GRID, LAUNCH_QUEUE, LAUNCH_PARTITION = 0, 1, 2
 RUN_ADJOINT = 1
 RUN_VB = 2
+ORDER_ROWMAJOR, ORDER_HILBERT = 0, 1
 
 
 class PscError(RuntimeError):
@@ -100,6 +101,8 @@ def load_library(path: str = LIB_PATH):
     L.psc_set_launch.argtypes = [vp, i32, i32, i32, i32, i32, vp]
     L.psc_balance.argtypes = [vp, C.c_double, vp]
     L.psc_partition.argtypes = [C.POINTER(C.c_double), i32, C.POINTER(C.c_double), i32, C.POINTER(C.c_int32)]
+    L.psc_set_unit_order.argtypes = [vp, i32, vp]
+    L.psc_hilbert_order.argtypes = [i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.psc_check.argtypes = [vp, vp, C.POINTER(C.c_uint32), i32]
     L.psc_status_string.argtypes = [i32]
     L.psc_status_string.restype = C.c_char_p
@@ -123,6 +126,20 @@ def partition(loads: Sequence[float], caps: Sequence[float]) -> np.ndarray:
                          out.ctypes.data_as(C.POINTER(C.c_int32)))
     if st != 0:
         raise PscError(st, "psc_partition")
+    return out
+
+
+def hilbert_order(dim: int, np_: Sequence[int]) -> np.ndarray:
+    """Patches of an np_[0] x np_[1] x np_[2] grid (x fastest) along the
+    library's Hilbert curve: row-major patch indices in curve order (host
+    function of the library)."""
+    L = load_library()
+    n = np.ascontiguousarray(np_, dtype=np.int32)
+    out = np.zeros(int(n[0]) * int(n[1]) * int(n[2]), np.int32)
+    st = L.psc_hilbert_order(int(dim), n.ctypes.data_as(C.POINTER(C.c_int32)),
+                             out.ctypes.data_as(C.POINTER(C.c_int32)))
+    if st != 0:
+        raise PscError(st, "psc_hilbert_order")
     return out
 
 
@@ -276,6 +293,9 @@ class PscSim:
     def set_launch(self, mode: int, chunk: int = 0, workers: int = 0, threads: int = 0, run: int = 0):
         self._call(self.L.psc_set_launch(self.ctx, int(mode), int(chunk), int(workers), int(threads), int(run),
                                          self._stream()))
+
+    def set_unit_order(self, order: int):
+        self._call(self.L.psc_set_unit_order(self.ctx, int(order), self._stream()))
 
     def balance(self, cell_cost: float = 1.0):
         self._call(self.L.psc_balance(self.ctx, float(cell_cost), self._stream()))

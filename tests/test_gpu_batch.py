@@ -93,3 +93,84 @@ def test_batched_runs_equal_alone_two_stream():
         Eb, _, _ = batch.field_arrays(r)
         Ea, _, _ = alone.field_arrays(0)
         assert np.abs(Eb - Ea).max() <= 1e-6 * max(np.abs(Ea).max(), 1e-30)
+
+
+def _uneven_batch(order):
+    """Four runs of one context: two-species thermal runs and a one-species
+    two-stream run, different particles per cell, ragged last patches, and
+    (at both orders) one run whose last patch is narrower than the current
+    halo, so that the batch folds by patch and with the alias search."""
+    def charged(seed, ny, nz, patch, ppc):
+        c = cases.thermal2d(ny=ny, nz=nz, ppc=ppc, order=order, patch=patch, seed=seed)
+        c.species[1].off = np.random.default_rng(seed + 1000).random(c.species[1].off.shape).astype(np.float32)
+        cases.random_fields(c, 0.02, 0.2, seed=seed + 1)
+        return c
+    ts = cases.twostream2d(ny=40, nz=20, ppc=10, order=order, patch=16, seed=77)
+    cases.random_fields(ts, 0.02, 0.2, seed=78)
+    narrow = 8 + 8 + order            # last patch of `order` cells: narrower than order + 1
+    return [charged(51, narrow, 12, 8, 6), charged(52, 24, 16, 8, 3), ts, charged(53, 30, 22, 8, 9)]
+
+
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2])
+def test_batch_matches_oracle(order, mode):
+    """Every run of a batched context against the double-precision oracle
+    run alone: one push (the parity tolerances of single runs), then three
+    whole steps replayed from a HIP graph."""
+    from oracle import oracle as O
+    from tests.helpers import particle_errors
+    cs = _uneven_batch(order)
+    sim = _sim(cs)
+    sim.set_launch(mode, chunk=512)
+    oras = [O.OracleSim(c) for c in cs]
+    sim.push_fields(0)
+    sim.push_particles()
+    sim.deposit_current()
+    assert sim.check() == 0
+    for r, (c, ora) in enumerate(zip(cs, oras)):
+        ora.push_b_half()
+        ora.push_particles()
+        for s, sp in enumerate(c.species):
+            dpos, du = particle_errors(c, sim.front_buffer(r, s), ora, s, float(np.std(sp.u)))
+            print(f"run {r} species {s}: one push |dxi| {dpos:.3e}, rel |du| {du:.3e}", flush=True)
+            assert dpos <= 1e-6 and du <= 1e-5
+        _, _, J = sim.field_arrays(r)
+        assert np.abs(J.ravel() - ora.J).max() <= 2e-5 * np.abs(ora.J).max()
+    sim2 = _sim(cs)
+    sim2.set_launch(mode, chunk=512)
+    oras = [O.OracleSim(c) for c in cs]
+    for _ in range(3):
+        sim2.step(1, use_graph=True)
+        for ora in oras:
+            ora.step(1)
+    assert sim2.check() == 0
+    for r, (c, ora) in enumerate(zip(cs, oras)):
+        for s, sp in enumerate(c.species):
+            dpos, du = particle_errors(c, sim2.particles(r, s), ora, s, float(np.std(sp.u)))
+            print(f"run {r} species {s}: 3 steps |dxi| {dpos:.3e}, rel |du| {du:.3e}", flush=True)
+            assert dpos <= 1e-5 and du <= 1e-4
+        E, B, _ = sim2.field_arrays(r)
+        assert np.abs(E.ravel() - ora.E).max() <= 1e-4 * np.abs(ora.E).max()
+        assert np.abs(B.ravel() - ora.B).max() <= 1e-4 * np.abs(ora.B).max()
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_unit_orders_agree(mode):
+    """Row-major and Hilbert unit orders hand the same work out in another
+    order: the same particles, and fields to the summation order of the
+    current tiles."""
+    from paper_1310_7866_amd.psc import ORDER_HILBERT, ORDER_ROWMAJOR
+    cs = _uneven_batch(2)
+    a, b = _sim(cs), _sim(cs)
+    a.set_launch(mode, chunk=512)
+    b.set_launch(mode, chunk=512)
+    b.set_unit_order(ORDER_ROWMAJOR)
+    for k in range(3):
+        a.step(1)
+        b.step(1, use_graph=k > 0)
+    b.set_unit_order(ORDER_HILBERT)
+    b.step(1)
+    a.step(1)
+    a.check()
+    b.check()
+    _same(_state(a), _state(b))

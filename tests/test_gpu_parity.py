@@ -379,3 +379,39 @@ def test_vb_deposit_matches_oracle(kind):
     rho_scale = np.abs(ora2.rho()).max()
     print(f"vb {kind}: Gauss drift over 3 steps {np.abs(g3 - g0).max():.3e} (rho scale {rho_scale:.3e})")
     assert np.abs(g3 - g0).max() <= 1e-5 * rho_scale
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_3d_patch8_matches_oracle(order):
+    """3-d with the Weibel workload's 8^3 patches (its LDS tile layout, its
+    deposit and the per-patch fold at that size): full patches plus a ragged
+    last patch of 4 cells along z, after one push and after five steps."""
+    c = _small_3d(order, seed=61, nxyz=(16, 16, 20), patch=8, ppc=4)
+    sim = _sim(c)
+    ora = O.OracleSim(c)
+    sim.push_fields(0)
+    sim.push_particles()
+    sim.deposit_current()
+    assert sim.check() == 0
+    ora.push_b_half()
+    ora.push_particles()
+    for s, sp in enumerate(c.species):
+        dpos, du = particle_errors(c, sim.front_buffer(0, s), ora, s, float(np.std(sp.u)))
+        print(f"one push, species {s}: |dxi| {dpos:.3e}, rel |du| {du:.3e}")
+        assert dpos <= 1e-6 and du <= 1e-5
+    _, _, J = sim.field_arrays(0)
+    assert np.abs(J.ravel() - ora.J).max() <= 2e-5 * np.abs(ora.J).max()
+    sim2 = _sim(c)
+    ora2 = O.OracleSim(c)
+    for _ in range(5):
+        sim2.step(1)
+        ora2.step(1)
+    assert sim2.check() == 0
+    for s, sp in enumerate(c.species):
+        dpos, du = particle_errors(c, sim2.particles(0, s), ora2, s, float(np.std(sp.u)))
+        print(f"5 steps, species {s}: |dxi| {dpos:.3e}, rel |du| {du:.3e}")
+        assert dpos <= 1e-5 and du <= 1e-4
+    E, B, J = sim2.field_arrays(0)
+    assert np.abs(E.ravel() - ora2.E).max() <= 1e-4 * np.abs(ora2.E).max()
+    assert np.abs(B.ravel() - ora2.B).max() <= 1e-4 * np.abs(ora2.B).max()
+    assert np.abs(J.ravel() - ora2.J).max() <= 1e-4 * np.abs(ora2.J).max()
