@@ -140,6 +140,31 @@ psc_status psc_workspace_size(const psc_ctx *ctx, size_t *bytes);
  * descriptor tables on `stream` (a hipStream_t, NULL = default stream). */
 psc_status psc_bind(psc_ctx *ctx, const psc_run_bufs *bufs, int n_runs, void *workspace, void *stream);
 
+/* Size of the library-held workspace of psc_bind_static, per device. */
+#define PSC_STATIC_WORKSPACE_BYTES (64u * 1024u * 1024u)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): psc_bind
+ * with the workspace taken from a device array the library holds, of
+ * PSC_STATIC_WORKSPACE_BYTES on each device, instead of a caller block.  The
+ * caller still allocates and passes the fields and particle buffers (bufs).
+ * The array of the current device (hipGetDevice) is used; its address is
+ * looked up once per device.  Clears what must start at zero (error word,
+ * current tiles, cell offsets, move counters) as psc_bind does: the array
+ * otherwise keeps whatever the last call left in it.  Calls no hipMalloc,
+ * hipFree or allocating library routine (the context's host tables were
+ * sized by psc_init_patches); synchronizes `stream` like psc_bind.
+ * Sharing: one context at a time holds a device's array.  Binding another
+ * context with this call hands the array to it; the previous holder is left
+ * unbound (its calls return PSC_ERR_STATE, and psc_last_error says why) until
+ * it is bound again, and its device state is lost.  Calls of two contexts
+ * that overlap on one device race on the array.  psc_bind or psc_destroy of
+ * the holder releases it.
+ * Errors: PSC_ERR_INVALID if psc_workspace_size exceeds
+ * PSC_STATIC_WORKSPACE_BYTES (psc_last_error states both sizes), otherwise
+ * as psc_bind. */
+psc_status psc_bind_static(psc_ctx *ctx, const psc_run_bufs *bufs, int n_runs, void *stream);
+
 /* Load the particles of one (run, species) from caller device arrays in
  * geometric form: gcell int32 (n) geometric cell index i + nx*(j + ny*k),
  * goff float32 (D, n) row-major (array d at goff + d*n), gu float32 (3, n),

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -26,6 +27,12 @@ static constexpr size_t kMaxLds = 160 * 1024;
 // slot of its own, so calls queue on the stream without a host wait (a slot
 // is reused only after the call that last used it has finished)
 static constexpr int kAdjRing = 4;
+
+// Library-held workspace of psc_bind_static, one per device (each device
+// that loads the library holds its own copy until the process ends).  Host
+// code never passes the array's name to a kernel or copy: it is a host-side
+// stand-in, and the device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[PSC_STATIC_WORKSPACE_BYTES];
 
 struct psc_ctx {
     std::vector<psc_run_desc> desc;
@@ -59,6 +66,7 @@ struct psc_ctx {
     int64_t total_seg_cells = 0;
     int64_t n_scan_blocks = 0;
     std::vector<int32_t> block_seg;
+    std::vector<ScanSeg> segs_host[2];   // scan segments per cs_sel, filled at bind (sized at init)
     int64_t max_cap = 0, max_ncell = 0;
     size_t cub_bytes = 0;
 
@@ -82,6 +90,8 @@ struct psc_ctx {
     uint64_t adj_calls = 0;
     std::vector<size_t> off_b1, off_lj, off_gt;
     std::vector<std::vector<size_t>> off_soff, off_su, off_acs;
+
+    int static_dev = -1;                 // device whose library-held workspace this context is bound to
 
     // state
     bool bound = false;
@@ -152,6 +162,13 @@ void build_units(psc_ctx *ctx) {
             for (int s = 0; s < R.n_species; ++s) ctx->units.push_back(Unit{r, s, p, 0});
     }
 }
+
+// device addresses of `scratch` (taken once per device with that device
+// current) and the context each device's copy is bound to
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+psc_ctx *g_scratch_owner[kMaxDevices] = {};
 
 }  // namespace
 
@@ -342,6 +359,8 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
     ctx->off.seg_sp = take(sizeof(int32_t) * ctx->n_segs);
     ctx->off.segs0 = take(sizeof(ScanSeg) * ctx->n_segs);
     ctx->off.segs1 = take(sizeof(ScanSeg) * ctx->n_segs);
+    ctx->segs_host[0].resize(ctx->n_segs);
+    ctx->segs_host[1].resize(ctx->n_segs);
     // block sums, block -> segment table, partial sums (kScanBlock / 256 per block)
     ctx->off.scan_tmp = take(sizeof(int32_t) * (2 + kScanBlock / 256) * ctx->n_scan_blocks);
     ctx->off.err = take(sizeof(uint32_t) * 64);
@@ -442,7 +461,13 @@ psc_status psc_bind(psc_ctx *ctx, const psc_run_bufs *bufs, int n_runs, void *wo
         psc_status st = psc_workspace_size(ctx, &b);
         if (st != PSC_OK) return st;
     }
+    if (ctx->static_dev >= 0) {   // leaves the library-held workspace for the caller's
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (g_scratch_owner[ctx->static_dev] == ctx) g_scratch_owner[ctx->static_dev] = nullptr;
+        ctx->static_dev = -1;
+    }
     hipStream_t s = (hipStream_t)stream;
+    ctx->bound = false;
     ctx->ws = (char *)workspace;
     for (int r = 0; r < ctx->n_runs; ++r) {
         RunDev &R = ctx->runs[r];
@@ -474,7 +499,7 @@ psc_status psc_bind(psc_ctx *ctx, const psc_run_bufs *bufs, int n_runs, void *wo
             S.tot = ctx->at<int32_t>(ctx->off_tot[r][sp]);
         }
     }
-    std::vector<ScanSeg> segs0(ctx->n_segs), segs1(ctx->n_segs);
+    std::vector<ScanSeg> &segs0 = ctx->segs_host[0], &segs1 = ctx->segs_host[1];
     {
         int64_t b0 = 0;
         for (int g = 0; g < ctx->n_segs; ++g) {
@@ -548,6 +573,43 @@ psc_status psc_bind(psc_ctx *ctx, const psc_run_bufs *bufs, int n_runs, void *wo
         psc_status st = psc_set_launch(ctx, PSC_LAUNCH_QUEUE, 0, 0, threads, run, stream);
         if (st != PSC_ERR_LDS) return st;
     }
+    return PSC_OK;
+}
+
+psc_status psc_bind_static(psc_ctx *ctx, const psc_run_bufs *bufs, int n_runs, void *stream) {
+    if (!ctx || !bufs || n_runs != ctx->n_runs) return PSC_ERR_INVALID;
+    size_t need = 0;
+    psc_status st = psc_workspace_size(ctx, &need);
+    if (st != PSC_OK) return st;
+    if (need > (size_t)PSC_STATIC_WORKSPACE_BYTES)
+        return fail(ctx, PSC_ERR_INVALID,
+                    "the runs need " + std::to_string(need) + " bytes of workspace; the library-held workspace " +
+                        "holds " + std::to_string((size_t)PSC_STATIC_WORKSPACE_BYTES) + " (use psc_bind)");
+    int dev = 0;
+    HIPCHECK(hipGetDevice(&dev), "get device");
+    if (dev < 0 || dev >= kMaxDevices) return fail(ctx, PSC_ERR_INVALID, "device index beyond the static table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIPCHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "address of the static workspace");
+        if (!p || reinterpret_cast<uintptr_t>(p) % 256) return fail(ctx, PSC_ERR_HIP, "static workspace address");
+        g_scratch_ptr[dev] = p;
+    }
+    // the previous holder of this device's copy loses it (its workspace is
+    // about to be overwritten): it must be bound again before further use
+    psc_ctx *prev = g_scratch_owner[dev];
+    if (prev && prev != ctx) {
+        prev->bound = false;
+        prev->static_dev = -1;
+        prev->last_error = "the library-held workspace was bound to another context";
+    }
+    g_scratch_owner[dev] = nullptr;
+    if (ctx->static_dev >= 0 && ctx->static_dev != dev) g_scratch_owner[ctx->static_dev] = nullptr;
+    ctx->static_dev = -1;
+    st = psc_bind(ctx, bufs, n_runs, g_scratch_ptr[dev], stream);
+    if (st != PSC_OK) return st;
+    ctx->static_dev = dev;
+    g_scratch_owner[dev] = ctx;
     return PSC_OK;
 }
 
@@ -1056,6 +1118,10 @@ psc_status psc_check(psc_ctx *ctx, void *stream, uint32_t *word, int clear) {
 
 psc_status psc_destroy(psc_ctx *ctx) {
     if (!ctx) return PSC_ERR_INVALID;
+    if (ctx->static_dev >= 0) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (g_scratch_owner[ctx->static_dev] == ctx) g_scratch_owner[ctx->static_dev] = nullptr;
+    }
     for (auto &kv : ctx->graphs) hipGraphExecDestroy(kv.second);
     if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
     delete ctx;

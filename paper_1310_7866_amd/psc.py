@@ -26,7 +26,7 @@ STATUS = {0: "PSC_OK", 1: "PSC_ERR_INVALID", 2: "PSC_ERR_CFL", 3: "PSC_ERR_LDS",
           5: "PSC_ERR_NONFINITE", 6: "PSC_ERR_PARTICLE", 7: "PSC_ERR_UNSUPPORTED", 8: "PSC_ERR_STATE"}
 
 # every symbol include/psc.h declares
-EXPORTS = ["psc_init_patches", "psc_workspace_size", "psc_bind", "psc_load_particles", "psc_load_sorted",
+EXPORTS = ["psc_init_patches", "psc_workspace_size", "psc_bind", "psc_bind_static", "psc_load_particles", "psc_load_sorted",
            "psc_push_fields",
            "psc_push_particles", "psc_deposit_current", "psc_sort", "psc_sort_radix", "psc_step", "psc_get_particles",
            "psc_keys_to_cells", "psc_particle_count", "psc_front", "psc_sort_view", "psc_diagnostics",
@@ -81,6 +81,7 @@ def load_library(path: str = LIB_PATH):
     L.psc_init_patches.argtypes = [C.POINTER(RunDesc), i32, i32, C.POINTER(vp)]
     L.psc_workspace_size.argtypes = [vp, C.POINTER(C.c_size_t)]
     L.psc_bind.argtypes = [vp, C.POINTER(RunBufs), i32, vp, vp]
+    L.psc_bind_static.argtypes = [vp, C.POINTER(RunBufs), i32, vp]
     L.psc_load_particles.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp, vp]
     L.psc_load_sorted.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp, vp]
     L.psc_push_fields.argtypes = [vp, i32, vp]
@@ -165,10 +166,12 @@ class PscSim:
 
     ``cases``: a ``cases.Case`` or a list of them (a batch: one launch per
     kernel covers every run).  Buffers are torch tensors on ``device``.
+    ``static_workspace``: bind with psc_bind_static (the library-held
+    workspace) instead of a torch-allocated one.
     """
 
     def __init__(self, cases, device: str = "cuda", with_ids: bool = True, chunk: int = 0,
-                 adjoint: bool = False):
+                 adjoint: bool = False, static_workspace: bool = False):
         import torch
         self.torch = torch
         if not torch.cuda.is_available():
@@ -184,8 +187,12 @@ class PscSim:
         self.ctx = ctx
         nbytes = C.c_size_t()
         self._call(self.L.psc_workspace_size(self.ctx, C.byref(nbytes)))
-        self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
-        ws_ptr = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.workspace_bytes = int(nbytes.value)
+        if static_workspace:
+            self.workspace = None
+        else:
+            self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+            ws_ptr = (self.workspace.data_ptr() + 255) // 256 * 256
         f32, i32 = torch.float32, torch.int32
         self.fields = []
         self.parts = []   # per run: per species: [set0, set1] of dict(cell, off, u, id)
@@ -212,7 +219,10 @@ class PscSim:
                     bufs[r].id[s][k] = t["id"].data_ptr() if with_ids else None
                 per_sp.append(sets)
             self.parts.append(per_sp)
-        self._call(self.L.psc_bind(self.ctx, bufs, n_runs, C.c_void_p(ws_ptr), self._stream()))
+        if static_workspace:
+            self._call(self.L.psc_bind_static(self.ctx, bufs, n_runs, self._stream()))
+        else:
+            self._call(self.L.psc_bind(self.ctx, bufs, n_runs, C.c_void_p(ws_ptr), self._stream()))
         self.with_ids = with_ids
         for r, c in enumerate(self.cases):
             for s, sp in enumerate(c.species):
