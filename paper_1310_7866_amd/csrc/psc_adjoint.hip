@@ -462,7 +462,7 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles(const RunDev *__res
         const float igm = rsqrt_ge1(1.0f + dot3(um, um));
         const float3 t = scale3(Bp, h * igm);
         const float t2 = dot3(t, t);
-        const float f = 2.0f / (1.0f + t2);
+        const float f = boris_factor(t2);
         const float3 s = scale3(t, f);
         const float3 up = add3(um, cross3(um, t));
         const float3 uq = add3(um, cross3(up, s));

@@ -146,6 +146,10 @@ __device__ __forceinline__ int divmod_small(int a, int b, float inv_b, int &rem)
 // 1/sqrt(x) for x >= 1 (no denormal range to guard): the hardware estimate
 __device__ __forceinline__ float rsqrt_ge1(float x) { return __builtin_amdgcn_rsqf(x); }
 
+// 2 / (1 + t^2) of the Boris rotation, t^2 >= 0, with the hardware
+// reciprocal (1 ulp; the IEEE division takes ten instructions)
+__device__ __forceinline__ float boris_factor(float t2) { return 2.0f * __builtin_amdgcn_rcpf(1.0f + t2); }
+
 // pointers into device memory known to be global (loads and stores become
 // global_* instead of flat_*, which would also wait on LDS traffic)
 template <typename T>

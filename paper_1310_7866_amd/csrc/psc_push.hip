@@ -59,6 +59,14 @@ namespace psc {
 #ifndef PSC_WAVES_3D1
 #define PSC_WAVES_3D1 4
 #endif
+//   PSC_PREFETCH     1: with one particle per lane, the permutation entry
+//                    and cell key of a lane's next particle are loaded while
+//                    the current one is pushed, so a round waits for one
+//                    memory round trip (its offsets and momenta) instead of
+//                    three dependent ones (permutation, key, state)
+#ifndef PSC_PREFETCH
+#define PSC_PREFETCH 1
+#endif
 //   PSC_WAVES_PER_EU occupancy the register allocator must allow for every
 //                    instantiation (0: the measured per-shape choice below)
 #ifndef PSC_WAVES_PER_EU
@@ -603,6 +611,31 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
         __builtin_amdgcn_wave_barrier();
     };
 
+    // K = 1 with prefetching: the source slot (through the permutation) and
+    // cell key of the lane's particle in the round starting at r; lanes
+    // without a particle stand in with the chunk's first particle
+    constexpr bool prefetch = single && PSC_PREFETCH;
+    int32_t p_src = beg, p_key = 0;
+    auto lane_slot = [&](int32_t r, bool &ok) {
+        int32_t g = r + (int32_t)threadIdx.x;
+        if constexpr (PSC_MIX && !RUNS) g = mix_lane(g, nruns);   // ablation only
+        ok = g < nruns;
+        return ok ? beg + g : beg;
+    };
+    auto checked_src = [&](int32_t slot, int32_t raw, bool ok) {
+        if ((uint32_t)raw >= (uint32_t)S.n) {   // corrupt permutation: stay in bounds
+            if (ok) flags |= PSC_DEV_KEY;
+            return slot;
+        }
+        return raw;
+    };
+    if constexpr (prefetch) {
+        bool ok;
+        const int32_t sl = lane_slot(0, ok);
+        p_src = checked_src(sl, use_perm ? perm[sl] : sl, ok);
+        p_key = cell_in[p_src];
+    }
+
     // every lane runs the same number of rounds and of steps per round (the
     // wave operations need all 64 lanes); lanes without a particle carry zero
     // current and write nothing
@@ -705,12 +738,14 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
             // lanes without a particle stand in with the chunk's first
             // particle (taken through the permutation, so it lies in range)
             const int32_t slot = valid ? first + j : beg;
-            int32_t src = use_perm ? perm[slot] : slot;
-            if ((uint32_t)src >= (uint32_t)S.n) {   // corrupt permutation: stay in bounds
-                if (valid) flags |= PSC_DEV_KEY;
-                src = slot;
+            int32_t src, key;
+            if constexpr (prefetch) {
+                src = p_src;
+                key = p_key;
+            } else {
+                src = checked_src(slot, use_perm ? perm[slot] : slot, valid);
+                key = cell_in[src];
             }
-            const int32_t key = cell_in[src];
             c = key - (int32_t)kb;
             if (c < 0 || c >= pcells) {   // not in this patch: corrupt state
                 if (valid) flags |= PSC_DEV_KEY;
@@ -729,6 +764,14 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
             o[2] = off_in[(DIM == 3 ? 2 : 1) * cap + src];
             float ux = u_in[src], uy = u_in[cap + src], uz = u_in[2 * cap + src];
             const int32_t idv = id_in ? id_in[src] : 0;
+            // the next round's permutation entry (the round loop is uniform)
+            const bool more = prefetch && r0 + NT < nruns;
+            bool n_ok = false;
+            int32_t n_slot = beg, n_raw = beg;
+            if (more) {
+                n_slot = lane_slot(r0 + NT, n_ok);
+                n_raw = use_perm ? perm[n_slot] : n_slot;
+            }
 
             // ---- interpolation ----------------------------------------------
             float wny[ORDER + 1], why[ORDER + 1], wnz[ORDER + 1], whz[ORDER + 1];
@@ -765,7 +808,7 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
                 const float mx = fmaf(h, Ex, ux), my = fmaf(h, Ey, uy), mz = fmaf(h, Ez, uz);
                 const float igm = rsqrt_ge1(1.0f + mx * mx + my * my + mz * mz);
                 const float tx = h * Bx * igm, ty = h * By * igm, tz = h * Bz * igm;
-                const float f = 2.0f / (1.0f + tx * tx + ty * ty + tz * tz);
+                const float f = boris_factor(tx * tx + ty * ty + tz * tz);
                 const float sx = f * tx, sy = f * ty, sz = f * tz;
                 const float px = mx + (my * tz - mz * ty);
                 const float py = my + (mz * tx - mx * tz);
@@ -776,6 +819,10 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
             }
             const float ig = rsqrt_ge1(1.0f + ux * ux + uy * uy + uz * uz);
             if (valid && !(ig > 0.0f)) flags |= PSC_DEV_NONFINITE;   // NaN or Inf momentum
+            if (more) {
+                p_src = checked_src(n_slot, n_raw, n_ok);
+                p_key = cell_in[p_src];
+            }
 
             // ---- move: xi^{n+3/2} = xi^{n+1/2} + dt u^{n+1} / (gamma dx) ---
             int s[3] = {0, 0, 0};
