@@ -156,6 +156,29 @@ __host__ __device__ inline int64_t encode_key(const RunDev &r, int i, int j, int
     return patch_key_base(r, pi, pj, pk) + li + (int64_t)hx * (lj + (int64_t)hy * lk);
 }
 
+// Key of the cell at local coordinates l of patch pc (extents h), where each
+// l[d] lies within one cell of the patch: -1 <= l[d] <= h[d].  A coordinate
+// outside the patch moves to the neighbouring patch with periodic wrap.
+// Equals encode_key of the wrapped geometric cell, without divisions.
+__host__ __device__ inline int64_t neighbour_key(const RunDev &r, const int pc[3], const int h[3], const int l[3]) {
+    int q[3], m[3], e[3];
+    for (int d = 0; d < 3; ++d) {
+        q[d] = pc[d];
+        m[d] = l[d];
+        e[d] = h[d];
+        if (l[d] < 0) {
+            q[d] = pc[d] == 0 ? r.np[d] - 1 : pc[d] - 1;
+            e[d] = patch_ext(r, d, q[d]);
+            m[d] = e[d] - 1;
+        } else if (l[d] >= h[d]) {
+            q[d] = pc[d] + 1 == r.np[d] ? 0 : pc[d] + 1;
+            e[d] = patch_ext(r, d, q[d]);
+            m[d] = 0;
+        }
+    }
+    return patch_key_base(r, q[0], q[1], q[2]) + m[0] + (int64_t)e[0] * (m[1] + (int64_t)e[1] * m[2]);
+}
+
 // inverse of encode_key
 __host__ __device__ inline void decode_key(const RunDev &r, int64_t key, int g[3]) {
     int64_t slab = (int64_t)r.P[2] * r.n[1] * r.n[0];

@@ -696,6 +696,31 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
                     for (int b = 0; b < FL; ++b)
                         acc[2 * NY2 + b * FL + a] = fmaf(pa, Az[b], fmaf(qa, DSz[b], acc[2 * NY2 + b * FL + a]));
                 }
+            } else if constexpr (ORDER == 1) {
+                // in-cell move of a 1st-order particle: with displacements
+                // d and path midpoints m (cell units), Jx on the edge (b, c)
+                // of the cell is -jfx dx (W_b(my) W_c(mz) +- dy dz / 12),
+                // W_0 = 1 - m, W_1 = m, sign + where b == c.  Summed over the
+                // particles of a cell that is a combination of four moments
+                // (P, P my, P mz, P (my mz + dy dz / 12)), P = -jfx dx;
+                // likewise Jy with (x, z) and Jz with (x, y).  The frame holds
+                // the moments, turned into edge currents after the wave sums.
+                const float ex = o1[0] - o[0], ey = o1[1] - o[1], ez = o1[2] - o[2];
+                const float mx = fmaf(0.5f, ex, o[0]), my = fmaf(0.5f, ey, o[1]), mz = fmaf(0.5f, ez, o[2]);
+                const float px = frame ? -jfx * ex : 0.0f, py = frame ? -jfy * ey : 0.0f,
+                            pz = frame ? -jfz * ez : 0.0f;
+                acc[0] += px;
+                acc[1] = fmaf(px, my, acc[1]);
+                acc[2] = fmaf(px, mz, acc[2]);
+                acc[3] = fmaf(px, fmaf(ey * ez, 1.0f / 12.0f, my * mz), acc[3]);
+                acc[4] += py;
+                acc[5] = fmaf(py, mx, acc[5]);
+                acc[6] = fmaf(py, mz, acc[6]);
+                acc[7] = fmaf(py, fmaf(ex * ez, 1.0f / 12.0f, mx * mz), acc[7]);
+                acc[8] += pz;
+                acc[9] = fmaf(pz, mx, acc[9]);
+                acc[10] = fmaf(pz, my, acc[10]);
+                acc[11] = fmaf(pz, fmaf(ex * ey, 1.0f / 12.0f, mx * my), acc[11]);
             } else {
                 const float gx = frame ? jfx : 0.0f;
                 float S0x[FL], S1x[FL];
@@ -922,8 +947,8 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
                 if (nlx >= 0 && nlx < hx && nly >= 0 && nly < hy && nlz >= 0 && nlz < hz) {
                     nkey = (int32_t)kb + nlx + hx * (nly + hy * nlz);
                 } else {
-                    const int gx = DIM == 3 ? wrap(ox + nlx, R.n[0]) : 0;
-                    nkey = (int32_t)encode_key(R, gx, wrap(oy + nly, R.n[1]), wrap(oz + nlz, R.n[2]));
+                    const int hh[3] = {hx, hy, hz}, nl[3] = {nlx, nly, nlz};
+                    nkey = (int32_t)neighbour_key(R, pc, hh, nl);
                 }
                 const int code = DIM == 3 ? (s[0] + 1) + 3 * (s[1] + 1) + 9 * (s[2] + 1) : (s[1] + 1) + 3 * (s[2] + 1);
                 if constexpr (single) {
@@ -1000,6 +1025,18 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
             if constexpr (!single) add_frame(fa1, fb1, fx1, fr1);
             const RowScan rs = row_scan_setup<SW>(cf);
             row_scan<SW>(acc, rs);
+            if constexpr (DIM == 3 && ORDER == 1) {
+                // moments (S, S_a, S_b, S_ab) of each component -> the currents
+                // of its four edges (a, b) = (0,0), (1,0), (0,1), (1,1)
+#pragma unroll
+                for (int g3 = 0; g3 < 3; ++g3) {
+                    float *m = acc + 4 * g3;
+                    const float m0 = m[0], m1 = m[1], m2 = m[2], m3 = m[3];
+                    m[0] = (m0 - m1) - (m2 - m3);
+                    m[1] = m1 - m3;
+                    m[2] = m2 - m3;
+                }
+            }
             const bool put = rs.tail && len > 0;
             int base;
             if constexpr (DIM == 2) base = (fz_ + FB + JLO) * jy_ + (fy_ + FB + JLO);

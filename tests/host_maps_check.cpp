@@ -35,8 +35,45 @@ static void check_mix_lane() {
         }
 }
 
+// The particle kernel's key of a cell just outside a patch: equals the
+// general encoder of the wrapped geometric cell, for every patch and every
+// local coordinate within one cell of it, on grids with truncated last
+// patches, single patches along a dimension, and 2-d (x invariant) runs.
+static void check_neighbour_key() {
+    struct G { int n[3], P[3]; };
+    const G grids[] = {{{1, 12, 9}, {1, 4, 4}}, {{1, 10, 7}, {1, 4, 3}}, {{1, 8, 5}, {1, 8, 2}},
+                       {{7, 9, 6}, {3, 4, 2}}, {{8, 8, 8}, {4, 4, 4}}, {{5, 6, 7}, {5, 2, 3}},
+                       {{9, 4, 10}, {4, 4, 3}}};
+    for (const G &g : grids) {
+        RunDev r{};
+        for (int d = 0; d < 3; ++d) {
+            r.n[d] = g.n[d];
+            r.P[d] = g.P[d];
+            r.np[d] = (g.n[d] + g.P[d] - 1) / g.P[d];
+        }
+        r.dim = g.n[0] == 1 ? 2 : 3;
+        for (int p = 0; p < r.np[0] * r.np[1] * r.np[2]; ++p) {
+            int pc[3];
+            patch_coords(r, p, pc);
+            const int h[3] = {patch_ext(r, 0, pc[0]), patch_ext(r, 1, pc[1]), patch_ext(r, 2, pc[2])};
+            const int lo0 = r.dim == 2 ? 0 : -1, hi0 = r.dim == 2 ? 0 : h[0];
+            for (int a = lo0; a <= hi0; ++a)
+                for (int b = -1; b <= h[1]; ++b)
+                    for (int c = -1; c <= h[2]; ++c) {
+                        const int l[3] = {a, b, c};
+                        const int gi = wrap(pc[0] * r.P[0] + a, r.n[0]), gj = wrap(pc[1] * r.P[1] + b, r.n[1]),
+                                  gk = wrap(pc[2] * r.P[2] + c, r.n[2]);
+                        const int64_t want = encode_key(r, gi, gj, gk), got = neighbour_key(r, pc, h, l);
+                        CHECK(want == got, "grid %dx%dx%d patch %d local (%d,%d,%d): %lld != %lld", r.n[0], r.n[1],
+                              r.n[2], p, a, b, c, (long long)got, (long long)want);
+                    }
+        }
+    }
+}
+
 int main() {
     check_mix_lane();
+    check_neighbour_key();
     if (failures) {
         std::printf("%d failures\n", failures);
         return 1;
