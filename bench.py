@@ -1,18 +1,20 @@
 """Benchmark of the particle-in-cell hot path on one MI355X.
 
-Workload (default): the 2-d double Harris current sheet, 1024 x 512 cells,
-100 particles per cell per species at the sheet peak (20 in the 0.2
-background), m_i/m_e = 25, T_i/T_e = 5, 2nd-order shape, float32, 32 x 32
-patches -- about 29.2 M particles.  A step is one full pass of the hot path in
-the order of the paper's optimized time step: B half step, fused particle
-kernel (gather, Boris, move, Esirkepov deposit), B half step, current fold,
-E full step, sort.  Inputs are synthetic and seeded, resident in HBM before
-the timed region.
+Workload (default): the 3-d periodic counter-streaming electron Weibel
+setup, 256^3 cells, 32 electrons per cell in two beams at +-0.3c along z
+with v_th = 0.05c, immobile ions, 1st-order shape, float32 cell-index +
+offset particles, 8^3 patches -- 536,870,912 particles.  A step is one full
+pass of the hot path in the order of the paper's optimized time step: B
+half step, fused particle kernel (gather, Boris, move, Esirkepov deposit),
+B half step, current fold, E full step, sort.  Inputs are synthetic and
+seeded, resident in HBM before the timed region.
 
 Prints one JSON line: whole-step particle throughput (particle pushes per
 second over complete steps), the roofline of the dominant kernel (the fused
 particle kernel) from HIP events recorded on its stream inside the timed
-region, and the double-precision oracle timed on a bounded sample on the host.
+region, and the double-precision oracle timed on a bounded sample on the
+host (one thread and every thread).  Extra keys: the same measurement on the
+2-d Harris sheet, the adjoint, the batched runs and the sort ablation.
 """
 from __future__ import annotations
 
@@ -45,6 +47,10 @@ def algorithmic_bytes(case) -> float:
     return case.n_particles * per_particle + case.ncell * (6 + 3) * 4
 
 
+# every n-th particle of a workload for the oracle's baseline and error legs
+CPU_THIN = {"weibel3d": 32, "harris2d": 1, "thermal2d": 1, "harris2d_small": 1}
+
+
 def make_case(name: str):
     from paper_1310_7866_amd import cases
     if name == "harris2d":
@@ -58,21 +64,66 @@ def make_case(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(case, thin: int):
-    """The oracle as it stands, single-threaded, on every `thin`-th particle
-    of the same workload for one complete step."""
+    """The oracle as it stands on every `thin`-th particle of the workload
+    (full grid) for one complete step, timed on this host with one thread
+    and with every thread the process may use.  Both legs use a copy of the
+    oracle compiled here for this host (gcc -O3 -march=native, float64
+    with -ffp-contract=off, no fast-math: the same arithmetic as the tests'
+    build); the threaded leg is built with OpenMP, whose particle loop gives
+    each thread its own current array and whose field updates split the
+    grid.  The sort stays single-threaded in both.  The first leg's state
+    after the step gives the GPU path's error."""
+    import tempfile
     from oracle import oracle as O
     from paper_1310_7866_amd import cases
     sample = cases.thin(case, thin)
-    sim = O.OracleSim(sample)
-    t0 = time.perf_counter()
-    sim.step(1)
-    dt = time.perf_counter() - t0
-    return dict(value=sample.n_particles / dt, unit="particle pushes/s", cores=1, kind="oracle",
+    tmp = os.path.join(os.environ.get("TMPDIR", tempfile.gettempdir()), f"psc_oracle_{os.getpid()}")
+    libs = {1: O.build_host_tuned(tmp, openmp=False), 0: O.build_host_tuned(tmp, openmp=True)}
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    legs, first = {}, None
+    for want in (1, threads):
+        O.use_library(libs[1 if want == 1 else 0])
+        used = O.set_threads(want)
+        sim = O.OracleSim(sample)
+        t0 = time.perf_counter()
+        sim.push_b_half()
+        t1 = time.perf_counter()
+        sim.push_particles()
+        t2 = time.perf_counter()
+        sim.push_b_half()
+        sim.push_e_full()
+        t3 = time.perf_counter()
+        sim.sort()
+        t4 = time.perf_counter()
+        legs[used] = dict(value=sample.n_particles / (t4 - t0), seconds=t4 - t0, particle_loop_s=t2 - t1,
+                          fields_s=(t1 - t0) + (t3 - t2), sort_s=t4 - t3)
+        print(f"[bench] oracle on {used} thread(s): {t4 - t0:.2f} s per step", file=sys.stderr, flush=True)
+        if first is None:
+            first = sim
+        else:
+            del sim
+    O.use_library(None)
+    err = oracle_error(sample, first)
+    top = max(legs)
+    return dict(value=legs[top]["value"], unit="particle pushes/s", cores=top, kind="oracle",
                 sample=f"1 full step of every {thin}th particle ({sample.n_particles} particles) "
-                       f"of the {case.name} workload on the full {case.gdims[1]}x{case.gdims[2]}"
-                       f"{'' if case.dim == 2 else 'x' + str(case.gdims[0])} grid, float64, 1 thread",
-                seconds=dt, error_of_gpu_path=oracle_error(sample, sim))
+                       f"of the {case.name} workload on the full "
+                       f"{'x'.join(str(g) for g in case.gdims if g > 1)} grid, float64",
+                cpu_model=cpu_model(), compiler="gcc " + " ".join(O.HOST_TUNED_FLAGS) + " [-fopenmp]",
+                threads={str(k): v for k, v in sorted(legs.items())},
+                error_of_gpu_path=err)
 
 
 def oracle_error(sample, osim):
@@ -396,71 +447,16 @@ def batch_leg(steps: int = 10, n_runs: int = 64, tune_cache=None, retune=False):
                 max_abs_du_vs_alone=dev)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="harris2d")
-    ap.add_argument("--chunk", type=int, default=0)
-    ap.add_argument("--cpu-thin", type=int, default=1,
-                    help="oracle baseline on every n-th particle (1: the whole Harris workload, about 18 s)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the adjoint and batch legs")
-    ap.add_argument("--only", choices=("adjoint", "batch", "supercells", "marder", "deposit", "ablation"),
-                    default=None,
-                    help="run only the adjoint or the batch leg and print its JSON")
-    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
-    ap.add_argument("--launch", default="", help="fixed launch shape mode,chunk,threads,run (skips tuning)")
-    ap.add_argument("--tune-cache", default=TUNED, help="autotuner cache (JSON) to read and extend")
-    ap.add_argument("--retune", action="store_true", help="time every launch shape again")
-    ap.add_argument("--calibrate", action="store_true",
-                    help="first run a 1 GiB fill and a 1 GiB device copy (reference kernels of known "
-                         "traffic for hardware-counter runs)")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: the particle path has no multi-GPU code "
-              "(its sharding is a design, not an implementation); run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
-
+def measure(case, args, sort_ablation: bool):
+    """Warm-up and timed steps of one workload in its own context: whole-step
+    throughput, the particle kernel's and the sort's mean duration from HIP
+    events on the stream they run on, and the particle kernel's roofline."""
     import torch
     from paper_1310_7866_amd.psc import PscSim, B_HALF, E_FULL
-
-    if args.only == "adjoint":
-        print(json.dumps({"adjoint": adjoint_leg()}))
-        return
-    if args.only == "batch":
-        print(json.dumps({"batched": batch_leg(tune_cache=args.tune_cache, retune=args.retune)}))
-        return
-    if args.only == "supercells":
-        print(json.dumps({"supercells": supercell_leg()}))
-        return
-    if args.only == "marder":
-        print(json.dumps({"marder": marder_leg()}))
-        return
-    if args.only == "deposit":
-        print(json.dumps({"deposit": deposit_leg()}))
-        return
-    if args.only == "ablation":
-        print(json.dumps({"deposit_ablation": deposit_ablation_leg()}))
-        return
-
-    if args.calibrate:
-        n = 256 * 1024 * 1024                      # float32 -> 1 GiB
-        src = torch.ones(n, dtype=torch.float32, device="cuda")   # fill: writes 1 GiB
-        dst = torch.empty_like(src)
-        dst.copy_(src)                                             # copy: reads and writes 1 GiB
-        torch.cuda.synchronize()
-        print(f"[bench] calibration fill + copy of {4 * n} bytes", file=sys.stderr, flush=True)
-        del src, dst
-        torch.cuda.empty_cache()
-
-    case = make_case(args.workload)
     print(f"[bench] workload {case.name}: gdims={case.gdims} order={case.order} patch={case.patch} "
           f"particles={case.n_particles}", file=sys.stderr, flush=True)
     sim = PscSim(case, with_ids=False, chunk=args.chunk)
     stream = torch.cuda.current_stream()
-
     launch = None
     if args.launch:
         mode, chunk, threads, run = (int(x) for x in args.launch.split(","))
@@ -500,64 +496,144 @@ def main():
     total_ms = t_start.elapsed_time(t_end)
     push_ms = sum(a.elapsed_time(b) for a, b in push_ev) / args.steps
     sort_ms = sum(a.elapsed_time(b) for a, b in sort_ev) / args.steps
-    sort_ablation = None if args.no_extras else sort_ablation_leg(sim, stream, min(args.steps, 10))
-    ms_step = total_ms / args.steps
+    ablation = sort_ablation_leg(sim, stream, min(args.steps, 10)) if sort_ablation else None
     n = case.n_particles
-    value = n * args.steps / (total_ms / 1e3)
     abytes = algorithmic_bytes(case)
     achieved_gbs = abytes / (push_ms / 1e3) / 1e9
-
     roof = dict(bound="hbm", achieved=round(achieved_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved_gbs / HBM_PEAK_GBS, 4), traffic=None)
+                frac=round(achieved_gbs / HBM_PEAK_GBS, 4), traffic=None,
+                algorithmic_bytes=abytes, kernel_ms=push_ms)
     # hardware counters of this kernel source at this launch shape, if recorded
     roofs = None
     counters = _recorded_counters(case, launch)
     if counters is not None:
-        roof["traffic"] = counters["bytes_per_launch"]
+        tb = counters["bytes_per_launch"]
+        roof.update(traffic=tb, traffic_gbs=round(tb / (push_ms / 1e3) / 1e9, 1),
+                    traffic_frac=round(tb / (push_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                    traffic_over_algorithmic=round(tb / abytes, 3))
         valu_rate = counters["valu_per_launch"] / (push_ms / 1e3)
         roofs = {"hbm_frac": roof["frac"],
                  "valu_issue": {"achieved_instr_per_s": valu_rate, "peak_instr_per_s": VALU_ISSUE_PEAK,
                                 "frac": round(valu_rate / VALU_ISSUE_PEAK, 4)},
                  "counters": counters["source"]}
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return dict(value=n * args.steps / (total_ms / 1e3), ms_per_step=total_ms / args.steps, launch=launch,
+                push_kernel_ms=push_ms, push_kernel_pushes_per_s=n / (push_ms / 1e3), sort_ms=sort_ms,
+                wall_s_timed=wall, roofline=roof, roofs=roofs,
+                sort_ablation=(dict(ablation, counting_sort_ms=sort_ms,
+                                    radix_over_counting=ablation["radix_sort_ms"] / sort_ms) if ablation else None))
 
+
+def workload_label(case) -> str:
+    return (f"{case.name} {'x'.join(str(g) for g in case.gdims if g > 1)} cells, order {case.order}, "
+            f"patches {'x'.join(str(p) for p, g in zip(case.patch, case.gdims) if g > 1)}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="weibel3d", choices=("weibel3d", "harris2d", "thermal2d", "harris2d_small"))
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--cpu-thin", type=int, default=0,
+                    help="oracle baseline on every n-th particle (0: 32 for weibel3d, 1 for the 2-d workloads)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the Harris, adjoint, batch and sort-ablation legs")
+    ap.add_argument("--only", choices=("adjoint", "batch", "supercells", "marder", "deposit", "ablation"),
+                    default=None,
+                    help="run only the adjoint or the batch leg and print its JSON")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--launch", default="", help="fixed launch shape mode,chunk,threads,run (skips tuning)")
+    ap.add_argument("--tune-cache", default=TUNED, help="autotuner cache (JSON) to read and extend")
+    ap.add_argument("--retune", action="store_true", help="time every launch shape again")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="first run a 1 GiB fill and a 1 GiB device copy (reference kernels of known "
+                         "traffic for hardware-counter runs)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the particle path has no multi-GPU code "
+              "(its sharding is a design, not an implementation); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if args.only == "adjoint":
+        print(json.dumps({"adjoint": adjoint_leg()}))
+        return
+    if args.only == "batch":
+        print(json.dumps({"batched": batch_leg(tune_cache=args.tune_cache, retune=args.retune)}))
+        return
+    if args.only == "supercells":
+        print(json.dumps({"supercells": supercell_leg()}))
+        return
+    if args.only == "marder":
+        print(json.dumps({"marder": marder_leg()}))
+        return
+    if args.only == "deposit":
+        print(json.dumps({"deposit": deposit_leg()}))
+        return
+    if args.only == "ablation":
+        print(json.dumps({"deposit_ablation": deposit_ablation_leg()}))
+        return
+
+    if args.calibrate:
+        n = 256 * 1024 * 1024                      # float32 -> 1 GiB
+        src = torch.ones(n, dtype=torch.float32, device="cuda")   # fill: writes 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)                                             # copy: reads and writes 1 GiB
+        torch.cuda.synchronize()
+        print(f"[bench] calibration fill + copy of {4 * n} bytes", file=sys.stderr, flush=True)
+        del src, dst
+        torch.cuda.empty_cache()
+
+    case = make_case(args.workload)
+    res = measure(case, args, sort_ablation=not args.no_extras)
     out = {
         "metric": "particle pushes/sec (gather+push+deposit) and % HBM roofline; adjoint/forward time",
-        "value": value,
+        "value": res["value"],
         "unit": "particle pushes/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{case.name} {case.gdims[1]}x{case.gdims[2]}"
-                               f"{'' if case.dim == 2 else 'x' + str(case.gdims[0])} cells, "
-                               f"order {case.order}, patches {case.patch[1]}x{case.patch[2]}",
-                   "particles": n, "cells": case.ncell, "order": case.order,
-                   "patch": list(case.patch), "parallelism": "single GPU", "launch": launch},
-        "push_kernel_ms": push_ms,
-        "push_kernel_pushes_per_s": n / (push_ms / 1e3),
-        "sort_ms": sort_ms,
-        "wall_s_timed": wall,
-        **({"sort_ablation": dict(sort_ablation, counting_sort_ms=sort_ms,
-                                  radix_over_counting=sort_ablation["radix_sort_ms"] / sort_ms)}
-           if sort_ablation else {}),
-        "roofline": roof,
+        "config": {"workload": workload_label(case), "particles": case.n_particles, "cells": case.ncell,
+                   "order": case.order, "patch": list(case.patch), "parallelism": "single GPU",
+                   "launch": res["launch"]},
+        "push_kernel_ms": res["push_kernel_ms"],
+        "push_kernel_pushes_per_s": res["push_kernel_pushes_per_s"],
+        "sort_ms": res["sort_ms"],
+        "wall_s_timed": res["wall_s_timed"],
+        "roofline": res["roofline"],
     }
-    if roofs is not None:
-        out["roofs"] = roofs
-    del sim
-    torch.cuda.empty_cache()
+    if res["roofs"] is not None:
+        out["roofs"] = res["roofs"]
+    if res["sort_ablation"] is not None:
+        out["sort_ablation"] = res["sort_ablation"]
     if not args.no_extras:
+        if args.workload != "harris2d":
+            print("[bench] harris2d leg", file=sys.stderr, flush=True)
+            hc = make_case("harris2d")
+            hr = measure(hc, args, sort_ablation=False)
+            out["harris2d"] = dict(workload=workload_label(hc), particles=hc.n_particles,
+                                   pushes_per_s=hr["value"], ms_per_step=hr["ms_per_step"],
+                                   push_kernel_ms=hr["push_kernel_ms"], sort_ms=hr["sort_ms"],
+                                   launch=hr["launch"], roofline=hr["roofline"], roofs=hr["roofs"])
+            del hc
         print("[bench] adjoint leg", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_leg()
         print("[bench] batch leg", file=sys.stderr, flush=True)
         out["batched"] = batch_leg(tune_cache=args.tune_cache, retune=args.retune)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case, args.cpu_thin)
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_thin or CPU_THIN.get(case.name, 1))
     print(json.dumps(out))
 
 

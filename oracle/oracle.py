@@ -40,7 +40,36 @@ class _Grid(C.Structure):
                 ("dt", C.c_double), ("order", C.c_int), ("vb", C.c_int)]
 
 
+def build_host_tuned(out_dir: str, openmp: bool) -> str:
+    """Compile a copy of the oracle for timing it on the host that runs
+    this call: gcc -O3 -march=native (this host's instruction set), still
+    float64 with -ffp-contract=off; with ``openmp`` its particle loop and
+    field updates run on every thread (see psc_oracle.c).  Returns the path
+    of the library and leaves the default build alone."""
+    os.makedirs(out_dir, exist_ok=True)
+    out = os.path.join(out_dir, "liboracle_omp.so" if openmp else "liboracle_1t.so")
+    srcs = [s for s in _SRC if os.path.exists(s)]
+    cmd = ["gcc", *HOST_TUNED_FLAGS, *(["-fopenmp"] if openmp else []), "-o", out] + srcs + ["-lm"]
+    subprocess.run(cmd, check=True)
+    return out
+
+
+HOST_TUNED_FLAGS = ["-O3", "-march=native", "-std=c99", "-fPIC", "-shared", "-fno-fast-math", "-ffp-contract=off"]
+
 _lib = None
+
+
+def use_library(path: Optional[str]):
+    """Route the following oracle calls to the library at ``path`` (a
+    build_host_tuned copy), or back to the default build (None)."""
+    global _lib
+    _lib = None if path is None else _bind(C.CDLL(path))
+
+
+def set_threads(n: int) -> int:
+    """Threads of the loaded oracle's parallel loops (1 unless it was built
+    with OpenMP); returns the count in effect."""
+    return int(lib().orc_set_threads(int(n)))
 
 
 def lib():
@@ -49,37 +78,42 @@ def lib():
         if not os.path.exists(_LIB) or any(
                 os.path.getmtime(s) > os.path.getmtime(_LIB) for s in _SRC if os.path.exists(s)):
             build()
-        L = C.CDLL(_LIB)
-        dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
-        ip = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
-        g = C.POINTER(_Grid)
-        L.orc_bspline.argtypes = [C.c_int, C.c_double]
-        L.orc_bspline.restype = C.c_double
-        L.orc_interp.argtypes = [g, dp, dp, dp]
-        L.orc_interp.restype = C.c_double
-        L.orc_boris.argtypes = [dp, dp, dp, C.c_double]
-        L.orc_deposit.argtypes = [g, dp, dp, dp, C.c_double, C.c_double]
-        L.orc_deposit_vb.argtypes = [g, dp, dp, dp, C.c_double, C.c_double]
-        L.orc_push_particles.argtypes = [g, C.c_long, dp, dp, dp, dp, dp, C.c_double, C.c_double, C.c_double]
-        L.orc_push_b.argtypes = [g, dp, dp, C.c_double]
-        L.orc_push_e.argtypes = [g, dp, dp, C.c_void_p, C.c_double]
-        L.orc_div_e.argtypes = [g, dp, dp]
-        L.orc_marder.argtypes = [g, dp, dp, C.c_double]
-        L.orc_div_b.argtypes = [g, dp, dp]
-        L.orc_deposit_rho.argtypes = [g, C.c_long, dp, C.c_double, dp]
-        L.orc_patch_keys.argtypes = [g, ip, ip]
-        L.orc_stable_sort.argtypes = [C.c_long, ip, C.c_int32, ip]
-        L.orc_stable_sort.restype = C.c_int
-        L.orc_cell_of.argtypes = [g, dp]
-        L.orc_cell_of.restype = C.c_long
-        L.orc_field_energy.argtypes = [g, dp]
-        L.orc_field_energy.restype = C.c_double
-        L.orc_kinetic_energy.argtypes = [g, C.c_long, dp, C.c_double, C.c_double]
-        L.orc_kinetic_energy.restype = C.c_double
-        if hasattr(L, "orc_adjoint_step"):
-            _bind_adjoint(L, g, dp, ip)
-        _lib = L
+        _lib = _bind(C.CDLL(_LIB))
     return _lib
+
+
+def _bind(L):
+    dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+    ip = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+    g = C.POINTER(_Grid)
+    L.orc_bspline.argtypes = [C.c_int, C.c_double]
+    L.orc_bspline.restype = C.c_double
+    L.orc_interp.argtypes = [g, dp, dp, dp]
+    L.orc_interp.restype = C.c_double
+    L.orc_boris.argtypes = [dp, dp, dp, C.c_double]
+    L.orc_deposit.argtypes = [g, dp, dp, dp, C.c_double, C.c_double]
+    L.orc_deposit_vb.argtypes = [g, dp, dp, dp, C.c_double, C.c_double]
+    L.orc_push_particles.argtypes = [g, C.c_long, dp, dp, dp, dp, dp, C.c_double, C.c_double, C.c_double]
+    L.orc_push_b.argtypes = [g, dp, dp, C.c_double]
+    L.orc_push_e.argtypes = [g, dp, dp, C.c_void_p, C.c_double]
+    L.orc_div_e.argtypes = [g, dp, dp]
+    L.orc_marder.argtypes = [g, dp, dp, C.c_double]
+    L.orc_div_b.argtypes = [g, dp, dp]
+    L.orc_deposit_rho.argtypes = [g, C.c_long, dp, C.c_double, dp]
+    L.orc_patch_keys.argtypes = [g, ip, ip]
+    L.orc_stable_sort.argtypes = [C.c_long, ip, C.c_int32, ip]
+    L.orc_stable_sort.restype = C.c_int
+    L.orc_cell_of.argtypes = [g, dp]
+    L.orc_cell_of.restype = C.c_long
+    L.orc_field_energy.argtypes = [g, dp]
+    L.orc_field_energy.restype = C.c_double
+    L.orc_kinetic_energy.argtypes = [g, C.c_long, dp, C.c_double, C.c_double]
+    L.orc_kinetic_energy.restype = C.c_double
+    L.orc_set_threads.argtypes = [C.c_int]
+    L.orc_set_threads.restype = C.c_int
+    if hasattr(L, "orc_adjoint_step"):
+        _bind_adjoint(L, g, dp, ip)
+    return L
 
 
 def _bind_adjoint(L, g, dp, ip):

@@ -45,6 +45,24 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Built with OpenMP (only for timing the oracle on all host cores), the
+ * particle loop and the field updates run in parallel threads; each thread
+ * deposits into its own copy of J, and the copies are added in thread
+ * order.  The default build (the tests' reference) has no threads. */
+/* Threads of the parallel loops (1 without OpenMP); returns the count. */
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 typedef struct {
     int dim;        /* 2: (y,z) plane, x invariant; 3: (x,y,z)          */
@@ -298,38 +316,68 @@ void orc_deposit_vb(const orc_grid *g, double *J, const double xi0[3], const dou
 /* Particle loop (fig. psc_new: push_particle_p, push_particle_x, deposit_j) */
 /* ----------------------------------------------------------------------- */
 
+/* One particle p of the loop below: gather E and B at its position, Boris
+ * push, move, deposit its current into J. */
+static void push_particle(const orc_grid *g, long np, long p, double *xi, double *u, const double *E,
+                          const double *B, double *J, double q, double m, double w) {
+    long nc = ncell(g);
+    double qdt_2m = q * g->dt / (2.0 * m);
+    double x0[3], x1[3], uu[3], Ep[3], Bp[3];
+    for (int d = 0; d < 3; ++d) { x0[d] = xi[d * np + p]; uu[d] = u[d * np + p]; }
+    for (int c = 0; c < 3; ++c) {
+        Ep[c] = orc_interp(g, E + c * nc, x0, STAG_E[c]);
+        Bp[c] = orc_interp(g, B + c * nc, x0, STAG_B[c]);
+    }
+    orc_boris(uu, Ep, Bp, qdt_2m);
+    double gam = sqrt(1.0 + uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2]);
+    for (int d = 0; d < 3; ++d)
+        x1[d] = active(g, d) ? x0[d] + g->dt * uu[d] / (gam * g->d[d]) : x0[d];
+    if (g->vb) orc_deposit_vb(g, J, x0, x1, q * w, uu[0] / gam);
+    else orc_deposit(g, J, x0, x1, q * w, uu[0] / gam);
+    for (int d = 0; d < 3; ++d) {
+        double x = x1[d];
+        if (active(g, d)) {
+            if (x < 0.0) x += g->n[d];
+            if (x >= g->n[d]) x -= g->n[d];
+            if (x >= g->n[d]) x -= g->n[d];   /* -tiny + n rounded to n */
+        }
+        xi[d * np + p] = x;
+        u[d * np + p] = uu[d];
+    }
+}
+
 /* xi: (3, n) absolute positions in cells at t^{n+1/2}; u: (3, n) at t^n.
  * E at t^{n+1/2}, B at t^{n+1/2}; J accumulates (not cleared here).
  * On return xi holds t^{n+3/2} (wrapped into [0, n_d)) and u holds t^{n+1}. */
 void orc_push_particles(const orc_grid *g, long np, double *xi, double *u,
                         const double *E, const double *B, double *J,
                         double q, double m, double w) {
-    long nc = ncell(g);
-    double qdt_2m = q * g->dt / (2.0 * m);
-    for (long p = 0; p < np; ++p) {
-        double x0[3], x1[3], uu[3], Ep[3], Bp[3];
-        for (int d = 0; d < 3; ++d) { x0[d] = xi[d * np + p]; uu[d] = u[d * np + p]; }
-        for (int c = 0; c < 3; ++c) {
-            Ep[c] = orc_interp(g, E + c * nc, x0, STAG_E[c]);
-            Bp[c] = orc_interp(g, B + c * nc, x0, STAG_B[c]);
-        }
-        orc_boris(uu, Ep, Bp, qdt_2m);
-        double gam = sqrt(1.0 + uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2]);
-        for (int d = 0; d < 3; ++d)
-            x1[d] = active(g, d) ? x0[d] + g->dt * uu[d] / (gam * g->d[d]) : x0[d];
-        if (g->vb) orc_deposit_vb(g, J, x0, x1, q * w, uu[0] / gam);
-        else orc_deposit(g, J, x0, x1, q * w, uu[0] / gam);
-        for (int d = 0; d < 3; ++d) {
-            double x = x1[d];
-            if (active(g, d)) {
-                if (x < 0.0) x += g->n[d];
-                if (x >= g->n[d]) x -= g->n[d];
-                if (x >= g->n[d]) x -= g->n[d];   /* -tiny + n rounded to n */
+#ifdef _OPENMP
+    int nt = omp_get_max_threads();
+    size_t len = 3 * (size_t)ncell(g);
+    double *Jt = nt > 1 ? (double *)malloc((size_t)nt * len * sizeof(double)) : NULL;
+    if (Jt) {
+        int team = 1;
+#pragma omp parallel num_threads(nt)
+        {
+            double *Jp = Jt + (size_t)omp_get_thread_num() * len;
+            memset(Jp, 0, len * sizeof(double));
+#pragma omp single
+            team = omp_get_num_threads();   /* copies in use (the barrier follows) */
+#pragma omp for schedule(static)
+            for (long p = 0; p < np; ++p) push_particle(g, np, p, xi, u, E, B, Jp, q, m, w);
+#pragma omp for schedule(static)
+            for (long i = 0; i < (long)len; ++i) {
+                double a = 0.0;
+                for (int t = 0; t < team; ++t) a += Jt[(size_t)t * len + i];
+                J[i] += a;
             }
-            xi[d * np + p] = x;
-            u[d * np + p] = uu[d];
         }
+        free(Jt);
+        return;
     }
+#endif
+    for (long p = 0; p < np; ++p) push_particle(g, np, p, xi, u, E, B, J, q, m, w);
 }
 
 /* ----------------------------------------------------------------------- */
@@ -342,6 +390,7 @@ void orc_push_b(const orc_grid *g, const double *E, double *B, double h) {
     const double *Ex = E, *Ey = E + nc, *Ez = E + 2 * nc;
     double *Bx = B, *By = B + nc, *Bz = B + 2 * nc;
     double ix = active(g, 0) ? 1.0 / g->d[0] : 0.0, iy = 1.0 / g->d[1], iz = 1.0 / g->d[2];
+#pragma omp parallel for
     for (int k = 0; k < g->n[2]; ++k)
         for (int j = 0; j < g->n[1]; ++j)
             for (int i = 0; i < g->n[0]; ++i) {
@@ -362,6 +411,7 @@ void orc_push_e(const orc_grid *g, double *E, const double *B, const double *J, 
     const double *Bx = B, *By = B + nc, *Bz = B + 2 * nc;
     const double *Jx = J, *Jy = J + nc, *Jz = J + 2 * nc;
     double ix = active(g, 0) ? 1.0 / g->d[0] : 0.0, iy = 1.0 / g->d[1], iz = 1.0 / g->d[2];
+#pragma omp parallel for
     for (int k = 0; k < g->n[2]; ++k)
         for (int j = 0; j < g->n[1]; ++j)
             for (int i = 0; i < g->n[0]; ++i) {
