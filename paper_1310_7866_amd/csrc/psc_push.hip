@@ -114,31 +114,39 @@ __host__ __device__ inline PushLds push_lds_layout(int fcells, int jcells, int w
 // ---------------------------------------------------------------------------
 // work items
 // ---------------------------------------------------------------------------
-// One workgroup computes, per unit, how many chunks its particles need and the
+// Work items per unit: one thread per unit writes how many chunks its
+// particles need into item_start[u]; k_items_scan turns the counts into the
 // exclusive prefix item_start[0..n_units].
-__global__ void __launch_bounds__(1024) k_build_items(const RunDev *__restrict__ runs, const Unit *__restrict__ units,
-                                                      int n_units, int chunk, int cs_sel,
-                                                      int32_t *__restrict__ item_start,
-                                                      int32_t *__restrict__ queue) {
+__global__ void __launch_bounds__(256) k_unit_items(const RunDev *__restrict__ runs, const Unit *__restrict__ units,
+                                                    int n_units, int chunk, int cs_sel,
+                                                    int32_t *__restrict__ item_start) {
+    const int u = blockIdx.x * 256 + threadIdx.x;
+    if (u >= n_units) return;
+    const Unit U = units[u];
+    const RunDev &R = runs[U.run];
+    int pc[3];
+    patch_coords(R, U.patch, pc);
+    const int64_t kb = patch_key_base(R, pc[0], pc[1], pc[2]);
+    const int64_t ke = kb + (int64_t)patch_ext(R, 0, pc[0]) * patch_ext(R, 1, pc[1]) * patch_ext(R, 2, pc[2]);
+    const int32_t *cs = R.sp[U.species].cs[cs_sel];
+    item_start[u] = (cs[ke] - cs[kb] + chunk - 1) / chunk;
+}
+
+// One workgroup: exclusive prefix of the per-unit item counts in place, the
+// total in item_start[n_units]; each thread sums a contiguous run of units
+// (independent loads), the workgroup scans the run totals.  Also resets the
+// work queues of the persistent launch (written before the particle kernel
+// starts: same stream).
+__global__ void __launch_bounds__(1024) k_items_scan(int n_units, int32_t *__restrict__ item_start,
+                                                     int32_t *__restrict__ queue) {
     __shared__ int32_t part[1024];
-    // reset the work queues of the persistent launch (written before the
-    // particle kernel starts: same stream)
     if (queue && threadIdx.x < 8) queue[kQueueStride * threadIdx.x] = 0;
     const int t = threadIdx.x;
     const int per = (n_units + 1023) / 1024;
-    const int u0 = t * per, u1 = imin(u0 + per, n_units);
+    const int u0 = imin(t * per, n_units), u1 = imin(u0 + per, n_units);
     int32_t sum = 0;
-    for (int u = u0; u < u1; ++u) {
-        const Unit U = units[u];
-        const RunDev &R = runs[U.run];
-        int pc[3];
-        patch_coords(R, U.patch, pc);
-        const int64_t kb = patch_key_base(R, pc[0], pc[1], pc[2]);
-        const int64_t ke = kb + (int64_t)patch_ext(R, 0, pc[0]) * patch_ext(R, 1, pc[1]) * patch_ext(R, 2, pc[2]);
-        const int32_t *cs = R.sp[U.species].cs[cs_sel];
-        const int32_t cnt = cs[ke] - cs[kb];
-        sum += (cnt + chunk - 1) / chunk;
-    }
+#pragma unroll 8
+    for (int u = u0; u < u1; ++u) sum += item_start[u];
     part[t] = sum;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
@@ -149,15 +157,9 @@ __global__ void __launch_bounds__(1024) k_build_items(const RunDev *__restrict__
     }
     int32_t run = part[t] - sum;  // exclusive
     for (int u = u0; u < u1; ++u) {
+        const int32_t c = item_start[u];
         item_start[u] = run;
-        const Unit U = units[u];
-        const RunDev &R = runs[U.run];
-        int pc[3];
-        patch_coords(R, U.patch, pc);
-        const int64_t kb = patch_key_base(R, pc[0], pc[1], pc[2]);
-        const int64_t ke = kb + (int64_t)patch_ext(R, 0, pc[0]) * patch_ext(R, 1, pc[1]) * patch_ext(R, 2, pc[2]);
-        const int32_t *cs = R.sp[U.species].cs[cs_sel];
-        run += (cs[ke] - cs[kb] + chunk - 1) / chunk;
+        run += c;
     }
     if (t == 1023) item_start[n_units] = part[1023];
 }
@@ -1193,8 +1195,9 @@ template <int DIM, int ORDER, int NT, bool RUNS>
 static hipError_t launch_push_r(const Launch &L, const Unit *units, int n_units, int32_t *item_start,
                                 int64_t max_items, int chunk, int front, int cs_sel, int use_perm,
                                 size_t lds, const PushMode &pm) {
-    hipLaunchKernelGGL(k_build_items, dim3(1), dim3(1024), 0, L.stream, L.runs_dev, units, n_units, chunk,
-                       cs_sel, item_start, pm.queue);
+    hipLaunchKernelGGL(k_unit_items, dim3((unsigned)imax(1, (n_units + 255) / 256)), dim3(256), 0, L.stream, L.runs_dev,
+                       units, n_units, chunk, cs_sel, item_start);
+    hipLaunchKernelGGL(k_items_scan, dim3(1), dim3(1024), 0, L.stream, n_units, item_start, pm.queue);
     if (pm.mode == 1) {
         hipLaunchKernelGGL((k_push_queue<DIM, ORDER, NT, RUNS>), dim3((unsigned)pm.workers), dim3(NT), lds, L.stream,
                            L.runs_dev, units, item_start, n_units, chunk, front, cs_sel, use_perm, pm.run, L.err,
