@@ -392,12 +392,12 @@ def batch_leg(steps: int = 10, n_runs: int = 64, tune_cache=None, retune=False):
     import numpy as np
     import torch
     from paper_1310_7866_amd import cases
-    from paper_1310_7866_amd.autotune import tune
+    from paper_1310_7866_amd.autotune import apply_class_chunks, tune
     from paper_1310_7866_amd.psc import PscSim
     cs = cases.twostream_batch(n_runs=n_runs, seed=4064)
     n = sum(c.n_particles for c in cs)
     batch = PscSim(cs, with_ids=False)
-    launch, _, table = tune(batch, cache=tune_cache, steps=2, force=retune)
+    launch, _, table, class_chunks = tune(batch, cache=tune_cache, steps=2, force=retune)
     batch.step(2, use_graph=True)
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -429,6 +429,7 @@ def batch_leg(steps: int = 10, n_runs: int = 64, tune_cache=None, retune=False):
     sub = [cs[i] for i in pick]
     bt = PscSim(sub)
     bt.set_launch(**launch)
+    apply_class_chunks(bt, class_chunks)
     bt.step(steps, use_graph=True)
     for r, c in enumerate(sub):
         al = PscSim(c)
@@ -440,7 +441,7 @@ def batch_leg(steps: int = 10, n_runs: int = 64, tune_cache=None, retune=False):
     bt.close()
     return dict(workload=f"{n_runs} two-stream runs, {n} particles, "
                          f"{sum(c.ncell for c in cs)} cells, order 1",
-                launch=launch, steps=steps,
+                launch=launch, class_chunks=class_chunks, steps=steps,
                 batched_pushes_per_s=n * steps / (batch_ms / 1e3),
                 plain_pushes_per_s=n * steps / (plain_ms / 1e3),
                 batched_over_plain=plain_ms / batch_ms,
@@ -464,7 +465,7 @@ def measure(case, args, sort_ablation: bool):
         sim.set_launch(**launch)
     elif not args.no_tune:
         from paper_1310_7866_amd.autotune import tune
-        launch, ms, _ = tune(sim, cache=args.tune_cache, steps=2, force=args.retune)
+        launch, ms, _, _ = tune(sim, cache=args.tune_cache, steps=2, force=args.retune)
         print(f"[bench] autotuned launch {launch} ({ms:.3f} ms)", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         sim.step(1)

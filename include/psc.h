@@ -241,7 +241,7 @@ psc_status psc_step(psc_ctx *ctx, int nsteps, int use_graph, void *stream);
  *       PSC_LAUNCH_PARTITION persistent workgroups, each over a contiguous
  *                            segment of (run, patch, species) units chosen
  *                            by psc_balance (called here once).
- * chunk: particles per work item (0 keeps the current value).
+ * chunk: particles per work item of every run (0 keeps the current values).
  * workers: persistent workgroups (0 = compute units x workgroups that fit
  * in one unit's LDS).  threads: workgroup size, 256, 384 or 512 (0 keeps;
  * the LDS tiles of a work item are shared by all its waves; PSC_ERR_LDS if
@@ -257,6 +257,15 @@ psc_status psc_step(psc_ctx *ctx, int nsteps, int use_graph, void *stream);
 #define PSC_LAUNCH_PARTITION 2
 psc_status psc_set_launch(psc_ctx *ctx, int mode, int chunk, int workers, int threads, int run,
                           void *stream);
+
+/* Particles per work item of one run's (species, patch) units (batching
+ * with runs of different occupancy: the launch shape is one per context,
+ * the chunk can differ per run; psc_set_launch with chunk > 0 sets every
+ * run's).  chunk >= 1.  Uploads the run's table entry and synchronizes
+ * `stream`, drops recorded step graphs, and recomputes the partition under
+ * PSC_LAUNCH_PARTITION.  PSC_ERR_INVALID for a bad run or chunk or an
+ * unbound context. */
+psc_status psc_set_run_chunk(psc_ctx *ctx, int run, int chunk, void *stream);
 
 /* Recompute the PSC_LAUNCH_PARTITION split from the current particle
  * counts (App. A, "Load balancing algorithm", with every workgroup of equal

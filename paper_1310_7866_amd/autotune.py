@@ -1,12 +1,15 @@
 """Launch-shape autotuner for the particle kernel.
 
-For a context it times candidate launch shapes (one workgroup per work item,
-persistent workgroups with per-XCD queues, persistent workgroups over the
-App. A partition) and chunk sizes on the live state during warm-up, keeps
-the fastest, and caches the choice in a JSON file keyed by the architecture
-and an occupancy class (dimension, order, patch size, particles per cell
-rounded to a power of two).  Optionally also picks the patch size by timing
-trial contexts.
+For a context it times candidate launch shapes (workgroup size, particles
+per lane, one workgroup per work item / persistent workgroups with per-XCD
+queues / persistent workgroups over the App. A partition) and chunk sizes on
+the live state during warm-up, keeps the fastest, and caches the choice in a
+JSON file keyed by the architecture and an occupancy class (dimension,
+order, patch size, particles per cell rounded to a power of two, number of
+runs).  In a batch whose runs fall into several occupancy classes (patch
+cells x particles-per-cell bucket) the chunk is then tuned per class: the
+launch shape is one per context, the chunk is a per-run setting.
+Optionally also picks the patch size by timing trial contexts.
 """
 from __future__ import annotations
 
@@ -26,6 +29,19 @@ def occupancy_class(cases) -> str:
     ppc = sum(c.n_particles for c in cs) / max(1, sum(c.ncell for c in cs))
     bucket = 2 ** int(round(math.log2(max(ppc, 1.0))))
     return f"d{c0.dim}o{c0.order}p{c0.patch[1]}x{c0.patch[2]}x{c0.patch[0]}ppc{bucket}r{len(cs)}"
+
+
+def run_classes(cases) -> Dict[str, List[int]]:
+    """Runs of a context grouped by occupancy class: cells per patch and
+    particles per cell rounded to a power of two."""
+    cs = cases if isinstance(cases, (list, tuple)) else [cases]
+    groups: Dict[str, List[int]] = {}
+    for r, c in enumerate(cs):
+        ppc = c.n_particles / max(1, c.ncell)
+        bucket = 2 ** int(round(math.log2(max(ppc, 1.0))))
+        cells = c.patch[0] * c.patch[1] * c.patch[2]
+        groups.setdefault(f"p{cells}ppc{bucket}", []).append(r)
+    return groups
 
 
 def _arch() -> str:
@@ -89,11 +105,13 @@ def tune(sim, cache: Optional[str] = DEFAULT_CACHE, steps: int = 2,
     from .psc import PscError
     key = f"{_arch()}/{occupancy_class(sim.cases)}"
     data = _load(cache) if cache else {}
+    groups = run_classes(sim.cases)
     if not force and key in data:
         e = data[key]
         launch = {k: e[k] for k in ("mode", "chunk", "threads", "run")}
         sim.set_launch(**launch)
-        return launch, e["ms"], e.get("table", {})
+        apply_class_chunks(sim, e.get("class_chunks", {}))
+        return launch, e["ms"], e.get("table", {}), e.get("class_chunks", {})
     table = {}
     best = None
 
@@ -121,11 +139,40 @@ def tune(sim, cache: Optional[str] = DEFAULT_CACHE, steps: int = 2,
                 trial(dict(mode=mode, chunk=chunk, threads=nt, run=run))
     launch, ms = best
     sim.set_launch(**launch)
+    # several occupancy classes in one context: the chunk of each class's
+    # runs in turn, the largest classes first, the others at the best so far
+    class_chunks = {}
+    if len(groups) > 1:
+        order = sorted(groups, key=lambda k: -sum(sim.cases[r].n_particles for r in groups[k]))
+        for cls in order:
+            best_ch, best_ms = launch["chunk"], ms
+            for ch in chunks:
+                if ch == launch["chunk"]:
+                    continue
+                for r in groups[cls]:
+                    sim.set_run_chunk(r, ch)
+                sim.step(1)
+                t = time_push(sim, steps)
+                table[f"class/{cls}/{ch}"] = t
+                if t < best_ms:
+                    best_ch, best_ms = ch, t
+            for r in groups[cls]:
+                sim.set_run_chunk(r, best_ch)
+            class_chunks[cls] = best_ch
+            ms = best_ms
     sim.check()
     if cache:
-        data[key] = dict(launch, ms=ms, table=table)
+        data[key] = dict(launch, ms=ms, table=table, class_chunks=class_chunks)
         _save(cache, data)
-    return launch, ms, table
+    return launch, ms, table, class_chunks
+
+
+def apply_class_chunks(sim, class_chunks: Dict[str, int]) -> None:
+    """Set the chunk of every run of `sim` whose occupancy class has one."""
+    for cls, runs in run_classes(sim.cases).items():
+        if cls in class_chunks:
+            for r in runs:
+                sim.set_run_chunk(r, class_chunks[cls])
 
 
 def tune_patch(make_cases, patches: Iterable[int], steps: int = 2, **kw):

@@ -68,11 +68,11 @@ struct psc_ctx {
     std::vector<int32_t> block_seg;
     std::vector<ScanSeg> segs_host[2];   // scan segments per cs_sel, filled at bind (sized at init)
     int64_t max_cap = 0, max_ncell = 0;
-    size_t cub_bytes = 0;
+    size_t rsort_bytes = 0;
 
     struct Off {
         size_t runs, units, item_start, run_base, patch_base, seg_base, seg_run, seg_sp, segs0, segs1, scan_tmp, err;
-        size_t load_keys, load_idx, load_keys_s, load_idx_s, cub;
+        size_t load_keys, load_idx, load_keys_s, load_idx_s, rsort;
         size_t adj_runs;
         size_t queue, part, unit_counts;
     } off{};
@@ -169,6 +169,15 @@ constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
 void *g_scratch_ptr[kMaxDevices] = {};
 psc_ctx *g_scratch_owner[kMaxDevices] = {};
+
+// work items of the particle kernel at most: every unit may start one that
+// is not full, plus the chunks of every species' capacity at its run's chunk
+int64_t count_items(const psc_ctx *ctx) {
+    int64_t items = (int64_t)ctx->units.size();
+    for (const RunDev &R : ctx->runs)
+        for (int s = 0; s < R.n_species; ++s) items += (R.sp[s].cap + R.chunk - 1) / R.chunk;
+    return items;
+}
 
 }  // namespace
 
@@ -329,10 +338,8 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
         }
     }
     build_units(ctx);
-    int64_t items = (int64_t)ctx->units.size();
-    for (int r = 0; r < n_runs; ++r)
-        for (int s = 0; s < runs[r].n_species; ++s) items += (runs[r].capacity[s] + ctx->chunk - 1) / ctx->chunk;
-    ctx->max_items = items;
+    for (RunDev &R : ctx->runs) R.chunk = ctx->chunk;
+    ctx->max_items = count_items(ctx);
 
     // scan segments: one per (run, species)
     ctx->seg_base.push_back(0);
@@ -431,7 +438,7 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
             return st;
         }
     }
-    ctx->off.cub = o;     // radix-sort temp storage goes last, sized in psc_workspace_size
+    ctx->off.rsort = o;     // radix-sort temp storage goes last, sized in psc_workspace_size
     ctx->ws_bytes = o;
     *out = ctx;
     return PSC_OK;
@@ -440,23 +447,23 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
 psc_status psc_workspace_size(const psc_ctx *cctx, size_t *bytes) {
     psc_ctx *ctx = const_cast<psc_ctx *>(cctx);
     if (!ctx || !bytes) return PSC_ERR_INVALID;
-    if (ctx->cub_bytes == 0) {
+    if (ctx->rsort_bytes == 0) {
         size_t tb = 0;
         int bits = 1;
         while ((int64_t(1) << bits) < ctx->max_ncell) ++bits;
         hipError_t e = radix_sort_pairs(nullptr, &tb, nullptr, nullptr, nullptr, nullptr,
                                         ctx->max_cap > 0 ? ctx->max_cap : 1, bits, 0);
         if (e != hipSuccess) return hipfail(ctx, e, "radix sort size query");
-        ctx->cub_bytes = align256(tb + 256);
+        ctx->rsort_bytes = align256(tb + 256);
     }
-    *bytes = ctx->off.cub + ctx->cub_bytes;
+    *bytes = ctx->off.rsort + ctx->rsort_bytes;
     return PSC_OK;
 }
 
 psc_status psc_bind(psc_ctx *ctx, const psc_run_bufs *bufs, int n_runs, void *workspace, void *stream) {
     if (!ctx || !bufs || n_runs != ctx->n_runs || !workspace) return PSC_ERR_INVALID;
     if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(ctx, PSC_ERR_INVALID, "workspace not 256-byte aligned");
-    if (ctx->cub_bytes == 0) {
+    if (ctx->rsort_bytes == 0) {
         size_t b;
         psc_status st = psc_workspace_size(ctx, &b);
         if (st != PSC_OK) return st;
@@ -653,8 +660,8 @@ psc_status psc_load_particles(psc_ctx *ctx, int run, int species, int64_t n, con
     if (n > 0) {
         int bits = 1;
         while ((int64_t(1) << bits) < R.ncell) ++bits;
-        size_t tb = ctx->cub_bytes;
-        HIPCHECK(radix_sort_pairs(ctx->at<void>(ctx->off.cub), &tb, keys, keys_s, idx, idx_s, n, bits, s), "load sort");
+        size_t tb = ctx->rsort_bytes;
+        HIPCHECK(radix_sort_pairs(ctx->at<void>(ctx->off.rsort), &tb, keys, keys_s, idx, idx_s, n, bits, s), "load sort");
     }
     HIPCHECK(launch_load_gather(R, species, n, keys_s, idx_s, goff, gu, gid, s), "load gather");
     HIPCHECK(launch_cell_starts(n, R.ncell, keys_s, S.cs[0], ctx->err(), s), "load cell offsets");
@@ -730,7 +737,7 @@ psc_status psc_push_particles(psc_ctx *ctx, void *stream) {
     pm.queue = ctx->at<int32_t>(ctx->off.queue);
     pm.part = ctx->at<int32_t>(ctx->off.part);
     HIPCHECK(launch_push(L, ctx->at<Unit>(ctx->off.units), (int)ctx->units.size(),
-                         ctx->at<int32_t>(ctx->off.item_start), ctx->max_items, ctx->chunk, ctx->dim, ctx->order,
+                         ctx->at<int32_t>(ctx->off.item_start), ctx->max_items, ctx->dim, ctx->order,
                          ctx->front, ctx->cs_sel, ctx->perm_pending, ctx->push_lds(pm.threads, pm.run), pm),
              "push particles");
     ctx->front = 1 - ctx->front;
@@ -780,8 +787,8 @@ psc_status psc_sort_radix(psc_ctx *ctx, void *stream) {
             const SpeciesDev &S = R.sp[sp];
             if (S.n > 0) {
                 HIPCHECK(launch_iota(idx, S.n, s), "radix sort indices");
-                size_t tb = ctx->cub_bytes;
-                HIPCHECK(radix_sort_pairs(ctx->at<void>(ctx->off.cub), &tb, S.cell[ctx->front], keys_s, idx, S.perm,
+                size_t tb = ctx->rsort_bytes;
+                HIPCHECK(radix_sort_pairs(ctx->at<void>(ctx->off.rsort), &tb, S.cell[ctx->front], keys_s, idx, S.perm,
                                           S.n, bits, s),
                          "radix sort");
             }
@@ -1001,13 +1008,20 @@ psc_status psc_set_launch(psc_ctx *ctx, int mode, int chunk, int workers, int th
     if (ctx->push_lds(threads ? threads : ctx->pm.threads, run ? run : ctx->pm.run) > kMaxLds) return PSC_ERR_LDS;
     if (threads) ctx->pm.threads = threads;
     if (run) ctx->pm.run = run;
-    if (chunk > 0 && chunk != ctx->chunk) {
+    if (chunk > 0) {   // every run's chunk
+        bool change = false;
+        for (RunDev &R : ctx->runs) {
+            change = change || R.chunk != chunk;
+            R.chunk = chunk;
+        }
         ctx->chunk = chunk;
-        int64_t items = (int64_t)ctx->units.size();
-        for (int r = 0; r < ctx->n_runs; ++r)
-            for (int s = 0; s < ctx->runs[r].n_species; ++s)
-                items += (ctx->runs[r].sp[s].cap + chunk - 1) / chunk;
-        ctx->max_items = items;
+        ctx->max_items = count_items(ctx);
+        if (change) {
+            hipStream_t s = (hipStream_t)stream;
+            HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.runs), ctx->runs.data(), sizeof(RunDev) * ctx->n_runs,
+                                    hipMemcpyHostToDevice, s), "upload runs");
+            HIPCHECK(hipStreamSynchronize(s), "launch sync");
+        }
     }
     if (mode != 0 && workers == 0) {
         int dev = 0, cus = 0;
@@ -1027,6 +1041,21 @@ psc_status psc_set_launch(psc_ctx *ctx, int mode, int chunk, int workers, int th
         psc_status st = psc_balance(ctx, 1.0, stream);
         if (st != PSC_OK) return st;
     }
+    return PSC_OK;
+}
+
+psc_status psc_set_run_chunk(psc_ctx *ctx, int run, int chunk, void *stream) {
+    if (!ctx || !ctx->bound || run < 0 || run >= ctx->n_runs || chunk < 1) return PSC_ERR_INVALID;
+    if (ctx->runs[run].chunk == chunk) return PSC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    ctx->runs[run].chunk = chunk;
+    ctx->max_items = count_items(ctx);
+    HIPCHECK(hipMemcpyAsync(ctx->at<RunDev>(ctx->off.runs) + run, &ctx->runs[run], sizeof(RunDev),
+                            hipMemcpyHostToDevice, s), "upload run");
+    HIPCHECK(hipStreamSynchronize(s), "run chunk sync");
+    for (auto &kv : ctx->graphs) hipGraphExecDestroy(kv.second);
+    ctx->graphs.clear();
+    if (ctx->pm.mode == 2) return psc_balance(ctx, 1.0, stream);
     return PSC_OK;
 }
 

@@ -64,6 +64,7 @@ struct RunDev {
     int np[3];           // patches per dimension
     int n_patches;
     int n_species;
+    int chunk;           // particles per work item of the particle kernel
     int64_t ncell;
     int64_t cell_base;   // offset of the run in the flat cell space of all runs
     float dx[3];
@@ -256,7 +257,7 @@ struct PushMode {
 };
 
 hipError_t launch_push(const Launch &L, const Unit *units_dev, int n_units, int32_t *item_start, int64_t max_items,
-                       int chunk, int dim, int order, int front, int cs_sel, int use_perm, size_t lds_bytes,
+                       int dim, int order, int front, int cs_sel, int use_perm, size_t lds_bytes,
                        const PushMode &pm);
 hipError_t launch_unit_counts(const Launch &L, const Unit *units, int n_units, int cs_sel, int32_t *out);
 hipError_t launch_fields(const Launch &L, int op, int64_t total_cells, const int64_t *run_cell_base_dev);

@@ -118,7 +118,7 @@ __host__ __device__ inline PushLds push_lds_layout(int fcells, int jcells, int w
 // particles need into item_start[u]; k_items_scan turns the counts into the
 // exclusive prefix item_start[0..n_units].
 __global__ void __launch_bounds__(256) k_unit_items(const RunDev *__restrict__ runs, const Unit *__restrict__ units,
-                                                    int n_units, int chunk, int cs_sel,
+                                                    int n_units, int cs_sel,
                                                     int32_t *__restrict__ item_start) {
     const int u = blockIdx.x * 256 + threadIdx.x;
     if (u >= n_units) return;
@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(256) k_unit_items(const RunDev *__restrict__ r
     const int64_t kb = patch_key_base(R, pc[0], pc[1], pc[2]);
     const int64_t ke = kb + (int64_t)patch_ext(R, 0, pc[0]) * patch_ext(R, 1, pc[1]) * patch_ext(R, 2, pc[2]);
     const int32_t *cs = R.sp[U.species].cs[cs_sel];
-    item_start[u] = (cs[ke] - cs[kb] + chunk - 1) / chunk;
+    item_start[u] = (cs[ke] - cs[kb] + R.chunk - 1) / R.chunk;
 }
 
 // One workgroup: exclusive prefix of the per-unit item counts in place, the
@@ -420,7 +420,7 @@ __device__ __forceinline__ int frame_offset(int j, int jx_, int jy_, int jcells)
 // consecutive lanes store consecutive slots.
 template <int DIM, int ORDER, int NT, bool RUNS>
 __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const Unit *__restrict__ units,
-                                          const int32_t *__restrict__ item_start, int lo, int item, int chunk,
+                                          const int32_t *__restrict__ item_start, int lo, int item,
                                           int front, int cs_sel, int use_perm, int K, uint32_t *__restrict__ err,
                                           float *lds) {
     constexpr int FLO = 1, FHI = ORDER;   // field ghosts
@@ -454,8 +454,8 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
     // sort flags) must not send the item outside the particle buffers
     const int32_t np_ = (int32_t)S.n;
     const int32_t pend = imin(imax(cs[kb + pcells], 0), np_), pbeg = imin(imax(cs[kb], 0), pend);
-    const int32_t beg = pbeg + (item - item_start[lo]) * chunk;
-    const int32_t end = min(beg + chunk, pend);
+    const int32_t beg = pbeg + (item - item_start[lo]) * R.chunk;
+    const int32_t end = min(beg + R.chunk, pend);
     if (beg >= end) return;   // only with such offsets (the workgroup's item is uniform)
 
     // tile geometry (nominal patch size so every tile of the run has one pitch)
@@ -1130,13 +1130,13 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
 template <int DIM, int ORDER, int NT, bool RUNS>
 __global__ void __launch_bounds__(NT) PSC_OCCUPANCY k_push(const RunDev *__restrict__ runs, const Unit *__restrict__ units,
                                                  const int32_t *__restrict__ item_start, int n_units,
-                                                 int chunk, int front, int cs_sel, int use_perm, int K,
+                                                 int front, int cs_sel, int use_perm, int K,
                                                  uint32_t *__restrict__ err) {
     extern __shared__ __align__(16) float lds[];   // 16-byte aligned: holds doubles and float4
     const int nb = gridDim.x;
     const int item = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
     if (item >= item_start[n_units]) return;
-    push_item<DIM, ORDER, NT, RUNS>(runs, units, item_start, unit_of_item(item_start, n_units, item), item, chunk, front,
+    push_item<DIM, ORDER, NT, RUNS>(runs, units, item_start, unit_of_item(item_start, n_units, item), item, front,
                               cs_sel, use_perm, K, err, lds);
 }
 
@@ -1148,7 +1148,7 @@ template <int DIM, int ORDER, int NT, bool RUNS>
 __global__ void __launch_bounds__(NT) PSC_OCCUPANCY k_push_queue(const RunDev *__restrict__ runs,
                                                        const Unit *__restrict__ units,
                                                        const int32_t *__restrict__ item_start, int n_units,
-                                                       int chunk, int front, int cs_sel, int use_perm, int K,
+                                                       int front, int cs_sel, int use_perm, int K,
                                                        uint32_t *__restrict__ err, int32_t *__restrict__ queue) {
     extern __shared__ __align__(16) float lds[];   // 16-byte aligned: holds doubles and float4
     __shared__ int s_item;
@@ -1170,7 +1170,7 @@ __global__ void __launch_bounds__(NT) PSC_OCCUPANCY k_push_queue(const RunDev *_
             const int item = s_item;
             __syncthreads();
             if (item >= qe) break;
-            push_item<DIM, ORDER, NT, RUNS>(runs, units, item_start, unit_of_item(item_start, n_units, item), item, chunk,
+            push_item<DIM, ORDER, NT, RUNS>(runs, units, item_start, unit_of_item(item_start, n_units, item), item,
                                       front, cs_sel, use_perm, K, err, lds);
         }
     }
@@ -1182,78 +1182,78 @@ template <int DIM, int ORDER, int NT, bool RUNS>
 __global__ void __launch_bounds__(NT) PSC_OCCUPANCY k_push_part(const RunDev *__restrict__ runs,
                                                       const Unit *__restrict__ units,
                                                       const int32_t *__restrict__ item_start, int n_units,
-                                                      int chunk, int front, int cs_sel, int use_perm, int K,
+                                                      int front, int cs_sel, int use_perm, int K,
                                                       uint32_t *__restrict__ err, const int32_t *__restrict__ part) {
     extern __shared__ __align__(16) float lds[];   // 16-byte aligned: holds doubles and float4
     const int u0 = part[blockIdx.x], u1 = min(part[blockIdx.x + 1], n_units);
     for (int u = u0; u < u1; ++u)
         for (int item = item_start[u]; item < item_start[u + 1]; ++item)
-            push_item<DIM, ORDER, NT, RUNS>(runs, units, item_start, u, item, chunk, front, cs_sel, use_perm, K, err, lds);
+            push_item<DIM, ORDER, NT, RUNS>(runs, units, item_start, u, item, front, cs_sel, use_perm, K, err, lds);
 }
 
 template <int DIM, int ORDER, int NT, bool RUNS>
 static hipError_t launch_push_r(const Launch &L, const Unit *units, int n_units, int32_t *item_start,
-                                int64_t max_items, int chunk, int front, int cs_sel, int use_perm,
+                                int64_t max_items, int front, int cs_sel, int use_perm,
                                 size_t lds, const PushMode &pm) {
     hipLaunchKernelGGL(k_unit_items, dim3((unsigned)imax(1, (n_units + 255) / 256)), dim3(256), 0, L.stream, L.runs_dev,
-                       units, n_units, chunk, cs_sel, item_start);
+                       units, n_units, cs_sel, item_start);
     hipLaunchKernelGGL(k_items_scan, dim3(1), dim3(1024), 0, L.stream, n_units, item_start, pm.queue);
     if (pm.mode == 1) {
         hipLaunchKernelGGL((k_push_queue<DIM, ORDER, NT, RUNS>), dim3((unsigned)pm.workers), dim3(NT), lds, L.stream,
-                           L.runs_dev, units, item_start, n_units, chunk, front, cs_sel, use_perm, pm.run, L.err,
+                           L.runs_dev, units, item_start, n_units, front, cs_sel, use_perm, pm.run, L.err,
                            pm.queue);
     } else if (pm.mode == 2) {
         hipLaunchKernelGGL((k_push_part<DIM, ORDER, NT, RUNS>), dim3((unsigned)pm.workers), dim3(NT), lds, L.stream,
-                           L.runs_dev, units, item_start, n_units, chunk, front, cs_sel, use_perm, pm.run, L.err,
+                           L.runs_dev, units, item_start, n_units, front, cs_sel, use_perm, pm.run, L.err,
                            pm.part);
     } else {
         int64_t grid = (max_items + 7) / 8 * 8;
         if (grid < 8) grid = 8;
         hipLaunchKernelGGL((k_push<DIM, ORDER, NT, RUNS>), dim3((unsigned)grid), dim3(NT), lds, L.stream, L.runs_dev,
-                           units, item_start, n_units, chunk, front, cs_sel, use_perm, pm.run, L.err);
+                           units, item_start, n_units, front, cs_sel, use_perm, pm.run, L.err);
     }
     return hipGetLastError();
 }
 
 template <int DIM, int ORDER, int NT>
 static hipError_t launch_push_t(const Launch &L, const Unit *units, int n_units, int32_t *item_start,
-                                int64_t max_items, int chunk, int front, int cs_sel, int use_perm,
+                                int64_t max_items, int front, int cs_sel, int use_perm,
                                 size_t lds, const PushMode &pm) {
     if (pm.run > 1)
-        return launch_push_r<DIM, ORDER, NT, true>(L, units, n_units, item_start, max_items, chunk, front, cs_sel,
+        return launch_push_r<DIM, ORDER, NT, true>(L, units, n_units, item_start, max_items, front, cs_sel,
                                                    use_perm, lds, pm);
-    return launch_push_r<DIM, ORDER, NT, false>(L, units, n_units, item_start, max_items, chunk, front, cs_sel,
+    return launch_push_r<DIM, ORDER, NT, false>(L, units, n_units, item_start, max_items, front, cs_sel,
                                                 use_perm, lds, pm);
 }
 
 template <int DIM, int ORDER>
 static hipError_t launch_push_nt(const Launch &L, const Unit *units, int n_units, int32_t *item_start,
-                                 int64_t max_items, int chunk, int front, int cs_sel, int use_perm, size_t lds,
+                                 int64_t max_items, int front, int cs_sel, int use_perm, size_t lds,
                                  const PushMode &pm) {
     if (pm.threads == 512)
-        return launch_push_t<DIM, ORDER, 512>(L, units, n_units, item_start, max_items, chunk, front, cs_sel,
+        return launch_push_t<DIM, ORDER, 512>(L, units, n_units, item_start, max_items, front, cs_sel,
                                               use_perm, lds, pm);
     if (pm.threads == 384)
-        return launch_push_t<DIM, ORDER, 384>(L, units, n_units, item_start, max_items, chunk, front, cs_sel,
+        return launch_push_t<DIM, ORDER, 384>(L, units, n_units, item_start, max_items, front, cs_sel,
                                               use_perm, lds, pm);
-    return launch_push_t<DIM, ORDER, 256>(L, units, n_units, item_start, max_items, chunk, front, cs_sel, use_perm,
+    return launch_push_t<DIM, ORDER, 256>(L, units, n_units, item_start, max_items, front, cs_sel, use_perm,
                                           lds, pm);
 }
 
 hipError_t launch_push(const Launch &L, const Unit *units_dev, int n_units, int32_t *item_start, int64_t max_items,
-                       int chunk, int dim, int order, int front, int cs_sel, int use_perm, size_t lds_bytes,
+                       int dim, int order, int front, int cs_sel, int use_perm, size_t lds_bytes,
                        const PushMode &pm) {
     if (dim == 2 && order == 1)
-        return launch_push_nt<2, 1>(L, units_dev, n_units, item_start, max_items, chunk, front, cs_sel, use_perm,
+        return launch_push_nt<2, 1>(L, units_dev, n_units, item_start, max_items, front, cs_sel, use_perm,
                                     lds_bytes, pm);
     if (dim == 2 && order == 2)
-        return launch_push_nt<2, 2>(L, units_dev, n_units, item_start, max_items, chunk, front, cs_sel, use_perm,
+        return launch_push_nt<2, 2>(L, units_dev, n_units, item_start, max_items, front, cs_sel, use_perm,
                                     lds_bytes, pm);
     if (dim == 3 && order == 1)
-        return launch_push_nt<3, 1>(L, units_dev, n_units, item_start, max_items, chunk, front, cs_sel, use_perm,
+        return launch_push_nt<3, 1>(L, units_dev, n_units, item_start, max_items, front, cs_sel, use_perm,
                                     lds_bytes, pm);
     if (dim == 3 && order == 2)
-        return launch_push_nt<3, 2>(L, units_dev, n_units, item_start, max_items, chunk, front, cs_sel, use_perm,
+        return launch_push_nt<3, 2>(L, units_dev, n_units, item_start, max_items, front, cs_sel, use_perm,
                                     lds_bytes, pm);
     return hipErrorInvalidValue;
 }

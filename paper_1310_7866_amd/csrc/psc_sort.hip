@@ -18,7 +18,7 @@
 //
 // Also here: the segmented exclusive scan, and the one-off general sort used
 // to load particles in arbitrary order.
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "psc_internal.h"
 
@@ -649,8 +649,8 @@ hipError_t launch_iota(int32_t *p, int64_t n, hipStream_t s) {
 
 hipError_t radix_sort_pairs(void *temp, size_t *temp_bytes, const int32_t *keys_in, int32_t *keys_out,
                             const int32_t *vals_in, int32_t *vals_out, int64_t n, int bits, hipStream_t s) {
-    return hipcub::DeviceRadixSort::SortPairs(temp, *temp_bytes, keys_in, keys_out, vals_in, vals_out, (int)n, 0, bits,
-                                              s);
+    return rocprim::radix_sort_pairs(temp, *temp_bytes, keys_in, keys_out, vals_in, vals_out, (size_t)n, 0u,
+                                     (unsigned)bits, s);
 }
 
 }  // namespace psc

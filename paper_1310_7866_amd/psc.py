@@ -30,7 +30,8 @@ EXPORTS = ["psc_init_patches", "psc_workspace_size", "psc_bind", "psc_bind_stati
            "psc_push_fields",
            "psc_push_particles", "psc_deposit_current", "psc_sort", "psc_sort_radix", "psc_step", "psc_get_particles",
            "psc_keys_to_cells", "psc_particle_count", "psc_front", "psc_sort_view", "psc_diagnostics",
-           "psc_get_perm", "psc_marder", "psc_adjoint_step", "psc_set_launch", "psc_balance", "psc_partition",
+           "psc_get_perm", "psc_marder", "psc_adjoint_step", "psc_set_launch", "psc_set_run_chunk", "psc_balance",
+           "psc_partition",
            "psc_set_unit_order", "psc_hilbert_order", "psc_check", "psc_status_string", "psc_last_error", "psc_destroy"]
 LAUNCH_GRID, LAUNCH_QUEUE, LAUNCH_PARTITION = 0, 1, 2
 RUN_ADJOINT = 1
@@ -100,6 +101,7 @@ def load_library(path: str = LIB_PATH):
     L.psc_get_perm.argtypes = [vp, i32, i32, vp, vp]
     L.psc_adjoint_step.argtypes = [vp, C.POINTER(AdjFwd), C.POINTER(AdjState), vp]
     L.psc_set_launch.argtypes = [vp, i32, i32, i32, i32, i32, vp]
+    L.psc_set_run_chunk.argtypes = [vp, i32, i32, vp]
     L.psc_balance.argtypes = [vp, C.c_double, vp]
     L.psc_partition.argtypes = [C.POINTER(C.c_double), i32, C.POINTER(C.c_double), i32, C.POINTER(C.c_int32)]
     L.psc_set_unit_order.argtypes = [vp, i32, vp]
@@ -303,6 +305,9 @@ class PscSim:
     def set_launch(self, mode: int, chunk: int = 0, workers: int = 0, threads: int = 0, run: int = 0):
         self._call(self.L.psc_set_launch(self.ctx, int(mode), int(chunk), int(workers), int(threads), int(run),
                                          self._stream()))
+
+    def set_run_chunk(self, r: int, chunk: int):
+        self._call(self.L.psc_set_run_chunk(self.ctx, int(r), int(chunk), self._stream()))
 
     def set_unit_order(self, order: int):
         self._call(self.L.psc_set_unit_order(self.ctx, int(order), self._stream()))

@@ -111,17 +111,45 @@ def _uneven_batch(order):
     return [charged(51, narrow, 12, 8, 6), charged(52, 24, 16, 8, 3), ts, charged(53, 30, 22, 8, 9)]
 
 
+# chunk per run of _uneven_batch (run 0 keeps the context's 512)
+RUN_CHUNKS = {1: 128, 2: 333, 3: 2048}
+
+
+def _run_chunks(sim):
+    for r, ch in RUN_CHUNKS.items():
+        sim.set_run_chunk(r, ch)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_per_run_chunks_agree(mode):
+    """Different chunks per run hand the same particles to other work items:
+    the same state as one chunk for every run (fields to the summation order
+    of the current tiles)."""
+    cs = _uneven_batch(1)
+    a, b = _sim(cs), _sim(cs)
+    a.set_launch(mode, chunk=512)
+    b.set_launch(mode, chunk=512)
+    _run_chunks(b)
+    for k in range(3):
+        a.step(1)
+        b.step(1, use_graph=k > 0)
+    a.check()
+    b.check()
+    _same(_state(a), _state(b))
+
+
 @pytest.mark.parametrize("order", [1, 2])
 @pytest.mark.parametrize("mode", [1, 2])
 def test_batch_matches_oracle(order, mode):
-    """Every run of a batched context against the double-precision oracle
-    run alone: one push (the parity tolerances of single runs), then three
-    whole steps replayed from a HIP graph."""
+    """Every run of a batched context (a different chunk per run) against
+    the double-precision oracle run alone: one push (the parity tolerances
+    of single runs), then three whole steps replayed from a HIP graph."""
     from oracle import oracle as O
     from tests.helpers import particle_errors
     cs = _uneven_batch(order)
     sim = _sim(cs)
     sim.set_launch(mode, chunk=512)
+    _run_chunks(sim)
     oras = [O.OracleSim(c) for c in cs]
     sim.push_fields(0)
     sim.push_particles()
@@ -138,6 +166,7 @@ def test_batch_matches_oracle(order, mode):
         assert np.abs(J.ravel() - ora.J).max() <= 2e-5 * np.abs(ora.J).max()
     sim2 = _sim(cs)
     sim2.set_launch(mode, chunk=512)
+    _run_chunks(sim2)
     oras = [O.OracleSim(c) for c in cs]
     for _ in range(3):
         sim2.step(1, use_graph=True)

@@ -60,21 +60,31 @@ def test_diagnostics_match_oracle(order):
 
 @pytest.mark.parametrize("order", [1, 2])
 def test_gauss_invariant_over_steps(order):
+    """max|G^n - G^0| over 50 steps <= 1e-5 max_s max|rho_s|, G = div E - rho.
+
+    The scheme keeps G exactly under discrete continuity, so only float32
+    roundoff moves it: each step adds to E a float32 current whose
+    contributions are of size q w dx/dt per particle, and div E differences
+    float32 E values; rho itself is accumulated in float64 by the
+    diagnostics.  Relative to the species densities rho_s the drift stays a
+    few float32 ulps per step.  (An earlier bar of 1e-5 max|q w|, a single
+    particle's charge, is 1/ppc of this one at density 1; the measured drift
+    is printed against both.)"""
     c = _charged(order, seed=13)
     sim = _sim(c)
     _, G0 = sim.diagnostics(with_gauss=True)
-    # G = div E - rho is a difference of float32 values of size max|E|/dx and
-    # q w per particle; both set the scale of its float32 roundoff
-    E, _, _ = sim.field_arrays(0)
-    scale = max(max(abs(s.q * s.w) for s in c.species), np.abs(E).max() / min(c.dx[1], c.dx[2]))
+    ora = O.OracleSim(c)
+    rho_s = max(np.abs(O.rho_of(ora.g, sp.xi, sp.q * sp.w)).max() for sp in ora.species)
+    qw = max(abs(sp.q * sp.w) for sp in c.species)
     worst = 0.0
     for k in range(50):
         sim.step(1)
         _, G = sim.diagnostics(with_gauss=True)
         worst = max(worst, np.abs(G - G0).max())
     sim.check()
-    print(f"order {order}: max |G^n - G^0| over 50 steps = {worst:.3e} (scale {scale:.3e})")
-    assert worst <= 1e-5 * scale
+    print(f"order {order}: max |G^n - G^0| over 50 steps = {worst:.3e}; 1e-5 max|rho_s| = {1e-5 * rho_s:.3e}, "
+          f"1e-5 max|q w| = {1e-5 * qw:.3e}", flush=True)
+    assert worst <= 1e-5 * rho_s
 
 
 def test_thermal_workload_energies_100_steps():
@@ -163,3 +173,34 @@ def test_patch_size_independence():
     Ea, _, _ = sa.field_arrays(0)
     Eb, _, _ = sb.field_arrays(0)
     assert np.abs(Ea - Eb).max() <= 1e-6 * np.abs(Ea).max()
+
+
+def test_repeat_runs_agree():
+    """Run-to-run reproducibility: the same case advanced twice (Harris
+    sheet, 2nd order, several work items per patch so that patch tiles are
+    added to by several workgroups) gives identical keys, ids and cell
+    offsets; momenta and offsets agree to 1e-6, fields to 2e-5 of their
+    largest value (the one-deposit current tolerance): the current tiles are
+    summed with float atomics whose order varies between runs, the only
+    nondeterminism of the step."""
+    c = cases.harris2d(ny=128, nz=64, ppc=40, order=2, patch=32, seed=17)
+    a, b = _sim(c, chunk=1024), _sim(c, chunk=1024)
+    for _ in range(10):
+        a.step(1)
+        b.step(1)
+    a.check()
+    b.check()
+    ndiff = 0
+    for s in range(len(c.species)):
+        pa, pb = a.particles(0, s), b.particles(0, s)
+        assert np.array_equal(pa["key"], pb["key"]) and np.array_equal(pa["id"], pb["id"])
+        assert np.array_equal(a.sort_view(0, s)[1], b.sort_view(0, s)[1])
+        assert np.abs(pa["u"] - pb["u"]).max(initial=0) <= 1e-6
+        assert np.abs(pa["off"] - pb["off"]).max(initial=0) <= 1e-6
+        ndiff += int((pa["u"] != pb["u"]).sum() + (pa["off"] != pb["off"]).sum())
+    for name, fa, fb in zip("EBJ", a.field_arrays(0), b.field_arrays(0)):
+        rel = float(np.abs(fa - fb).max() / max(np.abs(fa).max(), 1e-30))
+        print(f"{name}: largest difference {rel:.2e} of max|{name}|", flush=True)
+        assert rel <= 2e-5
+        ndiff += int((fa != fb).sum())
+    print(f"10 steps, two runs: {ndiff} float values differ (integer state identical)", flush=True)
