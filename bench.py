@@ -457,6 +457,9 @@ def measure(case, args, sort_ablation: bool):
     print(f"[bench] workload {case.name}: gdims={case.gdims} order={case.order} patch={case.patch} "
           f"particles={case.n_particles}", file=sys.stderr, flush=True)
     sim = PscSim(case, with_ids=False, chunk=args.chunk)
+    if args.unit_order:
+        from paper_1310_7866_amd.psc import ORDER_HILBERT, ORDER_ROWMAJOR
+        sim.set_unit_order(ORDER_HILBERT if args.unit_order == "hilbert" else ORDER_ROWMAJOR)
     stream = torch.cuda.current_stream()
     launch = None
     if args.launch:
@@ -551,6 +554,9 @@ def main():
     ap.add_argument("--launch", default="", help="fixed launch shape mode,chunk,threads,run (skips tuning)")
     ap.add_argument("--tune-cache", default=TUNED, help="autotuner cache (JSON) to read and extend")
     ap.add_argument("--retune", action="store_true", help="time every launch shape again")
+    ap.add_argument("--unit-order", choices=("hilbert", "rowmajor"), default=None,
+                    help="order in which patches are handed out to the particle kernel's workgroups "
+                         "(default: the library's, row-major)")
     ap.add_argument("--calibrate", action="store_true",
                     help="first run a 1 GiB fill and a 1 GiB device copy (reference kernels of known "
                          "traffic for hardware-counter runs)")
@@ -608,7 +614,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload_label(case), "particles": case.n_particles, "cells": case.ncell,
                    "order": case.order, "patch": list(case.patch), "parallelism": "single GPU",
-                   "launch": res["launch"]},
+                   "launch": res["launch"], "unit_order": args.unit_order or "rowmajor"},
         "push_kernel_ms": res["push_kernel_ms"],
         "push_kernel_pushes_per_s": res["push_kernel_pushes_per_s"],
         "sort_ms": res["sort_ms"],

@@ -289,7 +289,9 @@ psc_status psc_partition(const double *L, int n_patches, const double *C, int n_
  * item range (PSC_LAUNCH_GRID) or one workgroup's partition segment
  * (PSC_LAUNCH_PARTITION) covers; it does not change the particle layout,
  * the cell keys or any result beyond the summation order of the current.
- * PSC_ORDER_HILBERT is the default. */
+ * PSC_ORDER_ROWMAJOR is the default: it hands each XCD a contiguous range of
+ * the patch-major particle arrays, and on one GPU it is the faster of the
+ * two (the Hilbert order spreads an XCD's items over the arrays). */
 #define PSC_ORDER_ROWMAJOR 0   /* patch index order, x fastest               */
 #define PSC_ORDER_HILBERT 1    /* psc_hilbert_order                           */
 
@@ -395,6 +397,13 @@ typedef struct {
  * the call's end.  Successive calls on different streams must be ordered by
  * the caller, since they share the adjoint scratch. */
 psc_status psc_adjoint_step(psc_ctx *ctx, const psc_adj_fwd *fwd, const psc_adj_state *adj, void *stream);
+
+/* Seed of the reverse pass for W = final field energy, 1/2 sum(E^2 + B^2) dV
+ * (psc_diagnostics [0] + [1]), from the context's current fields: per run
+ * lE = dW/dE = E dV, lB = dW/dB = B dV, and the particle adjoints loff, lu
+ * (D x n and 3 x n, n the current particle count) zero.  adj holds n_runs
+ * entries of caller device arrays.  Asynchronous on `stream`. */
+psc_status psc_adjoint_seed(psc_ctx *ctx, const psc_adj_state *adj, void *stream);
 
 /* Synchronize `stream` and return the device error word as a status:
  * PSC_OK, PSC_ERR_NONFINITE, PSC_ERR_PARTICLE. *word (optional) receives the

@@ -1,34 +1,23 @@
 """Gradient of the final field energy through the GPU time steps.
 
 W = 1/2 sum(E^2 + B^2) dV after N steps.  The forward pass keeps a full
-device snapshot every ``every`` steps; the reverse pass restores each
-snapshot in turn, recomputes its segment while keeping every step's state and
-sort permutation, and runs the hand-written reverse step (psc_adjoint_step)
+device snapshot every ``every`` steps; the reverse pass seeds the adjoint
+state in the library (psc_adjoint_seed), restores each snapshot in turn,
+recomputes its segment while keeping every step's state and sort
+permutation, and runs the hand-written reverse step (psc_adjoint_step)
 backwards through the segment.  The result is dW/dE^{1/2}, dW/dB^0 and
 dW/du^0 of every particle (in the case's particle order).
 
 ``FieldEnergy`` exposes the same computation as a torch.autograd.Function of
-the initial fields and momenta.
+the initial fields and momenta; it keeps one context per (case, steps,
+checkpoint interval), loads new inputs into it on the device, and returns
+the gradients on the inputs' device.
 """
 from __future__ import annotations
-
-import dataclasses
 
 import numpy as np
 
 from .psc import PscSim
-
-
-def _seed(sim):
-    torch = sim.torch
-    lam = []
-    for r, c in enumerate(sim.cases):
-        E, B, _ = sim.fields[r]
-        dV = c.dx[1] * c.dx[2] * (c.dx[0] if c.dim == 3 else 1.0)
-        lam.append(dict(lE=(E * dV).contiguous(), lB=(B * dV).contiguous(),
-                        loff=[torch.zeros(c.dim * sp.n, dtype=torch.float32, device=sim.device) for sp in c.species],
-                        lu=[torch.zeros(3 * sp.n, dtype=torch.float32, device=sim.device) for sp in c.species]))
-    return lam
 
 
 def _state(sim):
@@ -46,6 +35,36 @@ class EnergyGradient:
     def __init__(self, cases, nsteps: int, every: int = 10, chunk: int = 0):
         self.sim = PscSim(cases, adjoint=True, chunk=chunk)
         self.nsteps, self.every = int(nsteps), int(every)
+        sim, torch = self.sim, self.sim.torch
+        # positions of the initial particles (fixed inputs) for reloading
+        # new momenta, and the adjoint state, allocated once
+        self._pos, self.lam = [], []
+        for r, c in enumerate(sim.cases):
+            self._pos.append([(torch.from_numpy(np.ascontiguousarray(sp.cell, dtype=np.int32)).to(sim.device),
+                               torch.from_numpy(np.ascontiguousarray(sp.off, dtype=np.float32).reshape(-1))
+                               .to(sim.device)) for sp in c.species])
+            f32 = torch.float32
+            self.lam.append(dict(lE=torch.empty(3 * c.ncell, dtype=f32, device=sim.device),
+                                 lB=torch.empty(3 * c.ncell, dtype=f32, device=sim.device),
+                                 loff=[torch.empty(c.dim * max(sp.n, 1), dtype=f32, device=sim.device)
+                                       for sp in c.species],
+                                 lu=[torch.empty(3 * max(sp.n, 1), dtype=f32, device=sim.device)
+                                     for sp in c.species]))
+
+    def set_initial(self, E0, B0, u0):
+        """Restart from new initial fields and momenta (device tensors, float32,
+        per run: E0, B0 of 3 * ncell values, u0 a list of (3, n) per species),
+        positions as in the case."""
+        sim, torch = self.sim, self.sim.torch
+        for r, c in enumerate(sim.cases):
+            E, B, _ = sim.fields[r]
+            E.copy_(E0[r].reshape(-1))
+            B.copy_(B0[r].reshape(-1))
+            for s, sp in enumerate(c.species):
+                cell, off = self._pos[r][s]
+                u = u0[r][s].to(device=sim.device, dtype=torch.float32).reshape(-1).contiguous()
+                ids = torch.arange(sp.n, dtype=torch.int32, device=sim.device)
+                sim.load(r, s, cell, off, u, ids)
 
     def forward(self):
         sim, torch = self.sim, self.sim.torch
@@ -65,12 +84,15 @@ class EnergyGradient:
         self.W = d[:, 0] + d[:, 1]
         return self.W
 
-    def backward(self):
+    def backward_device(self):
+        """Reverse pass; per run (dW/dE0 (3, ncell), dW/dB0 (3, ncell),
+        [dW/du0 (3, n) per species in case order]) as device tensors."""
         sim, torch = self.sim, self.sim.torch
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         a.record()
-        lam = _seed(sim)
+        lam = self.lam
+        sim.adjoint_seed(lam)
         for k0, snap in reversed(self.ckpts):
             k1 = min(k0 + self.every, self.nsteps)
             sim.restore(snap)
@@ -87,20 +109,23 @@ class EnergyGradient:
         torch.cuda.synchronize()
         self.adjoint_ms = a.elapsed_time(b)
         sim.check()
-        # map particle adjoints from the initial sorted order to case order
+        # particle adjoints from the initial sorted order to case order
         out = []
         snap0 = self.ckpts[0][1]
         for r, c in enumerate(sim.cases):
-            gE = lam[r]["lE"].cpu().numpy().reshape(3, -1)
-            gB = lam[r]["lB"].cpu().numpy().reshape(3, -1)
             gU = []
             for s, sp in enumerate(c.species):
-                ids = snap0[r]["parts"][s]["id"].cpu().numpy()
-                g = np.empty((3, sp.n), np.float32)
-                g[:, ids] = lam[r]["lu"][s].cpu().numpy().reshape(3, sp.n)
+                ids = snap0[r]["parts"][s]["id"].long()
+                g = torch.empty((3, sp.n), dtype=torch.float32, device=sim.device)
+                g[:, ids] = lam[r]["lu"][s][:3 * sp.n].view(3, sp.n)
                 gU.append(g)
-            out.append((gE, gB, gU))
+            out.append((lam[r]["lE"].view(3, -1).clone(), lam[r]["lB"].view(3, -1).clone(), gU))
         return out
+
+    def backward(self):
+        """backward_device with numpy arrays."""
+        return [(gE.cpu().numpy(), gB.cpu().numpy(), [g.cpu().numpy() for g in gU])
+                for gE, gB, gU in self.backward_device()]
 
 
 def energy_gradient(case, nsteps: int, every: int = 10, chunk: int = 0):
@@ -111,6 +136,25 @@ def energy_gradient(case, nsteps: int, every: int = 10, chunk: int = 0):
     return float(W[0]), gE, gB, gU, eg.forward_ms, eg.adjoint_ms
 
 
+# contexts of FieldEnergy, keyed by (id(case), nsteps, every); the case is
+# kept with its context so that its id is not reused while cached
+_CONTEXTS = {}
+_MAX_CONTEXTS = 4
+
+
+def _context(case, nsteps: int, every: int) -> EnergyGradient:
+    key = (id(case), int(nsteps), int(every))
+    hit = _CONTEXTS.get(key)
+    if hit is not None and hit[0] is case:
+        return hit[1]
+    while len(_CONTEXTS) >= _MAX_CONTEXTS:
+        _, (_, old) = _CONTEXTS.popitem()
+        old.sim.close()
+    eg = EnergyGradient(case, nsteps, every)
+    _CONTEXTS[key] = (case, eg)
+    return eg
+
+
 def _torch_function():
     import torch
 
@@ -118,26 +162,26 @@ def _torch_function():
         """W(E0, B0, u0 of each species) = final field energy after nsteps.
 
         Inputs are float32 tensors with the case's layouts: E0, B0 (3, ncell)
-        and u0 (3, n) per species; positions come from ``case``."""
+        and u0 (3, n) per species; positions come from ``case``.  W and the
+        gradients are on E0's device."""
 
         @staticmethod
         def forward(ctx, case, nsteps, every, E0, B0, *u0):
-            c = dataclasses.replace(
-                case, E=E0.detach().cpu().numpy().astype(np.float32).reshape(3, -1).copy(),
-                B=B0.detach().cpu().numpy().astype(np.float32).reshape(3, -1).copy(),
-                species=[dataclasses.replace(sp, u=u.detach().cpu().numpy().astype(np.float32).copy())
-                         for sp, u in zip(case.species, u0)])
-            eg = EnergyGradient(c, nsteps, every)
+            eg = _context(case, nsteps, every)
+            dev = eg.sim.device
+            eg.set_initial([E0.detach().to(dev, torch.float32)], [B0.detach().to(dev, torch.float32)],
+                           [[u.detach() for u in u0]])
             W = eg.forward()
             ctx.eg = eg
-            return torch.tensor(float(W[0]), dtype=torch.float64)
+            ctx.like = [(t.shape, t.device) for t in (E0, B0, *u0)]
+            return torch.tensor(float(W[0]), dtype=torch.float64, device=E0.device)
 
         @staticmethod
         def backward(ctx, gW):
-            (gE, gB, gU), = ctx.eg.backward()
-            g = float(gW)
-            grads = [torch.from_numpy(gE * g), torch.from_numpy(gB * g)] + [torch.from_numpy(x * g) for x in gU]
-            return (None, None, None, *grads)
+            (gE, gB, gU), = ctx.eg.backward_device()
+            g = gW.to(gE.device, torch.float32)
+            grads = [gE * g, gB * g] + [x * g for x in gU]
+            return (None, None, None, *[t.reshape(shape).to(dev) for t, (shape, dev) in zip(grads, ctx.like)])
 
     return FieldEnergy
 

@@ -798,6 +798,23 @@ __global__ void __launch_bounds__(256) k_adj_fold(const RunDev *__restrict__ run
     }
 }
 
+// Adjoint seed of W = 1/2 sum(E^2 + B^2) dV at the final state: dW/dE = E dV,
+// dW/dB = B dV (n = 3 ncell values of one run).
+__global__ void k_adj_seed(const float *__restrict__ E, const float *__restrict__ B, float *__restrict__ lE,
+                           float *__restrict__ lB, int64_t n, float dV) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    lE[i] = E[i] * dV;
+    lB[i] = B[i] * dV;
+}
+
+hipError_t launch_adj_seed(const float *E, const float *B, float *lE, float *lB, int64_t n, float dV,
+                           hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adj_seed, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, E, B, lE, lB, n, dV);
+    return hipGetLastError();
+}
+
 size_t adjoint_lds_bytes(int order, const int P[3]) {
     const int fcells = (P[1] + 1 + order) * (P[2] + 1 + order);
     const int jcells = (P[1] + 2 * order + 1) * (P[2] + 2 * order + 1);

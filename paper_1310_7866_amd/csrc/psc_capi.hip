@@ -52,7 +52,7 @@ struct psc_ctx {
     size_t ws_bytes = 0;
     char *ws = nullptr;
     std::vector<Unit> units;
-    int unit_order = PSC_ORDER_HILBERT;  // patch order of the units within a run
+    int unit_order = PSC_ORDER_ROWMAJOR;  // patch order of the units within a run
     int64_t max_items = 0;
     int64_t total_cells = 0;
     std::vector<int64_t> run_base;       // n_runs + 1
@@ -1128,6 +1128,26 @@ psc_status psc_adjoint_step(psc_ctx *ctx, const psc_adj_fwd *fwd, const psc_adj_
                             ctx->order, ctx->total_cells, ctx->at<int64_t>(ctx->off.run_base), ctx->adj_lds, s),
              "adjoint step");
     HIPCHECK(hipEventRecord(ctx->adj_done[slot], s), "adjoint step event");
+    return PSC_OK;
+}
+
+psc_status psc_adjoint_seed(psc_ctx *ctx, const psc_adj_state *adj, void *stream) {
+    if (!ctx || !ctx->bound || !adj) return PSC_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    for (int r = 0; r < ctx->n_runs; ++r) {
+        const RunDev &R = ctx->runs[r];
+        const psc_run_desc &d = ctx->desc[r];
+        if (!adj[r].lE || !adj[r].lB) return PSC_ERR_INVALID;
+        const double dV = d.dx[1] * d.dx[2] * (R.dim == 3 ? d.dx[0] : 1.0);
+        HIPCHECK(launch_adj_seed(R.E, R.B, adj[r].lE, adj[r].lB, 3 * R.ncell, (float)dV, s), "adjoint seed");
+        for (int sp = 0; sp < R.n_species; ++sp) {
+            const int64_t n = R.sp[sp].n;
+            if (n == 0) continue;
+            if (!adj[r].loff[sp] || !adj[r].lu[sp]) return PSC_ERR_INVALID;
+            HIPCHECK(launch_fill_i32(reinterpret_cast<int32_t *>(adj[r].loff[sp]), R.dim * n, 0, s), "adjoint seed");
+            HIPCHECK(launch_fill_i32(reinterpret_cast<int32_t *>(adj[r].lu[sp]), 3 * n, 0, s), "adjoint seed");
+        }
+    }
     return PSC_OK;
 }
 

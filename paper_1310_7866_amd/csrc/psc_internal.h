@@ -284,6 +284,8 @@ hipError_t launch_cell_starts(int64_t n, int64_t ncell, const int32_t *sorted_ke
 hipError_t launch_get(const RunDev &r, int species, int front, int perm_pending, int32_t *cell,
                       float *off, float *u, int32_t *id, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_adj_seed(const float *E, const float *B, float *lE, float *lB, int64_t n, float dV,
+                           hipStream_t s);
 hipError_t launch_iota(int32_t *p, int64_t n, hipStream_t s);
 hipError_t launch_diag(const Launch &L, double *out, double *gauss, int64_t total_cells,
                        const int64_t *run_cell_base_dev, int front);

@@ -26,13 +26,13 @@ STATUS = {0: "PSC_OK", 1: "PSC_ERR_INVALID", 2: "PSC_ERR_CFL", 3: "PSC_ERR_LDS",
           5: "PSC_ERR_NONFINITE", 6: "PSC_ERR_PARTICLE", 7: "PSC_ERR_UNSUPPORTED", 8: "PSC_ERR_STATE"}
 
 # every symbol include/psc.h declares
-EXPORTS = ["psc_init_patches", "psc_workspace_size", "psc_bind", "psc_bind_static", "psc_load_particles", "psc_load_sorted",
-           "psc_push_fields",
-           "psc_push_particles", "psc_deposit_current", "psc_sort", "psc_sort_radix", "psc_step", "psc_get_particles",
-           "psc_keys_to_cells", "psc_particle_count", "psc_front", "psc_sort_view", "psc_diagnostics",
-           "psc_get_perm", "psc_marder", "psc_adjoint_step", "psc_set_launch", "psc_set_run_chunk", "psc_balance",
-           "psc_partition",
-           "psc_set_unit_order", "psc_hilbert_order", "psc_check", "psc_status_string", "psc_last_error", "psc_destroy"]
+EXPORTS = ["psc_init_patches", "psc_workspace_size", "psc_bind", "psc_bind_static", "psc_load_particles",
+           "psc_load_sorted", "psc_push_fields", "psc_push_particles", "psc_deposit_current", "psc_sort",
+           "psc_sort_radix", "psc_step", "psc_get_particles", "psc_keys_to_cells", "psc_particle_count",
+           "psc_front", "psc_sort_view", "psc_diagnostics", "psc_get_perm", "psc_marder", "psc_adjoint_step",
+           "psc_adjoint_seed", "psc_set_launch", "psc_set_run_chunk", "psc_balance", "psc_partition",
+           "psc_set_unit_order", "psc_hilbert_order", "psc_check", "psc_status_string", "psc_last_error",
+           "psc_destroy"]
 LAUNCH_GRID, LAUNCH_QUEUE, LAUNCH_PARTITION = 0, 1, 2
 RUN_ADJOINT = 1
 RUN_VB = 2
@@ -100,6 +100,7 @@ def load_library(path: str = LIB_PATH):
     L.psc_diagnostics.argtypes = [vp, vp, vp, vp]
     L.psc_get_perm.argtypes = [vp, i32, i32, vp, vp]
     L.psc_adjoint_step.argtypes = [vp, C.POINTER(AdjFwd), C.POINTER(AdjState), vp]
+    L.psc_adjoint_seed.argtypes = [vp, C.POINTER(AdjState), vp]
     L.psc_set_launch.argtypes = [vp, i32, i32, i32, i32, i32, vp]
     L.psc_set_run_chunk.argtypes = [vp, i32, i32, vp]
     L.psc_balance.argtypes = [vp, C.c_double, vp]
@@ -448,6 +449,18 @@ class PscSim:
                 F[r].perm[s] = fwd[r]["perm"][s].data_ptr()
                 S[r].loff[s], S[r].lu[s] = lam[r]["loff"][s].data_ptr(), lam[r]["lu"][s].data_ptr()
         self._call(self.L.psc_adjoint_step(self.ctx, F, S, self._stream()))
+
+    def adjoint_seed(self, lam):
+        """Seed lam (per run dict(lE, lB, loff=[...], lu=[...]) of device
+        tensors) for W = the current field energy: lE = E dV, lB = B dV,
+        particle adjoints zero."""
+        n_runs = len(self.cases)
+        S = (AdjState * n_runs)()
+        for r in range(n_runs):
+            S[r].lE, S[r].lB = lam[r]["lE"].data_ptr(), lam[r]["lB"].data_ptr()
+            for s, _ in enumerate(self.cases[r].species):
+                S[r].loff[s], S[r].lu[s] = lam[r]["loff"][s].data_ptr(), lam[r]["lu"][s].data_ptr()
+        self._call(self.L.psc_adjoint_seed(self.ctx, S, self._stream()))
 
     def field_arrays(self, r: int):
         self.torch.cuda.synchronize()

@@ -62,6 +62,24 @@ def test_autograd_function_matches_driver():
     assert _rel(B0.grad.numpy(), gB) <= 1e-4
     for s in range(2):
         assert _rel(u0[s].grad.numpy(), gU[s]) <= 1e-4
+    # a second call on the same case reuses its context with the new inputs
+    # (on the device: the inputs and the gradients stay on the GPU)
+    import dataclasses
+    dev = torch.device("cuda")
+    E1 = (1.1 * torch.tensor(c.E)).to(dev).requires_grad_(True)
+    B1 = torch.tensor(c.B, device=dev, requires_grad=True)
+    u1 = [(0.9 * torch.tensor(sp.u)).to(dev).requires_grad_(True) for sp in c.species]
+    W1 = field_energy(c, 6, 3, E1, B1, *u1)
+    W1.backward()
+    assert W1.device.type == "cuda" and E1.grad.device.type == "cuda"
+    c1 = dataclasses.replace(c, E=E1.detach().cpu().numpy(), species=[
+        dataclasses.replace(sp, u=u.detach().cpu().numpy()) for sp, u in zip(c.species, u1)])
+    W3, hE, hB, hU, _, _ = energy_gradient(c1, 6, 3)
+    assert abs(W1.item() - W3) <= 1e-6 * W3
+    assert _rel(E1.grad.cpu().numpy(), hE) <= 1e-4
+    assert _rel(B1.grad.cpu().numpy(), hB) <= 1e-4
+    for s in range(2):
+        assert _rel(u1[s].grad.cpu().numpy(), hU[s]) <= 1e-4
 
 
 def test_checkpoint_interval_does_not_change_gradient():

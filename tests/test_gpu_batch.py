@@ -193,11 +193,11 @@ def test_unit_orders_agree(mode):
     a, b = _sim(cs), _sim(cs)
     a.set_launch(mode, chunk=512)
     b.set_launch(mode, chunk=512)
-    b.set_unit_order(ORDER_ROWMAJOR)
+    b.set_unit_order(ORDER_HILBERT)   # the default is row-major
     for k in range(3):
         a.step(1)
         b.step(1, use_graph=k > 0)
-    b.set_unit_order(ORDER_HILBERT)
+    b.set_unit_order(ORDER_ROWMAJOR)
     b.step(1)
     a.step(1)
     a.check()
