@@ -363,16 +363,42 @@ psc_status psc_marder(psc_ctx *ctx, const double *ref, double d, int iters, void
  * psc_push_particles wrote, of the particle that sorts to position j. */
 psc_status psc_get_perm(psc_ctx *ctx, int run, int species, int32_t *perm, void *stream);
 
+/* Copy the current cell offsets of (run, species) (int32, ncell + 1: the
+ * sorted particles of cell key c are slots [out[c], out[c+1]) of the order
+ * psc_get_particles writes) to a caller device array. */
+psc_status psc_get_cell_offsets(psc_ctx *ctx, int run, int species, int32_t *out, void *stream);
+
+/* Replace the device arrays of particle buffer set `set` (0 or 1) of (run,
+ * species) with caller arrays of the same capacity and layout (cell, off,
+ * u, and id exactly when the context carries ids).  The set psc_front does
+ * not name is the one the next psc_push_particles writes, so swapping it
+ * before each step keeps every step's particles in arrays of their own (the
+ * adjoint's recomputed segments); swapping the front set is allowed only
+ * with arrays that hold the same particles.  Uploads the run's table entry
+ * on `stream` (through a pinned staging slot, no host wait); drops recorded
+ * step graphs. */
+psc_status psc_set_particle_buffers(psc_ctx *ctx, int run, int species, int set, int32_t *cell, float *off, float *u,
+                                    int32_t *id, void *stream);
+
 /* Forward state of one step, per run, as the adjoint needs it: fields at the
- * start of the step (E^{n+1/2}, B^n), the particles at the start of the step
- * in sorted key order (as psc_get_particles writes them, stride n), and the
- * permutation of the step's sort (psc_get_perm after the step). */
+ * start of the step (E^{n+1/2}, B^n), the particles at the start of the step,
+ * and the permutation of the step's sort (psc_get_perm after the step).
+ * The particles come either in sorted key order (as psc_get_particles
+ * writes them, stride n; read_perm NULL) or as the buffer set the step's
+ * push read them from, with read_perm the permutation of the previous sort
+ * (sorted slot -> buffer slot, as psc_get_perm returned it before the step)
+ * and stride the buffers' capacity.  cell_start: optional cell offsets of
+ * the sorted keys (ncell + 1, as psc_get_cell_offsets returned them before
+ * the step); NULL computes them from sorted keys (read_perm NULL only). */
 typedef struct {
     const float *E, *B;
     const int32_t *cell[PSC_MAX_SPECIES];
     const float *off[PSC_MAX_SPECIES];
     const float *u[PSC_MAX_SPECIES];
     const int32_t *perm[PSC_MAX_SPECIES];
+    const int32_t *read_perm[PSC_MAX_SPECIES];   /* NULL: particles in sorted order   */
+    const int32_t *cell_start[PSC_MAX_SPECIES];  /* NULL: from the sorted keys         */
+    int64_t stride[PSC_MAX_SPECIES];             /* 0: n                               */
 } psc_adj_fwd;
 
 /* Adjoint state, per run: on entry the adjoints of the step's outputs

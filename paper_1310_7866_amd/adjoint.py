@@ -20,15 +20,6 @@ import numpy as np
 from .psc import PscSim
 
 
-def _state(sim):
-    st = []
-    for r, c in enumerate(sim.cases):
-        E, B, _ = sim.fields[r]
-        st.append(dict(E=E.clone(), B=B.clone(),   # the reverse step reads no ids
-                       parts=[sim.device_particles(r, s, ids=False) for s in range(len(c.species))]))
-    return st
-
-
 class EnergyGradient:
     """Forward with checkpoints, then reverse; timings in milliseconds."""
 
@@ -84,10 +75,26 @@ class EnergyGradient:
         self.W = d[:, 0] + d[:, 1]
         return self.W
 
+    def _ring(self):
+        """every + 1 particle buffer sets per (run, species), allocated once:
+        the recomputed steps of a segment each write their own set, so the
+        reverse step reads a step's particles where its push read them."""
+        if getattr(self, "_ring_bufs", None) is None:
+            sim, torch = self.sim, self.sim.torch
+            i32, f32 = torch.int32, torch.float32
+            self._ring_bufs = [[[dict(cell=torch.empty(max(sp.n, 1), dtype=i32, device=sim.device),
+                                      off=torch.empty(c.dim * max(sp.n, 1), dtype=f32, device=sim.device),
+                                      u=torch.empty(3 * max(sp.n, 1), dtype=f32, device=sim.device),
+                                      id=torch.empty(max(sp.n, 1), dtype=i32, device=sim.device)
+                                      if sim.with_ids else None)
+                                 for _ in range(self.every + 1)] for sp in c.species] for c in sim.cases]
+        return self._ring_bufs
+
     def backward_device(self):
         """Reverse pass; per run (dW/dE0 (3, ncell), dW/dB0 (3, ncell),
         [dW/du0 (3, n) per species in case order]) as device tensors."""
         sim, torch = self.sim, self.sim.torch
+        ring = self._ring()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         a.record()
@@ -95,13 +102,29 @@ class EnergyGradient:
         sim.adjoint_seed(lam)
         for k0, snap in reversed(self.ckpts):
             k1 = min(k0 + self.every, self.nsteps)
+            # the segment starts from its snapshot, loaded (sorted) into ring set 0
+            for r, c in enumerate(sim.cases):
+                for s in range(len(c.species)):
+                    sim.set_particle_buffers(r, s, 0, ring[r][s][0])
             sim.restore(snap)
             states = []
-            for _ in range(k0, k1):
-                st = _state(sim)
+            read_perm = [[None] * len(c.species) for c in sim.cases]
+            for j in range(k1 - k0):
+                front, _ = sim.front()
+                st = []
+                for r, c in enumerate(sim.cases):
+                    E, B, _ = sim.fields[r]
+                    parts = []
+                    for s, sp in enumerate(c.species):
+                        q = ring[r][s][j]
+                        parts.append(dict(key=q["cell"], off=q["off"], u=q["u"], stride=sp.n,
+                                          read_perm=read_perm[r][s], cell_start=sim.cell_offsets(r, s)))
+                        sim.set_particle_buffers(r, s, 1 - front, ring[r][s][j + 1])
+                    st.append(dict(E=E.clone(), B=B.clone(), parts=parts))
                 sim.step(1)
                 for r, c in enumerate(sim.cases):
                     st[r]["perm"] = [sim.get_perm(r, s) for s in range(len(c.species))]
+                    read_perm[r] = st[r]["perm"]
                 states.append(st)
             for st in reversed(states):
                 sim.adjoint_step(st, lam)
@@ -109,6 +132,12 @@ class EnergyGradient:
         torch.cuda.synchronize()
         self.adjoint_ms = a.elapsed_time(b)
         sim.check()
+        # back on the context's own buffers, at the initial state
+        for r, c in enumerate(sim.cases):
+            for s in range(len(c.species)):
+                sim.set_particle_buffers(r, s, 0, sim.parts[r][s][0])
+                sim.set_particle_buffers(r, s, 1, sim.parts[r][s][1])
+        sim.restore(self.ckpts[0][1])
         # particle adjoints from the initial sorted order to case order
         out = []
         snap0 = self.ckpts[0][1]

@@ -275,39 +275,22 @@ __global__ void k_adj_unpermute(const AdjRun *__restrict__ adj, int r, int s, in
     for (int c = 0; c < 3; ++c) S.su[c * S.n + p] = S.lu[c * S.n + j];
 }
 
-__global__ void __launch_bounds__(1024) k_adj_items(const RunDev *__restrict__ runs, const AdjRun *__restrict__ adj,
-                                                    const Unit *__restrict__ units, int n_units, int chunk,
-                                                    int32_t *__restrict__ item_start) {
-    __shared__ int32_t part[1024];
-    const int t = threadIdx.x;
-    const int per = (n_units + 1023) / 1024;
-    const int u0 = t * per, u1 = imin(u0 + per, n_units);
-    auto count = [&](int u) {
-        const Unit U = units[u];
-        const RunDev &R = runs[U.run];
-        int pc[3];
-        patch_coords(R, U.patch, pc);
-        const int64_t kb = patch_key_base(R, pc[0], pc[1], pc[2]);
-        const int64_t ke = kb + (int64_t)patch_ext(R, 0, pc[0]) * patch_ext(R, 1, pc[1]) * patch_ext(R, 2, pc[2]);
-        const int32_t *cs = adj[U.run].sp[U.species].cs;
-        return (cs[ke] - cs[kb] + chunk - 1) / chunk;
-    };
-    int32_t sum = 0;
-    for (int u = u0; u < u1; ++u) sum += count(u);
-    part[t] = sum;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        int32_t v = t >= off ? part[t - off] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    int32_t run = part[t] - sum;
-    for (int u = u0; u < u1; ++u) {
-        item_start[u] = run;
-        run += count(u);
-    }
-    if (t == 1023) item_start[n_units] = part[1023];
+// work items of the particle adjoint per unit (one thread per unit); the
+// prefix over units follows with launch_items_scan
+__global__ void __launch_bounds__(256) k_adj_unit_items(const RunDev *__restrict__ runs,
+                                                        const AdjRun *__restrict__ adj,
+                                                        const Unit *__restrict__ units, int n_units, int chunk,
+                                                        int32_t *__restrict__ item_start) {
+    const int u = blockIdx.x * 256 + threadIdx.x;
+    if (u >= n_units) return;
+    const Unit U = units[u];
+    const RunDev &R = runs[U.run];
+    int pc[3];
+    patch_coords(R, U.patch, pc);
+    const int64_t kb = patch_key_base(R, pc[0], pc[1], pc[2]);
+    const int64_t ke = kb + (int64_t)patch_ext(R, 0, pc[0]) * patch_ext(R, 1, pc[1]) * patch_ext(R, 2, pc[2]);
+    const int32_t *cs = adj[U.run].sp[U.species].cs;
+    item_start[u] = (cs[ke] - cs[kb] + chunk - 1) / chunk;
 }
 
 // ---------------------------------------------------------------------------
@@ -380,8 +363,14 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles(const RunDev *__res
     // stencils reach are staged, cleared and flushed.  Field-tile rows:
     // lz + FLO - 1 .. lz + FLO + ORDER; current-tile rows: lz .. lz + 2 ORDER + 1.
     const int pc_cells = hy * hz;
-    const int lf = imin(imax(AS.key[beg] - (int32_t)kb, 0), pc_cells - 1);
-    const int ll = imin(imax(AS.key[end - 1] - (int32_t)kb, 0), pc_cells - 1);
+    // buffer slot of the forward particle at sorted slot i
+    auto slot_of = [&](int32_t i) -> int64_t {
+        if (!AS.rperm) return i;
+        const int32_t q = AS.rperm[i];
+        return (uint32_t)q < (uint32_t)AS.stride ? q : 0;   // a corrupt permutation stays in bounds
+    };
+    const int lf = imin(imax(AS.key[slot_of(beg)] - (int32_t)kb, 0), pc_cells - 1);
+    const int ll = imin(imax(AS.key[slot_of(end - 1)] - (int32_t)kb, 0), pc_cells - 1);
     const int zf = lf / hy, zl = ll / hy;
     const int fr0 = zf + FLO - 1, fr1 = imin(zl + FLO + ORDER, fz - 1);   // field-tile rows [fr0, fr1]
     const int jr0 = zf, jr1 = imin(zl + 2 * ORDER + 1, jz - 1);           // current-tile rows [jr0, jr1]
@@ -425,13 +414,15 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles(const RunDev *__res
     for (int32_t base = beg; base < end; base += NT) {
         const bool valid = base + (int32_t)threadIdx.x < end;
         const int32_t i = valid ? base + (int32_t)threadIdx.x : beg;
-        const int32_t key = AS.key[i];
+        const int64_t q = slot_of(i);
+        const int64_t st = AS.stride;
+        const int32_t key = AS.key[q];
         int local = key - (int32_t)kb;
         if (local < 0 || local >= hy * hz) local = 0;
         int ly;
         const int lz = divmod_small(local, hy, inv_hy, ly);
-        const float oyv = AS.off[i], ozv = AS.off[n + i];
-        const float3 u0 = make_float3(AS.u[i], AS.u[n + i], AS.u[2 * n + i]);
+        const float oyv = AS.off[q], ozv = AS.off[st + q];
+        const float3 u0 = make_float3(AS.u[q], AS.u[st + q], AS.u[2 * st + q]);
 
         // ---- forward recompute: interpolation (with offset derivatives) ----
         float wny[ORDER + 1], why[ORDER + 1], wnz[ORDER + 1], whz[ORDER + 1];
@@ -837,12 +828,19 @@ hipError_t launch_adjoint(const Launch &L, const AdjRun *adj_dev, const AdjRun *
             if (S.n > 0)
                 hipLaunchKernelGGL(k_adj_unpermute, dim3((unsigned)((S.n + 255) / 256)), dim3(256), 0, s, adj_dev, r,
                                    sp, R.dim);
-            hipError_t e = launch_cell_starts(S.n, R.ncell, S.key, S.cs, L.err, s);
-            if (e != hipSuccess) return e;
+            if (S.cs == S.cs_scratch) {   // offsets not given: from the sorted keys
+                hipError_t e = launch_cell_starts(S.n, R.ncell, S.key, S.cs_scratch, L.err, s);
+                if (e != hipSuccess) return e;
+            }
         }
     }
     // (4) particles
-    hipLaunchKernelGGL(k_adj_items, dim3(1), dim3(1024), 0, s, L.runs_dev, adj_dev, units, n_units, chunk, item_start);
+    hipLaunchKernelGGL(k_adj_unit_items, dim3((unsigned)imax(1, (n_units + 255) / 256)), dim3(256), 0, s, L.runs_dev,
+                       adj_dev, units, n_units, chunk, item_start);
+    {
+        hipError_t e = launch_items_scan(n_units, item_start, nullptr, s);
+        if (e != hipSuccess) return e;
+    }
     int64_t grid = (max_items + 7) / 8 * 8;
     if (grid < 8) grid = 8;
     if (order == 1)

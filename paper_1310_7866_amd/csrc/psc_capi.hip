@@ -27,6 +27,9 @@ static constexpr size_t kMaxLds = 160 * 1024;
 // slot of its own, so calls queue on the stream without a host wait (a slot
 // is reused only after the call that last used it has finished)
 static constexpr int kAdjRing = 4;
+// run-table entries in flight from psc_set_particle_buffers (pinned slots,
+// reused once the upload that last used them has finished)
+static constexpr int kRunRing = 8;
 
 // Library-held workspace of psc_bind_static, one per device (each device
 // that loads the library holds its own copy until the process ends).  Host
@@ -85,6 +88,9 @@ struct psc_ctx {
     size_t adj_lds = 0;
     int64_t adj_items = 0;                  // work items of the particle adjoint (kAdjChunk particles)
     std::vector<AdjRun> adj;                 // host mirror of the adjoint table
+    RunDev *run_pinned = nullptr;            // kRunRing staged run-table entries (pinned)
+    hipEvent_t run_done[kRunRing] = {};
+    uint64_t run_calls = 0;
     AdjRun *adj_pinned = nullptr;            // kAdjRing * n_runs tables in pinned host memory
     hipEvent_t adj_done[kAdjRing] = {};      // completion of the call that last used each slot
     uint64_t adj_calls = 0;
@@ -110,6 +116,9 @@ struct psc_ctx {
         for (hipEvent_t &e : adj_done)
             if (e) hipEventDestroy(e);
         if (adj_pinned) hipHostFree(adj_pinned);
+        for (hipEvent_t &e : run_done)
+            if (e) hipEventDestroy(e);
+        if (run_pinned) hipHostFree(run_pinned);
     }
 };
 
@@ -563,7 +572,7 @@ psc_status psc_bind(psc_ctx *ctx, const psc_run_bufs *bufs, int n_runs, void *wo
                 AdjSpecies &S = A.sp[sp];
                 S.soff = ctx->at<float>(ctx->off_soff[r][sp]);
                 S.su = ctx->at<float>(ctx->off_su[r][sp]);
-                S.cs = ctx->at<int32_t>(ctx->off_acs[r][sp]);
+                S.cs = S.cs_scratch = ctx->at<int32_t>(ctx->off_acs[r][sp]);
             }
         }
     }
@@ -1074,6 +1083,50 @@ psc_status psc_set_unit_order(psc_ctx *ctx, int order, void *stream) {
     return PSC_OK;
 }
 
+psc_status psc_get_cell_offsets(psc_ctx *ctx, int run, int species, int32_t *out, void *stream) {
+    if (!ctx || !ctx->bound || run < 0 || run >= ctx->n_runs || species < 0 || species >= ctx->runs[run].n_species ||
+        !out)
+        return PSC_ERR_INVALID;
+    const RunDev &R = ctx->runs[run];
+    HIPCHECK(hipMemcpyAsync(out, R.sp[species].cs[ctx->cs_sel], sizeof(int32_t) * (R.ncell + 1),
+                            hipMemcpyDeviceToDevice, (hipStream_t)stream),
+             "copy cell offsets");
+    return PSC_OK;
+}
+
+psc_status psc_set_particle_buffers(psc_ctx *ctx, int run, int species, int set, int32_t *cell, float *off, float *u,
+                                    int32_t *id, void *stream) {
+    if (!ctx || !ctx->bound || run < 0 || run >= ctx->n_runs || species < 0 || species >= ctx->runs[run].n_species ||
+        set < 0 || set > 1)
+        return PSC_ERR_INVALID;
+    RunDev &R = ctx->runs[run];
+    SpeciesDev &S = R.sp[species];
+    if (S.cap > 0 && (!cell || !off || !u)) return fail(ctx, PSC_ERR_INVALID, "null particle buffer");
+    if ((id != nullptr) != (S.id[set] != nullptr))
+        return fail(ctx, PSC_ERR_INVALID, "ids must be given exactly when the context carries them");
+    if (!ctx->run_pinned) {
+        HIPCHECK(hipHostMalloc((void **)&ctx->run_pinned, sizeof(RunDev) * kRunRing, hipHostMallocDefault),
+                 "run table staging");
+        for (hipEvent_t &e : ctx->run_done) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+    }
+    S.cell[set] = cell;
+    S.off[set] = off;
+    S.u[set] = u;
+    S.id[set] = id;
+    // upload through a pinned slot, ordered on the stream, without a host wait
+    hipStream_t s = (hipStream_t)stream;
+    const int slot = (int)(ctx->run_calls++ % kRunRing);
+    HIPCHECK(hipEventSynchronize(ctx->run_done[slot]), "run table slot");
+    ctx->run_pinned[slot] = R;
+    HIPCHECK(hipMemcpyAsync(ctx->at<RunDev>(ctx->off.runs) + run, ctx->run_pinned + slot, sizeof(RunDev),
+                            hipMemcpyHostToDevice, s),
+             "upload run");
+    HIPCHECK(hipEventRecord(ctx->run_done[slot], s), "run table event");
+    for (auto &kv : ctx->graphs) hipGraphExecDestroy(kv.second);
+    ctx->graphs.clear();
+    return PSC_OK;
+}
+
 psc_status psc_get_perm(psc_ctx *ctx, int run, int species, int32_t *perm, void *stream) {
     if (!ctx || !ctx->bound || run < 0 || run >= ctx->n_runs || species < 0 || species >= ctx->runs[run].n_species ||
         !perm)
@@ -1111,6 +1164,10 @@ psc_status psc_adjoint_step(psc_ctx *ctx, const psc_adj_fwd *fwd, const psc_adj_
             S.off = fwd[r].off[sp];
             S.u = fwd[r].u[sp];
             S.perm = fwd[r].perm[sp];
+            S.rperm = fwd[r].read_perm[sp];
+            S.stride = fwd[r].stride[sp] > 0 ? fwd[r].stride[sp] : S.n;
+            if (S.rperm && S.stride < S.n) return fail(ctx, PSC_ERR_INVALID, "forward buffer stride below n");
+            S.cs = fwd[r].cell_start[sp] ? fwd[r].cell_start[sp] : S.cs_scratch;
             S.loff = adj[r].loff[sp];
             S.lu = adj[r].lu[sp];
         }

@@ -94,14 +94,18 @@ struct ScanSeg {
 
 // Adjoint step: forward state, adjoint state and scratch of one species/run.
 struct AdjSpecies {
-    const int32_t *key;   // forward particles at the start of the step, sorted by key
-    const float *off;     // D x n (stride n)
-    const float *u;       // 3 x n
+    const int32_t *key;   // forward particles at the start of the step: sorted by key,
+    const float *off;     // or, with rperm, in the buffer order the step's push read
+    const float *u;       // them in; off D x stride, u 3 x stride
+    const int32_t *rperm; // null, or sorted slot -> buffer slot of key/off/u
+    int64_t stride;       // array stride of off and u (n for sorted copies)
     const int32_t *perm;  // sort permutation of the step: next sorted slot -> slot
     int64_t n;
     float *loff, *lu;     // caller: in (next step's sorted order), out (this step's)
     float *soff, *su;     // scratch: incoming adjoints moved to this step's slots
-    int32_t *cs;          // scratch: cell offsets of `key`, ncell + 1
+    const int32_t *cs;    // cell offsets of the sorted keys, ncell + 1 (given, or computed
+                          // into cs_scratch)
+    int32_t *cs_scratch;
 };
 
 struct AdjRun {
@@ -284,6 +288,7 @@ hipError_t launch_cell_starts(int64_t n, int64_t ncell, const int32_t *sorted_ke
 hipError_t launch_get(const RunDev &r, int species, int front, int perm_pending, int32_t *cell,
                       float *off, float *u, int32_t *id, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_items_scan(int n_units, int32_t *item_start, int32_t *queue, hipStream_t s);
 hipError_t launch_adj_seed(const float *E, const float *B, float *lE, float *lB, int64_t n, float dV,
                            hipStream_t s);
 hipError_t launch_iota(int32_t *p, int64_t n, hipStream_t s);

@@ -164,6 +164,11 @@ __global__ void __launch_bounds__(1024) k_items_scan(int n_units, int32_t *__res
     if (t == 1023) item_start[n_units] = part[1023];
 }
 
+hipError_t launch_items_scan(int n_units, int32_t *item_start, int32_t *queue, hipStream_t s) {
+    hipLaunchKernelGGL(k_items_scan, dim3(1), dim3(1024), 0, s, n_units, item_start, queue);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Esirkepov current of one particle, added lane by lane with LDS atomics
 // (general stencil: used for particles whose support changes cell)

@@ -31,8 +31,8 @@ EXPORTS = ["psc_init_patches", "psc_workspace_size", "psc_bind", "psc_bind_stati
            "psc_sort_radix", "psc_step", "psc_get_particles", "psc_keys_to_cells", "psc_particle_count",
            "psc_front", "psc_sort_view", "psc_diagnostics", "psc_get_perm", "psc_marder", "psc_adjoint_step",
            "psc_adjoint_seed", "psc_set_launch", "psc_set_run_chunk", "psc_balance", "psc_partition",
-           "psc_set_unit_order", "psc_hilbert_order", "psc_check", "psc_status_string", "psc_last_error",
-           "psc_destroy"]
+           "psc_set_unit_order", "psc_hilbert_order", "psc_get_cell_offsets", "psc_set_particle_buffers",
+           "psc_check", "psc_status_string", "psc_last_error", "psc_destroy"]
 LAUNCH_GRID, LAUNCH_QUEUE, LAUNCH_PARTITION = 0, 1, 2
 RUN_ADJOINT = 1
 RUN_VB = 2
@@ -54,7 +54,8 @@ class RunDesc(C.Structure):
 
 class AdjFwd(C.Structure):
     _fields_ = [("E", C.c_void_p), ("B", C.c_void_p), ("cell", C.c_void_p * 4), ("off", C.c_void_p * 4),
-                ("u", C.c_void_p * 4), ("perm", C.c_void_p * 4)]
+                ("u", C.c_void_p * 4), ("perm", C.c_void_p * 4), ("read_perm", C.c_void_p * 4),
+                ("cell_start", C.c_void_p * 4), ("stride", C.c_int64 * 4)]
 
 
 class AdjState(C.Structure):
@@ -101,6 +102,8 @@ def load_library(path: str = LIB_PATH):
     L.psc_get_perm.argtypes = [vp, i32, i32, vp, vp]
     L.psc_adjoint_step.argtypes = [vp, C.POINTER(AdjFwd), C.POINTER(AdjState), vp]
     L.psc_adjoint_seed.argtypes = [vp, C.POINTER(AdjState), vp]
+    L.psc_get_cell_offsets.argtypes = [vp, i32, i32, vp, vp]
+    L.psc_set_particle_buffers.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp]
     L.psc_set_launch.argtypes = [vp, i32, i32, i32, i32, i32, vp]
     L.psc_set_run_chunk.argtypes = [vp, i32, i32, vp]
     L.psc_balance.argtypes = [vp, C.c_double, vp]
@@ -435,9 +438,9 @@ class PscSim:
                 self.load_sorted(r, s, p["key"], p["off"], p["u"], p["id"])
 
     def adjoint_step(self, fwd, lam):
-        """One reverse step.  fwd: per run dict(E, B, parts=[dict(key, off, u)],
-        perm=[tensor]); lam: per run dict(lE, lB, loff=[...], lu=[...]) updated
-        in place."""
+        """One reverse step.  fwd: per run dict(E, B, parts=[dict(key, off, u)
+        and optionally read_perm, cell_start, stride)], perm=[tensor]); lam:
+        per run dict(lE, lB, loff=[...], lu=[...]) updated in place."""
         n_runs = len(self.cases)
         F = (AdjFwd * n_runs)()
         S = (AdjState * n_runs)()
@@ -447,8 +450,27 @@ class PscSim:
             for s, p in enumerate(fwd[r]["parts"]):
                 F[r].cell[s], F[r].off[s], F[r].u[s] = p["key"].data_ptr(), p["off"].data_ptr(), p["u"].data_ptr()
                 F[r].perm[s] = fwd[r]["perm"][s].data_ptr()
+                if p.get("read_perm") is not None:
+                    F[r].read_perm[s] = p["read_perm"].data_ptr()
+                if p.get("cell_start") is not None:
+                    F[r].cell_start[s] = p["cell_start"].data_ptr()
+                F[r].stride[s] = int(p.get("stride", 0))
                 S[r].loff[s], S[r].lu[s] = lam[r]["loff"][s].data_ptr(), lam[r]["lu"][s].data_ptr()
         self._call(self.L.psc_adjoint_step(self.ctx, F, S, self._stream()))
+
+    def cell_offsets(self, r: int, s: int):
+        """Device copy of the current cell offsets of (run, species) (ncell + 1)."""
+        out = self.torch.empty(self.cases[r].ncell + 1, dtype=self.torch.int32, device=self.device)
+        self._call(self.L.psc_get_cell_offsets(self.ctx, r, s, out.data_ptr(), self._stream()))
+        return out
+
+    def set_particle_buffers(self, r: int, s: int, bset: int, bufs):
+        """Point buffer set `bset` of (run, species) at bufs = dict(cell, off, u,
+        id) (device tensors of the species' capacity)."""
+        idp = bufs["id"].data_ptr() if bufs.get("id") is not None else None
+        self._call(self.L.psc_set_particle_buffers(self.ctx, r, s, int(bset), bufs["cell"].data_ptr(),
+                                                   bufs["off"].data_ptr(), bufs["u"].data_ptr(), idp,
+                                                   self._stream()))
 
     def adjoint_seed(self, lam):
         """Seed lam (per run dict(lE, lB, loff=[...], lu=[...]) of device
