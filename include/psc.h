@@ -109,6 +109,22 @@ typedef struct {
  * midpoint) instead of Esirkepov's.  Order 2: PSC_ERR_UNSUPPORTED.  Not
  * with PSC_RUN_ADJOINT (the reverse step differentiates Esirkepov). */
 #define PSC_RUN_VB 2
+/* psc_run_desc.flags: accumulate this run's current in per-patch float
+ * tiles with halos in the workspace (float atomics), folded into J by
+ * psc_deposit_current (fig. psc_new: add_and_fill_ghosts_j as a pass of its
+ * own).  Without it the particle kernel adds each work item's LDS tile
+ * straight into a per-cell accumulator of the run, its halo wrapped onto the
+ * neighbouring patches' cells (the fold fused into the deposit, section
+ * "Fusing of GPU kernels"), in 64-bit fixed point: integer sums, so J does
+ * not depend on the order in which work items add and a step is bitwise
+ * reproducible; psc_deposit_current then converts the sums to J (one
+ * elementwise pass) and clears them.  The unit is a power of two chosen
+ * from the run's largest |q w|, dx/dt and particle capacity so that no sum
+ * can overflow; each tile value added is rounded to it, by at most 2^-29 of
+ * the bound on one particle's contribution.  Runs too small for the direct path (an active dimension
+ * with fewer cells than order, or with 2 * cells + 1 < patch + order + 1)
+ * always take the tiles. */
+#define PSC_RUN_TILE_FOLD 4
 
 typedef struct {
     float *E, *B, *J;                          /* 3 * ncell float32 each               */
@@ -197,14 +213,19 @@ psc_status psc_push_fields(psc_ctx *ctx, int op, void *stream);
  * staged in LDS with ghost layers; each particle is interpolated (b1/b2
  * weights of its Yee component), pushed with the relativistic Boris scheme,
  * moved, and its Esirkepov current is accumulated in an LDS tile that is
- * added to the patch's current tile in the workspace.  Reads the particles
+ * added into the run's fixed-point current sums (or, under
+ * PSC_RUN_TILE_FOLD, the patch's float tile); psc_deposit_current turns
+ * them into J.  Reads the particles
  * through the permutation left by psc_sort (if any), writes them in that
  * sorted order into the other buffer set, and records each particle's move
  * code for the next psc_sort. */
 psc_status psc_push_particles(psc_ctx *ctx, void *stream);
 
-/* Fold the per-patch current tiles (with their halos) into J with periodic
- * wrap, in a fixed order, and clear the tiles (fig. psc_new:
+/* J of the last psc_push_particles, then the accumulators cleared: the
+ * runs' fixed-point sums (whose halos the particle kernel already wrapped)
+ * converted to float; for the runs that keep tiles (PSC_RUN_TILE_FOLD or too
+ * small for the direct path) the per-patch tiles with their halos folded
+ * into J with periodic wrap, in a fixed order (fig. psc_new:
  * add_and_fill_ghosts_j). */
 psc_status psc_deposit_current(psc_ctx *ctx, void *stream);
 

@@ -2,6 +2,7 @@
 // tables, call sequencing and HIP graph capture of whole time steps.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -62,6 +63,7 @@ struct psc_ctx {
     std::vector<int64_t> patch_base;     // n_runs + 1: first patch of each run in the flat patch space
     int max_patch_cells = 0;             // cells of the largest patch of any run
     int fold_direct_dims = 0;            // bit 1 << dim: a run of that dimension folds by patch
+    bool any_jdirect = false;            // a run whose particle kernel adds into J directly
     bool any_fold_search = false;
     int n_segs = 0;
     std::vector<int64_t> seg_base;       // n_segs + 1
@@ -81,7 +83,7 @@ struct psc_ctx {
     } off{};
     PushMode pm;                             // particle-kernel launch shape
     int max_workers = 0;
-    std::vector<size_t> off_jtile, off_rho;
+    std::vector<size_t> off_jtile, off_jacc, off_rho;
     std::vector<std::vector<size_t>> off_cs0, off_cs1, off_perm, off_mc, off_cnt, off_pre, off_tot;
     // adjoint scratch (PSC_RUN_ADJOINT)
     bool adjoint = false;
@@ -317,14 +319,17 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
         }
         R.n_patches = R.np[0] * R.np[1] * R.np[2];
         R.fold_direct = 1;
+        R.jdirect = (d.flags & PSC_RUN_TILE_FOLD) == 0;
         for (int k = (d.dim == 3 ? 0 : 1); k < 3; ++k) {
             const int last = d.gdims[k] - (R.np[k] - 1) * d.patch[k];
             const int halo = imax(cur_lo(d.order), cur_hi(d.order));
             if (d.patch[k] < halo || last < halo) R.fold_direct = 0;
+            if (!current_direct_fits(d.gdims[k], d.patch[k], d.order)) R.jdirect = 0;
         }
         ctx->patch_base[r + 1] = ctx->patch_base[r] + R.n_patches;
         ctx->max_patch_cells = imax(ctx->max_patch_cells, d.patch[0] * d.patch[1] * d.patch[2]);
-        if (R.fold_direct) ctx->fold_direct_dims |= 1 << d.dim;
+        if (R.jdirect) ctx->any_jdirect = true;
+        else if (R.fold_direct) ctx->fold_direct_dims |= 1 << d.dim;
         else ctx->any_fold_search = true;
         R.n_species = d.n_species;
         R.ncell = (int64_t)d.gdims[0] * d.gdims[1] * d.gdims[2];
@@ -344,6 +349,25 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
             S.cap = d.capacity[s];
             S.n = 0;
             if (S.cap > ctx->max_cap) ctx->max_cap = S.cap;
+        }
+        if (R.jdirect) {
+            // Fixed-point unit of the current sums: a particle adds at most
+            // bound = 4 max|q w| max(dx / dt, 1) to one current component of a
+            // cell in a push (an Esirkepov or Villasenor-Buneman flux of at most
+            // one cell's worth, or the 2-d q w v_x term), and a cell's sum over
+            // the run's particle slots stays below 2^62 units:
+            // jq = bound * 2^(ceil(log2 slots) - 62), a power of two.
+            double qw = 0.0, slots = 1.0, dxdt = 1.0;
+            for (int s = 0; s < d.n_species; ++s) {
+                qw = std::max(qw, std::fabs(d.q[s] * d.w[s]));
+                slots += (double)d.capacity[s];
+            }
+            for (int k = (d.dim == 3 ? 0 : 1); k < 3; ++k) dxdt = std::max(dxdt, d.dx[k] / d.dt);
+            const double bound = 4.0 * (qw > 0.0 ? qw : 1.0) * dxdt;   // no charge: any unit
+            const int e = std::min(std::max((int)std::ceil(std::log2(bound)) + (int)std::ceil(std::log2(slots)) - 62,
+                                            -1000), 1000);
+            R.jq = std::ldexp(1.0, e);
+            R.jinvq = std::ldexp(1.0, -e);
         }
     }
     build_units(ctx);
@@ -389,12 +413,14 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
     ctx->off.load_keys_s = take(sizeof(int32_t) * ctx->max_cap);
     ctx->off.load_idx_s = take(sizeof(int32_t) * ctx->max_cap);
     ctx->off_jtile.resize(n_runs);
+    ctx->off_jacc.resize(n_runs);
     ctx->off_rho.resize(n_runs);
     ctx->off_cs0.assign(n_runs, std::vector<size_t>(PSC_MAX_SPECIES, 0));
     ctx->off_cs1 = ctx->off_perm = ctx->off_mc = ctx->off_cnt = ctx->off_pre = ctx->off_tot = ctx->off_cs0;
     for (int r = 0; r < n_runs; ++r) {
         const RunDev &R = ctx->runs[r];
-        ctx->off_jtile[r] = take(sizeof(float) * (size_t)R.n_patches * 3 * R.jtile_cells);
+        ctx->off_jtile[r] = take(R.jdirect ? 0 : sizeof(float) * (size_t)R.n_patches * 3 * R.jtile_cells);
+        ctx->off_jacc[r] = take(R.jdirect ? sizeof(long long) * 3 * (size_t)R.ncell : 0);
         ctx->off_rho[r] = take(sizeof(double) * R.ncell);
         for (int s = 0; s < R.n_species; ++s) {
             ctx->off_cs0[r][s] = take(sizeof(int32_t) * (R.ncell + 1));
@@ -493,6 +519,7 @@ psc_status psc_bind(psc_ctx *ctx, const psc_run_bufs *bufs, int n_runs, void *wo
         R.B = b.B;
         R.J = b.J;
         R.jtile = ctx->at<float>(ctx->off_jtile[r]);
+        R.jacc = ctx->at<long long>(ctx->off_jacc[r]);
         R.rho = ctx->at<double>(ctx->off_rho[r]);
         for (int sp = 0; sp < R.n_species; ++sp) {
             SpeciesDev &S = R.sp[sp];
@@ -551,7 +578,11 @@ psc_status psc_bind(psc_ctx *ctx, const psc_run_bufs *bufs, int n_runs, void *wo
     // clear the current tiles and every cell-offset array once
     for (int r = 0; r < ctx->n_runs; ++r) {
         const RunDev &R = ctx->runs[r];
-        HIPCHECK(hipMemsetAsync(R.jtile, 0, sizeof(float) * (size_t)R.n_patches * 3 * R.jtile_cells, s), "clear tiles");
+        if (R.jdirect)
+            HIPCHECK(hipMemsetAsync(R.jacc, 0, sizeof(long long) * 3 * (size_t)R.ncell, s), "clear accumulators");
+        else
+            HIPCHECK(hipMemsetAsync(R.jtile, 0, sizeof(float) * (size_t)R.n_patches * 3 * R.jtile_cells, s),
+                     "clear tiles");
         for (int sp = 0; sp < R.n_species; ++sp) {
             HIPCHECK(hipMemsetAsync(R.sp[sp].cs[0], 0, sizeof(int32_t) * (R.ncell + 1), s), "clear cs");
             HIPCHECK(hipMemsetAsync(R.sp[sp].cs[1], 0, sizeof(int32_t) * (R.ncell + 1), s), "clear cs");
@@ -759,6 +790,9 @@ psc_status psc_push_particles(psc_ctx *ctx, void *stream) {
 psc_status psc_deposit_current(psc_ctx *ctx, void *stream) {
     if (!ctx || !ctx->bound) return PSC_ERR_STATE;
     Launch L = make_launch(ctx, (hipStream_t)stream);
+    if (ctx->any_jdirect)
+        HIPCHECK(launch_finish_current(L, ctx->total_cells, ctx->at<int64_t>(ctx->off.run_base)), "finish current");
+    if (ctx->fold_direct_dims == 0 && !ctx->any_fold_search) return PSC_OK;   // no run keeps tiles
     HIPCHECK(launch_fold(L, ctx->total_cells, ctx->at<int64_t>(ctx->off.run_base), ctx->patch_base[ctx->n_runs],
                          ctx->at<int64_t>(ctx->off.patch_base), ctx->max_patch_cells, ctx->fold_direct_dims,
                          ctx->any_fold_search),

@@ -114,6 +114,29 @@ hipError_t launch_fields(const Launch &L, int op, int64_t total, const int64_t *
     return hipGetLastError();
 }
 
+// J from the fixed-point sums of the runs whose particle kernel adds its
+// current tiles into jacc (integer sums: the same whatever order the work
+// items added in), and jacc cleared for the next push
+__global__ void __launch_bounds__(256) k_finish_current(const RunDev *__restrict__ runs, int n_runs,
+                                                        const int64_t *__restrict__ run_base, int64_t total) {
+    with_run(runs, run_base, n_runs, total, [&](const RunDev &R, int64_t idx) {
+        if (!R.jdirect) return;
+        const int64_t nc = R.ncell;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const long long a = R.jacc[c * nc + idx];
+            R.J[c * nc + idx] = (float)((double)a * R.jq);
+            R.jacc[c * nc + idx] = 0;
+        }
+    });
+}
+
+hipError_t launch_finish_current(const Launch &L, int64_t total, const int64_t *run_base) {
+    const unsigned grid = (unsigned)((total + 255) / 256);
+    hipLaunchKernelGGL(k_finish_current, dim3(grid), dim3(256), 0, L.stream, L.runs_dev, L.n_runs, run_base, total);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // J fold: J(cell) = sum of every patch tile entry that maps onto the cell
 // (own patch and the halos of its neighbours, periodic), in a fixed order;
@@ -132,7 +155,7 @@ __global__ void __launch_bounds__(256) k_fold(const RunDev *__restrict__ runs, i
     float sx = 0.0f, sy = 0.0f, sz = 0.0f;
     const int64_t jc = R.jtile_cells;
     const int64_t nc = R.ncell;
-    if (R.fold_direct) return;   // folded by patch (k_fold_patch)
+    if (R.fold_direct || R.jdirect) return;   // folded by patch (k_fold_patch), or J is complete
     // candidate patch coordinates per dimension (deduplicated), and for each
     // the tile-local coordinates that alias this cell
     int cand[3][3], ncand[3];
@@ -200,7 +223,7 @@ __global__ void __launch_bounds__(kFoldBlock) k_fold_patch(const RunDev *__restr
     const int64_t gp = blockIdx.x;
     const int r = find_run(patch_base, n_runs, gp);
     const RunDev &R = runs[r];
-    if (!R.fold_direct || R.dim != DIM) return;
+    if (!R.fold_direct || R.jdirect || R.dim != DIM) return;
     const int p = (int)(gp - patch_base[r]);
     int pc[3], ext[3];
     pc[0] = p % R.np[0];

@@ -59,6 +59,9 @@ struct RunDev {
     int vb;              // order 1: Villasenor-Buneman deposit instead of Esirkepov
     int fold_direct;     // every patch extent >= the current halo (order + 1):
                          // a tile aliases cells of its own and adjacent patches only
+    int jdirect;         // the particle kernel adds its LDS tiles straight into the
+                         // run's current accumulator jacc (every tile coordinate
+                         // maps into [-n, 3n) per dimension)
     int n[3];            // cells
     int P[3];            // nominal patch size
     int np[3];           // patches per dimension
@@ -75,6 +78,8 @@ struct RunDev {
     int64_t jtile_cells; // jt[0]*jt[1]*jt[2]
     float *E, *B, *J;
     float *jtile;        // n_patches * 3 * jtile_cells
+    long long *jacc;     // jdirect: 3 * ncell fixed-point sums of the current in units
+    double jq, jinvq;    // of jq (a power of two) and its inverse
     double *rho;         // ncell, diagnostics scratch
     SpeciesDev sp[kMaxSpecies];
 };
@@ -133,6 +138,19 @@ __host__ __device__ inline int imax(int a, int b) { return a > b ? a : b; }
 __host__ __device__ inline int wrap(int i, int n) {
     int r = i % n;
     return r < 0 ? r + n : r;
+}
+// periodic image in [0, n) of -n <= i < 3n, without a division
+__host__ __device__ inline int wrap_near(int i, int n) {
+    i += i < 0 ? n : 0;
+    i -= i >= n ? n : 0;
+    return i >= n ? i - n : i;
+}
+// The direct current path: a run's tile coordinate t in [0, P + lo + hi)
+// along an active dimension stands for cell o + t - lo of a patch at origin
+// o <= n - 1, i.e. for -lo <= i <= n + P + hi - 2; wrap_near covers that
+// when lo <= n and P + hi <= 2 n + 1.
+__host__ __device__ inline bool current_direct_fits(int n, int P, int order) {
+    return cur_lo(order) <= n && P + cur_hi(order) <= 2 * n + 1;
 }
 
 // actual extent of patch coordinate pc along d (the last one is truncated)
@@ -270,6 +288,8 @@ hipError_t launch_fields(const Launch &L, int op, int64_t total_cells, const int
 // others by cell with the alias search
 hipError_t launch_fold(const Launch &L, int64_t total_cells, const int64_t *run_cell_base_dev, int64_t total_patches,
                        const int64_t *run_patch_base_dev, int max_patch_cells, int direct_dims, bool any_search);
+// J = jacc * jq and jacc = 0 in the runs with jdirect
+hipError_t launch_finish_current(const Launch &L, int64_t total_cells, const int64_t *run_cell_base_dev);
 hipError_t launch_sort(const Launch &L, const int64_t *seg_cell_base_dev, const int32_t *seg_run_dev,
                        const int32_t *seg_species_dev, int n_segs, int64_t total_seg_cells,
                        const ScanSeg *segs_dev, int64_t n_scan_blocks, int32_t *scan_tmp, int cs_sel,

@@ -1116,15 +1116,49 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
     if (flags) atomicOr(err, flags);
     __syncthreads();
 
-    // add the LDS current tile into the patch's tile in HBM
-    float *gt = R.jtile + (int64_t)U.patch * 3 * jcells;
-    for (int q = threadIdx.x; q < 3 * n_jband; q += NT) {
-        const int c = q / n_jband;
-        const int t = c * jcells + jr0 * jplane + (q - c * n_jband);
-        double v = jtile[t];
+    if (R.jdirect) {
+        // add the LDS current tile into the run's accumulator: tile entry
+        // (tx, ty, tz) is cell (ox, oy, oz) + (tx, ty, tz) - JLO, periodic,
+        // so the halo lands on the neighbouring patches' cells (the fold
+        // done here).  Fixed point in units of jq: integer sums, so the
+        // result does not depend on the order in which work items add
+        const int64_t nc = R.ncell;
+        unsigned long long *acc = reinterpret_cast<unsigned long long *>(R.jacc);
+        const double inv_q = R.jinvq;
+        const float inv_jx = 1.0f / jx_, inv_jy = 1.0f / jy_;
+        for (int q = threadIdx.x; q < n_jband; q += NT) {
+            const int t = jr0 * jplane + q;
+            int tx = 0, ty, tz;
+            if constexpr (DIM == 3) {
+                const int r = divmod_small(t, jx_, inv_jx, tx);
+                tz = divmod_small(r, jy_, inv_jy, ty);
+            } else {
+                tz = divmod_small(t, jy_, inv_jy, ty);
+            }
+            const int gx = DIM == 3 ? wrap_near(ox + tx - JLO, R.n[0]) : 0;
+            const int gy = wrap_near(oy + ty - JLO, R.n[1]);
+            const int gz = wrap_near(oz + tz - JLO, R.n[2]);
+            const int64_t g = gx + (int64_t)R.n[0] * (gy + (int64_t)R.n[1] * gz);
 #pragma unroll
-        for (int cp = 1; cp < kJCopies; ++cp) v += jtile[3 * cp * jcells + t];
-        if (v != 0.0) atomicAdd(&gt[t], (float)v);
+            for (int c = 0; c < 3; ++c) {
+                double v = jtile[c * jcells + t];
+#pragma unroll
+                for (int cp = 1; cp < kJCopies; ++cp) v += jtile[(3 * cp + c) * jcells + t];
+                const long long k = (long long)__builtin_rint(v * inv_q);
+                if (k != 0) atomicAdd(&acc[c * nc + g], (unsigned long long)k);   // two's complement
+            }
+        }
+    } else {
+        // add the LDS current tile into the patch's tile in HBM
+        float *gt = R.jtile + (int64_t)U.patch * 3 * jcells;
+        for (int q = threadIdx.x; q < 3 * n_jband; q += NT) {
+            const int c = q / n_jband;
+            const int t = c * jcells + jr0 * jplane + (q - c * n_jband);
+            double v = jtile[t];
+#pragma unroll
+            for (int cp = 1; cp < kJCopies; ++cp) v += jtile[3 * cp * jcells + t];
+            if (v != 0.0) atomicAdd(&gt[t], (float)v);
+        }
     }
     __syncthreads();
 }

@@ -36,6 +36,7 @@ EXPORTS = ["psc_init_patches", "psc_workspace_size", "psc_bind", "psc_bind_stati
 LAUNCH_GRID, LAUNCH_QUEUE, LAUNCH_PARTITION = 0, 1, 2
 RUN_ADJOINT = 1
 RUN_VB = 2
+RUN_TILE_FOLD = 4
 ORDER_ROWMAJOR, ORDER_HILBERT = 0, 1
 
 
@@ -173,11 +174,14 @@ class PscSim:
     ``cases``: a ``cases.Case`` or a list of them (a batch: one launch per
     kernel covers every run).  Buffers are torch tensors on ``device``.
     ``static_workspace``: bind with psc_bind_static (the library-held
-    workspace) instead of a torch-allocated one.
+    workspace) instead of a torch-allocated one.  ``tile_fold``: every run
+    keeps per-patch current tiles folded by psc_deposit_current
+    (PSC_RUN_TILE_FOLD) instead of adding its current into J in the particle
+    kernel.
     """
 
     def __init__(self, cases, device: str = "cuda", with_ids: bool = True, chunk: int = 0,
-                 adjoint: bool = False, static_workspace: bool = False):
+                 adjoint: bool = False, static_workspace: bool = False, tile_fold: bool = False):
         import torch
         self.torch = torch
         if not torch.cuda.is_available():
@@ -186,7 +190,7 @@ class PscSim:
         self.cases = list(cases) if isinstance(cases, (list, tuple)) else [cases]
         self.device = torch.device(device)
         n_runs = len(self.cases)
-        flags = RUN_ADJOINT if adjoint else 0
+        flags = (RUN_ADJOINT if adjoint else 0) | (RUN_TILE_FOLD if tile_fold else 0)
         descs = (RunDesc * n_runs)(*[run_desc(c, flags=flags) for c in self.cases])
         ctx = C.c_void_p()
         self._call(self.L.psc_init_patches(descs, n_runs, int(chunk), C.byref(ctx)), None)

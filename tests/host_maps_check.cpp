@@ -71,9 +71,38 @@ static void check_neighbour_key() {
     }
 }
 
+// The direct current path: for every geometry current_direct_fits accepts
+// (cells n, patch P, order), every tile coordinate of every patch maps by
+// wrap_near onto the same cell as the general periodic wrap, inside [0, n)
+// (and the test covers refused geometries too).
+static void check_current_direct_map() {
+    int accepted = 0, refused = 0;
+    for (int order = 1; order <= 2; ++order)
+        for (int n = 1; n <= 40; ++n)
+            for (int P = 1; P <= 48; ++P) {
+                const int lo = cur_lo(order), hi = cur_hi(order), jt = P + lo + hi;
+                const int np = (n + P - 1) / P;
+                bool in_range = true;
+                for (int pc = 0; pc < np; ++pc)
+                    for (int t = 0; t < jt; ++t) {
+                        const int i = pc * P + t - lo;
+                        const int w = wrap_near(i, n);
+                        in_range &= w >= 0 && w < n && w == wrap(i, n);
+                    }
+                if (current_direct_fits(n, P, order)) {
+                    ++accepted;
+                    CHECK(in_range, "order %d n %d P %d: a tile coordinate leaves [0, n)", order, n, P);
+                } else {
+                    ++refused;
+                }
+            }
+    CHECK(accepted > 0 && refused > 0, "direct-path geometries: %d accepted, %d refused", accepted, refused);
+}
+
 int main() {
     check_mix_lane();
     check_neighbour_key();
+    check_current_direct_map();
     if (failures) {
         std::printf("%d failures\n", failures);
         return 1;

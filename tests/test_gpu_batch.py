@@ -99,7 +99,8 @@ def _uneven_batch(order):
     """Four runs of one context: two-species thermal runs and a one-species
     two-stream run, different particles per cell, ragged last patches, and
     (at both orders) one run whose last patch is narrower than the current
-    halo, so that the batch folds by patch and with the alias search."""
+    halo, so that with per-patch current tiles the batch folds by patch and
+    with the alias search."""
     def charged(seed, ny, nz, patch, ppc):
         c = cases.thermal2d(ny=ny, nz=nz, ppc=ppc, order=order, patch=patch, seed=seed)
         c.species[1].off = np.random.default_rng(seed + 1000).random(c.species[1].off.shape).astype(np.float32)
@@ -138,16 +139,18 @@ def test_per_run_chunks_agree(mode):
     _same(_state(a), _state(b))
 
 
-@pytest.mark.parametrize("order", [1, 2])
-@pytest.mark.parametrize("mode", [1, 2])
-def test_batch_matches_oracle(order, mode):
+@pytest.mark.parametrize("order,mode,tile_fold", [(1, 1, False), (1, 2, False), (2, 1, False), (2, 2, False),
+                                                  (1, 1, True), (2, 2, True)])
+def test_batch_matches_oracle(order, mode, tile_fold):
     """Every run of a batched context (a different chunk per run) against
     the double-precision oracle run alone: one push (the parity tolerances
-    of single runs), then three whole steps replayed from a HIP graph."""
+    of single runs), then three whole steps replayed from a HIP graph.
+    tile_fold: the current through per-patch tiles and both fold kernels
+    instead of the particle kernel adding it into J."""
     from oracle import oracle as O
     from tests.helpers import particle_errors
     cs = _uneven_batch(order)
-    sim = _sim(cs)
+    sim = _sim(cs, tile_fold=tile_fold)
     sim.set_launch(mode, chunk=512)
     _run_chunks(sim)
     oras = [O.OracleSim(c) for c in cs]
@@ -164,7 +167,7 @@ def test_batch_matches_oracle(order, mode):
             assert dpos <= 1e-6 and du <= 1e-5
         _, _, J = sim.field_arrays(r)
         assert np.abs(J.ravel() - ora.J).max() <= 2e-5 * np.abs(ora.J).max()
-    sim2 = _sim(cs)
+    sim2 = _sim(cs, tile_fold=tile_fold)
     sim2.set_launch(mode, chunk=512)
     _run_chunks(sim2)
     oras = [O.OracleSim(c) for c in cs]

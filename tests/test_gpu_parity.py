@@ -66,10 +66,13 @@ def test_fields_match_oracle(kind, order):
     assert np.abs(E.ravel() - ora.E).max() <= 1e-6 * max(np.abs(ora.E).max(), 1e-30)
 
 
+@pytest.mark.parametrize("tile_fold", [False, True])
 @pytest.mark.parametrize("kind,order", CASES)
-def test_push_and_deposit_match_oracle(kind, order):
+def test_push_and_deposit_match_oracle(kind, order, tile_fold):
+    # tile_fold: the current through per-patch tiles and the fold pass
+    # instead of the particle kernel adding it into J
     c = _make(kind, order)
-    sim = _sim(c)
+    sim = _sim(c, tile_fold=tile_fold)
     ora = O.OracleSim(c)
     sim.push_fields(0)
     sim.push_particles()
@@ -140,11 +143,11 @@ def test_steps_match_oracle(kind, order):
 
 @pytest.mark.parametrize("order", [1, 2])
 def test_steps_match_oracle_3d_patch_fold(order):
-    # every patch 4 wide (at least the current halo at both orders): the 3-d
-    # run folds its current tiles by patch, which the default 3-d case (with
-    # narrower last patches) does not reach
+    # every patch 4 wide (at least the current halo at both orders): with
+    # per-patch current tiles the 3-d run folds them by patch, which the
+    # default 3-d case (with narrower last patches) does not reach
     c = _small_3d(order, seed=18, nxyz=(8, 8, 12), patch=4, ppc=3)
-    sim = _sim(c)
+    sim = _sim(c, tile_fold=True)
     ora = O.OracleSim(c)
     for _ in range(3):
         sim.step(1)
@@ -381,13 +384,15 @@ def test_vb_deposit_matches_oracle(kind):
     assert np.abs(g3 - g0).max() <= 1e-5 * rho_scale
 
 
+@pytest.mark.parametrize("tile_fold", [False, True])
 @pytest.mark.parametrize("order", [1, 2])
-def test_3d_patch8_matches_oracle(order):
+def test_3d_patch8_matches_oracle(order, tile_fold):
     """3-d with the Weibel workload's 8^3 patches (its LDS tile layout, its
-    deposit and the per-patch fold at that size): full patches plus a ragged
-    last patch of 4 cells along z, after one push and after five steps."""
+    deposit, the current added into J with the halo wrapped or the per-patch
+    fold at that size): full patches plus a ragged last patch of 4 cells
+    along z, after one push and after five steps."""
     c = _small_3d(order, seed=61, nxyz=(16, 16, 20), patch=8, ppc=4)
-    sim = _sim(c)
+    sim = _sim(c, tile_fold=tile_fold)
     ora = O.OracleSim(c)
     sim.push_fields(0)
     sim.push_particles()
@@ -401,7 +406,7 @@ def test_3d_patch8_matches_oracle(order):
         assert dpos <= 1e-6 and du <= 1e-5
     _, _, J = sim.field_arrays(0)
     assert np.abs(J.ravel() - ora.J).max() <= 2e-5 * np.abs(ora.J).max()
-    sim2 = _sim(c)
+    sim2 = _sim(c, tile_fold=tile_fold)
     ora2 = O.OracleSim(c)
     for _ in range(5):
         sim2.step(1)

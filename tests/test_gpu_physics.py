@@ -123,9 +123,9 @@ def test_plasma_frequency_gpu(order):
     assert abs(omega - want) <= 1e-5 * want
 
 
-def _batch_vs_alone(runs):
-    batch = _sim(runs)
-    alone = [_sim(r) for r in runs]
+def _batch_vs_alone(runs, **kw):
+    batch = _sim(runs, **kw)
+    alone = [_sim(r, **kw) for r in runs]
     for _ in range(4):
         batch.step(1)
         for a in alone:
@@ -150,12 +150,12 @@ def test_batch_equals_runs_alone():
 
 
 def test_batch_mixing_fold_paths_equals_runs_alone():
-    # order 2 (current halo 3 cells): 18 = 8 + 8 + 2 leaves a last patch
-    # narrower than the halo, folded with the alias search; the other run's
-    # patches are all wide enough for the per-patch fold.  One batch launches
-    # both fold kernels.
+    # per-patch current tiles, order 2 (current halo 3 cells): 18 = 8 + 8 + 2
+    # leaves a last patch narrower than the halo, folded with the alias
+    # search; the other run's patches are all wide enough for the per-patch
+    # fold.  One batch launches both fold kernels.
     _batch_vs_alone([_charged(2, seed=41, ny=18, nz=12, patch=8, ppc=6),
-                     _charged(2, seed=42, ny=24, nz=16, patch=8, ppc=6)])
+                     _charged(2, seed=42, ny=24, nz=16, patch=8, ppc=6)], tile_fold=True)
 
 
 def test_patch_size_independence():
@@ -175,16 +175,31 @@ def test_patch_size_independence():
     assert np.abs(Ea - Eb).max() <= 1e-6 * np.abs(Ea).max()
 
 
-def test_repeat_runs_agree():
-    """Run-to-run reproducibility: the same case advanced twice (Harris
-    sheet, 2nd order, several work items per patch so that patch tiles are
-    added to by several workgroups) gives identical keys, ids and cell
-    offsets; momenta and offsets agree to 1e-6, fields to 2e-5 of their
-    largest value (the one-deposit current tolerance): the current tiles are
-    summed with float atomics whose order varies between runs, the only
-    nondeterminism of the step."""
-    c = cases.harris2d(ny=128, nz=64, ppc=40, order=2, patch=32, seed=17)
-    a, b = _sim(c, chunk=1024), _sim(c, chunk=1024)
+def _weibel_small():
+    c = cases.weibel3d(ppc=16, order=1, patch=8, nxyz=(16, 16, 24), seed=19)
+    cases.random_fields(c, 0.05, 0.3, seed=20)
+    return c
+
+
+REPEAT_CASES = {
+    "harris2d": lambda: cases.harris2d(ny=128, nz=64, ppc=40, order=2, patch=32, seed=17),
+    "weibel3d": _weibel_small,
+}
+
+
+@pytest.mark.parametrize("tile_fold", [False, True])
+@pytest.mark.parametrize("name", sorted(REPEAT_CASES))
+def test_repeat_runs_agree(name, tile_fold):
+    """Run-to-run reproducibility: the same case advanced twice (several work
+    items per patch, so that a patch's current is added to by several
+    workgroups in an order that varies between runs) gives identical keys,
+    ids and cell offsets.  With the current added into J by the particle
+    kernel, in fixed point (integer sums), the whole state is bit for bit
+    identical.  With per-patch float tiles (tile_fold) the tiles are summed
+    with float atomics: momenta and offsets agree to 1e-6, fields to 2e-5 of
+    their largest value (the one-deposit current tolerance)."""
+    c = REPEAT_CASES[name]()
+    a, b = _sim(c, chunk=1024, tile_fold=tile_fold), _sim(c, chunk=1024, tile_fold=tile_fold)
     for _ in range(10):
         a.step(1)
         b.step(1)
@@ -198,9 +213,11 @@ def test_repeat_runs_agree():
         assert np.abs(pa["u"] - pb["u"]).max(initial=0) <= 1e-6
         assert np.abs(pa["off"] - pb["off"]).max(initial=0) <= 1e-6
         ndiff += int((pa["u"] != pb["u"]).sum() + (pa["off"] != pb["off"]).sum())
-    for name, fa, fb in zip("EBJ", a.field_arrays(0), b.field_arrays(0)):
+    for fname, fa, fb in zip("EBJ", a.field_arrays(0), b.field_arrays(0)):
         rel = float(np.abs(fa - fb).max() / max(np.abs(fa).max(), 1e-30))
-        print(f"{name}: largest difference {rel:.2e} of max|{name}|", flush=True)
+        print(f"{fname}: largest difference {rel:.2e} of max|{fname}|", flush=True)
         assert rel <= 2e-5
         ndiff += int((fa != fb).sum())
-    print(f"10 steps, two runs: {ndiff} float values differ (integer state identical)", flush=True)
+    print(f"{name}, 10 steps, two runs: {ndiff} float values differ (integer state identical)", flush=True)
+    if not tile_fold:
+        assert ndiff == 0
