@@ -252,6 +252,80 @@ __host__ __device__ inline void move_delta(int dim, int m, int d[3]) {
     }
 }
 
+// Patch coordinate, local coordinate and patch extent of each cell along
+// one dimension, and of its neighbours one cell down (index 0) and up (2):
+// a move of at most one cell leaves the patch only at its faces, so the
+// neighbour's patch is the same or the adjacent one (periodic) and needs
+// no division.
+struct Axis {
+    int pc[3], l[3], ext[3];
+};
+
+__host__ __device__ inline Axis axis_neighbours(int P, int n, int np, int pc, int l) {
+    Axis a;
+    const int ext = imin(P, n - pc * P);
+    const int pdn = pc == 0 ? np - 1 : pc - 1, pup = pc == np - 1 ? 0 : pc + 1;
+    const int edn = imin(P, n - pdn * P);
+    a.pc[1] = pc;
+    a.l[1] = l;
+    a.ext[1] = ext;
+    const bool out_dn = l == 0;
+    a.pc[0] = out_dn ? pdn : pc;
+    a.l[0] = out_dn ? edn - 1 : l - 1;
+    a.ext[0] = out_dn ? edn : ext;
+    const bool out_up = l == ext - 1;
+    a.pc[2] = out_up ? pup : pc;
+    a.l[2] = out_up ? 0 : l + 1;
+    a.ext[2] = out_up ? imin(P, n - pup * P) : ext;
+    return a;
+}
+
+// key of the cell at (patch, local) coordinates, extents given
+__host__ __device__ inline uint32_t key_of(const RunDev &r, int p0, int p1, int p2, int l0, int l1, int l2, int e0,
+                                           int e1, int e2) {
+    return (uint32_t)p2 * r.P[2] * r.n[1] * r.n[0] + (uint32_t)p1 * r.P[1] * e2 * r.n[0] +
+           (uint32_t)p0 * r.P[0] * e1 * e2 + (uint32_t)(l0 + e0 * (l1 + e1 * l2));
+}
+
+// Rank, in key order, of the source cell of each move code m of a new
+// cell (the cell one move against m; ax: the new cell's per-axis
+// candidates below / own / above from axis_neighbours).  Keys order cells
+// by patch coordinate (z, y, x), then by local coordinate (z, y, x), so per
+// axis it is enough to know, for each candidate a, how many of the three
+// lie in a lower patch (lo), in the same patch (eq, a included) and in the
+// same patch at a lower local coordinate (in):
+//   rank = lo_z 3 K + eq_z (lo_y K + eq_y lo_x) + in_z eq_y eq_x + in_y eq_x + in_x
+// with K the candidates per x (3 in 3-d; 2-d: x inactive, lo = in = 0,
+// eq = 1).  Distinct source cells (every active axis has >= 3 cells) get
+// the ranks 0 .. M - 1.
+template <int DIM>
+__host__ __device__ inline void source_ranks(const Axis ax[3], int rank[]) {
+    constexpr int M = DIM == 3 ? 27 : 9;
+    constexpr int K = DIM == 3 ? 3 : 1;
+    int lo[3][3], eq[3][3], in[3][3];
+    for (int d = 0; d < 3; ++d)
+        for (int a = 0; a < 3; ++a) {
+            lo[d][a] = 0;
+            eq[d][a] = 1;
+            in[d][a] = 0;
+            if (DIM == 2 && d == 0) continue;
+            for (int b = 0; b < 3; ++b) {
+                if (b == a) continue;
+                lo[d][a] += ax[d].pc[b] < ax[d].pc[a] ? 1 : 0;
+                eq[d][a] += ax[d].pc[b] == ax[d].pc[a] ? 1 : 0;
+                in[d][a] += ax[d].pc[b] == ax[d].pc[a] && ax[d].l[b] < ax[d].l[a] ? 1 : 0;
+            }
+        }
+    for (int m = 0; m < M; ++m) {
+        int dm[3];
+        move_delta(DIM, m, dm);
+        const int x = DIM == 3 ? 1 - dm[0] : 1, y = 1 - dm[1], z = 1 - dm[2];
+        const int r = lo[2][z] * 3 * K + eq[2][z] * (lo[1][y] * K + eq[1][y] * lo[0][x]) +
+                      in[2][z] * eq[1][y] * eq[0][x] + in[1][y] * eq[0][x] + in[0][x];
+        rank[m] = r < M - 1 ? r : M - 1;
+    }
+}
+
 // ----------------------------------------------------------------------------
 // launchers (defined in the .hip files)
 // ----------------------------------------------------------------------------

@@ -174,34 +174,6 @@ __device__ __forceinline__ void walk_cells(const int32_t *sb, int nw, int32_t pb
     }
 }
 
-// Patch coordinate, local coordinate and patch extent of each cell along
-// one dimension, and of its neighbours one cell down (index 0) and up (2):
-// a move of at most one cell leaves the patch only at its faces, so the
-// neighbour's patch is the same or the adjacent one (periodic) and needs
-// no division.
-struct Axis {
-    int pc[3], l[3], ext[3];
-};
-
-__device__ __forceinline__ Axis axis_neighbours(int P, int n, int np, int pc, int l) {
-    Axis a;
-    const int ext = imin(P, n - pc * P);
-    const int pdn = pc == 0 ? np - 1 : pc - 1, pup = pc == np - 1 ? 0 : pc + 1;
-    const int edn = imin(P, n - pdn * P);
-    a.pc[1] = pc;
-    a.l[1] = l;
-    a.ext[1] = ext;
-    const bool out_dn = l == 0;
-    a.pc[0] = out_dn ? pdn : pc;
-    a.l[0] = out_dn ? edn - 1 : l - 1;
-    a.ext[0] = out_dn ? edn : ext;
-    const bool out_up = l == ext - 1;
-    a.pc[2] = out_up ? pup : pc;
-    a.l[2] = out_up ? 0 : l + 1;
-    a.ext[2] = out_up ? imin(P, n - pup * P) : ext;
-    return a;
-}
-
 // decode_key in 32-bit arithmetic (keys and every product below are less
 // than the run's cell count, which is below 2^31)
 __device__ __forceinline__ void decode_key32(const RunDev &r, uint32_t key, int pc[3], int l[3]) {
@@ -223,18 +195,14 @@ __device__ __forceinline__ void decode_key32(const RunDev &r, uint32_t key, int 
     l[2] = (int)(q / hy);
 }
 
-// key of the cell at (patch, local) coordinates, extents given
-__device__ __forceinline__ uint32_t key_of(const RunDev &r, int p0, int p1, int p2, int l0, int l1, int l2, int e0,
-                                           int e1, int e2) {
-    return (uint32_t)p2 * r.P[2] * r.n[1] * r.n[0] + (uint32_t)p1 * r.P[1] * e2 * r.n[0] +
-           (uint32_t)p0 * r.P[0] * e1 * e2 + (uint32_t)(l0 + e0 * (l1 + e1 * l2));
-}
-
-// per new cell n of species S of run R: order the source cells by key and
-// assign arrival prefixes
+// per new cell n of species S of run R: the arrivals from each source cell
+// (one move against each move code), ordered by the source's key, give
+// each (move, source) its arrival prefix.  The order comes in closed form
+// from source_ranks; the prefix sums run through this thread's M words of
+// LDS (`slot`), written in rank order.
 template <int DIM>
 __device__ __forceinline__ int32_t prefix_cell(const RunDev &R, const SpeciesDev &S, int64_t n, int cs_sel,
-                                               uint32_t *err) {
+                                               uint32_t *err, int32_t *slot) {
     constexpr int M = DIM == 3 ? 27 : 9;
     constexpr int CENTER = M / 2;   // the move that stays in the cell
     const int64_t nc = R.ncell;
@@ -243,6 +211,8 @@ __device__ __forceinline__ int32_t prefix_cell(const RunDev &R, const SpeciesDev
     Axis ax[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) ax[d] = axis_neighbours(R.P[d], R.n[d], R.np[d], pc[d], lc[d]);
+    int rk[M];
+    source_ranks<DIM>(ax, rk);
     int32_t ks[M];
     int32_t cn[M];
     // arrivals into n from each source (the particle kernel counts the
@@ -267,15 +237,17 @@ __device__ __forceinline__ int32_t prefix_cell(const RunDev &R, const SpeciesDev
         stay = 0;
     }
     cn[CENTER] = stay;
+#pragma unroll
+    for (int m = 0; m < M; ++m) slot[rk[m]] = cn[m];
     int32_t tot = 0;
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-        int32_t pre = 0;
-#pragma unroll
-        for (int q = 0; q < M; ++q) pre += ks[q] < ks[m] ? cn[q] : 0;
-        S.pre[m * nc + ks[m]] = (uint16_t)pre;
-        tot += cn[m];
+    for (int k = 0; k < M; ++k) {
+        const int32_t v = slot[k];
+        slot[k] = tot;
+        tot += v;
     }
+#pragma unroll
+    for (int m = 0; m < M; ++m) S.pre[m * nc + ks[m]] = (uint16_t)slot[rk[m]];
     if (tot > 65535) atomicOr(err, PSC_DEV_OVERFULL);
     S.tot[n] = tot;
     return tot;
@@ -293,14 +265,16 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_prefix(const RunDev *__rest
                                                             const int32_t *__restrict__ seg_run,
                                                             const int32_t *__restrict__ seg_sp, int cs_sel,
                                                             int32_t *__restrict__ partial, uint32_t *err) {
+    constexpr int M = DIM == 3 ? 27 : 9;
     __shared__ int32_t wsum[kSortBlock / 64];
+    __shared__ int32_t slots[kSortBlock * M];   // M words per thread (odd stride: no bank conflicts in order)
     const int64_t blk = blockIdx.x;
     const int64_t b = blk / kPrefixPerScan;
     const int sg = block_seg[b];
     const RunDev &R = runs[seg_run[sg]];
     const int64_t n = (b - segs[sg].block0) * kScanBlock + (blk - b * kPrefixPerScan) * kSortBlock + threadIdx.x;
     int32_t tot = 0;
-    if (n < segs[sg].n) tot = prefix_cell<DIM>(R, R.sp[seg_sp[sg]], n, cs_sel, err);
+    if (n < segs[sg].n) tot = prefix_cell<DIM>(R, R.sp[seg_sp[sg]], n, cs_sel, err, slots + threadIdx.x * M);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off, 64);
     if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = tot;

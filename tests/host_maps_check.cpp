@@ -99,10 +99,71 @@ static void check_current_direct_map() {
     CHECK(accepted > 0 && refused > 0, "direct-path geometries: %d accepted, %d refused", accepted, refused);
 }
 
+// The sort's closed-form order of the source cells of a new cell (one move
+// against each move code) equals the order of their keys, found by brute
+// force, for every cell of grids with truncated last patches, single
+// patches and 3-cell axes, in 2-d and 3-d; and the ranks are 0 .. M - 1.
+template <int DIM>
+static void check_source_ranks_grid(const int n[3], const int P[3]) {
+    constexpr int M = DIM == 3 ? 27 : 9;
+    RunDev r{};
+    r.dim = DIM;
+    for (int d = 0; d < 3; ++d) {
+        r.n[d] = n[d];
+        r.P[d] = P[d];
+        r.np[d] = (n[d] + P[d] - 1) / P[d];
+    }
+    const int64_t nc = (int64_t)n[0] * n[1] * n[2];
+    for (int64_t key = 0; key < nc; ++key) {
+        int g[3], pc[3], l[3];
+        decode_key(r, key, g);
+        Axis ax[3];
+        for (int d = 0; d < 3; ++d) {
+            pc[d] = g[d] / P[d];
+            l[d] = g[d] - pc[d] * P[d];
+            ax[d] = axis_neighbours(P[d], n[d], r.np[d], pc[d], l[d]);
+        }
+        int rk[M];
+        source_ranks<DIM>(ax, rk);
+        uint32_t ks[M];
+        for (int m = 0; m < M; ++m) {
+            int dm[3];
+            move_delta(DIM, m, dm);
+            const int a0 = DIM == 3 ? 1 - dm[0] : 1, a1 = 1 - dm[1], a2 = 1 - dm[2];
+            ks[m] = key_of(r, ax[0].pc[a0], ax[1].pc[a1], ax[2].pc[a2], ax[0].l[a0], ax[1].l[a1], ax[2].l[a2],
+                           ax[0].ext[a0], ax[1].ext[a1], ax[2].ext[a2]);
+            // the source is the wrapped cell one move back
+            const int gi = wrap(g[0] - dm[0], n[0]), gj = wrap(g[1] - dm[1], n[1]), gk = wrap(g[2] - dm[2], n[2]);
+            CHECK((int64_t)ks[m] == encode_key(r, gi, gj, gk), "grid %dx%dx%d key %lld move %d: wrong source",
+                  n[0], n[1], n[2], (long long)key, m);
+        }
+        int seen[M] = {0};
+        for (int m = 0; m < M; ++m) {
+            int want = 0;
+            for (int q = 0; q < M; ++q) want += ks[q] < ks[m] ? 1 : 0;
+            CHECK(rk[m] == want, "grid %dx%dx%d patch %dx%dx%d key %lld move %d: rank %d, key order %d", n[0], n[1],
+                  n[2], P[0], P[1], P[2], (long long)key, m, rk[m], want);
+            if (rk[m] >= 0 && rk[m] < M) ++seen[rk[m]];
+        }
+        for (int k = 0; k < M; ++k) CHECK(seen[k] == 1, "key %lld: rank %d taken %d times", (long long)key, k, seen[k]);
+    }
+}
+
+static void check_source_ranks() {
+    struct G { int n[3], P[3]; };
+    const G g3[] = {{{8, 8, 8}, {4, 4, 4}}, {{10, 9, 7}, {4, 4, 4}}, {{7, 9, 6}, {3, 4, 2}}, {{3, 3, 3}, {3, 3, 3}},
+                    {{5, 6, 7}, {5, 2, 3}}, {{9, 4, 10}, {4, 4, 3}}, {{16, 16, 20}, {8, 8, 8}}, {{3, 5, 4}, {1, 2, 4}}};
+    for (const G &g : g3) check_source_ranks_grid<3>(g.n, g.P);
+    const G g2[] = {{{1, 12, 9}, {1, 4, 4}}, {{1, 10, 7}, {1, 4, 3}}, {{1, 8, 5}, {1, 8, 2}}, {{1, 3, 3}, {1, 3, 3}},
+                    {{1, 20, 12}, {1, 8, 8}}, {{1, 18, 12}, {1, 8, 8}}, {{1, 5, 9}, {1, 1, 4}}};
+    for (const G &g : g2) check_source_ranks_grid<2>(g.n, g.P);
+}
+
 int main() {
     check_mix_lane();
     check_neighbour_key();
     check_current_direct_map();
+    check_source_ranks();
     if (failures) {
         std::printf("%d failures\n", failures);
         return 1;
