@@ -121,6 +121,45 @@ def test_sort_matches_stable_sort(kind, order):
             assert np.array_equal(cst, np.concatenate([[0], np.cumsum(counts)]))
 
 
+# Sort workloads of different densities for the scatter pass (waves of 64
+# cells in 3-d, 32 in 2-d, each walking its particles 64 at a time): groups
+# spanning many cells, about one cell, a fraction of a cell, and one cell
+# holding hundreds of particles.
+SORT_LOADS = [("3d", 3, 0), ("3d", 20, 0), ("3d", 40, 0), ("3d", 45, 0), ("3d", 4, 400), ("2d", 40, 0),
+              ("2d", 90, 0), ("2d", 5, 300)]
+
+
+@pytest.mark.parametrize("kind,ppc,dense", SORT_LOADS)
+def test_sort_scatter_paths_match_stable_sort(kind, ppc, dense):
+    if kind == "3d":
+        c = _small_3d(1, seed=91, nxyz=(8, 8, 12), patch=4, ppc=ppc)
+    else:
+        c = _small_2d(1, seed=92, ny=64, nz=16, patch=16, ppc=ppc)
+    if dense:
+        # `dense` particles of species 0 moved into one cell
+        sp = c.species[0]
+        sp.cell[:dense] = sp.cell[0]
+    sim = _sim(c)
+    for step in range(2):
+        sim.push_fields(0)
+        sim.push_particles()
+        sim.push_fields(0)
+        sim.deposit_current()
+        sim.push_fields(1)
+        sim.sort()
+        assert sim.error_word() == 0
+        for s in range(len(c.species)):
+            f, _ = sim.front()
+            n = c.species[s].n
+            keys = sim.parts[0][s][f]["cell"][:n].cpu().numpy()
+            perm, cst = sim.sort_view(0, s)
+            assert np.array_equal(perm, O.stable_sort(keys, c.ncell)), (step, s)
+            counts = np.bincount(keys, minlength=c.ncell)
+            assert np.array_equal(cst, np.concatenate([[0], np.cumsum(counts)]))
+            if dense and s == 0:
+                assert counts.max() >= dense // 2   # the dense cell is still dense
+
+
 @pytest.mark.parametrize("kind,order", CASES)
 def test_steps_match_oracle(kind, order):
     c = _make(kind, order)
