@@ -395,11 +395,26 @@ psc_status psc_get_cell_offsets(psc_ctx *ctx, int run, int species, int32_t *out
  * not name is the one the next psc_push_particles writes, so swapping it
  * before each step keeps every step's particles in arrays of their own (the
  * adjoint's recomputed segments); swapping the front set is allowed only
- * with arrays that hold the same particles.  Uploads the run's table entry
- * on `stream` (through a pinned staging slot, no host wait); drops recorded
- * step graphs. */
+ * with arrays that hold the same particles.  The run table is uploaded on
+ * the stream of the next call that launches kernels (one copy through a
+ * pinned staging slot for all changes since the last upload, no host
+ * wait); drops recorded step graphs.  `stream` is unused. */
 psc_status psc_set_particle_buffers(psc_ctx *ctx, int run, int species, int set, int32_t *cell, float *off, float *u,
                                     int32_t *id, void *stream);
+
+/* Direct the outputs of the next psc_sort (or psc_sort_radix) of (run,
+ * species) to caller device arrays: its permutation into `perm` (int32,
+ * the species' capacity) and its new cell offsets into `cs` (int32, ncell
+ * + 1).  The following psc_push_particles reads them there, and
+ * psc_get_perm / psc_get_cell_offsets copy from there, so a caller that
+ * redirects every step keeps each step's permutation and offsets in arrays
+ * of their own without copies (the adjoint's recomputed segments).  perm ==
+ * cs == NULL returns to the workspace's own arrays, copying the current
+ * offsets (and a pending permutation) back into them on `stream`.  Both or
+ * neither must be NULL (PSC_ERR_INVALID otherwise).  The run table is
+ * uploaded before the next launch, as with psc_set_particle_buffers; drops
+ * recorded step graphs. */
+psc_status psc_set_sort_outputs(psc_ctx *ctx, int run, int species, int32_t *perm, int32_t *cs, void *stream);
 
 /* Forward state of one step, per run, as the adjoint needs it: fields at the
  * start of the step (E^{n+1/2}, B^n), the particles at the start of the step,

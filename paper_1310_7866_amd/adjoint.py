@@ -90,11 +90,23 @@ class EnergyGradient:
                                  for _ in range(self.every + 1)] for sp in c.species] for c in sim.cases]
         return self._ring_bufs
 
+    def _sort_ring(self):
+        """every + 1 (permutation, cell offsets) pairs per (run, species),
+        allocated once: the sort of recomputed step j writes pair j + 1, which
+        step j + 1 reads and the reverse step uses, with no copies."""
+        if getattr(self, "_sort_bufs", None) is None:
+            sim, torch = self.sim, self.sim.torch
+            i32 = torch.int32
+            self._sort_bufs = [[[dict(perm=torch.empty(max(sp.n, 1), dtype=i32, device=sim.device),
+                                      cs=torch.empty(c.ncell + 1, dtype=i32, device=sim.device))
+                                 for _ in range(self.every + 1)] for sp in c.species] for c in sim.cases]
+        return self._sort_bufs
+
     def backward_device(self):
         """Reverse pass; per run (dW/dE0 (3, ncell), dW/dB0 (3, ncell),
         [dW/du0 (3, n) per species in case order]) as device tensors."""
         sim, torch = self.sim, self.sim.torch
-        ring = self._ring()
+        ring, sring = self._ring(), self._sort_ring()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         a.record()
@@ -102,29 +114,31 @@ class EnergyGradient:
         sim.adjoint_seed(lam)
         for k0, snap in reversed(self.ckpts):
             k1 = min(k0 + self.every, self.nsteps)
-            # the segment starts from its snapshot, loaded (sorted) into ring set 0
+            # the segment starts from its snapshot, loaded (sorted) into ring
+            # set 0, with the workspace's permutation and offsets
             for r, c in enumerate(sim.cases):
                 for s in range(len(c.species)):
+                    sim.set_sort_outputs(r, s, None, None)
                     sim.set_particle_buffers(r, s, 0, ring[r][s][0])
             sim.restore(snap)
             states = []
-            read_perm = [[None] * len(c.species) for c in sim.cases]
             for j in range(k1 - k0):
                 front, _ = sim.front()
                 st = []
                 for r, c in enumerate(sim.cases):
-                    E, B, _ = sim.fields[r]
+                    nc3 = 3 * c.ncell
+                    EB = sim.field_blocks[r][:2 * nc3].clone()   # E and B of the step, one copy
                     parts = []
                     for s, sp in enumerate(c.species):
                         q = ring[r][s][j]
                         parts.append(dict(key=q["cell"], off=q["off"], u=q["u"], stride=sp.n,
-                                          read_perm=read_perm[r][s], cell_start=sim.cell_offsets(r, s)))
+                                          read_perm=sring[r][s][j]["perm"] if j else None,
+                                          cell_start=sring[r][s][j]["cs"] if j else sim.cell_offsets(r, s)))
                         sim.set_particle_buffers(r, s, 1 - front, ring[r][s][j + 1])
-                    st.append(dict(E=E.clone(), B=B.clone(), parts=parts))
+                        sim.set_sort_outputs(r, s, sring[r][s][j + 1]["perm"], sring[r][s][j + 1]["cs"])
+                    st.append(dict(E=EB[:nc3], B=EB[nc3:], parts=parts,
+                                   perm=[sring[r][s][j + 1]["perm"][:sp.n] for s, sp in enumerate(c.species)]))
                 sim.step(1)
-                for r, c in enumerate(sim.cases):
-                    st[r]["perm"] = [sim.get_perm(r, s) for s in range(len(c.species))]
-                    read_perm[r] = st[r]["perm"]
                 states.append(st)
             for st in reversed(states):
                 sim.adjoint_step(st, lam)
@@ -135,6 +149,7 @@ class EnergyGradient:
         # back on the context's own buffers, at the initial state
         for r, c in enumerate(sim.cases):
             for s in range(len(c.species)):
+                sim.set_sort_outputs(r, s, None, None)
                 sim.set_particle_buffers(r, s, 0, sim.parts[r][s][0])
                 sim.set_particle_buffers(r, s, 1, sim.parts[r][s][1])
         sim.restore(self.ckpts[0][1])

@@ -63,7 +63,7 @@ struct psc_ctx {
     std::vector<int64_t> patch_base;     // n_runs + 1: first patch of each run in the flat patch space
     int max_patch_cells = 0;             // cells of the largest patch of any run
     int fold_direct_dims = 0;            // bit 1 << dim: a run of that dimension folds by patch
-    bool any_jdirect = false;            // a run whose particle kernel adds into J directly
+    bool any_jdirect = false;            // a run whose particle kernel adds into fixed-point current sums
     bool any_fold_search = false;
     int n_segs = 0;
     std::vector<int64_t> seg_base;       // n_segs + 1
@@ -90,9 +90,12 @@ struct psc_ctx {
     size_t adj_lds = 0;
     int64_t adj_items = 0;                  // work items of the particle adjoint (kAdjChunk particles)
     std::vector<AdjRun> adj;                 // host mirror of the adjoint table
-    RunDev *run_pinned = nullptr;            // kRunRing staged run-table entries (pinned)
+    RunDev *run_pinned = nullptr;            // kRunRing staged copies of the run table (pinned)
     hipEvent_t run_done[kRunRing] = {};
     uint64_t run_calls = 0;
+    bool runs_dirty = false;                 // host run table changed since its last upload
+    bool segs_dirty = false;                 // ... and with it the scan segments' output offsets
+    ScanSeg *segs_pinned = nullptr;          // kRunRing staged copies of both scan-segment tables
     AdjRun *adj_pinned = nullptr;            // kAdjRing * n_runs tables in pinned host memory
     hipEvent_t adj_done[kAdjRing] = {};      // completion of the call that last used each slot
     uint64_t adj_calls = 0;
@@ -121,6 +124,7 @@ struct psc_ctx {
         for (hipEvent_t &e : run_done)
             if (e) hipEventDestroy(e);
         if (run_pinned) hipHostFree(run_pinned);
+        if (segs_pinned) hipHostFree(segs_pinned);
     }
 };
 
@@ -153,6 +157,52 @@ Launch make_launch(psc_ctx *ctx, hipStream_t s) {
     L.stream = s;
     L.err = ctx->err();
     return L;
+}
+
+// Upload the host run table if psc_set_particle_buffers / psc_set_sort_outputs
+// changed it: one copy through a pinned staging slot, ordered on the stream,
+// without a host wait (a slot is reused once its copy has completed).
+// Called by every entry point that launches kernels reading the table.
+static psc_status sync_runs(psc_ctx *ctx, hipStream_t s) {
+    if (!ctx->runs_dirty) return PSC_OK;
+    if (!ctx->run_pinned) {
+        HIPCHECK(hipHostMalloc((void **)&ctx->run_pinned, sizeof(RunDev) * kRunRing * ctx->n_runs,
+                               hipHostMallocDefault),
+                 "run table staging");
+        for (hipEvent_t &e : ctx->run_done) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+    }
+    const int slot = (int)(ctx->run_calls++ % kRunRing);
+    HIPCHECK(hipEventSynchronize(ctx->run_done[slot]), "run table slot");
+    RunDev *staged = ctx->run_pinned + (size_t)slot * ctx->n_runs;
+    std::memcpy(staged, ctx->runs.data(), sizeof(RunDev) * ctx->n_runs);
+    HIPCHECK(hipMemcpyAsync(ctx->at<RunDev>(ctx->off.runs), staged, sizeof(RunDev) * ctx->n_runs,
+                            hipMemcpyHostToDevice, s),
+             "upload runs");
+    if (ctx->segs_dirty) {
+        // the scan writes the new cell offsets through the segment tables
+        // (table c for cs_sel == c: into cs[1 - c])
+        if (!ctx->segs_pinned)
+            HIPCHECK(hipHostMalloc((void **)&ctx->segs_pinned, sizeof(ScanSeg) * kRunRing * 2 * ctx->n_segs,
+                                   hipHostMallocDefault),
+                     "segment table staging");
+        ScanSeg *sg = ctx->segs_pinned + (size_t)slot * 2 * ctx->n_segs;
+        for (int c = 0; c < 2; ++c)
+            for (int g = 0; g < ctx->n_segs; ++g) {
+                ScanSeg &t = ctx->segs_host[c][g];
+                t.out = ctx->runs[ctx->seg_run[g]].sp[ctx->seg_sp[g]].cs[1 - c];
+                sg[(size_t)c * ctx->n_segs + g] = t;
+            }
+        HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.segs0), sg, sizeof(ScanSeg) * ctx->n_segs,
+                                hipMemcpyHostToDevice, s),
+                 "upload segs0");
+        HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.segs1), sg + ctx->n_segs, sizeof(ScanSeg) * ctx->n_segs,
+                                hipMemcpyHostToDevice, s),
+                 "upload segs1");
+        ctx->segs_dirty = false;
+    }
+    HIPCHECK(hipEventRecord(ctx->run_done[slot], s), "run table event");
+    ctx->runs_dirty = false;
+    return PSC_OK;
 }
 
 // the (run, species, patch) units: runs one after another, each run's
@@ -535,7 +585,7 @@ psc_status psc_bind(psc_ctx *ctx, const psc_run_bufs *bufs, int n_runs, void *wo
             }
             S.cs[0] = ctx->at<int32_t>(ctx->off_cs0[r][sp]);
             S.cs[1] = ctx->at<int32_t>(ctx->off_cs1[r][sp]);
-            S.perm = ctx->at<int32_t>(ctx->off_perm[r][sp]);
+            S.perm[0] = S.perm[1] = ctx->at<int32_t>(ctx->off_perm[r][sp]);
             S.mc = ctx->at<uint8_t>(ctx->off_mc[r][sp]);
             S.cnt = ctx->at<uint16_t>(ctx->off_cnt[r][sp]);
             S.pre = ctx->at<uint16_t>(ctx->off_pre[r][sp]);
@@ -572,6 +622,7 @@ psc_status psc_bind(psc_ctx *ctx, const psc_run_bufs *bufs, int n_runs, void *wo
                             hipMemcpyHostToDevice, s), "upload segs0");
     HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.segs1), segs1.data(), sizeof(ScanSeg) * ctx->n_segs,
                             hipMemcpyHostToDevice, s), "upload segs1");
+    ctx->runs_dirty = ctx->segs_dirty = false;   // the bound table is the one uploaded here
     HIPCHECK(hipMemcpyAsync(ctx->at<int32_t>(ctx->off.scan_tmp) + ctx->n_scan_blocks, ctx->block_seg.data(),
                             sizeof(int32_t) * ctx->n_scan_blocks, hipMemcpyHostToDevice, s), "upload block table");
     HIPCHECK(hipMemsetAsync(ctx->err(), 0, sizeof(uint32_t), s), "clear error word");
@@ -763,6 +814,7 @@ static psc_status require_loaded(psc_ctx *ctx) {
 psc_status psc_push_fields(psc_ctx *ctx, int op, void *stream) {
     if (!ctx || !ctx->bound) return PSC_ERR_STATE;
     if (op != PSC_B_HALF && op != PSC_E_FULL) return PSC_ERR_INVALID;
+    if (psc_status rs = sync_runs(ctx, (hipStream_t)stream); rs != PSC_OK) return rs;
     Launch L = make_launch(ctx, (hipStream_t)stream);
     HIPCHECK(launch_fields(L, op, ctx->total_cells, ctx->at<int64_t>(ctx->off.run_base)), "push fields");
     return PSC_OK;
@@ -772,6 +824,7 @@ psc_status psc_push_particles(psc_ctx *ctx, void *stream) {
     psc_status st = require_loaded(ctx);
     if (st != PSC_OK) return st;
     if (ctx->mc_valid && (st = clear_move_counts(ctx, (hipStream_t)stream)) != PSC_OK) return st;
+    if (psc_status rs = sync_runs(ctx, (hipStream_t)stream); rs != PSC_OK) return rs;
     Launch L = make_launch(ctx, (hipStream_t)stream);
     PushMode pm = ctx->pm;
     pm.queue = ctx->at<int32_t>(ctx->off.queue);
@@ -789,6 +842,7 @@ psc_status psc_push_particles(psc_ctx *ctx, void *stream) {
 
 psc_status psc_deposit_current(psc_ctx *ctx, void *stream) {
     if (!ctx || !ctx->bound) return PSC_ERR_STATE;
+    if (psc_status rs = sync_runs(ctx, (hipStream_t)stream); rs != PSC_OK) return rs;
     Launch L = make_launch(ctx, (hipStream_t)stream);
     if (ctx->any_jdirect)
         HIPCHECK(launch_finish_current(L, ctx->total_cells, ctx->at<int64_t>(ctx->off.run_base)), "finish current");
@@ -804,6 +858,7 @@ psc_status psc_sort(psc_ctx *ctx, void *stream) {
     psc_status st = require_loaded(ctx);
     if (st != PSC_OK) return st;
     if (!ctx->mc_valid) return fail(ctx, PSC_ERR_STATE, "psc_sort needs a preceding psc_push_particles");
+    if (psc_status rs = sync_runs(ctx, (hipStream_t)stream); rs != PSC_OK) return rs;
     Launch L = make_launch(ctx, (hipStream_t)stream);
     HIPCHECK(launch_sort(L, ctx->at<int64_t>(ctx->off.seg_base), ctx->at<int32_t>(ctx->off.seg_run),
                          ctx->at<int32_t>(ctx->off.seg_sp), ctx->n_segs, ctx->total_seg_cells,
@@ -831,7 +886,7 @@ psc_status psc_sort_radix(psc_ctx *ctx, void *stream) {
             if (S.n > 0) {
                 HIPCHECK(launch_iota(idx, S.n, s), "radix sort indices");
                 size_t tb = ctx->rsort_bytes;
-                HIPCHECK(radix_sort_pairs(ctx->at<void>(ctx->off.rsort), &tb, S.cell[ctx->front], keys_s, idx, S.perm,
+                HIPCHECK(radix_sort_pairs(ctx->at<void>(ctx->off.rsort), &tb, S.cell[ctx->front], keys_s, idx, S.perm[1 - ctx->cs_sel],
                                           S.n, bits, s),
                          "radix sort");
             }
@@ -862,6 +917,7 @@ psc_status psc_step(psc_ctx *ctx, int nsteps, int use_graph, void *stream) {
     if (st != PSC_OK) return st;
     if (nsteps < 0) return PSC_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
+    if ((st = sync_runs(ctx, s)) != PSC_OK) return st;   // before any capture
     for (int k = 0; k < nsteps; ++k) {
         if (!use_graph) {
             if ((st = one_step(ctx, stream)) != PSC_OK) return st;
@@ -907,7 +963,9 @@ psc_status psc_get_particles(psc_ctx *ctx, int run, int species, int32_t *cell, 
                              void *stream) {
     if (!ctx || !ctx->bound) return PSC_ERR_STATE;
     if (run < 0 || run >= ctx->n_runs || species < 0 || species >= ctx->runs[run].n_species) return PSC_ERR_INVALID;
-    HIPCHECK(launch_get(ctx->runs[run], species, ctx->front, ctx->perm_pending, cell, off, u, id, (hipStream_t)stream),
+    const SpeciesDev &Sg = ctx->runs[run].sp[species];
+    HIPCHECK(launch_get(ctx->runs[run], species, ctx->front, ctx->perm_pending ? Sg.perm[ctx->cs_sel] : nullptr, cell, off,
+                        u, id, (hipStream_t)stream),
              "get particles");
     return PSC_OK;
 }
@@ -935,13 +993,14 @@ psc_status psc_front(const psc_ctx *ctx, int *front, int *perm_pending) {
 psc_status psc_sort_view(const psc_ctx *ctx, int run, int species, const int32_t **perm, const int32_t **cell_start) {
     if (!ctx || !ctx->bound || run < 0 || run >= ctx->n_runs || species < 0 || species >= ctx->runs[run].n_species)
         return PSC_ERR_INVALID;
-    if (perm) *perm = ctx->runs[run].sp[species].perm;
+    if (perm) *perm = ctx->runs[run].sp[species].perm[ctx->cs_sel];
     if (cell_start) *cell_start = ctx->runs[run].sp[species].cs[ctx->cs_sel];
     return PSC_OK;
 }
 
 psc_status psc_diagnostics(psc_ctx *ctx, double *out_dev, double *gauss_dev, void *stream) {
     if (!ctx || !ctx->bound || !out_dev) return PSC_ERR_INVALID;
+    if (psc_status rs = sync_runs(ctx, (hipStream_t)stream); rs != PSC_OK) return rs;
     Launch L = make_launch(ctx, (hipStream_t)stream);
     HIPCHECK(launch_diag(L, out_dev, gauss_dev, ctx->total_cells, ctx->at<int64_t>(ctx->off.run_base), ctx->front),
              "diagnostics");
@@ -958,6 +1017,7 @@ psc_status psc_marder(psc_ctx *ctx, const double *ref, double d, int iters, void
         for (int k = (r.dim == 3 ? 0 : 1); k < 3; ++k) lap += 4.0 / (r.dx[k] * r.dx[k]);
         if (d * r.dt * lap > 2.0) return fail(ctx, PSC_ERR_INVALID, "Marder coefficient above the stability bound");
     }
+    if (psc_status rs = sync_runs(ctx, (hipStream_t)stream); rs != PSC_OK) return rs;
     Launch L = make_launch(ctx, (hipStream_t)stream);
     HIPCHECK(launch_marder(L, ref, d, iters, ctx->total_cells, ctx->at<int64_t>(ctx->off.run_base), ctx->front),
              "marder");
@@ -1016,6 +1076,7 @@ psc_status psc_balance(psc_ctx *ctx, double cell_cost, void *stream) {
     const int workers = ctx->pm.workers;
     if (workers < 1) return fail(ctx, PSC_ERR_STATE, "psc_balance needs a persistent launch shape");
     hipStream_t s = (hipStream_t)stream;
+    if (psc_status rs = sync_runs(ctx, s); rs != PSC_OK) return rs;
     Launch L = make_launch(ctx, s);
     const int nu = (int)ctx->units.size();
     HIPCHECK(launch_unit_counts(L, ctx->at<Unit>(ctx->off.units), nu, ctx->cs_sel, ctx->at<int32_t>(ctx->off.unit_counts)),
@@ -1138,24 +1199,44 @@ psc_status psc_set_particle_buffers(psc_ctx *ctx, int run, int species, int set,
     if (S.cap > 0 && (!cell || !off || !u)) return fail(ctx, PSC_ERR_INVALID, "null particle buffer");
     if ((id != nullptr) != (S.id[set] != nullptr))
         return fail(ctx, PSC_ERR_INVALID, "ids must be given exactly when the context carries them");
-    if (!ctx->run_pinned) {
-        HIPCHECK(hipHostMalloc((void **)&ctx->run_pinned, sizeof(RunDev) * kRunRing, hipHostMallocDefault),
-                 "run table staging");
-        for (hipEvent_t &e : ctx->run_done) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
-    }
+    (void)stream;
     S.cell[set] = cell;
     S.off[set] = off;
     S.u[set] = u;
     S.id[set] = id;
-    // upload through a pinned slot, ordered on the stream, without a host wait
+    ctx->runs_dirty = true;   // uploaded before the next launch
+    for (auto &kv : ctx->graphs) hipGraphExecDestroy(kv.second);
+    ctx->graphs.clear();
+    return PSC_OK;
+}
+
+psc_status psc_set_sort_outputs(psc_ctx *ctx, int run, int species, int32_t *perm, int32_t *cs, void *stream) {
+    if (!ctx || !ctx->bound || run < 0 || run >= ctx->n_runs || species < 0 || species >= ctx->runs[run].n_species ||
+        (perm == nullptr) != (cs == nullptr))
+        return PSC_ERR_INVALID;
+    RunDev &R = ctx->runs[run];
+    SpeciesDev &S = R.sp[species];
     hipStream_t s = (hipStream_t)stream;
-    const int slot = (int)(ctx->run_calls++ % kRunRing);
-    HIPCHECK(hipEventSynchronize(ctx->run_done[slot]), "run table slot");
-    ctx->run_pinned[slot] = R;
-    HIPCHECK(hipMemcpyAsync(ctx->at<RunDev>(ctx->off.runs) + run, ctx->run_pinned + slot, sizeof(RunDev),
-                            hipMemcpyHostToDevice, s),
-             "upload run");
-    HIPCHECK(hipEventRecord(ctx->run_done[slot], s), "run table event");
+    if (perm) {
+        S.perm[1 - ctx->cs_sel] = perm;
+        S.cs[1 - ctx->cs_sel] = cs;
+    } else {
+        // back to the workspace's arrays, keeping the current offsets and
+        // the pending permutation
+        int32_t *ws_perm = ctx->at<int32_t>(ctx->off_perm[run][species]);
+        int32_t *ws_cs[2] = {ctx->at<int32_t>(ctx->off_cs0[run][species]), ctx->at<int32_t>(ctx->off_cs1[run][species])};
+        const int c = ctx->cs_sel;
+        if (S.cs[c] != ws_cs[c])
+            HIPCHECK(hipMemcpyAsync(ws_cs[c], S.cs[c], sizeof(int32_t) * (R.ncell + 1), hipMemcpyDeviceToDevice, s),
+                     "keep cell offsets");
+        if (ctx->perm_pending && S.perm[c] != ws_perm && S.n > 0)
+            HIPCHECK(hipMemcpyAsync(ws_perm, S.perm[c], sizeof(int32_t) * S.n, hipMemcpyDeviceToDevice, s),
+                     "keep permutation");
+        S.perm[0] = S.perm[1] = ws_perm;
+        S.cs[0] = ws_cs[0];
+        S.cs[1] = ws_cs[1];
+    }
+    ctx->runs_dirty = ctx->segs_dirty = true;   // uploaded before the next launch
     for (auto &kv : ctx->graphs) hipGraphExecDestroy(kv.second);
     ctx->graphs.clear();
     return PSC_OK;
@@ -1167,7 +1248,7 @@ psc_status psc_get_perm(psc_ctx *ctx, int run, int species, int32_t *perm, void 
         return PSC_ERR_INVALID;
     if (!ctx->perm_pending) return fail(ctx, PSC_ERR_STATE, "no permutation: psc_sort has not run since the last push");
     const SpeciesDev &S = ctx->runs[run].sp[species];
-    HIPCHECK(hipMemcpyAsync(perm, S.perm, sizeof(int32_t) * S.n, hipMemcpyDeviceToDevice, (hipStream_t)stream),
+    HIPCHECK(hipMemcpyAsync(perm, S.perm[ctx->cs_sel], sizeof(int32_t) * S.n, hipMemcpyDeviceToDevice, (hipStream_t)stream),
              "copy permutation");
     return PSC_OK;
 }
@@ -1213,6 +1294,7 @@ psc_status psc_adjoint_step(psc_ctx *ctx, const psc_adj_fwd *fwd, const psc_adj_
     std::copy(ctx->adj.begin(), ctx->adj.end(), host);
     HIPCHECK(hipMemcpyAsync(dev, host, sizeof(AdjRun) * ctx->n_runs, hipMemcpyHostToDevice, s),
              "upload adjoint table");
+    if (psc_status rs = sync_runs(ctx, s); rs != PSC_OK) return rs;
     Launch L = make_launch(ctx, s);
     HIPCHECK(launch_adjoint(L, dev, ctx->adj.data(), ctx->at<Unit>(ctx->off.units),
                             (int)ctx->units.size(), ctx->at<int32_t>(ctx->off.item_start), ctx->adj_items, kAdjChunk,

@@ -45,7 +45,9 @@ struct SpeciesDev {
     float *u[2];
     int32_t *id[2];      // both null when ids are not carried
     int32_t *cs[2];      // cell start offsets, ncell + 1
-    int32_t *perm;       // sorted slot -> index in the pushed buffer
+    int32_t *perm[2];    // sorted slot -> index in the pushed buffer: perm[c] goes with
+                         // cs[c] (the sort writes both of 1 - cs_sel, the push reads
+                         // those of cs_sel; by default both name one workspace array)
     uint8_t *mc;         // move code of each pushed particle
     uint16_t *cnt;       // [m * ncell + cell]: particles of `cell` with move m != stay
                          // (counted by the particle kernel, cleared by the sort's scatter)
@@ -379,7 +381,7 @@ hipError_t launch_load_gather(const RunDev &r, int species, int64_t n, const int
                               const int32_t *gid, hipStream_t s);
 hipError_t launch_cell_starts(int64_t n, int64_t ncell, const int32_t *sorted_keys, int32_t *cs, uint32_t *err,
                               hipStream_t s);
-hipError_t launch_get(const RunDev &r, int species, int front, int perm_pending, int32_t *cell,
+hipError_t launch_get(const RunDev &r, int species, int front, const int32_t *perm, int32_t *cell,
                       float *off, float *u, int32_t *id, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_items_scan(int n_units, int32_t *item_start, int32_t *queue, hipStream_t s);

@@ -495,7 +495,7 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
     const int fplane = fx * fy, jplane = jx_ * jy_;
     int fr0, fr1, jr0, jr1;
     {
-        int32_t sf = use_perm ? S.perm[beg] : beg, sl = use_perm ? S.perm[end - 1] : end - 1;
+        int32_t sf = use_perm ? S.perm[cs_sel][beg] : beg, sl = use_perm ? S.perm[cs_sel][end - 1] : end - 1;
         if ((uint32_t)sf >= (uint32_t)S.n) sf = beg;
         if ((uint32_t)sl >= (uint32_t)S.n) sl = end - 1;
         const int32_t *ck = S.cell[front];
@@ -569,7 +569,7 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
     const gptr<float> off_out = to_global(S.off[outb]);
     const gptr<float> u_out = to_global(S.u[outb]);
     const gptr<int32_t> id_out = to_global(S.id[outb]);
-    const gptr<const int32_t> perm = to_global<const int32_t>(S.perm);
+    const gptr<const int32_t> perm = to_global<const int32_t>(S.perm[cs_sel]);
     const gptr<uint8_t> mc = to_global(S.mc);
     uint32_t *cnt32 = reinterpret_cast<uint32_t *>(S.cnt);   // pairs of 16-bit counters
     const int64_t cap = S.cap;

@@ -336,7 +336,7 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(const RunDev *__r
         }
     }
     __builtin_amdgcn_wave_barrier();
-    const gptr_i32 perm = (gptr_i32)S.perm;
+    const gptr_i32 perm = (gptr_i32)S.perm[1 - cs_sel];
     const int32_t n = (int32_t)S.n;
     uint32_t flags = 0;
     bool bad = false;
@@ -586,13 +586,13 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
     return hipGetLastError();
 }
 
-__global__ void k_get(RunDev R, int sp, int front, int perm_pending, int32_t *__restrict__ cell,
+__global__ void k_get(RunDev R, int sp, int front, const int32_t *__restrict__ perm, int32_t *__restrict__ cell,
                       float *__restrict__ off, float *__restrict__ u, int32_t *__restrict__ id) {
     const SpeciesDev &S = R.sp[sp];
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = S.n;
     if (r >= n) return;
-    const int64_t src = perm_pending ? S.perm[r] : r;
+    const int64_t src = perm ? perm[r] : r;
     if (cell) cell[r] = S.cell[front][src];
     if (off)
         for (int d = 0; d < R.dim; ++d) off[d * n + r] = S.off[front][d * S.cap + src];
@@ -601,11 +601,11 @@ __global__ void k_get(RunDev R, int sp, int front, int perm_pending, int32_t *__
     if (id) id[r] = S.id[front] ? S.id[front][src] : -1;
 }
 
-hipError_t launch_get(const RunDev &r, int species, int front, int perm_pending, int32_t *cell, float *off, float *u,
+hipError_t launch_get(const RunDev &r, int species, int front, const int32_t *perm, int32_t *cell, float *off, float *u,
                       int32_t *id, hipStream_t s) {
     const int64_t n = r.sp[species].n;
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_get, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, r, species, front, perm_pending,
+    hipLaunchKernelGGL(k_get, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, r, species, front, perm,
                        cell, off, u, id);
     return hipGetLastError();
 }

@@ -32,6 +32,7 @@ EXPORTS = ["psc_init_patches", "psc_workspace_size", "psc_bind", "psc_bind_stati
            "psc_front", "psc_sort_view", "psc_diagnostics", "psc_get_perm", "psc_marder", "psc_adjoint_step",
            "psc_adjoint_seed", "psc_set_launch", "psc_set_run_chunk", "psc_balance", "psc_partition",
            "psc_set_unit_order", "psc_hilbert_order", "psc_get_cell_offsets", "psc_set_particle_buffers",
+           "psc_set_sort_outputs",
            "psc_check", "psc_status_string", "psc_last_error", "psc_destroy"]
 LAUNCH_GRID, LAUNCH_QUEUE, LAUNCH_PARTITION = 0, 1, 2
 RUN_ADJOINT = 1
@@ -105,6 +106,7 @@ def load_library(path: str = LIB_PATH):
     L.psc_adjoint_seed.argtypes = [vp, C.POINTER(AdjState), vp]
     L.psc_get_cell_offsets.argtypes = [vp, i32, i32, vp, vp]
     L.psc_set_particle_buffers.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp]
+    L.psc_set_sort_outputs.argtypes = [vp, i32, i32, vp, vp, vp]
     L.psc_set_launch.argtypes = [vp, i32, i32, i32, i32, i32, vp]
     L.psc_set_run_chunk.argtypes = [vp, i32, i32, vp]
     L.psc_balance.argtypes = [vp, C.c_double, vp]
@@ -207,10 +209,14 @@ class PscSim:
         self.fields = []
         self.parts = []   # per run: per species: [set0, set1] of dict(cell, off, u, id)
         bufs = (RunBufs * n_runs)()
+        self.field_blocks = []   # per run: one tensor holding E, B, J in turn
         for r, c in enumerate(self.cases):
-            E = torch.from_numpy(np.ascontiguousarray(c.E.reshape(-1))).to(self.device)
-            B = torch.from_numpy(np.ascontiguousarray(c.B.reshape(-1))).to(self.device)
-            J = torch.zeros(3 * c.ncell, dtype=f32, device=self.device)
+            nc3 = 3 * c.ncell
+            EBJ = torch.zeros(3 * nc3, dtype=f32, device=self.device)
+            E, B, J = EBJ[:nc3], EBJ[nc3:2 * nc3], EBJ[2 * nc3:]
+            E.copy_(torch.from_numpy(np.ascontiguousarray(c.E.reshape(-1), dtype=np.float32)))
+            B.copy_(torch.from_numpy(np.ascontiguousarray(c.B.reshape(-1), dtype=np.float32)))
+            self.field_blocks.append(EBJ)
             self.fields.append((E, B, J))
             bufs[r].E, bufs[r].B, bufs[r].J = E.data_ptr(), B.data_ptr(), J.data_ptr()
             per_sp = []
@@ -475,6 +481,13 @@ class PscSim:
         self._call(self.L.psc_set_particle_buffers(self.ctx, r, s, int(bset), bufs["cell"].data_ptr(),
                                                    bufs["off"].data_ptr(), bufs["u"].data_ptr(), idp,
                                                    self._stream()))
+
+    def set_sort_outputs(self, r: int, s: int, perm=None, cs=None):
+        """Direct the next sort's permutation (int32, capacity) and new cell
+        offsets (int32, ncell + 1) of (run, species) to device tensors; both
+        None returns to the workspace's arrays."""
+        self._call(self.L.psc_set_sort_outputs(self.ctx, r, s, perm.data_ptr() if perm is not None else None,
+                                               cs.data_ptr() if cs is not None else None, self._stream()))
 
     def adjoint_seed(self, lam):
         """Seed lam (per run dict(lE, lB, loff=[...], lu=[...]) of device

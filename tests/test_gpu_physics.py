@@ -221,3 +221,39 @@ def test_repeat_runs_agree(name, tile_fold):
     print(f"{name}, 10 steps, two runs: {ndiff} float values differ (integer state identical)", flush=True)
     if not tile_fold:
         assert ndiff == 0
+
+
+def test_sort_outputs_redirected_equal_workspace():
+    """psc_set_sort_outputs: a run whose sorts write their permutation and
+    cell offsets into caller arrays (switched every step, as the adjoint
+    does) stays bit for bit equal to the same run on the workspace's arrays;
+    the arrays hold that run's permutation and offsets; returning to the
+    workspace keeps the state (the next steps stay equal too)."""
+    import torch
+    c = cases.harris2d(ny=64, nz=32, ppc=20, order=2, patch=16, seed=23)
+    a, b = _sim(c, chunk=1024), _sim(c, chunk=1024)
+    bufs = [[dict(perm=torch.empty(sp.n, dtype=torch.int32, device="cuda"),
+                  cs=torch.empty(c.ncell + 1, dtype=torch.int32, device="cuda")) for _ in range(2)]
+            for sp in c.species]
+    for k in range(6):
+        for s in range(len(c.species)):
+            b.set_sort_outputs(0, s, bufs[s][k % 2]["perm"], bufs[s][k % 2]["cs"])
+        a.step(1)
+        b.step(1)
+        for s in range(len(c.species)):
+            assert torch.equal(a.get_perm(0, s), bufs[s][k % 2]["perm"])
+            assert torch.equal(a.cell_offsets(0, s), bufs[s][k % 2]["cs"])
+            assert torch.equal(b.get_perm(0, s), bufs[s][k % 2]["perm"])
+    for s in range(len(c.species)):
+        b.set_sort_outputs(0, s, None, None)
+    for _ in range(3):
+        a.step(1)
+        b.step(1, use_graph=True)
+    assert a.check() == 0 and b.check() == 0
+    for s in range(len(c.species)):
+        pa, pb = a.particles(0, s), b.particles(0, s)
+        for key in ("key", "id", "off", "u"):
+            assert np.array_equal(pa[key], pb[key]), key
+        assert np.array_equal(a.sort_view(0, s)[1], b.sort_view(0, s)[1])
+    for fa, fb in zip(a.field_arrays(0), b.field_arrays(0)):
+        assert np.array_equal(fa, fb)
