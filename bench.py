@@ -75,7 +75,7 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(case, thin: int):
+def cpu_baseline(case, thin: int, batch_error: bool = False, tune_cache=None):
     """The oracle as it stands on every `thin`-th particle of the workload
     (full grid) for one complete step, timed on this host with one thread
     and with every thread the process may use.  Both legs use a copy of the
@@ -116,8 +116,11 @@ def cpu_baseline(case, thin: int):
             del sim
     O.use_library(None)
     err = oracle_error(sample, first)
+    extra = {}
+    if batch_error:
+        extra["error_of_batched_path"] = batched_oracle_error(tune_cache=tune_cache)
     top = max(legs)
-    return dict(value=legs[top]["value"], unit="particle pushes/s", cores=top, kind="oracle",
+    return dict(**extra, value=legs[top]["value"], unit="particle pushes/s", cores=top, kind="oracle",
                 sample=f"1 full step of every {thin}th particle ({sample.n_particles} particles) "
                        f"of the {case.name} workload on the full "
                        f"{'x'.join(str(g) for g in case.gdims if g > 1)} grid, float64",
@@ -126,20 +129,24 @@ def cpu_baseline(case, thin: int):
                 error_of_gpu_path=err)
 
 
-def oracle_error(sample, osim):
+def oracle_error(sample, osim, g=None, run=0):
     """The float32 GPU path against the float64 oracle after the same full
     step on the same sample: largest position difference (cells), largest
     momentum difference relative to the species' largest |u|, and largest
-    field differences relative to the largest oracle value."""
+    field differences relative to the largest oracle value.  g: a context
+    already stepped that holds the sample as run `run` (a batch), else one
+    is made for the sample alone."""
     import numpy as np
     from paper_1310_7866_amd.psc import PscSim
-    g = PscSim(sample, with_ids=True)
-    g.step(1)
-    g.check()
+    own = g is None
+    if own:
+        g = PscSim(sample, with_ids=True)
+        g.step(1)
+        g.check()
     nx, ny, nz = sample.gdims
     dpos, du = 0.0, 0.0
     for s in range(len(sample.species)):
-        p = g.particles(0, s)
+        p = g.particles(run, s)
         ids = p["id"].astype(np.int64)
         c = p["cell"].astype(np.int64)
         idx = (c % nx, (c // nx) % ny, c // (nx * ny))
@@ -155,11 +162,44 @@ def oracle_error(sample, osim):
         ug = np.empty((3, ids.size))
         ug[:, ids] = p["u"].astype(np.float64)
         du = max(du, float(np.abs(ug - uo).max(initial=0.0) / max(np.abs(uo).max(initial=0.0), 1e-30)))
-    E, B, J = g.field_arrays(0)
+    E, B, J = g.field_arrays(run)
     rel = lambda a, b: float(np.abs(a.astype(np.float64).ravel() - b).max() / max(np.abs(b).max(), 1e-30))
     out = dict(steps=1, max_position_cells=dpos, max_momentum_rel=du,
                E_rel=rel(E, osim.E), B_rel=rel(B, osim.B), J_rel=rel(J, osim.J))
+    if own:
+        g.close()
+    return out
+
+
+def batched_oracle_error(n_runs: int = 64, thin: int = 4, tune_cache=None):
+    """The batched path against the oracle: three runs of the batch
+    workload (its first, middle and last, every `thin`-th particle) in one
+    context with the batch's launch shape, one full step replayed from a HIP
+    graph, each run against the oracle stepping it alone; the largest errors
+    over the runs (as in oracle_error)."""
+    from oracle import oracle as O
+    from paper_1310_7866_amd import autotune as AT
+    from paper_1310_7866_amd import cases
+    from paper_1310_7866_amd.psc import PscSim
+    cs = cases.twostream_batch(n_runs=n_runs, seed=4064)
+    # the batch's launch shape from the tuning cache (the library's default without an entry)
+    entry = AT._load(tune_cache or AT.DEFAULT_CACHE).get(f"{AT._arch()}/{AT.occupancy_class(cs)}")
+    sub = [cases.thin(cs[i], thin) for i in (0, n_runs // 2, n_runs - 1)]
+    osims = []
+    for c in sub:
+        o = O.OracleSim(c)
+        o.step(1)
+        osims.append(o)
+    g = PscSim(sub, with_ids=True)
+    if entry:
+        g.set_launch(**{k: entry[k] for k in ("mode", "chunk", "threads", "run")})
+    g.step(1, use_graph=True)
+    g.check()
+    errs = [oracle_error(c, o, g, r) for r, (c, o) in enumerate(zip(sub, osims))]
     g.close()
+    out = {k: max(e[k] for e in errs) for k in errs[0] if k != "steps"}
+    out.update(steps=1, runs=f"runs 0, {n_runs // 2}, {n_runs - 1} of the batch, every {thin}th particle, "
+                              f"{sum(c.n_particles for c in sub)} particles, in one context with the batch's launch shape")
     return out
 
 
@@ -640,7 +680,8 @@ def main():
         print("[bench] batch leg", file=sys.stderr, flush=True)
         out["batched"] = batch_leg(tune_cache=args.tune_cache, retune=args.retune)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case, args.cpu_thin or CPU_THIN.get(case.name, 1))
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_thin or CPU_THIN.get(case.name, 1),
+                                           batch_error=not args.no_extras, tune_cache=args.tune_cache)
     print(json.dumps(out))
 
 

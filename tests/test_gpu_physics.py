@@ -226,20 +226,30 @@ def test_repeat_runs_agree(name, tile_fold):
 def test_sort_outputs_redirected_equal_workspace():
     """psc_set_sort_outputs: a run whose sorts write their permutation and
     cell offsets into caller arrays (switched every step, as the adjoint
-    does) stays bit for bit equal to the same run on the workspace's arrays;
-    the arrays hold that run's permutation and offsets; returning to the
-    workspace keeps the state (the next steps stay equal too)."""
+    does, with the counting sort, the radix sort and graph replay) stays bit
+    for bit equal to the same run on the workspace's arrays; the arrays hold
+    that run's permutation and offsets; returning to the workspace keeps the
+    state (the next steps stay equal too)."""
     import torch
     c = cases.harris2d(ny=64, nz=32, ppc=20, order=2, patch=16, seed=23)
     a, b = _sim(c, chunk=1024), _sim(c, chunk=1024)
     bufs = [[dict(perm=torch.empty(sp.n, dtype=torch.int32, device="cuda"),
                   cs=torch.empty(c.ncell + 1, dtype=torch.int32, device="cuda")) for _ in range(2)]
             for sp in c.species]
+    from paper_1310_7866_amd.psc import B_HALF, E_FULL
     for k in range(6):
         for s in range(len(c.species)):
             b.set_sort_outputs(0, s, bufs[s][k % 2]["perm"], bufs[s][k % 2]["cs"])
         a.step(1)
-        b.step(1)
+        if k % 3 == 2:   # the general radix sort writes the same outputs
+            b.push_fields(B_HALF)
+            b.push_particles()
+            b.push_fields(B_HALF)
+            b.deposit_current()
+            b.push_fields(E_FULL)
+            b.sort_radix()
+        else:
+            b.step(1, use_graph=k == 4)
         for s in range(len(c.species)):
             assert torch.equal(a.get_perm(0, s), bufs[s][k % 2]["perm"])
             assert torch.equal(a.cell_offsets(0, s), bufs[s][k % 2]["cs"])
