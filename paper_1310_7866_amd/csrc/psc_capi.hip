@@ -90,12 +90,11 @@ struct psc_ctx {
     size_t adj_lds = 0;
     int64_t adj_items = 0;                  // work items of the particle adjoint (kAdjChunk particles)
     std::vector<AdjRun> adj;                 // host mirror of the adjoint table
-    RunDev *run_pinned = nullptr;            // kRunRing staged copies of the run table (pinned)
+    RunDev *run_pinned = nullptr;            // kRunRing staged copies of the run and segment tables (pinned)
     hipEvent_t run_done[kRunRing] = {};
     uint64_t run_calls = 0;
     bool runs_dirty = false;                 // host run table changed since its last upload
     bool segs_dirty = false;                 // ... and with it the scan segments' output offsets
-    ScanSeg *segs_pinned = nullptr;          // kRunRing staged copies of both scan-segment tables
     AdjRun *adj_pinned = nullptr;            // kAdjRing * n_runs tables in pinned host memory
     hipEvent_t adj_done[kAdjRing] = {};      // completion of the call that last used each slot
     uint64_t adj_calls = 0;
@@ -124,7 +123,6 @@ struct psc_ctx {
         for (hipEvent_t &e : run_done)
             if (e) hipEventDestroy(e);
         if (run_pinned) hipHostFree(run_pinned);
-        if (segs_pinned) hipHostFree(segs_pinned);
     }
 };
 
@@ -165,41 +163,32 @@ Launch make_launch(psc_ctx *ctx, hipStream_t s) {
 // Called by every entry point that launches kernels reading the table.
 static psc_status sync_runs(psc_ctx *ctx, hipStream_t s) {
     if (!ctx->runs_dirty) return PSC_OK;
+    // one staging block per slot: the run table, then both segment tables
+    const size_t run_bytes = sizeof(RunDev) * ctx->n_runs, seg_bytes = 2 * sizeof(ScanSeg) * ctx->n_segs;
     if (!ctx->run_pinned) {
-        HIPCHECK(hipHostMalloc((void **)&ctx->run_pinned, sizeof(RunDev) * kRunRing * ctx->n_runs,
-                               hipHostMallocDefault),
+        HIPCHECK(hipHostMalloc((void **)&ctx->run_pinned, (run_bytes + seg_bytes) * kRunRing, hipHostMallocDefault),
                  "run table staging");
         for (hipEvent_t &e : ctx->run_done) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
     }
     const int slot = (int)(ctx->run_calls++ % kRunRing);
     HIPCHECK(hipEventSynchronize(ctx->run_done[slot]), "run table slot");
-    RunDev *staged = ctx->run_pinned + (size_t)slot * ctx->n_runs;
-    std::memcpy(staged, ctx->runs.data(), sizeof(RunDev) * ctx->n_runs);
-    HIPCHECK(hipMemcpyAsync(ctx->at<RunDev>(ctx->off.runs), staged, sizeof(RunDev) * ctx->n_runs,
-                            hipMemcpyHostToDevice, s),
-             "upload runs");
+    char *staged = reinterpret_cast<char *>(ctx->run_pinned) + (run_bytes + seg_bytes) * slot;
+    std::memcpy(staged, ctx->runs.data(), run_bytes);
+    size_t bytes = run_bytes;
     if (ctx->segs_dirty) {
         // the scan writes the new cell offsets through the segment tables
         // (table c for cs_sel == c: into cs[1 - c])
-        if (!ctx->segs_pinned)
-            HIPCHECK(hipHostMalloc((void **)&ctx->segs_pinned, sizeof(ScanSeg) * kRunRing * 2 * ctx->n_segs,
-                                   hipHostMallocDefault),
-                     "segment table staging");
-        ScanSeg *sg = ctx->segs_pinned + (size_t)slot * 2 * ctx->n_segs;
+        ScanSeg *sg = reinterpret_cast<ScanSeg *>(staged + run_bytes);
         for (int c = 0; c < 2; ++c)
             for (int g = 0; g < ctx->n_segs; ++g) {
                 ScanSeg &t = ctx->segs_host[c][g];
                 t.out = ctx->runs[ctx->seg_run[g]].sp[ctx->seg_sp[g]].cs[1 - c];
                 sg[(size_t)c * ctx->n_segs + g] = t;
             }
-        HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.segs0), sg, sizeof(ScanSeg) * ctx->n_segs,
-                                hipMemcpyHostToDevice, s),
-                 "upload segs0");
-        HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.segs1), sg + ctx->n_segs, sizeof(ScanSeg) * ctx->n_segs,
-                                hipMemcpyHostToDevice, s),
-                 "upload segs1");
+        bytes += seg_bytes;
         ctx->segs_dirty = false;
     }
+    HIPCHECK(hipMemcpyAsync(ctx->at<void>(ctx->off.runs), staged, bytes, hipMemcpyHostToDevice, s), "upload runs");
     HIPCHECK(hipEventRecord(ctx->run_done[slot], s), "run table event");
     ctx->runs_dirty = false;
     return PSC_OK;
@@ -439,7 +428,11 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
         }
 
     const int M = n_moves(ctx->dim);
-    ctx->off.runs = take(sizeof(RunDev) * n_runs);
+    // the run table and the two scan-segment tables in one block (one upload)
+    static_assert(sizeof(RunDev) % alignof(ScanSeg) == 0, "segment tables follow the run table");
+    ctx->off.runs = take(sizeof(RunDev) * n_runs + 2 * sizeof(ScanSeg) * ctx->n_segs);
+    ctx->off.segs0 = ctx->off.runs + sizeof(RunDev) * n_runs;
+    ctx->off.segs1 = ctx->off.segs0 + sizeof(ScanSeg) * ctx->n_segs;
     ctx->off.units = take(sizeof(Unit) * ctx->units.size());
     ctx->off.item_start = take(sizeof(int32_t) * (ctx->units.size() + 1));
     ctx->off.run_base = take(sizeof(int64_t) * (n_runs + 1));
@@ -447,8 +440,6 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
     ctx->off.seg_base = take(sizeof(int64_t) * (ctx->n_segs + 1));
     ctx->off.seg_run = take(sizeof(int32_t) * ctx->n_segs);
     ctx->off.seg_sp = take(sizeof(int32_t) * ctx->n_segs);
-    ctx->off.segs0 = take(sizeof(ScanSeg) * ctx->n_segs);
-    ctx->off.segs1 = take(sizeof(ScanSeg) * ctx->n_segs);
     ctx->segs_host[0].resize(ctx->n_segs);
     ctx->segs_host[1].resize(ctx->n_segs);
     // block sums, block -> segment table, partial sums (kScanBlock / 256 per block)
