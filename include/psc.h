@@ -453,8 +453,10 @@ typedef struct {
  * Esirkepov deposit, move, Boris rotation and interpolation, first B half
  * step).  The paper defines no adjoint; this is the exact derivative of the
  * forward kernels' arithmetic.  Needs PSC_RUN_ADJOINT in every run's flags;
- * 2-d runs only (PSC_ERR_UNSUPPORTED for 3-d).  fwd and adj hold n_runs
- * entries.  Asynchronous on `stream` (the pointer tables are copied before
+ * 2-d and 3-d runs (in 3-d the particle part adds its transposed
+ * interpolation into lE, lB with float atomics, so its summation order varies
+ * between calls; the 2-d fold is in a fixed order); PSC_ERR_UNSUPPORTED with
+ * PSC_RUN_VB.  fwd and adj hold n_runs entries.  Asynchronous on `stream` (the pointer tables are copied before
  * the call returns): the buffers must stay valid until the stream reaches
  * the call's end.  Successive calls on different streams must be ordered by
  * the caller, since they share the adjoint scratch. */

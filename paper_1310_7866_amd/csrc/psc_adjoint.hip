@@ -1,4 +1,4 @@
-// psc_adjoint.hip -- hand-written reverse of one time step (2-d runs).
+// psc_adjoint.hip -- hand-written reverse of one time step (2-d and 3-d runs).
 //
 // The paper has no adjoint; this is the exact transpose of the discrete step
 // of fig. psc_new as implemented by the forward kernels:
@@ -648,6 +648,346 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles(const RunDev *__res
     }
 }
 
+// interpolation of one component in 3-d with its offset derivatives (g: d/dx, d/dy, d/dz)
+template <int ORDER>
+__device__ __forceinline__ float gather3_d(const float *F, int px, int pxy, int ix, int iy, int iz, const float *wx,
+                                           const float *dwx, const float *wy, const float *dwy, const float *wz,
+                                           const float *dwz, float g[3]) {
+    const float *p = F + iz * pxy + iy * px + ix;
+    float s = 0.0f, sx = 0.0f, sy = 0.0f, sz = 0.0f;
+#pragma unroll
+    for (int c = 0; c <= ORDER; ++c) {
+        float t = 0.0f, tx = 0.0f, ty = 0.0f;
+#pragma unroll
+        for (int b = 0; b <= ORDER; ++b) {
+            float r = 0.0f, rx = 0.0f;
+#pragma unroll
+            for (int a = 0; a <= ORDER; ++a) {
+                const float f = p[c * pxy + b * px + a];
+                r = fmaf(wx[a], f, r);
+                rx = fmaf(dwx[a], f, rx);
+            }
+            t = fmaf(wy[b], r, t);
+            tx = fmaf(wy[b], rx, tx);
+            ty = fmaf(dwy[b], r, ty);
+        }
+        s = fmaf(wz[c], t, s);
+        sx = fmaf(wz[c], tx, sx);
+        sy = fmaf(wz[c], ty, sy);
+        sz = fmaf(dwz[c], t, sz);
+    }
+    g[0] = sx;
+    g[1] = sy;
+    g[2] = sz;
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// the particle adjoint kernel (3-d)
+// ---------------------------------------------------------------------------
+// The same reverse as the 2-d kernel with the third dimension: the forward of
+// every particle is recomputed (gather with weight derivatives, Boris, move),
+// then reversed through the 3-d Esirkepov deposit (J_x(a; b, c) = jfx C_x(a)
+// (A_y(b) A_z(c) + DS_y(b) DS_z(c) / 12) and its two rotations, A = S0 + DS/2,
+// C the running sum of DS = S1 - S0), the move, the Boris rotation and the
+// interpolation.  The transposed interpolation goes by per-lane double LDS
+// atomics into a tile per work item, added at the end straight into lE and
+// lB with the tile's halo wrapped onto the neighbouring cells (float atomics:
+// the summation order of a cell's contributions varies between runs).
+template <int ORDER>
+__global__ void __launch_bounds__(kAdjBlock) k_adj_particles3(const RunDev *__restrict__ runs,
+                                                              const AdjRun *__restrict__ adj,
+                                                              const Unit *__restrict__ units,
+                                                              const int32_t *__restrict__ item_start, int n_units,
+                                                              int chunk) {
+    extern __shared__ __align__(16) float lds[];   // 16-byte aligned: holds doubles
+    constexpr int L = ORDER + 2;
+    constexpr int FLO = 1, FHI = ORDER;
+    constexpr int JLO = ORDER, JHI = ORDER + 1;
+    constexpr int NT = kAdjBlock;
+    // half-grid flags (x, y, z) of Ex, Ey, Ez, Bx, By, Bz
+    constexpr bool HS[6][3] = {{true, false, false}, {false, true, false}, {false, false, true},
+                               {false, true, true},  {true, false, true},  {true, true, false}};
+
+    const int nb = gridDim.x;
+    const int item = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+    const int total = item_start[n_units];
+    if (item >= total) return;
+    int lo = 0, hi = n_units;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (item_start[mid] <= item) lo = mid; else hi = mid;
+    }
+    const Unit U = units[lo];
+    const RunDev &R = runs[U.run];
+    const AdjRun &A = adj[U.run];
+    const SpeciesDev &S = R.sp[U.species];
+    const AdjSpecies &AS = A.sp[U.species];
+
+    int pc[3];
+    patch_coords(R, U.patch, pc);
+    const int hx = patch_ext(R, 0, pc[0]), hy = patch_ext(R, 1, pc[1]), hz = patch_ext(R, 2, pc[2]);
+    const int ox = pc[0] * R.P[0], oy = pc[1] * R.P[1], oz = pc[2] * R.P[2];
+    const int64_t kb = patch_key_base(R, pc[0], pc[1], pc[2]);
+    const int pcells = hx * hy * hz;
+    // offsets outside [0, n] (a corrupt input) must not send the item outside the buffers
+    const int32_t n32 = (int32_t)AS.n;
+    const int32_t pend = min(max(AS.cs[kb + pcells], 0), n32), pbeg = min(max(AS.cs[kb], 0), pend);
+    const int32_t beg = pbeg + (item - item_start[lo]) * chunk;
+    const int32_t end = min(beg + chunk, pend);
+
+    const int fx = R.P[0] + FLO + FHI, fy = R.P[1] + FLO + FHI, fz = R.P[2] + FLO + FHI;
+    const int fxy = fx * fy, fcells = fxy * fz;
+    const int jx = R.P[0] + JLO + JHI, jy = R.P[1] + JLO + JHI, jz = R.P[2] + JLO + JHI;
+    const int jxy = jx * jy, jcells = jxy * jz;
+    const AdjLds LL = adj_lds_layout(fcells, jcells);
+    float *ftile = lds;               // E, B1
+    float *ljt = lds + LL.lj;         // LJ
+    double *gt = reinterpret_cast<double *>(lds + LL.gt);
+    const int64_t nc = R.ncell;
+    auto tile_cell = [&](int q, int px, int pxy, int lo_, int64_t &g) {
+        const int tz = q / pxy, r = q - tz * pxy, ty = r / px, tx = r - ty * px;
+        g = wrap(ox + tx - lo_, R.n[0]) +
+            (int64_t)R.n[0] * (wrap(oy + ty - lo_, R.n[1]) + (int64_t)R.n[1] * wrap(oz + tz - lo_, R.n[2]));
+    };
+    for (int q = threadIdx.x; q < fcells; q += NT) {
+        int64_t g;
+        tile_cell(q, fx, fxy, FLO, g);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            ftile[c * fcells + q] = A.E[c * nc + g];
+            ftile[(3 + c) * fcells + q] = A.B1[c * nc + g];
+            gt[c * fcells + q] = 0.0;
+            gt[(3 + c) * fcells + q] = 0.0;
+        }
+    }
+    for (int q = threadIdx.x; q < jcells; q += NT) {
+        int64_t g;
+        tile_cell(q, jx, jxy, JLO, g);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ljt[c * jcells + q] = A.LJ[c * nc + g];
+    }
+    __syncthreads();
+
+    const int64_t n = AS.n, st = AS.stride;
+    const float h = S.qdt_2m, qw = S.qw, dt = R.dt;
+    const float cf[3] = {dt * R.inv_dx[0], dt * R.inv_dx[1], dt * R.inv_dx[2]};
+    const float jf[3] = {-qw * R.dx[0] / dt, -qw * R.dx[1] / dt, -qw * R.dx[2] / dt};
+    auto slot_of = [&](int32_t i) -> int64_t {
+        if (!AS.rperm) return i;
+        const int32_t q = AS.rperm[i];
+        return (uint32_t)q < (uint32_t)AS.stride ? q : 0;   // a corrupt permutation stays in bounds
+    };
+
+    for (int32_t base = beg; base < end; base += NT) {
+        const bool valid = base + (int32_t)threadIdx.x < end;
+        if (!valid) continue;
+        const int32_t i = base + (int32_t)threadIdx.x;
+        const int64_t q = slot_of(i);
+        int local = AS.key[q] - (int32_t)kb;
+        if (local < 0 || local >= pcells) local = 0;
+        const int lz = local / (hx * hy), rr = local - lz * hx * hy, ly = rr / hx, lx = rr - ly * hx;
+        const float o0[3] = {AS.off[q], AS.off[st + q], AS.off[2 * st + q]};
+        const float3 u0 = make_float3(AS.u[q], AS.u[st + q], AS.u[2 * st + q]);
+
+        // ---- forward recompute: interpolation (with offset derivatives) ----
+        float wn[3][ORDER + 1], wh[3][ORDER + 1], dn[3][ORDER + 1], dh[3][ORDER + 1];
+        int bn[3], bh[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            bn[d] = node_weights<ORDER>(o0[d], wn[d]);
+            bh[d] = half_weights<ORDER>(o0[d], wh[d]);
+            node_dweights<ORDER>(o0[d], dn[d]);
+            half_dweights<ORDER>(o0[d], dh[d]);
+        }
+        float F[6], G[6][3];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            const int ix = lx + FLO + (HS[c][0] ? bh[0] : bn[0]);
+            const int iy = ly + FLO + (HS[c][1] ? bh[1] : bn[1]);
+            const int iz = lz + FLO + (HS[c][2] ? bh[2] : bn[2]);
+            F[c] = gather3_d<ORDER>(ftile + c * fcells, fx, fxy, ix, iy, iz, HS[c][0] ? wh[0] : wn[0],
+                                    HS[c][0] ? dh[0] : dn[0], HS[c][1] ? wh[1] : wn[1], HS[c][1] ? dh[1] : dn[1],
+                                    HS[c][2] ? wh[2] : wn[2], HS[c][2] ? dh[2] : dn[2], G[c]);
+        }
+        const float3 Ep = make_float3(F[0], F[1], F[2]);
+        const float3 Bp = make_float3(F[3], F[4], F[5]);
+
+        // ---- Boris with intermediates ---------------------------------------
+        const float3 um = add3(u0, scale3(Ep, h));
+        const float igm = rsqrt_ge1(1.0f + dot3(um, um));
+        const float3 t = scale3(Bp, h * igm);
+        const float t2 = dot3(t, t);
+        const float f = boris_factor(t2);
+        const float3 sv = scale3(t, f);
+        const float3 up = add3(um, cross3(um, t));
+        const float3 uq = add3(um, cross3(up, sv));
+        const float3 un = add3(uq, scale3(Ep, h));
+        const float ig = rsqrt_ge1(1.0f + dot3(un, un));
+        const float unv[3] = {un.x, un.y, un.z};
+
+        // ---- move -------------------------------------------------------------
+        int sh[3];
+        float o1[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            float disp = cf[d] * unv[d] * ig;
+            if (!(fabsf(disp) < 0.99f)) disp = 0.0f;
+            const float x1 = o0[d] + disp;
+            int sd = (int)floorf(x1);
+            float od = x1 - (float)sd;
+            if (od >= 1.0f) { od -= 1.0f; sd += 1; }
+            sh[d] = sd;
+            o1[d] = od;
+        }
+
+        // ---- reverse ----------------------------------------------------------
+        float lx1[3] = {AS.soff[i], AS.soff[n + i], AS.soff[2 * n + i]};   // adjoint of the moved offsets
+        float lun[3] = {AS.su[i], AS.su[n + i], AS.su[2 * n + i]};
+        float lo0[3] = {0.0f, 0.0f, 0.0f};
+        float lig = 0.0f;
+
+        // deposit: J values on the stencil, adjoint read from the LJ tile
+        {
+            float S0[3][L], S1[3][L], D0[3][L], D1[3][L];
+            int bs[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) bs[d] = stencil_d<ORDER>(o0[d], sh[d], o1[d], S0[d], S1[d], D0[d], D1[d]);
+            float DS[3][L], Aw[3][L], C[3][L], gC[3][L], gA[3][L], gD[3][L];
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int r = 0; r < L; ++r) {
+                    DS[d][r] = S1[d][r] - S0[d][r];
+                    Aw[d][r] = fmaf(0.5f, DS[d][r], S0[d][r]);
+                    C[d][r] = r == 0 ? DS[d][0] : C[d][r - 1] + DS[d][r];
+                    gC[d][r] = gA[d][r] = gD[d][r] = 0.0f;
+                }
+            const float *lj = ljt + ((lz + bs[2] + JLO) * jy + (ly + bs[1] + JLO)) * jx + (lx + bs[0] + JLO);
+            constexpr float k12 = 1.0f / 12.0f;
+#pragma unroll
+            for (int c = 0; c < L; ++c)
+#pragma unroll
+                for (int b = 0; b < L; ++b)
+#pragma unroll
+                    for (int a = 0; a < L; ++a) {
+                        const int idx = (c * jy + b) * jx + a;
+                        if (a < L - 1) {   // J_x(a; b, c) = jfx C_x(a) (A_y(b) A_z(c) + DS_y(b) DS_z(c) / 12)
+                            const float lam = jf[0] * lj[idx];
+                            gC[0][a] += lam * fmaf(DS[1][b] * DS[2][c], k12, Aw[1][b] * Aw[2][c]);
+                            const float tt = lam * C[0][a];
+                            gA[1][b] += tt * Aw[2][c];
+                            gA[2][c] += tt * Aw[1][b];
+                            gD[1][b] += tt * DS[2][c] * k12;
+                            gD[2][c] += tt * DS[1][b] * k12;
+                        }
+                        if (b < L - 1) {   // J_y(a; b, c) = jfy C_y(b) (A_x(a) A_z(c) + DS_x(a) DS_z(c) / 12)
+                            const float lam = jf[1] * lj[jcells + idx];
+                            gC[1][b] += lam * fmaf(DS[0][a] * DS[2][c], k12, Aw[0][a] * Aw[2][c]);
+                            const float tt = lam * C[1][b];
+                            gA[0][a] += tt * Aw[2][c];
+                            gA[2][c] += tt * Aw[0][a];
+                            gD[0][a] += tt * DS[2][c] * k12;
+                            gD[2][c] += tt * DS[0][a] * k12;
+                        }
+                        if (c < L - 1) {   // J_z(a, b; c) = jfz C_z(c) (A_x(a) A_y(b) + DS_x(a) DS_y(b) / 12)
+                            const float lam = jf[2] * lj[2 * jcells + idx];
+                            gC[2][c] += lam * fmaf(DS[0][a] * DS[1][b], k12, Aw[0][a] * Aw[1][b]);
+                            const float tt = lam * C[2][c];
+                            gA[0][a] += tt * Aw[1][b];
+                            gA[1][b] += tt * Aw[0][a];
+                            gD[0][a] += tt * DS[1][b] * k12;
+                            gD[1][b] += tt * DS[0][a] * k12;
+                        }
+                    }
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                // C(r) = sum_{r' <= r} DS(r'), used for r < L - 1
+                float acc = 0.0f;
+#pragma unroll
+                for (int r = L - 1; r >= 0; --r) {
+                    acc += r < L - 1 ? gC[d][r] : 0.0f;
+                    gD[d][r] += acc;
+                }
+                // A = S0 + DS/2, DS = S1 - S0
+                float l1 = 0.0f;
+#pragma unroll
+                for (int r = 0; r < L; ++r) {
+                    const float ds = gD[d][r] + 0.5f * gA[d][r];
+                    lo0[d] += (gA[d][r] - ds) * D0[d][r];
+                    l1 += ds * D1[d][r];
+                }
+                lx1[d] += l1;
+            }
+        }
+        // move: x1 = o0 + cf un ig
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            lo0[d] += lx1[d];
+            lun[d] += cf[d] * ig * lx1[d];
+            lig += cf[d] * unv[d] * lx1[d];
+        }
+        float3 lu3 = add3(make_float3(lun[0], lun[1], lun[2]), scale3(un, -ig * ig * ig * lig));
+
+        // Boris reverse
+        float3 lE = scale3(lu3, h);
+        const float3 luq = lu3;
+        float3 lum = luq;
+        const float3 lup = cross3(sv, luq);
+        const float3 ls = cross3(luq, up);
+        lum = add3(lum, add3(lup, cross3(t, lup)));
+        float3 lt = cross3(lup, um);
+        // s = f t with f = 2 / (1 + |t|^2), df/dt = -f^2 t
+        lt = add3(lt, add3(scale3(ls, f), scale3(t, -f * f * dot3(ls, t))));
+        const float3 lB = scale3(lt, h * igm);
+        const float ligm = h * dot3(Bp, lt);
+        lum = add3(lum, scale3(um, -igm * igm * igm * ligm));
+        lE = add3(lE, scale3(lum, h));
+        const float3 lu0 = lum;
+
+        // interpolation reverse: offsets, then the transposed interpolation
+        const float lF[6] = {lE.x, lE.y, lE.z, lB.x, lB.y, lB.z};
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) lo0[d] += lF[c] * G[c][d];
+        AS.loff[i] = lo0[0];
+        AS.loff[n + i] = lo0[1];
+        AS.loff[2 * n + i] = lo0[2];
+        AS.lu[i] = lu0.x;
+        AS.lu[n + i] = lu0.y;
+        AS.lu[2 * n + i] = lu0.z;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            const float *wxx = HS[c][0] ? wh[0] : wn[0], *wyy = HS[c][1] ? wh[1] : wn[1], *wzz = HS[c][2] ? wh[2] : wn[2];
+            const int ix = lx + FLO + (HS[c][0] ? bh[0] : bn[0]);
+            const int iy = ly + FLO + (HS[c][1] ? bh[1] : bn[1]);
+            const int iz = lz + FLO + (HS[c][2] ? bh[2] : bn[2]);
+            double *g0 = gt + c * fcells + (iz * fy + iy) * fx + ix;
+#pragma unroll
+            for (int cz = 0; cz <= ORDER; ++cz)
+#pragma unroll
+                for (int by = 0; by <= ORDER; ++by) {
+                    const float lyz = lF[c] * wyy[by] * wzz[cz];
+#pragma unroll
+                    for (int ax = 0; ax <= ORDER; ++ax) lds_add(g0 + (cz * fy + by) * fx + ax, lyz * wxx[ax]);
+                }
+        }
+    }
+    __syncthreads();
+    // the tile into lE, lB: entry (tx, ty, tz) is cell (ox, oy, oz) + (tx, ty, tz) - FLO, periodic
+    for (int q = threadIdx.x; q < fcells; q += NT) {
+        int64_t g;
+        tile_cell(q, fx, fxy, FLO, g);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double ve = gt[c * fcells + q], vb = gt[(3 + c) * fcells + q];
+            if (ve != 0.0) atomicAdd(&A.lE[c * nc + g], (float)ve);
+            if (vb != 0.0) atomicAdd(&A.lB[c * nc + g], (float)vb);
+        }
+    }
+}
+
 // fold the transposed-interpolation tiles (field-tile geometry) into lE, lB
 // Runs whose patches are all at least as wide as the current halo (so also
 // as the field tile's): per dimension the patch below (when l < hi), the
@@ -806,14 +1146,15 @@ hipError_t launch_adj_seed(const float *E, const float *B, float *lE, float *lB,
     return hipGetLastError();
 }
 
-size_t adjoint_lds_bytes(int order, const int P[3]) {
-    const int fcells = (P[1] + 1 + order) * (P[2] + 1 + order);
-    const int jcells = (P[1] + 2 * order + 1) * (P[2] + 2 * order + 1);
+size_t adjoint_lds_bytes(int dim, int order, const int P[3]) {
+    const int fx = dim == 3 ? P[0] + 1 + order : 1, jx = dim == 3 ? P[0] + 2 * order + 1 : 1;
+    const int fcells = fx * (P[1] + 1 + order) * (P[2] + 1 + order);
+    const int jcells = jx * (P[1] + 2 * order + 1) * (P[2] + 2 * order + 1);
     return sizeof(float) * (size_t)adj_lds_layout(fcells, jcells).total;
 }
 
 hipError_t launch_adjoint(const Launch &L, const AdjRun *adj_dev, const AdjRun *adj_host, const Unit *units,
-                          int n_units, int32_t *item_start, int64_t max_items, int chunk, int order,
+                          int n_units, int32_t *item_start, int64_t max_items, int chunk, int dim, int order,
                           int64_t total_cells, const int64_t *run_base, size_t lds, hipStream_t s) {
     const unsigned gc = (unsigned)((total_cells + 255) / 256);
     // (1) LJ = -dt lE', lB2 = lB' + dt curl^+ lE'
@@ -843,14 +1184,25 @@ hipError_t launch_adjoint(const Launch &L, const AdjRun *adj_dev, const AdjRun *
     }
     int64_t grid = (max_items + 7) / 8 * 8;
     if (grid < 8) grid = 8;
-    if (order == 1)
-        hipLaunchKernelGGL(k_adj_particles<1>, dim3((unsigned)grid), dim3(kAdjBlock), lds, s, L.runs_dev, adj_dev, units,
-                           item_start, n_units, chunk);
-    else
-        hipLaunchKernelGGL(k_adj_particles<2>, dim3((unsigned)grid), dim3(kAdjBlock), lds, s, L.runs_dev, adj_dev, units,
-                           item_start, n_units, chunk);
-    // (5) transposed interpolation into lE, lB1
-    hipLaunchKernelGGL(k_adj_fold, dim3(gc), dim3(256), 0, s, L.runs_dev, adj_dev, L.n_runs, run_base, total_cells);
+    if (dim == 3) {
+        // the 3-d kernel adds its transposed interpolation into lE, lB1 itself
+        if (order == 1)
+            hipLaunchKernelGGL(k_adj_particles3<1>, dim3((unsigned)grid), dim3(kAdjBlock), lds, s, L.runs_dev, adj_dev,
+                               units, item_start, n_units, chunk);
+        else
+            hipLaunchKernelGGL(k_adj_particles3<2>, dim3((unsigned)grid), dim3(kAdjBlock), lds, s, L.runs_dev, adj_dev,
+                               units, item_start, n_units, chunk);
+    } else {
+        if (order == 1)
+            hipLaunchKernelGGL(k_adj_particles<1>, dim3((unsigned)grid), dim3(kAdjBlock), lds, s, L.runs_dev, adj_dev,
+                               units, item_start, n_units, chunk);
+        else
+            hipLaunchKernelGGL(k_adj_particles<2>, dim3((unsigned)grid), dim3(kAdjBlock), lds, s, L.runs_dev, adj_dev,
+                               units, item_start, n_units, chunk);
+        // (5) transposed interpolation into lE, lB1
+        hipLaunchKernelGGL(k_adj_fold, dim3(gc), dim3(256), 0, s, L.runs_dev, adj_dev, L.n_runs, run_base,
+                           total_cells);
+    }
     // (6) lE -= dt/2 curl^- lB1   (lB = lB1 is the adjoint of B^n)
     hipLaunchKernelGGL(k_adj_fields, dim3(gc), dim3(256), 0, s, L.runs_dev, adj_dev, L.n_runs, run_base, total_cells, 2);
     return hipGetLastError();

@@ -484,12 +484,14 @@ psc_status psc_init_patches(const psc_run_desc *runs, int n_runs, int chunk, psc
         ctx->off_soff = ctx->off_su = ctx->off_acs = ctx->off_cs0;
         for (int r = 0; r < n_runs; ++r) {
             const RunDev &R = ctx->runs[r];
-            const size_t lds = adjoint_lds_bytes(R.order, R.P);
+            const size_t lds = adjoint_lds_bytes(R.dim, R.order, R.P);
             if (lds > ctx->adj_lds) ctx->adj_lds = lds;
             const int fy = R.P[1] + 1 + R.order, fz = R.P[2] + 1 + R.order;
             ctx->off_b1[r] = take(sizeof(float) * 3 * R.ncell);
             ctx->off_lj[r] = take(sizeof(float) * 3 * R.ncell);
-            ctx->off_gt[r] = take(sizeof(float) * (size_t)R.n_patches * 6 * fy * fz);
+            // 2-d: per-patch transposed-interpolation tiles, folded by k_adj_fold
+            // (the 3-d kernel adds its tiles into the grid adjoints itself)
+            ctx->off_gt[r] = take(R.dim == 2 ? sizeof(float) * (size_t)R.n_patches * 6 * fy * fz : 0);
             for (int s = 0; s < R.n_species; ++s) {
                 ctx->off_soff[r][s] = take(sizeof(float) * R.dim * R.sp[s].cap);
                 ctx->off_su[r][s] = take(sizeof(float) * 3 * R.sp[s].cap);
@@ -640,7 +642,9 @@ psc_status psc_bind(psc_ctx *ctx, const psc_run_bufs *bufs, int n_runs, void *wo
             A.LJ = ctx->at<float>(ctx->off_lj[r]);
             A.gtile = ctx->at<float>(ctx->off_gt[r]);
             const int fy = R.P[1] + 1 + R.order, fz = R.P[2] + 1 + R.order;
-            HIPCHECK(hipMemsetAsync(A.gtile, 0, sizeof(float) * (size_t)R.n_patches * 6 * fy * fz, s), "clear adj tiles");
+            if (R.dim == 2)   // the only runs with per-patch adjoint tiles
+                HIPCHECK(hipMemsetAsync(A.gtile, 0, sizeof(float) * (size_t)R.n_patches * 6 * fy * fz, s),
+                         "clear adj tiles");
             for (int sp = 0; sp < R.n_species; ++sp) {
                 AdjSpecies &S = A.sp[sp];
                 S.soff = ctx->at<float>(ctx->off_soff[r][sp]);
@@ -1247,7 +1251,6 @@ psc_status psc_get_perm(psc_ctx *ctx, int run, int species, int32_t *perm, void 
 psc_status psc_adjoint_step(psc_ctx *ctx, const psc_adj_fwd *fwd, const psc_adj_state *adj, void *stream) {
     if (!ctx || !ctx->bound || !fwd || !adj) return PSC_ERR_INVALID;
     if (!ctx->adjoint) return fail(ctx, PSC_ERR_STATE, "context was created without PSC_RUN_ADJOINT");
-    if (ctx->dim != 2) return fail(ctx, PSC_ERR_UNSUPPORTED, "the adjoint step is implemented for 2-d runs");
     for (int r = 0; r < ctx->n_runs; ++r)
         if (ctx->runs[r].vb)
             return fail(ctx, PSC_ERR_UNSUPPORTED, "the adjoint step differentiates the Esirkepov deposit");
@@ -1289,7 +1292,7 @@ psc_status psc_adjoint_step(psc_ctx *ctx, const psc_adj_fwd *fwd, const psc_adj_
     Launch L = make_launch(ctx, s);
     HIPCHECK(launch_adjoint(L, dev, ctx->adj.data(), ctx->at<Unit>(ctx->off.units),
                             (int)ctx->units.size(), ctx->at<int32_t>(ctx->off.item_start), ctx->adj_items, kAdjChunk,
-                            ctx->order, ctx->total_cells, ctx->at<int64_t>(ctx->off.run_base), ctx->adj_lds, s),
+                            ctx->dim, ctx->order, ctx->total_cells, ctx->at<int64_t>(ctx->off.run_base), ctx->adj_lds, s),
              "adjoint step");
     HIPCHECK(hipEventRecord(ctx->adj_done[slot], s), "adjoint step event");
     return PSC_OK;

@@ -392,9 +392,9 @@ hipError_t launch_diag(const Launch &L, double *out, double *gauss, int64_t tota
                        const int64_t *run_cell_base_dev, int front);
 hipError_t launch_marder(const Launch &L, const double *ref, double d, int iters, int64_t total_cells,
                          const int64_t *run_cell_base_dev, int front);
-size_t adjoint_lds_bytes(int order, const int P[3]);
+size_t adjoint_lds_bytes(int dim, int order, const int P[3]);
 hipError_t launch_adjoint(const Launch &L, const AdjRun *adj_dev, const AdjRun *adj_host, const Unit *units,
-                          int n_units, int32_t *item_start, int64_t max_items, int chunk, int order,
+                          int n_units, int32_t *item_start, int64_t max_items, int chunk, int dim, int order,
                           int64_t total_cells, const int64_t *run_base, size_t lds, hipStream_t s);
 hipError_t radix_sort_pairs(void *temp, size_t *temp_bytes, const int32_t *keys_in, int32_t *keys_out,
                             const int32_t *vals_in, int32_t *vals_out, int64_t n, int bits,

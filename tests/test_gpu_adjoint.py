@@ -160,3 +160,23 @@ def test_adjoint_harris256_directional_derivatives():
     assert errs["W"] <= 1e-5
     for k, v in errs.items():
         assert v <= 1e-3, (k, v)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_adjoint_3d_matches_fp64_oracle(order):
+    """3-d runs (two 4^3 patches along each axis of an 8 x 8 x 8 grid, beams
+    along z with random fields): the GPU gradient after 6 steps with
+    checkpoints every 3 against the float64 autograd adjoint, every block."""
+    from paper_1310_7866_amd.adjoint import energy_gradient
+    c = cases.weibel3d(ppc=3, order=order, patch=4, seed=90 + order, nxyz=(8, 8, 8))
+    cases.random_fields(c, 0.05, 0.3, seed=93 + order)
+    print(f"[gpu] 3-d adjoint order {order} n={c.n_particles}", flush=True)
+    W, gE, gB, gU, _, _ = energy_gradient(c, 6, 3)
+    Wo, oE, oB, oU = A.energy_gradient(c, 6)
+    errs = dict(W=abs(W - Wo) / Wo, E=_rel(gE, oE.reshape(3, -1)), B=_rel(gB, oB.reshape(3, -1)))
+    for s in range(len(gU)):
+        errs[f"u{s}"] = _rel(gU[s], oU[s])
+    print(f"3-d order {order}: relative errors {errs}", flush=True)
+    assert errs["W"] <= 1e-5
+    for k, v in errs.items():
+        assert v <= 1e-3, (k, v)
