@@ -682,6 +682,41 @@ __device__ __forceinline__ float gather3_d(const float *F, int px, int pxy, int 
     return s;
 }
 
+// Transposed interpolation of one component in 3-d through a per-cell frame:
+// each lane forms lam * wx * wy * wz over the window of its cell (the
+// AdjFrame windows per dimension), the lanes of one cell are summed with the
+// segmented wave scan, and the last lane of each cell adds the frame to the
+// double LDS tile.  Every lane of the wave must call it.
+template <int ORDER, bool HX, bool HY, bool HZ>
+__device__ __forceinline__ void frame3_scan_add(double *G, int px, int pxy, int tx, int ty, int tz, float lam,
+                                                const float *wx, const float *wy, const float *wz,
+                                                const RowScan &rs, bool add) {
+    constexpr int nx = AdjFrame<ORDER, HX>::len, ny = AdjFrame<ORDER, HY>::len, nz = AdjFrame<ORDER, HZ>::len;
+    constexpr int N = nx * ny * nz, NV = (N + 3) & ~3;
+    float v[NV];
+#pragma unroll
+    for (int k = 0; k < nz; ++k)
+#pragma unroll
+        for (int b = 0; b < ny; ++b) {
+            const float lyz = lam * wy[b] * wz[k];
+#pragma unroll
+            for (int a = 0; a < nx; ++a) v[(k * ny + b) * nx + a] = lyz * wx[a];
+        }
+#pragma unroll
+    for (int k = N; k < NV; ++k) v[k] = 0.0f;
+    row_scan<64>(v, rs);
+    if (add) {
+        double *p = G + (tz + AdjFrame<ORDER, HZ>::origin) * pxy + (ty + AdjFrame<ORDER, HY>::origin) * px + tx +
+                    AdjFrame<ORDER, HX>::origin;
+#pragma unroll
+        for (int k = 0; k < nz; ++k)
+#pragma unroll
+            for (int b = 0; b < ny; ++b)
+#pragma unroll
+                for (int a = 0; a < nx; ++a) lds_add(p + k * pxy + b * px + a, v[(k * ny + b) * nx + a]);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // the particle adjoint kernel (3-d)
 // ---------------------------------------------------------------------------
@@ -690,10 +725,12 @@ __device__ __forceinline__ float gather3_d(const float *F, int px, int pxy, int 
 // then reversed through the 3-d Esirkepov deposit (J_x(a; b, c) = jfx C_x(a)
 // (A_y(b) A_z(c) + DS_y(b) DS_z(c) / 12) and its two rotations, A = S0 + DS/2,
 // C the running sum of DS = S1 - S0), the move, the Boris rotation and the
-// interpolation.  The transposed interpolation goes by per-lane double LDS
-// atomics into a tile per work item, added at the end straight into lE and
-// lB with the tile's halo wrapped onto the neighbouring cells (float atomics:
-// the summation order of a cell's contributions varies between runs).
+// interpolation.  The transposed interpolation goes through per-cell frames
+// and the segmented wave scan (as in 2-d; at order 2, whose frames would not
+// fit the registers, by per-lane atomics) into a double LDS tile per work
+// item, added at the end straight into lE and lB with the tile's halo
+// wrapped onto the neighbouring cells (float atomics: the summation order of
+// a cell's contributions varies between runs).
 template <int ORDER>
 __global__ void __launch_bounds__(kAdjBlock) k_adj_particles3(const RunDev *__restrict__ runs,
                                                               const AdjRun *__restrict__ adj,
@@ -779,10 +816,16 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles3(const RunDev *__re
         return (uint32_t)q < (uint32_t)AS.stride ? q : 0;   // a corrupt permutation stays in bounds
     };
 
+    // every round gives each thread one particle; at order 1 the rounds are
+    // uniform over the workgroup so that the wave scans see all lanes (lanes
+    // past the end recompute the item's first particle and add zeros in a
+    // segment of their own)
     for (int32_t base = beg; base < end; base += NT) {
         const bool valid = base + (int32_t)threadIdx.x < end;
-        if (!valid) continue;
-        const int32_t i = base + (int32_t)threadIdx.x;
+        if constexpr (ORDER != 1) {
+            if (!valid) continue;   // no wave scans at order 2
+        }
+        const int32_t i = valid ? base + (int32_t)threadIdx.x : beg;
         const int64_t q = slot_of(i);
         int local = AS.key[q] - (int32_t)kb;
         if (local < 0 || local >= pcells) local = 0;
@@ -951,27 +994,57 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles3(const RunDev *__re
         for (int c = 0; c < 6; ++c)
 #pragma unroll
             for (int d = 0; d < 3; ++d) lo0[d] += lF[c] * G[c][d];
-        AS.loff[i] = lo0[0];
-        AS.loff[n + i] = lo0[1];
-        AS.loff[2 * n + i] = lo0[2];
-        AS.lu[i] = lu0.x;
-        AS.lu[n + i] = lu0.y;
-        AS.lu[2 * n + i] = lu0.z;
+        if (valid) {
+            AS.loff[i] = lo0[0];
+            AS.loff[n + i] = lo0[1];
+            AS.loff[2 * n + i] = lo0[2];
+            AS.lu[i] = lu0.x;
+            AS.lu[n + i] = lu0.y;
+            AS.lu[2 * n + i] = lu0.z;
+        }
+        if constexpr (ORDER == 1) {
+            float fn[3][AdjFrame<ORDER, false>::len], fh[3][AdjFrame<ORDER, true>::len];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            const float *wxx = HS[c][0] ? wh[0] : wn[0], *wyy = HS[c][1] ? wh[1] : wn[1], *wzz = HS[c][2] ? wh[2] : wn[2];
-            const int ix = lx + FLO + (HS[c][0] ? bh[0] : bn[0]);
-            const int iy = ly + FLO + (HS[c][1] ? bh[1] : bn[1]);
-            const int iz = lz + FLO + (HS[c][2] ? bh[2] : bn[2]);
-            double *g0 = gt + c * fcells + (iz * fy + iy) * fx + ix;
+            for (int d = 0; d < 3; ++d) {
+                frame_place<ORDER, false>(bn[d], wn[d], fn[d]);
+                frame_place<ORDER, true>(bh[d], wh[d], fh[d]);
+            }
+            const float vm = valid ? 1.0f : 0.0f;
+            const RowScan rs = row_scan_setup<64>(valid ? local : -1);
+            const bool add = rs.tail && valid;
+            const int tx = lx + FLO, ty = ly + FLO, tz = lz + FLO;
+            frame3_scan_add<ORDER, true, false, false>(gt, fx, fxy, tx, ty, tz, vm * lF[0], fh[0], fn[1], fn[2], rs, add);
+            frame3_scan_add<ORDER, false, true, false>(gt + fcells, fx, fxy, tx, ty, tz, vm * lF[1], fn[0], fh[1], fn[2],
+                                                       rs, add);
+            frame3_scan_add<ORDER, false, false, true>(gt + 2 * fcells, fx, fxy, tx, ty, tz, vm * lF[2], fn[0], fn[1],
+                                                       fh[2], rs, add);
+            frame3_scan_add<ORDER, false, true, true>(gt + 3 * fcells, fx, fxy, tx, ty, tz, vm * lF[3], fn[0], fh[1],
+                                                      fh[2], rs, add);
+            frame3_scan_add<ORDER, true, false, true>(gt + 4 * fcells, fx, fxy, tx, ty, tz, vm * lF[4], fh[0], fn[1],
+                                                      fh[2], rs, add);
+            frame3_scan_add<ORDER, true, true, false>(gt + 5 * fcells, fx, fxy, tx, ty, tz, vm * lF[5], fh[0], fh[1],
+                                                      fn[2], rs, add);
+        } else {
+            // order 2: the frames would not fit the registers; per-lane atomics
+            if (valid) {
 #pragma unroll
-            for (int cz = 0; cz <= ORDER; ++cz)
+                for (int c = 0; c < 6; ++c) {
+                    const float *wxx = HS[c][0] ? wh[0] : wn[0], *wyy = HS[c][1] ? wh[1] : wn[1],
+                                *wzz = HS[c][2] ? wh[2] : wn[2];
+                    const int ix = lx + FLO + (HS[c][0] ? bh[0] : bn[0]);
+                    const int iy = ly + FLO + (HS[c][1] ? bh[1] : bn[1]);
+                    const int iz = lz + FLO + (HS[c][2] ? bh[2] : bn[2]);
+                    double *g0 = gt + c * fcells + (iz * fy + iy) * fx + ix;
 #pragma unroll
-                for (int by = 0; by <= ORDER; ++by) {
-                    const float lyz = lF[c] * wyy[by] * wzz[cz];
+                    for (int cz = 0; cz <= ORDER; ++cz)
 #pragma unroll
-                    for (int ax = 0; ax <= ORDER; ++ax) lds_add(g0 + (cz * fy + by) * fx + ax, lyz * wxx[ax]);
+                        for (int by = 0; by <= ORDER; ++by) {
+                            const float lyz = lF[c] * wyy[by] * wzz[cz];
+#pragma unroll
+                            for (int ax = 0; ax <= ORDER; ++ax) lds_add(g0 + (cz * fy + by) * fx + ax, lyz * wxx[ax]);
+                        }
                 }
+            }
         }
     }
     __syncthreads();
