@@ -91,86 +91,123 @@ __device__ __forceinline__ CellBlock cell_block(const RunDev *runs, const ScanSe
 // non-decreasing, so two ballots give the cells [qa, qb] that a group of 64
 // particles touches, and a lane's cell is qa plus the number of starts in
 // (qa, qb] at or below its index (a short uniform loop over scalar reads;
-// a binary search when the group spans many cells).  Ranks: one ballot for
-// the particles that stay in their cell, one per distinct move code among
-// the others.
-template <int M, typename F>
+// a binary search when the group spans many cells).  Its cell's lanes
+// [lo, hi) follow from the cell's first indices.  Ranks: particles that stay
+// in their cell have one ballot for the group; a lane's count of staying
+// lanes below it, less that count at lane lo, is its rank, and it is the
+// last one if its count plus one is the count at lane hi (both taken
+// across the wave by lane shuffles).  Particles that change cell: one
+// ballot per distinct (cell, move code) among them.
+template <int M, typename L, typename F>
 __device__ __forceinline__ void walk_cells(const int32_t *sb, int nw, int32_t pb, int32_t pe,
-                                           gcptr_u8 mc, uint32_t &flags, F &&f) {
+                                           L &&load_code, uint32_t &flags, F &&f) {
     constexpr int CENTER = M / 2;
     constexpr int kLoopCells = 8;   // longest cell range walked by the loop
     const int lane = threadIdx.x & 63;
-    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
     const uint64_t cells = nw >= 64 ? ~0ull : ((1ull << nw) - 1);
     const int32_t sbl = sb[lane < nw ? lane : nw];
-    auto group = [&](int32_t i0, int m_here) {
-        const int32_t i = i0 + lane;
-        const bool valid = i < pe;
-        const int32_t il = i0 + 63 < pe ? i0 + 63 : pe - 1;
-        const int qa = 63 - __clzll(__ballot(sbl <= i0) & cells);   // sb[0] = pb <= i0
-        const int qb = 63 - __clzll(__ballot(sbl <= il) & cells);
-        int q = qa;
-        bool head = lane == 0 || i == pe;
-        if (qb - qa <= kLoopCells) {
-            for (int k = qa + 1; k <= qb; ++k) {
-                const int32_t s = __builtin_amdgcn_readlane(sbl, k);
-                q += s <= i ? 1 : 0;
-                head |= s == i;
-            }
-        } else {
-            int a = qa, b = qb + 1;   // sb[a] <= i < sb[b] (or b = qb + 1)
-            while (b - a > 1) {
-                const int h = (a + b) >> 1;
-                if (sb[h] <= i) a = h;
-                else b = h;
-            }
-            q = a;
-            head |= sb[a] == i;
-        }
-        int m = -1;
-        if (valid) {
-            m = m_here;
-            if (m >= M) { flags |= PSC_DEV_MOVE; m = CENTER; }
-        } else {
-            q = -1;
-        }
-        // lanes of my cell: from the last head at or below me to the next head
-        const uint64_t heads = __ballot(head);
-        const int s0 = 63 - __clzll(heads & upto);
-        const uint64_t after = heads & ~upto;
-        const int e1 = after ? __ffsll((unsigned long long)after) - 1 : 64;
-        const uint64_t mine = (e1 == 64 ? ~0ull : ((1ull << e1) - 1)) & ~((1ull << s0) - 1);
-        // lanes with my move code
-        uint64_t bm = __ballot(m == CENTER);
-        uint64_t mv = __ballot(valid && m != CENTER);
-        while (mv) {
-            const int k = __builtin_amdgcn_readlane(m, __ffsll((unsigned long long)mv) - 1);
-            const uint64_t bk = __ballot(m == k);
-            if (m == k) bm = bk;
-            mv &= ~bk;
-        }
-        const uint64_t grp = bm & mine;
-        const int rank = __popcll(grp & below);
-        const bool last = (grp & ~upto) == 0;
-        f(valid, i, q, m, rank, last);
-        __builtin_amdgcn_wave_barrier();
-    };
-    // Groups go in pairs, each with its own register for move codes loaded
-    // two groups ahead; every load and store is issued on every group (a
-    // group past the end has no valid lane), so the wait for a group's codes
-    // leaves the two most recent stores in flight.
+    // Groups go in pairs, with move codes loaded two pairs ahead; every load
+    // and store is issued on every group (a group past the end has no valid
+    // lane), so the wait for a pair's codes (loads and stores retire in
+    // issue order) leaves the stores of the last pairs in flight.  The two groups of a pair are ranked
+    // in phases before either updates the counters, so that the LDS reads
+    // and lane shuffles of one overlap those of the other.
     if (pb >= pe) return;
-    const int32_t last_i = pe - 1;
-    int ma = (int)mc[imin(pb + lane, last_i)];
-    int mb = (int)mc[imin(pb + 64 + lane, last_i)];
+    int ma = load_code(pb + lane);
+    int mb = load_code(pb + 64 + lane);
+    int mc2 = load_code(pb + 128 + lane);
+    int md = load_code(pb + 192 + lane);
     for (int32_t i0 = pb; i0 < pe; i0 += 128) {
-        const int m0 = ma;
-        ma = (int)mc[imin(i0 + 128 + lane, last_i)];
-        group(i0, m0);
-        const int m1 = mb;
-        mb = (int)mc[imin(i0 + 192 + lane, last_i)];
-        group(i0 + 64, m1);
+        const int mh[2] = {ma, mb};
+        ma = mc2;
+        mb = md;
+        mc2 = load_code(i0 + 256 + lane);
+        md = load_code(i0 + 320 + lane);
+        int32_t gi[2];
+        int q[2], lend[2], lo[2], hi[2], m[2], s_me[2], s_lo[2], s_hi[2], g_me[2];
+        bool valid[2], st[2];
+        uint64_t stay[2], grp[2];
+        // the lanes' cells
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            const int32_t g0 = i0 + 64 * g;
+            gi[g] = g0 + lane;
+            valid[g] = gi[g] < pe;
+            lend[g] = pe - g0 < 64 ? (int)(pe - g0) : 64;   // lanes [0, lend) hold particles
+            const int32_t il = g0 + lend[g] - 1;
+            const int qa = 63 - __clzll(__ballot(sbl <= g0) & cells);   // sb[0] = pb <= g0
+            const int qb = 63 - __clzll(__ballot(sbl <= il) & cells);
+            int qq = qa;
+            if (qb - qa <= kLoopCells) {
+                for (int k = qa + 1; k <= qb; ++k) qq += __builtin_amdgcn_readlane(sbl, k) <= gi[g] ? 1 : 0;
+            } else {
+                int a = qa, b = qb + 1;   // sb[a] <= i < sb[b] (or b = qb + 1)
+                while (b - a > 1) {
+                    const int h = (a + b) >> 1;
+                    if (sb[h] <= gi[g]) a = h;
+                    else b = h;
+                }
+                qq = a;
+            }
+            q[g] = qq;
+        }
+        // each cell's lanes [lo, hi) (q + 1 <= qb + 1 <= nw: inside sb)
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            lo[g] = imax(sb[q[g]] - (i0 + 64 * g), 0);
+            hi[g] = imin(sb[q[g] + 1] - (i0 + 64 * g), lend[g]);
+        }
+        // codes; staying lanes below each lane
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            m[g] = -1;
+            if (valid[g]) {
+                m[g] = mh[g];
+                if (m[g] >= M) { flags |= PSC_DEV_MOVE; m[g] = CENTER; }
+            }
+            st[g] = m[g] == CENTER;
+            stay[g] = __ballot(st[g]);
+            s_me[g] = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(stay[g] >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)stay[g], 0u));
+        }
+        // the counts at the cell's first lane and at its end
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            s_lo[g] = __shfl(s_me[g], lo[g], 64);
+            s_hi[g] = __shfl(s_me[g], hi[g] & 63, 64);
+        }
+        // lanes that move: the lanes of their (cell, code)
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            uint64_t gr = 0;
+            const int key = valid[g] ? q[g] * 32 + m[g] : -1;
+            uint64_t mv = __ballot(valid[g] && !st[g]);
+            while (mv) {
+                const int k = __builtin_amdgcn_readlane(key, __ffsll((unsigned long long)mv) - 1);
+                const uint64_t bk = __ballot(key == k);
+                if (key == k) gr = bk;
+                mv &= ~bk;
+            }
+            grp[g] = gr;
+            g_me[g] = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(gr >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)gr, 0u));
+        }
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            // grp is empty for the lanes that stay: the two ranks add
+            // (written without branches)
+            const int rank = g_me[g] + ((s_me[g] - s_lo[g]) & -(int)st[g]);
+            // last: a staying lane whose count plus one is its cell's count
+            // (all staying lanes of the group when the cell runs to lane 64);
+            // a moving lane with none of its group above it (grp <= upto)
+            const int s_end = hi[g] < 64 ? s_hi[g] : __popcll(stay[g]);
+            const uint64_t lastm =
+                (stay[g] & __ballot(s_me[g] + 1 == s_end)) | (~stay[g] & __ballot(grp[g] <= upto));
+            const bool last = (lastm >> lane) & 1;
+            f(valid[g], gi[g], valid[g] ? q[g] : -1, m[g], rank, last);
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -287,8 +324,16 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_prefix(const RunDev *__rest
     }
 }
 
-// target of the scatter's stores from lanes that have no position
+// target of the scatter's stores from lanes that have no position (species
+// too large for a buffer resource)
 __device__ int32_t sort_sink;
+// raw buffer resource of the permutation (4th word: 32-bit data format, as
+// for every gfx9-family chip); offsets at or past n * 4 bytes are dropped.
+// kBufferDrop lies past every buffer of at most kBufferMaxN words, also
+// when the range check adds the store's 4 bytes
+constexpr int kBufferWord3 = 0x00020000;
+constexpr int32_t kBufferMaxN = 0x3FFFFFF0;
+constexpr int kBufferDrop = (int)0xFFFFFFE0u;
 
 // per old cell: stable positions of its particles.  Lane q sets up the first
 // position of every move code of its cell in LDS; the walk then writes
@@ -336,7 +381,6 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(const RunDev *__r
         }
     }
     __builtin_amdgcn_wave_barrier();
-    const gptr_i32 perm = (gptr_i32)S.perm[1 - cs_sel];
     const int32_t n = (int32_t)S.n;
     uint32_t flags = 0;
     bool bad = false;
@@ -344,19 +388,42 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(const RunDev *__r
     // kept inside [0, n] also for offsets corrupted by a counter overflow
     const int32_t pe = imin(imax(__builtin_amdgcn_readfirstlane(sb[nw]), 0), n);
     const int32_t pb = imin(imax(__builtin_amdgcn_readfirstlane(sb[0]), 0), pe);
-    walk_cells<M>(sb, nw, pb, pe, (gcptr_u8)S.mc, flags,
-                  [&](bool valid, int32_t i, int q, int m, int rank, bool last) {
-                      const int slot = valid ? m * 64 + q : 0;
-                      const int32_t p = tab[slot] + rank;
-                      // out of range only after a counter overflow
-                      const bool ok = valid && p >= 0 && p < n;
-                      bad |= valid && !ok;
-                      // one store per group on every lane: lanes without a
-                      // position write the sink word
-                      const gptr_i32 dst = ok ? perm + p : (gptr_i32)&sort_sink;
-                      *dst = i;
-                      if (valid && last) tab[slot] = p + 1;
-                  });
+    auto walk = [&](auto &&load_code, auto &&store) {
+        walk_cells<M>(sb, nw, pb, pe, load_code, flags,
+                      [&](bool valid, int32_t i, int q, int m, int rank, bool last) {
+                          const int slot = valid ? m * 64 + q : 0;
+                          const int32_t p = tab[slot] + rank;
+                          // out of range only after a counter overflow
+                          const bool ok = valid && p >= 0 && p < n;
+                          bad |= valid && !ok;
+                          store(ok, p, i);   // on every lane of every group
+                          if (valid && last) tab[slot] = p + 1;
+                      });
+    };
+    if (n <= kBufferMaxN) {
+        // a raw buffer store: the hardware drops stores at offsets past
+        // the buffer's n * 4 bytes, so lanes without a position need no
+        // other target
+        const __amdgpu_buffer_rsrc_t prs =
+            __builtin_amdgcn_make_buffer_rsrc(S.perm[1 - cs_sel], (short)0, (int)((uint32_t)n << 2), kBufferWord3);
+        // move codes through a byte buffer of n entries: indices past the
+        // end read 0 (their lanes hold no particle)
+        const __amdgpu_buffer_rsrc_t mrs = __builtin_amdgcn_make_buffer_rsrc(S.mc, (short)0, n, kBufferWord3);
+        walk([&](int32_t idx) { return (int)__builtin_amdgcn_raw_buffer_load_b8(mrs, idx, 0, 0); },
+             [&](bool ok, int32_t p, int32_t i) {
+            __builtin_amdgcn_raw_buffer_store_b32((uint32_t)i, prs, ok ? (int)((uint32_t)p << 2) : kBufferDrop, 0, 0);
+        });
+    } else {
+        // lanes without a position write the sink word
+        const gptr_i32 perm = (gptr_i32)S.perm[1 - cs_sel];
+        const gcptr_u8 mc = (gcptr_u8)S.mc;
+        const int32_t last_i = pe - 1;
+        walk([&](int32_t idx) { return (int)mc[imin(idx, last_i)]; },
+             [&](bool ok, int32_t p, int32_t i) {
+            const gptr_i32 dst = ok ? perm + p : (gptr_i32)&sort_sink;
+            *dst = i;
+        });
+    }
     if (bad) flags |= PSC_DEV_OVERFULL;
     if (flags) atomicOr(err, flags);   // also an invalid move code (PSC_DEV_MOVE)
 }
