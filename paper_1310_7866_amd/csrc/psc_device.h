@@ -150,6 +150,10 @@ __device__ __forceinline__ float rsqrt_ge1(float x) { return __builtin_amdgcn_rs
 // reciprocal (1 ulp; the IEEE division takes ten instructions)
 __device__ __forceinline__ float boris_factor(float t2) { return 2.0f * __builtin_amdgcn_rcpf(1.0f + t2); }
 
+// s_waitcnt immediate that waits for every vector memory operation and for
+// nothing else (vmcnt 0; expcnt 7 and lgkmcnt 15 do not wait)
+constexpr int kWaitVmcnt0 = 0x0F70;
+
 // pointers into device memory known to be global (loads and stores become
 // global_* instead of flat_*, which would also wait on LDS traffic)
 template <typename T>

@@ -10,6 +10,8 @@
 // through the sort permutation, writing them in sorted order into the other
 // buffer set, so the physical reorder of the sort costs no extra pass), and
 // adds the LDS tile into the patch's current tile in HBM.
+#include <type_traits>
+
 #include "psc_device.h"
 
 namespace psc {
@@ -571,7 +573,10 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
     const gptr<int32_t> id_out = to_global(S.id[outb]);
     const gptr<const int32_t> perm = to_global<const int32_t>(S.perm[cs_sel]);
     const gptr<uint8_t> mc = to_global(S.mc);
-    uint32_t *cnt32 = reinterpret_cast<uint32_t *>(S.cnt);   // pairs of 16-bit counters
+    // pairs of 16-bit counters.  Global (not generic) pointers here and for
+    // the current flush: a pending flat atomic can complete out of order, so
+    // every later wait for a load would have to drain all memory operations
+    const gptr<uint32_t> cnt32 = to_global(reinterpret_cast<uint32_t *>(S.cnt));
     const int64_t cap = S.cap;
     const float h = S.qdt_2m;
     const float qw = S.qw;
@@ -618,11 +623,15 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
         __builtin_amdgcn_wave_barrier();
     };
 
-    // K = 1 with prefetching: the source slot (through the permutation) and
-    // cell key of the lane's particle in the round starting at r; lanes
-    // without a particle stand in with the chunk's first particle
+    // K = 1 with prefetching: the state of the lane's particle in the next
+    // round (cell key, offsets, momenta, id) is loaded at the start of the
+    // current round, before its stores, and its permutation entry one round
+    // earlier still.  Loads and stores retire in issue order, so the next
+    // round's wait for its particle leaves this round's stores in flight.
+    // Lanes without a particle stand in with the chunk's first particle.
     constexpr bool prefetch = single && PSC_PREFETCH;
-    int32_t p_src = beg, p_key = 0;
+    int32_t p_key = 0, p_raw = beg, p_id = 0;
+    float p_o[3] = {0.0f, 0.0f, 0.0f}, p_u[3] = {0.0f, 0.0f, 0.0f};
     auto lane_slot = [&](int32_t r, bool &ok) {
         int32_t g = r + (int32_t)threadIdx.x;
         if constexpr (PSC_MIX && !RUNS) g = mix_lane(g, nruns);   // ablation only
@@ -636,17 +645,36 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
         }
         return raw;
     };
+    auto load_state = [&](int32_t src) {
+        p_key = cell_in[src];
+        if constexpr (DIM == 3) p_o[0] = off_in[src];
+        p_o[1] = off_in[(DIM == 3 ? 1 : 0) * cap + src];
+        p_o[2] = off_in[(DIM == 3 ? 2 : 1) * cap + src];
+        p_u[0] = u_in[src];
+        p_u[1] = u_in[cap + src];
+        p_u[2] = u_in[2 * cap + src];
+        p_id = id_in ? id_in[src] : 0;
+    };
     if constexpr (prefetch) {
         bool ok;
         const int32_t sl = lane_slot(0, ok);
-        p_src = checked_src(sl, use_perm ? perm[sl] : sl, ok);
-        p_key = cell_in[p_src];
+        load_state(checked_src(sl, use_perm ? perm[sl] : sl, ok));
+        const int32_t sl1 = lane_slot(NT, ok);
+        p_raw = use_perm ? perm[sl1] : sl1;
+        // these loads complete here, once per item: the compiler's waits in
+        // the round loop then count only the loop's own memory operations
+        // (entering with the prologue's loads pending, it would wait for all
+        // outstanding operations on every round)
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     }
 
     // every lane runs the same number of rounds and of steps per round (the
     // wave operations need all 64 lanes); lanes without a particle carry zero
     // current and write nothing
-    for (int32_t r0 = 0; r0 < nruns; r0 += NT) {
+    // FULL: every lane of the round holds a particle (compile-time, so that
+    // such rounds issue their loads and stores on every path)
+    auto round = [&](int32_t r0, auto full_tag) {
+        constexpr bool FULL = decltype(full_tag)::value;
         int32_t g = r0 + (int32_t)threadIdx.x;
         if constexpr (PSC_MIX && !RUNS) g = mix_lane(g, nruns);   // ablation only
         const int32_t first = beg + g * K;                       // this lane's strip
@@ -766,13 +794,12 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
         float pu0[3] = {0.0f, 0.0f, 0.0f}, pu1[3] = {0.0f, 0.0f, 0.0f};
 
         for (int j = 0; j < K; ++j) {
-            const bool valid = j < len;
+            const bool valid = FULL || j < len;
             // lanes without a particle stand in with the chunk's first
             // particle (taken through the permutation, so it lies in range)
             const int32_t slot = valid ? first + j : beg;
-            int32_t src, key;
+            int32_t src = 0, key;
             if constexpr (prefetch) {
-                src = p_src;
                 key = p_key;
             } else {
                 src = checked_src(slot, use_perm ? perm[slot] : slot, valid);
@@ -790,19 +817,35 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
                 fy_ = ly;
                 fz_ = lz;
             }
-            float o[3];
-            o[0] = DIM == 3 ? off_in[src] : 0.0f;
-            o[1] = off_in[(DIM == 3 ? 1 : 0) * cap + src];
-            o[2] = off_in[(DIM == 3 ? 2 : 1) * cap + src];
-            float ux = u_in[src], uy = u_in[cap + src], uz = u_in[2 * cap + src];
-            const int32_t idv = id_in ? id_in[src] : 0;
-            // the next round's permutation entry (the round loop is uniform)
-            const bool more = prefetch && r0 + NT < nruns;
-            bool n_ok = false;
-            int32_t n_slot = beg, n_raw = beg;
-            if (more) {
-                n_slot = lane_slot(r0 + NT, n_ok);
-                n_raw = use_perm ? perm[n_slot] : n_slot;
+            float o[3], ux, uy, uz;
+            int32_t idv;
+            if constexpr (prefetch) {
+                o[0] = DIM == 3 ? p_o[0] : 0.0f;
+                o[1] = p_o[1];
+                o[2] = p_o[2];
+                ux = p_u[0];
+                uy = p_u[1];
+                uz = p_u[2];
+                idv = p_id;
+            } else {
+                o[0] = DIM == 3 ? off_in[src] : 0.0f;
+                o[1] = off_in[(DIM == 3 ? 1 : 0) * cap + src];
+                o[2] = off_in[(DIM == 3 ? 2 : 1) * cap + src];
+                ux = u_in[src];
+                uy = u_in[cap + src];
+                uz = u_in[2 * cap + src];
+                idv = id_in ? id_in[src] : 0;
+            }
+            // the next round's particle (its permutation entry was read a
+            // round ago), then the permutation entry of the round after it
+            // (the round loop is uniform; past the end a lane reads the
+            // chunk's first particle)
+            if constexpr (prefetch) {
+                bool n_ok;
+                const int32_t n_slot = lane_slot(r0 + NT, n_ok);
+                load_state(checked_src(n_slot, p_raw, n_ok));
+                const int32_t sl2 = lane_slot(r0 + 2 * NT, n_ok);
+                p_raw = use_perm ? perm[sl2] : sl2;
             }
 
             // ---- interpolation ----------------------------------------------
@@ -851,10 +894,6 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
             }
             const float ig = rsqrt_ge1(1.0f + ux * ux + uy * uy + uz * uz);
             if (valid && !(ig > 0.0f)) flags |= PSC_DEV_NONFINITE;   // NaN or Inf momentum
-            if (more) {
-                p_src = checked_src(n_slot, n_raw, n_ok);
-                p_key = cell_in[p_src];
-            }
 
             // ---- move: xi^{n+3/2} = xi^{n+1/2} + dt u^{n+1} / (gamma dx) ---
             int s[3] = {0, 0, 0};
@@ -943,7 +982,7 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
                 const int code = DIM == 3 ? (s[0] + 1) + 3 * (s[1] + 1) + 9 * (s[2] + 1) : (s[1] + 1) + 3 * (s[2] + 1);
                 if (valid && code != CENTER) {
                     const int64_t w = (int64_t)code * R.ncell + kb + c;
-                    atomicAdd(cnt32 + (w >> 1), 1u << (16 * (int)(w & 1)));
+                    atomicAdd((uint32_t *)(cnt32 + (w >> 1)), 1u << (16 * (int)(w & 1)));
                 }
             }
 
@@ -1109,6 +1148,14 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
                 }
             }
         }
+    };
+    if constexpr (single && !PSC_MIX) {
+        // the full rounds, then the item's partial last round
+        int32_t r0 = 0;
+        for (; r0 + NT <= nruns; r0 += NT) round(r0, std::true_type{});
+        if (r0 < nruns) round(r0, std::false_type{});
+    } else {
+        for (int32_t r0 = 0; r0 < nruns; r0 += NT) round(r0, std::false_type{});
     }
     if constexpr (kReduce) {
         if (qn) drain(qn);
@@ -1123,7 +1170,7 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
         // done here).  Fixed point in units of jq: integer sums, so the
         // result does not depend on the order in which work items add
         const int64_t nc = R.ncell;
-        unsigned long long *acc = reinterpret_cast<unsigned long long *>(R.jacc);
+        const gptr<unsigned long long> acc = to_global(reinterpret_cast<unsigned long long *>(R.jacc));
         const double inv_q = R.jinvq;
         const float inv_jx = 1.0f / jx_, inv_jy = 1.0f / jy_;
         for (int q = threadIdx.x; q < n_jband; q += NT) {
@@ -1145,19 +1192,19 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
 #pragma unroll
                 for (int cp = 1; cp < kJCopies; ++cp) v += jtile[(3 * cp + c) * jcells + t];
                 const long long k = (long long)__builtin_rint(v * inv_q);
-                if (k != 0) atomicAdd(&acc[c * nc + g], (unsigned long long)k);   // two's complement
+                if (k != 0) atomicAdd((unsigned long long *)(acc + (c * nc + g)), (unsigned long long)k);   // two's complement
             }
         }
     } else {
         // add the LDS current tile into the patch's tile in HBM
-        float *gt = R.jtile + (int64_t)U.patch * 3 * jcells;
+        const gptr<float> gt = to_global(R.jtile + (int64_t)U.patch * 3 * jcells);
         for (int q = threadIdx.x; q < 3 * n_jband; q += NT) {
             const int c = q / n_jband;
             const int t = c * jcells + jr0 * jplane + (q - c * n_jband);
             double v = jtile[t];
 #pragma unroll
             for (int cp = 1; cp < kJCopies; ++cp) v += jtile[3 * cp * jcells + t];
-            if (v != 0.0) atomicAdd(&gt[t], (float)v);
+            if (v != 0.0) atomicAdd((float *)(gt + t), (float)v);
         }
     }
     __syncthreads();
