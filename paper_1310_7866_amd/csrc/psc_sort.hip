@@ -20,7 +20,7 @@
 // to load particles in arbitrary order.
 #include <rocprim/device/device_radix_sort.hpp>
 
-#include "psc_internal.h"
+#include "psc_device.h"
 
 namespace psc {
 
@@ -254,7 +254,11 @@ __device__ __forceinline__ int32_t prefix_cell(const RunDev &R, const SpeciesDev
     int32_t cn[M];
     // arrivals into n from each source (the particle kernel counts the
     // particles that change cell); those that stay in n are the rest of n
-    const int32_t *cs_old = S.cs[cs_sel];
+    // global (not generic) pointers throughout: a flat access also counts
+    // against the LDS counter, so every wait for the LDS slots would wait
+    // for memory as well
+    const gptr<const int32_t> cs_old = to_global<const int32_t>(S.cs[cs_sel]);
+    const gptr<const uint16_t> cnt = to_global<const uint16_t>(S.cnt);
     int32_t stay = cs_old[n + 1] - cs_old[n];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
@@ -265,8 +269,8 @@ __device__ __forceinline__ int32_t prefix_cell(const RunDev &R, const SpeciesDev
         ks[m] = (int32_t)key_of(R, ax[0].pc[a0], ax[1].pc[a1], ax[2].pc[a2], ax[0].l[a0], ax[1].l[a1], ax[2].l[a2],
                                 ax[0].ext[a0], ax[1].ext[a1], ax[2].ext[a2]);
         if (m != CENTER) {
-            cn[m] = S.cnt[m * nc + ks[m]];
-            stay -= S.cnt[m * nc + n];   // leaving n with move m
+            cn[m] = cnt[m * nc + ks[m]];
+            stay -= cnt[m * nc + n];   // leaving n with move m
         }
     }
     if (stay < 0) {   // counts inconsistent with the cell offsets
@@ -283,10 +287,11 @@ __device__ __forceinline__ int32_t prefix_cell(const RunDev &R, const SpeciesDev
         slot[k] = tot;
         tot += v;
     }
+    const gptr<uint16_t> pre = to_global(S.pre);
 #pragma unroll
-    for (int m = 0; m < M; ++m) S.pre[m * nc + ks[m]] = (uint16_t)slot[rk[m]];
+    for (int m = 0; m < M; ++m) pre[m * nc + ks[m]] = (uint16_t)slot[rk[m]];
     if (tot > 65535) atomicOr(err, PSC_DEV_OVERFULL);
-    S.tot[n] = tot;
+    to_global(S.tot)[n] = tot;
     return tot;
 }
 
@@ -356,8 +361,10 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(const RunDev *__r
     const RunDev &R = *B.R;
     const SpeciesDev &S = *B.S;
     const int64_t nc = R.ncell;
-    const int32_t *cs_old = S.cs[cs_sel];
-    const int32_t *cs_new = S.cs[1 - cs_sel];
+    const gptr<const int32_t> cs_old = to_global<const int32_t>(S.cs[cs_sel]);
+    const gptr<const int32_t> cs_new = to_global<const int32_t>(S.cs[1 - cs_sel]);
+    const gptr<const uint16_t> pre = to_global<const uint16_t>(S.pre);
+    const gptr<uint16_t> cnt = to_global(S.cnt);
     const int nw = (int)(B.ce - B.cw);
     sb[lane] = cs_old[B.cw + (lane < nw ? lane : nw)];
     if (lane == 0) sb[64] = cs_old[B.ce];
@@ -376,8 +383,8 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(const RunDev *__r
             const int a0 = DIM == 3 ? 1 + d[0] : 1, a1 = 1 + d[1], a2 = 1 + d[2];
             const uint32_t dst = key_of(R, ax[0].pc[a0], ax[1].pc[a1], ax[2].pc[a2], ax[0].l[a0], ax[1].l[a1],
                                         ax[2].l[a2], ax[0].ext[a0], ax[1].ext[a1], ax[2].ext[a2]);
-            tab[m * 64 + lane] = cs_new[dst] + S.pre[m * nc + o];
-            if (m != M / 2) S.cnt[m * nc + o] = 0;   // consumed by the prefix pass: clear for the next push
+            tab[m * 64 + lane] = cs_new[dst] + pre[m * nc + o];
+            if (m != M / 2) cnt[m * nc + o] = 0;   // consumed by the prefix pass: clear for the next push
         }
     }
     __builtin_amdgcn_wave_barrier();
