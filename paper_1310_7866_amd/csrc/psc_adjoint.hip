@@ -207,7 +207,7 @@ __device__ __forceinline__ void adj_field_cell(const RunDev &R, const AdjRun &A,
     const int64_t im = i > 0 ? idx - 1 : idx + (nx - 1);
     const int64_t jm = j > 0 ? idx - sy : idx + (int64_t)(ny - 1) * sy;
     const int64_t km = k > 0 ? idx - sz : idx + (int64_t)(nz - 1) * sz;
-    auto curl_plus = [&](const float *F, float &cx, float &cy, float &cz) {
+    auto curl_plus = [&](const gptr<const float> F, float &cx, float &cy, float &cz) {
         const float fx = F[idx], fy = F[nc + idx], fz = F[2 * nc + idx];
         const float fz_j = F[2 * nc + jp], fy_k = F[nc + kp], fx_k = F[kp], fz_i = F[2 * nc + ip], fy_i = F[nc + ip],
                     fx_j = F[jp];
@@ -215,7 +215,7 @@ __device__ __forceinline__ void adj_field_cell(const RunDev &R, const AdjRun &A,
         cy = (fx_k - fx) * iz - (fz_i - fz) * ix;
         cz = (fy_i - fy) * ix - (fx_j - fx) * iy;
     };
-    auto curl_minus = [&](const float *F, float &cx, float &cy, float &cz) {
+    auto curl_minus = [&](const gptr<const float> F, float &cx, float &cy, float &cz) {
         const float fx = F[idx], fy = F[nc + idx], fz = F[2 * nc + idx];
         const float fz_j = F[2 * nc + jm], fy_k = F[nc + km], fx_k = F[km], fz_i = F[2 * nc + im], fy_i = F[nc + im],
                     fx_j = F[jm];
@@ -226,32 +226,32 @@ __device__ __forceinline__ void adj_field_cell(const RunDev &R, const AdjRun &A,
     const float dt = R.dt;
     float cx, cy, cz;
     if (op == 0) {
-        curl_plus(A.lE, cx, cy, cz);
-        const float e0 = A.lE[idx], e1 = A.lE[nc + idx], e2 = A.lE[2 * nc + idx];
-        const float b0 = A.lB[idx], b1 = A.lB[nc + idx], b2 = A.lB[2 * nc + idx];
-        A.LJ[idx] = -dt * e0;
-        A.LJ[nc + idx] = -dt * e1;
-        A.LJ[2 * nc + idx] = -dt * e2;
-        A.lB[idx] = b0 + dt * cx;
-        A.lB[nc + idx] = b1 + dt * cy;
-        A.lB[2 * nc + idx] = b2 + dt * cz;
+        curl_plus(to_global<const float>(A.lE), cx, cy, cz);
+        const float e0 = to_global(A.lE)[idx], e1 = to_global(A.lE)[nc + idx], e2 = to_global(A.lE)[2 * nc + idx];
+        const float b0 = to_global(A.lB)[idx], b1 = to_global(A.lB)[nc + idx], b2 = to_global(A.lB)[2 * nc + idx];
+        to_global(A.LJ)[idx] = -dt * e0;
+        to_global(A.LJ)[nc + idx] = -dt * e1;
+        to_global(A.LJ)[2 * nc + idx] = -dt * e2;
+        to_global(A.lB)[idx] = b0 + dt * cx;
+        to_global(A.lB)[nc + idx] = b1 + dt * cy;
+        to_global(A.lB)[2 * nc + idx] = b2 + dt * cz;
     } else {
-        curl_minus(A.lB, cx, cy, cz);
+        curl_minus(to_global<const float>(A.lB), cx, cy, cz);
         float ex = 0.0f, ey = 0.0f, ez = 0.0f, bx = 0.0f, by = 0.0f, bz = 0.0f;
-        const float e0 = A.lE[idx], e1 = A.lE[nc + idx], e2 = A.lE[2 * nc + idx];
+        const float e0 = to_global(A.lE)[idx], e1 = to_global(A.lE)[nc + idx], e2 = to_global(A.lE)[2 * nc + idx];
         if (op == 1) {
-            curl_plus(A.E, ex, ey, ez);
-            bx = A.B[idx];
-            by = A.B[nc + idx];
-            bz = A.B[2 * nc + idx];
+            curl_plus(to_global(A.E), ex, ey, ez);
+            bx = to_global(A.B)[idx];
+            by = to_global(A.B)[nc + idx];
+            bz = to_global(A.B)[2 * nc + idx];
         }
-        A.lE[idx] = e0 - 0.5f * dt * cx;
-        A.lE[nc + idx] = e1 - 0.5f * dt * cy;
-        A.lE[2 * nc + idx] = e2 - 0.5f * dt * cz;
+        to_global(A.lE)[idx] = e0 - 0.5f * dt * cx;
+        to_global(A.lE)[nc + idx] = e1 - 0.5f * dt * cy;
+        to_global(A.lE)[2 * nc + idx] = e2 - 0.5f * dt * cz;
         if (op == 1) {
-            A.B1[idx] = bx - 0.5f * dt * ex;
-            A.B1[nc + idx] = by - 0.5f * dt * ey;
-            A.B1[2 * nc + idx] = bz - 0.5f * dt * ez;
+            to_global(A.B1)[idx] = bx - 0.5f * dt * ex;
+            to_global(A.B1)[nc + idx] = by - 0.5f * dt * ey;
+            to_global(A.B1)[2 * nc + idx] = bz - 0.5f * dt * ez;
         }
     }
 }
@@ -269,10 +269,12 @@ __global__ void k_adj_unpermute(const AdjRun *__restrict__ adj, int r, int s, in
     const AdjSpecies &S = adj[r].sp[s];
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= S.n) return;
-    const int64_t p = S.perm[j];
+    const int64_t p = to_global(S.perm)[j];
     if (p < 0 || p >= S.n) return;
-    for (int d = 0; d < dim; ++d) S.soff[d * S.n + p] = S.loff[d * S.n + j];
-    for (int c = 0; c < 3; ++c) S.su[c * S.n + p] = S.lu[c * S.n + j];
+    const gptr<float> soff = to_global(S.soff), su = to_global(S.su);
+    const gptr<const float> loff = to_global<const float>(S.loff), lu = to_global<const float>(S.lu);
+    for (int d = 0; d < dim; ++d) soff[d * S.n + p] = loff[d * S.n + j];
+    for (int c = 0; c < 3; ++c) su[c * S.n + p] = lu[c * S.n + j];
 }
 
 // work items of the particle adjoint per unit (one thread per unit); the
@@ -343,7 +345,7 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles(const RunDev *__res
     const int hy = patch_ext(R, 1, pc[1]), hz = patch_ext(R, 2, pc[2]);
     const int oy = pc[1] * R.P[1], oz = pc[2] * R.P[2];
     const int64_t kb = patch_key_base(R, 0, pc[1], pc[2]);
-    const int32_t pbeg = AS.cs[kb], pend = AS.cs[kb + (int64_t)hy * hz];
+    const int32_t pbeg = to_global(AS.cs)[kb], pend = to_global(AS.cs)[kb + (int64_t)hy * hz];
     const int32_t beg = pbeg + (item - item_start[lo]) * chunk;
     const int32_t end = min(beg + chunk, pend);
 
@@ -366,11 +368,11 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles(const RunDev *__res
     // buffer slot of the forward particle at sorted slot i
     auto slot_of = [&](int32_t i) -> int64_t {
         if (!AS.rperm) return i;
-        const int32_t q = AS.rperm[i];
+        const int32_t q = to_global(AS.rperm)[i];
         return (uint32_t)q < (uint32_t)AS.stride ? q : 0;   // a corrupt permutation stays in bounds
     };
-    const int lf = imin(imax(AS.key[slot_of(beg)] - (int32_t)kb, 0), pc_cells - 1);
-    const int ll = imin(imax(AS.key[slot_of(end - 1)] - (int32_t)kb, 0), pc_cells - 1);
+    const int lf = imin(imax(to_global(AS.key)[slot_of(beg)] - (int32_t)kb, 0), pc_cells - 1);
+    const int ll = imin(imax(to_global(AS.key)[slot_of(end - 1)] - (int32_t)kb, 0), pc_cells - 1);
     const int zf = lf / hy, zl = ll / hy;
     const int fr0 = zf + FLO - 1, fr1 = imin(zl + FLO + ORDER, fz - 1);   // field-tile rows [fr0, fr1]
     const int jr0 = zf, jr1 = imin(zl + 2 * ORDER + 1, jz - 1);           // current-tile rows [jr0, jr1]
@@ -384,8 +386,8 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles(const RunDev *__res
             const int64_t g = wrap(oy + ty - FLO, R.n[1]) + (int64_t)R.n[1] * wrap(oz + tz - FLO, R.n[2]);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                ftile[c * fcells + t] = A.E[c * nc + g];
-                ftile[(3 + c) * fcells + t] = A.B1[c * nc + g];
+                ftile[c * fcells + t] = to_global(A.E)[c * nc + g];
+                ftile[(3 + c) * fcells + t] = to_global(A.B1)[c * nc + g];
                 gt[c * fcells + t] = 0.0;
                 gt[(3 + c) * fcells + t] = 0.0;
             }
@@ -398,7 +400,7 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles(const RunDev *__res
             const int t = tz * jy + ty;
             const int64_t g = wrap(oy + ty - JLO, R.n[1]) + (int64_t)R.n[1] * wrap(oz + tz - JLO, R.n[2]);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) ljt[c * jcells + t] = A.LJ[c * nc + g];
+            for (int c = 0; c < 3; ++c) ljt[c * jcells + t] = to_global(A.LJ)[c * nc + g];
         }
     }
     __syncthreads();
@@ -416,13 +418,13 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles(const RunDev *__res
         const int32_t i = valid ? base + (int32_t)threadIdx.x : beg;
         const int64_t q = slot_of(i);
         const int64_t st = AS.stride;
-        const int32_t key = AS.key[q];
+        const int32_t key = to_global(AS.key)[q];
         int local = key - (int32_t)kb;
         if (local < 0 || local >= hy * hz) local = 0;
         int ly;
         const int lz = divmod_small(local, hy, inv_hy, ly);
-        const float oyv = AS.off[q], ozv = AS.off[st + q];
-        const float3 u0 = make_float3(AS.u[q], AS.u[st + q], AS.u[2 * st + q]);
+        const float oyv = to_global(AS.off)[q], ozv = to_global(AS.off)[st + q];
+        const float3 u0 = make_float3(to_global(AS.u)[q], to_global(AS.u)[st + q], to_global(AS.u)[2 * st + q]);
 
         // ---- forward recompute: interpolation (with offset derivatives) ----
         float wny[ORDER + 1], why[ORDER + 1], wnz[ORDER + 1], whz[ORDER + 1];
@@ -479,8 +481,8 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles(const RunDev *__res
         }
 
         // ---- reverse ----------------------------------------------------------
-        float lx1[2] = {AS.soff[i], AS.soff[n + i]};          // adjoint of the moved offsets
-        float3 lun = make_float3(AS.su[i], AS.su[n + i], AS.su[2 * n + i]);
+        float lx1[2] = {to_global(AS.soff)[i], to_global(AS.soff)[n + i]};          // adjoint of the moved offsets
+        float3 lun = make_float3(to_global(AS.su)[i], to_global(AS.su)[n + i], to_global(AS.su)[2 * n + i]);
         float lo0[2] = {0.0f, 0.0f};
         float lig = 0.0f;
 
@@ -587,11 +589,11 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles(const RunDev *__res
             lo0[1] += lF[c] * Gz[c];
         }
         if (valid) {
-            AS.loff[i] = lo0[0];
-            AS.loff[n + i] = lo0[1];
-            AS.lu[i] = lu0.x;
-            AS.lu[n + i] = lu0.y;
-            AS.lu[2 * n + i] = lu0.z;
+            to_global(AS.loff)[i] = lo0[0];
+            to_global(AS.loff)[n + i] = lo0[1];
+            to_global(AS.lu)[i] = lu0.x;
+            to_global(AS.lu)[n + i] = lu0.y;
+            to_global(AS.lu)[2 * n + i] = lu0.z;
         }
         float fny[AdjFrame<ORDER, false>::len], fhy[AdjFrame<ORDER, true>::len];
         float fnz[AdjFrame<ORDER, false>::len], fhz[AdjFrame<ORDER, true>::len];
@@ -638,13 +640,13 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles(const RunDev *__res
         }
     }
     __syncthreads();
-    float *gp = A.gtile + (int64_t)U.patch * 6 * fcells;
+    const gptr<float> gp = to_global(A.gtile + (int64_t)U.patch * 6 * fcells);
     const int n_f = (fr1 - fr0 + 1) * fy;
     for (int q = threadIdx.x; q < 6 * n_f; q += NT) {
         const int c = q / n_f, r = q - c * n_f;
         const int t2 = c * fcells + fr0 * fy + r;
         const double v = gt[t2];
-        if (v != 0.0) atomicAdd(&gp[t2], (float)v);
+        if (v != 0.0) atomicAdd((float *)(gp + t2), (float)v);
     }
 }
 
@@ -769,7 +771,7 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles3(const RunDev *__re
     const int pcells = hx * hy * hz;
     // offsets outside [0, n] (a corrupt input) must not send the item outside the buffers
     const int32_t n32 = (int32_t)AS.n;
-    const int32_t pend = min(max(AS.cs[kb + pcells], 0), n32), pbeg = min(max(AS.cs[kb], 0), pend);
+    const int32_t pend = min(max(to_global(AS.cs)[kb + pcells], 0), n32), pbeg = min(max(to_global(AS.cs)[kb], 0), pend);
     const int32_t beg = pbeg + (item - item_start[lo]) * chunk;
     const int32_t end = min(beg + chunk, pend);
 
@@ -792,8 +794,8 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles3(const RunDev *__re
         tile_cell(q, fx, fxy, FLO, g);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            ftile[c * fcells + q] = A.E[c * nc + g];
-            ftile[(3 + c) * fcells + q] = A.B1[c * nc + g];
+            ftile[c * fcells + q] = to_global(A.E)[c * nc + g];
+            ftile[(3 + c) * fcells + q] = to_global(A.B1)[c * nc + g];
             gt[c * fcells + q] = 0.0;
             gt[(3 + c) * fcells + q] = 0.0;
         }
@@ -802,7 +804,7 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles3(const RunDev *__re
         int64_t g;
         tile_cell(q, jx, jxy, JLO, g);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) ljt[c * jcells + q] = A.LJ[c * nc + g];
+        for (int c = 0; c < 3; ++c) ljt[c * jcells + q] = to_global(A.LJ)[c * nc + g];
     }
     __syncthreads();
 
@@ -812,7 +814,7 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles3(const RunDev *__re
     const float jf[3] = {-qw * R.dx[0] / dt, -qw * R.dx[1] / dt, -qw * R.dx[2] / dt};
     auto slot_of = [&](int32_t i) -> int64_t {
         if (!AS.rperm) return i;
-        const int32_t q = AS.rperm[i];
+        const int32_t q = to_global(AS.rperm)[i];
         return (uint32_t)q < (uint32_t)AS.stride ? q : 0;   // a corrupt permutation stays in bounds
     };
 
@@ -827,11 +829,11 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles3(const RunDev *__re
         }
         const int32_t i = valid ? base + (int32_t)threadIdx.x : beg;
         const int64_t q = slot_of(i);
-        int local = AS.key[q] - (int32_t)kb;
+        int local = to_global(AS.key)[q] - (int32_t)kb;
         if (local < 0 || local >= pcells) local = 0;
         const int lz = local / (hx * hy), rr = local - lz * hx * hy, ly = rr / hx, lx = rr - ly * hx;
-        const float o0[3] = {AS.off[q], AS.off[st + q], AS.off[2 * st + q]};
-        const float3 u0 = make_float3(AS.u[q], AS.u[st + q], AS.u[2 * st + q]);
+        const float o0[3] = {to_global(AS.off)[q], to_global(AS.off)[st + q], to_global(AS.off)[2 * st + q]};
+        const float3 u0 = make_float3(to_global(AS.u)[q], to_global(AS.u)[st + q], to_global(AS.u)[2 * st + q]);
 
         // ---- forward recompute: interpolation (with offset derivatives) ----
         float wn[3][ORDER + 1], wh[3][ORDER + 1], dn[3][ORDER + 1], dh[3][ORDER + 1];
@@ -885,8 +887,8 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles3(const RunDev *__re
         }
 
         // ---- reverse ----------------------------------------------------------
-        float lx1[3] = {AS.soff[i], AS.soff[n + i], AS.soff[2 * n + i]};   // adjoint of the moved offsets
-        float lun[3] = {AS.su[i], AS.su[n + i], AS.su[2 * n + i]};
+        float lx1[3] = {to_global(AS.soff)[i], to_global(AS.soff)[n + i], to_global(AS.soff)[2 * n + i]};   // adjoint of the moved offsets
+        float lun[3] = {to_global(AS.su)[i], to_global(AS.su)[n + i], to_global(AS.su)[2 * n + i]};
         float lo0[3] = {0.0f, 0.0f, 0.0f};
         float lig = 0.0f;
 
@@ -995,12 +997,12 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles3(const RunDev *__re
 #pragma unroll
             for (int d = 0; d < 3; ++d) lo0[d] += lF[c] * G[c][d];
         if (valid) {
-            AS.loff[i] = lo0[0];
-            AS.loff[n + i] = lo0[1];
-            AS.loff[2 * n + i] = lo0[2];
-            AS.lu[i] = lu0.x;
-            AS.lu[n + i] = lu0.y;
-            AS.lu[2 * n + i] = lu0.z;
+            to_global(AS.loff)[i] = lo0[0];
+            to_global(AS.loff)[n + i] = lo0[1];
+            to_global(AS.loff)[2 * n + i] = lo0[2];
+            to_global(AS.lu)[i] = lu0.x;
+            to_global(AS.lu)[n + i] = lu0.y;
+            to_global(AS.lu)[2 * n + i] = lu0.z;
         }
         if constexpr (ORDER == 1) {
             float fn[3][AdjFrame<ORDER, false>::len], fh[3][AdjFrame<ORDER, true>::len];
@@ -1055,8 +1057,8 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles3(const RunDev *__re
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const double ve = gt[c * fcells + q], vb = gt[(3 + c) * fcells + q];
-            if (ve != 0.0) atomicAdd(&A.lE[c * nc + g], (float)ve);
-            if (vb != 0.0) atomicAdd(&A.lB[c * nc + g], (float)vb);
+            if (ve != 0.0) atomicAdd((float *)(to_global(A.lE) + (c * nc + g)), (float)ve);
+            if (vb != 0.0) atomicAdd((float *)(to_global(A.lB) + (c * nc + g)), (float)vb);
         }
     }
 }
@@ -1105,7 +1107,7 @@ __device__ __forceinline__ void adj_fold_direct(const RunDev &R, const AdjRun &A
             at[k] = use ? (int64_t)p * 6 * fcells + (ls[0][y] + lo) + (int64_t)fy * (ls[1][z] + lo) : own;
             float w[6];
 #pragma unroll
-            for (int q = 0; q < 6; ++q) w[q] = A.gtile[q * fcells + at[k]];
+            for (int q = 0; q < 6; ++q) w[q] = to_global(A.gtile)[q * fcells + at[k]];
 #pragma unroll
             for (int q = 0; q < 6; ++q) v[k][q] = use ? w[q] : 0.0f;
         }
@@ -1113,8 +1115,8 @@ __device__ __forceinline__ void adj_fold_direct(const RunDev &R, const AdjRun &A
     float cur[6];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        cur[q] = A.lE[q * nc + idx];
-        cur[3 + q] = A.lB[q * nc + idx];
+        cur[q] = to_global(A.lE)[q * nc + idx];
+        cur[3 + q] = to_global(A.lB)[q * nc + idx];
     }
     float acc[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
@@ -1127,11 +1129,11 @@ __device__ __forceinline__ void adj_fold_direct(const RunDev &R, const AdjRun &A
         for (int y = 0; y < 3; ++y)
             if (on[1][z] && on[0][y])
 #pragma unroll
-                for (int q = 0; q < 6; ++q) A.gtile[q * fcells + at[z * 3 + y]] = 0.0f;
+                for (int q = 0; q < 6; ++q) to_global(A.gtile)[q * fcells + at[z * 3 + y]] = 0.0f;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        A.lE[q * nc + idx] = cur[q] + acc[q];
-        A.lB[q * nc + idx] = cur[3 + q] + acc[3 + q];
+        to_global(A.lE)[q * nc + idx] = cur[q] + acc[q];
+        to_global(A.lB)[q * nc + idx] = cur[3 + q] + acc[3 + q];
     }
 }
 
@@ -1174,7 +1176,7 @@ __global__ void __launch_bounds__(256) k_adj_fold(const RunDev *__restrict__ run
         for (int a0 = 0; a0 < ncand[0]; ++a0) {
             const int pcy = cand[0][a0], pcz = cand[1][a1];
             const int p = R.np[0] * (pcy + R.np[1] * pcz);
-            float *tile = A.gtile + (int64_t)p * 6 * fcells;
+            const gptr<float> tile = to_global(A.gtile + (int64_t)p * 6 * fcells);
             int ls[2][3], nl[2];
             const int pcs[2] = {pcy, pcz};
             for (int d = 0; d < 2; ++d) {
@@ -1197,8 +1199,8 @@ __global__ void __launch_bounds__(256) k_adj_fold(const RunDev *__restrict__ run
         }
     const int64_t nc = R.ncell;
     for (int q = 0; q < 3; ++q) {
-        A.lE[q * nc + idx] += acc[q];
-        A.lB[q * nc + idx] += acc[3 + q];
+        to_global(A.lE)[q * nc + idx] += acc[q];
+        to_global(A.lB)[q * nc + idx] += acc[3 + q];
     }
 }
 

@@ -122,11 +122,15 @@ __global__ void __launch_bounds__(256) k_finish_current(const RunDev *__restrict
     with_run(runs, run_base, n_runs, total, [&](const RunDev &R, int64_t idx) {
         if (!R.jdirect) return;
         const int64_t nc = R.ncell;
+        const gptr<long long> acc = to_global(R.jacc);
+        const gptr<float> J = to_global(R.J);
+        long long a[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a[c] = acc[c * nc + idx];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const long long a = R.jacc[c * nc + idx];
-            R.J[c * nc + idx] = (float)((double)a * R.jq);
-            R.jacc[c * nc + idx] = 0;
+            J[c * nc + idx] = (float)((double)a[c] * R.jq);
+            acc[c * nc + idx] = 0;
         }
     });
 }
