@@ -7,6 +7,7 @@
 // All kernels index a flat cell space spanning every run; the run of a cell is
 // found by binary search over the runs' cell offsets.
 #include "psc_device.h"
+#include "psc_xcd.h"
 
 namespace psc {
 
@@ -23,7 +24,7 @@ __device__ __forceinline__ int find_run(const int64_t *base, int n_runs, int64_t
 // usual case: then the run's fields are read once, through scalar loads),
 // else -1.
 __device__ __forceinline__ int block_run(const int64_t *base, int n_runs, int64_t total) {
-    const int64_t c0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t c0 = (int64_t)xcd_block() * blockDim.x;
     const int64_t c1 = (c0 + blockDim.x < total ? c0 + blockDim.x : total) - 1;
     const int r = find_run(base, n_runs, c0);
     return base[r + 1] > c1 ? r : -1;
@@ -33,7 +34,7 @@ __device__ __forceinline__ int block_run(const int64_t *base, int n_runs, int64_
 // run R), with R uniform over the workgroup when block_run finds one run.
 template <typename F>
 __device__ __forceinline__ void with_run(const RunDev *runs, const int64_t *base, int n_runs, int64_t total, F &&f) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
     const int rb = block_run(base, n_runs, total);
     if (c >= total) return;
     if (rb >= 0) {

@@ -21,6 +21,7 @@
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include "psc_device.h"
+#include "psc_xcd.h"
 
 namespace psc {
 
@@ -68,13 +69,14 @@ __device__ __forceinline__ CellBlock cell_block(const RunDev *runs, const ScanSe
                                                 const int32_t *seg_run, const int32_t *seg_sp) {
     CellBlock B;
     constexpr int WC = wave_cells<DIM>(), SPS = sort_per_scan<DIM>();
-    const int sg = block_seg[blockIdx.x / SPS];
+    const int64_t bid = xcd_block_sort();   // dispatch order unless PSC_XCD_SORT
+    const int sg = block_seg[bid / SPS];
     B.R = &runs[seg_run[sg]];
     B.S = &B.R->sp[seg_sp[sg]];
     // the wave index as a scalar: the walk's bounds, loop counters and cell
     // masks then live in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    B.cw = ((int64_t)blockIdx.x - SPS * segs[sg].block0) * (4 * WC) + WC * wave;
+    B.cw = (bid - SPS * segs[sg].block0) * (4 * WC) + WC * wave;
     B.ce = B.cw + WC < B.R->ncell ? B.cw + WC : B.R->ncell;
     return B;
 }
@@ -269,8 +271,12 @@ __device__ __forceinline__ int32_t prefix_cell(const RunDev &R, const SpeciesDev
         ks[m] = (int32_t)key_of(R, ax[0].pc[a0], ax[1].pc[a1], ax[2].pc[a2], ax[0].l[a0], ax[1].l[a1], ax[2].l[a2],
                                 ax[0].ext[a0], ax[1].ext[a1], ax[2].ext[a2]);
         if (m != CENTER) {
-            cn[m] = cnt[m * nc + ks[m]];
-            stay -= cnt[m * nc + n];   // leaving n with move m
+            // the code's plane of counters from a scalar base, indexed by an
+            // unsigned 32-bit cell (keys and n are below 2^31): one address
+            // operation per load
+            const gptr<const uint16_t> cm = cnt + (int64_t)m * nc;
+            cn[m] = cm[(uint32_t)ks[m]];
+            stay -= cm[(uint32_t)n];   // leaving n with move m
         }
     }
     if (stay < 0) {   // counts inconsistent with the cell offsets
@@ -289,7 +295,7 @@ __device__ __forceinline__ int32_t prefix_cell(const RunDev &R, const SpeciesDev
     }
     const gptr<uint16_t> pre = to_global(S.pre);
 #pragma unroll
-    for (int m = 0; m < M; ++m) pre[m * nc + ks[m]] = (uint16_t)slot[rk[m]];
+    for (int m = 0; m < M; ++m) (pre + (int64_t)m * nc)[(uint32_t)ks[m]] = (uint16_t)slot[rk[m]];
     if (tot > 65535) atomicOr(err, PSC_DEV_OVERFULL);
     to_global(S.tot)[n] = tot;
     return tot;
@@ -310,7 +316,7 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_prefix(const RunDev *__rest
     constexpr int M = DIM == 3 ? 27 : 9;
     __shared__ int32_t wsum[kSortBlock / 64];
     __shared__ int32_t slots[kSortBlock * M];   // M words per thread (odd stride: no bank conflicts in order)
-    const int64_t blk = blockIdx.x;
+    const int64_t blk = xcd_block_sort();   // dispatch order unless PSC_XCD_SORT
     const int64_t b = blk / kPrefixPerScan;
     const int sg = block_seg[b];
     const RunDev &R = runs[seg_run[sg]];

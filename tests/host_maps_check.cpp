@@ -4,6 +4,7 @@
 #include <vector>
 
 #include "../paper_1310_7866_amd/csrc/psc_internal.h"
+#include "../paper_1310_7866_amd/csrc/psc_xcd.h"
 
 using namespace psc;
 
@@ -159,7 +160,24 @@ static void check_source_ranks() {
     for (const G &g : g2) check_source_ranks_grid<2>(g.n, g.P);
 }
 
+// The XCD placement of workgroups: a bijection on [0, G) for every grid size,
+// and the workgroups one XCD runs (b = x, x + 8, ...) map onto one contiguous
+// range in order.
+static void check_xcd_map() {
+    for (uint32_t G = 1; G <= 3000; ++G) {
+        std::vector<int> seen(G, 0);
+        for (uint32_t b = 0; b < G; ++b) {
+            const uint32_t L = xcd_map(b, G);
+            CHECK(L < G, "xcd_map(%u, %u) = %u out of range", b, G, L);
+            if (L < G) ++seen[L];
+            if (b >= kXcds) CHECK(L == xcd_map(b - kXcds, G) + 1, "G %u: workgroup %u not after %u", G, b, b - kXcds);
+        }
+        for (uint32_t L = 0; L < G; ++L) CHECK(seen[L] == 1, "G %u: index %u taken %d times", G, L, seen[L]);
+    }
+}
+
 int main() {
+    check_xcd_map();
     check_mix_lane();
     check_neighbour_key();
     check_current_direct_map();
