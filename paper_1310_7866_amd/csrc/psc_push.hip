@@ -793,18 +793,39 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
         float po0[3] = {0.0f, 0.0f, 0.0f}, po1[3] = {0.0f, 0.0f, 0.0f};
         float pu0[3] = {0.0f, 0.0f, 0.0f}, pu1[3] = {0.0f, 0.0f, 0.0f};
 
+        // K = 2: both particles' permutation entries, then both particles'
+        // keys and states, issued together at the round start (two memory
+        // round trips per round instead of three per particle)
+        int32_t h_key[KS] = {};
+        float h_o[KS][3] = {}, h_u[KS][3] = {};
+        int32_t h_id[KS] = {};
+        if constexpr (!prefetch) {
+            int32_t h_slot[KS], h_raw[KS];
+#pragma unroll
+            for (int j = 0; j < KS; ++j) {
+                h_slot[j] = j < len ? first + j : beg;
+                h_raw[j] = use_perm ? perm[h_slot[j]] : h_slot[j];
+            }
+#pragma unroll
+            for (int j = 0; j < KS; ++j) {
+                const int32_t src = checked_src(h_slot[j], h_raw[j], j < len);
+                h_key[j] = cell_in[src];
+                if constexpr (DIM == 3) h_o[j][0] = off_in[src];
+                h_o[j][1] = off_in[(DIM == 3 ? 1 : 0) * cap + src];
+                h_o[j][2] = off_in[(DIM == 3 ? 2 : 1) * cap + src];
+                h_u[j][0] = u_in[src];
+                h_u[j][1] = u_in[cap + src];
+                h_u[j][2] = u_in[2 * cap + src];
+                h_id[j] = id_in ? id_in[src] : 0;
+            }
+        }
+#pragma unroll
         for (int j = 0; j < K; ++j) {
             const bool valid = FULL || j < len;
             // lanes without a particle stand in with the chunk's first
             // particle (taken through the permutation, so it lies in range)
             const int32_t slot = valid ? first + j : beg;
-            int32_t src = 0, key;
-            if constexpr (prefetch) {
-                key = p_key;
-            } else {
-                src = checked_src(slot, use_perm ? perm[slot] : slot, valid);
-                key = cell_in[src];
-            }
+            const int32_t key = prefetch ? p_key : h_key[j];
             c = key - (int32_t)kb;
             if (c < 0 || c >= pcells) {   // not in this patch: corrupt state
                 if (valid) flags |= PSC_DEV_KEY;
@@ -828,13 +849,13 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
                 uz = p_u[2];
                 idv = p_id;
             } else {
-                o[0] = DIM == 3 ? off_in[src] : 0.0f;
-                o[1] = off_in[(DIM == 3 ? 1 : 0) * cap + src];
-                o[2] = off_in[(DIM == 3 ? 2 : 1) * cap + src];
-                ux = u_in[src];
-                uy = u_in[cap + src];
-                uz = u_in[2 * cap + src];
-                idv = id_in ? id_in[src] : 0;
+                o[0] = DIM == 3 ? h_o[j][0] : 0.0f;
+                o[1] = h_o[j][1];
+                o[2] = h_o[j][2];
+                ux = h_u[j][0];
+                uy = h_u[j][1];
+                uz = h_u[j][2];
+                idv = h_id[j];
             }
             // the next round's particle (its permutation entry was read a
             // round ago), then the permutation entry of the round after it
