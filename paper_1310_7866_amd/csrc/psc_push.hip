@@ -673,6 +673,25 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
     // current and write nothing
     // FULL: every lane of the round holds a particle (compile-time, so that
     // such rounds issue their loads and stores on every path)
+    // K = 2: the permutation entries of a lane's two particles in the round
+    // starting at r are read during the round before it (strip slots past
+    // the end stand in with the chunk's first particle)
+    int32_t h_raw[KS] = {};
+    auto strip_slots = [&](int32_t r, int32_t slot[KS]) {
+        const int32_t g_ = r + (int32_t)threadIdx.x;
+        const int32_t first_ = beg + g_ * KS;
+        const int32_t len_ = g_ < nruns ? imin(KS, end - first_) : 0;
+#pragma unroll
+        for (int j = 0; j < KS; ++j) slot[j] = j < len_ ? first_ + j : beg;
+        return len_;
+    };
+    if constexpr (!prefetch) {
+        int32_t sl[KS];
+        strip_slots(0, sl);
+#pragma unroll
+        for (int j = 0; j < KS; ++j) h_raw[j] = use_perm ? perm[sl[j]] : sl[j];
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);   // as for K = 1: the loop's waits count only its own operations
+    }
     auto round = [&](int32_t r0, auto full_tag) {
         constexpr bool FULL = decltype(full_tag)::value;
         int32_t g = r0 + (int32_t)threadIdx.x;
@@ -793,19 +812,15 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
         float po0[3] = {0.0f, 0.0f, 0.0f}, po1[3] = {0.0f, 0.0f, 0.0f};
         float pu0[3] = {0.0f, 0.0f, 0.0f}, pu1[3] = {0.0f, 0.0f, 0.0f};
 
-        // K = 2: both particles' permutation entries, then both particles'
-        // keys and states, issued together at the round start (two memory
-        // round trips per round instead of three per particle)
+        // K = 2: both particles' keys and states, issued together at the
+        // round start from the permutation entries read a round ago, then
+        // the next round's entries (one memory round trip per round)
         int32_t h_key[KS] = {};
         float h_o[KS][3] = {}, h_u[KS][3] = {};
         int32_t h_id[KS] = {};
         if constexpr (!prefetch) {
-            int32_t h_slot[KS], h_raw[KS];
-#pragma unroll
-            for (int j = 0; j < KS; ++j) {
-                h_slot[j] = j < len ? first + j : beg;
-                h_raw[j] = use_perm ? perm[h_slot[j]] : h_slot[j];
-            }
+            int32_t h_slot[KS];
+            strip_slots(r0, h_slot);
 #pragma unroll
             for (int j = 0; j < KS; ++j) {
                 const int32_t src = checked_src(h_slot[j], h_raw[j], j < len);
@@ -818,6 +833,10 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
                 h_u[j][2] = u_in[2 * cap + src];
                 h_id[j] = id_in ? id_in[src] : 0;
             }
+            int32_t n_slot[KS];
+            strip_slots(r0 + NT, n_slot);
+#pragma unroll
+            for (int j = 0; j < KS; ++j) h_raw[j] = use_perm ? perm[n_slot[j]] : n_slot[j];
         }
 #pragma unroll
         for (int j = 0; j < K; ++j) {
