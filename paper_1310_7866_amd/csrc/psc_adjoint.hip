@@ -412,11 +412,19 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles(const RunDev *__res
     const float inv_hy = 1.0f / hy;
 
     // every round gives each thread one particle; the rounds are uniform over
-    // the workgroup so that the wave scans see all lanes
+    // the workgroup so that the wave scans see all lanes.  A round's buffer
+    // slot is read through the permutation a round ahead, and the round's
+    // loads (state and incoming adjoints) are issued together at its start
+    auto round_slot = [&](int32_t b0) {
+        const int32_t ii = b0 + (int32_t)threadIdx.x;
+        return slot_of(ii < end ? ii : beg);
+    };
+    int64_t p_q = round_slot(beg);
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);   // the loop's waits then count only its own operations
     for (int32_t base = beg; base < end; base += NT) {
         const bool valid = base + (int32_t)threadIdx.x < end;
         const int32_t i = valid ? base + (int32_t)threadIdx.x : beg;
-        const int64_t q = slot_of(i);
+        const int64_t q = p_q;
         const int64_t st = AS.stride;
         const int32_t key = to_global(AS.key)[q];
         int local = key - (int32_t)kb;
@@ -425,6 +433,9 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles(const RunDev *__res
         const int lz = divmod_small(local, hy, inv_hy, ly);
         const float oyv = to_global(AS.off)[q], ozv = to_global(AS.off)[st + q];
         const float3 u0 = make_float3(to_global(AS.u)[q], to_global(AS.u)[st + q], to_global(AS.u)[2 * st + q]);
+        const float lx1_0 = to_global(AS.soff)[i], lx1_1 = to_global(AS.soff)[n + i];   // adjoint of the moved offsets
+        const float3 lun0 = make_float3(to_global(AS.su)[i], to_global(AS.su)[n + i], to_global(AS.su)[2 * n + i]);
+        p_q = round_slot(base + NT);
 
         // ---- forward recompute: interpolation (with offset derivatives) ----
         float wny[ORDER + 1], why[ORDER + 1], wnz[ORDER + 1], whz[ORDER + 1];
@@ -481,8 +492,8 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles(const RunDev *__res
         }
 
         // ---- reverse ----------------------------------------------------------
-        float lx1[2] = {to_global(AS.soff)[i], to_global(AS.soff)[n + i]};          // adjoint of the moved offsets
-        float3 lun = make_float3(to_global(AS.su)[i], to_global(AS.su)[n + i], to_global(AS.su)[2 * n + i]);
+        float lx1[2] = {lx1_0, lx1_1};
+        float3 lun = lun0;
         float lo0[2] = {0.0f, 0.0f};
         float lig = 0.0f;
 
@@ -822,18 +833,29 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles3(const RunDev *__re
     // uniform over the workgroup so that the wave scans see all lanes (lanes
     // past the end recompute the item's first particle and add zeros in a
     // segment of their own)
+    // (a round's buffer slot is read through the permutation a round ahead,
+    // and its loads are issued together at its start)
+    auto round_slot = [&](int32_t b0) {
+        const int32_t ii = b0 + (int32_t)threadIdx.x;
+        return slot_of(ii < end ? ii : beg);
+    };
+    int64_t p_q = round_slot(beg);
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);   // the loop's waits then count only its own operations
     for (int32_t base = beg; base < end; base += NT) {
         const bool valid = base + (int32_t)threadIdx.x < end;
+        const int64_t q = p_q;
+        p_q = round_slot(base + NT);
         if constexpr (ORDER != 1) {
             if (!valid) continue;   // no wave scans at order 2
         }
         const int32_t i = valid ? base + (int32_t)threadIdx.x : beg;
-        const int64_t q = slot_of(i);
         int local = to_global(AS.key)[q] - (int32_t)kb;
         if (local < 0 || local >= pcells) local = 0;
         const int lz = local / (hx * hy), rr = local - lz * hx * hy, ly = rr / hx, lx = rr - ly * hx;
         const float o0[3] = {to_global(AS.off)[q], to_global(AS.off)[st + q], to_global(AS.off)[2 * st + q]};
         const float3 u0 = make_float3(to_global(AS.u)[q], to_global(AS.u)[st + q], to_global(AS.u)[2 * st + q]);
+        const float lx1_0[3] = {to_global(AS.soff)[i], to_global(AS.soff)[n + i], to_global(AS.soff)[2 * n + i]};
+        const float lun_0[3] = {to_global(AS.su)[i], to_global(AS.su)[n + i], to_global(AS.su)[2 * n + i]};
 
         // ---- forward recompute: interpolation (with offset derivatives) ----
         float wn[3][ORDER + 1], wh[3][ORDER + 1], dn[3][ORDER + 1], dh[3][ORDER + 1];
@@ -887,8 +909,8 @@ __global__ void __launch_bounds__(kAdjBlock) k_adj_particles3(const RunDev *__re
         }
 
         // ---- reverse ----------------------------------------------------------
-        float lx1[3] = {to_global(AS.soff)[i], to_global(AS.soff)[n + i], to_global(AS.soff)[2 * n + i]};   // adjoint of the moved offsets
-        float lun[3] = {to_global(AS.su)[i], to_global(AS.su)[n + i], to_global(AS.su)[2 * n + i]};
+        float lx1[3] = {lx1_0[0], lx1_0[1], lx1_0[2]};   // adjoint of the moved offsets
+        float lun[3] = {lun_0[0], lun_0[1], lun_0[2]};
         float lo0[3] = {0.0f, 0.0f, 0.0f};
         float lig = 0.0f;
 
