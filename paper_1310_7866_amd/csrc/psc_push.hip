@@ -61,11 +61,12 @@ namespace psc {
 #ifndef PSC_WAVES_3D1
 #define PSC_WAVES_3D1 4
 #endif
-//   PSC_PREFETCH     1: with one particle per lane, the permutation entry
-//                    and cell key of a lane's next particle are loaded while
-//                    the current one is pushed, so a round waits for one
-//                    memory round trip (its offsets and momenta) instead of
-//                    three dependent ones (permutation, key, state)
+//   PSC_PREFETCH     1: with one particle per lane, the state of a lane's
+//                    next particle (cell key, offsets, momenta) is loaded at
+//                    the start of the current round and its permutation entry
+//                    a round earlier, so a round waits for no memory round
+//                    trip of its own (0: three dependent ones per round:
+//                    permutation, key, state)
 #ifndef PSC_PREFETCH
 #define PSC_PREFETCH 1
 #endif
