@@ -48,7 +48,7 @@ def algorithmic_bytes(case) -> float:
 
 
 # every n-th particle of a workload for the oracle's baseline and error legs
-CPU_THIN = {"weibel3d": 32, "harris2d": 1, "thermal2d": 1, "harris2d_small": 1}
+CPU_THIN = {"weibel3d": 32, "harris2d": 1, "thermal2d": 1, "harris2d_small": 1, "thermal2d_1024x512": 4}
 
 
 def make_case(name: str):
@@ -61,6 +61,9 @@ def make_case(name: str):
         return cases.weibel3d()
     if name == "harris2d_small":
         return cases.harris2d(ny=256, nz=256, ppc=64, seed=5050, steps=50)
+    if name == "thermal2d_1024x512":   # the 2-d order-1 kernel at full size (16.8 M particles)
+        import dataclasses
+        return dataclasses.replace(cases.thermal2d(ny=1024, nz=512, ppc=16, order=1, patch=32), name=name)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -580,7 +583,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="weibel3d", choices=("weibel3d", "harris2d", "thermal2d", "harris2d_small"))
+    ap.add_argument("--workload", default="weibel3d", choices=("weibel3d", "harris2d", "thermal2d", "harris2d_small",
+                                                                      "thermal2d_1024x512"))
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--cpu-thin", type=int, default=0,
                     help="oracle baseline on every n-th particle (0: 32 for weibel3d, 1 for the 2-d workloads)")
