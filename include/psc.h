@@ -96,7 +96,7 @@ typedef struct {
     double q[PSC_MAX_SPECIES];      /* charge                                        */
     double m[PSC_MAX_SPECIES];      /* mass                                          */
     double w[PSC_MAX_SPECIES];      /* density weight per particle                   */
-    int64_t capacity[PSC_MAX_SPECIES]; /* particle slots per buffer, <= 2^31 - 1024  */
+    int64_t capacity[PSC_MAX_SPECIES]; /* particle slots per buffer, <= 2^30 - 1024  */
     int flags;                      /* PSC_RUN_* bits                                 */
 } psc_run_desc;
 

@@ -3,6 +3,8 @@
 // interpolation from LDS tiles.
 #pragma once
 
+#include <type_traits>
+
 #include "psc_internal.h"
 
 namespace psc {
@@ -153,6 +155,18 @@ __device__ __forceinline__ float boris_factor(float t2) { return 2.0f * __builti
 // s_waitcnt immediate that waits for every vector memory operation and for
 // nothing else (vmcnt 0; expcnt 7 and lgkmcnt 15 do not wait)
 constexpr int kWaitVmcnt0 = 0x0F70;
+
+// Element i of a global array whose byte offsets stay below 2^32 (a species'
+// arrays: at most 2^30 entries): the base stays in scalar registers and each
+// lane adds a 32-bit byte offset, one address operation per lane shared by
+// every array indexed with i instead of a 64-bit add per access.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *at32(__attribute__((address_space(1))) T *base,
+                                                                     uint32_t i) {
+    using B = typename std::conditional<std::is_const<T>::value, const uint8_t, uint8_t>::type;
+    return reinterpret_cast<__attribute__((address_space(1))) T *>(
+        reinterpret_cast<__attribute__((address_space(1))) B *>(base) + i * (uint32_t)sizeof(T));
+}
 
 // pointers into device memory known to be global (loads and stores become
 // global_* instead of flat_*, which would also wait on LDS traffic)

@@ -29,7 +29,9 @@ constexpr int kScanPerThread = 8;    // elements per thread in the scans
 constexpr int kScanBlock = 256 * kScanPerThread;
 // particle slots per species buffer: indices and the sort's group offsets
 // (index + 255) stay in int32
-constexpr int64_t kMaxCapacity = (1ll << 31) - 1024;
+// particle slots per species buffer: the byte offsets of a species' arrays
+// stay below 2^32, so the kernels address them as a base plus a 32-bit offset
+constexpr int64_t kMaxCapacity = (1ll << 30) - 1024;
 constexpr int kAdjBlock = 512;       // threads per workgroup of the particle adjoint
 constexpr int kAdjChunk = 2048;      // particles per work item of the particle adjoint
 

@@ -579,6 +579,13 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
     // every later wait for a load would have to drain all memory operations
     const gptr<uint32_t> cnt32 = to_global(reinterpret_cast<uint32_t *>(S.cnt));
     const int64_t cap = S.cap;
+    // per-component bases of the particle arrays (uniform), indexed through
+    // at32 with 32-bit slots; offsets: components (y, z) in 2-d, (x, y, z) in 3-d
+    constexpr int D = DIM == 3 ? 3 : 2;
+    const gptr<const float> oin[3] = {off_in, off_in + cap, D == 3 ? off_in + 2 * cap : off_in};
+    const gptr<const float> uin[3] = {u_in, u_in + cap, u_in + 2 * cap};
+    const gptr<float> oout[3] = {off_out, off_out + cap, D == 3 ? off_out + 2 * cap : off_out};
+    const gptr<float> uout[3] = {u_out, u_out + cap, u_out + 2 * cap};
     const float h = S.qdt_2m;
     const float qw = S.qw;
     const float dt = R.dt;
@@ -647,21 +654,22 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
         return raw;
     };
     auto load_state = [&](int32_t src) {
-        p_key = cell_in[src];
-        if constexpr (DIM == 3) p_o[0] = off_in[src];
-        p_o[1] = off_in[(DIM == 3 ? 1 : 0) * cap + src];
-        p_o[2] = off_in[(DIM == 3 ? 2 : 1) * cap + src];
-        p_u[0] = u_in[src];
-        p_u[1] = u_in[cap + src];
-        p_u[2] = u_in[2 * cap + src];
-        p_id = id_in ? id_in[src] : 0;
+        const uint32_t i = (uint32_t)src;
+        p_key = *at32(cell_in, i);
+        if constexpr (DIM == 3) p_o[0] = *at32(oin[0], i);
+        p_o[1] = *at32(oin[D - 2], i);
+        p_o[2] = *at32(oin[D - 1], i);
+        p_u[0] = *at32(uin[0], i);
+        p_u[1] = *at32(uin[1], i);
+        p_u[2] = *at32(uin[2], i);
+        p_id = id_in ? *at32(id_in, i) : 0;
     };
     if constexpr (prefetch) {
         bool ok;
         const int32_t sl = lane_slot(0, ok);
-        load_state(checked_src(sl, use_perm ? perm[sl] : sl, ok));
+        load_state(checked_src(sl, use_perm ? *at32(perm, (uint32_t)sl) : sl, ok));
         const int32_t sl1 = lane_slot(NT, ok);
-        p_raw = use_perm ? perm[sl1] : sl1;
+        p_raw = use_perm ? *at32(perm, (uint32_t)sl1) : sl1;
         // these loads complete here, once per item: the compiler's waits in
         // the round loop then count only the loop's own memory operations
         // (entering with the prologue's loads pending, it would wait for all
@@ -690,7 +698,7 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
         int32_t sl[KS];
         strip_slots(0, sl);
 #pragma unroll
-        for (int j = 0; j < KS; ++j) h_raw[j] = use_perm ? perm[sl[j]] : sl[j];
+        for (int j = 0; j < KS; ++j) h_raw[j] = use_perm ? *at32(perm, (uint32_t)sl[j]) : sl[j];
         __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);   // as for K = 1: the loop's waits count only its own operations
     }
     auto round = [&](int32_t r0, auto full_tag) {
@@ -825,19 +833,20 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
 #pragma unroll
             for (int j = 0; j < KS; ++j) {
                 const int32_t src = checked_src(h_slot[j], h_raw[j], j < len);
-                h_key[j] = cell_in[src];
-                if constexpr (DIM == 3) h_o[j][0] = off_in[src];
-                h_o[j][1] = off_in[(DIM == 3 ? 1 : 0) * cap + src];
-                h_o[j][2] = off_in[(DIM == 3 ? 2 : 1) * cap + src];
-                h_u[j][0] = u_in[src];
-                h_u[j][1] = u_in[cap + src];
-                h_u[j][2] = u_in[2 * cap + src];
-                h_id[j] = id_in ? id_in[src] : 0;
+                const uint32_t i = (uint32_t)src;
+                h_key[j] = *at32(cell_in, i);
+                if constexpr (DIM == 3) h_o[j][0] = *at32(oin[0], i);
+                h_o[j][1] = *at32(oin[D - 2], i);
+                h_o[j][2] = *at32(oin[D - 1], i);
+                h_u[j][0] = *at32(uin[0], i);
+                h_u[j][1] = *at32(uin[1], i);
+                h_u[j][2] = *at32(uin[2], i);
+                h_id[j] = id_in ? *at32(id_in, i) : 0;
             }
             int32_t n_slot[KS];
             strip_slots(r0 + NT, n_slot);
 #pragma unroll
-            for (int j = 0; j < KS; ++j) h_raw[j] = use_perm ? perm[n_slot[j]] : n_slot[j];
+            for (int j = 0; j < KS; ++j) h_raw[j] = use_perm ? *at32(perm, (uint32_t)n_slot[j]) : n_slot[j];
         }
 #pragma unroll
         for (int j = 0; j < K; ++j) {
@@ -886,7 +895,7 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
                 const int32_t n_slot = lane_slot(r0 + NT, n_ok);
                 load_state(checked_src(n_slot, p_raw, n_ok));
                 const int32_t sl2 = lane_slot(r0 + 2 * NT, n_ok);
-                p_raw = use_perm ? perm[sl2] : sl2;
+                p_raw = use_perm ? *at32(perm, (uint32_t)sl2) : sl2;
             }
 
             // ---- interpolation ----------------------------------------------
@@ -1039,20 +1048,16 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
                 }
                 const int code = DIM == 3 ? (s[0] + 1) + 3 * (s[1] + 1) + 9 * (s[2] + 1) : (s[1] + 1) + 3 * (s[2] + 1);
                 if constexpr (single) {
-                    cell_out[slot] = nkey;
-                    if constexpr (DIM == 3) {
-                        off_out[slot] = o1[0];
-                        off_out[cap + slot] = o1[1];
-                        off_out[2 * cap + slot] = o1[2];
-                    } else {
-                        off_out[slot] = o1[1];
-                        off_out[cap + slot] = o1[2];
-                    }
-                    mc[slot] = (uint8_t)code;
-                    u_out[slot] = ux;
-                    u_out[cap + slot] = uy;
-                    u_out[2 * cap + slot] = uz;
-                    if (id_out) id_out[slot] = idv;
+                    const uint32_t i = (uint32_t)slot;
+                    *at32(cell_out, i) = nkey;
+                    if constexpr (DIM == 3) *at32(oout[0], i) = o1[0];
+                    *at32(oout[D - 2], i) = o1[1];
+                    *at32(oout[D - 1], i) = o1[2];
+                    *at32(mc, i) = (uint8_t)code;
+                    *at32(uout[0], i) = ux;
+                    *at32(uout[1], i) = uy;
+                    *at32(uout[2], i) = uz;
+                    if (id_out) *at32(id_out, i) = idv;
                 } else if (j == 0) {
                     pk0 = nkey; po0[0] = o1[0]; po0[1] = o1[1]; po0[2] = o1[2];
                     pu0[0] = ux; pu0[1] = uy; pu0[2] = uz; pc0 = code; pi0 = idv;
@@ -1085,23 +1090,19 @@ __device__ __forceinline__ void push_item(const RunDev *__restrict__ runs, const
 #pragma unroll
                 for (int d = 0; d < 3; ++d) u[d] = pick(pu0[d], pu1[d]);
                 if (ok) {
-                    cell_out[slot] = k;
-                    if constexpr (DIM == 3) {
-                        off_out[slot] = o[0];
-                        off_out[cap + slot] = o[1];
-                        off_out[2 * cap + slot] = o[2];
-                    } else {
-                        off_out[slot] = o[1];
-                        off_out[cap + slot] = o[2];
-                    }
-                    mc[slot] = (uint8_t)code;
-                    u_out[slot] = u[0];
-                    u_out[cap + slot] = u[1];
-                    u_out[2 * cap + slot] = u[2];
+                    const uint32_t i = (uint32_t)slot;
+                    *at32(cell_out, i) = k;
+                    if constexpr (DIM == 3) *at32(oout[0], i) = o[0];
+                    *at32(oout[D - 2], i) = o[1];
+                    *at32(oout[D - 1], i) = o[2];
+                    *at32(mc, i) = (uint8_t)code;
+                    *at32(uout[0], i) = u[0];
+                    *at32(uout[1], i) = u[1];
+                    *at32(uout[2], i) = u[2];
                 }
                 if (id_out) {
                     const int32_t iv = pick(pi0, pi1);
-                    if (ok) id_out[slot] = iv;
+                    if (ok) *at32(id_out, (uint32_t)slot) = iv;
                 }
             }
         }

@@ -27,9 +27,6 @@ namespace psc {
 
 constexpr int kSortBlock = 256;
 
-using gptr_i32 = __attribute__((address_space(1))) int32_t *;
-using gcptr_u8 = const __attribute__((address_space(1))) uint8_t *;
-
 // Scatter: a workgroup owns 4 wave_cells consecutive old cells of one
 // segment, each of its four waves wave_cells of them (lane q: cell cw + q),
 // i.e. one contiguous range of particles (the buffer is ordered by old
@@ -335,9 +332,6 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_prefix(const RunDev *__rest
     }
 }
 
-// target of the scatter's stores from lanes that have no position (species
-// too large for a buffer resource)
-__device__ int32_t sort_sink;
 // raw buffer resource of the permutation (4th word: 32-bit data format, as
 // for every gfx9-family chip); offsets at or past n * 4 bytes are dropped.
 // kBufferDrop lies past every buffer of at most kBufferMaxN words, also
@@ -345,6 +339,7 @@ __device__ int32_t sort_sink;
 constexpr int kBufferWord3 = 0x00020000;
 constexpr int32_t kBufferMaxN = 0x3FFFFFF0;
 constexpr int kBufferDrop = (int)0xFFFFFFE0u;
+static_assert(kMaxCapacity <= kBufferMaxN, "every species fits a buffer resource");
 
 // per old cell: stable positions of its particles.  Lane q sets up the first
 // position of every move code of its cell in LDS; the walk then writes
@@ -413,30 +408,18 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(const RunDev *__r
                           if (valid && last) tab[slot] = p + 1;
                       });
     };
-    if (n <= kBufferMaxN) {
-        // a raw buffer store: the hardware drops stores at offsets past
-        // the buffer's n * 4 bytes, so lanes without a position need no
-        // other target
-        const __amdgpu_buffer_rsrc_t prs =
-            __builtin_amdgcn_make_buffer_rsrc(S.perm[1 - cs_sel], (short)0, (int)((uint32_t)n << 2), kBufferWord3);
-        // move codes through a byte buffer of n entries: indices past the
-        // end read 0 (their lanes hold no particle)
-        const __amdgpu_buffer_rsrc_t mrs = __builtin_amdgcn_make_buffer_rsrc(S.mc, (short)0, n, kBufferWord3);
-        walk([&](int32_t idx) { return (int)__builtin_amdgcn_raw_buffer_load_b8(mrs, idx, 0, 0); },
-             [&](bool ok, int32_t p, int32_t i) {
-            __builtin_amdgcn_raw_buffer_store_b32((uint32_t)i, prs, ok ? (int)((uint32_t)p << 2) : kBufferDrop, 0, 0);
-        });
-    } else {
-        // lanes without a position write the sink word
-        const gptr_i32 perm = (gptr_i32)S.perm[1 - cs_sel];
-        const gcptr_u8 mc = (gcptr_u8)S.mc;
-        const int32_t last_i = pe - 1;
-        walk([&](int32_t idx) { return (int)mc[imin(idx, last_i)]; },
-             [&](bool ok, int32_t p, int32_t i) {
-            const gptr_i32 dst = ok ? perm + p : (gptr_i32)&sort_sink;
-            *dst = i;
-        });
-    }
+    // a raw buffer store: the hardware drops stores at offsets past the
+    // buffer's n * 4 bytes, so lanes without a position need no other target
+    const __amdgpu_buffer_rsrc_t prs =
+        __builtin_amdgcn_make_buffer_rsrc(S.perm[1 - cs_sel], (short)0, (int)((uint32_t)n << 2), kBufferWord3);
+    // move codes through a byte buffer of n entries: indices past the end
+    // read 0 (their lanes hold no particle)
+    const __amdgpu_buffer_rsrc_t mrs = __builtin_amdgcn_make_buffer_rsrc(S.mc, (short)0, n, kBufferWord3);
+    walk([&](int32_t idx) { return (int)__builtin_amdgcn_raw_buffer_load_b8(mrs, idx, 0, 0); },
+         [&](bool ok, int32_t p, int32_t i) {
+             __builtin_amdgcn_raw_buffer_store_b32((uint32_t)i, prs, ok ? (int)((uint32_t)p << 2) : kBufferDrop, 0,
+                                                   0);
+         });
     if (bad) flags |= PSC_DEV_OVERFULL;
     if (flags) atomicOr(err, flags);   // also an invalid move code (PSC_DEV_MOVE)
 }

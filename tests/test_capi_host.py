@@ -69,12 +69,13 @@ def test_bad_geometry_rejected():
 
 
 def test_capacity_limit():
-    # particle indices and the sort's look-ahead offsets stay in int32
+    # the byte offsets of a species' arrays stay below 2^32 (the kernels
+    # address them as a base plus a 32-bit offset)
     c = cases.thermal2d(ny=16, nz=12, ppc=2, patch=8)
     d = psc.run_desc(c)
-    d.capacity[0] = (1 << 31) - 1024
+    d.capacity[0] = (1 << 30) - 1024
     assert _init(d) == 0
-    d.capacity[0] = (1 << 31) - 1023
+    d.capacity[0] = (1 << 30) - 1023
     assert _init(d) == 1
 
 
