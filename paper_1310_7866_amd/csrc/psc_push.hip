@@ -136,35 +136,71 @@ __global__ void __launch_bounds__(256) k_unit_items(const RunDev *__restrict__ r
 }
 
 // One workgroup: exclusive prefix of the per-unit item counts in place, the
-// total in item_start[n_units]; each thread sums a contiguous run of units
-// (independent loads), the workgroup scans the run totals.  Also resets the
-// work queues of the persistent launch (written before the particle kernel
-// starts: same stream).
+// total in item_start[n_units].  The counts pass through LDS in tiles of
+// kItemsTile: coalesced loads, eight consecutive counts per thread, a scan of
+// the thread sums (within each wave by lane shuffles, then over the waves),
+// and coalesced stores of the prefixes.  Each lane reading its own run of
+// counts straight from memory would touch a separate cache line per lane and
+// instruction, all on the one compute unit.  Also resets the work queues of
+// the persistent launch (written before the particle kernel starts: same
+// stream).
+constexpr int kItemsPer = 8;
+constexpr int kItemsTile = 1024 * kItemsPer;
 __global__ void __launch_bounds__(1024) k_items_scan(int n_units, int32_t *__restrict__ item_start,
                                                      int32_t *__restrict__ queue) {
-    __shared__ int32_t part[1024];
-    if (queue && threadIdx.x < 8) queue[kQueueStride * threadIdx.x] = 0;
-    const int t = threadIdx.x;
-    const int per = (n_units + 1023) / 1024;
-    const int u0 = imin(t * per, n_units), u1 = imin(u0 + per, n_units);
-    int32_t sum = 0;
-#pragma unroll 8
-    for (int u = u0; u < u1; ++u) sum += item_start[u];
-    part[t] = sum;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        int32_t v = t >= off ? part[t - off] : 0;
+    __shared__ __align__(16) int32_t tile[kItemsTile];
+    __shared__ int32_t wtot[16];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    if (queue && t < 8) queue[kQueueStride * t] = 0;
+    int32_t carry = 0;
+    for (int base = 0; base < n_units; base += kItemsTile) {
+        const int n = imin(kItemsTile, n_units - base);
+#pragma unroll
+        for (int k = 0; k < kItemsPer; ++k) {
+            const int i = k * 1024 + t;
+            tile[i] = i < n ? item_start[base + i] : 0;
+        }
         __syncthreads();
-        part[t] += v;
+        int4 *mine = reinterpret_cast<int4 *>(tile) + 2 * t;   // counts 8t .. 8t + 7
+        const int4 va = mine[0], vb = mine[1];
+        const int32_t sum = va.x + va.y + va.z + va.w + vb.x + vb.y + vb.z + vb.w;
+        int32_t inc = sum;   // inclusive scan over the wave's lanes
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int32_t v = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += v;
+        }
+        if (lane == 63) wtot[wv] = inc;
         __syncthreads();
+        int32_t before = carry, total = 0;   // sums of the waves below, of all waves
+#pragma unroll
+        for (int w = 0; w < 16; ++w) {
+            const int32_t x = wtot[w];
+            before += w < wv ? x : 0;
+            total += x;
+        }
+        int32_t run = before + inc - sum;   // exclusive prefix of count 8t
+        int4 pa, pb;
+        pa.x = run; run += va.x;
+        pa.y = run; run += va.y;
+        pa.z = run; run += va.z;
+        pa.w = run; run += va.w;
+        pb.x = run; run += vb.x;
+        pb.y = run; run += vb.y;
+        pb.z = run; run += vb.z;
+        pb.w = run;
+        mine[0] = pa;
+        mine[1] = pb;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kItemsPer; ++k) {
+            const int i = k * 1024 + t;
+            if (i < n) item_start[base + i] = tile[i];
+        }
+        carry += total;
+        __syncthreads();   // the tile and the wave totals are reused
     }
-    int32_t run = part[t] - sum;  // exclusive
-    for (int u = u0; u < u1; ++u) {
-        const int32_t c = item_start[u];
-        item_start[u] = run;
-        run += c;
-    }
-    if (t == 1023) item_start[n_units] = part[1023];
+    if (t == 0) item_start[n_units] = carry;
 }
 
 hipError_t launch_items_scan(int n_units, int32_t *item_start, int32_t *queue, hipStream_t s) {
