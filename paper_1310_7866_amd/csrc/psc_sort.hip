@@ -427,22 +427,6 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(const RunDev *__r
 // ---------------------------------------------------------------------------
 // segmented exclusive scan: out[0..n] with out[n] = total, per segment
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *sh, int32_t &total) {
-    const int t = threadIdx.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        const int32_t a = t >= off ? sh[t - off] : 0;
-        __syncthreads();
-        sh[t] += a;
-        __syncthreads();
-    }
-    total = sh[255];
-    const int32_t r = sh[t] - v;
-    __syncthreads();
-    return r;
-}
-
 // one workgroup: segmented exclusive scan of the scan blocks' totals (each
 // the sum of its kPrefixPerScan partial sums) into block_sums
 __global__ void __launch_bounds__(1024) k_scan_blocks(const ScanSeg *__restrict__ segs,
@@ -483,30 +467,65 @@ __global__ void __launch_bounds__(1024) k_scan_blocks(const ScanSeg *__restrict_
     }
 }
 
+// Scan block b of its segment: the block's values pass through LDS
+// (coalesced loads and stores), each thread scans eight consecutive ones, and
+// the thread sums are scanned within each wave by lane shuffles, then over
+// the four waves.  Threads reading their eight values straight from memory
+// would touch a separate cache line per lane and load.
+static_assert(kScanPerThread == 8 && kScanBlock == 256 * kScanPerThread, "two int4 per thread");
 __global__ void __launch_bounds__(256) k_scan_final(const ScanSeg *__restrict__ segs,
                                                     const int32_t *__restrict__ block_seg,
                                                     const int32_t *__restrict__ block_sums) {
-    __shared__ int32_t sh[256];
+    __shared__ __align__(16) int32_t tile[kScanBlock];
+    __shared__ int32_t wtot[4];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int64_t b = blockIdx.x;
     const ScanSeg sg = segs[block_seg[b]];
     const int32_t offset = block_sums[b];
-    const int64_t i0 = (b - sg.block0) * kScanBlock + (int64_t)threadIdx.x * kScanPerThread;
-    int32_t v[kScanPerThread];
-    int32_t s = 0;
+    const int64_t base = (b - sg.block0) * kScanBlock;
+    const int n = (int)(sg.n - base < kScanBlock ? sg.n - base : kScanBlock);
 #pragma unroll
     for (int q = 0; q < kScanPerThread; ++q) {
-        v[q] = i0 + q < sg.n ? sg.in[i0 + q] : 0;
-        s += v[q];
+        const int i = q * 256 + t;
+        tile[i] = i < n ? sg.in[base + i] : 0;
     }
-    int32_t total;
-    int32_t run = block_exclusive_scan(s, sh, total) + offset;
+    __syncthreads();
+    int4 *mine = reinterpret_cast<int4 *>(tile) + 2 * t;   // values 8t .. 8t + 7
+    const int4 va = mine[0], vb = mine[1];
+    const int32_t sum = va.x + va.y + va.z + va.w + vb.x + vb.y + vb.z + vb.w;
+    int32_t inc = sum;   // inclusive scan over the wave's lanes
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t v = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += v;
+    }
+    if (lane == 63) wtot[wv] = inc;
+    __syncthreads();
+    int32_t run = offset + inc - sum, total = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const int32_t x = wtot[w];
+        run += w < wv ? x : 0;
+        total += x;
+    }
+    int4 pa, pb;
+    pa.x = run; run += va.x;
+    pa.y = run; run += va.y;
+    pa.z = run; run += va.z;
+    pa.w = run; run += va.w;
+    pb.x = run; run += vb.x;
+    pb.y = run; run += vb.y;
+    pb.z = run; run += vb.z;
+    pb.w = run;
+    mine[0] = pa;
+    mine[1] = pb;
+    __syncthreads();
 #pragma unroll
     for (int q = 0; q < kScanPerThread; ++q) {
-        if (i0 + q < sg.n) sg.out[i0 + q] = run;
-        run += v[q];
+        const int i = q * 256 + t;
+        if (i < n) sg.out[base + i] = tile[i];
     }
-    const int64_t blocks = (sg.n + kScanBlock - 1) / kScanBlock;
-    if (threadIdx.x == 255 && b - sg.block0 == blocks - 1) sg.out[sg.n] = offset + total;
+    if (t == 255 && base + kScanBlock >= sg.n) sg.out[sg.n] = offset + total;   // the segment's last block
 }
 
 // partial: kPrefixPerScan partial sums per scan block (from k_sort_prefix)
